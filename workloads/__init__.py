@@ -1,0 +1,160 @@
+"""Seeded synthetic inputs for the spectral Poisson solver.
+
+This module is shared by the oracle, the tests and the benchmark.  It holds
+no arithmetic of the solver itself: it only draws seeded random coefficient
+arrays with the decay profiles of the workloads, and samples the manufactured
+right-hand sides (analytic Laplacians of closed-form solutions) on Chebyshev
+grids.
+
+Conventions (rows <-> y, columns <-> x, as in the expansion (3.2)):
+  square: F[j, k] is the coefficient of T_j(y) T_k(x);
+  cube:   F[i, j, k] is the coefficient of T_i(z) T_j(y) T_k(x).
+All arrays are float64, C-contiguous.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "decayed_normal", "square_rhs", "cube_rhs", "batched_problems",
+    "adjoint_case", "cheb_coeffs_2d", "cheb_coeffs_3d",
+    "manufactured_square", "manufactured_cube", "oscillatory_square_rhs",
+]
+
+
+def decayed_normal(rng: np.random.Generator, shape, decay: float) -> np.ndarray:
+    """N(0,1) entries drawn in C order, multiplied by prod_axis (1+idx)^-decay."""
+    F = rng.standard_normal(shape)
+    for ax, n in enumerate(shape):
+        w = (1.0 + np.arange(n, dtype=np.float64)) ** (-decay)
+        sh = [1] * len(shape)
+        sh[ax] = n
+        F *= w.reshape(sh)
+    return np.ascontiguousarray(F)
+
+
+def square_rhs(n: int, seed: int = 0, decay: float = 2.0) -> np.ndarray:
+    """F_jk = N(0,1) (1+j)^-decay (1+k)^-decay, default_rng(seed)."""
+    return decayed_normal(np.random.default_rng(seed), (n, n), decay)
+
+
+def cube_rhs(n: int, seed: int = 2, decay: float = 2.0) -> np.ndarray:
+    """F_ijk = N(0,1) (1+i)^-2 (1+j)^-2 (1+k)^-2, default_rng(seed)."""
+    return decayed_normal(np.random.default_rng(seed), (n, n, n), decay)
+
+
+def batched_problems(count: int = 256, seed: int = 1, step: int = 32,
+                     nmax_steps: int = 32, decay: float = 1.5):
+    """Sizes n_b = step * U{1..nmax_steps} then each F_b, all from one rng."""
+    rng = np.random.default_rng(seed)
+    sizes = [int(s) for s in step * rng.integers(1, nmax_steps + 1, count)]
+    Fs = [decayed_normal(rng, (n, n), decay) for n in sizes]
+    return sizes, Fs
+
+
+def adjoint_case(n: int, batch: int, n_dirs: int = 32, seed_f: int = 0,
+                 seed_target: int = 3, seed_dirs: int = 4):
+    """Differentiable-solve workload: inputs F (batch, n, n), target right-hand
+    side F* (seed 3) and unit-Frobenius Gaussian directions (seed 4)."""
+    rng = np.random.default_rng(seed_f)
+    F = np.stack([decayed_normal(rng, (n, n), 2.0) for _ in range(batch)])
+    Fstar = decayed_normal(np.random.default_rng(seed_target), (n, n), 2.0)
+    rd = np.random.default_rng(seed_dirs)
+    dirs = rd.standard_normal((n_dirs, batch, n, n))
+    dirs /= np.sqrt((dirs ** 2).sum(axis=(1, 2, 3), keepdims=True))
+    return F, Fstar, dirs
+
+
+# --- Chebyshev interpolation of sampled functions (input preparation) -------
+
+def _cheb_points(N: int) -> np.ndarray:
+    # first-kind points x_m = cos((m + 1/2) pi / N)
+    return np.cos((np.arange(N) + 0.5) * np.pi / N)
+
+
+def _dct_coeffs_axis(vals: np.ndarray, axis: int) -> np.ndarray:
+    N = vals.shape[axis]
+    m = np.arange(N)
+    C = np.cos(np.outer(np.arange(N), (m + 0.5) * np.pi / N)) * (2.0 / N)
+    C[0] *= 0.5
+    return np.moveaxis(np.tensordot(C, vals, axes=([1], [axis])), 0, axis)
+
+
+def cheb_coeffs_2d(fun, N: int) -> np.ndarray:
+    """Chebyshev coefficients C[j, k] (T_j(y) T_k(x)) of the degree-(N-1)
+    interpolant of fun(x, y) on the N x N first-kind grid."""
+    x = _cheb_points(N)
+    Y, X = np.meshgrid(x, x, indexing="ij")
+    v = fun(X, Y)
+    return _dct_coeffs_axis(_dct_coeffs_axis(v, 0), 1)
+
+
+def cheb_coeffs_3d(fun, N: int) -> np.ndarray:
+    x = _cheb_points(N)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    v = fun(X, Y, Z)
+    for ax in range(3):
+        v = _dct_coeffs_axis(v, ax)
+    return v
+
+
+def _pad(C: np.ndarray, n: int) -> np.ndarray:
+    out = np.zeros((n,) * C.ndim)
+    sl = tuple(slice(0, min(n, s)) for s in C.shape)
+    out[sl] = C[sl]
+    return out
+
+
+def manufactured_square(n: int, N: int = 128):
+    """u = (1-x^2)(1-y^2) exp(sin 3x cos 2y) and f = Lap u.
+
+    Returns (F, u_fun): F are the n x n Chebyshev coefficients of f (the
+    degree-(N-1) interpolant, truncated or zero-padded to n), u_fun(x, y)
+    evaluates the exact solution."""
+    def u_fun(x, y):
+        return (1 - x * x) * (1 - y * y) * np.exp(np.sin(3 * x) * np.cos(2 * y))
+
+    def f_fun(x, y):
+        a, b = 1 - x * x, 1 - y * y
+        s = np.sin(3 * x) * np.cos(2 * y)
+        E = np.exp(s)
+        sx = 3 * np.cos(3 * x) * np.cos(2 * y)
+        sxx = -9 * np.sin(3 * x) * np.cos(2 * y)
+        sy = -2 * np.sin(3 * x) * np.sin(2 * y)
+        syy = -4 * np.sin(3 * x) * np.cos(2 * y)
+        uxx = b * E * (-2 + 2 * (-2 * x) * sx + a * (sx * sx + sxx))
+        uyy = a * E * (-2 + 2 * (-2 * y) * sy + b * (sy * sy + syy))
+        return uxx + uyy
+
+    return _pad(cheb_coeffs_2d(f_fun, N), n), u_fun
+
+
+def manufactured_cube(n: int, N: int = 48):
+    """u = (1-x^2)(1-y^2)(1-z^2) cos(x y z^2) and f = Lap u (Fig. cube)."""
+    def u_fun(x, y, z):
+        return (1 - x * x) * (1 - y * y) * (1 - z * z) * np.cos(x * y * z * z)
+
+    def f_fun(x, y, z):
+        a, b, c = 1 - x * x, 1 - y * y, 1 - z * z
+        t = x * y * z * z
+        C, S = np.cos(t), np.sin(t)
+        tx, txx = y * z * z, 0.0
+        ty, tyy = x * z * z, 0.0
+        tz, tzz = 2 * x * y * z, 2 * x * y
+        # g = cos(t): g' = -S t', g'' = -C t'^2 - S t''
+        gx, gxx = -S * tx, -C * tx * tx - S * txx
+        gy, gyy = -S * ty, -C * ty * ty - S * tyy
+        gz, gzz = -S * tz, -C * tz * tz - S * tzz
+        uxx = b * c * (-2 * C + 2 * (-2 * x) * gx + a * gxx)
+        uyy = a * c * (-2 * C + 2 * (-2 * y) * gy + b * gyy)
+        uzz = a * b * (-2 * C + 2 * (-2 * z) * gz + c * gzz)
+        return uxx + uyy + uzz
+
+    return _pad(cheb_coeffs_3d(f_fun, N), n), u_fun
+
+
+def oscillatory_square_rhs(n: int, N: int = 256) -> np.ndarray:
+    """f = -100 x sin(20 pi x^2 y) cos(4 pi (x + y)) (Fig. square, left)."""
+    def f_fun(x, y):
+        return -100 * x * np.sin(20 * np.pi * x * x * y) * np.cos(4 * np.pi * (x + y))
+    return _pad(cheb_coeffs_2d(f_fun, N), n)
