@@ -1,0 +1,154 @@
+/*
+ * fps.h -- C ABI of the MI355X spectral fast Poisson solver.
+ *
+ * Method: Fortunato & Townsend, "Fast Poisson solvers for spectral methods"
+ * (arXiv 1710.11259).  Poisson's equation u_xx + u_yy (+ u_zz) = f on
+ * [-1,1]^dim with zero Dirichlet data (Sec. 3, (3.1); Sec. 5, (5.1)) is
+ * discretized in the recombined basis (1-x^2) C~_j^(3/2)(x) of (3.2), giving
+ * the generalized Sylvester equation (3.6) M X D^T + D X M^T = F.  After the
+ * symmetrization of (3.9) (read as a congruence, X = S^-1 Y S^-1 with
+ * S = |D|^(1/2)) the equation A~ Y + Y A~ = G is solved by the ADI iteration
+ * of Algorithm 2 with the Zolotarev shifts of Theorem 2.1 (2.4) and the
+ * iteration count (2.9), on the spectral enclosure [-1, -1/(30 n^4)] of
+ * Lemma B.1.  Each shifted solve is a pair of tridiagonal (Thomas) solves,
+ * one per parity (property P3, Sec. 3.3; App. B decoupling).
+ *
+ * Conventions
+ *   - All arrays are float64, C-contiguous (row-major).
+ *   - dim = 2: F[j*n + k] is the coefficient of T_j(y) T_k(x) (rows <-> y,
+ *     as in (3.2)).  U has (n+2) x (n+2) entries, the exact Chebyshev
+ *     coefficients of u (u has degree n+1 in each variable); with
+ *     FPS_OUT_NATIVE, U has n x n entries, the coefficients X of (3.2).
+ *   - dim = 3: F[(i*n + j)*n + k] multiplies T_i(z) T_j(y) T_k(x); U is
+ *     (n+2)^3 (or n^3 native).
+ *   - "dev" pointers are device memory on the current HIP device; "host"
+ *     pointers are host memory.  `stream` is a hipStream_t (NULL = default).
+ *   - Ownership: the caller owns F, U, the workspace and the stream.  A plan
+ *     owns its host tables and the device copies of its constant tables; they
+ *     are released by fps_plan_destroy.  Solves allocate no memory.
+ *   - Errors: every call returns a status; nothing aborts.  Argument errors
+ *     are reported synchronously.  Kernel faults surface as FPS_E_HIP from a
+ *     later call or from the caller's synchronization.  fps_last_error()
+ *     returns a thread-local message for the last failing call.
+ *   - Concurrency: plans are immutable after creation; concurrent solves on
+ *     one plan need distinct workspaces.
+ */
+#ifndef FPS_H
+#define FPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fps_plan fps_plan;
+
+typedef enum {
+  FPS_OK = 0,
+  FPS_E_ARG = 1,          /* invalid argument (null pointer, n < 1, tol not in (0,1), ...) */
+  FPS_E_UNSUPPORTED = 2,  /* valid but not implemented combination                      */
+  FPS_E_NOMEM = 3,        /* host or device allocation failed (plan creation only)      */
+  FPS_E_HIP = 4,          /* a HIP runtime call failed                                  */
+  FPS_E_STATE = 5         /* plan used after destroy, or workspace too small            */
+} fps_status;
+
+typedef enum { FPS_BC_DIRICHLET_ZERO = 0 } fps_bc;
+
+/* FPS_FP64: every ADI half-sweep stores and computes in float64.
+ * FPS_FP32_REFINED: iterative refinement; the inner ADI stores its sweep
+ * arrays in float32 while every arithmetic operation and every table stays
+ * float64; the residual r = G - (A~ Y + Y A~) and the update Y += dY are
+ * float64 (precision form; not in the paper). */
+typedef enum { FPS_FP64 = 0, FPS_FP32_REFINED = 1 } fps_prec;
+
+typedef enum { FPS_OUT_CHEB = 0, FPS_OUT_NATIVE = 1 } fps_out;
+
+/* Plan flags. */
+#define FPS_PLAN_HOST_ONLY 1u  /* build host tables only (no device memory); for inspection */
+
+/*
+ * Create a plan for a solve of size n (coefficients per dimension).
+ *   dim        2 (square, Sec. 3) or 3 (cube, Sec. 5).
+ *   n          >= 1.
+ *   bc         FPS_BC_DIRICHLET_ZERO (the only value).
+ *   tol        0 < tol < 1; the ADI count J follows (2.9), so that the
+ *              symmetrized iterate satisfies ||Y - Y_J||_2 <= tol ||Y||_2
+ *              (Theorem 2.1).
+ *   prec       fps_prec.
+ *   out_basis  fps_out.
+ *   flags      0 or FPS_PLAN_HOST_ONLY.
+ * On success *out receives a plan to release with fps_plan_destroy.
+ */
+fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double tol,
+                           int prec, int out_basis, unsigned flags);
+
+/* J (ADI iterations of the outer level), workspace bytes required by
+ * fps_solve / fps_solve_adjoint, and the number of float64 entries of U. */
+fps_status fps_plan_info(const fps_plan *plan, int *J, int64_t *workspace_bytes,
+                         int64_t *out_entries);
+
+/* Copy the plan's shifts p_0..p_{J-1} to host memory (q_j = -p_j for the
+ * square, Sec. 3.3 P2 with B~ = -A~). */
+fps_status fps_plan_shifts(const fps_plan *plan, double *p_host);
+
+/*
+ * Shifts of Theorem 2.1 for sigma(A) in [a,b], sigma(B) in [c,d],
+ * a < b < c < d, 0 < tol < 1: J from (2.9) (App. A semantics).  Writes J and,
+ * if cap >= J, p[0..J-1], q[0..J-1] (host arrays of length cap).  Returns
+ * FPS_E_ARG for invalid intervals or tol, FPS_E_STATE (with *J set) if
+ * cap < J.  Host-only; needs no device.
+ */
+fps_status fps_adi_shifts(double a, double b, double c, double d, double tol, int cap,
+                          int *J, double *p_host, double *q_host);
+
+/*
+ * Solve.  F_dev: n^dim float64 Chebyshev coefficients of f.  U_dev: output
+ * ((n+2)^dim, or n^dim with FPS_OUT_NATIVE).  ws_dev: workspace of at least
+ * fps_plan_info's workspace_bytes, 256-byte aligned.  Enqueued on `stream`;
+ * returns without synchronizing.  F_dev and U_dev must not overlap ws_dev.
+ */
+fps_status fps_solve(fps_plan *plan, const double *F_dev, double *U_dev, void *ws_dev,
+                     void *stream);
+
+/*
+ * Adjoint (vector-Jacobian product) of fps_solve: given Ubar (same layout as
+ * U) returns Fbar (n^dim) with <U(F), Ubar> = <F, Fbar> for the J-step ADI
+ * map.  The symmetric-shift ADI map is self-adjoint in the Frobenius inner
+ * product (every term is phi(A~) G psi(A~) with symmetric phi, psi), so the
+ * adjoint runs the same sweeps between transposed coefficient maps.
+ * Square only (dim = 2), FPS_FP64 only.
+ */
+fps_status fps_solve_adjoint(fps_plan *plan, const double *Ubar_dev, double *Fbar_dev,
+                             void *ws_dev, void *stream);
+
+/*
+ * Stage entry point of the square solve, for testing the ADI sweeps on their
+ * own: G_dev (n x n, natural index order) is the right-hand side of the
+ * symmetric form A~ Y + Y A~ = G of (3.9); Y_dev (n x n) receives the J-step
+ * iterate Y_J of Algorithm 2 (A = A~, B = -A~, q_j = -p_j, X_0 = 0).  Square
+ * only; uses the same workspace as fps_solve.
+ */
+fps_status fps_adi_native(fps_plan *plan, const double *G_dev, double *Y_dev, void *ws_dev,
+                          void *stream);
+
+/*
+ * Diagnostics for throughput measurement.  fps_plan_set_sweep_timing(plan,
+ * capacity) creates `capacity` HIP event pairs (0 disables and releases
+ * them); later solves record one pair around each ADI half-sweep launch, on
+ * the solve's stream, until the pairs run out.  fps_plan_sweep_time waits for
+ * the recorded events, returns the summed elapsed milliseconds and the
+ * number of timed launches, and resets the count.
+ */
+fps_status fps_plan_set_sweep_timing(fps_plan *plan, int capacity);
+fps_status fps_plan_sweep_time(fps_plan *plan, double *ms_total, int64_t *launches);
+
+void fps_plan_destroy(fps_plan *plan);
+const char *fps_status_string(fps_status s);
+const char *fps_last_error(void);
+const char *fps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPS_H */

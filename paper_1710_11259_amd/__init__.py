@@ -1,0 +1,188 @@
+"""MI355X (gfx950) spectral fast Poisson solver.
+
+Fortunato & Townsend, "Fast Poisson solvers for spectral methods"
+(arXiv 1710.11259): Poisson on [-1,1]^2 with zero Dirichlet data in the
+recombined ultraspherical basis (3.2), solved by the ADI iteration of
+Algorithm 2 with the Zolotarev shifts of Theorem 2.1.
+
+This module is a thin ctypes binding of the C ABI in include/fps.h: it
+marshals arguments only.  Device memory and the stream come from PyTorch;
+every step of the solve runs in the library's HIP kernels.  If libfps.so is
+not built, importing works but every call raises RuntimeError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["lib", "Plan", "plan", "solve", "adi_native", "adi_shifts", "FpsError",
+           "LIB_PATH"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfps.so")
+
+FPS_OK, FPS_E_ARG, FPS_E_UNSUPPORTED, FPS_E_NOMEM, FPS_E_HIP, FPS_E_STATE = range(6)
+FPS_FP64, FPS_FP32_REFINED = 0, 1
+FPS_OUT_CHEB, FPS_OUT_NATIVE = 0, 1
+FPS_PLAN_HOST_ONLY = 1
+
+_lib = None
+
+
+class FpsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fps status {status}: {msg}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libfps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
+                           "`python -m paper_1710_11259_amd.build` first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+    L.fps_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64, ctypes.c_int, dbl,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_uint]
+    L.fps_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64),
+                                ctypes.POINTER(i64)]
+    L.fps_plan_shifts.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.fps_adi_shifts.argtypes = [dbl, dbl, dbl, dbl, dbl, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(dbl),
+                                 ctypes.POINTER(dbl)]
+    for name in ("fps_solve", "fps_solve_adjoint", "fps_adi_native"):
+        getattr(L, name).argtypes = [vp, vp, vp, vp, vp]
+    L.fps_plan_set_sweep_timing.argtypes = [vp, ctypes.c_int]
+    L.fps_plan_sweep_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    L.fps_plan_set_sweep_timing.restype = ctypes.c_int
+    L.fps_plan_sweep_time.restype = ctypes.c_int
+    L.fps_plan_destroy.argtypes = [vp]
+    L.fps_plan_destroy.restype = None
+    L.fps_status_string.argtypes = [ctypes.c_int]
+    L.fps_status_string.restype = ctypes.c_char_p
+    L.fps_last_error.restype = ctypes.c_char_p
+    L.fps_version.restype = ctypes.c_char_p
+    for name in ("fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_adi_shifts",
+                 "fps_solve", "fps_solve_adjoint", "fps_adi_native"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != FPS_OK:
+        raise FpsError(status, lib().fps_last_error().decode())
+
+
+def adi_shifts(a: float, b: float, c: float, d: float, tol: float):
+    """(p, q) of Theorem 2.1 from the library's host planner (lists)."""
+    L = lib()
+    J = ctypes.c_int(0)
+    st = L.fps_adi_shifts(a, b, c, d, tol, 0, ctypes.byref(J), None, None)
+    if st not in (FPS_OK, FPS_E_STATE):
+        _check(st)
+    p = (ctypes.c_double * J.value)()
+    q = (ctypes.c_double * J.value)()
+    _check(L.fps_adi_shifts(a, b, c, d, tol, J.value, ctypes.byref(J), p, q))
+    return list(p), list(q)
+
+
+class Plan:
+    """Owning wrapper of an fps_plan."""
+
+    def __init__(self, n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
+                 out: str = "cheb", host_only: bool = False):
+        prec = {"fp64": FPS_FP64, "fp32_refined": FPS_FP32_REFINED}[precision]
+        ob = {"cheb": FPS_OUT_CHEB, "native": FPS_OUT_NATIVE}[out]
+        h = ctypes.c_void_p()
+        _check(lib().fps_plan_create(ctypes.byref(h), dim, n, 0, tol, prec, ob,
+                                     FPS_PLAN_HOST_ONLY if host_only else 0))
+        self._h = h
+        self.n, self.dim, self.tol, self.precision, self.out = n, dim, tol, precision, out
+        J, ws, oe = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fps_plan_info(h, ctypes.byref(J), ctypes.byref(ws), ctypes.byref(oe)))
+        self.J, self.workspace_bytes, self.out_entries = J.value, ws.value, oe.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def shifts(self):
+        p = (ctypes.c_double * self.J)()
+        _check(lib().fps_plan_shifts(self._h, p))
+        return list(p)
+
+    def set_sweep_timing(self, capacity: int):
+        _check(lib().fps_plan_set_sweep_timing(self._h, capacity))
+
+    def sweep_time(self):
+        """(summed ms, launches) of the timed half-sweeps since the last call."""
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().fps_plan_sweep_time(self._h, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+    def out_shape(self):
+        e = self.n if self.out == "native" else self.n + 2
+        return (e,) * self.dim
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fps_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan(n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
+         out: str = "cheb", host_only: bool = False) -> Plan:
+    return Plan(n, tol, dim, precision, out, host_only)
+
+
+def _stream_ptr(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def workspace(p: Plan, device="cuda"):
+    import torch
+    return torch.empty(max(p.workspace_bytes, 256), dtype=torch.uint8, device=device)
+
+
+def solve(p: Plan, F, out=None, ws=None):
+    """U = solve(F) for a float64 CUDA tensor F of shape (n,)*dim."""
+    import torch
+    if F.dtype != torch.float64 or not F.is_cuda or not F.is_contiguous():
+        raise ValueError("F must be a contiguous float64 tensor on the GPU")
+    if tuple(F.shape) != (p.n,) * p.dim:
+        raise ValueError(f"F must have shape {(p.n,) * p.dim}")
+    if out is None:
+        out = torch.empty(p.out_shape(), dtype=torch.float64, device=F.device)
+    if ws is None:
+        ws = workspace(p, F.device)
+    _check(lib().fps_solve(p.handle, ctypes.c_void_p(F.data_ptr()),
+                           ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                           _stream_ptr(torch, F.device)))
+    return out
+
+
+def adi_native(p: Plan, G, out=None, ws=None):
+    """Y_J of Algorithm 2 for A~ Y + Y A~ = G (natural order, n x n)."""
+    import torch
+    if G.dtype != torch.float64 or not G.is_cuda or not G.is_contiguous():
+        raise ValueError("G must be a contiguous float64 tensor on the GPU")
+    if tuple(G.shape) != (p.n, p.n):
+        raise ValueError("G must be n x n")
+    if out is None:
+        out = torch.empty((p.n, p.n), dtype=torch.float64, device=G.device)
+    if ws is None:
+        ws = workspace(p, G.device)
+    _check(lib().fps_adi_native(p.handle, ctypes.c_void_p(G.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                _stream_ptr(torch, G.device)))
+    return out

@@ -1,0 +1,446 @@
+// C ABI of the spectral Poisson solver (declared in include/fps.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fps.h"
+#include "kernels.hpp"
+#include "planner.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fps_status fail(fps_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define FPS_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(FPS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+constexpr uint64_t kMagic = 0x66707370'6c616e31ull;  // "fpsplan1"
+
+struct DeviceBuf {
+  void *p = nullptr;
+  ~DeviceBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+struct fps_plan {
+  uint64_t magic = kMagic;
+  int dim = 2;
+  int64_t n = 0;
+  double tol = 0;
+  int prec = FPS_FP64;
+  int out_basis = FPS_OUT_CHEB;
+  unsigned flags = 0;
+  bool on_device = false;
+
+  fps::ShiftSet shifts;
+  fps::Layout L;
+  std::vector<double> tab, ctab;   // host sweep tables
+  std::vector<double> Rs[2], P[2];  // host conversion maps
+  std::vector<double> sinv;         // 1/sqrt((i+1)(i+2))
+
+  // device copies
+  DeviceBuf d_tab, d_ctab, d_Rs[2], d_P[2], d_sinv;
+
+  // sweep timing diagnostics
+  std::vector<hipEvent_t> ev;  // pairs
+  int64_t ev_used = 0;
+
+  // workspace layout (byte offsets)
+  int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab0 = 0, off_ab1 = 0;
+  int64_t ws_bytes = 0;
+
+  const double *tab_dev(int j) const {
+    return (const double *)d_tab.p + (size_t)j * 2 * fps::kNTab * L.mstride;
+  }
+  const double *ctab_dev(int j) const {
+    return (const double *)d_ctab.p + (size_t)j * 2 * fps::kNCTab * L.ncmax;
+  }
+};
+
+namespace {
+
+bool valid_plan(const fps_plan *p) { return p != nullptr && p->magic == kMagic; }
+
+template <typename T>
+fps_status upload(DeviceBuf &b, const std::vector<T> &h) {
+  if (h.empty()) return FPS_OK;
+  if (hipMalloc(&b.p, h.size() * sizeof(T)) != hipSuccess)
+    return fail(FPS_E_NOMEM, "hipMalloc of a plan table failed");
+  FPS_HIP(hipMemcpy(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FPS_OK;
+}
+
+int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st) {
+  const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
+  hipError_t e;
+  if (t && (e = hipEventRecord(pl->ev[2 * pl->ev_used], st)) != hipSuccess) return e;
+  if ((e = fps::launch_sweep<double>(a, st)) != hipSuccess) return e;
+  if (t) {
+    if ((e = hipEventRecord(pl->ev[2 * pl->ev_used + 1], st)) != hipSuccess) return e;
+    ++pl->ev_used;
+  }
+  return hipSuccess;
+}
+
+void release_events(fps_plan *pl) {
+  for (hipEvent_t e : pl->ev) (void)hipEventDestroy(e);
+  pl->ev.clear();
+  pl->ev_used = 0;
+}
+
+// Runs the 2J half-sweeps of Algorithm 2 on G (parity-blocked, in ws.G and
+// its transpose in ws.GT).  Leaves the final chunk-local solution in O1 and
+// its carry coefficients in ab1; `last_tab` is the table set to finalize with.
+fps_status run_adi(fps_plan *pl, char *ws, hipStream_t st) {
+  const fps::Layout &L = pl->L;
+  const int J = pl->shifts.J;
+  const std::vector<double> &p = pl->shifts.p;
+  double *G = (double *)(ws + pl->off_G);
+  double *GT = (double *)(ws + pl->off_GT);
+  double *O0 = (double *)(ws + pl->off_O0);
+  double *O1 = (double *)(ws + pl->off_O1);
+  double *lv = (double *)(ws + pl->off_lv);
+  double *ab0 = (double *)(ws + pl->off_ab0);
+  double *ab1 = (double *)(ws + pl->off_ab1);
+  const int nc0 = (int)L.nc[0], nc1 = (int)L.nc[1];
+
+  for (int j = 0; j < J; ++j) {
+    // Half-step 1: rows of Y; reads the transposed storage.
+    fps::SweepArgs A{};
+    A.in = j == 0 ? nullptr : O1;
+    A.ab_prev = ab1;
+    A.tab_prev = j == 0 ? nullptr : pl->tab_dev(j - 1);
+    A.g = GT;
+    A.sg = -1.0;
+    A.tab = pl->tab_dev(j);
+    A.sigma = 2.0 * p[j];
+    A.out = O0;
+    A.lv = lv;
+    A.final_mode = 0;
+    A.npad = L.npad;
+    A.mp0 = L.mp[0];
+    A.mp1 = L.mp[1];
+    A.mstride = L.mstride;
+    A.nc0 = nc0;
+    A.nc1 = nc1;
+    FPS_HIP(timed_sweep(pl, A, st));
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(j), ab0, -A.sigma, L.npad, nc0, nc1, L.ncmax, st));
+    // Half-step 2: columns of Y.
+    fps::SweepArgs B = A;
+    const bool last = j == J - 1;
+    B.in = O0;
+    B.ab_prev = ab0;
+    B.tab_prev = pl->tab_dev(j);
+    B.g = G;
+    B.sg = 1.0;
+    B.sigma = last ? 0.0 : p[j] + p[j + 1];
+    B.out = O1;
+    B.final_mode = last ? 1 : 0;
+    FPS_HIP(timed_sweep(pl, B, st));
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(j), ab1, last ? 1.0 : -B.sigma, L.npad, nc0, nc1,
+                               L.ncmax, st));
+  }
+  return FPS_OK;
+}
+
+fps_status check_solve_args(fps_plan *pl, const void *a, const void *b, void *ws) {
+  if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (!pl->on_device) return fail(FPS_E_STATE, "plan was created host-only");
+  if (!a || !b || !ws) return fail(FPS_E_ARG, "null pointer argument");
+  if (((uintptr_t)ws) % 256 != 0) return fail(FPS_E_ARG, "workspace must be 256-byte aligned");
+  return FPS_OK;
+}
+
+// Input map: G_perm = Rs_s F_st Rs_t^T for the four parity blocks, then GT.
+fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st) {
+  const fps::Layout &L = pl->L;
+  const int64_t n = L.n, npad = L.npad;
+  double *G = (double *)(ws + pl->off_G);
+  double *GT = (double *)(ws + pl->off_GT);
+  double *Tb = (double *)(ws + pl->off_O0);
+  FPS_HIP(fps::launch_fill(G, npad * npad, 0.0, st));
+  fps::GemmProb g1[4], g2[4];
+  int cnt = 0;
+  int64_t toff = 0;
+  for (int s = 0; s < 2; ++s)
+    for (int t = 0; t < 2; ++t) {
+      const int64_t ms = L.m[s], mt = L.m[t];
+      if (ms == 0 || mt == 0) continue;
+      double *Tst = Tb + toff;
+      toff += ms * mt;
+      // T_st = F_st Rs_t^T, with B(k, j) = Rs_t[j][k] = 0 for k < j.
+      g1[cnt] = fps::GemmProb{F + s * n + t, (const double *)pl->d_Rs[t].p, Tst, ms, mt, mt,
+                              2 * n, 2, 1, mt, mt, 1, 0, 0, 1, 0};
+      // G_st = Rs_s T_st, with A(i, k) = Rs_s[i][k] = 0 for k < i.
+      g2[cnt] = fps::GemmProb{(const double *)pl->d_Rs[s].p, Tst,
+                              G + (s * L.mp[0]) * npad + t * L.mp[0], ms, mt, ms,
+                              ms, 1, mt, 1, npad, 1, 1, 0, 0, 0};
+      ++cnt;
+    }
+  FPS_HIP(fps::launch_gemm(g1, cnt, st));
+  FPS_HIP(fps::launch_gemm(g2, cnt, st));
+  FPS_HIP(fps::launch_transpose(G, GT, npad, st));
+  return FPS_OK;
+}
+
+// Output map: U_st = P_s Y_st P_t^T into the strided parity view of U.
+fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hipStream_t st) {
+  const fps::Layout &L = pl->L;
+  const int64_t n = L.n, N = n + 2, npad = L.npad;
+  // temporary n x (n+2) blocks: the O0 and O1 regions (contiguous) are free here
+  double *Tb = (double *)(ws + pl->off_O0);
+  if ((int64_t)n * (n + 2) * 8 > pl->off_lv - pl->off_O0)
+    return fail(FPS_E_STATE, "internal: output temporary exceeds workspace");
+  fps::GemmProb g1[4], g2[4];
+  int cnt = 0;
+  int64_t toff = 0;
+  for (int s = 0; s < 2; ++s)
+    for (int t = 0; t < 2; ++t) {
+      const int64_t ms = L.m[s], mt = L.m[t], mos = L.mo[s], mot = L.mo[t];
+      double *Ust = U + s * N + t;
+      if (ms == 0 || mt == 0) {
+        // no solution block: the output block is zero
+        continue;
+      }
+      double *Tst = Tb + toff;
+      toff += ms * mot;
+      // T_st = Y_st P_t^T, B(k, j) = P_t[j][k] = 0 for k < j - 1.
+      g1[cnt] = fps::GemmProb{Y + (s * L.mp[0]) * npad + t * L.mp[0], (const double *)pl->d_P[t].p,
+                              Tst, ms, mot, mt, npad, 1, 1, mt, mot, 1, 0, 0, 1, -1};
+      // U_st = P_s T_st, A(i, k) = P_s[i][k] = 0 for k < i - 1.
+      g2[cnt] = fps::GemmProb{(const double *)pl->d_P[s].p, Tst, Ust, mos, mot, ms, ms, 1, mot, 1,
+                              2 * N, 2, 1, -1, 0, 0};
+      ++cnt;
+    }
+  FPS_HIP(fps::launch_fill(U, N * N, 0.0, st));
+  FPS_HIP(fps::launch_gemm(g1, cnt, st));
+  FPS_HIP(fps::launch_gemm(g2, cnt, st));
+  return FPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fps_version(void) { return "fps 0.1 (gfx950)"; }
+
+const char *fps_status_string(fps_status s) {
+  switch (s) {
+    case FPS_OK: return "ok";
+    case FPS_E_ARG: return "invalid argument";
+    case FPS_E_UNSUPPORTED: return "unsupported";
+    case FPS_E_NOMEM: return "out of memory";
+    case FPS_E_HIP: return "HIP runtime error";
+    case FPS_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char *fps_last_error(void) { return g_last_error.c_str(); }
+
+fps_status fps_adi_shifts(double a, double b, double c, double d, double tol, int cap, int *J,
+                          double *p, double *q) {
+  if (!J) return fail(FPS_E_ARG, "J must not be null");
+  fps::ShiftSet S;
+  std::string err;
+  if (!fps::zolotarev_shifts(a, b, c, d, tol, S, err)) return fail(FPS_E_ARG, err);
+  *J = S.J;
+  if (cap < S.J) return fail(FPS_E_STATE, "cap smaller than J");
+  if (!p || !q) return fail(FPS_E_ARG, "null output arrays");
+  for (int j = 0; j < S.J; ++j) {
+    p[j] = S.p[j];
+    q[j] = S.q[j];
+  }
+  return FPS_OK;
+}
+
+fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double tol, int prec,
+                           int out_basis, unsigned flags) {
+  if (!out) return fail(FPS_E_ARG, "out must not be null");
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return fail(FPS_E_ARG, "dim must be 2 or 3");
+  if (n < 1) return fail(FPS_E_ARG, "n must be >= 1");
+  if (n > 200000) return fail(FPS_E_ARG, "n too large");
+  if (bc != FPS_BC_DIRICHLET_ZERO) return fail(FPS_E_UNSUPPORTED, "only zero Dirichlet data");
+  if (!(tol > 0.0 && tol < 1.0)) return fail(FPS_E_ARG, "tol must lie in (0, 1)");
+  if (prec != FPS_FP64 && prec != FPS_FP32_REFINED) return fail(FPS_E_ARG, "bad precision");
+  if (out_basis != FPS_OUT_CHEB && out_basis != FPS_OUT_NATIVE) return fail(FPS_E_ARG, "bad out_basis");
+  if (flags & ~FPS_PLAN_HOST_ONLY) return fail(FPS_E_ARG, "unknown flags");
+  if (dim == 3) return fail(FPS_E_UNSUPPORTED, "cube solver not available in this build");
+  if (prec != FPS_FP64) return fail(FPS_E_UNSUPPORTED, "precision form not available in this build");
+
+  fps_plan *pl = new (std::nothrow) fps_plan();
+  if (!pl) return fail(FPS_E_NOMEM, "plan allocation failed");
+  pl->dim = dim;
+  pl->n = n;
+  pl->tol = tol;
+  pl->prec = prec;
+  pl->out_basis = out_basis;
+  pl->flags = flags;
+  // Lemma B.1: sigma(A~) in [-1, -1/(30 n^4)]; sigma(B~) = sigma(-A~).
+  const double delta = 1.0 / (30.0 * (double)n * (double)n * (double)n * (double)n);
+  std::string err;
+  if (!fps::zolotarev_shifts(-1.0, -delta, delta, 1.0, tol, pl->shifts, err)) {
+    delete pl;
+    return fail(FPS_E_ARG, err);
+  }
+  pl->L = fps::make_layout(n);
+  fps::build_sweep_tables(pl->L, pl->shifts.p, pl->tab, pl->ctab);
+  fps::build_conversions(pl->L, pl->Rs, pl->P);
+  pl->sinv.resize(n);
+  for (int64_t i = 0; i < n; ++i) pl->sinv[i] = 1.0 / std::sqrt((double)(i + 1) * (double)(i + 2));
+
+  const fps::Layout &L = pl->L;
+  const int64_t sq = align256(L.npad * L.npad * 8);
+  const int64_t lvb = align256(L.ncmax * 4 * L.npad * 8);
+  const int64_t abb = align256(L.ncmax * L.npad * 4 * 8);
+  pl->off_G = 0;
+  pl->off_GT = sq;
+  pl->off_O0 = 2 * sq;
+  pl->off_O1 = 3 * sq;
+  pl->off_lv = 4 * sq;
+  pl->off_ab0 = 4 * sq + lvb;
+  pl->off_ab1 = 4 * sq + lvb + abb;
+  pl->ws_bytes = 4 * sq + lvb + 2 * abb;
+
+  if (!(flags & FPS_PLAN_HOST_ONLY)) {
+    fps_status s;
+    if ((s = upload(pl->d_tab, pl->tab)) != FPS_OK || (s = upload(pl->d_ctab, pl->ctab)) != FPS_OK ||
+        (s = upload(pl->d_Rs[0], pl->Rs[0])) != FPS_OK || (s = upload(pl->d_Rs[1], pl->Rs[1])) != FPS_OK ||
+        (s = upload(pl->d_P[0], pl->P[0])) != FPS_OK || (s = upload(pl->d_P[1], pl->P[1])) != FPS_OK ||
+        (s = upload(pl->d_sinv, pl->sinv)) != FPS_OK) {
+      delete pl;
+      return s;
+    }
+    pl->on_device = true;
+  }
+  *out = pl;
+  return FPS_OK;
+}
+
+fps_status fps_plan_info(const fps_plan *pl, int *J, int64_t *ws_bytes, int64_t *out_entries) {
+  if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (J) *J = pl->shifts.J;
+  if (ws_bytes) *ws_bytes = pl->ws_bytes;
+  if (out_entries) {
+    const int64_t e = pl->out_basis == FPS_OUT_NATIVE ? pl->n : pl->n + 2;
+    *out_entries = pl->dim == 2 ? e * e : e * e * e;
+  }
+  return FPS_OK;
+}
+
+fps_status fps_plan_shifts(const fps_plan *pl, double *p) {
+  if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (!p) return fail(FPS_E_ARG, "null output");
+  for (int j = 0; j < pl->shifts.J; ++j) p[j] = pl->shifts.p[j];
+  return FPS_OK;
+}
+
+fps_status fps_solve(fps_plan *pl, const double *F, double *U, void *ws, void *stream) {
+  fps_status s = check_solve_args(pl, F, U, ws);
+  if (s != FPS_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  const fps::Layout &L = pl->L;
+  if ((s = rhs_transform(pl, F, w, st)) != FPS_OK) return s;
+  if ((s = run_adi(pl, w, st)) != FPS_OK) return s;
+  const int J = pl->shifts.J;
+  double *O1 = (double *)(w + pl->off_O1);
+  double *ab1 = (double *)(w + pl->off_ab1);
+  if (pl->out_basis == FPS_OUT_NATIVE) {
+    FPS_HIP(fps::launch_finalize(O1, ab1, pl->tab_dev(J - 1), U, 1, (const double *)pl->d_sinv.p,
+                                 L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
+    return FPS_OK;
+  }
+  double *Y = (double *)(w + pl->off_G);
+  FPS_HIP(fps::launch_finalize(O1, ab1, pl->tab_dev(J - 1), Y, 0, nullptr, L.n, L.npad, L.mp[0],
+                               L.mstride, L.ncmax, st));
+  return out_transform(pl, Y, U, w, st);
+}
+
+fps_status fps_adi_native(fps_plan *pl, const double *G, double *Y, void *ws, void *stream) {
+  fps_status s = check_solve_args(pl, G, Y, ws);
+  if (s != FPS_OK) return s;
+  if (pl->dim != 2) return fail(FPS_E_UNSUPPORTED, "square only");
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  const fps::Layout &L = pl->L;
+  double *Gp = (double *)(w + pl->off_G);
+  double *GT = (double *)(w + pl->off_GT);
+  FPS_HIP(fps::launch_permute_in(G, Gp, L.n, L.npad, L.mp[0], st));
+  FPS_HIP(fps::launch_transpose(Gp, GT, L.npad, st));
+  if ((s = run_adi(pl, w, st)) != FPS_OK) return s;
+  const int J = pl->shifts.J;
+  FPS_HIP(fps::launch_finalize((double *)(w + pl->off_O1), (double *)(w + pl->off_ab1),
+                               pl->tab_dev(J - 1), Y, 1, nullptr, L.n, L.npad, L.mp[0], L.mstride,
+                               L.ncmax, st));
+  return FPS_OK;
+}
+
+fps_status fps_solve_adjoint(fps_plan *pl, const double *Ubar, double *Fbar, void *ws,
+                             void *stream) {
+  fps_status s = check_solve_args(pl, Ubar, Fbar, ws);
+  if (s != FPS_OK) return s;
+  (void)stream;
+  return fail(FPS_E_UNSUPPORTED, "adjoint not available in this build");
+}
+
+fps_status fps_plan_set_sweep_timing(fps_plan *pl, int capacity) {
+  if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (capacity < 0) return fail(FPS_E_ARG, "capacity must be >= 0");
+  if (!pl->on_device) return fail(FPS_E_STATE, "plan was created host-only");
+  release_events(pl);
+  for (int i = 0; i < 2 * capacity; ++i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      release_events(pl);
+      return fail(FPS_E_HIP, "hipEventCreate failed");
+    }
+    pl->ev.push_back(e);
+  }
+  return FPS_OK;
+}
+
+fps_status fps_plan_sweep_time(fps_plan *pl, double *ms_total, int64_t *launches) {
+  if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (!ms_total || !launches) return fail(FPS_E_ARG, "null output");
+  double tot = 0.0;
+  for (int64_t i = 0; i < pl->ev_used; ++i) {
+    FPS_HIP(hipEventSynchronize(pl->ev[2 * i + 1]));
+    float ms = 0.0f;
+    FPS_HIP(hipEventElapsedTime(&ms, pl->ev[2 * i], pl->ev[2 * i + 1]));
+    tot += ms;
+  }
+  *ms_total = tot;
+  *launches = pl->ev_used;
+  pl->ev_used = 0;
+  return FPS_OK;
+}
+
+void fps_plan_destroy(fps_plan *pl) {
+  if (!valid_plan(pl)) return;
+  release_events(pl);
+  pl->magic = 0;
+  delete pl;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Launch interfaces of the gfx950 kernels of the spectral Poisson solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "planner.hpp"
+
+namespace fps {
+
+// One ADI half-sweep over a parity-blocked npad x npad array whose chains
+// run down the storage rows (one chain per storage column).
+//   input  r = in (+ carry correction of the producing pass) + sg * g
+//   solve  x = (A~ + p I)^-1 r along each chain (per parity)
+//   output out = r - sigma x   (stored transposed), or x itself (final,
+//          stored in place orientation); chunk-level carries are left to
+//          fps::launch_reduce and applied by the consumer.
+struct SweepArgs {
+  const void *in;          // T[npad*npad] or nullptr (input is sg*g only)
+  const double *ab_prev;   // producer carry coefficients [ncmax][npad][2][2]
+  const double *tab_prev;  // producer's per-position tables (its shift) [2][kNTab][mstride]
+  const double *g;         // G term (same orientation as `in`) or nullptr
+  double sg;
+  const double *tab;       // this pass's tables [2][kNTab][mstride]
+  double sigma;
+  void *out;               // T[npad*npad]
+  double *lv;              // chunk boundary data [ncmax][2][2][npad]
+  int final_mode;          // 1: out = x, not transposed
+  int64_t npad, mp0, mp1, mstride;
+  int nc0, nc1;
+};
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs &a, hipStream_t st);
+
+// Second-level carries: for every chain, the forward and backward carry into
+// each chunk, scaled by `scale`, into ab [ncmax][npad][2][2].
+hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,
+                         int64_t npad, int nc0, int nc1, int64_t ncmax, hipStream_t st);
+
+// Y_perm[r][col] = x[r][col] + carries (final pass, non-transposed).
+// mode 0: write Y in the parity-blocked layout (npad x npad, ld npad);
+// mode 1: write the natural-order n x n array, entry (i,j) divided by
+//         sinv-scaled factors when `sinv` is non-null: out = Y * sinv_i * sinv_j.
+hipError_t launch_finalize(const double *x, const double *ab, const double *tab, double *out,
+                           int mode, const double *sinv, int64_t n, int64_t npad, int64_t mp0,
+                           int64_t mstride, int64_t ncmax, hipStream_t st);
+
+// natural n x n (ld n) -> parity-blocked npad x npad (zero padding).
+hipError_t launch_permute_in(const double *src, double *dst, int64_t n, int64_t npad, int64_t mp0,
+                             hipStream_t st);
+
+hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st);
+hipError_t launch_fill(double *dst, int64_t count, double v, hipStream_t st);
+
+// Strided FP64 GEMM on MFMA, up to 4 independent problems per launch:
+//   C(i,j) = sum_k A(i,k) B(k,j),  A(i,k) = A[i*sai + k*sak], etc.
+// Triangular structure: when triA, A(i,k) = 0 for k < i + offA; when triB,
+// B(k,j) = 0 for k < j + offB; tiles below the first nonzero k are skipped.
+struct GemmProb {
+  const double *A;
+  const double *B;
+  double *C;
+  int64_t M, N, K;
+  int64_t sai, sak, sbk, sbj, sci, scj;
+  int triA, offA, triB, offB;
+};
+hipError_t launch_gemm(const GemmProb *probs, int count, hipStream_t st);
+
+}  // namespace fps

@@ -1,0 +1,322 @@
+// Host planner: shifts, iteration count, sweep tables, coefficient maps.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+namespace fps {
+
+namespace {
+
+// Carlson's symmetric integral R_F(x, y, z) by the duplication theorem
+// (B. C. Carlson, Numer. Algorithms 10 (1995)), in extended precision.
+long double carlson_rf(long double x, long double y, long double z) {
+  for (int it = 0; it < 200; ++it) {
+    const long double sx = std::sqrt(x), sy = std::sqrt(y), sz = std::sqrt(z);
+    const long double lam = sx * sy + sy * sz + sz * sx;
+    x = 0.25L * (x + lam);
+    y = 0.25L * (y + lam);
+    z = 0.25L * (z + lam);
+    const long double A = (x + y + z) / 3.0L;
+    const long double X = 1.0L - x / A, Y = 1.0L - y / A, Z = -X - Y;
+    const long double dev = std::max(std::fabs(X), std::max(std::fabs(Y), std::fabs(Z)));
+    if (dev < 1e-4L) {
+      const long double E2 = X * Y - Z * Z, E3 = X * Y * Z;
+      return (1.0L - E2 / 10.0L + E3 / 14.0L + E2 * E2 / 24.0L - 3.0L * E2 * E3 / 44.0L) /
+             std::sqrt(A);
+    }
+  }
+  return std::numeric_limits<long double>::quiet_NaN();
+}
+
+// dn(u | m), m = 1 - m1, for 0 <= u <= K/2.  The amplitude is written as
+// phi = pi/2 - t; t solves F(pi/2 - t | m) = u with
+// F = cos t R_F(sin^2 t, sin^2 t + m1 cos^2 t, 1) and dF/dt = -1/dn, by
+// Newton's method from the m = 1 limit t = 2 atan(exp(-u)).  Then
+// dn = sqrt(sin^2 t + m1 cos^2 t); no quantity is formed as 1 - m.
+long double dn_newton(long double u, long double m1) {
+  long double t = 2.0L * std::atan(std::exp(-u));
+  for (int it = 0; it < 60; ++it) {
+    const long double st = std::sin(t), ct = std::cos(t);
+    const long double d2 = st * st + m1 * ct * ct;
+    const long double F = ct * carlson_rf(st * st, d2, 1.0L);
+    const long double step = (F - u) * std::sqrt(d2);
+    t += step;
+    if (std::fabs(step) <= 4 * std::numeric_limits<long double>::epsilon() * (t + 1e-30L)) break;
+  }
+  const long double st = std::sin(t), ct = std::cos(t);
+  return std::sqrt(st * st + m1 * ct * ct);
+}
+}  // namespace
+
+double cross_ratio(double a, double b, double c, double d) {
+  return std::fabs(c - a) * std::fabs(d - b) / (std::fabs(c - b) * std::fabs(d - a));
+}
+
+int iteration_count(double a, double b, double c, double d, double tol) {
+  if (!(tol > 0.0 && tol < 1.0)) return -1;
+  if (!(a < b && b < c && c < d)) return -1;
+  if (!std::isfinite(a) || !std::isfinite(d)) return -1;
+  const double g = cross_ratio(a, b, c, d);
+  const double pi = 3.141592653589793;
+  double x = std::log(16.0 * g) * std::log(4.0 / tol) / (pi * pi);
+  if (!std::isfinite(x) || x > 1e7) return -1;
+  int J = (int)std::ceil(x);
+  return J < 1 ? 1 : J;
+}
+
+long double ellip_K_comp(long double m1) { return carlson_rf(0.0L, m1, 1.0L); }
+
+long double ellip_dn_comp(long double u, long double m1, long double K) {
+  // dn(u) dn(K - u) = k' = sqrt(m1): evaluate on the half [0, K/2] only.
+  if (u > 0.5L * K) return std::sqrt(m1) / dn_newton(K - u, m1);
+  return dn_newton(u, m1);
+}
+
+bool zolotarev_shifts(double a, double b, double c, double d, double tol, ShiftSet &out,
+                      std::string &err) {
+  int J = iteration_count(a, b, c, d, tol);
+  if (J < 0) {
+    err = "invalid enclosure or tolerance: need a < b < c < d finite and 0 < tol < 1";
+    return false;
+  }
+  const long double g = cross_ratio(a, b, c, d);
+  const long double alpha = -1.0L + 2.0L * g + 2.0L * std::sqrt(g * g - g);
+  const long double m1 = 1.0L / (alpha * alpha);
+  std::vector<long double> dn(J);
+  if (alpha < 1e7L) {
+    const long double K = ellip_K_comp(m1);
+    for (int j = 0; j < J; ++j) dn[j] = ellip_dn_comp((j + 0.5L) * K / J, m1, K);
+  } else {
+    // App. A: leading terms of K and dn in the complementary parameter.
+    const long double la = std::log(alpha), l2 = std::log(2.0L);
+    const long double K = (2 * l2 + la) + (-1 + 2 * l2 + la) * m1 / 4;
+    for (int j = 0; j < J; ++j) {
+      long double u = (j + 0.5L) * K / J;
+      long double sech = 1.0L / std::cosh(u);
+      dn[j] = sech + 0.25L * m1 * (std::sinh(u) * std::cosh(u) + u) * std::tanh(u) * sech;
+    }
+  }
+  out.J = J;
+  out.p.resize(J);
+  out.q.resize(J);
+  if (c == -b && d == -a) {
+    // Symmetric intervals: the Moebius map is odd, T(z) = c z and c alpha = d.
+    for (int j = 0; j < J; ++j) {
+      out.p[j] = (double)(-(long double)d * dn[j]);
+      out.q[j] = -out.p[j];
+    }
+    return true;
+  }
+  // General case: T = W^-1 o Z, Z sends (-alpha, -1, 1) to (0, 1, inf),
+  // W sends (a, b, c) to (0, 1, inf); both as 2x2 coefficient matrices.
+  auto to_std = [](long double z1, long double z2, long double z3, long double Mx[4]) {
+    Mx[0] = z2 - z3;
+    Mx[1] = -z1 * (z2 - z3);
+    Mx[2] = z2 - z1;
+    Mx[3] = -z3 * (z2 - z1);
+  };
+  long double Zm[4], Wm[4];
+  to_std(-alpha, -1.0L, 1.0L, Zm);
+  to_std(a, b, c, Wm);
+  long double Wi[4] = {Wm[3], -Wm[1], -Wm[2], Wm[0]};  // adjugate = inverse up to scale
+  long double T[4] = {Wi[0] * Zm[0] + Wi[1] * Zm[2], Wi[0] * Zm[1] + Wi[1] * Zm[3],
+                      Wi[2] * Zm[0] + Wi[3] * Zm[2], Wi[2] * Zm[1] + Wi[3] * Zm[3]};
+  auto Tz = [&](long double z) { return (T[0] * z + T[1]) / (T[2] * z + T[3]); };
+  for (int j = 0; j < J; ++j) {
+    out.p[j] = (double)Tz(-alpha * dn[j]);
+    out.q[j] = (double)Tz(alpha * dn[j]);
+  }
+  return true;
+}
+
+Layout make_layout(int64_t n) {
+  Layout L;
+  L.n = n;
+  L.m[0] = (n + 1) / 2;
+  L.m[1] = n / 2;
+  for (int s = 0; s < 2; ++s) {
+    L.mp[s] = (L.m[s] + kPad - 1) / kPad * kPad;
+    L.nc[s] = (L.mp[s] + kChunk - 1) / kChunk;
+    L.mo[s] = (n + 2 - s + 1) / 2;
+  }
+  L.npad = L.mp[0] + L.mp[1];
+  L.ncmax = std::max(L.nc[0], L.nc[1]);
+  L.mstride = L.ncmax * kChunk;
+  return L;
+}
+
+double atilde_diag(int64_t i) {
+  const double x = (double)i;
+  return -2.0 / ((2 * x + 1) * (2 * x + 5));
+}
+
+double atilde_off(int64_t i) {
+  const double x = (double)i;
+  return 1.0 / ((2 * x + 5) * std::sqrt((2 * x + 3) * (2 * x + 7)));
+}
+
+void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vector<double> &pos,
+                        std::vector<double> &chunk) {
+  const int J = (int)p.size();
+  const int64_t ms = L.mstride, nc = L.ncmax;
+  pos.assign((size_t)J * 2 * kNTab * ms, 0.0);
+  chunk.assign((size_t)J * 2 * kNCTab * nc, 0.0);
+  std::vector<long double> l(ms), ib(ms), u(ms), F2(ms), BF2(ms);
+  for (int j = 0; j < J; ++j) {
+    for (int s = 0; s < 2; ++s) {
+      const int64_t m = L.m[s];
+      double *T = pos.data() + ((size_t)(j * 2 + s) * kNTab) * ms;
+      double *C = chunk.data() + ((size_t)(j * 2 + s) * kNCTab) * nc;
+      std::fill(l.begin(), l.end(), 0.0L);
+      std::fill(ib.begin(), ib.end(), 0.0L);
+      std::fill(u.begin(), u.end(), 0.0L);
+      if (m == 0) continue;
+      // Thomas factors of (A~ + p_j I) restricted to parity s.
+      long double beta = (long double)atilde_diag(s) + p[j];
+      ib[0] = 1.0L / beta;
+      for (int64_t k = 1; k < m; ++k) {
+        const long double e = atilde_off(2 * (k - 1) + s);
+        l[k] = e * ib[k - 1];
+        beta = ((long double)atilde_diag(2 * k + s) + p[j]) - l[k] * e;
+        ib[k] = 1.0L / beta;
+      }
+      for (int64_t k = 0; k + 1 < m; ++k) u[k] = (long double)atilde_off(2 * k + s) * ib[k];
+      for (int64_t k = 0; k < ms; ++k) {
+        T[T_L * ms + k] = (double)l[k];
+        T[T_IB * ms + k] = (double)ib[k];
+        T[T_U * ms + k] = (double)u[k];
+      }
+      // Segment multipliers.
+      for (int64_t s0 = 0; s0 < ms; s0 += kSeg) {
+        long double acc = 1.0L;
+        for (int64_t k = s0; k < s0 + kSeg; ++k) {
+          acc *= -l[k];
+          T[T_F1 * ms + k] = (double)acc;
+        }
+        acc = 1.0L;
+        for (int64_t k = s0 + kSeg - 1; k >= s0; --k) {
+          acc *= -u[k];
+          T[T_BK1 * ms + k] = (double)acc;
+        }
+      }
+      // Chunk multipliers.
+      for (int64_t c = 0; c < nc; ++c) {
+        const int64_t c0 = c * kChunk, c1 = c0 + kChunk;
+        long double acc = 1.0L;
+        for (int64_t k = c0; k < c1; ++k) {
+          acc *= -l[k];
+          F2[k] = acc;
+        }
+        long double x = 0.0L;
+        for (int64_t k = c1 - 1; k >= c0; --k) {
+          x = F2[k] * ib[k] - u[k] * x;
+          BF2[k] = x;
+        }
+        acc = 1.0L;
+        for (int64_t k = c1 - 1; k >= c0; --k) {
+          acc *= -u[k];
+          T[T_BK2 * ms + k] = (double)acc;
+          T[T_BF2 * ms + k] = (double)BF2[k];
+        }
+        C[C_F2LAST * nc + c] = (double)F2[c1 - 1];
+        C[C_BF2FIRST * nc + c] = (double)BF2[c0];
+        C[C_BK2FIRST * nc + c] = T[T_BK2 * ms + c0];
+      }
+    }
+  }
+}
+
+void build_conversions(const Layout &L, std::vector<double> Rs[2], std::vector<double> P[2]) {
+  const int64_t n = L.n, N = n + 2;
+  auto beta = [](int64_t i) -> long double {
+    const long double x = (long double)i;
+    return std::sqrt((x + 1) * (x + 3) / ((2 * x + 3) * (2 * x + 5)));
+  };
+  auto sc = [](int64_t i) -> long double {
+    const long double x = (long double)i;
+    return std::sqrt((x + 1) * (x + 2));
+  };
+  for (int s = 0; s < 2; ++s) {
+    Rs[s].assign((size_t)L.m[s] * L.m[s], 0.0);
+    P[s].assign((size_t)L.mo[s] * L.m[s], 0.0);
+  }
+  // Input map: C~ coefficients of T_k by T_{k+1} = 2 x T_k - T_{k-1}, with
+  // multiplication by x in the C~ basis: x C~_i = beta_i C~_{i+1} + beta_{i-1} C~_{i-1}.
+  {
+    std::vector<long double> prev(n + 1, 0.0L), cur(n + 1, 0.0L), nxt(n + 1, 0.0L);
+    auto emit = [&](int64_t k, const std::vector<long double> &v) {
+      const int s = (int)(k & 1);
+      const int64_t b = k >> 1, ms = L.m[s];
+      for (int64_t i = s; i <= k; i += 2) Rs[s][(size_t)(i >> 1) * ms + b] = (double)(v[i] / sc(i));
+    };
+    auto jx = [&](const std::vector<long double> &v, int64_t deg, std::vector<long double> &w) {
+      // w = x * v for v with nonzeros at indices <= deg (same parity as deg)
+      for (int64_t i = 0; i <= deg + 1 && i <= n; ++i) w[i] = 0.0L;
+      for (int64_t i = deg & 1; i <= deg; i += 2) {
+        if (i + 1 <= n) w[i + 1] += beta(i) * v[i];
+        if (i >= 1) w[i - 1] += beta(i - 1) * v[i];
+      }
+    };
+    cur[0] = 2.0L / std::sqrt(3.0L);
+    emit(0, cur);
+    if (n > 1) {
+      jx(cur, 0, nxt);
+      std::swap(prev, cur);
+      std::swap(cur, nxt);
+      emit(1, cur);
+    }
+    for (int64_t k = 1; k + 1 < n; ++k) {
+      jx(cur, k, nxt);
+      for (int64_t i = (k + 1) & 1; i <= k + 1; i += 2) nxt[i] = 2.0L * nxt[i] - prev[i];
+      std::swap(prev, cur);
+      std::swap(cur, nxt);
+      emit(k + 1, cur);
+    }
+  }
+  // Output map: Chebyshev coefficients of phi_i = (1-x^2) C~_i by the same
+  // three-term recurrence, phi_{i+1} = (x phi_i - beta_{i-1} phi_{i-1}) / beta_i,
+  // with x T_0 = T_1 and x T_k = (T_{k+1} + T_{k-1}) / 2.
+  {
+    std::vector<long double> prev(N + 1, 0.0L), cur(N + 1, 0.0L), nxt(N + 1, 0.0L);
+    auto emit = [&](int64_t i, const std::vector<long double> &v) {
+      const int s = (int)(i & 1);
+      const int64_t b = i >> 1, ms = L.m[s];
+      for (int64_t k = s; k <= std::min(i + 2, N - 1); k += 2)
+        P[s][(size_t)(k >> 1) * ms + b] = (double)(v[k] / sc(i));
+    };
+    auto xt = [&](const std::vector<long double> &v, int64_t deg, std::vector<long double> &w) {
+      for (int64_t k = 0; k <= deg + 1 && k <= N; ++k) w[k] = 0.0L;
+      for (int64_t k = deg & 1; k <= deg; k += 2) {
+        if (k == 0) {
+          w[1] += v[0];
+        } else {
+          if (k + 1 <= N) w[k + 1] += 0.5L * v[k];
+          w[k - 1] += 0.5L * v[k];
+        }
+      }
+    };
+    const long double h = std::sqrt(3.0L) / 4.0L;
+    cur[0] = h;
+    cur[2] = -h;
+    emit(0, cur);
+    if (n > 1) {
+      xt(cur, 2, nxt);
+      for (int64_t k = 0; k <= 3; ++k) nxt[k] /= beta(0);
+      std::swap(prev, cur);
+      std::swap(cur, nxt);
+      emit(1, cur);
+    }
+    for (int64_t i = 1; i + 1 < n; ++i) {
+      xt(cur, i + 2, nxt);
+      const long double bi = beta(i), bm = beta(i - 1);
+      for (int64_t k = (i + 1) & 1; k <= i + 3; k += 2) nxt[k] = (nxt[k] - bm * prev[k]) / bi;
+      std::swap(prev, cur);
+      std::swap(cur, nxt);
+      emit(i + 1, cur);
+    }
+  }
+}
+
+}  // namespace fps

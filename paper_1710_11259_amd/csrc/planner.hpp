@@ -1,0 +1,87 @@
+// Host planner of the spectral Poisson solver: ADI iteration count and
+// Zolotarev shifts (Theorem 2.1, (2.4), (2.9), App. A), the per-shift Thomas
+// factor tables of the partitioned tridiagonal sweeps, and the dense
+// coefficient maps Chebyshev -> C~^(3/2) (input) and recombined C~ ->
+// Chebyshev (output).  Pure C++ (no HIP); float64 results, extended
+// precision where recurrences accumulate.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fps {
+
+// Sweep partition.  A chain of one parity is cut into lane segments of
+// kSeg positions; kWaves consecutive segments form a chunk handled by one
+// workgroup; chunks are joined through a second-level carry recurrence.
+constexpr int kSeg = 32;
+constexpr int kWaves = 8;
+constexpr int kChunk = kSeg * kWaves;
+constexpr int kCols = 64;   // chains per wavefront (one per lane)
+constexpr int kPad = 64;    // parity blocks are padded to a multiple of this
+
+// Per-position table slots (see build_sweep_tables).
+enum TabSlot { T_L = 0, T_IB = 1, T_U = 2, T_F1 = 3, T_BK1 = 4, T_BF2 = 5, T_BK2 = 6, kNTab = 7 };
+// Per-chunk table slots.
+enum ChunkSlot { C_F2LAST = 0, C_BF2FIRST = 1, C_BK2FIRST = 2, kNCTab = 3 };
+
+struct ShiftSet {
+  int J = 0;
+  std::vector<double> p, q;
+};
+
+// gamma of Theorem 2.1 (cross-ratio of a, b, c, d).
+double cross_ratio(double a, double b, double c, double d);
+
+// (2.9): J = ceil(log(16 gamma) log(4/tol) / pi^2).  Returns -1 on bad input.
+int iteration_count(double a, double b, double c, double d, double tol);
+
+// Complete elliptic integral K(m) = R_F(0, m1, 1) and dn(u | m) for the
+// parameter m = 1 - m1, given the complementary parameter m1 (never forms 1 - m1).
+long double ellip_K_comp(long double m1);
+long double ellip_dn_comp(long double u, long double m1, long double K);
+
+// Shifts of Theorem 2.1 for sigma(A) in [a,b], sigma(B) in [c,d].
+// Returns false (and sets err) on invalid input.
+bool zolotarev_shifts(double a, double b, double c, double d, double tol, ShiftSet &out,
+                      std::string &err);
+
+// Layout of the parity-blocked internal arrays of a size-n square solve.
+struct Layout {
+  int64_t n = 0;
+  int64_t m[2] = {0, 0};    // chain lengths: ceil(n/2), floor(n/2)
+  int64_t mp[2] = {0, 0};   // padded to kPad
+  int64_t npad = 0;         // mp[0] + mp[1]
+  int64_t nc[2] = {0, 0};   // chunks per parity
+  int64_t ncmax = 0;
+  int64_t mstride = 0;      // table length per (shift, parity, slot)
+  int64_t mo[2] = {0, 0};   // output rows per parity for the (n+2)-long Chebyshev index
+};
+Layout make_layout(int64_t n);
+
+// Entries of A~ = -S^-1 M S^-1 (symmetric, zero +-1 diagonals):
+// diagonal at index i, and coupling between i and i+2.
+double atilde_diag(int64_t i);
+double atilde_off(int64_t i);
+
+// Tables for the shifted solves (A~ + p I) along chains of one parity.
+// pos:   [J][2][kNTab][mstride]; chunk: [J][2][kNCTab][ncmax].
+// For chain position k (original index 2k + s), b_k = d_k + p, e_k the
+// coupling to k+1.  Thomas over the whole chain: l_k = e_{k-1}/beta_{k-1},
+// beta_k = b_k - l_k e_{k-1}, ib_k = 1/beta_k, u_k = e_k/beta_k.  Partition
+// multipliers: F1_k = prod_{segment start..k} (-l), Bk1_k = prod_{k..segment
+// end} (-u), BF2 = chunk-local backward solve of F2_k = prod_{chunk
+// start..k} (-l) with zero carry at the chunk end, Bk2_k = prod_{k..chunk
+// end} (-u).  Padded positions hold l = ib = u = 0 (inert).
+void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vector<double> &pos,
+                        std::vector<double> &chunk);
+
+// Conversion maps split by parity (row-major, float64):
+//   Rs[s]: m[s] x m[s], Rs[s][a][b] = R[2a+s][2b+s] / sqrt((2a+s+1)(2a+s+2)),
+//          R[i][k] = C~_i coefficient of T_k (upper triangular).
+//   P[s]:  mo[s] x m[s], P[s][a][b] = Chebyshev coefficient 2a+s of
+//          (1-x^2) C~_{2b+s}(x) / sqrt((2b+s+1)(2b+s+2)).
+void build_conversions(const Layout &L, std::vector<double> Rs[2], std::vector<double> P[2]);
+
+}  // namespace fps

@@ -1,0 +1,34 @@
+// Test-only C shim over the host planner (built with g++ by the CPU tests).
+#include <cstring>
+#include "../paper_1710_11259_amd/csrc/planner.hpp"
+
+extern "C" {
+void shim_layout(long long n, long long *out) {
+  fps::Layout L = fps::make_layout(n);
+  long long v[] = {L.m[0], L.m[1], L.mp[0], L.mp[1], L.npad, L.nc[0], L.nc[1], L.ncmax,
+                   L.mstride, L.mo[0], L.mo[1], fps::kSeg, fps::kWaves, fps::kChunk};
+  std::memcpy(out, v, sizeof(v));
+}
+void shim_tables(long long n, int J, const double *p, double *pos, double *chunk) {
+  fps::Layout L = fps::make_layout(n);
+  std::vector<double> pv(p, p + J), a, b;
+  fps::build_sweep_tables(L, pv, a, b);
+  std::memcpy(pos, a.data(), a.size() * sizeof(double));
+  std::memcpy(chunk, b.data(), b.size() * sizeof(double));
+}
+void shim_conversions(long long n, double *R0, double *R1, double *P0, double *P1) {
+  fps::Layout L = fps::make_layout(n);
+  std::vector<double> Rs[2], P[2];
+  fps::build_conversions(L, Rs, P);
+  std::memcpy(R0, Rs[0].data(), Rs[0].size() * sizeof(double));
+  std::memcpy(R1, Rs[1].data(), Rs[1].size() * sizeof(double));
+  std::memcpy(P0, P[0].data(), P[0].size() * sizeof(double));
+  std::memcpy(P1, P[1].data(), P[1].size() * sizeof(double));
+}
+int shim_dn(double alpha, int J, double *dn) {
+  long double m1 = 1.0L / ((long double)alpha * alpha);
+  long double K = fps::ellip_K_comp(m1);
+  for (int j = 0; j < J; ++j) dn[j] = (double)fps::ellip_dn_comp((j + 0.5L) * K / J, m1, K);
+  return 0;
+}
+}

@@ -1,0 +1,224 @@
+"""CPU tests of the product library: ABI exports, host planner against the
+oracle, argument validation (no device compute)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1710_11259_amd as fps
+from oracle import basis, shifts as oshifts, square
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fps.h")).read()
+    return sorted(set(re.findall(r"\b(fps_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fps.lib()
+    syms = _declared_symbols()
+    assert len(syms) >= 10
+    for s in syms:
+        assert hasattr(L, s), s
+    out = subprocess.run(["nm", "-D", "--defined-only", fps.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for s in syms:
+        assert re.search(rf"\bT {s}$", out, re.M), s
+
+
+def test_version_and_status_strings():
+    L = fps.lib()
+    assert b"gfx950" in L.fps_version()
+    assert L.fps_status_string(0) == b"ok"
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 24, 25, 64, 1024, 4096, 10000])
+def test_plan_shifts_match_oracle(n):
+    p = fps.plan(n, tol=1e-13, host_only=True)
+    J, po, _ = oshifts.square_shifts(n, 1e-13)
+    assert p.J == J
+    assert np.allclose(p.shifts(), po, rtol=2e-14, atol=0)
+
+
+@pytest.mark.parametrize("iv", [(-5.0, -0.5, 0.2, 3.0), (-1.0, -1e-3, 1e-3, 1.0), (-2.0, -1.0, 3.0, 100.0)])
+def test_general_interval_shifts_match_oracle(iv):
+    p, q = fps.adi_shifts(*iv, 1e-10)
+    J, po, qo = oshifts.zolotarev_shifts(*iv, tol=1e-10)
+    assert len(p) == J
+    assert np.allclose(p, po, rtol=1e-13, atol=1e-15 * max(map(abs, iv)))
+    assert np.allclose(q, qo, rtol=1e-13, atol=1e-15 * max(map(abs, iv)))
+
+
+def test_argument_errors():
+    L = fps.lib()
+    h = ctypes.c_void_p()
+    for args, code in [((2, 0, 0, 1e-13, 0, 0, 1), 1), ((2, 16, 0, 0.0, 0, 0, 1), 1),
+                       ((2, 16, 0, 1.0, 0, 0, 1), 1), ((4, 16, 0, 1e-13, 0, 0, 1), 1),
+                       ((2, 16, 7, 1e-13, 0, 0, 1), 2), ((2, 16, 0, 1e-13, 9, 0, 1), 1),
+                       ((2, 16, 0, 1e-13, 0, 5, 1), 1), ((2, 16, 0, 1e-13, 0, 0, 8), 1)]:
+        assert L.fps_plan_create(ctypes.byref(h), *args) == code, args
+        assert len(L.fps_last_error()) > 0
+    J = ctypes.c_int()
+    assert L.fps_adi_shifts(1.0, 0.5, 2.0, 3.0, 1e-8, 0, ctypes.byref(J), None, None) == 1
+    assert L.fps_adi_shifts(-1.0, -0.5, 2.0, 3.0, 1e-8, 0, ctypes.byref(J), None, None) == 5
+    assert J.value > 0
+    # solve on a host-only plan / null plan
+    p = fps.plan(16, host_only=True)
+    assert L.fps_solve(p.handle, None, None, None, None) == 5
+    assert L.fps_solve(None, None, None, None, None) == 5
+    assert L.fps_plan_info(None, None, None, None) == 5
+
+
+def test_workspace_and_extent_queries():
+    p = fps.plan(100, host_only=True)
+    assert p.out_entries == 102 * 102
+    assert p.workspace_bytes >= 4 * 128 * 128 * 8
+    q = fps.plan(100, out="native", host_only=True)
+    assert q.out_entries == 100 * 100
+
+
+# --- host planner internals through a g++-built shim -----------------------
+
+@pytest.fixture(scope="module")
+def shim(tmp_path_factory):
+    d = tmp_path_factory.mktemp("shim")
+    so = str(d / "libshim.so")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", so,
+                    os.path.join(ROOT, "tests", "planner_shim.cpp"),
+                    os.path.join(ROOT, "paper_1710_11259_amd", "csrc", "planner.cpp")],
+                   check=True)
+    L = ctypes.CDLL(so)
+    P = ctypes.POINTER(ctypes.c_double)
+    L.shim_layout.argtypes = [ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]
+    L.shim_tables.argtypes = [ctypes.c_longlong, ctypes.c_int, P, P, P]
+    L.shim_conversions.argtypes = [ctypes.c_longlong, P, P, P, P]
+    L.shim_dn.argtypes = [ctypes.c_double, ctypes.c_int, P]
+    return L
+
+
+def _layout(shim, n):
+    v = (ctypes.c_longlong * 14)()
+    shim.shim_layout(n, v)
+    keys = ["m0", "m1", "mp0", "mp1", "npad", "nc0", "nc1", "ncmax", "mstride", "mo0", "mo1",
+            "seg", "waves", "chunk"]
+    return dict(zip(keys, list(v)))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@pytest.mark.parametrize("alpha", [30.0, 480.0, 7680.0, 1.2e5, 2e6, 9.9e6])
+def test_agm_dn_branch_matches_exact(shim, alpha):
+    J = 40
+    dn = np.zeros(J)
+    shim.shim_dn(alpha, J, _ptr(dn))
+    assert np.allclose(dn, oshifts.exact_dn(alpha, J), rtol=1e-14)
+
+
+def _emulate_partitioned_solve(T, C, lay, s, r):
+    """Two-level partitioned Thomas with the planner's tables (kernel algorithm)."""
+    ms, seg, W, CH = lay["mstride"], lay["seg"], lay["waves"], lay["chunk"]
+    l, ib, u, F1, Bk1, BF2, Bk2 = (T[k] for k in range(7))
+    nc = lay["nc%d" % s]
+    rr = np.zeros(ms)
+    rr[: len(r)] = r
+    xloc = np.zeros(ms)
+    ylast = np.zeros(nc)
+    xfirst = np.zeros(nc)
+    for c in range(nc):
+        ys, xs = [], []
+        for w in range(W):
+            k0 = c * CH + w * seg
+            y = np.zeros(seg)
+            carry = 0.0
+            for i in range(seg):
+                y[i] = rr[k0 + i] - l[k0 + i] * carry
+                carry = y[i]
+            ys.append(y)
+        cf = 0.0
+        for w in range(W):
+            k0 = c * CH + w * seg
+            ys[w] = ys[w] + F1[k0: k0 + seg] * cf
+            cf = ys[w][-1]
+        for w in range(W):
+            k0 = c * CH + w * seg
+            x = np.zeros(seg)
+            xn = 0.0
+            for i in range(seg - 1, -1, -1):
+                x[i] = ys[w][i] * ib[k0 + i] - u[k0 + i] * xn
+                xn = x[i]
+            xs.append(x)
+        cb = 0.0
+        for w in range(W - 1, -1, -1):
+            k0 = c * CH + w * seg
+            xs[w] = xs[w] + Bk1[k0: k0 + seg] * cb
+            cb = xs[w][0]
+        xloc[c * CH:(c + 1) * CH] = np.concatenate(xs)
+        ylast[c] = ys[-1][-1]
+        xfirst[c] = xs[0][0]
+    F2last, BF2first, Bk2first = C
+    cfv = np.zeros(nc)
+    for c in range(1, nc):
+        cfv[c] = ylast[c - 1] + F2last[c - 1] * cfv[c - 1]
+    cbv = np.zeros(nc)
+    for c in range(nc - 2, -1, -1):
+        cbv[c] = xfirst[c + 1] + BF2first[c + 1] * cfv[c + 1] + Bk2first[c + 1] * cbv[c + 1]
+    x = xloc.copy()
+    for c in range(nc):
+        sl = slice(c * CH, (c + 1) * CH)
+        x[sl] += cfv[c] * BF2[sl] + cbv[c] * Bk2[sl]
+    return x
+
+
+@pytest.mark.parametrize("n", [3, 130, 700, 1300])
+def test_sweep_tables_reproduce_shifted_solves(shim, n):
+    lay = _layout(shim, n)
+    J, p, _ = oshifts.square_shifts(n, 1e-13)
+    sel = [0, J // 2, J - 1]
+    pv = np.ascontiguousarray(p[sel])
+    ms, nc = lay["mstride"], lay["ncmax"]
+    pos = np.zeros(len(sel) * 2 * 7 * ms)
+    ch = np.zeros(len(sel) * 2 * 3 * nc)
+    shim.shim_tables(n, len(sel), _ptr(pv), _ptr(pos), _ptr(ch))
+    pos = pos.reshape(len(sel), 2, 7, ms)
+    ch = ch.reshape(len(sel), 2, 3, nc)
+    A = square.atilde_dense(n)
+    rng = np.random.default_rng(n)
+    for jj, pj in enumerate(pv):
+        for s in (0, 1):
+            idx = np.arange(s, n, 2)
+            if idx.size == 0:
+                continue
+            Tm = A[np.ix_(idx, idx)] + pj * np.eye(idx.size)
+            r = rng.standard_normal(idx.size)
+            xr = np.linalg.solve(Tm, r)
+            x = _emulate_partitioned_solve(pos[jj, s], ch[jj, s], lay, s, r)
+            assert np.linalg.norm(x[: idx.size] - xr) <= 1e-10 * np.linalg.norm(xr)
+            assert np.all(x[idx.size:] == 0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 40, 301])
+def test_conversion_maps_match_oracle(shim, n):
+    lay = _layout(shim, n)
+    m, mo = (lay["m0"], lay["m1"]), (lay["mo0"], lay["mo1"])
+    R = [np.zeros(m[s] * m[s]) for s in (0, 1)]
+    P = [np.zeros(mo[s] * m[s]) for s in (0, 1)]
+    shim.shim_conversions(n, _ptr(R[0]), _ptr(R[1]), _ptr(P[0]), _ptr(P[1]))
+    Ro = basis.cheb_to_ct(n)
+    Po = basis.recombined_to_cheb(n)
+    sinv = 1.0 / square.s_diag(n)
+    for s in (0, 1):
+        if m[s] == 0:
+            continue
+        idx = np.arange(s, n, 2)
+        oidx = np.arange(s, n + 2, 2)
+        Rref = (sinv[:, None] * Ro)[np.ix_(idx, idx)]
+        Pref = (Po * sinv[None, :])[np.ix_(oidx, idx)]
+        assert np.abs(R[s].reshape(m[s], m[s]) - Rref).max() < 1e-13 * max(1, np.abs(Rref).max())
+        assert np.abs(P[s].reshape(mo[s], m[s]) - Pref).max() < 1e-13 * max(1, np.abs(Pref).max())
