@@ -56,7 +56,7 @@ def lib() -> ctypes.CDLL:
     for name in ("fps_solve", "fps_solve_adjoint", "fps_adi_native"):
         getattr(L, name).argtypes = [vp, vp, vp, vp, vp]
     L.fps_plan_set_sweep_timing.argtypes = [vp, ctypes.c_int]
-    L.fps_plan_sweep_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    L.fps_plan_sweep_time.argtypes = [vp, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64)]
     L.fps_plan_set_sweep_timing.restype = ctypes.c_int
     L.fps_plan_sweep_time.restype = ctypes.c_int
     L.fps_plan_destroy.argtypes = [vp]
@@ -118,11 +118,13 @@ class Plan:
     def set_sweep_timing(self, capacity: int):
         _check(lib().fps_plan_set_sweep_timing(self._h, capacity))
 
-    def sweep_time(self):
-        """(summed ms, launches) of the timed half-sweeps since the last call."""
-        ms, cnt = ctypes.c_double(), ctypes.c_int64()
-        _check(lib().fps_plan_sweep_time(self._h, ctypes.byref(ms), ctypes.byref(cnt)))
-        return ms.value, cnt.value
+    def sweep_time(self, cap: int = 1 << 20):
+        """Per-launch milliseconds of the timed half-sweeps since the last call
+        (half-step 1 and half-step 2 alternate)."""
+        buf = (ctypes.c_double * cap)()
+        cnt = ctypes.c_int64()
+        _check(lib().fps_plan_sweep_time(self._h, buf, cap, ctypes.byref(cnt)))
+        return list(buf[: min(cnt.value, cap)])
 
     def out_shape(self):
         e = self.n if self.out == "native" else self.n + 2

@@ -51,19 +51,19 @@ struct fps_plan {
 
   fps::ShiftSet shifts;
   fps::Layout L;
-  std::vector<double> tab, ctab;   // host sweep tables
+  std::vector<double> tab, ctab, comb, l1;  // host sweep tables
   std::vector<double> Rs[2], P[2];  // host conversion maps
   std::vector<double> sinv;         // 1/sqrt((i+1)(i+2))
 
   // device copies
-  DeviceBuf d_tab, d_ctab, d_Rs[2], d_P[2], d_sinv;
+  DeviceBuf d_tab, d_ctab, d_comb, d_l1, d_Rs[2], d_P[2], d_sinv;
 
   // sweep timing diagnostics
   std::vector<hipEvent_t> ev;  // pairs
   int64_t ev_used = 0;
 
   // workspace layout (byte offsets)
-  int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab0 = 0, off_ab1 = 0;
+  int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab = 0;
   int64_t ws_bytes = 0;
 
   const double *tab_dev(int j) const {
@@ -71,6 +71,12 @@ struct fps_plan {
   }
   const double *ctab_dev(int j) const {
     return (const double *)d_ctab.p + (size_t)j * 2 * fps::kNCTab * L.ncmax;
+  }
+  const double *comb_dev(int j) const {
+    return (const double *)d_comb.p + (size_t)j * 2 * L.ncmax * L.ncmax * fps::kNComb;
+  }
+  const double *l1_dev(int j) const {
+    return (const double *)d_l1.p + (size_t)j * 2 * L.ncmax * fps::kL1;
   }
 };
 
@@ -109,7 +115,7 @@ void release_events(fps_plan *pl) {
 
 // Runs the 2J half-sweeps of Algorithm 2 on G (parity-blocked, in ws.G and
 // its transpose in ws.GT).  Leaves the final chunk-local solution in O1 and
-// its carry coefficients in ab1; `last_tab` is the table set to finalize with.
+// its chunk carries in ab (to finalize with the tables of the last shift).
 fps_status run_adi(fps_plan *pl, char *ws, hipStream_t st) {
   const fps::Layout &L = pl->L;
   const int J = pl->shifts.J;
@@ -119,36 +125,44 @@ fps_status run_adi(fps_plan *pl, char *ws, hipStream_t st) {
   double *O0 = (double *)(ws + pl->off_O0);
   double *O1 = (double *)(ws + pl->off_O1);
   double *lv = (double *)(ws + pl->off_lv);
-  double *ab0 = (double *)(ws + pl->off_ab0);
-  double *ab1 = (double *)(ws + pl->off_ab1);
+  double *ab = (double *)(ws + pl->off_ab);
   const int nc0 = (int)L.nc[0], nc1 = (int)L.nc[1];
 
+  fps::SweepArgs A{};
+  A.npad = L.npad;
+  A.mp0 = L.mp[0];
+  A.mp1 = L.mp[1];
+  A.mstride = L.mstride;
+  A.ncmax = L.ncmax;
+  A.nc0 = nc0;
+  A.nc1 = nc1;
+  A.lv = lv;
+  // Half-step 1 of Algorithm 2 (rows of Y): right-hand side R_j =
+  // (A~ - p_j) Y_j - G, output V_j - G = R_j - 2 p_j Y_{j+1/2} (the G of
+  // V_j = G + Y_{j+1/2}(A~ - p_j) cancels against the -G in R_j).
+  // Half-step 2 (columns of Y): right-hand side V_j = (V_j - G) + G, output
+  // R_{j+1} = (A~ - p_{j+1}) Y_{j+1} - G = (V_j - G) - (p_j + p_{j+1}) Y_{j+1}.
+  // So only half-step 2 reads G.  R_0 = -G.  After every half-step the chunk
+  // carries are resolved into `ab`, which the next half-step folds in.
   for (int j = 0; j < J; ++j) {
-    // Half-step 1: rows of Y; reads the transposed storage.
-    fps::SweepArgs A{};
-    A.in = j == 0 ? nullptr : O1;
-    A.ab_prev = ab1;
+    A.in = j == 0 ? (const void *)GT : (const void *)O1;
+    A.in_scale = j == 0 ? -1.0 : 1.0;
+    A.ab_prev = j == 0 ? nullptr : ab;
     A.tab_prev = j == 0 ? nullptr : pl->tab_dev(j - 1);
-    A.g = GT;
-    A.sg = -1.0;
+    A.g = nullptr;
+    A.sg = 0.0;
     A.tab = pl->tab_dev(j);
+    A.l1 = pl->l1_dev(j);
     A.sigma = 2.0 * p[j];
     A.out = O0;
-    A.lv = lv;
     A.final_mode = 0;
-    A.npad = L.npad;
-    A.mp0 = L.mp[0];
-    A.mp1 = L.mp[1];
-    A.mstride = L.mstride;
-    A.nc0 = nc0;
-    A.nc1 = nc1;
     FPS_HIP(timed_sweep(pl, A, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(j), ab0, -A.sigma, L.npad, nc0, nc1, L.ncmax, st));
-    // Half-step 2: columns of Y.
+    FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(j), ab, -A.sigma, L.npad, nc0, nc1, L.ncmax, st));
     fps::SweepArgs B = A;
     const bool last = j == J - 1;
     B.in = O0;
-    B.ab_prev = ab0;
+    B.in_scale = 1.0;
+    B.ab_prev = ab;
     B.tab_prev = pl->tab_dev(j);
     B.g = G;
     B.sg = 1.0;
@@ -156,7 +170,7 @@ fps_status run_adi(fps_plan *pl, char *ws, hipStream_t st) {
     B.out = O1;
     B.final_mode = last ? 1 : 0;
     FPS_HIP(timed_sweep(pl, B, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(j), ab1, last ? 1.0 : -B.sigma, L.npad, nc0, nc1,
+    FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(j), ab, last ? 1.0 : -B.sigma, L.npad, nc0, nc1,
                                L.ncmax, st));
   }
   return FPS_OK;
@@ -304,27 +318,27 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
     return fail(FPS_E_ARG, err);
   }
   pl->L = fps::make_layout(n);
-  fps::build_sweep_tables(pl->L, pl->shifts.p, pl->tab, pl->ctab);
+  fps::build_sweep_tables(pl->L, pl->shifts.p, pl->tab, pl->ctab, pl->comb, pl->l1);
   fps::build_conversions(pl->L, pl->Rs, pl->P);
   pl->sinv.resize(n);
   for (int64_t i = 0; i < n; ++i) pl->sinv[i] = 1.0 / std::sqrt((double)(i + 1) * (double)(i + 2));
 
   const fps::Layout &L = pl->L;
   const int64_t sq = align256(L.npad * L.npad * 8);
-  const int64_t lvb = align256(L.ncmax * 4 * L.npad * 8);
-  const int64_t abb = align256(L.ncmax * L.npad * 4 * 8);
+  const int64_t lvb = align256(L.ncmax * 4 * L.npad * 8);  // [ncmax][2][2][npad]
+  const int64_t abb = align256(2 * L.ncmax * L.npad * 2 * 8);  // [2][ncmax][npad][2]
   pl->off_G = 0;
   pl->off_GT = sq;
   pl->off_O0 = 2 * sq;
   pl->off_O1 = 3 * sq;
   pl->off_lv = 4 * sq;
-  pl->off_ab0 = 4 * sq + lvb;
-  pl->off_ab1 = 4 * sq + lvb + abb;
-  pl->ws_bytes = 4 * sq + lvb + 2 * abb;
+  pl->off_ab = 4 * sq + lvb;
+  pl->ws_bytes = 4 * sq + lvb + abb;
 
   if (!(flags & FPS_PLAN_HOST_ONLY)) {
     fps_status s;
     if ((s = upload(pl->d_tab, pl->tab)) != FPS_OK || (s = upload(pl->d_ctab, pl->ctab)) != FPS_OK ||
+        (s = upload(pl->d_comb, pl->comb)) != FPS_OK || (s = upload(pl->d_l1, pl->l1)) != FPS_OK ||
         (s = upload(pl->d_Rs[0], pl->Rs[0])) != FPS_OK || (s = upload(pl->d_Rs[1], pl->Rs[1])) != FPS_OK ||
         (s = upload(pl->d_P[0], pl->P[0])) != FPS_OK || (s = upload(pl->d_P[1], pl->P[1])) != FPS_OK ||
         (s = upload(pl->d_sinv, pl->sinv)) != FPS_OK) {
@@ -365,7 +379,7 @@ fps_status fps_solve(fps_plan *pl, const double *F, double *U, void *ws, void *s
   if ((s = run_adi(pl, w, st)) != FPS_OK) return s;
   const int J = pl->shifts.J;
   double *O1 = (double *)(w + pl->off_O1);
-  double *ab1 = (double *)(w + pl->off_ab1);
+  double *ab1 = (double *)(w + pl->off_ab);
   if (pl->out_basis == FPS_OUT_NATIVE) {
     FPS_HIP(fps::launch_finalize(O1, ab1, pl->tab_dev(J - 1), U, 1, (const double *)pl->d_sinv.p,
                                  L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
@@ -390,7 +404,7 @@ fps_status fps_adi_native(fps_plan *pl, const double *G, double *Y, void *ws, vo
   FPS_HIP(fps::launch_transpose(Gp, GT, L.npad, st));
   if ((s = run_adi(pl, w, st)) != FPS_OK) return s;
   const int J = pl->shifts.J;
-  FPS_HIP(fps::launch_finalize((double *)(w + pl->off_O1), (double *)(w + pl->off_ab1),
+  FPS_HIP(fps::launch_finalize((double *)(w + pl->off_O1), (double *)(w + pl->off_ab),
                                pl->tab_dev(J - 1), Y, 1, nullptr, L.n, L.npad, L.mp[0], L.mstride,
                                L.ncmax, st));
   return FPS_OK;
@@ -420,17 +434,15 @@ fps_status fps_plan_set_sweep_timing(fps_plan *pl, int capacity) {
   return FPS_OK;
 }
 
-fps_status fps_plan_sweep_time(fps_plan *pl, double *ms_total, int64_t *launches) {
+fps_status fps_plan_sweep_time(fps_plan *pl, double *ms_host, int64_t cap, int64_t *launches) {
   if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
-  if (!ms_total || !launches) return fail(FPS_E_ARG, "null output");
-  double tot = 0.0;
+  if (!launches || (cap > 0 && !ms_host)) return fail(FPS_E_ARG, "null output");
   for (int64_t i = 0; i < pl->ev_used; ++i) {
     FPS_HIP(hipEventSynchronize(pl->ev[2 * i + 1]));
     float ms = 0.0f;
     FPS_HIP(hipEventElapsedTime(&ms, pl->ev[2 * i], pl->ev[2 * i + 1]));
-    tot += ms;
+    if (i < cap) ms_host[i] = ms;
   }
-  *ms_total = tot;
   *launches = pl->ev_used;
   pl->ev_used = 0;
   return FPS_OK;

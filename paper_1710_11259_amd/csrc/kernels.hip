@@ -14,7 +14,10 @@
 //   * the multiply by (A~ - p' I) that Algorithm 2 applies after each solve
 //     along the same direction is r - (p + p') x, so no neighbour access is
 //     needed; the pass output is stored transposed so that the next pass,
-//     which solves along the other direction, again reads whole rows.
+//     which solves along the other direction, again reads whole rows;
+//   * the right-hand side G enters only the column half-step: the row
+//     half-step's output V - G = R - 2p Y_{1/2} needs no G, and the column
+//     half-step adds G to its right-hand side but not to its output.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -28,144 +31,213 @@ __device__ __forceinline__ double ld_as_double(const T *p) {
   return (double)(*p);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kCols *kWaves) void k_sweep(SweepArgs a) {
-  __shared__ double sh_y[kWaves][kCols];
-  __shared__ double sh_x[kWaves][kCols];
+// LDS of one sweep workgroup (doubles).  The early region holds the
+// chunk's slice of the per-position tables, the producer's chunk carries of
+// this workgroup's rows, the segment-carry combinations and the segment
+// boundary values; it is dead before the staging tile of the transposed
+// store reuses the space.
+constexpr int kStage = kCols * (kSeg + 1);  // staging doubles per wavefront
+constexpr int kSweepLds = kWaves * kStage;
+constexpr int kTabSlots = 5;                // l, ib, u, F1, Bk1
+constexpr int OFF_TAB = 0;
+constexpr int OFF_AB = OFF_TAB + kTabSlots * kChunk;
+constexpr int OFF_L1 = OFF_AB + 2 * kChunk;
+constexpr int OFF_SY = OFF_L1 + kL1;
+constexpr int OFF_SX = OFF_SY + kWaves * kCols;
+constexpr int OFF_END = OFF_SX + kWaves * kCols;
+static_assert(OFF_END <= kSweepLds, "LDS carve-out");
+static_assert(kCols * kWaves >= 4 * kChunk && kTabSlots * kChunk <= 2 * kCols * kWaves,
+              "early loads: at most two per thread");
+static_assert(T_L == 0 && T_IB == 1 && T_U == 2 && T_F1 == 3 && T_BK1 == 4, "table slot order");
 
-  const int lane = threadIdx.x & (kCols - 1);
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t npad = a.npad, ms = a.mstride;
-  const int64_t col = (int64_t)blockIdx.x * kCols + lane;
+// kWithG: the right-hand side is v + sg * g while the output is v - sigma x
+// (g is not carried into the output); otherwise the right-hand side is v.
+// v = in_scale * in + (chunk carries of the producing pass).
+template <typename T, bool kWithG>
+__global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
+  __shared__ double lds[kSweepLds];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kCols - 1);
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t npad = a.npad, ms = a.mstride, ncmax = a.ncmax;
+  const int64_t col0 = (int64_t)blockIdx.x * kCols;
+  const int64_t col = col0 + lane;
   const int by = blockIdx.y;
   const int s = by < a.nc0 ? 0 : 1;
   const int c = by - (s ? a.nc0 : 0);
   const int64_t mps = s ? a.mp1 : a.mp0;
-  const int64_t k0 = (int64_t)c * kChunk + (int64_t)w * kSeg;
+  const int64_t kc0 = (int64_t)c * kChunk;     // first chain position of the chunk
+  const int64_t k0 = kc0 + (int64_t)w * kSeg;   // first position of this segment
   const bool active = k0 < mps;
-  const int64_t row0 = (s ? a.mp0 : 0) + k0;
+  const int64_t rbase = (s ? a.mp0 : 0) + kc0;  // storage row of the chunk start
+  const int64_t row0 = rbase + (int64_t)w * kSeg;
+  const bool has_prev = a.ab_prev != nullptr;
 
-  const double *__restrict__ tab = a.tab + (int64_t)s * kNTab * ms;
-  const double *__restrict__ tl = tab + T_L * ms + k0;
-  const double *__restrict__ tib = tab + T_IB * ms + k0;
-  const double *__restrict__ tu = tab + T_U * ms + k0;
-  const double *__restrict__ tf1 = tab + T_F1 * ms;
-  const double *__restrict__ tbk1 = tab + T_BK1 * ms;
+  // 1. Small loads, issued before the streaming loads and without divergent
+  //    branches (addresses are clamped), so that waiting for them does not
+  //    wait for the streaming loads.
+  const double *__restrict__ tab = a.tab + (int64_t)s * kNTab * ms + kc0;
+  const int e1 = tid + kCols * kWaves < kTabSlots * kChunk ? tid + kCols * kWaves : kTabSlots * kChunk - 1;
+  const double t0 = tab[(tid / kChunk) * ms + (tid % kChunk)];
+  const double t1 = tab[(e1 / kChunk) * ms + (e1 % kChunk)];
+  const double l1v = a.l1[((int64_t)s * ncmax + c) * kL1 + (tid < kL1 ? tid : kL1 - 1)];
+  const int sp = col0 >= a.mp0 ? 1 : 0;
+  const int64_t cp = (col0 - (sp ? a.mp0 : 0)) / kChunk;
+  double abv = 0.0, bf = 0.0, bk = 0.0;
+  if (has_prev) {
+    const int e2 = tid < 2 * kChunk ? tid : 2 * kChunk - 1;
+    abv = a.ab_prev[(((int64_t)sp * ncmax + cp) * npad + rbase) * 2 + e2];
+    const int64_t kp = col - (sp ? a.mp0 : 0);
+    const double *tp = a.tab_prev + (int64_t)sp * kNTab * ms;
+    bf = tp[T_BF2 * ms + kp];
+    bk = tp[T_BK2 * ms + kp];
+  }
 
-  double y[kSeg];
+  // 2. Streaming loads (rows clamped for the idle segments past the chain end).
+  double v[kSeg], y[kSeg];
+  {
+    const T *__restrict__ in = (const T *)a.in;
 #pragma unroll
-  for (int i = 0; i < kSeg; ++i) y[i] = 0.0;
-
-  if (active) {
-    if (a.in != nullptr) {
-      const T *__restrict__ in = (const T *)a.in;
-      // Producer of `in` solved along this pass's columns: its chain is this
-      // storage row, its position is this column.
-      const int64_t kap0 = (int64_t)blockIdx.x * kCols;
-      const int sp = kap0 >= a.mp0 ? 1 : 0;
-      const int64_t kp = col - (sp ? a.mp0 : 0);
-      const int64_t cp = (kap0 - (sp ? a.mp0 : 0)) / kChunk;
-      const double *tp = a.tab_prev + (int64_t)sp * kNTab * ms;
-      const double bf = tp[T_BF2 * ms + kp];
-      const double bk = tp[T_BK2 * ms + kp];
-      const double *__restrict__ ab = a.ab_prev + ((cp * npad + row0) * 2 + sp) * 2;
-#pragma unroll
-      for (int i = 0; i < kSeg; ++i) {
-        const double v = ld_as_double(in + (row0 + i) * npad + col);
-        y[i] = v + ab[i * 4 + 0] * bf + ab[i * 4 + 1] * bk;
-      }
+    for (int i = 0; i < kSeg; ++i) {
+      const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
+      v[i] = ld_as_double(in + r * npad + col);
     }
-    if (a.g != nullptr) {
-      const double *__restrict__ g = a.g;
+  }
+  if constexpr (kWithG) {
+    const double *__restrict__ gp = a.g;
 #pragma unroll
-      for (int i = 0; i < kSeg; ++i) y[i] += a.sg * g[(row0 + i) * npad + col];
+    for (int i = 0; i < kSeg; ++i) {
+      const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
+      y[i] = gp[r * npad + col];
     }
   }
 
-  // Forward elimination with zero carry-in.
+  lds[OFF_TAB + tid] = t0;
+  if (tid + kCols * kWaves < kTabSlots * kChunk) lds[OFF_TAB + tid + kCols * kWaves] = t1;
+  if (tid < kL1) lds[OFF_L1 + tid] = l1v;
+  if (tid < 2 * kChunk) lds[OFF_AB + tid] = abv;
+  __syncthreads();
+
+  const double *Tl = lds + OFF_TAB + 0 * kChunk + w * kSeg;
+  const double *Tib = lds + OFF_TAB + 1 * kChunk + w * kSeg;
+  const double *Tu = lds + OFF_TAB + 2 * kChunk + w * kSeg;
+  const double *Tf1 = lds + OFF_TAB + 3 * kChunk + w * kSeg;
+  const double *Tbk1 = lds + OFF_TAB + 4 * kChunk + w * kSeg;
+  const double *Ab = lds + OFF_AB + 2 * w * kSeg;
+
+  // 3. Right-hand side.  Idle segments carry exact zeros.
+  const double act = active ? 1.0 : 0.0;
+  const double isc = act * a.in_scale;
+  const double cA = has_prev ? act * bf : 0.0, cB = has_prev ? act * bk : 0.0;
+#pragma unroll
+  for (int i = 0; i < kSeg; ++i) {
+    v[i] = isc * v[i] + Ab[2 * i] * cA + Ab[2 * i + 1] * cB;
+    if constexpr (kWithG)
+      y[i] = v[i] + (act * a.sg) * y[i];
+    else
+      y[i] = v[i];
+  }
+
+  // 4. Forward elimination with zero carry-in, then the segment carry.
   {
     double carry = 0.0;
 #pragma unroll
     for (int i = 0; i < kSeg; ++i) {
-      y[i] = y[i] - tl[i] * carry;
+      y[i] = y[i] - Tl[i] * carry;
       carry = y[i];
     }
   }
-  sh_y[w][lane] = y[kSeg - 1];
+  lds[OFF_SY + w * kCols + lane] = y[kSeg - 1];
   __syncthreads();
   double cf1 = 0.0;
-  for (int v = 0; v < w; ++v) {
-    const int64_t last = (int64_t)c * kChunk + (int64_t)v * kSeg + kSeg - 1;
-    cf1 = sh_y[v][lane] + tf1[last] * cf1;
-  }
 #pragma unroll
-  for (int i = 0; i < kSeg; ++i) y[i] += tf1[k0 + i] * cf1;
+  for (int u = 0; u < kWaves; ++u)
+    cf1 += lds[OFF_L1 + (0 * kWaves + w) * kWaves + u] * lds[OFF_SY + u * kCols + lane];
+#pragma unroll
+  for (int i = 0; i < kSeg; ++i) y[i] += Tf1[i] * cf1;
   const double ylast_chunk = y[kSeg - 1];
 
-  // Backward substitution with zero carry-in, fused with the output.
+  // 5. Backward substitution with zero carry-in, fused with the output.
   const double sigma = a.sigma;
   double xnext = 0.0, xfirst = 0.0;
 #pragma unroll
   for (int i = kSeg - 1; i >= 0; --i) {
-    const double x = y[i] * tib[i] - tu[i] * xnext;
-    const double yprev = i > 0 ? y[i - 1] : cf1;
-    const double r = y[i] + tl[i] * yprev;  // the input value r_k
-    y[i] = a.final_mode ? x : r - sigma * x;
+    const double x = y[i] * Tib[i] - Tu[i] * xnext;
+    y[i] = a.final_mode ? x : v[i] - sigma * x;
     xnext = x;
     if (i == 0) xfirst = x;
   }
-  sh_x[w][lane] = xfirst;
+  lds[OFF_SX + w * kCols + lane] = xfirst;
   __syncthreads();
   double cb1 = 0.0;
-  for (int v = kWaves - 1; v > w; --v) {
-    const int64_t first = (int64_t)c * kChunk + (int64_t)v * kSeg;
-    cb1 = sh_x[v][lane] + tbk1[first] * cb1;
-  }
+#pragma unroll
+  for (int u = 0; u < kWaves; ++u)
+    cb1 += lds[OFF_L1 + (1 * kWaves + w) * kWaves + u] * lds[OFF_SX + u * kCols + lane];
   const double coef = (a.final_mode ? 1.0 : -sigma) * cb1;
 #pragma unroll
-  for (int i = 0; i < kSeg; ++i) y[i] += coef * tbk1[k0 + i];
+  for (int i = 0; i < kSeg; ++i) y[i] += coef * Tbk1[i];
 
-  // Chunk boundary data for the second-level carries.
+  // 6. Chunk boundary values for the chunk carries.
   if (w == kWaves - 1) a.lv[(((int64_t)c * 2 + s) * 2 + 0) * npad + col] = ylast_chunk;
-  if (w == 0) a.lv[(((int64_t)c * 2 + s) * 2 + 1) * npad + col] = xfirst + tbk1[k0] * cb1;
+  if (w == 0) a.lv[(((int64_t)c * 2 + s) * 2 + 1) * npad + col] = xfirst + Tbk1[0] * cb1;
 
-  if (active) {
-    T *__restrict__ out = (T *)a.out;
-    if (a.final_mode) {
+  T *__restrict__ out = (T *)a.out;
+  if (a.final_mode) {
+    if (active) {
 #pragma unroll
       for (int i = 0; i < kSeg; ++i) out[(row0 + i) * npad + col] = (T)y[i];
-    } else {
-      T *o = out + col * npad + row0;
+    }
+    return;
+  }
+  // 7. Transposed store staged through LDS: output row col0 + j receives this
+  //    segment's kSeg positions as one contiguous 128-byte run.
+  double *stage = lds + w * kStage;
+  __syncthreads();  // the early region is dead
 #pragma unroll
-      for (int i = 0; i < kSeg; ++i) o[i] = (T)y[i];
+  for (int i = 0; i < kSeg; ++i) stage[lane * (kSeg + 1) + i] = y[i];
+  __syncthreads();
+  if (active) {
+    constexpr int kLanesPerRow = kSeg / 2;
+    constexpr int kRowsPerStore = kCols / kLanesPerRow;
+#pragma unroll
+    for (int t = 0; t < kCols / kRowsPerStore; ++t) {
+      const int orow = kRowsPerStore * t + lane / kLanesPerRow;
+      const int ocol = 2 * (lane % kLanesPerRow);
+      const double v0 = stage[orow * (kSeg + 1) + ocol];
+      const double v1 = stage[orow * (kSeg + 1) + ocol + 1];
+      T *dst = out + (col0 + orow) * npad + row0 + ocol;
+      dst[0] = (T)v0;
+      dst[1] = (T)v1;
     }
   }
 }
 
-__global__ void k_reduce(const double *__restrict__ lv, const double *__restrict__ ctab,
-                         double *__restrict__ ab, double scale, int64_t npad, int nc0, int nc1,
-                         int64_t ncmax) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 2 * npad) return;
-  const int s = idx >= npad ? 1 : 0;
-  const int64_t col = idx - (s ? npad : 0);
+// Chunk carries of one half-sweep: thread (parity s, chunk c, chain r)
+// forms cf[c], cb[c] of chain r as linear combinations of the chain's chunk
+// boundary values (coefficients precomputed per shift), scaled by `scale`.
+// Output layout ab[s][c][r][2].
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ lv,
+                                                const double *__restrict__ comb,
+                                                double *__restrict__ ab, double scale,
+                                                int64_t npad, int nc0, int nc1, int64_t ncmax) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y >= ncmax ? 1 : 0;
+  const int c = blockIdx.y - (s ? (int)ncmax : 0);
   const int nc = s ? nc1 : nc0;
-  const double *C = ctab + (int64_t)s * kNCTab * ncmax;
-  double cf = 0.0;
-  for (int c = 0; c < nc; ++c) {
-    ab[(((int64_t)c * npad + col) * 2 + s) * 2 + 0] = cf;
-    const double yl = lv[(((int64_t)c * 2 + s) * 2 + 0) * npad + col];
-    cf = yl + C[C_F2LAST * ncmax + c] * cf;
+  if (c >= nc || r >= npad) return;
+  const double *__restrict__ W = comb + (((int64_t)s * ncmax + c) * ncmax) * kNComb;
+  const double *__restrict__ lp = lv + (int64_t)s * 2 * npad + r;
+  double A = 0.0, B = 0.0;
+#pragma unroll 16
+  for (int q = 0; q < nc; ++q) {
+    const double yl = lp[(int64_t)q * 4 * npad];
+    const double xf = lp[(int64_t)q * 4 * npad + npad];
+    A += W[q * kNComb + K_CF] * yl;
+    B += W[q * kNComb + K_CBY] * yl + W[q * kNComb + K_CBX] * xf;
   }
-  double cb = 0.0;
-  for (int c = nc - 1; c >= 0; --c) {
-    double *e = ab + (((int64_t)c * npad + col) * 2 + s) * 2;
-    const double cfc = e[0];
-    e[0] = scale * cfc;
-    e[1] = scale * cb;
-    const double xf = lv[(((int64_t)c * 2 + s) * 2 + 1) * npad + col];
-    cb = xf + C[C_BF2FIRST * ncmax + c] * cfc + C[C_BK2FIRST * ncmax + c] * cb;
-  }
+  double *o = ab + (((int64_t)s * ncmax + c) * npad + r) * 2;
+  o[0] = scale * A;
+  o[1] = scale * B;
 }
 
 __global__ void k_finalize(const double *__restrict__ x, const double *__restrict__ ab,
@@ -179,7 +251,7 @@ __global__ void k_finalize(const double *__restrict__ x, const double *__restric
   const int64_t k = r - (s ? mp0 : 0);
   const int64_t c = k / kChunk;
   const double *tp = tab + (int64_t)s * kNTab * mstride;
-  const double *e = ab + ((c * npad + col) * 2 + s) * 2;
+  const double *e = ab + (((int64_t)s * ncmax + c) * npad + col) * 2;
   const double v = x[r * npad + col] + e[0] * tp[T_BF2 * mstride + k] + e[1] * tp[T_BK2 * mstride + k];
   if (mode == 0) {
     out[r * npad + col] = v;
@@ -308,19 +380,21 @@ __global__ __launch_bounds__(256) void k_gemm(GemmBatch batch) {
 template <typename T>
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
   const int nchunks = a.nc0 + a.nc1;
-  if (a.npad % kCols != 0 || nchunks <= 0) return hipErrorInvalidValue;
+  if (a.npad % kCols != 0 || nchunks <= 0 || a.in == nullptr) return hipErrorInvalidValue;
   dim3 grid((unsigned)(a.npad / kCols), (unsigned)nchunks);
-  hipLaunchKernelGGL(k_sweep<T>, grid, dim3(kCols * kWaves), 0, st, a);
+  if (a.g != nullptr)
+    hipLaunchKernelGGL((k_sweep<T, true>), grid, dim3(kCols * kWaves), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_sweep<T, false>), grid, dim3(kCols * kWaves), 0, st, a);
   return hipGetLastError();
 }
 template hipError_t launch_sweep<double>(const SweepArgs &, hipStream_t);
 template hipError_t launch_sweep<float>(const SweepArgs &, hipStream_t);
 
-hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,
+hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
                          int64_t npad, int nc0, int nc1, int64_t ncmax, hipStream_t st) {
-  const int64_t total = 2 * npad;
-  hipLaunchKernelGGL(k_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, lv, ctab,
-                     ab, scale, npad, nc0, nc1, ncmax);
+  dim3 grid((unsigned)((npad + 255) / 256), (unsigned)(2 * ncmax));
+  hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, lv, comb, ab, scale, npad, nc0, nc1, ncmax);
   return hipGetLastError();
 }
 

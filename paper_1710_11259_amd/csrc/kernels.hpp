@@ -11,32 +11,38 @@ namespace fps {
 
 // One ADI half-sweep over a parity-blocked npad x npad array whose chains
 // run down the storage rows (one chain per storage column).
-//   input  r = in (+ carry correction of the producing pass) + sg * g
-//   solve  x = (A~ + p I)^-1 r along each chain (per parity)
-//   output out = r - sigma x   (stored transposed), or x itself (final,
-//          stored in place orientation); chunk-level carries are left to
-//          fps::launch_reduce and applied by the consumer.
+//   input  v = in_scale * in (+ carry correction of the producing pass)
+//   solve  x = (A~ + p I)^-1 r along each chain (per parity), r = v + sg * g
+//          (r = v when g is null)
+//   output out = v - sigma x   (stored transposed), or x itself (final,
+//          stored in place orientation).  Chunk-level carries are not applied
+//          by the producer: it leaves its chunk boundary values in `lv`;
+//          launch_reduce turns them into carries, which the consumer (the
+//          next sweep, or launch_finalize after the last one) folds in.
 struct SweepArgs {
-  const void *in;          // T[npad*npad] or nullptr (input is sg*g only)
-  const double *ab_prev;   // producer carry coefficients [ncmax][npad][2][2]
+  const void *in;          // T[npad*npad]
+  double in_scale;
+  const double *ab_prev;   // producer's chunk carries [2][ncmax][npad][2], or null
   const double *tab_prev;  // producer's per-position tables (its shift) [2][kNTab][mstride]
   const double *g;         // G term (same orientation as `in`) or nullptr
   double sg;
   const double *tab;       // this pass's tables [2][kNTab][mstride]
+  const double *l1;        // this pass's segment-carry combinations [2][ncmax][kL1]
   double sigma;
   void *out;               // T[npad*npad]
-  double *lv;              // chunk boundary data [ncmax][2][2][npad]
+  double *lv;              // chunk boundary values [ncmax][2][2][npad]
   int final_mode;          // 1: out = x, not transposed
-  int64_t npad, mp0, mp1, mstride;
+  int64_t npad, mp0, mp1, mstride, ncmax;
   int nc0, nc1;
 };
 
 template <typename T>
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st);
 
-// Second-level carries: for every chain, the forward and backward carry into
-// each chunk, scaled by `scale`, into ab [ncmax][npad][2][2].
-hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,
+// Chunk carries: for every chain, the forward and backward carry into each
+// chunk, scaled by `scale`, into ab [2][ncmax][npad][2] (comb: the carry
+// combinations of the producing pass's shift).
+hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
                          int64_t npad, int nc0, int nc1, int64_t ncmax, hipStream_t st);
 
 // Y_perm[r][col] = x[r][col] + carries (final pass, non-transposed).

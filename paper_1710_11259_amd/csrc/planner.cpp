@@ -158,11 +158,15 @@ double atilde_off(int64_t i) {
 }
 
 void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vector<double> &pos,
-                        std::vector<double> &chunk) {
+                        std::vector<double> &chunk, std::vector<double> &comb,
+                        std::vector<double> &l1) {
   const int J = (int)p.size();
   const int64_t ms = L.mstride, nc = L.ncmax;
   pos.assign((size_t)J * 2 * kNTab * ms, 0.0);
   chunk.assign((size_t)J * 2 * kNCTab * nc, 0.0);
+  comb.assign((size_t)J * 2 * nc * nc * kNComb, 0.0);
+  l1.assign((size_t)J * 2 * nc * kL1, 0.0);
+  std::vector<long double> CF((size_t)(nc + 1) * nc), CBY((size_t)nc * nc), CBX((size_t)nc * nc);
   std::vector<long double> l(ms), ib(ms), u(ms), F2(ms), BF2(ms);
   for (int j = 0; j < J; ++j) {
     for (int s = 0; s < 2; ++s) {
@@ -224,6 +228,52 @@ void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vect
         C[C_BF2FIRST * nc + c] = (double)BF2[c0];
         C[C_BK2FIRST * nc + c] = T[T_BK2 * ms + c0];
       }
+      // Segment-carry combinations inside each chunk.
+      for (int64_t cc = 0; cc < nc; ++cc) {
+        double *Lc = l1.data() + ((size_t)(j * 2 + s) * nc + cc) * kL1;
+        const int64_t c0 = cc * kChunk;
+        for (int w = 0; w < kWaves; ++w)
+          for (int u = 0; u < kWaves; ++u) {
+            long double f = 0.0L, b = 0.0L;
+            if (u < w) {
+              f = 1.0L;
+              for (int v = u + 1; v < w; ++v) f *= T[T_F1 * ms + c0 + (int64_t)v * kSeg + kSeg - 1];
+            }
+            if (u > w) {
+              b = 1.0L;
+              for (int v = w + 1; v < u; ++v) b *= T[T_BK1 * ms + c0 + (int64_t)v * kSeg];
+            }
+            Lc[(0 * kWaves + w) * kWaves + u] = (double)f;
+            Lc[(1 * kWaves + w) * kWaves + u] = (double)b;
+          }
+      }
+      // Coefficients of the chunk carries as linear forms in the boundary
+      // values: cf[0] = 0, cf[c+1] = ylast[c] + F2last[c] cf[c];
+      // cb[ncs-1] = 0, cb[c] = xfirst[c+1] + BF2first[c+1] cf[c+1] + Bk2first[c+1] cb[c+1].
+      const int64_t ncs = L.nc[s];
+      std::fill(CF.begin(), CF.end(), 0.0L);
+      std::fill(CBY.begin(), CBY.end(), 0.0L);
+      std::fill(CBX.begin(), CBX.end(), 0.0L);
+      for (int64_t cc = 0; cc + 1 < ncs; ++cc) {
+        const long double f = C[C_F2LAST * nc + cc];
+        for (int64_t q = 0; q < nc; ++q) CF[(cc + 1) * nc + q] = f * CF[cc * nc + q];
+        CF[(cc + 1) * nc + cc] += 1.0L;
+      }
+      for (int64_t cc = ncs - 2; cc >= 0; --cc) {
+        const long double bf = C[C_BF2FIRST * nc + cc + 1], bk = C[C_BK2FIRST * nc + cc + 1];
+        for (int64_t q = 0; q < nc; ++q) {
+          CBY[cc * nc + q] = bf * CF[(cc + 1) * nc + q] + bk * CBY[(cc + 1) * nc + q];
+          CBX[cc * nc + q] = bk * CBX[(cc + 1) * nc + q];
+        }
+        CBX[cc * nc + cc + 1] += 1.0L;
+      }
+      double *W = comb.data() + (size_t)(j * 2 + s) * nc * nc * kNComb;
+      for (int64_t cc = 0; cc < ncs; ++cc)
+        for (int64_t q = 0; q < ncs; ++q) {
+          W[(cc * nc + q) * kNComb + K_CF] = (double)CF[cc * nc + q];
+          W[(cc * nc + q) * kNComb + K_CBY] = (double)CBY[cc * nc + q];
+          W[(cc * nc + q) * kNComb + K_CBX] = (double)CBX[cc * nc + q];
+        }
     }
   }
 }

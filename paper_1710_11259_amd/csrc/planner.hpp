@@ -15,7 +15,7 @@ namespace fps {
 // Sweep partition.  A chain of one parity is cut into lane segments of
 // kSeg positions; kWaves consecutive segments form a chunk handled by one
 // workgroup; chunks are joined through a second-level carry recurrence.
-constexpr int kSeg = 32;
+constexpr int kSeg = 16;
 constexpr int kWaves = 8;
 constexpr int kChunk = kSeg * kWaves;
 constexpr int kCols = 64;   // chains per wavefront (one per lane)
@@ -25,6 +25,19 @@ constexpr int kPad = 64;    // parity blocks are padded to a multiple of this
 enum TabSlot { T_L = 0, T_IB = 1, T_U = 2, T_F1 = 3, T_BK1 = 4, T_BF2 = 5, T_BK2 = 6, kNTab = 7 };
 // Per-chunk table slots.
 enum ChunkSlot { C_F2LAST = 0, C_BF2FIRST = 1, C_BK2FIRST = 2, kNCTab = 3 };
+// Carry-combination slots: the chunk-level forward carry cf[c] and backward
+// carry cb[c] of a chain are linear in its chunk boundary values ylast[q]
+// (forward-eliminated value at the end of chunk q, zero chunk carries) and
+// xfirst[q] (back-substituted value at the start of chunk q):
+//   cf[c] = sum_q W[c][q][K_CF] ylast[q],
+//   cb[c] = sum_q W[c][q][K_CBY] ylast[q] + W[c][q][K_CBX] xfirst[q].
+enum CombSlot { K_CF = 0, K_CBY = 1, K_CBX = 2, kNComb = 3 };
+// Segment-carry combinations inside a chunk (waves w, u < kWaves):
+//   cf1[w] = sum_{u<w} L1[c][0][w][u] ylast_seg[u]    (forward carry into segment w)
+//   cb1[w] = sum_{u>w} L1[c][1][w][u] xfirst_seg[u]   (backward carry into segment w)
+// with L1[.][0][w][u] = prod_{u<v<w} F1(last position of segment v) and
+//      L1[.][1][w][u] = prod_{w<v<u} Bk1(first position of segment v).
+constexpr int kL1 = 2 * kWaves * kWaves;
 
 struct ShiftSet {
   int J = 0;
@@ -66,7 +79,9 @@ double atilde_diag(int64_t i);
 double atilde_off(int64_t i);
 
 // Tables for the shifted solves (A~ + p I) along chains of one parity.
-// pos:   [J][2][kNTab][mstride]; chunk: [J][2][kNCTab][ncmax].
+// pos:   [J][2][kNTab][mstride]; chunk: [J][2][kNCTab][ncmax];
+// comb:  [J][2][ncmax][ncmax][kNComb];
+// l1:    [J][2][ncmax][kL1].
 // For chain position k (original index 2k + s), b_k = d_k + p, e_k the
 // coupling to k+1.  Thomas over the whole chain: l_k = e_{k-1}/beta_{k-1},
 // beta_k = b_k - l_k e_{k-1}, ib_k = 1/beta_k, u_k = e_k/beta_k.  Partition
@@ -75,7 +90,8 @@ double atilde_off(int64_t i);
 // start..k} (-l) with zero carry at the chunk end, Bk2_k = prod_{k..chunk
 // end} (-u).  Padded positions hold l = ib = u = 0 (inert).
 void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vector<double> &pos,
-                        std::vector<double> &chunk);
+                        std::vector<double> &chunk, std::vector<double> &comb,
+                        std::vector<double> &l1);
 
 // Conversion maps split by parity (row-major, float64):
 //   Rs[s]: m[s] x m[s], Rs[s][a][b] = R[2a+s][2b+s] / sqrt((2a+s+1)(2a+s+2)),

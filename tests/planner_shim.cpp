@@ -11,10 +11,16 @@ void shim_layout(long long n, long long *out) {
 }
 void shim_tables(long long n, int J, const double *p, double *pos, double *chunk) {
   fps::Layout L = fps::make_layout(n);
-  std::vector<double> pv(p, p + J), a, b;
-  fps::build_sweep_tables(L, pv, a, b);
+  std::vector<double> pv(p, p + J), a, b, cmb, l1;
+  fps::build_sweep_tables(L, pv, a, b, cmb, l1);
   std::memcpy(pos, a.data(), a.size() * sizeof(double));
   std::memcpy(chunk, b.data(), b.size() * sizeof(double));
+}
+void shim_comb(long long n, int J, const double *p, double *comb) {
+  fps::Layout L = fps::make_layout(n);
+  std::vector<double> pv(p, p + J), a, b, cmb, l1;
+  fps::build_sweep_tables(L, pv, a, b, cmb, l1);
+  std::memcpy(comb, cmb.data(), cmb.size() * sizeof(double));
 }
 void shim_conversions(long long n, double *R0, double *R1, double *P0, double *P1) {
   fps::Layout L = fps::make_layout(n);

@@ -222,3 +222,35 @@ def test_conversion_maps_match_oracle(shim, n):
         Pref = (Po * sinv[None, :])[np.ix_(oidx, idx)]
         assert np.abs(R[s].reshape(m[s], m[s]) - Rref).max() < 1e-13 * max(1, np.abs(Rref).max())
         assert np.abs(P[s].reshape(mo[s], m[s]) - Pref).max() < 1e-13 * max(1, np.abs(Pref).max())
+
+
+@pytest.mark.parametrize("n", [130, 1300, 4096])
+def test_carry_combinations_match_recurrence(shim, n):
+    shim.shim_comb.argtypes = [ctypes.c_longlong, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double)]
+    lay = _layout(shim, n)
+    J, p, _ = oshifts.square_shifts(n, 1e-13)
+    pv = np.ascontiguousarray(p[[0, J // 2, J - 1]])
+    ms, nc = lay["mstride"], lay["ncmax"]
+    pos = np.zeros(3 * 2 * 7 * ms)
+    ch = np.zeros(3 * 2 * 3 * nc)
+    comb = np.zeros(3 * 2 * nc * nc * 3)
+    shim.shim_tables(n, 3, _ptr(pv), _ptr(pos), _ptr(ch))
+    shim.shim_comb(n, 3, _ptr(pv), _ptr(comb))
+    ch = ch.reshape(3, 2, 3, nc)
+    comb = comb.reshape(3, 2, nc, nc, 3)
+    rng = np.random.default_rng(0)
+    for jj in range(3):
+        for s in (0, 1):
+            ncs = lay["nc%d" % s]
+            yl, xf = rng.standard_normal(ncs), rng.standard_normal(ncs)
+            F2last, BF2first, Bk2first = ch[jj, s]
+            cf = np.zeros(ncs)
+            for c in range(1, ncs):
+                cf[c] = yl[c - 1] + F2last[c - 1] * cf[c - 1]
+            cb = np.zeros(ncs)
+            for c in range(ncs - 2, -1, -1):
+                cb[c] = xf[c + 1] + BF2first[c + 1] * cf[c + 1] + Bk2first[c + 1] * cb[c + 1]
+            W = comb[jj, s, :ncs, :ncs]
+            assert np.allclose(W[..., 0] @ yl, cf, rtol=1e-13, atol=1e-13)
+            assert np.allclose(W[..., 1] @ yl + W[..., 2] @ xf, cb, rtol=1e-13, atol=1e-13)
