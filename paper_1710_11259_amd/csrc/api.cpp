@@ -52,11 +52,15 @@ struct fps_plan {
   fps::ShiftSet shifts;
   fps::Layout L;
   std::vector<double> tab, ctab, comb, l1;  // host sweep tables
-  std::vector<double> Rs[2], P[2];  // host conversion maps
+  std::vector<double> Rs[2], P[2];  // host conversion maps (unpadded)
+  int64_t mop[2] = {0, 0};          // output parity lengths padded to 64
   std::vector<double> sinv;         // 1/sqrt((i+1)(i+2))
 
   // device copies
-  DeviceBuf d_tab, d_ctab, d_comb, d_l1, d_Rs[2], d_P[2], d_sinv;
+  DeviceBuf d_tab, d_ctab, d_comb, d_l1, d_sinv;
+  // GEMM operands, zero-padded to multiples of 64: RsA = Rs (mp x mp),
+  // RsB = Rs^T (mp x mp), PA = P (mop x mp), PB = P^T (mp x mop).
+  DeviceBuf d_RsA[2], d_RsB[2], d_PA[2], d_PB[2];
 
   // sweep timing diagnostics
   std::vector<hipEvent_t> ev;  // pairs
@@ -191,21 +195,23 @@ fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st
   double *G = (double *)(ws + pl->off_G);
   double *GT = (double *)(ws + pl->off_GT);
   double *Tb = (double *)(ws + pl->off_O0);
-  FPS_HIP(fps::launch_fill(G, npad * npad, 0.0, st));
+  // F in the parity-blocked layout (zero padded), staged in the GT region.
+  FPS_HIP(fps::launch_permute_in(F, GT, n, npad, L.mp[0], st));
   fps::GemmProb g1[4], g2[4];
   int cnt = 0;
   int64_t toff = 0;
   for (int s = 0; s < 2; ++s)
     for (int t = 0; t < 2; ++t) {
-      const int64_t ms = L.m[s], mt = L.m[t];
+      const int64_t ms = L.mp[s], mt = L.mp[t];
       if (ms == 0 || mt == 0) continue;
       double *Tst = Tb + toff;
       toff += ms * mt;
-      // T_st = F_st Rs_t^T, with B(k, j) = Rs_t[j][k] = 0 for k < j.
-      g1[cnt] = fps::GemmProb{F + s * n + t, (const double *)pl->d_Rs[t].p, Tst, ms, mt, mt,
-                              2 * n, 2, 1, mt, mt, 1, 0, 0, 1, 0};
-      // G_st = Rs_s T_st, with A(i, k) = Rs_s[i][k] = 0 for k < i.
-      g2[cnt] = fps::GemmProb{(const double *)pl->d_Rs[s].p, Tst,
+      const double *Fst = GT + (s * L.mp[0]) * npad + t * L.mp[0];
+      // T_st = F_st Rs_t^T; B(k, j) = Rs_t[j][k] = 0 for k < j.
+      g1[cnt] = fps::GemmProb{Fst, (const double *)pl->d_RsB[t].p, Tst, ms, mt, mt,
+                              npad, 1, mt, 1, mt, 1, 0, 0, 1, 0};
+      // G_st = Rs_s T_st; A(i, k) = Rs_s[i][k] = 0 for k < i.
+      g2[cnt] = fps::GemmProb{(const double *)pl->d_RsA[s].p, Tst,
                               G + (s * L.mp[0]) * npad + t * L.mp[0], ms, mt, ms,
                               ms, 1, mt, 1, npad, 1, 1, 0, 0, 0};
       ++cnt;
@@ -220,29 +226,25 @@ fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st
 fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hipStream_t st) {
   const fps::Layout &L = pl->L;
   const int64_t n = L.n, N = n + 2, npad = L.npad;
-  // temporary n x (n+2) blocks: the O0 and O1 regions (contiguous) are free here
+  // temporaries mp_s x mop_t: the O0 and O1 regions (contiguous) are free here
   double *Tb = (double *)(ws + pl->off_O0);
-  if ((int64_t)n * (n + 2) * 8 > pl->off_lv - pl->off_O0)
+  if (npad * (pl->mop[0] + pl->mop[1]) * 8 > pl->off_lv - pl->off_O0)
     return fail(FPS_E_STATE, "internal: output temporary exceeds workspace");
   fps::GemmProb g1[4], g2[4];
   int cnt = 0;
   int64_t toff = 0;
   for (int s = 0; s < 2; ++s)
     for (int t = 0; t < 2; ++t) {
-      const int64_t ms = L.m[s], mt = L.m[t], mos = L.mo[s], mot = L.mo[t];
-      double *Ust = U + s * N + t;
-      if (ms == 0 || mt == 0) {
-        // no solution block: the output block is zero
-        continue;
-      }
+      const int64_t ms = L.mp[s], mt = L.mp[t], mot = pl->mop[t];
+      if (L.m[s] == 0 || L.m[t] == 0) continue;  // that output block stays zero
       double *Tst = Tb + toff;
       toff += ms * mot;
-      // T_st = Y_st P_t^T, B(k, j) = P_t[j][k] = 0 for k < j - 1.
-      g1[cnt] = fps::GemmProb{Y + (s * L.mp[0]) * npad + t * L.mp[0], (const double *)pl->d_P[t].p,
-                              Tst, ms, mot, mt, npad, 1, 1, mt, mot, 1, 0, 0, 1, -1};
-      // U_st = P_s T_st, A(i, k) = P_s[i][k] = 0 for k < i - 1.
-      g2[cnt] = fps::GemmProb{(const double *)pl->d_P[s].p, Tst, Ust, mos, mot, ms, ms, 1, mot, 1,
-                              2 * N, 2, 1, -1, 0, 0};
+      // T_st = Y_st P_t^T; B(k, j) = P_t[j][k] = 0 for k < j - 1.
+      g1[cnt] = fps::GemmProb{Y + (s * L.mp[0]) * npad + t * L.mp[0], (const double *)pl->d_PB[t].p,
+                              Tst, ms, mot, mt, npad, 1, mot, 1, mot, 1, 0, 0, 1, -1};
+      // U_st = P_s T_st; A(i, k) = P_s[i][k] = 0 for k < i - 1.
+      g2[cnt] = fps::GemmProb{(const double *)pl->d_PA[s].p, Tst, U + s * N + t, L.mo[s], L.mo[t],
+                              ms, ms, 1, mot, 1, 2 * N, 2, 1, -1, 0, 0};
       ++cnt;
     }
   FPS_HIP(fps::launch_fill(U, N * N, 0.0, st));
@@ -320,6 +322,26 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   pl->L = fps::make_layout(n);
   fps::build_sweep_tables(pl->L, pl->shifts.p, pl->tab, pl->ctab, pl->comb, pl->l1);
   fps::build_conversions(pl->L, pl->Rs, pl->P);
+  std::vector<double> RsA[2], RsB[2], PA[2], PB[2];
+  for (int s = 0; s < 2; ++s) {
+    const int64_t m = pl->L.m[s], mp = pl->L.mp[s], mo = pl->L.mo[s];
+    const int64_t mop = (mo + fps::kPad - 1) / fps::kPad * fps::kPad;
+    pl->mop[s] = mop;
+    RsA[s].assign((size_t)mp * mp, 0.0);
+    RsB[s].assign((size_t)mp * mp, 0.0);
+    PA[s].assign((size_t)mop * mp, 0.0);
+    PB[s].assign((size_t)mp * mop, 0.0);
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t k = 0; k < m; ++k) {
+        RsA[s][(size_t)i * mp + k] = pl->Rs[s][(size_t)i * m + k];
+        RsB[s][(size_t)k * mp + i] = pl->Rs[s][(size_t)i * m + k];
+      }
+    for (int64_t i = 0; i < mo; ++i)
+      for (int64_t k = 0; k < m; ++k) {
+        PA[s][(size_t)i * mp + k] = pl->P[s][(size_t)i * m + k];
+        PB[s][(size_t)k * mop + i] = pl->P[s][(size_t)i * m + k];
+      }
+  }
   pl->sinv.resize(n);
   for (int64_t i = 0; i < n; ++i) pl->sinv[i] = 1.0 / std::sqrt((double)(i + 1) * (double)(i + 2));
 
@@ -339,8 +361,10 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
     fps_status s;
     if ((s = upload(pl->d_tab, pl->tab)) != FPS_OK || (s = upload(pl->d_ctab, pl->ctab)) != FPS_OK ||
         (s = upload(pl->d_comb, pl->comb)) != FPS_OK || (s = upload(pl->d_l1, pl->l1)) != FPS_OK ||
-        (s = upload(pl->d_Rs[0], pl->Rs[0])) != FPS_OK || (s = upload(pl->d_Rs[1], pl->Rs[1])) != FPS_OK ||
-        (s = upload(pl->d_P[0], pl->P[0])) != FPS_OK || (s = upload(pl->d_P[1], pl->P[1])) != FPS_OK ||
+        (s = upload(pl->d_RsA[0], RsA[0])) != FPS_OK || (s = upload(pl->d_RsA[1], RsA[1])) != FPS_OK ||
+        (s = upload(pl->d_RsB[0], RsB[0])) != FPS_OK || (s = upload(pl->d_RsB[1], RsB[1])) != FPS_OK ||
+        (s = upload(pl->d_PA[0], PA[0])) != FPS_OK || (s = upload(pl->d_PA[1], PA[1])) != FPS_OK ||
+        (s = upload(pl->d_PB[0], PB[0])) != FPS_OK || (s = upload(pl->d_PB[1], PB[1])) != FPS_OK ||
         (s = upload(pl->d_sinv, pl->sinv)) != FPS_OK) {
       delete pl;
       return s;

@@ -60,10 +60,12 @@ hipError_t launch_permute_in(const double *src, double *dst, int64_t n, int64_t 
 hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st);
 hipError_t launch_fill(double *dst, int64_t count, double v, hipStream_t st);
 
-// Strided FP64 GEMM on MFMA, up to 4 independent problems per launch:
-//   C(i,j) = sum_k A(i,k) B(k,j),  A(i,k) = A[i*sai + k*sak], etc.
+// FP64 GEMM on MFMA, up to 4 independent problems per launch:
+//   C(i,j) = sum_k A(i,k) B(k,j),  A(i,k) = A[i*sai + k], B(k,j) = B[k*sbk + j],
+//   C(i,j) at C[i*sci + j*scj]  (sak and sbj must be 1; K a multiple of 16;
+//   A, B 16-byte aligned with even row strides).
 // Triangular structure: when triA, A(i,k) = 0 for k < i + offA; when triB,
-// B(k,j) = 0 for k < j + offB; tiles below the first nonzero k are skipped.
+// B(k,j) = 0 for k < j + offB; k-tiles below the first nonzero are skipped.
 struct GemmProb {
   const double *A;
   const double *B;
