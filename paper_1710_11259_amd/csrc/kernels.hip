@@ -46,8 +46,10 @@ constexpr int OFF_SY = OFF_L1 + kL1;
 constexpr int OFF_SX = OFF_SY + kWaves * kCols;
 constexpr int OFF_END = OFF_SX + kWaves * kCols;
 static_assert(OFF_END <= kSweepLds, "LDS carve-out");
-static_assert(kCols * kWaves >= 4 * kChunk && kTabSlots * kChunk <= 2 * kCols * kWaves,
-              "early loads: at most two per thread");
+constexpr int kThreads = kCols * kWaves;
+constexpr int kTabN = kTabSlots * kChunk;
+constexpr int kTabLoads = (kTabN + kThreads - 1) / kThreads;
+static_assert(2 * kChunk <= kThreads && kL1 <= kThreads, "one carry / combination value per thread");
 static_assert(T_L == 0 && T_IB == 1 && T_U == 2 && T_F1 == 3 && T_BK1 == 4, "table slot order");
 
 // kWithG: the right-hand side is v + sg * g while the output is v - sigma x
@@ -77,9 +79,12 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
   //    branches (addresses are clamped), so that waiting for them does not
   //    wait for the streaming loads.
   const double *__restrict__ tab = a.tab + (int64_t)s * kNTab * ms + kc0;
-  const int e1 = tid + kCols * kWaves < kTabSlots * kChunk ? tid + kCols * kWaves : kTabSlots * kChunk - 1;
-  const double t0 = tab[(tid / kChunk) * ms + (tid % kChunk)];
-  const double t1 = tab[(e1 / kChunk) * ms + (e1 % kChunk)];
+  double tv[kTabLoads];
+#pragma unroll
+  for (int q = 0; q < kTabLoads; ++q) {
+    const int e = tid + q * kThreads < kTabN ? tid + q * kThreads : kTabN - 1;
+    tv[q] = tab[(e / kChunk) * ms + (e % kChunk)];
+  }
   const double l1v = a.l1[((int64_t)s * ncmax + c) * kL1 + (tid < kL1 ? tid : kL1 - 1)];
   const int sp = col0 >= a.mp0 ? 1 : 0;
   const int64_t cp = (col0 - (sp ? a.mp0 : 0)) / kChunk;
@@ -112,8 +117,9 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
     }
   }
 
-  lds[OFF_TAB + tid] = t0;
-  if (tid + kCols * kWaves < kTabSlots * kChunk) lds[OFF_TAB + tid + kCols * kWaves] = t1;
+#pragma unroll
+  for (int q = 0; q < kTabLoads; ++q)
+    if (tid + q * kThreads < kTabN) lds[OFF_TAB + tid + q * kThreads] = tv[q];
   if (tid < kL1) lds[OFF_L1 + tid] = l1v;
   if (tid < 2 * kChunk) lds[OFF_AB + tid] = abv;
   __syncthreads();
@@ -158,12 +164,19 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
   const double ylast_chunk = y[kSeg - 1];
 
   // 5. Backward substitution with zero carry-in, fused with the output.
+  //    Without a g term the right-hand side is recovered from the forward
+  //    values, r_k = y_k + l_k y_{k-1} (y_{-1} = cf1), so v need not live on.
   const double sigma = a.sigma;
   double xnext = 0.0, xfirst = 0.0;
 #pragma unroll
   for (int i = kSeg - 1; i >= 0; --i) {
     const double x = y[i] * Tib[i] - Tu[i] * xnext;
-    y[i] = a.final_mode ? x : v[i] - sigma * x;
+    double rhs;
+    if constexpr (kWithG)
+      rhs = v[i];
+    else
+      rhs = y[i] + Tl[i] * (i > 0 ? y[i - 1] : cf1);
+    y[i] = a.final_mode ? x : rhs - sigma * x;
     xnext = x;
     if (i == 0) xfirst = x;
   }

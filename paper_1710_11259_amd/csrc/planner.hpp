@@ -15,7 +15,7 @@ namespace fps {
 // Sweep partition.  A chain of one parity is cut into lane segments of
 // kSeg positions; kWaves consecutive segments form a chunk handled by one
 // workgroup; chunks are joined through a second-level carry recurrence.
-constexpr int kSeg = 16;
+constexpr int kSeg = 8;
 constexpr int kWaves = 8;
 constexpr int kChunk = kSeg * kWaves;
 constexpr int kCols = 64;   // chains per wavefront (one per lane)
