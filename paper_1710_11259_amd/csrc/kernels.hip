@@ -227,26 +227,30 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
 
 // Chunk carries of one half-sweep: thread (parity s, chunk c, chain r)
 // forms cf[c], cb[c] of chain r as linear combinations of the chain's chunk
-// boundary values (coefficients precomputed per shift), scaled by `scale`.
-// Output layout ab[s][c][r][2].
+// boundary values (coefficients precomputed per shift and staged in LDS, one
+// row per block), scaled by `scale`.  Output layout ab[s][c][r][2].
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ lv,
                                                 const double *__restrict__ comb,
                                                 double *__restrict__ ab, double scale,
                                                 int64_t npad, int nc0, int nc1, int64_t ncmax) {
+  extern __shared__ double wrow[];  // [nc][kNComb]
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y >= ncmax ? 1 : 0;
   const int c = blockIdx.y - (s ? (int)ncmax : 0);
   const int nc = s ? nc1 : nc0;
-  if (c >= nc || r >= npad) return;
+  if (c >= nc) return;
   const double *__restrict__ W = comb + (((int64_t)s * ncmax + c) * ncmax) * kNComb;
+  for (int e = threadIdx.x; e < nc * kNComb; e += blockDim.x) wrow[e] = W[e];
+  __syncthreads();
+  if (r >= npad) return;
   const double *__restrict__ lp = lv + (int64_t)s * 2 * npad + r;
   double A = 0.0, B = 0.0;
 #pragma unroll 16
   for (int q = 0; q < nc; ++q) {
     const double yl = lp[(int64_t)q * 4 * npad];
     const double xf = lp[(int64_t)q * 4 * npad + npad];
-    A += W[q * kNComb + K_CF] * yl;
-    B += W[q * kNComb + K_CBY] * yl + W[q * kNComb + K_CBX] * xf;
+    A += wrow[q * kNComb + K_CF] * yl;
+    B += wrow[q * kNComb + K_CBY] * yl + wrow[q * kNComb + K_CBX] * xf;
   }
   double *o = ab + (((int64_t)s * ncmax + c) * npad + r) * 2;
   o[0] = scale * A;
@@ -439,7 +443,9 @@ template hipError_t launch_sweep<float>(const SweepArgs &, hipStream_t);
 hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
                          int64_t npad, int nc0, int nc1, int64_t ncmax, hipStream_t st) {
   dim3 grid((unsigned)((npad + 255) / 256), (unsigned)(2 * ncmax));
-  hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, lv, comb, ab, scale, npad, nc0, nc1, ncmax);
+  const size_t shm = (size_t)ncmax * kNComb * sizeof(double);
+  if (shm > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce, grid, dim3(256), shm, st, lv, comb, ab, scale, npad, nc0, nc1, ncmax);
   return hipGetLastError();
 }
 
