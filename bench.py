@@ -18,6 +18,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "dof/s, square Poisson n=4096 at rel err ≤1e-12; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# Calibrated HBM traffic of the sweep kernel per launch at n = 4096 (rocprofv3
+# FETCH_SIZE x2.000 + WRITE_SIZE x1.000, see profiles/sweep_square_n4096.md),
+# valid only for the sweep source with this sha256.
+SWEEP_TRAFFIC = {"sha256": "3934e31aeec99cef01392722df5295b2dec6ba6ad9b4a80b9b9dae7d158c956d",
+                 "n": 4096, "half_step_1": 278.9e6, "half_step_2": 413.1e6}
 
 
 def main() -> int:
@@ -96,8 +101,17 @@ def main() -> int:
     t2 = sum(hs2) / max(len(hs2), 1) * 1e-3
     b1, b2 = 16.0 * dof, 24.0 * dof
     achieved = (b1 + b2) / (t1 + t2) / 1e9
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1710_11259_amd", "csrc", "sweep.hip"), "rb") as fh:
+        sweep_sha = hashlib.sha256(fh.read()).hexdigest()
+    traffic = None
+    if sweep_sha == SWEEP_TRAFFIC["sha256"] and n == SWEEP_TRAFFIC["n"]:
+        traffic = (SWEEP_TRAFFIC["half_step_1"] + SWEEP_TRAFFIC["half_step_2"]) / 2.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_note": "calibrated HBM bytes per launch, mean of the two half-steps "
+                                "(algorithmic mean 335.5e6)" if traffic else
+                                "null: sweep source changed since the counters were taken",
                 "kernel": "k_sweep (ADI half-sweeps; both variants, byte-weighted)",
                 "bytes_per_launch": {"half_step_1": b1, "half_step_2": b2},
                 "avg_launch_us": {"half_step_1": round(t1 * 1e6, 2),

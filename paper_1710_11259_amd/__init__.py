@@ -15,8 +15,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["lib", "Plan", "plan", "solve", "adi_native", "adi_shifts", "FpsError",
-           "LIB_PATH"]
+__all__ = ["lib", "Plan", "plan", "solve", "solve_adjoint", "solve_fn", "adi_native",
+           "adi_shifts", "FpsError", "LIB_PATH"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfps.so")
@@ -171,6 +171,65 @@ def solve(p: Plan, F, out=None, ws=None):
                            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                            _stream_ptr(torch, F.device)))
     return out
+
+
+def solve_adjoint(p: Plan, Ubar, out=None, ws=None):
+    """Fbar with <solve(F), Ubar> = <F, Fbar> (the transpose of the solve map)."""
+    import torch
+    if Ubar.dtype != torch.float64 or not Ubar.is_cuda or not Ubar.is_contiguous():
+        raise ValueError("Ubar must be a contiguous float64 tensor on the GPU")
+    if tuple(Ubar.shape) != p.out_shape():
+        raise ValueError(f"Ubar must have shape {p.out_shape()}")
+    if out is None:
+        out = torch.empty((p.n,) * p.dim, dtype=torch.float64, device=Ubar.device)
+    if ws is None:
+        ws = workspace(p, Ubar.device)
+    _check(lib().fps_solve_adjoint(p.handle, ctypes.c_void_p(Ubar.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(ws.data_ptr()),
+                                   _stream_ptr(torch, Ubar.device)))
+    return out
+
+
+def _solve_fn_class():
+    import torch
+
+    class SolveFn(torch.autograd.Function):
+        """Differentiable square solve.  forward: U = solve(F) for F of shape
+        (n, n) or (batch, n, n); backward: the adjoint solve (same ADI sweeps
+        between transposed coefficient maps), nothing stored from the forward
+        pass because the map is linear in F."""
+
+        @staticmethod
+        def forward(ctx, F, plan):
+            ctx.plan = plan
+            ws = workspace(plan, F.device)
+            Fc = F.contiguous()
+            if Fc.dim() == 2:
+                return solve(plan, Fc, ws=ws)
+            return torch.stack([solve(plan, Fc[b], ws=ws) for b in range(Fc.shape[0])])
+
+        @staticmethod
+        def backward(ctx, Ubar):
+            plan = ctx.plan
+            ws = workspace(plan, Ubar.device)
+            Uc = Ubar.contiguous()
+            if Uc.dim() == 2:
+                return solve_adjoint(plan, Uc, ws=ws), None
+            return torch.stack([solve_adjoint(plan, Uc[b], ws=ws)
+                                for b in range(Uc.shape[0])]), None
+
+    return SolveFn
+
+
+def solve_fn(F, plan: Plan):
+    """Autograd entry point: SolveFn.apply(F, plan)."""
+    global _SolveFn
+    try:
+        cls = _SolveFn
+    except NameError:
+        cls = _SolveFn = _solve_fn_class()
+    return cls.apply(F, plan)
 
 
 def adi_native(p: Plan, G, out=None, ws=None):

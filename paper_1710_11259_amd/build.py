@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfps.so")
-SOURCES = ["planner.cpp", "kernels.hip", "api.cpp"]
+SOURCES = ["planner.cpp", "sweep.hip", "gemm.hip", "kernels.hip", "api.cpp"]
 ARCH = os.environ.get("FPS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -68,6 +68,7 @@ struct fps_plan {
 
   // workspace layout (byte offsets)
   int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab = 0;
+  int64_t off_X = 0;  // adjoint: the output cotangent in the parity-blocked layout
   int64_t ws_bytes = 0;
 
   const double *tab_dev(int j) const {
@@ -209,11 +210,11 @@ fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st
       const double *Fst = GT + (s * L.mp[0]) * npad + t * L.mp[0];
       // T_st = F_st Rs_t^T; B(k, j) = Rs_t[j][k] = 0 for k < j.
       g1[cnt] = fps::GemmProb{Fst, (const double *)pl->d_RsB[t].p, Tst, ms, mt, mt,
-                              npad, 1, mt, 1, mt, 1, 0, 0, 1, 0};
+                              npad, 1, mt, 1, mt, 1, 0, 0, 1, 0, 0, 0, 0, 0};
       // G_st = Rs_s T_st; A(i, k) = Rs_s[i][k] = 0 for k < i.
       g2[cnt] = fps::GemmProb{(const double *)pl->d_RsA[s].p, Tst,
                               G + (s * L.mp[0]) * npad + t * L.mp[0], ms, mt, ms,
-                              ms, 1, mt, 1, npad, 1, 1, 0, 0, 0};
+                              ms, 1, mt, 1, npad, 1, 1, 0, 0, 0, 0, 0, 0, 0};
       ++cnt;
     }
   FPS_HIP(fps::launch_gemm(g1, cnt, st));
@@ -241,10 +242,10 @@ fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hip
       toff += ms * mot;
       // T_st = Y_st P_t^T; B(k, j) = P_t[j][k] = 0 for k < j - 1.
       g1[cnt] = fps::GemmProb{Y + (s * L.mp[0]) * npad + t * L.mp[0], (const double *)pl->d_PB[t].p,
-                              Tst, ms, mot, mt, npad, 1, mot, 1, mot, 1, 0, 0, 1, -1};
+                              Tst, ms, mot, mt, npad, 1, mot, 1, mot, 1, 0, 0, 1, -1, 0, 0, 0, 0};
       // U_st = P_s T_st; A(i, k) = P_s[i][k] = 0 for k < i - 1.
       g2[cnt] = fps::GemmProb{(const double *)pl->d_PA[s].p, Tst, U + s * N + t, L.mo[s], L.mo[t],
-                              ms, ms, 1, mot, 1, 2 * N, 2, 1, -1, 0, 0};
+                              ms, ms, 1, mot, 1, 2 * N, 2, 1, -1, 0, 0, 0, 0, 0, 0};
       ++cnt;
     }
   FPS_HIP(fps::launch_fill(U, N * N, 0.0, st));
@@ -355,7 +356,9 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   pl->off_O1 = 3 * sq;
   pl->off_lv = 4 * sq;
   pl->off_ab = 4 * sq + lvb;
-  pl->ws_bytes = 4 * sq + lvb + abb;
+  const int64_t mobar = pl->mop[0] + pl->mop[1];
+  pl->off_X = 4 * sq + lvb + abb;
+  pl->ws_bytes = pl->off_X + align256(mobar * mobar * 8);
 
   if (!(flags & FPS_PLAN_HOST_ONLY)) {
     fps_status s;
@@ -438,8 +441,75 @@ fps_status fps_solve_adjoint(fps_plan *pl, const double *Ubar, double *Fbar, voi
                              void *stream) {
   fps_status s = check_solve_args(pl, Ubar, Fbar, ws);
   if (s != FPS_OK) return s;
-  (void)stream;
-  return fail(FPS_E_UNSUPPORTED, "adjoint not available in this build");
+  if (pl->dim != 2 || pl->prec != FPS_FP64)
+    return fail(FPS_E_UNSUPPORTED, "adjoint: square FP64 plans only");
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  const fps::Layout &L = pl->L;
+  const int64_t n = L.n, npad = L.npad, N = n + 2;
+  double *G = (double *)(w + pl->off_G);
+  double *GT = (double *)(w + pl->off_GT);
+  double *Tb = (double *)(w + pl->off_O0);  // O0 and O1 (contiguous) as temporaries
+  // 1. Ybar = P^T Ubar P (Chebyshev output) or S^-1 Xbar S^-1 (native), in G.
+  if (pl->out_basis == FPS_OUT_NATIVE) {
+    FPS_HIP(fps::launch_permute_in(Ubar, G, n, npad, L.mp[0], st, (const double *)pl->d_sinv.p));
+  } else {
+    const int64_t mo0 = pl->mop[0], mobar = pl->mop[0] + pl->mop[1];
+    if (npad * mobar * 8 > pl->off_lv - pl->off_O0)
+      return fail(FPS_E_STATE, "internal: adjoint temporaries exceed workspace");
+    double *Up = (double *)(w + pl->off_X);  // Ubar in the parity-blocked layout, mobar x mobar
+    double *Tt = Tb;                          // temporaries mop_s x mp_t
+    FPS_HIP(fps::launch_permute_in(Ubar, Up, N, mobar, mo0, st));
+    fps::GemmProb g1[4], g2[4];
+    int cnt = 0;
+    int64_t toff = 0;
+    for (int s2 = 0; s2 < 2; ++s2)
+      for (int t = 0; t < 2; ++t) {
+        const int64_t ms = L.mp[s2], mt = L.mp[t], mos = pl->mop[s2], mot = pl->mop[t];
+        if (L.m[s2] == 0 || L.m[t] == 0) continue;
+        double *Tst = Tt + toff;
+        toff += mos * mt;
+        // T_st = Ubar_st P_t; B(k, j) = P_t[k][j] = 0 for k > j + 1.
+        g1[cnt] = fps::GemmProb{Up + (s2 * mo0) * mobar + t * mo0, (const double *)pl->d_PA[t].p,
+                                Tst, mos, mt, mot, mobar, 1, mt, 1, mt, 1, 0, 0, 0, 0, 0, 0, 1, 1};
+        // Ybar_st = P_s^T T_st; A(i, k) = P_s[k][i] = 0 for k > i + 1.
+        g2[cnt] = fps::GemmProb{(const double *)pl->d_PB[s2].p, Tst,
+                                G + (s2 * L.mp[0]) * npad + t * L.mp[0], ms, mt, mos, mos, 1, mt, 1,
+                                npad, 1, 0, 0, 0, 0, 1, 1, 0, 0};
+        ++cnt;
+      }
+    FPS_HIP(fps::launch_fill(G, npad * npad, 0.0, st));
+    FPS_HIP(fps::launch_gemm(g1, cnt, st));
+    FPS_HIP(fps::launch_gemm(g2, cnt, st));
+  }
+  // 2. The same J-step ADI map (self-adjoint for symmetric shifts).
+  FPS_HIP(fps::launch_transpose(G, GT, npad, st));
+  if ((s = run_adi(pl, w, st)) != FPS_OK) return s;
+  const int J = pl->shifts.J;
+  FPS_HIP(fps::launch_finalize((double *)(w + pl->off_O1), (double *)(w + pl->off_ab),
+                               pl->tab_dev(J - 1), G, 0, nullptr, n, npad, L.mp[0], L.mstride,
+                               L.ncmax, st));
+  // 3. Fbar = R^T S^-1 Gbar S^-1 R, blockwise Rs_s^T Gbar_st Rs_t into the strided view of Fbar.
+  fps::GemmProb g1[4], g2[4];
+  int cnt = 0;
+  int64_t toff = 0;
+  for (int s2 = 0; s2 < 2; ++s2)
+    for (int t = 0; t < 2; ++t) {
+      const int64_t ms = L.mp[s2], mt = L.mp[t];
+      if (L.m[s2] == 0 || L.m[t] == 0) continue;
+      double *Tst = Tb + toff;
+      toff += ms * mt;
+      // T_st = Gbar_st Rs_t; B(k, j) = Rs_t[k][j] = 0 for k > j.
+      g1[cnt] = fps::GemmProb{G + (s2 * L.mp[0]) * npad + t * L.mp[0], (const double *)pl->d_RsA[t].p,
+                              Tst, ms, mt, mt, npad, 1, mt, 1, mt, 1, 0, 0, 0, 0, 0, 0, 1, 0};
+      // Fbar_st = Rs_s^T T_st; A(i, k) = Rs_s[k][i] = 0 for k > i.
+      g2[cnt] = fps::GemmProb{(const double *)pl->d_RsB[s2].p, Tst, Fbar + s2 * n + t, L.m[s2],
+                              L.m[t], ms, ms, 1, mt, 1, 2 * n, 2, 0, 0, 0, 0, 1, 0, 0, 0};
+      ++cnt;
+    }
+  FPS_HIP(fps::launch_gemm(g1, cnt, st));
+  FPS_HIP(fps::launch_gemm(g2, cnt, st));
+  return FPS_OK;
 }
 
 fps_status fps_plan_set_sweep_timing(fps_plan *pl, int capacity) {

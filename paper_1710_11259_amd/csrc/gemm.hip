@@ -1,0 +1,162 @@
+// gfx950 FP64 MFMA GEMM for the dense coefficient maps of the spectral
+// Poisson solver (Chebyshev <-> C~^(3/2) maps of Sec. 3.4 and Table 1).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace fps {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// FP64 GEMM on v_mfma_f64_16x16x4f64: C = A B with A row-major (k
+// contiguous, lda), B row-major (n contiguous, ldb), C(i, j) at
+// C[i*ldci + j*ldcj].  Tile 128 x 128 x 16, four wavefronts in a 2 x 2
+// grid, each computing a 64 x 64 quarter as 4 x 4 MFMA blocks; the next
+// k-tile is fetched into registers while the current one is multiplied.
+// Operand layout of the 16x16x4 f64 instruction: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r of lane l
+// holds C[4r + l / 16][l % 16].
+// Requirements (checked by the launcher): K, lda, ldb multiples of 16 bytes'
+// worth of doubles (even) and A, B 16-byte aligned; rows/columns of A and B
+// beyond M, N, K must be readable up to the next multiple of the tile (the
+// plan pads every operand to multiples of 64 with zeros) -- loads are
+// clamped to M and N and zero-filled, so only K needs padding.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+struct GemmBatch {
+  GemmProb p[4];
+};
+
+constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
+
+__global__ __launch_bounds__(256, 2) void k_gemm(GemmBatch batch) {
+  const GemmProb g = batch.p[blockIdx.z];
+  const int64_t i0 = (int64_t)blockIdx.y * GBM, j0 = (int64_t)blockIdx.x * GBN;
+  if (i0 >= g.M || j0 >= g.N) return;
+  __shared__ double As[GBK][GBM + GPAD];
+  __shared__ double Bs[GBK][GBN + GPAD];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wy = wid >> 1, wx = wid & 1;
+
+  int64_t klo = 0;
+  if (g.triA) klo = i0 + g.offA > klo ? i0 + g.offA : klo;
+  if (g.triB) klo = j0 + g.offB > klo ? j0 + g.offB : klo;
+  klo = klo / GBK * GBK;
+  int64_t khi = g.K;
+  if (g.triAu) {
+    const int64_t e = i0 + GBM - 1 + g.offAu + 1;
+    khi = e < khi ? e : khi;
+  }
+  if (g.triBu) {
+    const int64_t e = j0 + GBN - 1 + g.offBu + 1;
+    khi = e < khi ? e : khi;
+  }
+  khi = (khi + GBK - 1) / GBK * GBK;
+  if (khi > g.K) khi = g.K;
+
+  // Loader mapping.  A tile 128 x 16: thread t reads row t/2, k-run (t%2)*8..+8.
+  // B tile 16 x 128: thread t reads k-row t/16, column run (t%16)*8..+8.
+  const int ar = tid >> 1, ak = (tid & 1) * 8;
+  const int bk = tid >> 4, bc = (tid & 15) * 8;
+  const int64_t arow = i0 + ar < g.M ? i0 + ar : g.M - 1;
+  const double az = i0 + ar < g.M ? 1.0 : 0.0;
+  const double *__restrict__ Ap = g.A + arow * g.sai + ak;
+  const double *__restrict__ Bp = g.B + (int64_t)bk * g.sbk + j0 + bc;
+  const bool bfull = j0 + bc + 8 <= g.N;
+
+  dbl2 ra[4], rb[4];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ra[q] = *(const dbl2 *)(Ap + k0 + 2 * q);
+    const double *bp = Bp + k0 * g.sbk;
+    if (bfull) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rb[q] = *(const dbl2 *)(bp + 2 * q);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t jj = j0 + bc + 2 * q;
+        rb[q].x = jj < g.N ? bp[2 * q] : 0.0;
+        rb[q].y = jj + 1 < g.N ? bp[2 * q + 1] : 0.0;
+      }
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[ak + 2 * q][ar] = az * ra[q].x;
+      As[ak + 2 * q + 1][ar] = az * ra[q].y;
+      *(dbl2 *)&Bs[bk][bc + 2 * q] = rb[q];
+    }
+  };
+
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  if (klo < khi) {
+    fetch(klo);
+    stash();
+    __syncthreads();
+    for (int64_t k0 = klo; k0 < khi; k0 += GBK) {
+      const bool more = k0 + GBK < khi;
+      if (more) fetch(k0 + GBK);
+#pragma unroll
+      for (int ks = 0; ks < GBK; ks += 4) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = As[ks + (lane >> 4)][wy * 64 + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = Bs[ks + (lane >> 4)][wx * 64 + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+      __syncthreads();
+      if (more) {
+        stash();
+        __syncthreads();
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + wy * 64 + a * 16 + 4 * r + (lane >> 4);
+        const int64_t gj = j0 + wx * 64 + b * 16 + (lane & 15);
+        if (gi < g.M && gj < g.N) g.C[gi * g.sci + gj * g.scj] = acc[a][b][r];
+      }
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmProb *probs, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (count > 4) return hipErrorInvalidValue;
+  GemmBatch b{};
+  int64_t mt = 1, nt = 1;
+  for (int i = 0; i < count; ++i) {
+    const GemmProb &q = probs[i];
+    // contiguous operands, 16-byte aligned, K padded to the k-tile
+    if (q.sak != 1 || q.sbj != 1 || q.K % GBK != 0 || (q.sai & 1) || (q.sbk & 1) ||
+        ((uintptr_t)q.A & 15) || ((uintptr_t)q.B & 15) || q.M < 1 || q.N < 1)
+      return hipErrorInvalidValue;
+    b.p[i] = probs[i];
+    mt = probs[i].M > mt * GBM ? (probs[i].M + GBM - 1) / GBM : mt;
+    nt = probs[i].N > nt * GBN ? (probs[i].N + GBN - 1) / GBN : nt;
+  }
+  dim3 grid((unsigned)nt, (unsigned)mt, (unsigned)count);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, b);
+  return hipGetLastError();
+}
+
+}  // namespace fps

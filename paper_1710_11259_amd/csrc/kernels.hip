@@ -1,23 +1,5 @@
-// gfx950 kernels of the spectral Poisson solver.
-//
-// Sweep design (one launch per ADI half-sweep of Algorithm 2):
-//   * every lane owns one chain (storage column) and kSeg consecutive
-//     positions of it; kWaves wavefronts stacked along the chain form a chunk;
-//   * the Thomas recurrences y_k = r_k - l_k y_{k-1} and
-//     x_k = ib_k y_k - u_k x_{k+1} use factors of the whole chain (computed
-//     once per shift on the host), so splitting a chain only re-associates
-//     the recurrences: each piece runs with zero carries and the true carry
-//     enters through precomputed multiplier products;
-//   * carries between the segments of a chunk go through LDS; carries
-//     between chunks are left in a small array, resolved by k_reduce, and
-//     folded into the next pass when it reads its input;
-//   * the multiply by (A~ - p' I) that Algorithm 2 applies after each solve
-//     along the same direction is r - (p + p') x, so no neighbour access is
-//     needed; the pass output is stored transposed so that the next pass,
-//     which solves along the other direction, again reads whole rows;
-//   * the right-hand side G enters only the column half-step: the row
-//     half-step's output V - G = R - 2p Y_{1/2} needs no G, and the column
-//     half-step adds G to its right-hand side but not to its output.
+// gfx950 element-wise and data-movement kernels of the spectral Poisson
+// solver: parity-blocked permutation, transpose, finalization, fill.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -25,237 +7,6 @@
 namespace fps {
 
 namespace {
-
-template <typename T>
-__device__ __forceinline__ double ld_as_double(const T *p) {
-  return (double)(*p);
-}
-
-// LDS of one sweep workgroup (doubles).  The early region holds the
-// chunk's slice of the per-position tables, the producer's chunk carries of
-// this workgroup's rows, the segment-carry combinations and the segment
-// boundary values; it is dead before the staging tile of the transposed
-// store reuses the space.
-constexpr int kStage = kCols * (kSeg + 1);  // staging doubles per wavefront
-constexpr int kSweepLds = kWaves * kStage;
-constexpr int kTabSlots = 5;                // l, ib, u, F1, Bk1
-constexpr int OFF_TAB = 0;
-constexpr int OFF_AB = OFF_TAB + kTabSlots * kChunk;
-constexpr int OFF_L1 = OFF_AB + 2 * kChunk;
-constexpr int OFF_SY = OFF_L1 + kL1;
-constexpr int OFF_SX = OFF_SY + kWaves * kCols;
-constexpr int OFF_END = OFF_SX + kWaves * kCols;
-static_assert(OFF_END <= kSweepLds, "LDS carve-out");
-constexpr int kThreads = kCols * kWaves;
-constexpr int kTabN = kTabSlots * kChunk;
-constexpr int kTabLoads = (kTabN + kThreads - 1) / kThreads;
-static_assert(2 * kChunk <= kThreads && kL1 <= kThreads, "one carry / combination value per thread");
-static_assert(T_L == 0 && T_IB == 1 && T_U == 2 && T_F1 == 3 && T_BK1 == 4, "table slot order");
-
-// kWithG: the right-hand side is v + sg * g while the output is v - sigma x
-// (g is not carried into the output); otherwise the right-hand side is v.
-// v = in_scale * in + (chunk carries of the producing pass).
-template <typename T, bool kWithG>
-__global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
-  __shared__ double lds[kSweepLds];
-  const int tid = threadIdx.x;
-  const int lane = tid & (kCols - 1);
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t npad = a.npad, ms = a.mstride, ncmax = a.ncmax;
-  const int64_t col0 = (int64_t)blockIdx.x * kCols;
-  const int64_t col = col0 + lane;
-  const int by = blockIdx.y;
-  const int s = by < a.nc0 ? 0 : 1;
-  const int c = by - (s ? a.nc0 : 0);
-  const int64_t mps = s ? a.mp1 : a.mp0;
-  const int64_t kc0 = (int64_t)c * kChunk;     // first chain position of the chunk
-  const int64_t k0 = kc0 + (int64_t)w * kSeg;   // first position of this segment
-  const bool active = k0 < mps;
-  const int64_t rbase = (s ? a.mp0 : 0) + kc0;  // storage row of the chunk start
-  const int64_t row0 = rbase + (int64_t)w * kSeg;
-  const bool has_prev = a.ab_prev != nullptr;
-
-  // 1. Small loads, issued before the streaming loads and without divergent
-  //    branches (addresses are clamped), so that waiting for them does not
-  //    wait for the streaming loads.
-  const double *__restrict__ tab = a.tab + (int64_t)s * kNTab * ms + kc0;
-  double tv[kTabLoads];
-#pragma unroll
-  for (int q = 0; q < kTabLoads; ++q) {
-    const int e = tid + q * kThreads < kTabN ? tid + q * kThreads : kTabN - 1;
-    tv[q] = tab[(e / kChunk) * ms + (e % kChunk)];
-  }
-  const double l1v = a.l1[((int64_t)s * ncmax + c) * kL1 + (tid < kL1 ? tid : kL1 - 1)];
-  const int sp = col0 >= a.mp0 ? 1 : 0;
-  const int64_t cp = (col0 - (sp ? a.mp0 : 0)) / kChunk;
-  double abv = 0.0, bf = 0.0, bk = 0.0;
-  if (has_prev) {
-    const int e2 = tid < 2 * kChunk ? tid : 2 * kChunk - 1;
-    abv = a.ab_prev[(((int64_t)sp * ncmax + cp) * npad + rbase) * 2 + e2];
-    const int64_t kp = col - (sp ? a.mp0 : 0);
-    const double *tp = a.tab_prev + (int64_t)sp * kNTab * ms;
-    bf = tp[T_BF2 * ms + kp];
-    bk = tp[T_BK2 * ms + kp];
-  }
-
-  // 2. Streaming loads (rows clamped for the idle segments past the chain end).
-  double v[kSeg], y[kSeg];
-  {
-    const T *__restrict__ in = (const T *)a.in;
-#pragma unroll
-    for (int i = 0; i < kSeg; ++i) {
-      const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
-      v[i] = ld_as_double(in + r * npad + col);
-    }
-  }
-  if constexpr (kWithG) {
-    const double *__restrict__ gp = a.g;
-#pragma unroll
-    for (int i = 0; i < kSeg; ++i) {
-      const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
-      y[i] = gp[r * npad + col];
-    }
-  }
-
-#pragma unroll
-  for (int q = 0; q < kTabLoads; ++q)
-    if (tid + q * kThreads < kTabN) lds[OFF_TAB + tid + q * kThreads] = tv[q];
-  if (tid < kL1) lds[OFF_L1 + tid] = l1v;
-  if (tid < 2 * kChunk) lds[OFF_AB + tid] = abv;
-  __syncthreads();
-
-  const double *Tl = lds + OFF_TAB + 0 * kChunk + w * kSeg;
-  const double *Tib = lds + OFF_TAB + 1 * kChunk + w * kSeg;
-  const double *Tu = lds + OFF_TAB + 2 * kChunk + w * kSeg;
-  const double *Tf1 = lds + OFF_TAB + 3 * kChunk + w * kSeg;
-  const double *Tbk1 = lds + OFF_TAB + 4 * kChunk + w * kSeg;
-  const double *Ab = lds + OFF_AB + 2 * w * kSeg;
-
-  // 3. Right-hand side.  Idle segments carry exact zeros.
-  const double act = active ? 1.0 : 0.0;
-  const double isc = act * a.in_scale;
-  const double cA = has_prev ? act * bf : 0.0, cB = has_prev ? act * bk : 0.0;
-#pragma unroll
-  for (int i = 0; i < kSeg; ++i) {
-    v[i] = isc * v[i] + Ab[2 * i] * cA + Ab[2 * i + 1] * cB;
-    if constexpr (kWithG)
-      y[i] = v[i] + (act * a.sg) * y[i];
-    else
-      y[i] = v[i];
-  }
-
-  // 4. Forward elimination with zero carry-in, then the segment carry.
-  {
-    double carry = 0.0;
-#pragma unroll
-    for (int i = 0; i < kSeg; ++i) {
-      y[i] = y[i] - Tl[i] * carry;
-      carry = y[i];
-    }
-  }
-  lds[OFF_SY + w * kCols + lane] = y[kSeg - 1];
-  __syncthreads();
-  double cf1 = 0.0;
-#pragma unroll
-  for (int u = 0; u < kWaves; ++u)
-    cf1 += lds[OFF_L1 + (0 * kWaves + w) * kWaves + u] * lds[OFF_SY + u * kCols + lane];
-#pragma unroll
-  for (int i = 0; i < kSeg; ++i) y[i] += Tf1[i] * cf1;
-  const double ylast_chunk = y[kSeg - 1];
-
-  // 5. Backward substitution with zero carry-in, fused with the output.
-  //    Without a g term the right-hand side is recovered from the forward
-  //    values, r_k = y_k + l_k y_{k-1} (y_{-1} = cf1), so v need not live on.
-  const double sigma = a.sigma;
-  double xnext = 0.0, xfirst = 0.0;
-#pragma unroll
-  for (int i = kSeg - 1; i >= 0; --i) {
-    const double x = y[i] * Tib[i] - Tu[i] * xnext;
-    double rhs;
-    if constexpr (kWithG)
-      rhs = v[i];
-    else
-      rhs = y[i] + Tl[i] * (i > 0 ? y[i - 1] : cf1);
-    y[i] = a.final_mode ? x : rhs - sigma * x;
-    xnext = x;
-    if (i == 0) xfirst = x;
-  }
-  lds[OFF_SX + w * kCols + lane] = xfirst;
-  __syncthreads();
-  double cb1 = 0.0;
-#pragma unroll
-  for (int u = 0; u < kWaves; ++u)
-    cb1 += lds[OFF_L1 + (1 * kWaves + w) * kWaves + u] * lds[OFF_SX + u * kCols + lane];
-  const double coef = (a.final_mode ? 1.0 : -sigma) * cb1;
-#pragma unroll
-  for (int i = 0; i < kSeg; ++i) y[i] += coef * Tbk1[i];
-
-  // 6. Chunk boundary values for the chunk carries.
-  if (w == kWaves - 1) a.lv[(((int64_t)c * 2 + s) * 2 + 0) * npad + col] = ylast_chunk;
-  if (w == 0) a.lv[(((int64_t)c * 2 + s) * 2 + 1) * npad + col] = xfirst + Tbk1[0] * cb1;
-
-  T *__restrict__ out = (T *)a.out;
-  if (a.final_mode) {
-    if (active) {
-#pragma unroll
-      for (int i = 0; i < kSeg; ++i) out[(row0 + i) * npad + col] = (T)y[i];
-    }
-    return;
-  }
-  // 7. Transposed store staged through LDS: output row col0 + j receives this
-  //    segment's kSeg positions as one contiguous 128-byte run.
-  double *stage = lds + w * kStage;
-  __syncthreads();  // the early region is dead
-#pragma unroll
-  for (int i = 0; i < kSeg; ++i) stage[lane * (kSeg + 1) + i] = y[i];
-  __syncthreads();
-  if (active) {
-    constexpr int kLanesPerRow = kSeg / 2;
-    constexpr int kRowsPerStore = kCols / kLanesPerRow;
-#pragma unroll
-    for (int t = 0; t < kCols / kRowsPerStore; ++t) {
-      const int orow = kRowsPerStore * t + lane / kLanesPerRow;
-      const int ocol = 2 * (lane % kLanesPerRow);
-      const double v0 = stage[orow * (kSeg + 1) + ocol];
-      const double v1 = stage[orow * (kSeg + 1) + ocol + 1];
-      T *dst = out + (col0 + orow) * npad + row0 + ocol;
-      dst[0] = (T)v0;
-      dst[1] = (T)v1;
-    }
-  }
-}
-
-// Chunk carries of one half-sweep: thread (parity s, chunk c, chain r)
-// forms cf[c], cb[c] of chain r as linear combinations of the chain's chunk
-// boundary values (coefficients precomputed per shift and staged in LDS, one
-// row per block), scaled by `scale`.  Output layout ab[s][c][r][2].
-__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ lv,
-                                                const double *__restrict__ comb,
-                                                double *__restrict__ ab, double scale,
-                                                int64_t npad, int nc0, int nc1, int64_t ncmax) {
-  extern __shared__ double wrow[];  // [nc][kNComb]
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = blockIdx.y >= ncmax ? 1 : 0;
-  const int c = blockIdx.y - (s ? (int)ncmax : 0);
-  const int nc = s ? nc1 : nc0;
-  if (c >= nc) return;
-  const double *__restrict__ W = comb + (((int64_t)s * ncmax + c) * ncmax) * kNComb;
-  for (int e = threadIdx.x; e < nc * kNComb; e += blockDim.x) wrow[e] = W[e];
-  __syncthreads();
-  if (r >= npad) return;
-  const double *__restrict__ lp = lv + (int64_t)s * 2 * npad + r;
-  double A = 0.0, B = 0.0;
-#pragma unroll 16
-  for (int q = 0; q < nc; ++q) {
-    const double yl = lp[(int64_t)q * 4 * npad];
-    const double xf = lp[(int64_t)q * 4 * npad + npad];
-    A += wrow[q * kNComb + K_CF] * yl;
-    B += wrow[q * kNComb + K_CBY] * yl + wrow[q * kNComb + K_CBX] * xf;
-  }
-  double *o = ab + (((int64_t)s * ncmax + c) * npad + r) * 2;
-  o[0] = scale * A;
-  o[1] = scale * B;
-}
 
 __global__ void k_finalize(const double *__restrict__ x, const double *__restrict__ ab,
                            const double *__restrict__ tab, double *__restrict__ out, int mode,
@@ -282,13 +33,18 @@ __global__ void k_finalize(const double *__restrict__ x, const double *__restric
 }
 
 __global__ void k_permute_in(const double *__restrict__ src, double *__restrict__ dst, int64_t n,
-                             int64_t npad, int64_t mp0) {
+                             int64_t npad, int64_t mp0, const double *__restrict__ sinv) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t r = blockIdx.y;
   if (q >= npad) return;
   const int s = r >= mp0 ? 1 : 0, t = q >= mp0 ? 1 : 0;
   const int64_t i = 2 * (r - (s ? mp0 : 0)) + s, j = 2 * (q - (t ? mp0 : 0)) + t;
-  dst[r * npad + q] = (i < n && j < n) ? src[i * n + j] : 0.0;
+  double v = 0.0;
+  if (i < n && j < n) {
+    v = src[i * n + j];
+    if (sinv) v *= sinv[i] * sinv[j];
+  }
+  dst[r * npad + q] = v;
 }
 
 __global__ __launch_bounds__(256) void k_transpose(const double *__restrict__ src,
@@ -306,148 +62,7 @@ __global__ void k_fill(double *__restrict__ dst, int64_t count, double v) {
   if (i < count) dst[i] = v;
 }
 
-// ---------------------------------------------------------------------------
-// FP64 GEMM on v_mfma_f64_16x16x4f64: C = A B with A row-major (k
-// contiguous, lda), B row-major (n contiguous, ldb), C(i, j) at
-// C[i*ldci + j*ldcj].  Tile 128 x 128 x 16, four wavefronts in a 2 x 2
-// grid, each computing a 64 x 64 quarter as 4 x 4 MFMA blocks; the next
-// k-tile is fetched into registers while the current one is multiplied.
-// Operand layout of the 16x16x4 f64 instruction: lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r of lane l
-// holds C[4r + l / 16][l % 16].
-// Requirements (checked by the launcher): K, lda, ldb multiples of 16 bytes'
-// worth of doubles (even) and A, B 16-byte aligned; rows/columns of A and B
-// beyond M, N, K must be readable up to the next multiple of the tile (the
-// plan pads every operand to multiples of 64 with zeros) -- loads are
-// clamped to M and N and zero-filled, so only K needs padding.
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-typedef double dbl2 __attribute__((ext_vector_type(2)));
-
-struct GemmBatch {
-  GemmProb p[4];
-};
-
-constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
-
-__global__ __launch_bounds__(256, 2) void k_gemm(GemmBatch batch) {
-  const GemmProb g = batch.p[blockIdx.z];
-  const int64_t i0 = (int64_t)blockIdx.y * GBM, j0 = (int64_t)blockIdx.x * GBN;
-  if (i0 >= g.M || j0 >= g.N) return;
-  __shared__ double As[GBK][GBM + GPAD];
-  __shared__ double Bs[GBK][GBN + GPAD];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wy = wid >> 1, wx = wid & 1;
-
-  int64_t klo = 0;
-  if (g.triA) klo = i0 + g.offA > klo ? i0 + g.offA : klo;
-  if (g.triB) klo = j0 + g.offB > klo ? j0 + g.offB : klo;
-  klo = klo / GBK * GBK;
-
-  // Loader mapping.  A tile 128 x 16: thread t reads row t/2, k-run (t%2)*8..+8.
-  // B tile 16 x 128: thread t reads k-row t/16, column run (t%16)*8..+8.
-  const int ar = tid >> 1, ak = (tid & 1) * 8;
-  const int bk = tid >> 4, bc = (tid & 15) * 8;
-  const int64_t arow = i0 + ar < g.M ? i0 + ar : g.M - 1;
-  const double az = i0 + ar < g.M ? 1.0 : 0.0;
-  const double *__restrict__ Ap = g.A + arow * g.sai + ak;
-  const double *__restrict__ Bp = g.B + (int64_t)bk * g.sbk + j0 + bc;
-  const bool bfull = j0 + bc + 8 <= g.N;
-
-  dbl2 ra[4], rb[4];
-  auto fetch = [&](int64_t k0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) ra[q] = *(const dbl2 *)(Ap + k0 + 2 * q);
-    const double *bp = Bp + k0 * g.sbk;
-    if (bfull) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) rb[q] = *(const dbl2 *)(bp + 2 * q);
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t jj = j0 + bc + 2 * q;
-        rb[q].x = jj < g.N ? bp[2 * q] : 0.0;
-        rb[q].y = jj + 1 < g.N ? bp[2 * q + 1] : 0.0;
-      }
-    }
-  };
-  auto stash = [&]() {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      As[ak + 2 * q][ar] = az * ra[q].x;
-      As[ak + 2 * q + 1][ar] = az * ra[q].y;
-      *(dbl2 *)&Bs[bk][bc + 2 * q] = rb[q];
-    }
-  };
-
-  dbl4 acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-
-  if (klo < g.K) {
-    fetch(klo);
-    stash();
-    __syncthreads();
-    for (int64_t k0 = klo; k0 < g.K; k0 += GBK) {
-      const bool more = k0 + GBK < g.K;
-      if (more) fetch(k0 + GBK);
-#pragma unroll
-      for (int ks = 0; ks < GBK; ks += 4) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = As[ks + (lane >> 4)][wy * 64 + a * 16 + (lane & 15)];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = Bs[ks + (lane >> 4)][wx * 64 + b * 16 + (lane & 15)];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-      }
-      __syncthreads();
-      if (more) {
-        stash();
-        __syncthreads();
-      }
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + wy * 64 + a * 16 + 4 * r + (lane >> 4);
-        const int64_t gj = j0 + wx * 64 + b * 16 + (lane & 15);
-        if (gi < g.M && gj < g.N) g.C[gi * g.sci + gj * g.scj] = acc[a][b][r];
-      }
-}
-
 }  // namespace
-
-template <typename T>
-hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
-  const int nchunks = a.nc0 + a.nc1;
-  if (a.npad % kCols != 0 || nchunks <= 0 || a.in == nullptr) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(a.npad / kCols), (unsigned)nchunks);
-  if (a.g != nullptr)
-    hipLaunchKernelGGL((k_sweep<T, true>), grid, dim3(kCols * kWaves), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_sweep<T, false>), grid, dim3(kCols * kWaves), 0, st, a);
-  return hipGetLastError();
-}
-template hipError_t launch_sweep<double>(const SweepArgs &, hipStream_t);
-template hipError_t launch_sweep<float>(const SweepArgs &, hipStream_t);
-
-hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
-                         int64_t npad, int nc0, int nc1, int64_t ncmax, hipStream_t st) {
-  dim3 grid((unsigned)((npad + 255) / 256), (unsigned)(2 * ncmax));
-  const size_t shm = (size_t)ncmax * kNComb * sizeof(double);
-  if (shm > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce, grid, dim3(256), shm, st, lv, comb, ab, scale, npad, nc0, nc1, ncmax);
-  return hipGetLastError();
-}
 
 hipError_t launch_finalize(const double *x, const double *ab, const double *tab, double *out,
                            int mode, const double *sinv, int64_t n, int64_t npad, int64_t mp0,
@@ -459,9 +74,9 @@ hipError_t launch_finalize(const double *x, const double *ab, const double *tab,
 }
 
 hipError_t launch_permute_in(const double *src, double *dst, int64_t n, int64_t npad, int64_t mp0,
-                             hipStream_t st) {
+                             hipStream_t st, const double *sinv) {
   dim3 grid((unsigned)((npad + 255) / 256), (unsigned)npad);
-  hipLaunchKernelGGL(k_permute_in, grid, dim3(256), 0, st, src, dst, n, npad, mp0);
+  hipLaunchKernelGGL(k_permute_in, grid, dim3(256), 0, st, src, dst, n, npad, mp0, sinv);
   return hipGetLastError();
 }
 
@@ -476,26 +91,6 @@ hipError_t launch_fill(double *dst, int64_t count, double v, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, dst, count,
                      v);
-  return hipGetLastError();
-}
-
-hipError_t launch_gemm(const GemmProb *probs, int count, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  if (count > 4) return hipErrorInvalidValue;
-  GemmBatch b{};
-  int64_t mt = 1, nt = 1;
-  for (int i = 0; i < count; ++i) {
-    const GemmProb &q = probs[i];
-    // contiguous operands, 16-byte aligned, K padded to the k-tile
-    if (q.sak != 1 || q.sbj != 1 || q.K % GBK != 0 || (q.sai & 1) || (q.sbk & 1) ||
-        ((uintptr_t)q.A & 15) || ((uintptr_t)q.B & 15) || q.M < 1 || q.N < 1)
-      return hipErrorInvalidValue;
-    b.p[i] = probs[i];
-    mt = probs[i].M > mt * GBM ? (probs[i].M + GBM - 1) / GBM : mt;
-    nt = probs[i].N > nt * GBN ? (probs[i].N + GBN - 1) / GBN : nt;
-  }
-  dim3 grid((unsigned)nt, (unsigned)mt, (unsigned)count);
-  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

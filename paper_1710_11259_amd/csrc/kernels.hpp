@@ -53,9 +53,10 @@ hipError_t launch_finalize(const double *x, const double *ab, const double *tab,
                            int mode, const double *sinv, int64_t n, int64_t npad, int64_t mp0,
                            int64_t mstride, int64_t ncmax, hipStream_t st);
 
-// natural n x n (ld n) -> parity-blocked npad x npad (zero padding).
+// natural n x n (ld n) -> parity-blocked npad x npad (zero padding); with
+// `sinv` non-null, entry (i, j) is multiplied by sinv[i] * sinv[j].
 hipError_t launch_permute_in(const double *src, double *dst, int64_t n, int64_t npad, int64_t mp0,
-                             hipStream_t st);
+                             hipStream_t st, const double *sinv = nullptr);
 
 hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st);
 hipError_t launch_fill(double *dst, int64_t count, double v, hipStream_t st);
@@ -73,6 +74,9 @@ struct GemmProb {
   int64_t M, N, K;
   int64_t sai, sak, sbk, sbj, sci, scj;
   int triA, offA, triB, offB;
+  // upper bounds: when triAu, A(i,k) = 0 for k > i + offAu; when triBu,
+  // B(k,j) = 0 for k > j + offBu; k-tiles above the last nonzero are skipped.
+  int triAu, offAu, triBu, offBu;
 };
 hipError_t launch_gemm(const GemmProb *probs, int count, hipStream_t st);
 
