@@ -34,6 +34,7 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-13)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP32-refined timing")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -132,6 +133,28 @@ def main() -> int:
                       "n": n, "J": J, "tol": args.tol},
            "roofline": roofline}
 
+    # Precision form: FP32 storage with FP64 refinement, same workload and tol.
+    forms = {}
+    if not args.no_forms:
+        pr = fps.plan(n, tol=args.tol, precision="fp32_refined")
+        wsr = fps.workspace(pr, dev)
+        Ur = torch.empty(pr.out_shape(), dtype=torch.float64, device=dev)
+        fps.solve(pr, F, out=Ur, ws=wsr)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            fps.solve(pr, F, out=Ur, ws=wsr)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_r = e0.elapsed_time(e1) / args.steps
+        forms["fp32_refined"] = {"ms_per_step": ms_r, "dof_per_s": dof / (ms_r * 1e-3),
+                                 "speedup_vs_fp64": ms_per_step / ms_r,
+                                 "inner_J": pr.J, "rounds": pr.rounds,
+                                 "f32_steps_per_round": pr.f32_steps}
+        del wsr
+    if forms:
+        out["forms"] = forms
+
     Ug = U.cpu().numpy()
     if not args.no_cpu_baseline or not args.no_check:
         from oracle import square
@@ -142,6 +165,9 @@ def main() -> int:
         err = float(np.linalg.norm(Ug - Uo) / np.linalg.norm(Uo))
         out["accuracy"] = {"rel_frobenius_err_vs_oracle": err, "bound": 1e-12,
                            "ok": bool(err <= 1e-12)}
+        if "fp32_refined" in forms:
+            er = float(np.linalg.norm(Ur.cpu().numpy() - Uo) / np.linalg.norm(Uo))
+            forms["fp32_refined"]["rel_frobenius_err_vs_oracle"] = er
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = {"value": dof / t_cpu, "unit": "dof/s", "cores": threads,
                                    "kind": "oracle",

@@ -56,10 +56,12 @@ typedef enum {
 typedef enum { FPS_BC_DIRICHLET_ZERO = 0 } fps_bc;
 
 /* FPS_FP64: every ADI half-sweep stores and computes in float64.
- * FPS_FP32_REFINED: iterative refinement; the inner ADI stores its sweep
- * arrays in float32 while every arithmetic operation and every table stays
- * float64; the residual r = G - (A~ Y + Y A~) and the update Y += dY are
- * float64 (precision form; not in the paper). */
+ * FPS_FP32_REFINED: iterative refinement (precision form; not in the paper).
+ * Each round forms the residual r = G - (A~ Y + Y A~) in float64, stores it
+ * in float32, runs an inner ADI to 1e-7 and adds its result to the float64
+ * Y.  The inner ADI's steps with |p_j| >= 1e-2 store their sweep arrays in
+ * float32, the small-shift steps in float64 (float storage there stalls the
+ * refinement); every arithmetic operation and every table stays float64. */
 typedef enum { FPS_FP64 = 0, FPS_FP32_REFINED = 1 } fps_prec;
 
 typedef enum { FPS_OUT_CHEB = 0, FPS_OUT_NATIVE = 1 } fps_out;
@@ -87,6 +89,11 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
  * fps_solve / fps_solve_adjoint, and the number of float64 entries of U. */
 fps_status fps_plan_info(const fps_plan *plan, int *J, int64_t *workspace_bytes,
                          int64_t *out_entries);
+
+/* Refinement structure of a plan: the number of rounds (1 for FPS_FP64) and
+ * the number of inner ADI steps that store their sweep arrays in float32 (0
+ * for FPS_FP64).  Either pointer may be null. */
+fps_status fps_plan_refinement(const fps_plan *plan, int *rounds, int *f32_steps);
 
 /* Copy the plan's shifts p_0..p_{J-1} to host memory (q_j = -p_j for the
  * square, Sec. 3.3 P2 with B~ = -A~). */

@@ -50,6 +50,8 @@ def lib() -> ctypes.CDLL:
     L.fps_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64),
                                 ctypes.POINTER(i64)]
     L.fps_plan_shifts.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.fps_plan_refinement.argtypes = [vp, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int)]
     L.fps_adi_shifts.argtypes = [dbl, dbl, dbl, dbl, dbl, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(dbl),
                                  ctypes.POINTER(dbl)]
@@ -65,7 +67,8 @@ def lib() -> ctypes.CDLL:
     L.fps_status_string.restype = ctypes.c_char_p
     L.fps_last_error.restype = ctypes.c_char_p
     L.fps_version.restype = ctypes.c_char_p
-    for name in ("fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_adi_shifts",
+    for name in ("fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_plan_refinement",
+                 "fps_adi_shifts",
                  "fps_solve", "fps_solve_adjoint", "fps_adi_native"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -105,6 +108,9 @@ class Plan:
         J, ws, oe = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().fps_plan_info(h, ctypes.byref(J), ctypes.byref(ws), ctypes.byref(oe)))
         self.J, self.workspace_bytes, self.out_entries = J.value, ws.value, oe.value
+        r, f = ctypes.c_int(), ctypes.c_int()
+        _check(lib().fps_plan_refinement(h, ctypes.byref(r), ctypes.byref(f)))
+        self.rounds, self.f32_steps = r.value, f.value
 
     @property
     def handle(self):

@@ -1,6 +1,7 @@
 // C ABI of the spectral Poisson solver (declared in include/fps.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -49,15 +50,22 @@ struct fps_plan {
   unsigned flags = 0;
   bool on_device = false;
 
-  fps::ShiftSet shifts;
+  fps::ShiftSet shifts;     // shifts of the ADI the sweeps run (inner ADI for FP32_REFINED)
+  int rounds = 1;           // refinement rounds (FP32_REFINED), 1 for FP64
+  double inner_tol = 0.0;   // ADI tolerance of one refinement round
+  // f32step[j] != 0: ADI step j stores its sweep outputs in float
+  // (FP32_REFINED, |p_j| >= kF32MinShift); f32step[J] = 0.
+  std::vector<char> f32step;
+  int n_f32 = 0;
   fps::Layout L;
   std::vector<double> tab, ctab, comb, l1;  // host sweep tables
+  std::vector<double> sdiag, soff;          // A~ stencil in the parity-blocked layout
   std::vector<double> Rs[2], P[2];  // host conversion maps (unpadded)
   int64_t mop[2] = {0, 0};          // output parity lengths padded to 64
   std::vector<double> sinv;         // 1/sqrt((i+1)(i+2))
 
   // device copies
-  DeviceBuf d_tab, d_ctab, d_comb, d_l1, d_sinv;
+  DeviceBuf d_tab, d_ctab, d_comb, d_l1, d_sinv, d_sdiag, d_soff;
   // GEMM operands, zero-padded to multiples of 64: RsA = Rs (mp x mp),
   // RsB = Rs^T (mp x mp), PA = P (mop x mp), PB = P^T (mp x mop).
   DeviceBuf d_RsA[2], d_RsB[2], d_PA[2], d_PB[2];
@@ -69,6 +77,7 @@ struct fps_plan {
   // workspace layout (byte offsets)
   int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab = 0;
   int64_t off_X = 0;  // adjoint: the output cotangent in the parity-blocked layout
+  int64_t off_R = 0;  // FP32_REFINED: the float residual and its transpose
   int64_t ws_bytes = 0;
 
   const double *tab_dev(int j) const {
@@ -104,7 +113,7 @@ hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st) {
   const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
   hipError_t e;
   if (t && (e = hipEventRecord(pl->ev[2 * pl->ev_used], st)) != hipSuccess) return e;
-  if ((e = fps::launch_sweep<double>(a, st)) != hipSuccess) return e;
+  if ((e = fps::launch_sweep(a, st)) != hipSuccess) return e;
   if (t) {
     if ((e = hipEventRecord(pl->ev[2 * pl->ev_used + 1], st)) != hipSuccess) return e;
     ++pl->ev_used;
@@ -118,20 +127,22 @@ void release_events(fps_plan *pl) {
   pl->ev_used = 0;
 }
 
-// Runs the 2J half-sweeps of Algorithm 2 on G (parity-blocked, in ws.G and
-// its transpose in ws.GT).  Leaves the final chunk-local solution in O1 and
-// its chunk carries in ab (to finalize with the tables of the last shift).
-fps_status run_adi(fps_plan *pl, char *ws, hipStream_t st) {
+// Runs the 2J half-sweeps of Algorithm 2.  `Gterm` is the right-hand side G
+// (parity-blocked, npad x npad) and `GTin` its transpose, both of storage
+// type g_f32; O0, O1 are the ping-pong arrays (room for npad^2 doubles
+// each).  Step j stores its outputs in float when pl->f32step[j] is set, so
+// a step reads its input in the type the previous step wrote it.  Leaves the
+// final chunk-local solution (double) in O1 and its chunk carries in ab, to
+// finalize with the tables of the last shift.
+fps_status run_adi(fps_plan *pl, const void *Gterm, const void *GTin, int g_f32, void *O0,
+                   void *O1, char *ws, hipStream_t st) {
   const fps::Layout &L = pl->L;
   const int J = pl->shifts.J;
   const std::vector<double> &p = pl->shifts.p;
-  double *G = (double *)(ws + pl->off_G);
-  double *GT = (double *)(ws + pl->off_GT);
-  double *O0 = (double *)(ws + pl->off_O0);
-  double *O1 = (double *)(ws + pl->off_O1);
   double *lv = (double *)(ws + pl->off_lv);
   double *ab = (double *)(ws + pl->off_ab);
   const int nc0 = (int)L.nc[0], nc1 = (int)L.nc[1];
+  auto f32 = [&](int j) { return j < (int)pl->f32step.size() && pl->f32step[j] ? 1 : 0; };
 
   fps::SweepArgs A{};
   A.npad = L.npad;
@@ -150,34 +161,76 @@ fps_status run_adi(fps_plan *pl, char *ws, hipStream_t st) {
   // So only half-step 2 reads G.  R_0 = -G.  After every half-step the chunk
   // carries are resolved into `ab`, which the next half-step folds in.
   for (int j = 0; j < J; ++j) {
-    A.in = j == 0 ? (const void *)GT : (const void *)O1;
+    A.in = j == 0 ? GTin : (const void *)O1;
+    A.in_f32 = j == 0 ? g_f32 : f32(j);
     A.in_scale = j == 0 ? -1.0 : 1.0;
     A.ab_prev = j == 0 ? nullptr : ab;
     A.tab_prev = j == 0 ? nullptr : pl->tab_dev(j - 1);
     A.g = nullptr;
+    A.g_f32 = 0;
     A.sg = 0.0;
     A.tab = pl->tab_dev(j);
     A.l1 = pl->l1_dev(j);
     A.sigma = 2.0 * p[j];
     A.out = O0;
+    A.out_f32 = f32(j);
     A.final_mode = 0;
     FPS_HIP(timed_sweep(pl, A, st));
     FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(j), ab, -A.sigma, L.npad, nc0, nc1, L.ncmax, st));
     fps::SweepArgs B = A;
     const bool last = j == J - 1;
     B.in = O0;
+    B.in_f32 = f32(j);
     B.in_scale = 1.0;
     B.ab_prev = ab;
     B.tab_prev = pl->tab_dev(j);
-    B.g = G;
+    B.g = Gterm;
+    B.g_f32 = g_f32;
     B.sg = 1.0;
     B.sigma = last ? 0.0 : p[j] + p[j + 1];
     B.out = O1;
+    B.out_f32 = last ? 0 : f32(j + 1);
     B.final_mode = last ? 1 : 0;
     FPS_HIP(timed_sweep(pl, B, st));
     FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(j), ab, last ? 1.0 : -B.sigma, L.npad, nc0, nc1,
                                L.ncmax, st));
   }
+  return FPS_OK;
+}
+
+// The symmetric-form solution Y (parity-blocked FP64, npad x npad) of
+// A~ Y + Y A~ = G for G in ws.G (and G^T in ws.GT): plain FP64 ADI, or
+// iterative refinement whose inner ADI stores its sweep arrays in float.
+// Returns Y's location.
+fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout) {
+  const fps::Layout &L = pl->L;
+  const int J = pl->shifts.J;
+  double *G = (double *)(w + pl->off_G);
+  double *ab = (double *)(w + pl->off_ab);
+  fps_status s;
+  if (pl->prec == FPS_FP64) {
+    double *GT = (double *)(w + pl->off_GT);
+    if ((s = run_adi(pl, G, GT, 0, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK) return s;
+    FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, pl->tab_dev(J - 1),
+                                         G, 0, nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax,
+                                         st));
+    *Yout = G;  // G is no longer needed
+    return FPS_OK;
+  }
+  // Refinement: Y <- Y + ADI_inner(G - (A~ Y + Y A~)); the residual is formed
+  // in FP64 and stored in float (with its transpose), the inner ADI stores
+  // its large-shift steps in float.
+  double *Y = (double *)(w + pl->off_GT);
+  float *r = (float *)(w + pl->off_R), *rT = r + L.npad * L.npad;
+  for (int k = 0; k < pl->rounds; ++k) {
+    FPS_HIP(fps::launch_residual(G, k == 0 ? nullptr : Y, (const double *)pl->d_sdiag.p,
+                                 (const double *)pl->d_soff.p, r, rT, L.npad, st));
+    if ((s = run_adi(pl, r, rT, 1, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK) return s;
+    FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, pl->tab_dev(J - 1),
+                                         Y, k == 0 ? 0 : 2, nullptr, L.n, L.npad, L.mp[0],
+                                         L.mstride, L.ncmax, st));
+  }
+  *Yout = Y;
   return FPS_OK;
 }
 
@@ -303,7 +356,6 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   if (out_basis != FPS_OUT_CHEB && out_basis != FPS_OUT_NATIVE) return fail(FPS_E_ARG, "bad out_basis");
   if (flags & ~FPS_PLAN_HOST_ONLY) return fail(FPS_E_ARG, "unknown flags");
   if (dim == 3) return fail(FPS_E_UNSUPPORTED, "cube solver not available in this build");
-  if (prec != FPS_FP64) return fail(FPS_E_UNSUPPORTED, "precision form not available in this build");
 
   fps_plan *pl = new (std::nothrow) fps_plan();
   if (!pl) return fail(FPS_E_NOMEM, "plan allocation failed");
@@ -315,11 +367,33 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   pl->flags = flags;
   // Lemma B.1: sigma(A~) in [-1, -1/(30 n^4)]; sigma(B~) = sigma(-A~).
   const double delta = 1.0 / (30.0 * (double)n * (double)n * (double)n * (double)n);
+  // FP32_REFINED: each refinement round runs an ADI to kInnerTol and the
+  // round count is the least R with kRoundFactor^R <= tol.  Float storage is
+  // used only by the steps with |p_j| >= kF32MinShift: a stored value enters
+  // the next solve through (A~ + p_j I)^-1, which magnifies its rounding
+  // error by up to about 1/|p_j| in the modes near the bottom of the
+  // spectrum; storing the small-shift steps in float stalls or reverses the
+  // refinement for n >= 256, while this split contracts the error by <= 1e-7
+  // per round.
+  constexpr double kInnerTol = 1e-7, kRoundFactor = 3e-7, kF32MinShift = 1e-2;
+  double adi_tol = tol;
+  if (prec == FPS_FP32_REFINED) {
+    pl->inner_tol = tol > kInnerTol ? tol : kInnerTol;
+    adi_tol = pl->inner_tol;
+    pl->rounds = std::max(1, (int)std::ceil(std::log(tol) / std::log(kRoundFactor) - 1e-9));
+  }
   std::string err;
-  if (!fps::zolotarev_shifts(-1.0, -delta, delta, 1.0, tol, pl->shifts, err)) {
+  if (!fps::zolotarev_shifts(-1.0, -delta, delta, 1.0, adi_tol, pl->shifts, err)) {
     delete pl;
     return fail(FPS_E_ARG, err);
   }
+  pl->f32step.assign((size_t)pl->shifts.J + 1, 0);
+  if (prec == FPS_FP32_REFINED)
+    for (int j = 0; j < pl->shifts.J; ++j)
+      if (std::fabs(pl->shifts.p[j]) >= kF32MinShift) {
+        pl->f32step[j] = 1;
+        ++pl->n_f32;
+      }
   pl->L = fps::make_layout(n);
   fps::build_sweep_tables(pl->L, pl->shifts.p, pl->tab, pl->ctab, pl->comb, pl->l1);
   fps::build_conversions(pl->L, pl->Rs, pl->P);
@@ -345,6 +419,15 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   }
   pl->sinv.resize(n);
   for (int64_t i = 0; i < n; ++i) pl->sinv[i] = 1.0 / std::sqrt((double)(i + 1) * (double)(i + 2));
+  // A~ as a stencil along each parity block of the internal layout.
+  pl->sdiag.assign(pl->L.npad, 0.0);
+  pl->soff.assign(pl->L.npad, 0.0);
+  for (int sp = 0; sp < 2; ++sp)
+    for (int64_t k = 0; k < pl->L.m[sp]; ++k) {
+      const int64_t r = sp * pl->L.mp[0] + k, i = 2 * k + sp;
+      pl->sdiag[r] = fps::atilde_diag(i);
+      if (k + 1 < pl->L.m[sp]) pl->soff[r] = fps::atilde_off(i);
+    }
 
   const fps::Layout &L = pl->L;
   const int64_t sq = align256(L.npad * L.npad * 8);
@@ -359,6 +442,10 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   const int64_t mobar = pl->mop[0] + pl->mop[1];
   pl->off_X = 4 * sq + lvb + abb;
   pl->ws_bytes = pl->off_X + align256(mobar * mobar * 8);
+  if (prec == FPS_FP32_REFINED) {
+    pl->off_R = pl->ws_bytes;  // r and r^T, npad^2 floats each
+    pl->ws_bytes += sq;
+  }
 
   if (!(flags & FPS_PLAN_HOST_ONLY)) {
     fps_status s;
@@ -368,7 +455,8 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
         (s = upload(pl->d_RsB[0], RsB[0])) != FPS_OK || (s = upload(pl->d_RsB[1], RsB[1])) != FPS_OK ||
         (s = upload(pl->d_PA[0], PA[0])) != FPS_OK || (s = upload(pl->d_PA[1], PA[1])) != FPS_OK ||
         (s = upload(pl->d_PB[0], PB[0])) != FPS_OK || (s = upload(pl->d_PB[1], PB[1])) != FPS_OK ||
-        (s = upload(pl->d_sinv, pl->sinv)) != FPS_OK) {
+        (s = upload(pl->d_sinv, pl->sinv)) != FPS_OK || (s = upload(pl->d_sdiag, pl->sdiag)) != FPS_OK ||
+        (s = upload(pl->d_soff, pl->soff)) != FPS_OK) {
       delete pl;
       return s;
     }
@@ -389,6 +477,13 @@ fps_status fps_plan_info(const fps_plan *pl, int *J, int64_t *ws_bytes, int64_t 
   return FPS_OK;
 }
 
+fps_status fps_plan_refinement(const fps_plan *pl, int *rounds, int *f32_steps) {
+  if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (rounds) *rounds = pl->rounds;
+  if (f32_steps) *f32_steps = pl->n_f32;
+  return FPS_OK;
+}
+
 fps_status fps_plan_shifts(const fps_plan *pl, double *p) {
   if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
   if (!p) return fail(FPS_E_ARG, "null output");
@@ -403,25 +498,20 @@ fps_status fps_solve(fps_plan *pl, const double *F, double *U, void *ws, void *s
   char *w = (char *)ws;
   const fps::Layout &L = pl->L;
   if ((s = rhs_transform(pl, F, w, st)) != FPS_OK) return s;
-  if ((s = run_adi(pl, w, st)) != FPS_OK) return s;
-  const int J = pl->shifts.J;
-  double *O1 = (double *)(w + pl->off_O1);
-  double *ab1 = (double *)(w + pl->off_ab);
+  double *Y = nullptr;
+  if ((s = solve_symmetric(pl, w, st, &Y)) != FPS_OK) return s;
   if (pl->out_basis == FPS_OUT_NATIVE) {
-    FPS_HIP(fps::launch_finalize(O1, ab1, pl->tab_dev(J - 1), U, 1, (const double *)pl->d_sinv.p,
-                                 L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
+    FPS_HIP(fps::launch_permute_out(Y, U, L.n, L.npad, L.mp[0], (const double *)pl->d_sinv.p, st));
     return FPS_OK;
   }
-  double *Y = (double *)(w + pl->off_G);
-  FPS_HIP(fps::launch_finalize(O1, ab1, pl->tab_dev(J - 1), Y, 0, nullptr, L.n, L.npad, L.mp[0],
-                               L.mstride, L.ncmax, st));
   return out_transform(pl, Y, U, w, st);
 }
 
 fps_status fps_adi_native(fps_plan *pl, const double *G, double *Y, void *ws, void *stream) {
   fps_status s = check_solve_args(pl, G, Y, ws);
   if (s != FPS_OK) return s;
-  if (pl->dim != 2) return fail(FPS_E_UNSUPPORTED, "square only");
+  if (pl->dim != 2 || pl->prec != FPS_FP64)
+    return fail(FPS_E_UNSUPPORTED, "the J-step iterate entry point needs a square FP64 plan");
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   const fps::Layout &L = pl->L;
@@ -429,11 +519,11 @@ fps_status fps_adi_native(fps_plan *pl, const double *G, double *Y, void *ws, vo
   double *GT = (double *)(w + pl->off_GT);
   FPS_HIP(fps::launch_permute_in(G, Gp, L.n, L.npad, L.mp[0], st));
   FPS_HIP(fps::launch_transpose(Gp, GT, L.npad, st));
-  if ((s = run_adi(pl, w, st)) != FPS_OK) return s;
+  if ((s = run_adi(pl, Gp, GT, 0, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK) return s;
   const int J = pl->shifts.J;
-  FPS_HIP(fps::launch_finalize((double *)(w + pl->off_O1), (double *)(w + pl->off_ab),
-                               pl->tab_dev(J - 1), Y, 1, nullptr, L.n, L.npad, L.mp[0], L.mstride,
-                               L.ncmax, st));
+  FPS_HIP(fps::launch_finalize<double>((double *)(w + pl->off_O1), (double *)(w + pl->off_ab),
+                                       pl->tab_dev(J - 1), Y, 1, nullptr, L.n, L.npad, L.mp[0],
+                                       L.mstride, L.ncmax, st));
   return FPS_OK;
 }
 
@@ -484,11 +574,8 @@ fps_status fps_solve_adjoint(fps_plan *pl, const double *Ubar, double *Fbar, voi
   }
   // 2. The same J-step ADI map (self-adjoint for symmetric shifts).
   FPS_HIP(fps::launch_transpose(G, GT, npad, st));
-  if ((s = run_adi(pl, w, st)) != FPS_OK) return s;
-  const int J = pl->shifts.J;
-  FPS_HIP(fps::launch_finalize((double *)(w + pl->off_O1), (double *)(w + pl->off_ab),
-                               pl->tab_dev(J - 1), G, 0, nullptr, n, npad, L.mp[0], L.mstride,
-                               L.ncmax, st));
+  double *Yb = nullptr;
+  if ((s = solve_symmetric(pl, w, st, &Yb)) != FPS_OK) return s;  // Gbar, in G
   // 3. Fbar = R^T S^-1 Gbar S^-1 R, blockwise Rs_s^T Gbar_st Rs_t into the strided view of Fbar.
   fps::GemmProb g1[4], g2[4];
   int cnt = 0;
@@ -500,7 +587,7 @@ fps_status fps_solve_adjoint(fps_plan *pl, const double *Ubar, double *Fbar, voi
       double *Tst = Tb + toff;
       toff += ms * mt;
       // T_st = Gbar_st Rs_t; B(k, j) = Rs_t[k][j] = 0 for k > j.
-      g1[cnt] = fps::GemmProb{G + (s2 * L.mp[0]) * npad + t * L.mp[0], (const double *)pl->d_RsA[t].p,
+      g1[cnt] = fps::GemmProb{Yb + (s2 * L.mp[0]) * npad + t * L.mp[0], (const double *)pl->d_RsA[t].p,
                               Tst, ms, mt, mt, npad, 1, mt, 1, mt, 1, 0, 0, 0, 0, 0, 0, 1, 0};
       // Fbar_st = Rs_s^T T_st; A(i, k) = Rs_s[k][i] = 0 for k > i.
       g2[cnt] = fps::GemmProb{(const double *)pl->d_RsB[s2].p, Tst, Fbar + s2 * n + t, L.m[s2],

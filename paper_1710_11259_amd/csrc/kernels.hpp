@@ -20,23 +20,26 @@ namespace fps {
 //          launch_reduce turns them into carries, which the consumer (the
 //          next sweep, or launch_finalize after the last one) folds in.
 struct SweepArgs {
-  const void *in;          // T[npad*npad]
+  const void *in;          // [npad*npad], storage type in_f32
   double in_scale;
   const double *ab_prev;   // producer's chunk carries [2][ncmax][npad][2], or null
   const double *tab_prev;  // producer's per-position tables (its shift) [2][kNTab][mstride]
-  const double *g;         // G term (same orientation as `in`) or nullptr
+  const void *g;           // [npad*npad] G term (same orientation as `in`) or nullptr
   double sg;
   const double *tab;       // this pass's tables [2][kNTab][mstride]
   const double *l1;        // this pass's segment-carry combinations [2][ncmax][kL1]
   double sigma;
-  void *out;               // T[npad*npad]
+  void *out;               // [npad*npad], storage type out_f32
   double *lv;              // chunk boundary values [ncmax][2][2][npad]
   int final_mode;          // 1: out = x, not transposed
   int64_t npad, mp0, mp1, mstride, ncmax;
   int nc0, nc1;
+  // Storage types (0: double, 1: float; arithmetic is double throughout).
+  // Supported: without g, in/out = d/d, f/d, f/f; with g, in/g/out =
+  // d/d/d, d/f/d, f/f/d, f/f/f.
+  int in_f32, g_f32, out_f32;
 };
 
-template <typename T>
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st);
 
 // Chunk carries: for every chain, the forward and backward carry into each
@@ -45,18 +48,33 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st);
 hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
                          int64_t npad, int nc0, int nc1, int64_t ncmax, hipStream_t st);
 
-// Y_perm[r][col] = x[r][col] + carries (final pass, non-transposed).
+// Y_perm[r][col] = x[r][col] + carries (final pass, non-transposed; x of
+// storage type T).
 // mode 0: write Y in the parity-blocked layout (npad x npad, ld npad);
-// mode 1: write the natural-order n x n array, entry (i,j) divided by
-//         sinv-scaled factors when `sinv` is non-null: out = Y * sinv_i * sinv_j.
-hipError_t launch_finalize(const double *x, const double *ab, const double *tab, double *out,
-                           int mode, const double *sinv, int64_t n, int64_t npad, int64_t mp0,
+// mode 1: write the natural-order n x n array, entry (i,j) times
+//         sinv_i * sinv_j when `sinv` is non-null;
+// mode 2: add Y into the parity-blocked FP64 array `out`.
+template <typename T>
+hipError_t launch_finalize(const T *x, const double *ab, const double *tab, double *out, int mode,
+                           const double *sinv, int64_t n, int64_t npad, int64_t mp0,
                            int64_t mstride, int64_t ncmax, hipStream_t st);
+
+// Residual of the symmetric Sylvester equation in the parity-blocked layout,
+// r = G - (A~ Y + Y A~) (Y null: r = G), in FP64, stored in float as r and
+// r^T.  A~ acts along each parity block as a tridiagonal stencil with
+// diagonal dv[] and coupling ev[] (ev[k] couples positions k and k+1).
+hipError_t launch_residual(const double *G, const double *Y, const double *dv, const double *ev,
+                           float *r, float *rT, int64_t npad, hipStream_t st);
 
 // natural n x n (ld n) -> parity-blocked npad x npad (zero padding); with
 // `sinv` non-null, entry (i, j) is multiplied by sinv[i] * sinv[j].
 hipError_t launch_permute_in(const double *src, double *dst, int64_t n, int64_t npad, int64_t mp0,
                              hipStream_t st, const double *sinv = nullptr);
+
+// parity-blocked npad x npad -> natural n x n, entry (i, j) times
+// sinv[i] * sinv[j] when sinv is non-null.
+hipError_t launch_permute_out(const double *src, double *dst, int64_t n, int64_t npad, int64_t mp0,
+                              const double *sinv, hipStream_t st);
 
 hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st);
 hipError_t launch_fill(double *dst, int64_t count, double v, hipStream_t st);

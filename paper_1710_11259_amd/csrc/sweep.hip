@@ -55,7 +55,7 @@ static_assert(T_L == 0 && T_IB == 1 && T_U == 2 && T_F1 == 3 && T_BK1 == 4, "tab
 // kWithG: the right-hand side is v + sg * g while the output is v - sigma x
 // (g is not carried into the output); otherwise the right-hand side is v.
 // v = in_scale * in + (chunk carries of the producing pass).
-template <typename T, bool kWithG>
+template <typename Tin, typename Tg, typename Tout, bool kWithG>
 __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
   __shared__ double lds[kSweepLds];
   const int tid = threadIdx.x;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
   // 2. Streaming loads (rows clamped for the idle segments past the chain end).
   double v[kSeg], y[kSeg];
   {
-    const T *__restrict__ in = (const T *)a.in;
+    const Tin *__restrict__ in = (const Tin *)a.in;
 #pragma unroll
     for (int i = 0; i < kSeg; ++i) {
       const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
@@ -109,11 +109,11 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
     }
   }
   if constexpr (kWithG) {
-    const double *__restrict__ gp = a.g;
+    const Tg *__restrict__ gp = (const Tg *)a.g;
 #pragma unroll
     for (int i = 0; i < kSeg; ++i) {
       const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
-      y[i] = gp[r * npad + col];
+      y[i] = ld_as_double(gp + r * npad + col);
     }
   }
 
@@ -194,11 +194,11 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
   if (w == kWaves - 1) a.lv[(((int64_t)c * 2 + s) * 2 + 0) * npad + col] = ylast_chunk;
   if (w == 0) a.lv[(((int64_t)c * 2 + s) * 2 + 1) * npad + col] = xfirst + Tbk1[0] * cb1;
 
-  T *__restrict__ out = (T *)a.out;
+  Tout *__restrict__ out = (Tout *)a.out;
   if (a.final_mode) {
     if (active) {
 #pragma unroll
-      for (int i = 0; i < kSeg; ++i) out[(row0 + i) * npad + col] = (T)y[i];
+      for (int i = 0; i < kSeg; ++i) out[(row0 + i) * npad + col] = (Tout)y[i];
     }
     return;
   }
@@ -218,9 +218,9 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
       const int ocol = 2 * (lane % kLanesPerRow);
       const double v0 = stage[orow * (kSeg + 1) + ocol];
       const double v1 = stage[orow * (kSeg + 1) + ocol + 1];
-      T *dst = out + (col0 + orow) * npad + row0 + ocol;
-      dst[0] = (T)v0;
-      dst[1] = (T)v1;
+      Tout *dst = out + (col0 + orow) * npad + row0 + ocol;
+      dst[0] = (Tout)v0;
+      dst[1] = (Tout)v1;
     }
   }
 }
@@ -259,19 +259,34 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ lv,
 
 }  // namespace
 
-template <typename T>
+template <typename Tin, typename Tg, typename Tout, bool kWithG>
+void launch_typed(const SweepArgs &a, hipStream_t st) {
+  dim3 grid((unsigned)(a.npad / kCols), (unsigned)(a.nc0 + a.nc1));
+  hipLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kWithG>), grid, dim3(kCols * kWaves), 0, st, a);
+}
+
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
   const int nchunks = a.nc0 + a.nc1;
   if (a.npad % kCols != 0 || nchunks <= 0 || a.in == nullptr) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(a.npad / kCols), (unsigned)nchunks);
-  if (a.g != nullptr)
-    hipLaunchKernelGGL((k_sweep<T, true>), grid, dim3(kCols * kWaves), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_sweep<T, false>), grid, dim3(kCols * kWaves), 0, st, a);
+  const int code = (a.in_f32 ? 4 : 0) | (a.g_f32 ? 2 : 0) | (a.out_f32 ? 1 : 0);
+  if (a.g == nullptr) {
+    switch (code & 5) {
+      case 0: launch_typed<double, double, double, false>(a, st); break;
+      case 4: launch_typed<float, double, double, false>(a, st); break;
+      case 5: launch_typed<float, double, float, false>(a, st); break;
+      default: return hipErrorInvalidValue;  // a float output from a double input
+    }
+  } else {
+    switch (code) {
+      case 0: launch_typed<double, double, double, true>(a, st); break;
+      case 2: launch_typed<double, float, double, true>(a, st); break;
+      case 6: launch_typed<float, float, double, true>(a, st); break;
+      case 7: launch_typed<float, float, float, true>(a, st); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
   return hipGetLastError();
 }
-template hipError_t launch_sweep<double>(const SweepArgs &, hipStream_t);
-template hipError_t launch_sweep<float>(const SweepArgs &, hipStream_t);
 
 hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
                          int64_t npad, int nc0, int nc1, int64_t ncmax, hipStream_t st) {

@@ -82,6 +82,23 @@ def test_workspace_and_extent_queries():
     assert q.out_entries == 100 * 100
 
 
+@pytest.mark.parametrize("n", [64, 512, 4096])
+def test_refinement_structure(n):
+    # FP64: one pass, no float steps.  FP32_REFINED to 1e-13: two rounds of
+    # an inner ADI to 1e-7 whose float-stored steps are exactly those with
+    # |p_j| >= 1e-2 (a prefix, since |p_j| decreases with j).
+    d = fps.plan(n, tol=1e-13, host_only=True)
+    assert (d.rounds, d.f32_steps) == (1, 0)
+    r = fps.plan(n, tol=1e-13, precision="fp32_refined", host_only=True)
+    _, p, _ = oshifts.square_shifts(n, 1e-7)
+    assert r.J == len(p)
+    assert r.rounds == 2
+    assert r.f32_steps == int(np.sum(np.abs(p) >= 1e-2))
+    assert 0 < r.f32_steps < r.J
+    assert np.all(np.diff(np.abs(p)) < 0)
+    assert r.workspace_bytes > d.workspace_bytes
+
+
 # --- host planner internals through a g++-built shim -----------------------
 
 @pytest.fixture(scope="module")
