@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct fps_plan fps_plan;
+typedef struct fps_batch fps_batch;
 
 typedef enum {
   FPS_OK = 0,
@@ -153,6 +154,36 @@ fps_status fps_plan_set_sweep_timing(fps_plan *plan, int capacity);
 fps_status fps_plan_sweep_time(fps_plan *plan, double *ms_host, int64_t cap, int64_t *launches);
 
 void fps_plan_destroy(fps_plan *plan);
+
+/*
+ * Batched square solves (a batching form of the same solve; not in the
+ * paper): `count` independent problems of sizes n[0..count-1], each solved
+ * exactly as fps_solve with a plan of that size, tol, precision and output
+ * basis would solve it.  Problems of equal n share one set of plan tables.
+ * The ADI half-sweeps of all problems run as one launch per half-step (the
+ * problems still iterating at that step), so a batch enqueues about 4 J_max
+ * sweep/carry launches plus a fixed number of map launches per problem.
+ *   dim must be 2; 1 <= count <= 65536; every n in [1, 65536]; tol, prec,
+ *   out_basis and flags as for fps_plan_create.  For FPS_FP32_REFINED the
+ *   inner ADI step j stores in float for every problem iff j < the least
+ *   float-step count of the problems' own plans (so each problem keeps the
+ *   convergence of its own plan).
+ * Data: F_dev packs the problems' n x n inputs back to back in the given
+ * order (row-major each, offsets sum of n_b^2); U_dev packs the outputs
+ * ((n_b+2)^2 or n_b^2 entries each).  fps_batch_info gives the totals and the
+ * workspace size; the workspace must be 256-byte aligned and must not
+ * overlap F or U.  fps_batch_solve enqueues on `stream` without allocating
+ * or synchronizing and without memset or memcpy nodes, so it may be captured
+ * into a HIP graph.
+ */
+fps_status fps_batch_create(fps_batch **out, int dim, int count, const int64_t *n, double tol,
+                            int prec, int out_basis, unsigned flags);
+fps_status fps_batch_info(const fps_batch *batch, int64_t *workspace_bytes, int64_t *in_entries,
+                          int64_t *out_entries, int *max_J);
+fps_status fps_batch_solve(fps_batch *batch, const double *F_dev, double *U_dev, void *ws_dev,
+                           void *stream);
+void fps_batch_destroy(fps_batch *batch);
+
 const char *fps_status_string(fps_status s);
 const char *fps_last_error(void);
 const char *fps_version(void);

@@ -16,7 +16,7 @@ import ctypes
 import os
 
 __all__ = ["lib", "Plan", "plan", "solve", "solve_adjoint", "solve_fn", "adi_native",
-           "adi_shifts", "FpsError", "LIB_PATH"]
+           "adi_shifts", "Batch", "batch", "batch_solve", "BatchGraph", "FpsError", "LIB_PATH"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfps.so")
@@ -57,6 +57,14 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(dbl)]
     for name in ("fps_solve", "fps_solve_adjoint", "fps_adi_native"):
         getattr(L, name).argtypes = [vp, vp, vp, vp, vp]
+    L.fps_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(i64), dbl, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_uint]
+    L.fps_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                 ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int)]
+    L.fps_batch_solve.argtypes = [vp, vp, vp, vp, vp]
+    L.fps_batch_destroy.argtypes = [vp]
+    L.fps_batch_destroy.restype = None
     L.fps_plan_set_sweep_timing.argtypes = [vp, ctypes.c_int]
     L.fps_plan_sweep_time.argtypes = [vp, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64)]
     L.fps_plan_set_sweep_timing.restype = ctypes.c_int
@@ -68,8 +76,8 @@ def lib() -> ctypes.CDLL:
     L.fps_last_error.restype = ctypes.c_char_p
     L.fps_version.restype = ctypes.c_char_p
     for name in ("fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_plan_refinement",
-                 "fps_adi_shifts",
-                 "fps_solve", "fps_solve_adjoint", "fps_adi_native"):
+                 "fps_adi_shifts", "fps_solve", "fps_solve_adjoint", "fps_adi_native",
+                 "fps_batch_create", "fps_batch_info", "fps_batch_solve"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -253,3 +261,110 @@ def adi_native(p: Plan, G, out=None, ws=None):
                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                 _stream_ptr(torch, G.device)))
     return out
+
+
+class Batch:
+    """Owning wrapper of an fps_batch: independent square solves of sizes
+    ns (packed back to back), ADI half-sweeps of all problems in one launch
+    per half-step."""
+
+    def __init__(self, ns, tol: float = 1e-13, precision: str = "fp64", out: str = "cheb",
+                 host_only: bool = False):
+        prec = {"fp64": FPS_FP64, "fp32_refined": FPS_FP32_REFINED}[precision]
+        ob = {"cheb": FPS_OUT_CHEB, "native": FPS_OUT_NATIVE}[out]
+        self.ns = [int(v) for v in ns]
+        arr = (ctypes.c_int64 * len(self.ns))(*self.ns)
+        h = ctypes.c_void_p()
+        _check(lib().fps_batch_create(ctypes.byref(h), 2, len(self.ns), arr, tol, prec, ob,
+                                      FPS_PLAN_HOST_ONLY if host_only else 0))
+        self._h = h
+        self.tol, self.precision, self.out = tol, precision, out
+        ws, ie, oe, J = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        _check(lib().fps_batch_info(h, ctypes.byref(ws), ctypes.byref(ie), ctypes.byref(oe),
+                                    ctypes.byref(J)))
+        self.workspace_bytes, self.in_entries, self.out_entries = ws.value, ie.value, oe.value
+        self.max_J = J.value
+        e = [v if out == "native" else v + 2 for v in self.ns]
+        self.in_offsets = [0]
+        self.out_offsets = [0]
+        for v, ev in zip(self.ns, e):
+            self.in_offsets.append(self.in_offsets[-1] + v * v)
+            self.out_offsets.append(self.out_offsets[-1] + ev * ev)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def pack(self, Fs, device="cuda"):
+        """Pack a list of n_b x n_b float64 arrays/tensors into one device tensor."""
+        import torch
+        parts = [torch.as_tensor(F, dtype=torch.float64).reshape(-1) for F in Fs]
+        return torch.cat(parts).to(device).contiguous()
+
+    def unpack(self, U):
+        """Views of the packed output as a list of square tensors."""
+        e = [v if self.out == "native" else v + 2 for v in self.ns]
+        return [U[self.out_offsets[b]:self.out_offsets[b + 1]].view(e[b], e[b])
+                for b in range(len(self.ns))]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fps_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch(ns, tol: float = 1e-13, precision: str = "fp64", out: str = "cheb",
+          host_only: bool = False) -> Batch:
+    return Batch(ns, tol, precision, out, host_only)
+
+
+def batch_solve(b: Batch, F, out=None, ws=None):
+    """Packed U for the packed float64 CUDA tensor F (see Batch.pack)."""
+    import torch
+    if F.dtype != torch.float64 or not F.is_cuda or not F.is_contiguous():
+        raise ValueError("F must be a contiguous float64 tensor on the GPU")
+    if F.numel() != b.in_entries:
+        raise ValueError(f"F must hold {b.in_entries} entries")
+    if out is None:
+        out = torch.empty(b.out_entries, dtype=torch.float64, device=F.device)
+    if out.numel() != b.out_entries or not out.is_contiguous():
+        raise ValueError(f"out must be contiguous with {b.out_entries} entries")
+    if ws is None:
+        ws = torch.empty(max(b.workspace_bytes, 256), dtype=torch.uint8, device=F.device)
+    _check(lib().fps_batch_solve(b.handle, ctypes.c_void_p(F.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                 _stream_ptr(torch, F.device)))
+    return out
+
+
+class BatchGraph:
+    """A batched solve captured once into a HIP graph (through torch's graph
+    capture) and replayed with one launch.  F, U and the workspace are fixed
+    device buffers: write new inputs into `self.F` before `replay()`."""
+
+    def __init__(self, b: Batch, device="cuda"):
+        import torch
+        self.batch = b
+        self.F = torch.zeros(b.in_entries, dtype=torch.float64, device=device)
+        self.U = torch.empty(b.out_entries, dtype=torch.float64, device=device)
+        self.ws = torch.empty(max(b.workspace_bytes, 256), dtype=torch.uint8, device=device)
+        side = torch.cuda.Stream(device)
+        side.wait_stream(torch.cuda.current_stream(device))
+        with torch.cuda.stream(side):  # one eager run before capture
+            batch_solve(b, self.F, out=self.U, ws=self.ws)
+        torch.cuda.current_stream(device).wait_stream(side)
+        torch.cuda.synchronize(device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            batch_solve(b, self.F, out=self.U, ws=self.ws)
+        torch.cuda.synchronize(device)
+
+    def replay(self):
+        self.graph.replay()
+        return self.U

@@ -9,103 +9,23 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fps.h"
-#include "kernels.hpp"
-#include "planner.hpp"
+#include "solver.hpp"
+
+namespace fps {
+namespace detail {
 
 namespace {
-
 thread_local std::string g_last_error;
+}
 
 fps_status fail(fps_status s, const std::string &msg) {
   g_last_error = msg;
   return s;
 }
 
-#define FPS_HIP(call)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (call);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(FPS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));        \
-  } while (0)
-
-constexpr uint64_t kMagic = 0x66707370'6c616e31ull;  // "fpsplan1"
-
-struct DeviceBuf {
-  void *p = nullptr;
-  ~DeviceBuf() {
-    if (p) (void)hipFree(p);
-  }
-};
-
-}  // namespace
-
-struct fps_plan {
-  uint64_t magic = kMagic;
-  int dim = 2;
-  int64_t n = 0;
-  double tol = 0;
-  int prec = FPS_FP64;
-  int out_basis = FPS_OUT_CHEB;
-  unsigned flags = 0;
-  bool on_device = false;
-
-  fps::ShiftSet shifts;     // shifts of the ADI the sweeps run (inner ADI for FP32_REFINED)
-  int rounds = 1;           // refinement rounds (FP32_REFINED), 1 for FP64
-  double inner_tol = 0.0;   // ADI tolerance of one refinement round
-  // f32step[j] != 0: ADI step j stores its sweep outputs in float
-  // (FP32_REFINED, |p_j| >= kF32MinShift); f32step[J] = 0.
-  std::vector<char> f32step;
-  int n_f32 = 0;
-  fps::Layout L;
-  std::vector<double> tab, ctab, comb, l1;  // host sweep tables
-  std::vector<double> sdiag, soff;          // A~ stencil in the parity-blocked layout
-  std::vector<double> Rs[2], P[2];  // host conversion maps (unpadded)
-  int64_t mop[2] = {0, 0};          // output parity lengths padded to 64
-  std::vector<double> sinv;         // 1/sqrt((i+1)(i+2))
-
-  // device copies
-  DeviceBuf d_tab, d_ctab, d_comb, d_l1, d_sinv, d_sdiag, d_soff;
-  // GEMM operands, zero-padded to multiples of 64: RsA = Rs (mp x mp),
-  // RsB = Rs^T (mp x mp), PA = P (mop x mp), PB = P^T (mp x mop).
-  DeviceBuf d_RsA[2], d_RsB[2], d_PA[2], d_PB[2];
-
-  // sweep timing diagnostics
-  std::vector<hipEvent_t> ev;  // pairs
-  int64_t ev_used = 0;
-
-  // workspace layout (byte offsets)
-  int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab = 0;
-  int64_t off_X = 0;  // adjoint: the output cotangent in the parity-blocked layout
-  int64_t off_R = 0;  // FP32_REFINED: the float residual and its transpose
-  int64_t ws_bytes = 0;
-
-  const double *tab_dev(int j) const {
-    return (const double *)d_tab.p + (size_t)j * 2 * fps::kNTab * L.mstride;
-  }
-  const double *ctab_dev(int j) const {
-    return (const double *)d_ctab.p + (size_t)j * 2 * fps::kNCTab * L.ncmax;
-  }
-  const double *comb_dev(int j) const {
-    return (const double *)d_comb.p + (size_t)j * 2 * L.ncmax * L.ncmax * fps::kNComb;
-  }
-  const double *l1_dev(int j) const {
-    return (const double *)d_l1.p + (size_t)j * 2 * L.ncmax * fps::kL1;
-  }
-};
-
-namespace {
+const char *last_error() { return g_last_error.c_str(); }
 
 bool valid_plan(const fps_plan *p) { return p != nullptr && p->magic == kMagic; }
-
-template <typename T>
-fps_status upload(DeviceBuf &b, const std::vector<T> &h) {
-  if (h.empty()) return FPS_OK;
-  if (hipMalloc(&b.p, h.size() * sizeof(T)) != hipSuccess)
-    return fail(FPS_E_NOMEM, "hipMalloc of a plan table failed");
-  FPS_HIP(hipMemcpy(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
-  return FPS_OK;
-}
 
 int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
@@ -307,7 +227,10 @@ fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hip
   return FPS_OK;
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace fps
+
+using namespace fps::detail;
 
 extern "C" {
 
@@ -325,7 +248,7 @@ const char *fps_status_string(fps_status s) {
   return "unknown status";
 }
 
-const char *fps_last_error(void) { return g_last_error.c_str(); }
+const char *fps_last_error(void) { return last_error(); }
 
 fps_status fps_adi_shifts(double a, double b, double c, double d, double tol, int cap, int *J,
                           double *p, double *q) {

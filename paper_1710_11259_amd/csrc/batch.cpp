@@ -1,0 +1,332 @@
+// Batched square solves (fps_batch_* in include/fps.h): many independent
+// problems, possibly of different sizes, whose ADI half-sweeps run as one
+// launch per half-step.  Every problem keeps the tables, workspace layout,
+// shifts and kernels of its own single-problem plan; only the launch of the
+// sweeps and of the chunk-carry reductions is shared.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "solver.hpp"
+
+using namespace fps::detail;
+
+namespace {
+
+constexpr uint64_t kBatchMagic = 0x66707362'61746331ull;  // "fpsbatc1"
+
+}  // namespace
+
+struct fps_batch {
+  uint64_t magic = kBatchMagic;
+  int count = 0, prec = FPS_FP64, out_basis = FPS_OUT_CHEB;
+  bool on_device = false;
+  std::vector<int64_t> n;            // per problem, caller's order
+  std::vector<fps_plan *> sub;       // one plan per distinct n (owned)
+  std::vector<int> which;            // problem -> index into sub
+  std::vector<int> order;            // sorted position -> problem (J descending)
+  std::vector<int64_t> f_off, u_off, ws_off;  // per problem: F / U entries, workspace bytes
+  int64_t in_entries = 0, out_entries = 0, ws_bytes = 0;
+  int J_max = 0;
+  int n_f32 = 0;                     // inner steps j < n_f32 store in float (refined)
+  std::vector<int> active;           // per step: problems (a sorted prefix) still iterating
+  std::vector<int> sw_start, rd_start;  // workgroup prefix sums over the sorted problems
+  int64_t ncmax_max = 0;
+  DeviceBuf d_sw, d_rd, d_swmap, d_rdmap;
+
+  ~fps_batch() {
+    for (fps_plan *p : sub) fps_plan_destroy(p);
+  }
+  const fps_plan *plan_of(int problem) const { return sub[which[problem]]; }
+};
+
+namespace {
+
+bool valid_batch(const fps_batch *b) { return b != nullptr && b->magic == kBatchMagic; }
+
+// Byte offset carried in a descriptor's pointer field.
+template <typename P>
+P off_ptr(int64_t off) {
+  return (P)(intptr_t)off;
+}
+
+// Builds the per-step descriptors of every problem (sorted order) and the
+// workgroup -> problem maps.
+fps_status build_descriptors(fps_batch *bt) {
+  const int C = bt->count;
+  const bool refined = bt->prec == FPS_FP32_REFINED;
+  const int gf = refined ? 1 : 0;
+  auto f32 = [&](int j) { return j < bt->n_f32 ? 1 : 0; };
+  std::vector<fps::BatchSweep> sw((size_t)bt->J_max * 2 * C);
+  std::vector<fps::BatchReduce> rd((size_t)bt->J_max * 2 * C);
+  for (int k = 0; k < C; ++k) {
+    const int b = bt->order[k];
+    const fps_plan *pl = bt->plan_of(b);
+    const fps::Layout &L = pl->L;
+    const int64_t W = bt->ws_off[b];
+    const int64_t Gterm = W + (refined ? pl->off_R : pl->off_G);
+    const int64_t GTin = refined ? W + pl->off_R + L.npad * L.npad * 4 : W + pl->off_GT;
+    const int64_t O0 = W + pl->off_O0, O1 = W + pl->off_O1, lv = W + pl->off_lv,
+                  ab = W + pl->off_ab;
+    const int J = pl->shifts.J;
+    const std::vector<double> &p = pl->shifts.p;
+    fps::SweepArgs A{};
+    A.npad = L.npad;
+    A.mp0 = L.mp[0];
+    A.mp1 = L.mp[1];
+    A.mstride = L.mstride;
+    A.ncmax = L.ncmax;
+    A.nc0 = (int)L.nc[0];
+    A.nc1 = (int)L.nc[1];
+    A.lv = off_ptr<double *>(lv);
+    const int nbx_s = (int)(L.npad / fps::kCols);
+    const int nbx_r = (int)((L.npad + 255) / 256);
+    for (int j = 0; j < J; ++j) {
+      const bool last = j == J - 1;
+      // half-step 1
+      fps::SweepArgs a1 = A;
+      a1.in = off_ptr<const void *>(j == 0 ? GTin : O1);
+      a1.in_f32 = j == 0 ? gf : f32(j);
+      a1.in_scale = j == 0 ? -1.0 : 1.0;
+      a1.ab_prev = j == 0 ? nullptr : off_ptr<const double *>(ab);
+      a1.tab_prev = j == 0 ? nullptr : pl->tab_dev(j - 1);
+      a1.g = nullptr;
+      a1.tab = pl->tab_dev(j);
+      a1.l1 = pl->l1_dev(j);
+      a1.sigma = 2.0 * p[j];
+      a1.out = off_ptr<void *>(O0);
+      a1.out_f32 = f32(j);
+      // half-step 2
+      fps::SweepArgs a2 = a1;
+      a2.in = off_ptr<const void *>(O0);
+      a2.in_f32 = f32(j);
+      a2.in_scale = 1.0;
+      a2.ab_prev = off_ptr<const double *>(ab);
+      a2.tab_prev = pl->tab_dev(j);
+      a2.g = off_ptr<const void *>(Gterm);
+      a2.g_f32 = gf;
+      a2.sg = 1.0;
+      a2.sigma = last ? 0.0 : p[j] + p[j + 1];
+      a2.out = off_ptr<void *>(O1);
+      a2.out_f32 = last ? 0 : f32(j + 1);
+      a2.final_mode = last ? 1 : 0;
+      const size_t i1 = ((size_t)j * 2 + 0) * C + k, i2 = ((size_t)j * 2 + 1) * C + k;
+      sw[i1] = fps::BatchSweep{a1, bt->sw_start[k], nbx_s};
+      sw[i2] = fps::BatchSweep{a2, bt->sw_start[k], nbx_s};
+      rd[i1] = fps::BatchReduce{lv, ab, pl->comb_dev(j), -a1.sigma, L.npad, L.ncmax,
+                                (int)L.nc[0], (int)L.nc[1], bt->rd_start[k], nbx_r};
+      rd[i2] = rd[i1];
+      rd[i2].scale = last ? 1.0 : -a2.sigma;
+    }
+  }
+  std::vector<int> swmap(bt->sw_start[C]), rdmap(bt->rd_start[C]);
+  for (int k = 0; k < C; ++k) {
+    std::fill(swmap.begin() + bt->sw_start[k], swmap.begin() + bt->sw_start[k + 1], k);
+    std::fill(rdmap.begin() + bt->rd_start[k], rdmap.begin() + bt->rd_start[k + 1], k);
+  }
+  fps_status s;
+  if ((s = upload(bt->d_sw, sw)) != FPS_OK || (s = upload(bt->d_rd, rd)) != FPS_OK ||
+      (s = upload(bt->d_swmap, swmap)) != FPS_OK || (s = upload(bt->d_rdmap, rdmap)) != FPS_OK)
+    return s;
+  return FPS_OK;
+}
+
+// The 2 J_max batched half-steps (and their carry reductions).  At step j the
+// problems with J > j form a prefix of the sorted order; a problem's last
+// step writes its final chunk-local solution to its O1 and its carries to
+// its ab, which later steps leave alone.
+fps_status run_adi_batch(fps_batch *bt, char *ws, hipStream_t st) {
+  const int C = bt->count;
+  const bool refined = bt->prec == FPS_FP32_REFINED;
+  const fps::BatchSweep *dsw = (const fps::BatchSweep *)bt->d_sw.p;
+  const fps::BatchReduce *drd = (const fps::BatchReduce *)bt->d_rd.p;
+  const int *swmap = (const int *)bt->d_swmap.p, *rdmap = (const int *)bt->d_rdmap.p;
+  for (int j = 0; j < bt->J_max; ++j) {
+    const int k = bt->active[j];
+    const bool next_f32 = j + 1 < bt->n_f32;
+    fps::SweepArgs t1{};
+    t1.in_f32 = j == 0 ? (refined ? 1 : 0) : (j < bt->n_f32 ? 1 : 0);
+    t1.out_f32 = j < bt->n_f32 ? 1 : 0;
+    fps::SweepArgs t2{};
+    t2.in_f32 = t1.out_f32;
+    t2.g_f32 = refined ? 1 : 0;
+    t2.out_f32 = next_f32 ? 1 : 0;
+    const size_t o1 = ((size_t)j * 2 + 0) * C, o2 = ((size_t)j * 2 + 1) * C;
+    FPS_HIP(fps::launch_sweep_batch(t1, false, dsw + o1, swmap, bt->sw_start[k], ws, st));
+    FPS_HIP(fps::launch_reduce_batch(drd + o1, rdmap, bt->rd_start[k], bt->ncmax_max, ws, st));
+    FPS_HIP(fps::launch_sweep_batch(t2, true, dsw + o2, swmap, bt->sw_start[k], ws, st));
+    FPS_HIP(fps::launch_reduce_batch(drd + o2, rdmap, bt->rd_start[k], bt->ncmax_max, ws, st));
+  }
+  return FPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fps_status fps_batch_create(fps_batch **out, int dim, int count, const int64_t *n, double tol,
+                            int prec, int out_basis, unsigned flags) {
+  if (!out) return fail(FPS_E_ARG, "out must not be null");
+  *out = nullptr;
+  if (dim == 3) return fail(FPS_E_UNSUPPORTED, "batched solves are square only");
+  if (dim != 2) return fail(FPS_E_ARG, "dim must be 2 or 3");
+  if (count < 1 || count > 65536) return fail(FPS_E_ARG, "count must lie in [1, 65536]");
+  if (!n) return fail(FPS_E_ARG, "n must not be null");
+  for (int b = 0; b < count; ++b)
+    if (n[b] < 1 || n[b] > 65536) return fail(FPS_E_ARG, "every n must lie in [1, 65536]");
+  fps_batch *bt = new (std::nothrow) fps_batch();
+  if (!bt) return fail(FPS_E_NOMEM, "batch allocation failed");
+  bt->count = count;
+  bt->prec = prec;
+  bt->out_basis = out_basis;
+  bt->n.assign(n, n + count);
+  std::map<int64_t, int> idx;
+  bt->which.resize(count);
+  for (int b = 0; b < count; ++b) {
+    auto it = idx.find(n[b]);
+    if (it == idx.end()) {
+      fps_plan *pl = nullptr;
+      fps_status s = fps_plan_create(&pl, 2, n[b], FPS_BC_DIRICHLET_ZERO, tol, prec, out_basis, flags);
+      if (s != FPS_OK) {
+        delete bt;
+        return s;
+      }
+      it = idx.emplace(n[b], (int)bt->sub.size()).first;
+      bt->sub.push_back(pl);
+    }
+    bt->which[b] = it->second;
+  }
+  bt->f_off.resize(count);
+  bt->u_off.resize(count);
+  bt->ws_off.resize(count);
+  for (int b = 0; b < count; ++b) {
+    const fps_plan *pl = bt->plan_of(b);
+    bt->f_off[b] = bt->in_entries;
+    bt->u_off[b] = bt->out_entries;
+    bt->ws_off[b] = bt->ws_bytes;
+    const int64_t e = out_basis == FPS_OUT_NATIVE ? n[b] : n[b] + 2;
+    bt->in_entries += n[b] * n[b];
+    bt->out_entries += e * e;
+    bt->ws_bytes += align256(pl->ws_bytes);
+  }
+  bt->order.resize(count);
+  std::iota(bt->order.begin(), bt->order.end(), 0);
+  std::stable_sort(bt->order.begin(), bt->order.end(), [&](int a, int c) {
+    const int Ja = bt->plan_of(a)->shifts.J, Jc = bt->plan_of(c)->shifts.J;
+    return Ja != Jc ? Ja > Jc : n[a] > n[c];
+  });
+  bt->J_max = bt->plan_of(bt->order[0])->shifts.J;
+  int J_min = bt->J_max, f_min = 1 << 30;
+  for (const fps_plan *pl : bt->sub) {
+    J_min = std::min(J_min, pl->shifts.J);
+    f_min = std::min(f_min, pl->n_f32);
+  }
+  bt->n_f32 = prec == FPS_FP32_REFINED ? std::max(0, std::min(f_min, J_min - 1)) : 0;
+  bt->active.assign(bt->J_max, 0);
+  for (int j = 0; j < bt->J_max; ++j)
+    for (int k = 0; k < count; ++k)
+      if (bt->plan_of(bt->order[k])->shifts.J > j) bt->active[j] = k + 1;
+  bt->sw_start.assign(count + 1, 0);
+  bt->rd_start.assign(count + 1, 0);
+  for (int k = 0; k < count; ++k) {
+    const fps::Layout &L = bt->plan_of(bt->order[k])->L;
+    const int64_t nsw = (L.npad / fps::kCols) * (L.nc[0] + L.nc[1]);
+    const int64_t nrd = ((L.npad + 255) / 256) * 2 * L.ncmax;
+    if ((int64_t)bt->sw_start[k] + nsw > (int64_t)1 << 30 ||
+        (int64_t)bt->rd_start[k] + nrd > (int64_t)1 << 30) {
+      delete bt;
+      return fail(FPS_E_UNSUPPORTED, "batch too large for one launch");
+    }
+    bt->sw_start[k + 1] = bt->sw_start[k] + (int)nsw;
+    bt->rd_start[k + 1] = bt->rd_start[k] + (int)nrd;
+    bt->ncmax_max = std::max(bt->ncmax_max, L.ncmax);
+  }
+  if (!(flags & FPS_PLAN_HOST_ONLY)) {
+    fps_status s = build_descriptors(bt);
+    if (s != FPS_OK) {
+      delete bt;
+      return s;
+    }
+    bt->on_device = true;
+  }
+  *out = bt;
+  return FPS_OK;
+}
+
+fps_status fps_batch_info(const fps_batch *bt, int64_t *ws_bytes, int64_t *in_entries,
+                          int64_t *out_entries, int *max_J) {
+  if (!valid_batch(bt)) return fail(FPS_E_STATE, "invalid or destroyed batch");
+  if (ws_bytes) *ws_bytes = bt->ws_bytes;
+  if (in_entries) *in_entries = bt->in_entries;
+  if (out_entries) *out_entries = bt->out_entries;
+  if (max_J) *max_J = bt->J_max;
+  return FPS_OK;
+}
+
+fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, void *stream) {
+  if (!valid_batch(bt)) return fail(FPS_E_STATE, "invalid or destroyed batch");
+  if (!bt->on_device) return fail(FPS_E_STATE, "batch was created host-only");
+  if (!F || !U || !ws) return fail(FPS_E_ARG, "null pointer argument");
+  if (((uintptr_t)ws) % 256 != 0) return fail(FPS_E_ARG, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  const int C = bt->count;
+  fps_status s;
+  for (int b = 0; b < C; ++b)
+    if ((s = rhs_transform(bt->sub[bt->which[b]], F + bt->f_off[b], w + bt->ws_off[b], st)) !=
+        FPS_OK)
+      return s;
+  // Y of every problem: FP64 lands in its G region, refined in its GT region
+  // (as the single-problem solve places it).
+  const bool refined = bt->prec == FPS_FP32_REFINED;
+  const int rounds = refined ? bt->sub[0]->rounds : 1;
+  for (int k = 0; k < rounds; ++k) {
+    if (refined)
+      for (int b = 0; b < C; ++b) {
+        fps_plan *pl = bt->sub[bt->which[b]];
+        char *wb = w + bt->ws_off[b];
+        float *r = (float *)(wb + pl->off_R);
+        FPS_HIP(fps::launch_residual((const double *)(wb + pl->off_G),
+                                     k == 0 ? nullptr : (const double *)(wb + pl->off_GT),
+                                     (const double *)pl->d_sdiag.p, (const double *)pl->d_soff.p,
+                                     r, r + pl->L.npad * pl->L.npad, pl->L.npad, st));
+      }
+    if ((s = run_adi_batch(bt, w, st)) != FPS_OK) return s;
+    for (int b = 0; b < C; ++b) {
+      fps_plan *pl = bt->sub[bt->which[b]];
+      const fps::Layout &L = pl->L;
+      char *wb = w + bt->ws_off[b];
+      double *Y = (double *)(wb + (refined ? pl->off_GT : pl->off_G));
+      FPS_HIP(fps::launch_finalize<double>((const double *)(wb + pl->off_O1),
+                                           (const double *)(wb + pl->off_ab),
+                                           pl->tab_dev(pl->shifts.J - 1), Y, k == 0 ? 0 : 2,
+                                           nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
+    }
+  }
+  for (int b = 0; b < C; ++b) {
+    fps_plan *pl = bt->sub[bt->which[b]];
+    const fps::Layout &L = pl->L;
+    char *wb = w + bt->ws_off[b];
+    double *Y = (double *)(wb + (refined ? pl->off_GT : pl->off_G));
+    double *Ub = U + bt->u_off[b];
+    if (bt->out_basis == FPS_OUT_NATIVE) {
+      FPS_HIP(fps::launch_permute_out(Y, Ub, L.n, L.npad, L.mp[0], (const double *)pl->d_sinv.p,
+                                      st));
+    } else if ((s = out_transform(pl, Y, Ub, wb, st)) != FPS_OK) {
+      return s;
+    }
+  }
+  return FPS_OK;
+}
+
+void fps_batch_destroy(fps_batch *bt) {
+  if (!valid_batch(bt)) return;
+  bt->magic = 0;
+  delete bt;
+}
+
+}  // extern "C"

@@ -42,11 +42,39 @@ struct SweepArgs {
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st);
 
+// Batched sweeps over several independent problems in one launch.  The
+// workspace pointers of each descriptor's SweepArgs (in, g, out, lv,
+// ab_prev) hold byte offsets from `base`; tab, tab_prev and l1 are device
+// pointers; ab_prev is used iff tab_prev is non-null.  Workgroup g runs
+// block (local % nbx, local / nbx), local = g - wg_start, of problem
+// wg_prob[g].  Storage types and the presence of g come from `types` /
+// `with_g` and must be those of every descriptor.
+struct BatchSweep {
+  SweepArgs a;
+  int wg_start, nbx;
+};
+hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSweep *d,
+                              const int *wg_prob, int nwg, char *base, hipStream_t st);
+
 // Chunk carries: for every chain, the forward and backward carry into each
 // chunk, scaled by `scale`, into ab [2][ncmax][npad][2] (comb: the carry
 // combinations of the producing pass's shift).
 hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
                          int64_t npad, int nc0, int nc1, int64_t ncmax, hipStream_t st);
+
+// Batched launch_reduce: lv_off / ab_off are byte offsets from `base`; the
+// grid of one problem is (ceil(npad / 256), 2 ncmax), flattened as for
+// BatchSweep; ncmax_max bounds every problem's ncmax (LDS size).
+struct BatchReduce {
+  int64_t lv_off, ab_off;
+  const double *comb;
+  double scale;
+  int64_t npad, ncmax;
+  int nc0, nc1;
+  int wg_start, nbx;
+};
+hipError_t launch_reduce_batch(const BatchReduce *d, const int *wg_prob, int nwg, int64_t ncmax_max,
+                               char *base, hipStream_t st);
 
 // Y_perm[r][col] = x[r][col] + carries (final pass, non-transposed; x of
 // storage type T).

@@ -55,16 +55,17 @@ static_assert(T_L == 0 && T_IB == 1 && T_U == 2 && T_F1 == 3 && T_BK1 == 4, "tab
 // kWithG: the right-hand side is v + sg * g while the output is v - sigma x
 // (g is not carried into the output); otherwise the right-hand side is v.
 // v = in_scale * in + (chunk carries of the producing pass).
+// One workgroup of a sweep: chain block bx (64 storage columns) and chunk
+// row by (parity-0 chunks first).
 template <typename Tin, typename Tg, typename Tout, bool kWithG>
-__global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
-  __shared__ double lds[kSweepLds];
+__device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, const int by,
+                                            double *lds) {
   const int tid = threadIdx.x;
   const int lane = tid & (kCols - 1);
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t npad = a.npad, ms = a.mstride, ncmax = a.ncmax;
-  const int64_t col0 = (int64_t)blockIdx.x * kCols;
+  const int64_t col0 = (int64_t)bx * kCols;
   const int64_t col = col0 + lane;
-  const int by = blockIdx.y;
   const int s = by < a.nc0 ? 0 : 1;
   const int c = by - (s ? a.nc0 : 0);
   const int64_t mps = s ? a.mp1 : a.mp0;
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
   const bool active = k0 < mps;
   const int64_t rbase = (s ? a.mp0 : 0) + kc0;  // storage row of the chunk start
   const int64_t row0 = rbase + (int64_t)w * kSeg;
-  const bool has_prev = a.ab_prev != nullptr;
+  const bool has_prev = a.tab_prev != nullptr;
 
   // 1. Small loads, issued before the streaming loads and without divergent
   //    branches (addresses are clamped), so that waiting for them does not
@@ -225,18 +226,43 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
   }
 }
 
+template <typename Tin, typename Tg, typename Tout, bool kWithG>
+__global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
+  __shared__ double lds[kSweepLds];
+  sweep_block<Tin, Tg, Tout, kWithG>(a, blockIdx.x, blockIdx.y, lds);
+}
+
+// Batched sweep: workgroup g belongs to problem wg_prob[g]; the problem's
+// descriptor holds workspace offsets in place of its workspace pointers.
+template <typename Tin, typename Tg, typename Tout, bool kWithG>
+__global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep_batch(const BatchSweep *__restrict__ d,
+                                                                  const int *__restrict__ wg_prob,
+                                                                  char *base) {
+  __shared__ double lds[kSweepLds];
+  const int k = __builtin_amdgcn_readfirstlane(wg_prob[blockIdx.x]);
+  const BatchSweep &e = d[k];
+  SweepArgs a = e.a;
+  a.in = base + (intptr_t)a.in;
+  if (kWithG) a.g = base + (intptr_t)a.g;
+  a.out = base + (intptr_t)a.out;
+  a.lv = (double *)(base + (intptr_t)a.lv);
+  if (a.tab_prev != nullptr) a.ab_prev = (const double *)(base + (intptr_t)a.ab_prev);
+  const int local = (int)blockIdx.x - e.wg_start;
+  sweep_block<Tin, Tg, Tout, kWithG>(a, local % e.nbx, local / e.nbx, lds);
+}
+
 // Chunk carries of one half-sweep: thread (parity s, chunk c, chain r)
 // forms cf[c], cb[c] of chain r as linear combinations of the chain's chunk
 // boundary values (coefficients precomputed per shift and staged in LDS, one
 // row per block), scaled by `scale`.  Output layout ab[s][c][r][2].
-__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ lv,
-                                                const double *__restrict__ comb,
-                                                double *__restrict__ ab, double scale,
-                                                int64_t npad, int nc0, int nc1, int64_t ncmax) {
-  extern __shared__ double wrow[];  // [nc][kNComb]
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = blockIdx.y >= ncmax ? 1 : 0;
-  const int c = blockIdx.y - (s ? (int)ncmax : 0);
+__device__ __forceinline__ void reduce_block(const double *__restrict__ lv,
+                                             const double *__restrict__ comb,
+                                             double *__restrict__ ab, double scale, int64_t npad,
+                                             int nc0, int nc1, int64_t ncmax, int bx, int by,
+                                             double *wrow /* [nc][kNComb], LDS */) {
+  const int64_t r = (int64_t)bx * blockDim.x + threadIdx.x;
+  const int s = by >= ncmax ? 1 : 0;
+  const int c = by - (s ? (int)ncmax : 0);
   const int nc = s ? nc1 : nc0;
   if (c >= nc) return;
   const double *__restrict__ W = comb + (((int64_t)s * ncmax + c) * ncmax) * kNComb;
@@ -257,35 +283,80 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ lv,
   o[1] = scale * B;
 }
 
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ lv,
+                                                const double *__restrict__ comb,
+                                                double *__restrict__ ab, double scale,
+                                                int64_t npad, int nc0, int nc1, int64_t ncmax) {
+  extern __shared__ double wrow[];
+  reduce_block(lv, comb, ab, scale, npad, nc0, nc1, ncmax, blockIdx.x, blockIdx.y, wrow);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_batch(const BatchReduce *__restrict__ d,
+                                                      const int *__restrict__ wg_prob, char *base) {
+  extern __shared__ double wrow[];
+  const int k = __builtin_amdgcn_readfirstlane(wg_prob[blockIdx.x]);
+  const BatchReduce &e = d[k];
+  const int local = (int)blockIdx.x - e.wg_start;
+  reduce_block((const double *)(base + e.lv_off), e.comb, (double *)(base + e.ab_off), e.scale,
+               e.npad, e.nc0, e.nc1, e.ncmax, local % e.nbx, local / e.nbx, wrow);
+}
+
 }  // namespace
 
-template <typename Tin, typename Tg, typename Tout, bool kWithG>
-void launch_typed(const SweepArgs &a, hipStream_t st) {
-  dim3 grid((unsigned)(a.npad / kCols), (unsigned)(a.nc0 + a.nc1));
-  hipLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kWithG>), grid, dim3(kCols * kWaves), 0, st, a);
+// Launches one sweep (single: d == nullptr, grid from `a`; batched: `nwg`
+// workgroups over the descriptors d) with the storage types of `a`.
+struct SweepLaunch {
+  const SweepArgs &a;
+  const BatchSweep *d;
+  const int *wg_prob;
+  char *base;
+  int nwg;
+  hipStream_t st;
+  template <typename Tin, typename Tg, typename Tout, bool kWithG>
+  void go() const {
+    if (d == nullptr) {
+      dim3 grid((unsigned)(a.npad / kCols), (unsigned)(a.nc0 + a.nc1));
+      hipLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kWithG>), grid, dim3(kCols * kWaves), 0, st, a);
+    } else {
+      hipLaunchKernelGGL((k_sweep_batch<Tin, Tg, Tout, kWithG>), dim3((unsigned)nwg),
+                         dim3(kCols * kWaves), 0, st, d, wg_prob, base);
+    }
+  }
+};
+
+hipError_t dispatch_sweep(const SweepLaunch &L, bool with_g) {
+  const SweepArgs &a = L.a;
+  const int code = (a.in_f32 ? 4 : 0) | (a.g_f32 ? 2 : 0) | (a.out_f32 ? 1 : 0);
+  if (!with_g) {
+    switch (code & 5) {
+      case 0: L.go<double, double, double, false>(); break;
+      case 4: L.go<float, double, double, false>(); break;
+      case 5: L.go<float, double, float, false>(); break;
+      default: return hipErrorInvalidValue;  // a float output from a double input
+    }
+  } else {
+    switch (code) {
+      case 0: L.go<double, double, double, true>(); break;
+      case 2: L.go<double, float, double, true>(); break;
+      case 6: L.go<float, float, double, true>(); break;
+      case 7: L.go<float, float, float, true>(); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
   const int nchunks = a.nc0 + a.nc1;
   if (a.npad % kCols != 0 || nchunks <= 0 || a.in == nullptr) return hipErrorInvalidValue;
-  const int code = (a.in_f32 ? 4 : 0) | (a.g_f32 ? 2 : 0) | (a.out_f32 ? 1 : 0);
-  if (a.g == nullptr) {
-    switch (code & 5) {
-      case 0: launch_typed<double, double, double, false>(a, st); break;
-      case 4: launch_typed<float, double, double, false>(a, st); break;
-      case 5: launch_typed<float, double, float, false>(a, st); break;
-      default: return hipErrorInvalidValue;  // a float output from a double input
-    }
-  } else {
-    switch (code) {
-      case 0: launch_typed<double, double, double, true>(a, st); break;
-      case 2: launch_typed<double, float, double, true>(a, st); break;
-      case 6: launch_typed<float, float, double, true>(a, st); break;
-      case 7: launch_typed<float, float, float, true>(a, st); break;
-      default: return hipErrorInvalidValue;
-    }
-  }
-  return hipGetLastError();
+  if ((a.ab_prev == nullptr) != (a.tab_prev == nullptr)) return hipErrorInvalidValue;
+  return dispatch_sweep(SweepLaunch{a, nullptr, nullptr, nullptr, 0, st}, a.g != nullptr);
+}
+
+hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSweep *d,
+                              const int *wg_prob, int nwg, char *base, hipStream_t st) {
+  if (nwg <= 0) return hipSuccess;
+  return dispatch_sweep(SweepLaunch{types, d, wg_prob, base, nwg, st}, with_g);
 }
 
 hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
@@ -294,6 +365,15 @@ hipError_t launch_reduce(const double *lv, const double *comb, double *ab, doubl
   const size_t shm = (size_t)ncmax * kNComb * sizeof(double);
   if (shm > 64 * 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce, grid, dim3(256), shm, st, lv, comb, ab, scale, npad, nc0, nc1, ncmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(const BatchReduce *d, const int *wg_prob, int nwg, int64_t ncmax_max,
+                               char *base, hipStream_t st) {
+  if (nwg <= 0) return hipSuccess;
+  const size_t shm = (size_t)ncmax_max * kNComb * sizeof(double);
+  if (shm > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)nwg), dim3(256), shm, st, d, wg_prob, base);
   return hipGetLastError();
 }
 

@@ -1,0 +1,108 @@
+"""GPU parity of the batched square solve: every problem of a batch equals
+the single-problem solve of the same size bit for bit (same kernels, same
+per-problem arithmetic), and the exact discrete solution of the oracle."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import square
+
+torch = pytest.importorskip("torch")
+import paper_1710_11259_amd as fps  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+MIXED = [1, 5, 64, 129, 32, 544, 64, 300, 2, 1030]
+
+
+def _rhs(ns, seed=7):
+    rng = np.random.default_rng(seed)
+    return [workloads.decayed_normal(rng, (n, n), 1.5) for n in ns]
+
+
+def _single(n, F, **kw):
+    p = fps.plan(n, **kw)
+    U = fps.solve(p, torch.from_numpy(F).cuda())
+    torch.cuda.synchronize()
+    return U.cpu().numpy()
+
+
+@pytest.mark.parametrize("out", ["cheb", "native"])
+def test_batch_equals_single_solves_bitwise(out):
+    Fs = _rhs(MIXED)
+    b = fps.batch(MIXED, tol=1e-13, out=out)
+    print(f"batch fp64 {out}: {len(MIXED)} problems, max J {b.max_J}", flush=True)
+    U = fps.batch_solve(b, b.pack(Fs))
+    torch.cuda.synchronize()
+    Us = [u.cpu().numpy() for u in b.unpack(U)]
+    for n, F, Ub in zip(MIXED, Fs, Us):
+        Ur = _single(n, F, tol=1e-13, out=out)
+        assert Ub.shape == Ur.shape
+        assert np.array_equal(Ub, Ur), f"n={n}: batched result differs from the single solve"
+    for n, F, Ub in zip(MIXED, Fs, Us):
+        if n <= 300:
+            Uo = square.poisson_square(F, out=out)
+            err = np.linalg.norm(Ub - Uo) / np.linalg.norm(Uo)
+            assert err <= 1e-12, f"n={n}: rel err {err:.3e}"
+
+
+def test_batch_refined_matches_oracle():
+    ns = [1, 5, 64, 129, 544, 1024, 32]
+    Fs = _rhs(ns, seed=8)
+    b = fps.batch(ns, tol=1e-13, precision="fp32_refined")
+    print(f"batch refined: max J {b.max_J}", flush=True)
+    U = fps.batch_solve(b, b.pack(Fs))
+    torch.cuda.synchronize()
+    for n, F, Ub in zip(ns, Fs, b.unpack(U)):
+        Uo = square.poisson_square(F)
+        err = np.linalg.norm(Ub.cpu().numpy() - Uo) / np.linalg.norm(Uo)
+        print(f"refined n={n} rel err {err:.3e}", flush=True)
+        assert err <= 1e-12
+
+
+def test_batch_workload_256_problems():
+    # 256 problems, n_b = 32 U{1..32}, seed 1 (the batched workload).
+    ns, Fs = workloads.batched_problems()
+    b = fps.batch(ns, tol=1e-13)
+    print(f"256-problem batch: sum n^2 = {sum(n * n for n in ns)}, max J {b.max_J}", flush=True)
+    U = fps.batch_solve(b, b.pack(Fs))
+    torch.cuda.synchronize()
+    Us = b.unpack(U)
+    # bitwise against single solves for one problem of every distinct size
+    seen = set()
+    for i, n in enumerate(ns):
+        if n in seen:
+            continue
+        seen.add(n)
+        Ur = _single(n, Fs[i], tol=1e-13)
+        assert np.array_equal(Us[i].cpu().numpy(), Ur), f"problem {i} (n={n})"
+    # against the oracle on a sample spanning the sizes
+    order = np.argsort(ns)
+    for i in order[:: max(1, len(ns) // 8)]:
+        Uo = square.poisson_square(Fs[i])
+        err = np.linalg.norm(Us[i].cpu().numpy() - Uo) / np.linalg.norm(Uo)
+        assert err <= 1e-12, f"problem {i} (n={ns[i]}): rel err {err:.3e}"
+
+
+def test_batch_graph_replays_match_eager():
+    ns = [32, 96, 64, 160, 512, 33]
+    Fs = _rhs(ns, seed=9)
+    b = fps.batch(ns, tol=1e-13)
+    g = fps.BatchGraph(b)
+    ref = fps.batch_solve(b, b.pack(Fs)).cpu().numpy()
+    for rep in range(3):
+        g.F.copy_(b.pack(Fs))
+        out = g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), f"replay {rep}"
+        # eager work on the same stream between replays
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64).sum()
+        torch.cuda.synchronize()
+        del junk
+    # a different input through the same graph
+    Fs2 = _rhs(ns, seed=10)
+    g.F.copy_(b.pack(Fs2))
+    out = g.replay()
+    torch.cuda.synchronize()
+    ref2 = fps.batch_solve(b, b.pack(Fs2)).cpu().numpy()
+    assert np.array_equal(out.cpu().numpy(), ref2)

@@ -99,6 +99,29 @@ def test_refinement_structure(n):
     assert r.workspace_bytes > d.workspace_bytes
 
 
+def test_batch_queries_and_errors():
+    ns = [32, 64, 544, 32, 1, 129]
+    b = fps.batch(ns, host_only=True)
+    assert b.in_entries == sum(n * n for n in ns)
+    assert b.out_entries == sum((n + 2) ** 2 for n in ns)
+    plans = {n: fps.plan(n, host_only=True) for n in set(ns)}
+    assert b.max_J == max(p.J for p in plans.values())
+    assert b.workspace_bytes == sum((plans[n].workspace_bytes + 255) // 256 * 256 for n in ns)
+    bn = fps.batch(ns, out="native", host_only=True)
+    assert bn.out_entries == sum(n * n for n in ns)
+    L = fps.lib()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int64 * 2)(4, 0)
+    assert L.fps_batch_create(ctypes.byref(h), 2, 2, arr, 1e-13, 0, 0, 1) == fps.FPS_E_ARG
+    arr = (ctypes.c_int64 * 1)(4)
+    assert L.fps_batch_create(ctypes.byref(h), 2, 0, arr, 1e-13, 0, 0, 1) == fps.FPS_E_ARG
+    assert L.fps_batch_create(ctypes.byref(h), 3, 1, arr, 1e-13, 0, 0, 1) == fps.FPS_E_UNSUPPORTED
+    assert L.fps_batch_create(ctypes.byref(h), 2, 1, arr, 2.0, 0, 0, 1) == fps.FPS_E_ARG
+    assert L.fps_batch_solve(None, None, None, None, None) == fps.FPS_E_STATE
+    hb = fps.batch([8], host_only=True)
+    assert L.fps_batch_solve(hb.handle, None, None, None, None) == fps.FPS_E_STATE
+
+
 # --- host planner internals through a g++-built shim -----------------------
 
 @pytest.fixture(scope="module")
