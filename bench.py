@@ -25,6 +25,59 @@ SWEEP_TRAFFIC = {"sha256": "3934e31aeec99cef01392722df5295b2dec6ba6ad9b4a80b9b9d
                  "n": 4096, "half_step_1": 278.9e6, "half_step_2": 413.1e6}
 
 
+def bench_batch(fps, workloads, torch, tol, reps=3):
+    """256 independent square solves (n_b = 32 U{1..32}, seed 1): one graph
+    launch per batch (FP64 and FP32-refined) against a sequential loop of
+    single FP64 solves."""
+    import numpy as np
+    ns, Fs = workloads.batched_problems()
+    dof = float(sum(n * n for n in ns))
+    res = {"problems": len(ns), "dof": dof}
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(k):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / k
+
+    # sequential single FP64 solves (the same inputs, one plan per size)
+    plans = {n: fps.plan(n, tol=tol) for n in sorted(set(ns))}
+    ws = torch.empty(max(p.workspace_bytes for p in plans.values()), dtype=torch.uint8,
+                     device="cuda")
+    Fd = [torch.from_numpy(F).cuda() for F in Fs]
+    Us = [torch.empty(plans[n].out_shape(), dtype=torch.float64, device="cuda") for n in ns]
+
+    def seq():
+        for n, F, U in zip(ns, Fd, Us):
+            fps.solve(plans[n], F, out=U, ws=ws)
+    t_seq = timed(seq, 1)
+    res["sequential_fp64_ms"] = t_seq
+    for prec in ("fp64", "fp32_refined"):
+        b = fps.batch(ns, tol=tol, precision=prec)
+        g = fps.BatchGraph(b)
+        g.F.copy_(b.pack(Fs))
+        t = timed(g.replay, reps)
+        r = {"ms_per_batch": t, "dof_per_s": dof / (t * 1e-3), "speedup_vs_sequential_fp64":
+             t_seq / t, "max_J": b.max_J, "launch": "one HIP graph"}
+        got = b.unpack(g.U)
+        worst = 0.0
+        for U, Ub in zip(Us, got):
+            d = float(torch.linalg.norm(Ub - U) / torch.linalg.norm(U))
+            worst = max(worst, d)
+        r["max_rel_diff_vs_sequential_fp64"] = worst
+        res[prec] = r
+        del g, b
+    del ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -34,7 +87,8 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-13)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the FP32-refined timing")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the FP32-refined and batched timings")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -152,6 +206,7 @@ def main() -> int:
                                  "inner_J": pr.J, "rounds": pr.rounds,
                                  "f32_steps_per_round": pr.f32_steps}
         del wsr
+        forms["batched"] = bench_batch(fps, workloads, torch, args.tol)
     if forms:
         out["forms"] = forms
 

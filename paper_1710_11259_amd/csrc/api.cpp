@@ -163,15 +163,12 @@ fps_status check_solve_args(fps_plan *pl, const void *a, const void *b, void *ws
 }
 
 // Input map: G_perm = Rs_s F_st Rs_t^T for the four parity blocks, then GT.
-fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st) {
+int rhs_gemms(const fps_plan *pl, char *ws, fps::GemmProb *g1, fps::GemmProb *g2) {
   const fps::Layout &L = pl->L;
-  const int64_t n = L.n, npad = L.npad;
+  const int64_t npad = L.npad;
   double *G = (double *)(ws + pl->off_G);
-  double *GT = (double *)(ws + pl->off_GT);
+  const double *GT = (const double *)(ws + pl->off_GT);
   double *Tb = (double *)(ws + pl->off_O0);
-  // F in the parity-blocked layout (zero padded), staged in the GT region.
-  FPS_HIP(fps::launch_permute_in(F, GT, n, npad, L.mp[0], st));
-  fps::GemmProb g1[4], g2[4];
   int cnt = 0;
   int64_t toff = 0;
   for (int s = 0; s < 2; ++s)
@@ -190,21 +187,28 @@ fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st
                               ms, 1, mt, 1, npad, 1, 1, 0, 0, 0, 0, 0, 0, 0};
       ++cnt;
     }
+  return cnt;
+}
+
+fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st) {
+  const fps::Layout &L = pl->L;
+  // F in the parity-blocked layout (zero padded), staged in the GT region.
+  FPS_HIP(fps::launch_permute_in(F, (double *)(ws + pl->off_GT), L.n, L.npad, L.mp[0], st));
+  fps::GemmProb g1[4], g2[4];
+  const int cnt = rhs_gemms(pl, ws, g1, g2);
   FPS_HIP(fps::launch_gemm(g1, cnt, st));
   FPS_HIP(fps::launch_gemm(g2, cnt, st));
-  FPS_HIP(fps::launch_transpose(G, GT, npad, st));
+  FPS_HIP(fps::launch_transpose((const double *)(ws + pl->off_G), (double *)(ws + pl->off_GT),
+                                L.npad, st));
   return FPS_OK;
 }
 
-// Output map: U_st = P_s Y_st P_t^T into the strided parity view of U.
-fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hipStream_t st) {
+int out_gemms(const fps_plan *pl, const double *Y, double *U, char *ws, fps::GemmProb *g1,
+              fps::GemmProb *g2) {
   const fps::Layout &L = pl->L;
-  const int64_t n = L.n, N = n + 2, npad = L.npad;
-  // temporaries mp_s x mop_t: the O0 and O1 regions (contiguous) are free here
+  const int64_t N = L.n + 2, npad = L.npad;
+  // temporaries mp_s x mop_t in the O0 and O1 regions (contiguous, free here)
   double *Tb = (double *)(ws + pl->off_O0);
-  if (npad * (pl->mop[0] + pl->mop[1]) * 8 > pl->off_lv - pl->off_O0)
-    return fail(FPS_E_STATE, "internal: output temporary exceeds workspace");
-  fps::GemmProb g1[4], g2[4];
   int cnt = 0;
   int64_t toff = 0;
   for (int s = 0; s < 2; ++s)
@@ -221,6 +225,16 @@ fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hip
                               ms, ms, 1, mot, 1, 2 * N, 2, 1, -1, 0, 0, 0, 0, 0, 0};
       ++cnt;
     }
+  return cnt;
+}
+
+fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hipStream_t st) {
+  const fps::Layout &L = pl->L;
+  const int64_t N = L.n + 2;
+  if (L.npad * (pl->mop[0] + pl->mop[1]) * 8 > pl->off_lv - pl->off_O0)
+    return fail(FPS_E_STATE, "internal: output temporary exceeds workspace");
+  fps::GemmProb g1[4], g2[4];
+  const int cnt = out_gemms(pl, Y, U, ws, g1, g2);
   FPS_HIP(fps::launch_fill(U, N * N, 0.0, st));
   FPS_HIP(fps::launch_gemm(g1, cnt, st));
   FPS_HIP(fps::launch_gemm(g2, cnt, st));

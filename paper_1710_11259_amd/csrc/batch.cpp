@@ -37,6 +37,9 @@ struct fps_batch {
   std::vector<int> sw_start, rd_start;  // workgroup prefix sums over the sorted problems
   int64_t ncmax_max = 0;
   DeviceBuf d_sw, d_rd, d_swmap, d_rdmap;
+  // coefficient-map GEMMs of all problems: input map g1, g2; output map g1, g2
+  DeviceBuf d_gd[4], d_gmap[4];
+  int gtiles[4] = {0, 0, 0, 0};
 
   ~fps_batch() {
     for (fps_plan *p : sub) fps_plan_destroy(p);
@@ -52,6 +55,46 @@ bool valid_batch(const fps_batch *b) { return b != nullptr && b->magic == kBatch
 template <typename P>
 P off_ptr(int64_t off) {
   return (P)(intptr_t)off;
+}
+
+// GEMM tables of the coefficient maps: the single-problem builders run on
+// synthetic base pointers (the problem's workspace offset, its U offset in
+// bytes), so every workspace or output operand comes out as an offset.
+fps_status build_gemm_tables(fps_batch *bt) {
+  std::vector<fps::GemmDesc> tab[4];
+  const bool refined = bt->prec == FPS_FP32_REFINED;
+  for (int b = 0; b < bt->count; ++b) {
+    const fps_plan *pl = bt->plan_of(b);
+    char *wsyn = (char *)(intptr_t)bt->ws_off[b];
+    fps::GemmProb g[4][4];
+    const int c_in = rhs_gemms(pl, wsyn, g[0], g[1]);
+    const double *Ysyn = (const double *)(wsyn + (refined ? pl->off_GT : pl->off_G));
+    double *Usyn = (double *)(intptr_t)(bt->u_off[b] * (int64_t)sizeof(double));
+    const int c_out = bt->out_basis == FPS_OUT_CHEB ? out_gemms(pl, Ysyn, Usyn, wsyn, g[2], g[3]) : 0;
+    // base ids (A, B, C): ws-relative 1, absolute 0, output-relative 2
+    static const int ids[4][3] = {{1, 0, 1}, {0, 1, 1}, {1, 0, 1}, {0, 1, 2}};
+    for (int t = 0; t < 4; ++t) {
+      const int cnt = t < 2 ? c_in : c_out;
+      for (int i = 0; i < cnt; ++i) {
+        if (!fps::gemm_operands_ok(g[t][i]))
+          return fail(FPS_E_STATE, "internal: batched GEMM operand layout");
+        fps::GemmDesc d{g[t][i], ids[t][0], ids[t][1], ids[t][2], bt->gtiles[t], 0};
+        bt->gtiles[t] += fps::gemm_tiles(g[t][i], &d.ntx);
+        tab[t].push_back(d);
+      }
+    }
+  }
+  for (int t = 0; t < 4; ++t) {
+    std::vector<int> map(bt->gtiles[t]);
+    for (size_t k = 0; k < tab[t].size(); ++k) {
+      const int end = k + 1 < tab[t].size() ? tab[t][k + 1].tile_start : bt->gtiles[t];
+      std::fill(map.begin() + tab[t][k].tile_start, map.begin() + end, (int)k);
+    }
+    fps_status s;
+    if ((s = upload(bt->d_gd[t], tab[t])) != FPS_OK || (s = upload(bt->d_gmap[t], map)) != FPS_OK)
+      return s;
+  }
+  return FPS_OK;
 }
 
 // Builds the per-step descriptors of every problem (sorted order) and the
@@ -132,7 +175,7 @@ fps_status build_descriptors(fps_batch *bt) {
   if ((s = upload(bt->d_sw, sw)) != FPS_OK || (s = upload(bt->d_rd, rd)) != FPS_OK ||
       (s = upload(bt->d_swmap, swmap)) != FPS_OK || (s = upload(bt->d_rdmap, rdmap)) != FPS_OK)
     return s;
-  return FPS_OK;
+  return build_gemm_tables(bt);
 }
 
 // The 2 J_max batched half-steps (and their carry reductions).  At step j the
@@ -276,10 +319,25 @@ fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, 
   char *w = (char *)ws;
   const int C = bt->count;
   fps_status s;
-  for (int b = 0; b < C; ++b)
-    if ((s = rhs_transform(bt->sub[bt->which[b]], F + bt->f_off[b], w + bt->ws_off[b], st)) !=
-        FPS_OK)
-      return s;
+  auto gemm = [&](int t) {
+    return fps::launch_gemm_table((const fps::GemmDesc *)bt->d_gd[t].p,
+                                  (const int *)bt->d_gmap[t].p, bt->gtiles[t], w, (char *)U, st);
+  };
+  // Input maps: F into each problem's GT region, the two GEMM stages of all
+  // problems, then G^T.
+  for (int b = 0; b < C; ++b) {
+    const fps_plan *pl = bt->plan_of(b);
+    FPS_HIP(fps::launch_permute_in(F + bt->f_off[b], (double *)(w + bt->ws_off[b] + pl->off_GT),
+                                   pl->L.n, pl->L.npad, pl->L.mp[0], st));
+  }
+  FPS_HIP(gemm(0));
+  FPS_HIP(gemm(1));
+  for (int b = 0; b < C; ++b) {
+    const fps_plan *pl = bt->plan_of(b);
+    char *wb = w + bt->ws_off[b];
+    FPS_HIP(fps::launch_transpose((const double *)(wb + pl->off_G), (double *)(wb + pl->off_GT),
+                                  pl->L.npad, st));
+  }
   // Y of every problem: FP64 lands in its G region, refined in its GT region
   // (as the single-problem solve places it).
   const bool refined = bt->prec == FPS_FP32_REFINED;
@@ -307,19 +365,19 @@ fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, 
                                            nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
     }
   }
-  for (int b = 0; b < C; ++b) {
-    fps_plan *pl = bt->sub[bt->which[b]];
-    const fps::Layout &L = pl->L;
-    char *wb = w + bt->ws_off[b];
-    double *Y = (double *)(wb + (refined ? pl->off_GT : pl->off_G));
-    double *Ub = U + bt->u_off[b];
-    if (bt->out_basis == FPS_OUT_NATIVE) {
-      FPS_HIP(fps::launch_permute_out(Y, Ub, L.n, L.npad, L.mp[0], (const double *)pl->d_sinv.p,
-                                      st));
-    } else if ((s = out_transform(pl, Y, Ub, wb, st)) != FPS_OK) {
-      return s;
+  if (bt->out_basis == FPS_OUT_NATIVE) {
+    for (int b = 0; b < C; ++b) {
+      fps_plan *pl = bt->sub[bt->which[b]];
+      const fps::Layout &L = pl->L;
+      const double *Y = (const double *)(w + bt->ws_off[b] + (refined ? pl->off_GT : pl->off_G));
+      FPS_HIP(fps::launch_permute_out(Y, U + bt->u_off[b], L.n, L.npad, L.mp[0],
+                                      (const double *)pl->d_sinv.p, st));
     }
+    return FPS_OK;
   }
+  FPS_HIP(fps::launch_fill(U, bt->out_entries, 0.0, st));
+  FPS_HIP(gemm(2));
+  FPS_HIP(gemm(3));
   return FPS_OK;
 }
 

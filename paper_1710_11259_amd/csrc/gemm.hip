@@ -31,12 +31,11 @@ struct GemmBatch {
 
 constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
 
-__global__ __launch_bounds__(256, 2) void k_gemm(GemmBatch batch) {
-  const GemmProb g = batch.p[blockIdx.z];
-  const int64_t i0 = (int64_t)blockIdx.y * GBM, j0 = (int64_t)blockIdx.x * GBN;
+// One 128 x 128 output tile (column tile bx, row tile by) of problem g.
+__device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const int by,
+                                          double (*As)[GBM + GPAD], double (*Bs)[GBN + GPAD]) {
+  const int64_t i0 = (int64_t)by * GBM, j0 = (int64_t)bx * GBN;
   if (i0 >= g.M || j0 >= g.N) return;
-  __shared__ double As[GBK][GBM + GPAD];
-  __shared__ double Bs[GBK][GBN + GPAD];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wy = wid >> 1, wx = wid & 1;
 
@@ -137,7 +136,54 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmBatch batch) {
       }
 }
 
+__global__ __launch_bounds__(256, 2) void k_gemm(GemmBatch batch) {
+  __shared__ double As[GBK][GBM + GPAD];
+  __shared__ double Bs[GBK][GBN + GPAD];
+  gemm_tile(batch.p[blockIdx.z], blockIdx.x, blockIdx.y, As, Bs);
+}
+
+// Table-driven GEMM: workgroup g computes tile (local % ntx, local / ntx),
+// local = g - tile_start, of problem tile_prob[g]; operand pointers are
+// rebased per GemmDesc base ids.
+__device__ __forceinline__ const double *rebase(const double *p, int id, char *ws, char *out) {
+  return id == 1 ? (const double *)(ws + (intptr_t)p)
+                 : id == 2 ? (const double *)(out + (intptr_t)p) : p;
+}
+
+__global__ __launch_bounds__(256, 2) void k_gemm_table(const GemmDesc *__restrict__ d,
+                                                       const int *__restrict__ tile_prob, char *ws,
+                                                       char *out) {
+  __shared__ double As[GBK][GBM + GPAD];
+  __shared__ double Bs[GBK][GBN + GPAD];
+  const int k = __builtin_amdgcn_readfirstlane(tile_prob[blockIdx.x]);
+  const GemmDesc &e = d[k];
+  GemmProb g = e.p;
+  g.A = rebase(g.A, e.abase, ws, out);
+  g.B = rebase(g.B, e.bbase, ws, out);
+  g.C = (double *)rebase(g.C, e.cbase, ws, out);
+  const int local = (int)blockIdx.x - e.tile_start;
+  gemm_tile(g, local % e.ntx, local / e.ntx, As, Bs);
+}
+
 }  // namespace
+
+bool gemm_operands_ok(const GemmProb &q) {
+  return q.sak == 1 && q.sbj == 1 && q.K % GBK == 0 && !(q.sai & 1) && !(q.sbk & 1) &&
+         !((uintptr_t)q.A & 15) && !((uintptr_t)q.B & 15) && q.M >= 1 && q.N >= 1;
+}
+
+int gemm_tiles(const GemmProb &q, int *ntx) {
+  *ntx = (int)((q.N + GBN - 1) / GBN);
+  return *ntx * (int)((q.M + GBM - 1) / GBM);
+}
+
+hipError_t launch_gemm_table(const GemmDesc *d, const int *tile_prob, int ntiles, char *ws,
+                             char *out, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemm_table, dim3((unsigned)ntiles), dim3(256), 0, st, d, tile_prob, ws,
+                     out);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm(const GemmProb *probs, int count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
@@ -147,9 +193,7 @@ hipError_t launch_gemm(const GemmProb *probs, int count, hipStream_t st) {
   for (int i = 0; i < count; ++i) {
     const GemmProb &q = probs[i];
     // contiguous operands, 16-byte aligned, K padded to the k-tile
-    if (q.sak != 1 || q.sbj != 1 || q.K % GBK != 0 || (q.sai & 1) || (q.sbk & 1) ||
-        ((uintptr_t)q.A & 15) || ((uintptr_t)q.B & 15) || q.M < 1 || q.N < 1)
-      return hipErrorInvalidValue;
+    if (!gemm_operands_ok(q)) return hipErrorInvalidValue;
     b.p[i] = probs[i];
     mt = probs[i].M > mt * GBM ? (probs[i].M + GBM - 1) / GBM : mt;
     nt = probs[i].N > nt * GBN ? (probs[i].N + GBN - 1) / GBN : nt;

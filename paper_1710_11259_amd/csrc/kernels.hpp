@@ -126,4 +126,22 @@ struct GemmProb {
 };
 hipError_t launch_gemm(const GemmProb *probs, int count, hipStream_t st);
 
+// The launcher's operand requirements (also for table-driven problems, with
+// offsets in place of pointers) and the tile count of one problem (ntx: its
+// column tiles).
+bool gemm_operands_ok(const GemmProb &q);
+int gemm_tiles(const GemmProb &q, int *ntx);
+
+// Table-driven GEMM over many problems in one launch.  Each pointer of a
+// descriptor's GemmProb is absolute (base id 0), a byte offset from `ws`
+// (1) or from `out` (2).  Workgroup g computes tile (local % ntx, local /
+// ntx), local = g - tile_start, of problem tile_prob[g].
+struct GemmDesc {
+  GemmProb p;
+  int abase, bbase, cbase;
+  int tile_start, ntx;
+};
+hipError_t launch_gemm_table(const GemmDesc *d, const int *tile_prob, int ntiles, char *ws,
+                             char *out, hipStream_t st);
+
 }  // namespace fps

@@ -111,6 +111,13 @@ fps_status upload(DeviceBuf &b, const std::vector<T> &h) {
 // Input map of one square problem: F (n x n, natural order) -> G and G^T in
 // the plan's workspace `ws`.
 fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st);
+// The coefficient-map GEMMs of one problem (up to 4 parity-block products
+// per stage; returns their count), operands formed from the workspace base
+// `ws` (and Y, U); rhs: g1 then g2 after k_permute_in of F into the GT
+// region; out: g1 then g2 after U is zero-filled.
+int rhs_gemms(const fps_plan *pl, char *ws, fps::GemmProb *g1, fps::GemmProb *g2);
+int out_gemms(const fps_plan *pl, const double *Y, double *U, char *ws, fps::GemmProb *g1,
+              fps::GemmProb *g2);
 // Output map: Y (parity-blocked) -> U in the plan's output basis.
 fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hipStream_t st);
 // Y of A~ Y + Y A~ = G for G in the workspace (FP64 or refined).
