@@ -78,6 +78,61 @@ def bench_batch(fps, workloads, torch, tol, reps=3):
     return res
 
 
+def bench_cube(fps, workloads, torch, tol, n=256, steps=2, check=True):
+    """Cube n^3 solve (two-level nested ADI, FP64): time per solve and the
+    fiber sweeps' achieved bandwidth.  Algorithmic bytes per dof: z sweep 24
+    (read zR and B, write), inner half-step 1 16, half-step 2 24."""
+    import numpy as np
+    F_host = workloads.cube_rhs(n)
+    F = torch.from_numpy(F_host).cuda()
+    p = fps.plan(n, tol=tol, dim=3)
+    counts = p.inner_counts()
+    ws = fps.workspace(p, "cuda")
+    U = torch.empty(p.out_shape(), dtype=torch.float64, device="cuda")
+    fps.solve(p, F, out=U, ws=ws)
+    torch.cuda.synchronize()
+    per_solve = sum(1 + 2 * c for c in counts)
+    p.set_sweep_timing(per_solve * steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fps.solve(p, F, out=U, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    t = p.sweep_time()
+    p.set_sweep_timing(0)
+    kinds = []
+    for _ in range(steps):
+        for c in counts:
+            kinds.append("z")
+            kinds.extend(["hs1", "hs2"] * c)
+    dof = float(n) ** 3
+    bpd = {"z": 24.0, "hs1": 16.0, "hs2": 24.0}
+    tot_b = sum(bpd[k] * dof for k in kinds[:len(t)])
+    tot_t = sum(t) * 1e-3
+    res = {"n": n, "dof": dof, "ms_per_solve": ms, "dof_per_s": dof / (ms * 1e-3),
+           "J_outer": p.J, "inner_steps": sum(counts), "sweeps_per_solve": per_solve,
+           "sweep_achieved_GBs": round(tot_b / tot_t / 1e9, 1),
+           "sweep_frac_of_8TBs": round(tot_b / tot_t / 8e12, 4),
+           "sweep_share_of_solve": round(sum(t) / (ms * steps), 4)}
+    for k in ("z", "hs1", "hs2"):
+        tk = [x for x, kk in zip(t, kinds) if kk == k]
+        if tk:
+            avg = sum(tk) / len(tk) * 1e-3
+            res[f"avg_us_{k}"] = round(avg * 1e6, 2)
+            res[f"GBs_{k}"] = round(bpd[k] * dof / avg / 1e9, 1)
+    if check:
+        from oracle import cube
+        Uo = cube.poisson_cube(F_host)
+        res["rel_frobenius_err_vs_oracle"] = float(
+            np.linalg.norm(U.cpu().numpy() - Uo) / np.linalg.norm(Uo))
+    del ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,7 +143,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the FP32-refined and batched timings")
+                    help="skip the FP32-refined, batched and cube timings")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -207,6 +262,7 @@ def main() -> int:
                                  "f32_steps_per_round": pr.f32_steps}
         del wsr
         forms["batched"] = bench_batch(fps, workloads, torch, args.tol)
+        forms["cube"] = bench_cube(fps, workloads, torch, args.tol, check=not args.no_check)
     if forms:
         out["forms"] = forms
 

@@ -96,8 +96,16 @@ fps_status fps_plan_info(const fps_plan *plan, int *J, int64_t *workspace_bytes,
  * for FPS_FP64).  Either pointer may be null. */
 fps_status fps_plan_refinement(const fps_plan *plan, int *rounds, int *f32_steps);
 
+/* Cube plans (dim = 3): the number of inner ADI steps of each of the J
+ * outer steps (the (x, y) half-step of outer step i runs counts[i] inner
+ * iterations on every z-slice).  Writes min(J, cap) entries; FPS_E_STATE for
+ * a square plan. */
+fps_status fps_plan_inner_counts(const fps_plan *plan, int *counts, int cap);
+
 /* Copy the plan's shifts p_0..p_{J-1} to host memory (q_j = -p_j for the
- * square, Sec. 3.3 P2 with B~ = -A~). */
+ * square, Sec. 3.3 P2 with B~ = -A~; for the cube, the outer shifts p_i in
+ * [-2/delta, -2] of the split of (5.2) into H = K_x + K_y and V = K_z,
+ * K = -A~^-1, whose partners q_i lie in [1, 1/delta]). */
 fps_status fps_plan_shifts(const fps_plan *plan, double *p_host);
 
 /*

@@ -52,6 +52,7 @@ def lib() -> ctypes.CDLL:
     L.fps_plan_shifts.argtypes = [vp, ctypes.POINTER(dbl)]
     L.fps_plan_refinement.argtypes = [vp, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int)]
+    L.fps_plan_inner_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
     L.fps_adi_shifts.argtypes = [dbl, dbl, dbl, dbl, dbl, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(dbl),
                                  ctypes.POINTER(dbl)]
@@ -76,6 +77,7 @@ def lib() -> ctypes.CDLL:
     L.fps_last_error.restype = ctypes.c_char_p
     L.fps_version.restype = ctypes.c_char_p
     for name in ("fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_plan_refinement",
+                 "fps_plan_inner_counts",
                  "fps_adi_shifts", "fps_solve", "fps_solve_adjoint", "fps_adi_native",
                  "fps_batch_create", "fps_batch_info", "fps_batch_solve"):
         getattr(L, name).restype = ctypes.c_int
@@ -128,6 +130,12 @@ class Plan:
         p = (ctypes.c_double * self.J)()
         _check(lib().fps_plan_shifts(self._h, p))
         return list(p)
+
+    def inner_counts(self):
+        """Cube plans: inner ADI steps per outer step."""
+        c = (ctypes.c_int * self.J)()
+        _check(lib().fps_plan_inner_counts(self._h, c, self.J))
+        return list(c)
 
     def set_sweep_timing(self, capacity: int):
         _check(lib().fps_plan_set_sweep_timing(self._h, capacity))

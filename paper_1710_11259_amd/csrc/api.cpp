@@ -66,6 +66,9 @@ fps_status run_adi(fps_plan *pl, const void *Gterm, const void *GTin, int g_f32,
 
   fps::SweepArgs A{};
   A.npad = L.npad;
+  A.ncols = L.npad;
+  A.ld = L.npad;
+  A.nbatch = 1;
   A.mp0 = L.mp[0];
   A.mp1 = L.mp[1];
   A.mstride = L.mstride;
@@ -94,7 +97,7 @@ fps_status run_adi(fps_plan *pl, const void *Gterm, const void *GTin, int g_f32,
     A.sigma = 2.0 * p[j];
     A.out = O0;
     A.out_f32 = f32(j);
-    A.final_mode = 0;
+    A.out_mode = 0;
     FPS_HIP(timed_sweep(pl, A, st));
     FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(j), ab, -A.sigma, L.npad, nc0, nc1, L.ncmax, st));
     fps::SweepArgs B = A;
@@ -110,7 +113,7 @@ fps_status run_adi(fps_plan *pl, const void *Gterm, const void *GTin, int g_f32,
     B.sigma = last ? 0.0 : p[j] + p[j + 1];
     B.out = O1;
     B.out_f32 = last ? 0 : f32(j + 1);
-    B.final_mode = last ? 1 : 0;
+    B.out_mode = last ? 1 : 0;
     FPS_HIP(timed_sweep(pl, B, st));
     FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(j), ab, last ? 1.0 : -B.sigma, L.npad, nc0, nc1,
                                L.ncmax, st));
@@ -292,7 +295,9 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   if (prec != FPS_FP64 && prec != FPS_FP32_REFINED) return fail(FPS_E_ARG, "bad precision");
   if (out_basis != FPS_OUT_CHEB && out_basis != FPS_OUT_NATIVE) return fail(FPS_E_ARG, "bad out_basis");
   if (flags & ~FPS_PLAN_HOST_ONLY) return fail(FPS_E_ARG, "unknown flags");
-  if (dim == 3) return fail(FPS_E_UNSUPPORTED, "cube solver not available in this build");
+  if (dim == 3 && prec != FPS_FP64)
+    return fail(FPS_E_UNSUPPORTED, "the cube solver runs in FP64 only");
+  if (dim == 3 && n > 1024) return fail(FPS_E_UNSUPPORTED, "cube solves are limited to n <= 1024");
 
   fps_plan *pl = new (std::nothrow) fps_plan();
   if (!pl) return fail(FPS_E_NOMEM, "plan allocation failed");
@@ -302,6 +307,17 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   pl->prec = prec;
   pl->out_basis = out_basis;
   pl->flags = flags;
+  if (dim == 3) {
+    fps_status s = cube_plan_build(pl);
+    if (s == FPS_OK && !(flags & FPS_PLAN_HOST_ONLY)) s = cube_plan_upload(pl);
+    if (s != FPS_OK) {
+      delete pl;
+      return s;
+    }
+    pl->on_device = !(flags & FPS_PLAN_HOST_ONLY);
+    *out = pl;
+    return FPS_OK;
+  }
   // Lemma B.1: sigma(A~) in [-1, -1/(30 n^4)]; sigma(B~) = sigma(-A~).
   const double delta = 1.0 / (30.0 * (double)n * (double)n * (double)n * (double)n);
   // FP32_REFINED: each refinement round runs an ADI to kInnerTol and the
@@ -421,6 +437,14 @@ fps_status fps_plan_refinement(const fps_plan *pl, int *rounds, int *f32_steps) 
   return FPS_OK;
 }
 
+fps_status fps_plan_inner_counts(const fps_plan *pl, int *counts, int cap) {
+  if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (pl->dim != 3) return fail(FPS_E_STATE, "inner counts exist for cube plans only");
+  if (!counts && cap > 0) return fail(FPS_E_ARG, "null output");
+  for (int i = 0; i < pl->shifts.J && i < cap; ++i) counts[i] = pl->inner_J[i];
+  return FPS_OK;
+}
+
 fps_status fps_plan_shifts(const fps_plan *pl, double *p) {
   if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
   if (!p) return fail(FPS_E_ARG, "null output");
@@ -434,6 +458,7 @@ fps_status fps_solve(fps_plan *pl, const double *F, double *U, void *ws, void *s
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   const fps::Layout &L = pl->L;
+  if (pl->dim == 3) return cube_solve(pl, F, U, w, st);
   if ((s = rhs_transform(pl, F, w, st)) != FPS_OK) return s;
   double *Y = nullptr;
   if ((s = solve_symmetric(pl, w, st, &Y)) != FPS_OK) return s;

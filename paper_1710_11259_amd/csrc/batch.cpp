@@ -119,6 +119,9 @@ fps_status build_descriptors(fps_batch *bt) {
     const std::vector<double> &p = pl->shifts.p;
     fps::SweepArgs A{};
     A.npad = L.npad;
+    A.ncols = L.npad;
+    A.ld = L.npad;
+    A.nbatch = 1;
     A.mp0 = L.mp[0];
     A.mp1 = L.mp[1];
     A.mstride = L.mstride;
@@ -156,7 +159,7 @@ fps_status build_descriptors(fps_batch *bt) {
       a2.sigma = last ? 0.0 : p[j] + p[j + 1];
       a2.out = off_ptr<void *>(O1);
       a2.out_f32 = last ? 0 : f32(j + 1);
-      a2.final_mode = last ? 1 : 0;
+      a2.out_mode = last ? 1 : 0;
       const size_t i1 = ((size_t)j * 2 + 0) * C + k, i2 = ((size_t)j * 2 + 1) * C + k;
       sw[i1] = fps::BatchSweep{a1, bt->sw_start[k], nbx_s};
       sw[i2] = fps::BatchSweep{a2, bt->sw_start[k], nbx_s};

@@ -108,7 +108,127 @@ __global__ void k_fill(double *__restrict__ dst, int64_t count, double v) {
   if (i < count) dst[i] = v;
 }
 
+// --- cube ----------------------------------------------------------------
+
+__device__ __forceinline__ int64_t pb_index(int64_t i, int64_t mb0) {
+  return (i & 1) * mb0 + (i >> 1);
+}
+
+// natural n^3 -> parity-blocked npad^3 (zero padding)
+__global__ void k_permute3_in(const double *__restrict__ src, double *__restrict__ dst, int64_t n,
+                              int64_t npad, int64_t mp0) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ry = blockIdx.y, rz = blockIdx.z;
+  if (q >= npad) return;
+  auto nat = [&](int64_t r) {
+    const int s = r >= mp0 ? 1 : 0;
+    return 2 * (r - (s ? mp0 : 0)) + s;
+  };
+  const int64_t ix = nat(q), iy = nat(ry), iz = nat(rz);
+  double v = 0.0;
+  if (ix < n && iy < n && iz < n) v = src[(iz * n + iy) * n + ix];
+  dst[(rz * npad + ry) * npad + q] = v;
+}
+
+// parity-blocked [.][.][ld] (parity-1 block at mb0 on every axis, row
+// length ld, plane ld * ld) -> natural N^3, times sinv_i sinv_j sinv_k when
+// sinv is non-null.
+__global__ void k_permute3_out(const double *__restrict__ src, double *__restrict__ dst, int64_t N,
+                               int64_t ld, int64_t mb0, const double *__restrict__ sinv) {
+  const int64_t ix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t iy = blockIdx.y, iz = blockIdx.z;
+  if (ix >= N) return;
+  double v = src[(pb_index(iz, mb0) * ld + pb_index(iy, mb0)) * ld + pb_index(ix, mb0)];
+  if (sinv) v *= sinv[iz] * sinv[iy] * sinv[ix];
+  dst[(iz * N + iy) * N + ix] = v;
+}
+
+// After a z-fiber sweep (chains = the npad^2 (y, x) columns, positions z):
+// R = x + chunk carries, written as R[z][y][x] and, per z-slice, R^T[z][x][y].
+__global__ __launch_bounds__(256) void k_cube_zfinal(const double *__restrict__ x,
+                                                     const double *__restrict__ ab,
+                                                     const double *__restrict__ tab,
+                                                     double *__restrict__ R,
+                                                     double *__restrict__ RT, int64_t npad,
+                                                     int64_t mp0, int64_t mstride,
+                                                     int64_t ncmax) {
+  __shared__ double tile[64][65];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t z = blockIdx.z;
+  const int64_t y0 = (int64_t)blockIdx.y * 64, x0 = (int64_t)blockIdx.x * 64;
+  const int s = z >= mp0 ? 1 : 0;
+  const int64_t k = z - (s ? mp0 : 0), c = k / kChunk;
+  const double *tp = tab + (int64_t)s * kNTab * mstride;
+  const double bf = tp[T_BF2 * mstride + k], bk = tp[T_BK2 * mstride + k];
+  const int64_t plane = npad * npad;
+  const double *e = ab + ((int64_t)s * ncmax + c) * plane * 2;
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t col = (y0 + rr) * npad + x0 + tx;
+    const double v = x[z * plane + col] + e[2 * col] * bf + e[2 * col + 1] * bk;
+    R[z * plane + col] = v;
+    tile[rr][tx] = v;
+  }
+  __syncthreads();
+  for (int rr = ty; rr < 64; rr += 4) RT[z * plane + (x0 + rr) * npad + y0 + tx] = tile[tx][rr];
+}
+
+// After the last inner sweep on every z-slice (chains = x columns, positions
+// y): Y = x + chunk carries; out = cy Y + cr R + cb B (R, B may be null when
+// their coefficient is 0).
+__global__ void k_cube_ifinal(const double *__restrict__ x, const double *__restrict__ ab,
+                              const double *__restrict__ tab, const double *__restrict__ R,
+                              const double *__restrict__ B, double *__restrict__ out, double cy,
+                              double cr, double cb, int64_t npad, int64_t mp0, int64_t mstride,
+                              int64_t ncmax) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t y = blockIdx.y, z = blockIdx.z;
+  if (q >= npad) return;
+  const int s = y >= mp0 ? 1 : 0;
+  const int64_t k = y - (s ? mp0 : 0), c = k / kChunk;
+  const double *tp = tab + (int64_t)s * kNTab * mstride;
+  const double *e = ab + z * (2 * ncmax * npad * 2) + (((int64_t)s * ncmax + c) * npad + q) * 2;
+  const int64_t i = (z * npad + y) * npad + q;
+  double v = cy * (x[i] + e[0] * tp[T_BF2 * mstride + k] + e[1] * tp[T_BK2 * mstride + k]);
+  if (R) v += cr * R[i];
+  if (B) v += cb * B[i];
+  out[i] = v;
+}
+
 }  // namespace
+
+hipError_t launch_permute3_in(const double *src, double *dst, int64_t n, int64_t npad, int64_t mp0,
+                              hipStream_t st) {
+  dim3 grid((unsigned)((npad + 255) / 256), (unsigned)npad, (unsigned)npad);
+  hipLaunchKernelGGL(k_permute3_in, grid, dim3(256), 0, st, src, dst, n, npad, mp0);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute3_out(const double *src, double *dst, int64_t N, int64_t ld, int64_t mb0,
+                               const double *sinv, hipStream_t st) {
+  dim3 grid((unsigned)((N + 255) / 256), (unsigned)N, (unsigned)N);
+  hipLaunchKernelGGL(k_permute3_out, grid, dim3(256), 0, st, src, dst, N, ld, mb0, sinv);
+  return hipGetLastError();
+}
+
+hipError_t launch_cube_zfinal(const double *x, const double *ab, const double *tab, double *R,
+                              double *RT, int64_t npad, int64_t mp0, int64_t mstride,
+                              int64_t ncmax, hipStream_t st) {
+  if (npad % 64 != 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(npad / 64), (unsigned)(npad / 64), (unsigned)npad);
+  hipLaunchKernelGGL(k_cube_zfinal, grid, dim3(256), 0, st, x, ab, tab, R, RT, npad, mp0, mstride,
+                     ncmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_cube_ifinal(const double *x, const double *ab, const double *tab,
+                              const double *R, const double *B, double *out, double cy, double cr,
+                              double cb, int64_t npad, int64_t mp0, int64_t mstride, int64_t ncmax,
+                              hipStream_t st) {
+  dim3 grid((unsigned)((npad + 255) / 256), (unsigned)npad, (unsigned)npad);
+  hipLaunchKernelGGL(k_cube_ifinal, grid, dim3(256), 0, st, x, ab, tab, R, B, out, cy, cr, cb,
+                     npad, mp0, mstride, ncmax);
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_finalize(const T *x, const double *ab, const double *tab, double *out, int mode,

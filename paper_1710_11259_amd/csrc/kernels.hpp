@@ -9,30 +9,44 @@
 
 namespace fps {
 
-// One ADI half-sweep over a parity-blocked npad x npad array whose chains
-// run down the storage rows (one chain per storage column).
-//   input  v = in_scale * in (+ carry correction of the producing pass)
-//   solve  x = (A~ + p I)^-1 r along each chain (per parity), r = v + sg * g
-//          (r = v when g is null)
-//   output out = v - sigma x   (stored transposed), or x itself (final,
-//          stored in place orientation).  Chunk-level carries are not applied
-//          by the producer: it leaves its chunk boundary values in `lv`;
+// One ADI half-sweep.  Chains run down the storage rows of a parity-blocked
+// array (npad rows = chain positions of both parities, row stride ld), one
+// chain per storage column (ncols of them); nbatch such arrays (e.g. the
+// z-slices of a cube) are swept together, batch b at offset b * bstride.
+//   input  v = in_scale * in + (carry correction of the producing pass)
+//   rhs    r = v + sg * g (g non-null, og == 0) or v; with `pre` non-null, r is
+//          first multiplied along the chain by the tridiagonal stencil with
+//          diagonal pre[row] and coupling pre[npad + row] (rows row, row + 1)
+//   solve  x = T^-1 r along each chain (per parity), T the pass's
+//          tridiagonal (tables)
+//   output out_mode 0: v + og * g - sigma x stored transposed (requires
+//          ncols == ld == npad; the next pass then solves along the other
+//          index); 1: x in place orientation; 2: v + og * g - sigma x in place
+//          orientation.  Chunk-level carries are not applied by the
+//          producer: it leaves its chunk boundary values in `lv`;
 //          launch_reduce turns them into carries, which the consumer (the
-//          next sweep, or launch_finalize after the last one) folds in.
+//          next sweep, or a finalize kernel) folds in.
+// A g array enters either the right-hand side (sg, og == 0) or, on stencil
+// passes only, the output base (og, sg == 0).
 struct SweepArgs {
-  const void *in;          // [npad*npad], storage type in_f32
+  const void *in;          // [npad rows][ld], storage type in_f32
   double in_scale;
-  const double *ab_prev;   // producer's chunk carries [2][ncmax][npad][2], or null
+  const double *ab_prev;   // producer's chunk carries [2][ncmax][npad][2] (producer chains = npad), or null
   const double *tab_prev;  // producer's per-position tables (its shift) [2][kNTab][mstride]
-  const void *g;           // [npad*npad] G term (same orientation as `in`) or nullptr
-  double sg;
+  const void *g;           // G term, same layout as `in`, or nullptr
+  double sg, og;
   const double *tab;       // this pass's tables [2][kNTab][mstride]
   const double *l1;        // this pass's segment-carry combinations [2][ncmax][kL1]
   double sigma;
-  void *out;               // [npad*npad], storage type out_f32
-  double *lv;              // chunk boundary values [ncmax][2][2][npad]
-  int final_mode;          // 1: out = x, not transposed
+  void *out;               // storage type out_f32
+  double *lv;              // chunk boundary values [ncmax][2][2][ncols]
+  const double *pre;       // stencil [2][npad] or nullptr (float64 storage only)
+  int out_mode;
   int64_t npad, mp0, mp1, mstride, ncmax;
+  int64_t ncols, ld;       // chains, row stride (elements)
+  int nbatch;              // arrays swept together (>= 1)
+  int64_t bstride;         // elements between arrays (in, g, out)
+  int64_t lvb, abb;        // doubles between the arrays' lv / ab_prev blocks
   int nc0, nc1;
   // Storage types (0: double, 1: float; arithmetic is double throughout).
   // Supported: without g, in/out = d/d, f/d, f/f; with g, in/g/out =
@@ -57,10 +71,12 @@ hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSw
                               const int *wg_prob, int nwg, char *base, hipStream_t st);
 
 // Chunk carries: for every chain, the forward and backward carry into each
-// chunk, scaled by `scale`, into ab [2][ncmax][npad][2] (comb: the carry
-// combinations of the producing pass's shift).
+// chunk, scaled by `scale`, into ab [2][ncmax][nchains][2] (comb: the carry
+// combinations of the producing pass's shift); nbatch blocks of lv / ab at
+// strides lvb / abb.
 hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
-                         int64_t npad, int nc0, int nc1, int64_t ncmax, hipStream_t st);
+                         int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
+                         int nbatch = 1, int64_t lvb = 0, int64_t abb = 0);
 
 // Batched launch_reduce: lv_off / ab_off are byte offsets from `base`; the
 // grid of one problem is (ceil(npad / 256), 2 ncmax), flattened as for
@@ -105,6 +121,26 @@ hipError_t launch_permute_out(const double *src, double *dst, int64_t n, int64_t
                               const double *sinv, hipStream_t st);
 
 hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st);
+
+// Cube (npad^3 arrays [z][y][x], every axis parity-blocked):
+// natural n^3 -> parity-blocked npad^3 (zero padding).
+hipError_t launch_permute3_in(const double *src, double *dst, int64_t n, int64_t npad, int64_t mp0,
+                              hipStream_t st);
+// parity-blocked (row length ld, parity-1 blocks at mb0 on every axis) ->
+// natural N^3, times sinv_i sinv_j sinv_k when sinv is non-null.
+hipError_t launch_permute3_out(const double *src, double *dst, int64_t N, int64_t ld, int64_t mb0,
+                               const double *sinv, hipStream_t st);
+// After a z-fiber sweep: R = x + chunk carries (ab over the npad^2 (y, x)
+// chains, tab of the sweep's shift), stored as R[z][y][x] and R^T[z][x][y].
+hipError_t launch_cube_zfinal(const double *x, const double *ab, const double *tab, double *R,
+                              double *RT, int64_t npad, int64_t mp0, int64_t mstride,
+                              int64_t ncmax, hipStream_t st);
+// After the last per-slice sweep (chains = x, positions = y, ab per slice):
+// out = cy (x + chunk carries) + cr R + cb B.
+hipError_t launch_cube_ifinal(const double *x, const double *ab, const double *tab,
+                              const double *R, const double *B, double *out, double cy, double cr,
+                              double cb, int64_t npad, int64_t mp0, int64_t mstride, int64_t ncmax,
+                              hipStream_t st);
 hipError_t launch_fill(double *dst, int64_t count, double v, hipStream_t st);
 
 // FP64 GEMM on MFMA, up to 4 independent problems per launch:

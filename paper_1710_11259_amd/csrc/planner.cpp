@@ -160,7 +160,14 @@ double atilde_off(int64_t i) {
 void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vector<double> &pos,
                         std::vector<double> &chunk, std::vector<double> &comb,
                         std::vector<double> &l1) {
-  const int J = (int)p.size();
+  build_sweep_tables_ab(L, std::vector<double>(p.size(), 1.0), p, pos, chunk, comb, l1);
+}
+
+void build_sweep_tables_ab(const Layout &L, const std::vector<double> &alpha,
+                           const std::vector<double> &beta0, std::vector<double> &pos,
+                           std::vector<double> &chunk, std::vector<double> &comb,
+                           std::vector<double> &l1) {
+  const int J = (int)alpha.size();
   const int64_t ms = L.mstride, nc = L.ncmax;
   pos.assign((size_t)J * 2 * kNTab * ms, 0.0);
   chunk.assign((size_t)J * 2 * kNCTab * nc, 0.0);
@@ -177,16 +184,18 @@ void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vect
       std::fill(ib.begin(), ib.end(), 0.0L);
       std::fill(u.begin(), u.end(), 0.0L);
       if (m == 0) continue;
-      // Thomas factors of (A~ + p_j I) restricted to parity s.
-      long double beta = (long double)atilde_diag(s) + p[j];
+      // Thomas factors of (alpha_j A~ + beta_j I) restricted to parity s.
+      const long double al = alpha[j], be = beta0[j];
+      long double beta = al * (long double)atilde_diag(s) + be;
       ib[0] = 1.0L / beta;
       for (int64_t k = 1; k < m; ++k) {
-        const long double e = atilde_off(2 * (k - 1) + s);
+        const long double e = al * (long double)atilde_off(2 * (k - 1) + s);
         l[k] = e * ib[k - 1];
-        beta = ((long double)atilde_diag(2 * k + s) + p[j]) - l[k] * e;
+        beta = (al * (long double)atilde_diag(2 * k + s) + be) - l[k] * e;
         ib[k] = 1.0L / beta;
       }
-      for (int64_t k = 0; k + 1 < m; ++k) u[k] = (long double)atilde_off(2 * k + s) * ib[k];
+      for (int64_t k = 0; k + 1 < m; ++k)
+        u[k] = al * (long double)atilde_off(2 * k + s) * ib[k];
       for (int64_t k = 0; k < ms; ++k) {
         T[T_L * ms + k] = (double)l[k];
         T[T_IB * ms + k] = (double)ib[k];

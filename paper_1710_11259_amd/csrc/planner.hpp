@@ -92,6 +92,12 @@ double atilde_off(int64_t i);
 void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vector<double> &pos,
                         std::vector<double> &chunk, std::vector<double> &comb,
                         std::vector<double> &l1);
+// The same tables for the matrices alpha_j A~ + beta_j I (one per entry of
+// alpha and beta); build_sweep_tables is the case alpha_j = 1, beta_j = p_j.
+void build_sweep_tables_ab(const Layout &L, const std::vector<double> &alpha,
+                           const std::vector<double> &beta, std::vector<double> &pos,
+                           std::vector<double> &chunk, std::vector<double> &comb,
+                           std::vector<double> &l1);
 
 // Conversion maps split by parity (row-major, float64):
 //   Rs[s]: m[s] x m[s], Rs[s][a][b] = R[2a+s][2b+s] / sqrt((2a+s+1)(2a+s+2)),

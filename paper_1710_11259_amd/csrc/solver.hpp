@@ -79,6 +79,21 @@ struct fps_plan {
   int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab = 0;
   int64_t off_X = 0;  // adjoint: the output cotangent in the parity-blocked layout
   int64_t off_R = 0;  // FP32_REFINED: the float residual and its transpose
+
+  // Cube (dim 3), two-level nested ADI: `shifts` holds the outer shifts
+  // (p in [-2/delta, -2], q in [1, 1/delta]); inner step (i, j) has shift
+  // inner_p[inner_off[i] + j]; sweep table id of the z pass of outer step i
+  // is i, of inner step (i, j) it is J + inner_off[i] + j.
+  std::vector<int> inner_J, inner_off;
+  std::vector<double> inner_p;
+  double cube_inner_tol = 0.0;
+  int64_t mqc[2] = {0, 0};  // compact output parity sizes (mo rounded up to even)
+  fps::detail::DeviceBuf d_pre;             // [2][npad]: A~ diagonal and coupling per row
+  fps::detail::DeviceBuf d_RbA[2], d_RbB[2];  // input map A~^-1 S^-1 R blocks and transposes
+  fps::detail::DeviceBuf d_gy_in, d_gy_out;   // mode-y GEMM tables (input / output map)
+  int gy_tiles[2] = {0, 0};
+  fps::detail::DeviceBuf d_gy_map_in, d_gy_map_out;
+  int64_t off_ZR = 0, off_RX = 0, off_RXT = 0;
   int64_t ws_bytes = 0;
 
   const double *tab_dev(int j) const {
@@ -122,6 +137,12 @@ int out_gemms(const fps_plan *pl, const double *Y, double *U, char *ws, fps::Gem
 fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hipStream_t st);
 // Y of A~ Y + Y A~ = G for G in the workspace (FP64 or refined).
 fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout);
+// Cube: host tables and workspace layout (after the common fields are set),
+// their upload, and the solve.
+fps_status cube_plan_build(fps_plan *pl);
+fps_status cube_plan_upload(fps_plan *pl);
+fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *ws, hipStream_t st);
+hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st);
 
 }  // namespace detail
 }  // namespace fps

@@ -33,9 +33,10 @@ __device__ __forceinline__ double ld_as_double(const T *p) {
 
 // LDS of one sweep workgroup (doubles).  The early region holds the
 // chunk's slice of the per-position tables, the producer's chunk carries of
-// this workgroup's rows, the segment-carry combinations and the segment
-// boundary values; it is dead before the staging tile of the transposed
-// store reuses the space.
+// this workgroup's rows, the segment-carry combinations, the segment
+// boundary values and (pre-multiplied passes) the stencil rows and the
+// segment end values of the right-hand side; it is dead before the staging
+// tile of the transposed store reuses the space.
 constexpr int kStage = kCols * (kSeg + 1);  // staging doubles per wavefront
 constexpr int kSweepLds = kWaves * kStage;
 constexpr int kTabSlots = 5;                // l, ib, u, F1, Bk1
@@ -44,7 +45,10 @@ constexpr int OFF_AB = OFF_TAB + kTabSlots * kChunk;
 constexpr int OFF_L1 = OFF_AB + 2 * kChunk;
 constexpr int OFF_SY = OFF_L1 + kL1;
 constexpr int OFF_SX = OFF_SY + kWaves * kCols;
-constexpr int OFF_END = OFF_SX + kWaves * kCols;
+constexpr int OFF_PRE = OFF_SX + kWaves * kCols;   // stencil diagonal, coupling [2][kChunk]
+constexpr int OFF_PF = OFF_PRE + 2 * kChunk;       // first rhs value of each segment
+constexpr int OFF_PL = OFF_PF + kWaves * kCols;    // last rhs value of each segment
+constexpr int OFF_END = OFF_PL + kWaves * kCols;
 static_assert(OFF_END <= kSweepLds, "LDS carve-out");
 constexpr int kThreads = kCols * kWaves;
 constexpr int kTabN = kTabSlots * kChunk;
@@ -52,18 +56,24 @@ constexpr int kTabLoads = (kTabN + kThreads - 1) / kThreads;
 static_assert(2 * kChunk <= kThreads && kL1 <= kThreads, "one carry / combination value per thread");
 static_assert(T_L == 0 && T_IB == 1 && T_U == 2 && T_F1 == 3 && T_BK1 == 4, "table slot order");
 
-// kWithG: the right-hand side is v + sg * g while the output is v - sigma x
-// (g is not carried into the output); otherwise the right-hand side is v.
-// v = in_scale * in + (chunk carries of the producing pass).
-// One workgroup of a sweep: chain block bx (64 storage columns) and chunk
-// row by (parity-0 chunks first).
-template <typename Tin, typename Tg, typename Tout, bool kWithG>
+// One workgroup of a sweep: chain block bx (64 chains) and chunk row by
+// (parity-0 chunks first).
+//   v   = in_scale * in + (chunk carries of the producing pass)
+//   rhs = v + sg * g (kG == 1) or v;  kPre: rhs <- P rhs with the
+//         tridiagonal stencil P (diagonal a.pre[r], coupling a.pre[npad + r]
+//         of rows r and r + 1) applied along the chain;
+//   x   = T^-1 rhs with T the pass's tridiagonal (tables);
+//   out = x (out_mode 1) or b - sigma x (out_mode 0, 2) with the output base
+//         b = v + og * g (kG == 2) or v.
+// kG selects how a g array enters: 0 none, 1 the right-hand side, 2 the
+// output base (the two are kept apart to keep register pressure low).
+template <typename Tin, typename Tg, typename Tout, int kG, bool kPre>
 __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, const int by,
                                             double *lds) {
   const int tid = threadIdx.x;
   const int lane = tid & (kCols - 1);
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t npad = a.npad, ms = a.mstride, ncmax = a.ncmax;
+  const int64_t npad = a.npad, ms = a.mstride, ncmax = a.ncmax, ld = a.ld, ncols = a.ncols;
   const int64_t col0 = (int64_t)bx * kCols;
   const int64_t col = col0 + lane;
   const int s = by < a.nc0 ? 0 : 1;
@@ -75,6 +85,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
   const int64_t rbase = (s ? a.mp0 : 0) + kc0;  // storage row of the chunk start
   const int64_t row0 = rbase + (int64_t)w * kSeg;
   const bool has_prev = a.tab_prev != nullptr;
+  const Tin *__restrict__ in = (const Tin *)a.in;
+  const Tg *__restrict__ gp = (const Tg *)a.g;
 
   // 1. Small loads, issued before the streaming loads and without divergent
   //    branches (addresses are clamped), so that waiting for them does not
@@ -98,23 +110,54 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
     bf = tp[T_BF2 * ms + kp];
     bk = tp[T_BK2 * ms + kp];
   }
+  // Pre-multiplied passes: the stencil rows of the chunk, and the
+  // right-hand side one row before and one row after the chunk (only when
+  // those rows belong to the same chain).
+  double prev_v = 0.0, prev_r = 0.0, next_r = 0.0, pe_before = 0.0;
+  const bool has_before = kPre && kc0 > 0;
+  const bool has_after = kPre && kc0 + kChunk < mps;
+  double prv = 0.0;
+  if constexpr (kPre) {
+    const int e2 = tid < 2 * kChunk ? tid : 2 * kChunk - 1;
+    prv = a.pre[(e2 / kChunk) * npad + rbase + (e2 % kChunk)];
+    if (has_before) pe_before = a.pre[npad + rbase - 1];
+    if (w == 0 && has_before) {
+      const int64_t r = rbase - 1;
+      double e0 = 0.0, e1 = 0.0;
+      if (has_prev) {
+        const double *q = a.ab_prev + (((int64_t)sp * ncmax + cp) * npad + r) * 2;
+        e0 = q[0];
+        e1 = q[1];
+      }
+      prev_v = a.in_scale * ld_as_double(in + r * ld + col) + e0 * bf + e1 * bk;
+      prev_r = prev_v;
+      if constexpr (kG == 1) prev_r += a.sg * ld_as_double(gp + r * ld + col);
+    }
+    if (w == kWaves - 1 && has_after) {
+      const int64_t r = rbase + kChunk;
+      double e0 = 0.0, e1 = 0.0;
+      if (has_prev) {
+        const double *q = a.ab_prev + (((int64_t)sp * ncmax + cp) * npad + r) * 2;
+        e0 = q[0];
+        e1 = q[1];
+      }
+      next_r = a.in_scale * ld_as_double(in + r * ld + col) + e0 * bf + e1 * bk;
+      if constexpr (kG == 1) next_r += a.sg * ld_as_double(gp + r * ld + col);
+    }
+  }
 
   // 2. Streaming loads (rows clamped for the idle segments past the chain end).
   double v[kSeg], y[kSeg];
-  {
-    const Tin *__restrict__ in = (const Tin *)a.in;
 #pragma unroll
-    for (int i = 0; i < kSeg; ++i) {
-      const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
-      v[i] = ld_as_double(in + r * npad + col);
-    }
+  for (int i = 0; i < kSeg; ++i) {
+    const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
+    v[i] = ld_as_double(in + r * ld + col);
   }
-  if constexpr (kWithG) {
-    const Tg *__restrict__ gp = (const Tg *)a.g;
+  if constexpr (kG != 0) {
 #pragma unroll
     for (int i = 0; i < kSeg; ++i) {
       const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
-      y[i] = ld_as_double(gp + r * npad + col);
+      y[i] = ld_as_double(gp + r * ld + col);
     }
   }
 
@@ -123,6 +166,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
     if (tid + q * kThreads < kTabN) lds[OFF_TAB + tid + q * kThreads] = tv[q];
   if (tid < kL1) lds[OFF_L1 + tid] = l1v;
   if (tid < 2 * kChunk) lds[OFF_AB + tid] = abv;
+  if constexpr (kPre) {
+    if (tid < 2 * kChunk) lds[OFF_PRE + tid] = prv;
+  }
   __syncthreads();
 
   const double *Tl = lds + OFF_TAB + 0 * kChunk + w * kSeg;
@@ -132,17 +178,41 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
   const double *Tbk1 = lds + OFF_TAB + 4 * kChunk + w * kSeg;
   const double *Ab = lds + OFF_AB + 2 * w * kSeg;
 
-  // 3. Right-hand side.  Idle segments carry exact zeros.
+  // 3. Right-hand side and output base.  Idle segments carry exact zeros.
   const double act = active ? 1.0 : 0.0;
   const double isc = act * a.in_scale;
   const double cA = has_prev ? act * bf : 0.0, cB = has_prev ? act * bk : 0.0;
 #pragma unroll
   for (int i = 0; i < kSeg; ++i) {
     v[i] = isc * v[i] + Ab[2 * i] * cA + Ab[2 * i + 1] * cB;
-    if constexpr (kWithG)
+    if constexpr (kG == 1) {
       y[i] = v[i] + (act * a.sg) * y[i];
-    else
+    } else if constexpr (kG == 2) {
+      const double gi = y[i];
       y[i] = v[i];
+      v[i] += (act * a.og) * gi;
+    } else {
+      y[i] = v[i];
+    }
+  }
+  if constexpr (kPre) {
+    lds[OFF_PF + w * kCols + lane] = y[0];
+    lds[OFF_PL + w * kCols + lane] = y[kSeg - 1];
+    __syncthreads();
+    const double ym = w > 0 ? lds[OFF_PL + (w - 1) * kCols + lane] : prev_r;
+    const double yp = w < kWaves - 1 ? lds[OFF_PF + (w + 1) * kCols + lane] : next_r;
+    const double *Pd = lds + OFF_PRE + w * kSeg;
+    const double *Pe = lds + OFF_PRE + kChunk + w * kSeg;
+    const double pem = w > 0 ? lds[OFF_PRE + kChunk + w * kSeg - 1] : pe_before;
+    double t[kSeg];
+#pragma unroll
+    for (int i = 0; i < kSeg; ++i) {
+      const double lo = i > 0 ? Pe[i - 1] * y[i - 1] : pem * ym;
+      const double hi = i < kSeg - 1 ? Pe[i] * y[i + 1] : Pe[kSeg - 1] * yp;
+      t[i] = Pd[i] * y[i] + lo + hi;
+    }
+#pragma unroll
+    for (int i = 0; i < kSeg; ++i) y[i] = act * t[i];
   }
 
   // 4. Forward elimination with zero carry-in, then the segment carry.
@@ -165,19 +235,22 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
   const double ylast_chunk = y[kSeg - 1];
 
   // 5. Backward substitution with zero carry-in, fused with the output.
-  //    Without a g term the right-hand side is recovered from the forward
-  //    values, r_k = y_k + l_k y_{k-1} (y_{-1} = cf1), so v need not live on.
+  //    Without a g term or stencil the right-hand side is recovered from the
+  //    forward values, r_k = y_k + l_k y_{k-1} (y_{-1} = cf1), so v need not
+  //    live on.
+  constexpr bool kKeepV = kG != 0 || kPre;
   const double sigma = a.sigma;
+  const bool out_x = a.out_mode == 1;
   double xnext = 0.0, xfirst = 0.0;
 #pragma unroll
   for (int i = kSeg - 1; i >= 0; --i) {
     const double x = y[i] * Tib[i] - Tu[i] * xnext;
     double rhs;
-    if constexpr (kWithG)
+    if constexpr (kKeepV)
       rhs = v[i];
     else
       rhs = y[i] + Tl[i] * (i > 0 ? y[i - 1] : cf1);
-    y[i] = a.final_mode ? x : rhs - sigma * x;
+    y[i] = out_x ? x : rhs - sigma * x;
     xnext = x;
     if (i == 0) xfirst = x;
   }
@@ -187,24 +260,24 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
 #pragma unroll
   for (int u = 0; u < kWaves; ++u)
     cb1 += lds[OFF_L1 + (1 * kWaves + w) * kWaves + u] * lds[OFF_SX + u * kCols + lane];
-  const double coef = (a.final_mode ? 1.0 : -sigma) * cb1;
+  const double coef = (out_x ? 1.0 : -sigma) * cb1;
 #pragma unroll
   for (int i = 0; i < kSeg; ++i) y[i] += coef * Tbk1[i];
 
   // 6. Chunk boundary values for the chunk carries.
-  if (w == kWaves - 1) a.lv[(((int64_t)c * 2 + s) * 2 + 0) * npad + col] = ylast_chunk;
-  if (w == 0) a.lv[(((int64_t)c * 2 + s) * 2 + 1) * npad + col] = xfirst + Tbk1[0] * cb1;
+  if (w == kWaves - 1) a.lv[(((int64_t)c * 2 + s) * 2 + 0) * ncols + col] = ylast_chunk;
+  if (w == 0) a.lv[(((int64_t)c * 2 + s) * 2 + 1) * ncols + col] = xfirst + Tbk1[0] * cb1;
 
   Tout *__restrict__ out = (Tout *)a.out;
-  if (a.final_mode) {
+  if (a.out_mode != 0) {
     if (active) {
 #pragma unroll
-      for (int i = 0; i < kSeg; ++i) out[(row0 + i) * npad + col] = (Tout)y[i];
+      for (int i = 0; i < kSeg; ++i) out[(row0 + i) * ld + col] = (Tout)y[i];
     }
     return;
   }
   // 7. Transposed store staged through LDS: output row col0 + j receives this
-  //    segment's kSeg positions as one contiguous 128-byte run.
+  //    segment's kSeg positions as one contiguous run.
   double *stage = lds + w * kStage;
   __syncthreads();  // the early region is dead
 #pragma unroll
@@ -219,22 +292,30 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
       const int ocol = 2 * (lane % kLanesPerRow);
       const double v0 = stage[orow * (kSeg + 1) + ocol];
       const double v1 = stage[orow * (kSeg + 1) + ocol + 1];
-      Tout *dst = out + (col0 + orow) * npad + row0 + ocol;
+      Tout *dst = out + (col0 + orow) * ld + row0 + ocol;
       dst[0] = (Tout)v0;
       dst[1] = (Tout)v1;
     }
   }
 }
 
-template <typename Tin, typename Tg, typename Tout, bool kWithG>
+template <typename Tin, typename Tg, typename Tout, int kG, bool kPre>
 __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
   __shared__ double lds[kSweepLds];
-  sweep_block<Tin, Tg, Tout, kWithG>(a, blockIdx.x, blockIdx.y, lds);
+  if (blockIdx.z != 0) {
+    const int64_t z = blockIdx.z;
+    a.in = (const Tin *)a.in + z * a.bstride;
+    if (kG != 0) a.g = (const Tg *)a.g + z * a.bstride;
+    a.out = (Tout *)a.out + z * a.bstride;
+    a.lv += z * a.lvb;
+    if (a.tab_prev != nullptr) a.ab_prev += z * a.abb;
+  }
+  sweep_block<Tin, Tg, Tout, kG, kPre>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 // Batched sweep: workgroup g belongs to problem wg_prob[g]; the problem's
 // descriptor holds workspace offsets in place of its workspace pointers.
-template <typename Tin, typename Tg, typename Tout, bool kWithG>
+template <typename Tin, typename Tg, typename Tout, int kG>
 __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep_batch(const BatchSweep *__restrict__ d,
                                                                   const int *__restrict__ wg_prob,
                                                                   char *base) {
@@ -243,12 +324,12 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep_batch(const BatchSwe
   const BatchSweep &e = d[k];
   SweepArgs a = e.a;
   a.in = base + (intptr_t)a.in;
-  if (kWithG) a.g = base + (intptr_t)a.g;
+  if (kG != 0) a.g = base + (intptr_t)a.g;
   a.out = base + (intptr_t)a.out;
   a.lv = (double *)(base + (intptr_t)a.lv);
   if (a.tab_prev != nullptr) a.ab_prev = (const double *)(base + (intptr_t)a.ab_prev);
   const int local = (int)blockIdx.x - e.wg_start;
-  sweep_block<Tin, Tg, Tout, kWithG>(a, local % e.nbx, local / e.nbx, lds);
+  sweep_block<Tin, Tg, Tout, kG, false>(a, local % e.nbx, local / e.nbx, lds);
 }
 
 // Chunk carries of one half-sweep: thread (parity s, chunk c, chain r)
@@ -260,6 +341,7 @@ __device__ __forceinline__ void reduce_block(const double *__restrict__ lv,
                                              double *__restrict__ ab, double scale, int64_t npad,
                                              int nc0, int nc1, int64_t ncmax, int bx, int by,
                                              double *wrow /* [nc][kNComb], LDS */) {
+  // npad here is the number of chains (the lv / ab row length).
   const int64_t r = (int64_t)bx * blockDim.x + threadIdx.x;
   const int s = by >= ncmax ? 1 : 0;
   const int c = by - (s ? (int)ncmax : 0);
@@ -286,9 +368,12 @@ __device__ __forceinline__ void reduce_block(const double *__restrict__ lv,
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ lv,
                                                 const double *__restrict__ comb,
                                                 double *__restrict__ ab, double scale,
-                                                int64_t npad, int nc0, int nc1, int64_t ncmax) {
+                                                int64_t nchains, int nc0, int nc1, int64_t ncmax,
+                                                int64_t lvb, int64_t abb) {
   extern __shared__ double wrow[];
-  reduce_block(lv, comb, ab, scale, npad, nc0, nc1, ncmax, blockIdx.x, blockIdx.y, wrow);
+  const int64_t z = blockIdx.z;
+  reduce_block(lv + z * lvb, comb, ab + z * abb, scale, nchains, nc0, nc1, ncmax, blockIdx.x,
+               blockIdx.y, wrow);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_batch(const BatchReduce *__restrict__ d,
@@ -312,13 +397,14 @@ struct SweepLaunch {
   char *base;
   int nwg;
   hipStream_t st;
-  template <typename Tin, typename Tg, typename Tout, bool kWithG>
+  template <typename Tin, typename Tg, typename Tout, int kG, bool kPre = false>
   void go() const {
     if (d == nullptr) {
-      dim3 grid((unsigned)(a.npad / kCols), (unsigned)(a.nc0 + a.nc1));
-      hipLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kWithG>), grid, dim3(kCols * kWaves), 0, st, a);
-    } else {
-      hipLaunchKernelGGL((k_sweep_batch<Tin, Tg, Tout, kWithG>), dim3((unsigned)nwg),
+      dim3 grid((unsigned)(a.ncols / kCols), (unsigned)(a.nc0 + a.nc1),
+                (unsigned)(a.nbatch > 0 ? a.nbatch : 1));
+      hipLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kG, kPre>), grid, dim3(kCols * kWaves), 0, st, a);
+    } else if constexpr (!kPre) {
+      hipLaunchKernelGGL((k_sweep_batch<Tin, Tg, Tout, kG>), dim3((unsigned)nwg),
                          dim3(kCols * kWaves), 0, st, d, wg_prob, base);
     }
   }
@@ -327,19 +413,33 @@ struct SweepLaunch {
 hipError_t dispatch_sweep(const SweepLaunch &L, bool with_g) {
   const SweepArgs &a = L.a;
   const int code = (a.in_f32 ? 4 : 0) | (a.g_f32 ? 2 : 0) | (a.out_f32 ? 1 : 0);
+  if (with_g && a.og != 0.0 && a.sg != 0.0) return hipErrorInvalidValue;
+  const bool g_out = with_g && a.og != 0.0;
+  if (a.pre != nullptr) {
+    // stencil passes: float64 storage only, single launches only
+    if (code != 0 || L.d != nullptr) return hipErrorInvalidValue;
+    if (!with_g)
+      L.go<double, double, double, 0, true>();
+    else if (g_out)
+      L.go<double, double, double, 2, true>();
+    else
+      L.go<double, double, double, 1, true>();
+    return hipGetLastError();
+  }
+  if (g_out) return hipErrorInvalidValue;  // g in the output base: stencil passes only
   if (!with_g) {
     switch (code & 5) {
-      case 0: L.go<double, double, double, false>(); break;
-      case 4: L.go<float, double, double, false>(); break;
-      case 5: L.go<float, double, float, false>(); break;
+      case 0: L.go<double, double, double, 0>(); break;
+      case 4: L.go<float, double, double, 0>(); break;
+      case 5: L.go<float, double, float, 0>(); break;
       default: return hipErrorInvalidValue;  // a float output from a double input
     }
   } else {
     switch (code) {
-      case 0: L.go<double, double, double, true>(); break;
-      case 2: L.go<double, float, double, true>(); break;
-      case 6: L.go<float, float, double, true>(); break;
-      case 7: L.go<float, float, float, true>(); break;
+      case 0: L.go<double, double, double, 1>(); break;
+      case 2: L.go<double, float, double, 1>(); break;
+      case 6: L.go<float, float, double, 1>(); break;
+      case 7: L.go<float, float, float, 1>(); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -348,8 +448,11 @@ hipError_t dispatch_sweep(const SweepLaunch &L, bool with_g) {
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
   const int nchunks = a.nc0 + a.nc1;
-  if (a.npad % kCols != 0 || nchunks <= 0 || a.in == nullptr) return hipErrorInvalidValue;
+  if (a.npad % kCols != 0 || a.ncols % kCols != 0 || nchunks <= 0 || a.in == nullptr)
+    return hipErrorInvalidValue;
   if ((a.ab_prev == nullptr) != (a.tab_prev == nullptr)) return hipErrorInvalidValue;
+  if (a.out_mode == 0 && (a.ncols != a.npad || a.ld != a.npad)) return hipErrorInvalidValue;
+  if (a.ld < a.ncols) return hipErrorInvalidValue;
   return dispatch_sweep(SweepLaunch{a, nullptr, nullptr, nullptr, 0, st}, a.g != nullptr);
 }
 
@@ -360,11 +463,14 @@ hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSw
 }
 
 hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
-                         int64_t npad, int nc0, int nc1, int64_t ncmax, hipStream_t st) {
-  dim3 grid((unsigned)((npad + 255) / 256), (unsigned)(2 * ncmax));
+                         int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
+                         int nbatch, int64_t lvb, int64_t abb) {
+  dim3 grid((unsigned)((nchains + 255) / 256), (unsigned)(2 * ncmax),
+            (unsigned)(nbatch > 0 ? nbatch : 1));
   const size_t shm = (size_t)ncmax * kNComb * sizeof(double);
   if (shm > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce, grid, dim3(256), shm, st, lv, comb, ab, scale, npad, nc0, nc1, ncmax);
+  hipLaunchKernelGGL(k_reduce, grid, dim3(256), shm, st, lv, comb, ab, scale, nchains, nc0, nc1,
+                     ncmax, lvb, abb);
   return hipGetLastError();
 }
 

@@ -99,6 +99,26 @@ def test_refinement_structure(n):
     assert r.workspace_bytes > d.workspace_bytes
 
 
+@pytest.mark.parametrize("n", [1, 16, 256])
+def test_cube_plan_outer_shifts_match_oracle(n):
+    from oracle import cube
+    p = fps.plan(n, tol=1e-13, dim=3, host_only=True)
+    J, po, _ = cube.kform_outer_shifts(n, 1e-13)
+    assert p.J == J
+    np.testing.assert_allclose(p.shifts(), po, rtol=1e-12)
+    assert p.out_entries == (n + 2) ** 3
+    assert fps.plan(n, dim=3, out="native", host_only=True).out_entries == n ** 3
+    # inner counts: (2.9) for the symmetric inner intervals at tol / 10
+    q = cube.kform_outer_shifts(n, 1e-13)[2]
+    want = [cube.kform_inner_shifts(n, qi, 1e-14)[0] for qi in q]
+    assert p.inner_counts() == want
+
+
+def test_cube_plan_rejects_refined():
+    with pytest.raises(fps.FpsError):
+        fps.plan(8, dim=3, precision="fp32_refined", host_only=True)
+
+
 def test_batch_queries_and_errors():
     ns = [32, 64, 544, 32, 1, 129]
     b = fps.batch(ns, host_only=True)
