@@ -35,10 +35,9 @@ __device__ __forceinline__ double ld_as_double(const T *p) {
 // chunk's slice of the per-position tables, the producer's chunk carries of
 // this workgroup's rows, the segment-carry combinations, the segment
 // boundary values and (pre-multiplied passes) the stencil rows and the
-// segment end values of the right-hand side; it is dead before the staging
-// tile of the transposed store reuses the space.
-constexpr int kStage = kCols * (kSeg + 1);  // staging doubles per wavefront
-constexpr int kSweepLds = kWaves * kStage;
+// segment end values of the right-hand side; it is dead before the tile of
+// the transposed store reuses the space.
+constexpr int kSweepLds = kWaves * kCols * (kSeg + 1);  // also holds the 64 x 65 store tile
 constexpr int kTabSlots = 5;                // l, ib, u, F1, Bk1
 constexpr int OFF_TAB = 0;
 constexpr int OFF_AB = OFF_TAB + kTabSlots * kChunk;
@@ -56,8 +55,8 @@ constexpr int kTabLoads = (kTabN + kThreads - 1) / kThreads;
 static_assert(2 * kChunk <= kThreads && kL1 <= kThreads, "one carry / combination value per thread");
 static_assert(T_L == 0 && T_IB == 1 && T_U == 2 && T_F1 == 3 && T_BK1 == 4, "table slot order");
 
-// One workgroup of a sweep: chain block bx (64 chains) and chunk row by
-// (parity-0 chunks first).
+// One workgroup unit of a sweep: chain block bx (64 chains) and chunk row
+// by (parity-0 chunks first).
 //   v   = in_scale * in + (chunk carries of the producing pass)
 //   rhs = v + sg * g (kG == 1) or v;  kPre: rhs <- P rhs with the
 //         tridiagonal stencil P (diagonal a.pre[r], coupling a.pre[npad + r]
@@ -67,107 +66,142 @@ static_assert(T_L == 0 && T_IB == 1 && T_U == 2 && T_F1 == 3 && T_BK1 == 4, "tab
 //         b = v + og * g (kG == 2) or v.
 // kG selects how a g array enters: 0 none, 1 the right-hand side, 2 the
 // output base (the two are kept apart to keep register pressure low).
-template <typename Tin, typename Tg, typename Tout, int kG, bool kPre>
-__device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, const int by,
-                                            double *lds) {
-  const int tid = threadIdx.x;
-  const int lane = tid & (kCols - 1);
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t npad = a.npad, ms = a.mstride, ncmax = a.ncmax, ld = a.ld, ncols = a.ncols;
-  const int64_t col0 = (int64_t)bx * kCols;
-  const int64_t col = col0 + lane;
-  const int s = by < a.nc0 ? 0 : 1;
-  const int c = by - (s ? a.nc0 : 0);
-  const int64_t mps = s ? a.mp1 : a.mp0;
-  const int64_t kc0 = (int64_t)c * kChunk;     // first chain position of the chunk
-  const int64_t k0 = kc0 + (int64_t)w * kSeg;   // first position of this segment
-  const bool active = k0 < mps;
-  const int64_t rbase = (s ? a.mp0 : 0) + kc0;  // storage row of the chunk start
-  const int64_t row0 = rbase + (int64_t)w * kSeg;
-  const bool has_prev = a.tab_prev != nullptr;
-  const Tin *__restrict__ in = (const Tin *)a.in;
-  const Tg *__restrict__ gp = (const Tg *)a.g;
 
-  // 1. Small loads, issued before the streaming loads and without divergent
-  //    branches (addresses are clamped), so that waiting for them does not
-  //    wait for the streaming loads.
-  const double *__restrict__ tab = a.tab + (int64_t)s * kNTab * ms + kc0;
-  double tv[kTabLoads];
-#pragma unroll
-  for (int q = 0; q < kTabLoads; ++q) {
-    const int e = tid + q * kThreads < kTabN ? tid + q * kThreads : kTabN - 1;
-    tv[q] = tab[(e / kChunk) * ms + (e % kChunk)];
+// Geometry of the unit at chunk row `by` for wavefront w.
+struct Unit {
+  int s, c;
+  int64_t mps, kc0, rbase, row0;
+  bool active;
+};
+
+__device__ __forceinline__ Unit unit_of(const SweepArgs &a, int by, int w) {
+  Unit u;
+  u.s = by < a.nc0 ? 0 : 1;
+  u.c = by - (u.s ? a.nc0 : 0);
+  u.mps = u.s ? a.mp1 : a.mp0;
+  u.kc0 = (int64_t)u.c * kChunk;
+  u.active = u.kc0 + (int64_t)w * kSeg < u.mps;
+  u.rbase = (u.s ? a.mp0 : 0) + u.kc0;
+  u.row0 = u.rbase + (int64_t)w * kSeg;
+  return u;
+}
+
+// Values of the chain block that do not depend on the chunk row: the
+// producer's chunk index of these chains (as positions of its chains) and
+// its carry vectors at those positions.
+struct Cols {
+  int64_t col0, col, cp;
+  int sp;
+  double bf, bk;
+};
+
+__device__ __forceinline__ Cols cols_of(const SweepArgs &a, int bx, int lane) {
+  Cols q;
+  q.col0 = (int64_t)bx * kCols;
+  q.col = q.col0 + lane;
+  q.sp = q.col0 >= a.mp0 ? 1 : 0;
+  q.cp = (q.col0 - (q.sp ? a.mp0 : 0)) / kChunk;
+  q.bf = q.bk = 0.0;
+  if (a.tab_prev != nullptr) {
+    const int64_t kp = q.col - (q.sp ? a.mp0 : 0);
+    const double *tp = a.tab_prev + (int64_t)q.sp * kNTab * a.mstride;
+    q.bf = tp[T_BF2 * a.mstride + kp];
+    q.bk = tp[T_BK2 * a.mstride + kp];
   }
-  const double l1v = a.l1[((int64_t)s * ncmax + c) * kL1 + (tid < kL1 ? tid : kL1 - 1)];
-  const int sp = col0 >= a.mp0 ? 1 : 0;
-  const int64_t cp = (col0 - (sp ? a.mp0 : 0)) / kChunk;
-  double abv = 0.0, bf = 0.0, bk = 0.0;
+  return q;
+}
+
+// Per-unit small values, loaded before the unit's streaming loads without
+// divergent branches (addresses are clamped), so that waiting for them does
+// not wait for the streaming loads.
+struct Small {
+  double tv[kTabLoads];
+  double l1v, abv, prv, prev_r, next_r, pe_before;
+};
+
+template <typename Tin, typename Tg, int kG, bool kPre>
+__device__ __forceinline__ void load_small(const SweepArgs &a, const Unit &u, const Cols &q,
+                                           int tid, int w, Small &m) {
+  const int64_t npad = a.npad, ms = a.mstride, ncmax = a.ncmax, ld = a.ld;
+  const double *__restrict__ tab = a.tab + (int64_t)u.s * kNTab * ms + u.kc0;
+#pragma unroll
+  for (int k = 0; k < kTabLoads; ++k) {
+    const int e = tid + k * kThreads < kTabN ? tid + k * kThreads : kTabN - 1;
+    m.tv[k] = tab[(e / kChunk) * ms + (e % kChunk)];
+  }
+  m.l1v = a.l1[((int64_t)u.s * ncmax + u.c) * kL1 + (tid < kL1 ? tid : kL1 - 1)];
+  m.abv = 0.0;
+  const bool has_prev = a.tab_prev != nullptr;
   if (has_prev) {
     const int e2 = tid < 2 * kChunk ? tid : 2 * kChunk - 1;
-    abv = a.ab_prev[(((int64_t)sp * ncmax + cp) * npad + rbase) * 2 + e2];
-    const int64_t kp = col - (sp ? a.mp0 : 0);
-    const double *tp = a.tab_prev + (int64_t)sp * kNTab * ms;
-    bf = tp[T_BF2 * ms + kp];
-    bk = tp[T_BK2 * ms + kp];
+    m.abv = a.ab_prev[(((int64_t)q.sp * ncmax + q.cp) * npad + u.rbase) * 2 + e2];
   }
-  // Pre-multiplied passes: the stencil rows of the chunk, and the
-  // right-hand side one row before and one row after the chunk (only when
-  // those rows belong to the same chain).
-  double prev_v = 0.0, prev_r = 0.0, next_r = 0.0, pe_before = 0.0;
-  const bool has_before = kPre && kc0 > 0;
-  const bool has_after = kPre && kc0 + kChunk < mps;
-  double prv = 0.0;
+  m.prv = m.prev_r = m.next_r = m.pe_before = 0.0;
   if constexpr (kPre) {
+    // The stencil rows of the chunk, and the right-hand side one row before
+    // and one row after the chunk when those rows belong to the same chain.
+    const Tin *__restrict__ in = (const Tin *)a.in;
+    const Tg *__restrict__ gp = (const Tg *)a.g;
+    const bool has_before = u.kc0 > 0, has_after = u.kc0 + kChunk < u.mps;
     const int e2 = tid < 2 * kChunk ? tid : 2 * kChunk - 1;
-    prv = a.pre[(e2 / kChunk) * npad + rbase + (e2 % kChunk)];
-    if (has_before) pe_before = a.pre[npad + rbase - 1];
-    if (w == 0 && has_before) {
-      const int64_t r = rbase - 1;
+    m.prv = a.pre[(e2 / kChunk) * npad + u.rbase + (e2 % kChunk)];
+    if (has_before) m.pe_before = a.pre[npad + u.rbase - 1];
+    if ((w == 0 && has_before) || (w == kWaves - 1 && has_after)) {
+      const int64_t r = w == 0 ? u.rbase - 1 : u.rbase + kChunk;
       double e0 = 0.0, e1 = 0.0;
       if (has_prev) {
-        const double *q = a.ab_prev + (((int64_t)sp * ncmax + cp) * npad + r) * 2;
-        e0 = q[0];
-        e1 = q[1];
+        const double *ep = a.ab_prev + (((int64_t)q.sp * ncmax + q.cp) * npad + r) * 2;
+        e0 = ep[0];
+        e1 = ep[1];
       }
-      prev_v = a.in_scale * ld_as_double(in + r * ld + col) + e0 * bf + e1 * bk;
-      prev_r = prev_v;
-      if constexpr (kG == 1) prev_r += a.sg * ld_as_double(gp + r * ld + col);
-    }
-    if (w == kWaves - 1 && has_after) {
-      const int64_t r = rbase + kChunk;
-      double e0 = 0.0, e1 = 0.0;
-      if (has_prev) {
-        const double *q = a.ab_prev + (((int64_t)sp * ncmax + cp) * npad + r) * 2;
-        e0 = q[0];
-        e1 = q[1];
-      }
-      next_r = a.in_scale * ld_as_double(in + r * ld + col) + e0 * bf + e1 * bk;
-      if constexpr (kG == 1) next_r += a.sg * ld_as_double(gp + r * ld + col);
+      double vr = a.in_scale * ld_as_double(in + r * ld + q.col) + e0 * q.bf + e1 * q.bk;
+      if constexpr (kG == 1) vr += a.sg * ld_as_double(gp + r * ld + q.col);
+      if (w == 0)
+        m.prev_r = vr;
+      else
+        m.next_r = vr;
     }
   }
+}
 
-  // 2. Streaming loads (rows clamped for the idle segments past the chain end).
-  double v[kSeg], y[kSeg];
+// Streaming loads (rows clamped for the idle segments past the chain end):
+// v <- in, y <- g.
+template <typename Tin, typename Tg, int kG>
+__device__ __forceinline__ void load_stream(const SweepArgs &a, const Unit &u, const Cols &q,
+                                            double *v, double *y) {
+  const int64_t npad = a.npad, ld = a.ld;
+  const Tin *__restrict__ in = (const Tin *)a.in;
 #pragma unroll
   for (int i = 0; i < kSeg; ++i) {
-    const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
-    v[i] = ld_as_double(in + r * ld + col);
+    const int64_t r = u.row0 + i < npad ? u.row0 + i : npad - 1;
+    v[i] = ld_as_double(in + r * ld + q.col);
   }
   if constexpr (kG != 0) {
+    const Tg *__restrict__ gp = (const Tg *)a.g;
 #pragma unroll
     for (int i = 0; i < kSeg; ++i) {
-      const int64_t r = row0 + i < npad ? row0 + i : npad - 1;
-      y[i] = ld_as_double(gp + r * ld + col);
+      const int64_t r = u.row0 + i < npad ? u.row0 + i : npad - 1;
+      y[i] = ld_as_double(gp + r * ld + q.col);
     }
   }
+}
 
+// Elimination and store of one unit (lead_sync: synchronize before the LDS
+// early region is written, for a workgroup that reuses its LDS).
+template <typename Tin, typename Tg, typename Tout, int kG, bool kPre>
+__device__ __forceinline__ void compute_store(const SweepArgs &a, const Unit &u, const Cols &q,
+                                              const Small &m, double *v, double *y, double *lds,
+                                              int tid, int lane, int w, bool lead_sync) {
+  const int64_t ncols = a.ncols, ld = a.ld;
+  const bool has_prev = a.tab_prev != nullptr;
+  if (lead_sync) __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kTabLoads; ++q)
-    if (tid + q * kThreads < kTabN) lds[OFF_TAB + tid + q * kThreads] = tv[q];
-  if (tid < kL1) lds[OFF_L1 + tid] = l1v;
-  if (tid < 2 * kChunk) lds[OFF_AB + tid] = abv;
+  for (int k = 0; k < kTabLoads; ++k)
+    if (tid + k * kThreads < kTabN) lds[OFF_TAB + tid + k * kThreads] = m.tv[k];
+  if (tid < kL1) lds[OFF_L1 + tid] = m.l1v;
+  if (tid < 2 * kChunk) lds[OFF_AB + tid] = m.abv;
   if constexpr (kPre) {
-    if (tid < 2 * kChunk) lds[OFF_PRE + tid] = prv;
+    if (tid < 2 * kChunk) lds[OFF_PRE + tid] = m.prv;
   }
   __syncthreads();
 
@@ -178,10 +212,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
   const double *Tbk1 = lds + OFF_TAB + 4 * kChunk + w * kSeg;
   const double *Ab = lds + OFF_AB + 2 * w * kSeg;
 
-  // 3. Right-hand side and output base.  Idle segments carry exact zeros.
-  const double act = active ? 1.0 : 0.0;
+  // Right-hand side and output base.  Idle segments carry exact zeros.
+  const double act = u.active ? 1.0 : 0.0;
   const double isc = act * a.in_scale;
-  const double cA = has_prev ? act * bf : 0.0, cB = has_prev ? act * bk : 0.0;
+  const double cA = has_prev ? act * q.bf : 0.0, cB = has_prev ? act * q.bk : 0.0;
 #pragma unroll
   for (int i = 0; i < kSeg; ++i) {
     v[i] = isc * v[i] + Ab[2 * i] * cA + Ab[2 * i + 1] * cB;
@@ -199,11 +233,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
     lds[OFF_PF + w * kCols + lane] = y[0];
     lds[OFF_PL + w * kCols + lane] = y[kSeg - 1];
     __syncthreads();
-    const double ym = w > 0 ? lds[OFF_PL + (w - 1) * kCols + lane] : prev_r;
-    const double yp = w < kWaves - 1 ? lds[OFF_PF + (w + 1) * kCols + lane] : next_r;
+    const double ym = w > 0 ? lds[OFF_PL + (w - 1) * kCols + lane] : m.prev_r;
+    const double yp = w < kWaves - 1 ? lds[OFF_PF + (w + 1) * kCols + lane] : m.next_r;
     const double *Pd = lds + OFF_PRE + w * kSeg;
     const double *Pe = lds + OFF_PRE + kChunk + w * kSeg;
-    const double pem = w > 0 ? lds[OFF_PRE + kChunk + w * kSeg - 1] : pe_before;
+    const double pem = w > 0 ? lds[OFF_PRE + kChunk + w * kSeg - 1] : m.pe_before;
     double t[kSeg];
 #pragma unroll
     for (int i = 0; i < kSeg; ++i) {
@@ -215,7 +249,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
     for (int i = 0; i < kSeg; ++i) y[i] = act * t[i];
   }
 
-  // 4. Forward elimination with zero carry-in, then the segment carry.
+  // Forward elimination with zero carry-in, then the segment carry.
   {
     double carry = 0.0;
 #pragma unroll
@@ -228,16 +262,16 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
   __syncthreads();
   double cf1 = 0.0;
 #pragma unroll
-  for (int u = 0; u < kWaves; ++u)
-    cf1 += lds[OFF_L1 + (0 * kWaves + w) * kWaves + u] * lds[OFF_SY + u * kCols + lane];
+  for (int k = 0; k < kWaves; ++k)
+    cf1 += lds[OFF_L1 + (0 * kWaves + w) * kWaves + k] * lds[OFF_SY + k * kCols + lane];
 #pragma unroll
   for (int i = 0; i < kSeg; ++i) y[i] += Tf1[i] * cf1;
   const double ylast_chunk = y[kSeg - 1];
 
-  // 5. Backward substitution with zero carry-in, fused with the output.
-  //    Without a g term or stencil the right-hand side is recovered from the
-  //    forward values, r_k = y_k + l_k y_{k-1} (y_{-1} = cf1), so v need not
-  //    live on.
+  // Backward substitution with zero carry-in, fused with the output.
+  // Without a g term or stencil the right-hand side is recovered from the
+  // forward values, r_k = y_k + l_k y_{k-1} (y_{-1} = cf1), so v need not
+  // live on.
   constexpr bool kKeepV = kG != 0 || kPre;
   const double sigma = a.sigma;
   const bool out_x = a.out_mode == 1;
@@ -258,41 +292,43 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
   __syncthreads();
   double cb1 = 0.0;
 #pragma unroll
-  for (int u = 0; u < kWaves; ++u)
-    cb1 += lds[OFF_L1 + (1 * kWaves + w) * kWaves + u] * lds[OFF_SX + u * kCols + lane];
+  for (int k = 0; k < kWaves; ++k)
+    cb1 += lds[OFF_L1 + (1 * kWaves + w) * kWaves + k] * lds[OFF_SX + k * kCols + lane];
   const double coef = (out_x ? 1.0 : -sigma) * cb1;
 #pragma unroll
   for (int i = 0; i < kSeg; ++i) y[i] += coef * Tbk1[i];
 
-  // 6. Chunk boundary values for the chunk carries.
-  if (w == kWaves - 1) a.lv[(((int64_t)c * 2 + s) * 2 + 0) * ncols + col] = ylast_chunk;
-  if (w == 0) a.lv[(((int64_t)c * 2 + s) * 2 + 1) * ncols + col] = xfirst + Tbk1[0] * cb1;
+  // Chunk boundary values for the chunk carries.
+  if (w == kWaves - 1) a.lv[(((int64_t)u.c * 2 + u.s) * 2 + 0) * ncols + q.col] = ylast_chunk;
+  if (w == 0) a.lv[(((int64_t)u.c * 2 + u.s) * 2 + 1) * ncols + q.col] = xfirst + Tbk1[0] * cb1;
 
   Tout *__restrict__ out = (Tout *)a.out;
   if (a.out_mode != 0) {
-    if (active) {
+    if (u.active) {
 #pragma unroll
-      for (int i = 0; i < kSeg; ++i) out[(row0 + i) * ld + col] = (Tout)y[i];
+      for (int i = 0; i < kSeg; ++i) out[(u.row0 + i) * ld + q.col] = (Tout)y[i];
     }
     return;
   }
-  // 7. Transposed store staged through LDS: output row col0 + j receives this
-  //    segment's kSeg positions as one contiguous run.
-  double *stage = lds + w * kStage;
+  // Transposed store staged through LDS: the workgroup's 64 x 64 tile
+  // (chain positions x chains) is transposed so that output row col0 + j
+  // receives the chunk's 64 positions as one contiguous 512-byte run.
+  static_assert(kChunk == kCols && kChunk * (kChunk + 1) <= kSweepLds, "store tile");
   __syncthreads();  // the early region is dead
 #pragma unroll
-  for (int i = 0; i < kSeg; ++i) stage[lane * (kSeg + 1) + i] = y[i];
+  for (int i = 0; i < kSeg; ++i) lds[lane * (kChunk + 1) + w * kSeg + i] = y[i];
   __syncthreads();
-  if (active) {
-    constexpr int kLanesPerRow = kSeg / 2;
-    constexpr int kRowsPerStore = kCols / kLanesPerRow;
+  {
+    // each wave stores kCols / kWaves output rows; 32 lanes per row, two
+    // consecutive positions per lane
+    constexpr int kRowsPerWave = kCols / kWaves;
 #pragma unroll
-    for (int t = 0; t < kCols / kRowsPerStore; ++t) {
-      const int orow = kRowsPerStore * t + lane / kLanesPerRow;
-      const int ocol = 2 * (lane % kLanesPerRow);
-      const double v0 = stage[orow * (kSeg + 1) + ocol];
-      const double v1 = stage[orow * (kSeg + 1) + ocol + 1];
-      Tout *dst = out + (col0 + orow) * ld + row0 + ocol;
+    for (int t = 0; t < kRowsPerWave / 2; ++t) {
+      const int orow = w * kRowsPerWave + 2 * t + (lane >> 5);
+      const int pos = 2 * (lane & 31);
+      const double v0 = lds[orow * (kChunk + 1) + pos];
+      const double v1 = lds[orow * (kChunk + 1) + pos + 1];
+      Tout *dst = out + (q.col0 + orow) * ld + u.rbase + pos;
       dst[0] = (Tout)v0;
       dst[1] = (Tout)v1;
     }
@@ -300,7 +336,24 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
 }
 
 template <typename Tin, typename Tg, typename Tout, int kG, bool kPre>
-__global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
+__device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, const int by,
+                                            double *lds) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (kCols - 1);
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const Cols q = cols_of(a, bx, lane);
+  const Unit u = unit_of(a, by, w);
+  Small m;
+  load_small<Tin, Tg, kG, kPre>(a, u, q, tid, w, m);
+  double v[kSeg], y[kSeg];
+  load_stream<Tin, Tg, kG>(a, u, q, v, y);
+  compute_store<Tin, Tg, Tout, kG, kPre>(a, u, q, m, v, y, lds, tid, lane, w, false);
+}
+
+// Six wavefronts per SIMD (three workgroups per compute unit) fit every
+// variant but the stencil pass with g in the output base, which would spill.
+template <typename Tin, typename Tg, typename Tout, int kG, bool kPre>
+__global__ __launch_bounds__(kCols *kWaves, (kPre && kG == 2) ? 4 : 6) void k_sweep(SweepArgs a) {
   __shared__ double lds[kSweepLds];
   if (blockIdx.z != 0) {
     const int64_t z = blockIdx.z;
@@ -316,7 +369,7 @@ __global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep(SweepArgs a) {
 // Batched sweep: workgroup g belongs to problem wg_prob[g]; the problem's
 // descriptor holds workspace offsets in place of its workspace pointers.
 template <typename Tin, typename Tg, typename Tout, int kG>
-__global__ __launch_bounds__(kCols *kWaves, 4) void k_sweep_batch(const BatchSweep *__restrict__ d,
+__global__ __launch_bounds__(kCols *kWaves, 6) void k_sweep_batch(const BatchSweep *__restrict__ d,
                                                                   const int *__restrict__ wg_prob,
                                                                   char *base) {
   __shared__ double lds[kSweepLds];
@@ -399,8 +452,9 @@ struct SweepLaunch {
   hipStream_t st;
   template <typename Tin, typename Tg, typename Tout, int kG, bool kPre = false>
   void go() const {
+    const int nch = a.nc0 + a.nc1;
     if (d == nullptr) {
-      dim3 grid((unsigned)(a.ncols / kCols), (unsigned)(a.nc0 + a.nc1),
+      dim3 grid((unsigned)(a.ncols / kCols), (unsigned)nch,
                 (unsigned)(a.nbatch > 0 ? a.nbatch : 1));
       hipLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kG, kPre>), grid, dim3(kCols * kWaves), 0, st, a);
     } else if constexpr (!kPre) {
