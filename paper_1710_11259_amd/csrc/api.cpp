@@ -100,7 +100,7 @@ fps_status run_adi(fps_plan *pl, const void *Gterm, const void *GTin, int g_f32,
     A.out_f32 = f32(j);
     A.out_mode = 0;
     FPS_HIP(timed_sweep(pl, A, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(j), ab, -A.sigma, L.npad, nc0, nc1, L.ncmax, st));
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(j), ab, -A.sigma, L.npad, nc0, nc1, L.ncmax, st));
     fps::SweepArgs B = A;
     const bool last = j == J - 1;
     B.in = O0;
@@ -116,7 +116,7 @@ fps_status run_adi(fps_plan *pl, const void *Gterm, const void *GTin, int g_f32,
     B.out_f32 = last ? 0 : f32(j + 1);
     B.out_mode = last ? 1 : 0;
     FPS_HIP(timed_sweep(pl, B, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(j), ab, last ? 1.0 : -B.sigma, L.npad, nc0, nc1,
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(j), ab, last ? 1.0 : -B.sigma, L.npad, nc0, nc1,
                                L.ncmax, st));
   }
   return FPS_OK;
@@ -349,7 +349,8 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
         ++pl->n_f32;
       }
   pl->L = fps::make_layout(n);
-  fps::build_sweep_tables(pl->L, pl->shifts.p, pl->tab, pl->ctab, pl->comb, pl->l1);
+  fps::build_sweep_tables_ab(pl->L, std::vector<double>(pl->shifts.p.size(), 1.0), pl->shifts.p,
+                             pl->tab, pl->ctab, nullptr, pl->l1);
   fps::build_conversions(pl->L, pl->Rs, pl->P);
   std::vector<double> RsA[2], RsB[2], PA[2], PB[2];
   for (int s = 0; s < 2; ++s) {
@@ -404,7 +405,7 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   if (!(flags & FPS_PLAN_HOST_ONLY)) {
     fps_status s;
     if ((s = upload(pl->d_tab, pl->tab)) != FPS_OK || (s = upload(pl->d_ctab, pl->ctab)) != FPS_OK ||
-        (s = upload(pl->d_comb, pl->comb)) != FPS_OK || (s = upload(pl->d_l1, pl->l1)) != FPS_OK ||
+        (s = upload(pl->d_l1, pl->l1)) != FPS_OK ||
         (s = upload(pl->d_RsA[0], RsA[0])) != FPS_OK || (s = upload(pl->d_RsA[1], RsA[1])) != FPS_OK ||
         (s = upload(pl->d_RsB[0], RsB[0])) != FPS_OK || (s = upload(pl->d_RsB[1], RsB[1])) != FPS_OK ||
         (s = upload(pl->d_PA[0], PA[0])) != FPS_OK || (s = upload(pl->d_PA[1], PA[1])) != FPS_OK ||

@@ -130,7 +130,7 @@ fps_status build_descriptors(fps_batch *bt) {
     A.nc1 = (int)L.nc[1];
     A.lv = off_ptr<double *>(lv);
     const int nbx_s = (int)(L.npad / fps::kCols);
-    const int nbx_r = (int)((L.npad + 255) / 256);
+    const int nbx_r = (int)((L.npad + fps::kReduceThreads - 1) / fps::kReduceThreads);
     for (int j = 0; j < J; ++j) {
       const bool last = j == J - 1;
       // half-step 1
@@ -163,7 +163,7 @@ fps_status build_descriptors(fps_batch *bt) {
       const size_t i1 = ((size_t)j * 2 + 0) * C + k, i2 = ((size_t)j * 2 + 1) * C + k;
       sw[i1] = fps::BatchSweep{a1, bt->sw_start[k], nbx_s};
       sw[i2] = fps::BatchSweep{a2, bt->sw_start[k], nbx_s};
-      rd[i1] = fps::BatchReduce{lv, ab, pl->comb_dev(j), -a1.sigma, L.npad, L.ncmax,
+      rd[i1] = fps::BatchReduce{lv, ab, pl->ctab_dev(j), -a1.sigma, L.npad, L.ncmax,
                                 (int)L.nc[0], (int)L.nc[1], bt->rd_start[k], nbx_r};
       rd[i2] = rd[i1];
       rd[i2].scale = last ? 1.0 : -a2.sigma;
@@ -281,7 +281,7 @@ fps_status fps_batch_create(fps_batch **out, int dim, int count, const int64_t *
   for (int k = 0; k < count; ++k) {
     const fps::Layout &L = bt->plan_of(bt->order[k])->L;
     const int64_t nsw = (L.npad / fps::kCols) * (L.nc[0] + L.nc[1]);
-    const int64_t nrd = ((L.npad + 255) / 256) * 2 * L.ncmax;
+    const int64_t nrd = ((L.npad + fps::kReduceThreads - 1) / fps::kReduceThreads) * 2;
     if ((int64_t)bt->sw_start[k] + nsw > (int64_t)1 << 30 ||
         (int64_t)bt->rd_start[k] + nrd > (int64_t)1 << 30) {
       delete bt;

@@ -138,7 +138,7 @@ fps_status cube_plan_build(fps_plan *pl) {
   }
   pl->L = fps::make_layout(n);
   const fps::Layout &L = pl->L;
-  fps::build_sweep_tables_ab(L, alpha, beta, pl->tab, pl->ctab, pl->comb, pl->l1);
+  fps::build_sweep_tables_ab(L, alpha, beta, pl->tab, pl->ctab, nullptr, pl->l1);
   fps::build_conversions(L, pl->Rs, pl->P);
   for (int s = 0; s < 2; ++s) {
     pl->mop[s] = (L.mo[s] + fps::kPad - 1) / fps::kPad * fps::kPad;
@@ -220,7 +220,7 @@ fps_status cube_plan_upload(fps_plan *pl) {
   std::vector<double> pre(pl->sdiag);
   pre.insert(pre.end(), pl->soff.begin(), pl->soff.end());
   if ((s = upload(pl->d_tab, pl->tab)) != FPS_OK || (s = upload(pl->d_ctab, pl->ctab)) != FPS_OK ||
-      (s = upload(pl->d_comb, pl->comb)) != FPS_OK || (s = upload(pl->d_l1, pl->l1)) != FPS_OK ||
+      (s = upload(pl->d_l1, pl->l1)) != FPS_OK ||
       (s = upload(pl->d_RbA[0], RbA[0])) != FPS_OK || (s = upload(pl->d_RbA[1], RbA[1])) != FPS_OK ||
       (s = upload(pl->d_RbB[0], RbB[0])) != FPS_OK || (s = upload(pl->d_RbB[1], RbB[1])) != FPS_OK ||
       (s = upload(pl->d_PA[0], PA[0])) != FPS_OK || (s = upload(pl->d_PA[1], PA[1])) != FPS_OK ||
@@ -319,7 +319,7 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
     Z.out = O0;
     Z.out_mode = 2;
     FPS_HIP(timed_sweep(pl, Z, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(i), ab, -Z.sigma, ch, Z.nc0, Z.nc1, L.ncmax, st));
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(i), ab, -Z.sigma, ch, Z.nc0, Z.nc1, L.ncmax, st));
     FPS_HIP(fps::launch_cube_zfinal(O0, ab, pl->tab_dev(i), RX, RXT, npad, mp0, L.mstride, L.ncmax,
                                     st));
     // (x, y) half-step: inner ADI on every z-slice
@@ -341,7 +341,7 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
       a.out = O0;
       a.out_mode = 0;
       FPS_HIP(timed_sweep(pl, a, st));
-      FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(t), ab, -a.sigma, npad, a.nc0, a.nc1, L.ncmax, st,
+      FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(t), ab, -a.sigma, npad, a.nc0, a.nc1, L.ncmax, st,
                                  (int)npad, S.lvb, S.abb));
       fps::SweepArgs b = a;
       b.in = O0;
@@ -354,7 +354,7 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
       b.out = O1;
       b.out_mode = last ? 1 : 0;
       FPS_HIP(timed_sweep(pl, b, st));
-      FPS_HIP(fps::launch_reduce(lv, pl->comb_dev(t), ab, last ? 1.0 : -b.sigma, npad, b.nc0, b.nc1,
+      FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(t), ab, last ? 1.0 : -b.sigma, npad, b.nc0, b.nc1,
                                  L.ncmax, st, (int)npad, S.lvb, S.abb));
     }
     const double *tl = pl->tab_dev(t0 + J2 - 1);

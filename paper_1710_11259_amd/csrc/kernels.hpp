@@ -71,19 +71,23 @@ hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSw
                               const int *wg_prob, int nwg, char *base, hipStream_t st);
 
 // Chunk carries: for every chain, the forward and backward carry into each
-// chunk, scaled by `scale`, into ab [2][ncmax][nchains][2] (comb: the carry
-// combinations of the producing pass's shift); nbatch blocks of lv / ab at
-// strides lvb / abb.
-hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
+// chunk, scaled by `scale`, into ab [2][ncmax][nchains][2] (ctab: the
+// per-chunk coefficients [2][kNCTab][ncmax] of the producing pass's shift);
+// nbatch blocks of lv / ab at strides lvb / abb.
+hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,
                          int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
                          int nbatch = 1, int64_t lvb = 0, int64_t abb = 0);
 
+// Threads per workgroup of the chunk-carry kernels (one chain per thread).
+constexpr int kReduceThreads = 64;
+
 // Batched launch_reduce: lv_off / ab_off are byte offsets from `base`; the
-// grid of one problem is (ceil(npad / 256), 2 ncmax), flattened as for
+// workgroups of one problem are (chain block b, parity s) -> local index
+// s * nbx + b with nbx = ceil(npad / kReduceThreads), flattened as for
 // BatchSweep; ncmax_max bounds every problem's ncmax (LDS size).
 struct BatchReduce {
   int64_t lv_off, ab_off;
-  const double *comb;
+  const double *ctab;
   double scale;
   int64_t npad, ncmax;
   int nc0, nc1;

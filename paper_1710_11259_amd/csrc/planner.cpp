@@ -160,18 +160,20 @@ double atilde_off(int64_t i) {
 void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vector<double> &pos,
                         std::vector<double> &chunk, std::vector<double> &comb,
                         std::vector<double> &l1) {
-  build_sweep_tables_ab(L, std::vector<double>(p.size(), 1.0), p, pos, chunk, comb, l1);
+  build_sweep_tables_ab(L, std::vector<double>(p.size(), 1.0), p, pos, chunk, &comb, l1);
 }
 
 void build_sweep_tables_ab(const Layout &L, const std::vector<double> &alpha,
                            const std::vector<double> &beta0, std::vector<double> &pos,
-                           std::vector<double> &chunk, std::vector<double> &comb,
+                           std::vector<double> &chunk, std::vector<double> *combp,
                            std::vector<double> &l1) {
+  std::vector<double> unused;
+  std::vector<double> &comb = combp ? *combp : unused;
   const int J = (int)alpha.size();
   const int64_t ms = L.mstride, nc = L.ncmax;
   pos.assign((size_t)J * 2 * kNTab * ms, 0.0);
   chunk.assign((size_t)J * 2 * kNCTab * nc, 0.0);
-  comb.assign((size_t)J * 2 * nc * nc * kNComb, 0.0);
+  if (combp) comb.assign((size_t)J * 2 * nc * nc * kNComb, 0.0);
   l1.assign((size_t)J * 2 * nc * kL1, 0.0);
   std::vector<long double> CF((size_t)(nc + 1) * nc), CBY((size_t)nc * nc), CBX((size_t)nc * nc);
   std::vector<long double> l(ms), ib(ms), u(ms), F2(ms), BF2(ms);
@@ -256,6 +258,7 @@ void build_sweep_tables_ab(const Layout &L, const std::vector<double> &alpha,
             Lc[(1 * kWaves + w) * kWaves + u] = (double)b;
           }
       }
+      if (!combp) continue;
       // Coefficients of the chunk carries as linear forms in the boundary
       // values: cf[0] = 0, cf[c+1] = ylast[c] + F2last[c] cf[c];
       // cb[ncs-1] = 0, cb[c] = xfirst[c+1] + BF2first[c+1] cf[c+1] + Bk2first[c+1] cb[c+1].

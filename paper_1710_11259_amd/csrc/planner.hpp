@@ -94,9 +94,11 @@ void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vect
                         std::vector<double> &l1);
 // The same tables for the matrices alpha_j A~ + beta_j I (one per entry of
 // alpha and beta); build_sweep_tables is the case alpha_j = 1, beta_j = p_j.
+// comb may be null: the chunk-carry linear forms are then not built (the
+// device evaluates the chunk-level recurrences from the chunk tables).
 void build_sweep_tables_ab(const Layout &L, const std::vector<double> &alpha,
                            const std::vector<double> &beta, std::vector<double> &pos,
-                           std::vector<double> &chunk, std::vector<double> &comb,
+                           std::vector<double> &chunk, std::vector<double> *comb,
                            std::vector<double> &l1);
 
 // Conversion maps split by parity (row-major, float64):

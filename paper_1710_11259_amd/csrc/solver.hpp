@@ -59,14 +59,14 @@ struct fps_plan {
   std::vector<char> f32step;
   int n_f32 = 0;
   fps::Layout L;
-  std::vector<double> tab, ctab, comb, l1;  // host sweep tables
+  std::vector<double> tab, ctab, l1;  // host sweep tables
   std::vector<double> sdiag, soff;          // A~ stencil in the parity-blocked layout
   std::vector<double> Rs[2], P[2];  // host conversion maps (unpadded)
   int64_t mop[2] = {0, 0};          // output parity lengths padded to 64
   std::vector<double> sinv;         // 1/sqrt((i+1)(i+2))
 
   // device copies
-  fps::detail::DeviceBuf d_tab, d_ctab, d_comb, d_l1, d_sinv, d_sdiag, d_soff;
+  fps::detail::DeviceBuf d_tab, d_ctab, d_l1, d_sinv, d_sdiag, d_soff;
   // GEMM operands, zero-padded to multiples of 64: RsA = Rs (mp x mp),
   // RsB = Rs^T (mp x mp), PA = P (mop x mp), PB = P^T (mp x mop).
   fps::detail::DeviceBuf d_RsA[2], d_RsB[2], d_PA[2], d_PB[2];
@@ -101,9 +101,6 @@ struct fps_plan {
   }
   const double *ctab_dev(int j) const {
     return (const double *)d_ctab.p + (size_t)j * 2 * fps::kNCTab * L.ncmax;
-  }
-  const double *comb_dev(int j) const {
-    return (const double *)d_comb.p + (size_t)j * 2 * L.ncmax * L.ncmax * fps::kNComb;
   }
   const double *l1_dev(int j) const {
     return (const double *)d_l1.p + (size_t)j * 2 * L.ncmax * fps::kL1;

@@ -385,58 +385,145 @@ __global__ __launch_bounds__(kCols *kWaves, 6) void k_sweep_batch(const BatchSwe
   sweep_block<Tin, Tg, Tout, kG, false>(a, local % e.nbx, local / e.nbx, lds);
 }
 
-// Chunk carries of one half-sweep: thread (parity s, chunk c, chain r)
-// forms cf[c], cb[c] of chain r as linear combinations of the chain's chunk
-// boundary values (coefficients precomputed per shift and staged in LDS, one
-// row per block), scaled by `scale`.  Output layout ab[s][c][r][2].
-__device__ __forceinline__ void reduce_block(const double *__restrict__ lv,
-                                             const double *__restrict__ comb,
-                                             double *__restrict__ ab, double scale, int64_t npad,
-                                             int nc0, int nc1, int64_t ncmax, int bx, int by,
-                                             double *wrow /* [nc][kNComb], LDS */) {
-  // npad here is the number of chains (the lv / ab row length).
-  const int64_t r = (int64_t)bx * blockDim.x + threadIdx.x;
-  const int s = by >= ncmax ? 1 : 0;
-  const int c = by - (s ? (int)ncmax : 0);
-  const int nc = s ? nc1 : nc0;
-  if (c >= nc) return;
-  const double *__restrict__ W = comb + (((int64_t)s * ncmax + c) * ncmax) * kNComb;
-  for (int e = threadIdx.x; e < nc * kNComb; e += blockDim.x) wrow[e] = W[e];
-  __syncthreads();
-  if (r >= npad) return;
-  const double *__restrict__ lp = lv + (int64_t)s * 2 * npad + r;
-  double A = 0.0, B = 0.0;
-#pragma unroll 16
-  for (int q = 0; q < nc; ++q) {
-    const double yl = lp[(int64_t)q * 4 * npad];
-    const double xf = lp[(int64_t)q * 4 * npad + npad];
-    A += wrow[q * kNComb + K_CF] * yl;
-    B += wrow[q * kNComb + K_CBY] * yl + wrow[q * kNComb + K_CBX] * xf;
+// Chunk carries of one half-sweep: thread (parity s, chain r) runs the
+// chunk-level recurrences of its chain on the chunk boundary values
+//   cf[0] = 0,        cf[c+1] = ylast[c] + F2last[c] cf[c],
+//   cb[nc-1] = 0,     cb[c] = xfirst[c+1] + BF2first[c+1] cf[c+1]
+//                            + Bk2first[c+1] cb[c+1],
+// (per-chunk coefficients ctab of the producing pass's shift, staged in LDS)
+// and writes ab[s][c][r] = scale (cf[c], cb[c]).  cf is parked in ab between
+// the two sweeps over the chunks (each thread rereads only what it wrote).
+__device__ __forceinline__ void reduce_chain(const double *__restrict__ lv,
+                                             const double *__restrict__ ct, double *__restrict__ ab,
+                                             double scale, int64_t nchains, int nc, int64_t ncmax,
+                                             int s, int64_t r) {
+  const double *__restrict__ yl = lv + (int64_t)s * 2 * nchains + r;  // chunk q at q * 4 nchains
+  const double *__restrict__ xf = yl + nchains;
+  double *__restrict__ o = ab + ((int64_t)s * ncmax * nchains + r) * 2;  // chunk c at c * 2 nchains
+  // forward: cf[c] parked (unscaled) in o[c][0]
+  double cf = 0.0;
+  for (int c0 = 0; c0 < nc; c0 += 8) {
+    double y8[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) y8[k] = c0 + k < nc ? yl[(int64_t)(c0 + k) * 4 * nchains] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int c = c0 + k;
+      if (c < nc) {
+        o[(int64_t)c * 2 * nchains] = cf;
+        cf = y8[k] + ct[C_F2LAST * ncmax + c] * cf;
+      }
+    }
   }
-  double *o = ab + (((int64_t)s * ncmax + c) * npad + r) * 2;
-  o[0] = scale * A;
-  o[1] = scale * B;
+  // backward, chunks nc-1 .. 0; cfn = unscaled cf of chunk c + 1
+  double cb = 0.0, cfn = 0.0;
+  for (int c1 = nc - 1; c1 >= 0; c1 -= 8) {
+    double f8[8], x8[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int c = c1 - k;
+      f8[k] = c >= 0 ? o[(int64_t)c * 2 * nchains] : 0.0;
+      x8[k] = c >= 0 && c + 1 < nc ? xf[(int64_t)(c + 1) * 4 * nchains] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int c = c1 - k;
+      if (c >= 0) {
+        cb = c + 1 < nc ? x8[k] + ct[C_BF2FIRST * ncmax + c + 1] * cfn +
+                              ct[C_BK2FIRST * ncmax + c + 1] * cb
+                        : 0.0;
+        double *oc = o + (int64_t)c * 2 * nchains;
+        oc[0] = scale * f8[k];
+        oc[1] = scale * cb;
+        cfn = f8[k];
+      }
+    }
+  }
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ lv,
-                                                const double *__restrict__ comb,
-                                                double *__restrict__ ab, double scale,
-                                                int64_t nchains, int nc0, int nc1, int64_t ncmax,
-                                                int64_t lvb, int64_t abb) {
-  extern __shared__ double wrow[];
+// The same recurrences with every boundary value of the chain loaded at
+// once into registers (nc <= NC chunks): one round of memory latency.
+template <int NC>
+__device__ __forceinline__ void reduce_chain_reg(const double *__restrict__ lv,
+                                                 const double *__restrict__ ct,
+                                                 double *__restrict__ ab, double scale,
+                                                 int64_t nchains, int nc, int64_t ncmax, int s,
+                                                 int64_t r) {
+  const double *__restrict__ yl = lv + (int64_t)s * 2 * nchains + r;
+  const double *__restrict__ xf = yl + nchains;
+  double *__restrict__ o = ab + ((int64_t)s * ncmax * nchains + r) * 2;
+  double y[NC], x[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    y[c] = c < nc ? yl[(int64_t)c * 4 * nchains] : 0.0;
+    x[c] = c < nc ? xf[(int64_t)c * 4 * nchains] : 0.0;
+  }
+  double cf = 0.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {  // y[c] <- cf[c]
+    const double next = y[c] + ct[C_F2LAST * ncmax + c] * cf;
+    y[c] = cf;
+    cf = next;
+  }
+  double cb = 0.0;
+#pragma unroll
+  for (int c = NC - 1; c >= 0; --c) {
+    if (c < nc) {
+      cb = c + 1 < nc ? x[c + 1] + ct[C_BF2FIRST * ncmax + c + 1] * y[c + 1] +
+                            ct[C_BK2FIRST * ncmax + c + 1] * cb
+                      : 0.0;
+      double *oc = o + (int64_t)c * 2 * nchains;
+      oc[0] = scale * y[c];
+      oc[1] = scale * cb;
+    }
+  }
+}
+
+__device__ __forceinline__ void reduce_any(const double *lv, const double *ct, double *ab,
+                                           double scale, int64_t nchains, int nc, int64_t ncmax,
+                                           int s, int64_t r) {
+  if (nc <= 8)
+    reduce_chain_reg<8>(lv, ct, ab, scale, nchains, nc, ncmax, s, r);
+  else if (nc <= 32)
+    reduce_chain_reg<32>(lv, ct, ab, scale, nchains, nc, ncmax, s, r);
+  else
+    reduce_chain(lv, ct, ab, scale, nchains, nc, ncmax, s, r);
+}
+
+// Grid: (ceil(nchains / kReduceThreads), 2 parities, batch).
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restrict__ lv,
+                                                           const double *__restrict__ ctab,
+                                                           double *__restrict__ ab, double scale,
+                                                           int64_t nchains, int nc0, int nc1,
+                                                           int64_t ncmax, int64_t lvb,
+                                                           int64_t abb) {
+  extern __shared__ double ct[];  // [kNCTab][ncmax] of this parity
+  const int s = blockIdx.y;
+  const int nc = s ? nc1 : nc0;
+  for (int e = threadIdx.x; e < kNCTab * ncmax; e += blockDim.x)
+    ct[e] = ctab[(int64_t)s * kNCTab * ncmax + e];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nchains || nc == 0) return;
   const int64_t z = blockIdx.z;
-  reduce_block(lv + z * lvb, comb, ab + z * abb, scale, nchains, nc0, nc1, ncmax, blockIdx.x,
-               blockIdx.y, wrow);
+  reduce_any(lv + z * lvb, ct, ab + z * abb, scale, nchains, nc, ncmax, s, r);
 }
 
-__global__ __launch_bounds__(256) void k_reduce_batch(const BatchReduce *__restrict__ d,
-                                                      const int *__restrict__ wg_prob, char *base) {
-  extern __shared__ double wrow[];
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_batch(
+    const BatchReduce *__restrict__ d, const int *__restrict__ wg_prob, char *base) {
+  extern __shared__ double ct[];
   const int k = __builtin_amdgcn_readfirstlane(wg_prob[blockIdx.x]);
   const BatchReduce &e = d[k];
   const int local = (int)blockIdx.x - e.wg_start;
-  reduce_block((const double *)(base + e.lv_off), e.comb, (double *)(base + e.ab_off), e.scale,
-               e.npad, e.nc0, e.nc1, e.ncmax, local % e.nbx, local / e.nbx, wrow);
+  const int s = local / e.nbx;
+  const int nc = s ? e.nc1 : e.nc0;
+  for (int i = threadIdx.x; i < kNCTab * e.ncmax; i += blockDim.x)
+    ct[i] = e.ctab[(int64_t)s * kNCTab * e.ncmax + i];
+  __syncthreads();
+  const int64_t r = (int64_t)(local % e.nbx) * blockDim.x + threadIdx.x;
+  if (r >= e.npad || nc == 0) return;
+  reduce_any((const double *)(base + e.lv_off), ct, (double *)(base + e.ab_off), e.scale, e.npad,
+             nc, e.ncmax, s, r);
 }
 
 }  // namespace
@@ -516,14 +603,14 @@ hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSw
   return dispatch_sweep(SweepLaunch{types, d, wg_prob, base, nwg, st}, with_g);
 }
 
-hipError_t launch_reduce(const double *lv, const double *comb, double *ab, double scale,
+hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,
                          int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
                          int nbatch, int64_t lvb, int64_t abb) {
-  dim3 grid((unsigned)((nchains + 255) / 256), (unsigned)(2 * ncmax),
+  dim3 grid((unsigned)((nchains + kReduceThreads - 1) / kReduceThreads), 2u,
             (unsigned)(nbatch > 0 ? nbatch : 1));
-  const size_t shm = (size_t)ncmax * kNComb * sizeof(double);
+  const size_t shm = (size_t)ncmax * kNCTab * sizeof(double);
   if (shm > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce, grid, dim3(256), shm, st, lv, comb, ab, scale, nchains, nc0, nc1,
+  hipLaunchKernelGGL(k_reduce, grid, dim3(kReduceThreads), shm, st, lv, ctab, ab, scale, nchains, nc0, nc1,
                      ncmax, lvb, abb);
   return hipGetLastError();
 }
@@ -531,9 +618,10 @@ hipError_t launch_reduce(const double *lv, const double *comb, double *ab, doubl
 hipError_t launch_reduce_batch(const BatchReduce *d, const int *wg_prob, int nwg, int64_t ncmax_max,
                                char *base, hipStream_t st) {
   if (nwg <= 0) return hipSuccess;
-  const size_t shm = (size_t)ncmax_max * kNComb * sizeof(double);
+  const size_t shm = (size_t)ncmax_max * kNCTab * sizeof(double);
   if (shm > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)nwg), dim3(256), shm, st, d, wg_prob, base);
+  hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)nwg), dim3(kReduceThreads), shm, st, d, wg_prob,
+                     base);
   return hipGetLastError();
 }
 
