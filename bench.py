@@ -21,8 +21,20 @@ HBM_PEAK_GBS = 8000.0
 # Calibrated HBM traffic of the sweep kernel per launch at n = 4096 (rocprofv3
 # FETCH_SIZE x2.000 + WRITE_SIZE x1.000, see profiles/sweep_square_n4096.md),
 # valid only for the sweep source with this sha256.
-SWEEP_TRAFFIC = {"sha256": "3934e31aeec99cef01392722df5295b2dec6ba6ad9b4a80b9b9dae7d158c956d",
-                 "n": 4096, "half_step_1": 278.9e6, "half_step_2": 413.1e6}
+SWEEP_TRAFFIC = {"sha256": "1ff2cb9befb119d624f372dbca442eda66c211eb63f8dce129e4eb2be2488129",
+                 "n": 4096, "half_step_1": 278.8e6, "half_step_2": 413.0e6}
+
+
+def calibration_copy(torch, dev, mib):
+    """One device-to-device copy of a known size (HBM counter calibration)."""
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    print(f"# calibration copy {nbytes} bytes read + {nbytes} bytes written", file=sys.stderr)
 
 
 def bench_batch(fps, workloads, torch, tol, reps=3):
@@ -150,6 +162,8 @@ def main() -> int:
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP32-refined, batched and cube timings")
+    ap.add_argument("--only", choices=["fp32_refined", "batched", "cube"],
+                    help="run only this form and print its figures (profiling)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -166,6 +180,14 @@ def main() -> int:
 
     n = args.n
     dev = torch.device("cuda:0")
+    if args.only in ("batched", "cube"):
+        if args.copy_calib_mib:
+            calibration_copy(torch, dev, args.copy_calib_mib)
+        res = (bench_batch(fps, workloads, torch, args.tol) if args.only == "batched" else
+               bench_cube(fps, workloads, torch, args.tol, steps=max(1, args.steps),
+                          check=not args.no_check))
+        print(json.dumps({"form": args.only, **res}), flush=True)
+        return 0
     F_host = workloads.square_rhs(n, seed=0)
     F = torch.from_numpy(F_host).to(dev)
     plan = fps.plan(n, tol=args.tol)
@@ -175,14 +197,7 @@ def main() -> int:
           flush=True)
 
     if args.copy_calib_mib:
-        nbytes = args.copy_calib_mib << 20
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        print(f"# calibration copy {nbytes} bytes read + {nbytes} bytes written", file=sys.stderr)
+        calibration_copy(torch, dev, args.copy_calib_mib)
 
     for _ in range(args.warmup):
         fps.solve(plan, F, out=U, ws=ws)
@@ -199,10 +214,9 @@ def main() -> int:
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
-    # Roofline pass: the same solves again with a HIP event pair recorded by
-    # the library around every half-sweep launch on the solve's stream (the
-    # pairs add a few microseconds per launch, so the figures are
-    # conservative).
+    # Roofline pass: the same solves again, every half-sweep launch carrying
+    # a HIP event pair that records the dispatch's own start and end on the
+    # solve's stream.
     plan.set_sweep_timing(2 * plan.J * args.steps)
     torch.cuda.synchronize()
     e0.record(stream)
@@ -247,7 +261,8 @@ def main() -> int:
                 "achieved_GBs": {"half_step_1": round(b1 / t1 / 1e9, 1),
                                  "half_step_2": round(b2 / t2 / 1e9, 1)},
                 "launches_timed": len(sweep_list),
-                "timing": "HIP event pair per launch, separate pass of the same solves "
+                "timing": "HIP events recording each sweep dispatch's start and end "
+                          "(hipExtLaunchKernelGGL), separate pass of the same solves "
                           f"({instr_ms / args.steps:.2f} ms per solve with the events)",
                 "sweep_share_of_step": round(sum(sweep_list) / instr_ms, 4)}
 
@@ -264,7 +279,7 @@ def main() -> int:
 
     # Precision form: FP32 storage with FP64 refinement, same workload and tol.
     forms = {}
-    if not args.no_forms:
+    if not args.no_forms or args.only == "fp32_refined":
         pr = fps.plan(n, tol=args.tol, precision="fp32_refined")
         wsr = fps.workspace(pr, dev)
         Ur = torch.empty(pr.out_shape(), dtype=torch.float64, device=dev)
@@ -281,8 +296,9 @@ def main() -> int:
                                  "inner_J": pr.J, "rounds": pr.rounds,
                                  "f32_steps_per_round": pr.f32_steps}
         del wsr
-        forms["batched"] = bench_batch(fps, workloads, torch, args.tol)
-        forms["cube"] = bench_cube(fps, workloads, torch, args.tol, check=not args.no_check)
+        if args.only is None:
+            forms["batched"] = bench_batch(fps, workloads, torch, args.tol)
+            forms["cube"] = bench_cube(fps, workloads, torch, args.tol, check=not args.no_check)
     if forms:
         out["forms"] = forms
 

@@ -151,12 +151,14 @@ fps_status fps_adi_native(fps_plan *plan, const double *G_dev, double *Y_dev, vo
 /*
  * Diagnostics for throughput measurement.  fps_plan_set_sweep_timing(plan,
  * capacity) creates `capacity` HIP event pairs (0 disables and releases
- * them); later solves record one pair around each ADI half-sweep launch, on
- * the solve's stream, until the pairs run out.  fps_plan_sweep_time waits for
- * the recorded events, writes the elapsed milliseconds of the timed launches
- * in launch order to ms_host[0..min(count, cap)-1] (ms_host may be null when
- * cap is 0), sets *launches to their count, and resets the count.  Half-step
- * 1 and half-step 2 of Algorithm 2 alternate, starting with half-step 1.
+ * them); later solves time each ADI half-sweep launch with one pair (the
+ * dispatch's own start and end timestamps), until the pairs run out.
+ * fps_plan_sweep_time waits for the recorded events, writes the elapsed
+ * milliseconds of the timed launches in launch order to
+ * ms_host[0..min(count, cap)-1] (ms_host may be null when cap is 0), sets
+ * *launches to their count, and resets the count.  Square plans: half-step 1
+ * and half-step 2 of Algorithm 2 alternate, starting with half-step 1; cube
+ * plans: per outer step one z sweep, then the inner half-steps 1 and 2.
  */
 fps_status fps_plan_set_sweep_timing(fps_plan *plan, int capacity);
 fps_status fps_plan_sweep_time(fps_plan *plan, double *ms_host, int64_t cap, int64_t *launches);

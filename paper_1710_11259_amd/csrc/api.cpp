@@ -32,14 +32,10 @@ int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
 hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st) {
   const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
-  hipError_t e;
-  if (t && (e = hipEventRecord(pl->ev[2 * pl->ev_used], st)) != hipSuccess) return e;
-  if ((e = fps::launch_sweep(a, st)) != hipSuccess) return e;
-  if (t) {
-    if ((e = hipEventRecord(pl->ev[2 * pl->ev_used + 1], st)) != hipSuccess) return e;
-    ++pl->ev_used;
-  }
-  return hipSuccess;
+  if (!t) return fps::launch_sweep(a, st);
+  const hipError_t e = fps::launch_sweep(a, st, pl->ev[2 * pl->ev_used], pl->ev[2 * pl->ev_used + 1]);
+  if (e == hipSuccess) ++pl->ev_used;
+  return e;
 }
 
 void release_events(fps_plan *pl) {

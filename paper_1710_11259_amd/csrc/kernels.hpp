@@ -54,7 +54,10 @@ struct SweepArgs {
   int in_f32, g_f32, out_f32;
 };
 
-hipError_t launch_sweep(const SweepArgs &a, hipStream_t st);
+// With ev0 / ev1 non-null the launch records the dispatch's own start and
+// end timestamps in them (no separate event packets).
+hipError_t launch_sweep(const SweepArgs &a, hipStream_t st, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 
 // Batched sweeps over several independent problems in one launch.  The
 // workspace pointers of each descriptor's SweepArgs (in, g, out, lv,

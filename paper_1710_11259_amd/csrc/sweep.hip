@@ -18,6 +18,7 @@
 //   * the right-hand side G enters only the column half-step: the row
 //     half-step's output V - G = R - 2p Y_{1/2} needs no G, and the column
 //     half-step adds G to its right-hand side but not to its output.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -537,13 +538,19 @@ struct SweepLaunch {
   char *base;
   int nwg;
   hipStream_t st;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // optional: timestamps of this dispatch
   template <typename Tin, typename Tg, typename Tout, int kG, bool kPre = false>
   void go() const {
     const int nch = a.nc0 + a.nc1;
     if (d == nullptr) {
       dim3 grid((unsigned)(a.ncols / kCols), (unsigned)nch,
                 (unsigned)(a.nbatch > 0 ? a.nbatch : 1));
-      hipLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kG, kPre>), grid, dim3(kCols * kWaves), 0, st, a);
+      if (ev0 != nullptr)
+        hipExtLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kG, kPre>), grid, dim3(kCols * kWaves), 0, st,
+                              ev0, ev1, 0, a);
+      else
+        hipLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kG, kPre>), grid, dim3(kCols * kWaves), 0, st,
+                           a);
     } else if constexpr (!kPre) {
       hipLaunchKernelGGL((k_sweep_batch<Tin, Tg, Tout, kG>), dim3((unsigned)nwg),
                          dim3(kCols * kWaves), 0, st, d, wg_prob, base);
@@ -587,14 +594,14 @@ hipError_t dispatch_sweep(const SweepLaunch &L, bool with_g) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
+hipError_t launch_sweep(const SweepArgs &a, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const int nchunks = a.nc0 + a.nc1;
   if (a.npad % kCols != 0 || a.ncols % kCols != 0 || nchunks <= 0 || a.in == nullptr)
     return hipErrorInvalidValue;
   if ((a.ab_prev == nullptr) != (a.tab_prev == nullptr)) return hipErrorInvalidValue;
   if (a.out_mode == 0 && (a.ncols != a.npad || a.ld != a.npad)) return hipErrorInvalidValue;
   if (a.ld < a.ncols) return hipErrorInvalidValue;
-  return dispatch_sweep(SweepLaunch{a, nullptr, nullptr, nullptr, 0, st}, a.g != nullptr);
+  return dispatch_sweep(SweepLaunch{a, nullptr, nullptr, nullptr, 0, st, ev0, ev1}, a.g != nullptr);
 }
 
 hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSweep *d,
