@@ -37,14 +37,15 @@ def calibration_copy(torch, dev, mib):
     print(f"# calibration copy {nbytes} bytes read + {nbytes} bytes written", file=sys.stderr)
 
 
-def bench_batch(fps, workloads, torch, tol, reps=3):
+def bench_batch(fps, workloads, torch, tol, reps=3, tight=True):
     """256 independent square solves (n_b = 32 U{1..32}, seed 1): one graph
     launch per batch (FP64 and FP32-refined) against a sequential loop of
     single FP64 solves."""
     import numpy as np
     ns, Fs = workloads.batched_problems()
     dof = float(sum(n * n for n in ns))
-    res = {"problems": len(ns), "dof": dof}
+    res = {"problems": len(ns), "dof": dof,
+           "enclosure": "computed spectrum" if tight else "Lemma B.1"}
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
 
@@ -59,7 +60,7 @@ def bench_batch(fps, workloads, torch, tol, reps=3):
         return ev0.elapsed_time(ev1) / k
 
     # sequential single FP64 solves (the same inputs, one plan per size)
-    plans = {n: fps.plan(n, tol=tol) for n in sorted(set(ns))}
+    plans = {n: fps.plan(n, tol=tol, tight=tight) for n in sorted(set(ns))}
     ws = torch.empty(max(p.workspace_bytes for p in plans.values()), dtype=torch.uint8,
                      device="cuda")
     Fd = [torch.from_numpy(F).cuda() for F in Fs]
@@ -71,7 +72,7 @@ def bench_batch(fps, workloads, torch, tol, reps=3):
     t_seq = timed(seq, 1)
     res["sequential_fp64_ms"] = t_seq
     for prec in ("fp64", "fp32_refined"):
-        b = fps.batch(ns, tol=tol, precision=prec)
+        b = fps.batch(ns, tol=tol, precision=prec, tight=tight)
         g = fps.BatchGraph(b)
         g.F.copy_(b.pack(Fs))
         t = timed(g.replay, reps)
@@ -90,14 +91,14 @@ def bench_batch(fps, workloads, torch, tol, reps=3):
     return res
 
 
-def bench_cube(fps, workloads, torch, tol, n=256, steps=2, check=True):
+def bench_cube(fps, workloads, torch, tol, n=256, steps=2, check=True, tight=True):
     """Cube n^3 solve (two-level nested ADI, FP64): time per solve and the
     fiber sweeps' achieved bandwidth.  Algorithmic bytes per dof: z sweep 24
     (read zR and B, write), inner half-step 1 16, half-step 2 24."""
     import numpy as np
     F_host = workloads.cube_rhs(n)
     F = torch.from_numpy(F_host).cuda()
-    p = fps.plan(n, tol=tol, dim=3)
+    p = fps.plan(n, tol=tol, dim=3, tight=tight)
     counts = p.inner_counts()
     ws = fps.workspace(p, "cuda")
     U = torch.empty(p.out_shape(), dtype=torch.float64, device="cuda")
@@ -131,6 +132,7 @@ def bench_cube(fps, workloads, torch, tol, n=256, steps=2, check=True):
     tot_b = sum(bpd[k] * dof for k in kinds[:len(t)])
     tot_t = sum(t) * 1e-3
     res = {"n": n, "dof": dof, "ms_per_solve": ms, "dof_per_s": dof / (ms * 1e-3),
+           "enclosure": "computed spectrum" if tight else "Lemma B.1",
            "J_outer": p.J, "inner_steps": sum(counts), "sweeps_per_solve": per_solve,
            "sweep_achieved_GBs": round(tot_b / tot_t / 1e9, 1),
            "sweep_frac_of_8TBs": round(tot_b / tot_t / 8e12, 4),
@@ -158,6 +160,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--tol", type=float, default=1e-13)
+    ap.add_argument("--enclosure", choices=["tight", "lemma"], default="tight",
+                    help="shift intervals: computed spectrum (default) or the Lemma B.1 enclosure")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
@@ -183,14 +187,16 @@ def main() -> int:
     if args.only in ("batched", "cube"):
         if args.copy_calib_mib:
             calibration_copy(torch, dev, args.copy_calib_mib)
-        res = (bench_batch(fps, workloads, torch, args.tol) if args.only == "batched" else
-               bench_cube(fps, workloads, torch, args.tol, steps=max(1, args.steps),
-                          check=not args.no_check))
+        tight = args.enclosure == "tight"
+        res = (bench_batch(fps, workloads, torch, args.tol, tight=tight) if args.only == "batched"
+               else bench_cube(fps, workloads, torch, args.tol, steps=max(1, args.steps),
+                               check=not args.no_check, tight=tight))
         print(json.dumps({"form": args.only, **res}), flush=True)
         return 0
     F_host = workloads.square_rhs(n, seed=0)
     F = torch.from_numpy(F_host).to(dev)
-    plan = fps.plan(n, tol=args.tol)
+    tight = args.enclosure == "tight"
+    plan = fps.plan(n, tol=args.tol, tight=tight)
     ws = fps.workspace(plan, dev)
     U = torch.empty(plan.out_shape(), dtype=torch.float64, device=dev)
     print(f"# plan n={n} J={plan.J} ws={plan.workspace_bytes / 2**20:.1f} MiB", file=sys.stderr,
@@ -273,14 +279,31 @@ def main() -> int:
            "config": {"workload": f"square [-1,1]^2 Poisson, zero Dirichlet, n={n} "
                                   f"({n}x{n} Chebyshev coefficients of f, "
                                   f"N(0,1)(1+j)^-2(1+k)^-2, seed 0), FP64, tol {args.tol:g}, "
-                                  f"J={J}, one right-hand side",
-                      "n": n, "J": J, "tol": args.tol},
+                                  f"J={J} (shift intervals: "
+                                  f"{'computed spectrum of A~' if tight else 'Lemma B.1 enclosure'}), "
+                                  "one right-hand side",
+                      "n": n, "J": J, "tol": args.tol,
+                      "enclosure": "computed spectrum" if tight else "Lemma B.1"},
            "roofline": roofline}
 
     # Precision form: FP32 storage with FP64 refinement, same workload and tol.
     forms = {}
     if not args.no_forms or args.only == "fp32_refined":
-        pr = fps.plan(n, tol=args.tol, precision="fp32_refined")
+        po = fps.plan(n, tol=args.tol, tight=not tight)
+        wso = fps.workspace(po, dev)
+        Uo_ = torch.empty(po.out_shape(), dtype=torch.float64, device=dev)
+        fps.solve(po, F, out=Uo_, ws=wso)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            fps.solve(po, F, out=Uo_, ws=wso)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_o = e0.elapsed_time(e1) / args.steps
+        forms["lemma_enclosure" if tight else "computed_spectrum"] = {
+            "ms_per_step": ms_o, "dof_per_s": dof / (ms_o * 1e-3), "J": po.J}
+        del wso, Uo_
+        pr = fps.plan(n, tol=args.tol, precision="fp32_refined", tight=tight)
         wsr = fps.workspace(pr, dev)
         Ur = torch.empty(pr.out_shape(), dtype=torch.float64, device=dev)
         fps.solve(pr, F, out=Ur, ws=wsr)
@@ -297,8 +320,9 @@ def main() -> int:
                                  "f32_steps_per_round": pr.f32_steps}
         del wsr
         if args.only is None:
-            forms["batched"] = bench_batch(fps, workloads, torch, args.tol)
-            forms["cube"] = bench_cube(fps, workloads, torch, args.tol, check=not args.no_check)
+            forms["batched"] = bench_batch(fps, workloads, torch, args.tol, tight=tight)
+            forms["cube"] = bench_cube(fps, workloads, torch, args.tol, check=not args.no_check,
+                                       tight=tight)
     if forms:
         out["forms"] = forms
 

@@ -25,6 +25,7 @@ FPS_OK, FPS_E_ARG, FPS_E_UNSUPPORTED, FPS_E_NOMEM, FPS_E_HIP, FPS_E_STATE = rang
 FPS_FP64, FPS_FP32_REFINED = 0, 1
 FPS_OUT_CHEB, FPS_OUT_NATIVE = 0, 1
 FPS_PLAN_HOST_ONLY = 1
+FPS_PLAN_TIGHT_SPECTRUM = 2
 
 _lib = None
 
@@ -107,14 +108,15 @@ class Plan:
     """Owning wrapper of an fps_plan."""
 
     def __init__(self, n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
-                 out: str = "cheb", host_only: bool = False):
+                 out: str = "cheb", host_only: bool = False, tight: bool = False):
         prec = {"fp64": FPS_FP64, "fp32_refined": FPS_FP32_REFINED}[precision]
         ob = {"cheb": FPS_OUT_CHEB, "native": FPS_OUT_NATIVE}[out]
         h = ctypes.c_void_p()
-        _check(lib().fps_plan_create(ctypes.byref(h), dim, n, 0, tol, prec, ob,
-                                     FPS_PLAN_HOST_ONLY if host_only else 0))
+        flags = (FPS_PLAN_HOST_ONLY if host_only else 0) | (FPS_PLAN_TIGHT_SPECTRUM if tight else 0)
+        _check(lib().fps_plan_create(ctypes.byref(h), dim, n, 0, tol, prec, ob, flags))
         self._h = h
         self.n, self.dim, self.tol, self.precision, self.out = n, dim, tol, precision, out
+        self.tight = tight
         J, ws, oe = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().fps_plan_info(h, ctypes.byref(J), ctypes.byref(ws), ctypes.byref(oe)))
         self.J, self.workspace_bytes, self.out_entries = J.value, ws.value, oe.value
@@ -165,8 +167,8 @@ class Plan:
 
 
 def plan(n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
-         out: str = "cheb", host_only: bool = False) -> Plan:
-    return Plan(n, tol, dim, precision, out, host_only)
+         out: str = "cheb", host_only: bool = False, tight: bool = False) -> Plan:
+    return Plan(n, tol, dim, precision, out, host_only, tight)
 
 
 def _stream_ptr(torch, device):
@@ -277,14 +279,14 @@ class Batch:
     per half-step."""
 
     def __init__(self, ns, tol: float = 1e-13, precision: str = "fp64", out: str = "cheb",
-                 host_only: bool = False):
+                 host_only: bool = False, tight: bool = False):
         prec = {"fp64": FPS_FP64, "fp32_refined": FPS_FP32_REFINED}[precision]
         ob = {"cheb": FPS_OUT_CHEB, "native": FPS_OUT_NATIVE}[out]
         self.ns = [int(v) for v in ns]
         arr = (ctypes.c_int64 * len(self.ns))(*self.ns)
         h = ctypes.c_void_p()
-        _check(lib().fps_batch_create(ctypes.byref(h), 2, len(self.ns), arr, tol, prec, ob,
-                                      FPS_PLAN_HOST_ONLY if host_only else 0))
+        flags = (FPS_PLAN_HOST_ONLY if host_only else 0) | (FPS_PLAN_TIGHT_SPECTRUM if tight else 0)
+        _check(lib().fps_batch_create(ctypes.byref(h), 2, len(self.ns), arr, tol, prec, ob, flags))
         self._h = h
         self.tol, self.precision, self.out = tol, precision, out
         ws, ie, oe, J = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
@@ -328,8 +330,8 @@ class Batch:
 
 
 def batch(ns, tol: float = 1e-13, precision: str = "fp64", out: str = "cheb",
-          host_only: bool = False) -> Batch:
-    return Batch(ns, tol, precision, out, host_only)
+          host_only: bool = False, tight: bool = False) -> Batch:
+    return Batch(ns, tol, precision, out, host_only, tight)
 
 
 def batch_solve(b: Batch, F, out=None, ws=None):

@@ -28,6 +28,14 @@ const char *last_error() { return g_last_error.c_str(); }
 
 bool valid_plan(const fps_plan *p) { return p != nullptr && p->magic == kMagic; }
 
+void spectrum_tight(int64_t n, double *a, double *b) {
+  long double lmin, lmax;
+  fps::atilde_extremes(n, &lmin, &lmax);
+  constexpr long double kMargin = 1e-6L;  // relative widening (bisection and rounding)
+  *a = (double)(lmin * (1.0L + kMargin));
+  *b = (double)(lmax * (1.0L - kMargin));
+}
+
 int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
 hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st) {
@@ -291,7 +299,7 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   if (!(tol > 0.0 && tol < 1.0)) return fail(FPS_E_ARG, "tol must lie in (0, 1)");
   if (prec != FPS_FP64 && prec != FPS_FP32_REFINED) return fail(FPS_E_ARG, "bad precision");
   if (out_basis != FPS_OUT_CHEB && out_basis != FPS_OUT_NATIVE) return fail(FPS_E_ARG, "bad out_basis");
-  if (flags & ~FPS_PLAN_HOST_ONLY) return fail(FPS_E_ARG, "unknown flags");
+  if (flags & ~(FPS_PLAN_HOST_ONLY | FPS_PLAN_TIGHT_SPECTRUM)) return fail(FPS_E_ARG, "unknown flags");
   if (dim == 3 && prec != FPS_FP64)
     return fail(FPS_E_UNSUPPORTED, "the cube solver runs in FP64 only");
   if (dim == 3 && n > 1024) return fail(FPS_E_UNSUPPORTED, "cube solves are limited to n <= 1024");
@@ -333,7 +341,9 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
     pl->rounds = std::max(1, (int)std::ceil(std::log(tol) / std::log(kRoundFactor) - 1e-9));
   }
   std::string err;
-  if (!fps::zolotarev_shifts(-1.0, -delta, delta, 1.0, adi_tol, pl->shifts, err)) {
+  double ea = -1.0, eb = -delta;  // enclosure of sigma(A~)
+  if (flags & FPS_PLAN_TIGHT_SPECTRUM) spectrum_tight(n, &ea, &eb);
+  if (!fps::zolotarev_shifts(ea, eb, -eb, -ea, adi_tol, pl->shifts, err)) {
     delete pl;
     return fail(FPS_E_ARG, err);
   }

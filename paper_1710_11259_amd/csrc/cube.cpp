@@ -107,8 +107,17 @@ Dims full_dims(const fps::Layout &L) {
 fps_status cube_plan_build(fps_plan *pl) {
   const int64_t n = pl->n;
   const double delta = 1.0 / (30.0 * (double)n * (double)n * (double)n * (double)n);
+  // sigma(K) = -1 / sigma(A~) in [klo, khi]: [1, 1/delta] from Lemma B.1, or
+  // from the computed extreme eigenvalues.
+  double klo = 1.0, khi = 1.0 / delta;
+  if (pl->flags & FPS_PLAN_TIGHT_SPECTRUM) {
+    double a, b;
+    spectrum_tight(n, &a, &b);
+    klo = -1.0 / a;
+    khi = -1.0 / b;
+  }
   std::string err;
-  if (!fps::zolotarev_shifts(-2.0 / delta, -2.0, 1.0, 1.0 / delta, pl->tol, pl->shifts, err))
+  if (!fps::zolotarev_shifts(-2.0 * khi, -2.0 * klo, klo, khi, pl->tol, pl->shifts, err))
     return fail(FPS_E_ARG, err);
   // The outer iteration needs its (x, y) half-steps solved well below its
   // own tolerance.
@@ -125,8 +134,8 @@ fps_status cube_plan_build(fps_plan *pl) {
   for (int i = 0; i < J1; ++i) {
     const double c = 0.5 * pl->shifts.q[i];
     fps::ShiftSet in;
-    if (!fps::zolotarev_shifts(-(1.0 / delta + c), -(1.0 + c), 1.0 + c, 1.0 / delta + c,
-                               pl->cube_inner_tol, in, err))
+    if (!fps::zolotarev_shifts(-(khi + c), -(klo + c), klo + c, khi + c, pl->cube_inner_tol, in,
+                               err))
       return fail(FPS_E_ARG, err);
     pl->inner_J[i] = in.J;
     pl->inner_off[i] = (int)pl->inner_p.size();

@@ -157,6 +157,53 @@ double atilde_off(int64_t i) {
   return 1.0 / ((2 * x + 5) * std::sqrt((2 * x + 3) * (2 * x + 7)));
 }
 
+namespace {
+
+// Number of eigenvalues below x of the parity-s block of A~ (m positions):
+// the negative pivots of the LDL^T factorization of the block minus x I.
+int64_t sturm_count(int64_t m, int s, long double x) {
+  int64_t cnt = 0;
+  long double q = 1.0L;
+  for (int64_t k = 0; k < m; ++k) {
+    const long double d = (long double)atilde_diag(2 * k + s) - x;
+    if (k == 0) {
+      q = d;
+    } else {
+      const long double e = atilde_off(2 * (k - 1) + s);
+      q = d - e * e / q;
+    }
+    if (q == 0.0L) q = -1e-4000L;  // a zero pivot counts as negative (x just above an eigenvalue)
+    if (q < 0.0L) ++cnt;
+  }
+  return cnt;
+}
+
+}  // namespace
+
+void atilde_extremes(int64_t n, long double *lmin, long double *lmax) {
+  // Lemma B.1 encloses the spectrum in [-1, 0); bisect each parity block's
+  // extreme eigenvalues inside it.
+  long double lo_all = 0.0L, hi_all = -1.0L;
+  for (int s = 0; s < 2; ++s) {
+    const int64_t m = (n - s + 1) / 2;
+    if (m == 0) continue;
+    long double lo = -1.0L, hi = 0.0L;  // smallest: count(x) >= 1
+    for (int it = 0; it < 200; ++it) {
+      const long double mid = 0.5L * (lo + hi);
+      if (sturm_count(m, s, mid) >= 1) hi = mid; else lo = mid;
+    }
+    lo_all = std::min(lo_all, lo);
+    lo = -1.0L, hi = 0.0L;  // largest: count(x) == m
+    for (int it = 0; it < 200; ++it) {
+      const long double mid = 0.5L * (lo + hi);
+      if (sturm_count(m, s, mid) >= m) hi = mid; else lo = mid;
+    }
+    hi_all = std::max(hi_all, hi);
+  }
+  *lmin = lo_all;
+  *lmax = hi_all;
+}
+
 void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vector<double> &pos,
                         std::vector<double> &chunk, std::vector<double> &comb,
                         std::vector<double> &l1) {

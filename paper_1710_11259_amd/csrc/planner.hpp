@@ -73,6 +73,10 @@ struct Layout {
 };
 Layout make_layout(int64_t n);
 
+// Smallest and largest eigenvalue of A~ (n x n, both parity blocks) by
+// Sturm-sequence bisection in extended precision; both are negative.
+void atilde_extremes(int64_t n, long double *lmin, long double *lmax);
+
 // Entries of A~ = -S^-1 M S^-1 (symmetric, zero +-1 diagonals):
 // diagonal at index i, and coupling between i and i+2.
 double atilde_diag(int64_t i);

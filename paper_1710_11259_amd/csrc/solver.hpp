@@ -111,6 +111,9 @@ namespace fps {
 namespace detail {
 
 bool valid_plan(const fps_plan *p);
+// Enclosure [a, b] of sigma(A~) (both negative) from the computed extreme
+// eigenvalues, widened by a relative 1e-6.
+void spectrum_tight(int64_t n, double *a, double *b);
 int64_t align256(int64_t x);
 template <typename T>
 fps_status upload(DeviceBuf &b, const std::vector<T> &h) {

@@ -31,6 +31,13 @@ void shim_conversions(long long n, double *R0, double *R1, double *P0, double *P
   std::memcpy(P0, P[0].data(), P[0].size() * sizeof(double));
   std::memcpy(P1, P[1].data(), P[1].size() * sizeof(double));
 }
+void shim_extremes(long long n, double *out) {
+  long double lo, hi;
+  fps::atilde_extremes(n, &lo, &hi);
+  out[0] = (double)lo;
+  out[1] = (double)hi;
+}
+
 int shim_dn(double alpha, int J, double *dn) {
   long double m1 = 1.0L / ((long double)alpha * alpha);
   long double K = fps::ellip_K_comp(m1);

@@ -51,3 +51,16 @@ def test_cube_headline_size():
     err = np.linalg.norm(U - Uo) / np.linalg.norm(Uo)
     print(f"cube n=256 rel err {err:.3e}", flush=True)
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("n", [5, 64, 256])
+def test_cube_tight_spectrum_matches_exact(n):
+    F = workloads.cube_rhs(n)
+    p = fps.plan(n, tol=1e-13, dim=3, tight=True)
+    print(f"cube tight n={n} J_outer={p.J} inner={sum(p.inner_counts())}", flush=True)
+    U = fps.solve(p, torch.from_numpy(F).cuda())
+    torch.cuda.synchronize()
+    Uo = cube.poisson_cube(F)
+    err = np.linalg.norm(U.cpu().numpy() - Uo) / np.linalg.norm(Uo)
+    print(f"rel err {err:.3e}", flush=True)
+    assert err <= 1e-12

@@ -92,3 +92,17 @@ def test_headline_size_full_parity():
     err = _rel(Ug, Uo)
     print(f"n=4096 rel err {err:.3e}", flush=True)
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 300, 1024, 4096])
+def test_tight_spectrum_solve_matches_exact(n):
+    # Shift intervals from the computed spectrum (fewer iterations, same bound).
+    F = workloads.square_rhs(n, seed=0)
+    p = fps.plan(n, tol=1e-13, tight=True)
+    print(f"tight n={n} J={p.J}", flush=True)
+    U = fps.solve(p, torch.from_numpy(F).cuda())
+    torch.cuda.synchronize()
+    Uo = square.poisson_square(F)
+    err = np.linalg.norm(U.cpu().numpy() - Uo) / np.linalg.norm(Uo)
+    print(f"rel err {err:.3e}", flush=True)
+    assert err <= 1e-12

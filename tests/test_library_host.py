@@ -158,6 +158,7 @@ def shim(tmp_path_factory):
     L.shim_tables.argtypes = [ctypes.c_longlong, ctypes.c_int, P, P, P]
     L.shim_conversions.argtypes = [ctypes.c_longlong, P, P, P, P]
     L.shim_dn.argtypes = [ctypes.c_double, ctypes.c_int, P]
+    L.shim_extremes.argtypes = [ctypes.c_longlong, P]
     return L
 
 
@@ -314,3 +315,32 @@ def test_carry_combinations_match_recurrence(shim, n):
             W = comb[jj, s, :ncs, :ncs]
             assert np.allclose(W[..., 0] @ yl, cf, rtol=1e-13, atol=1e-13)
             assert np.allclose(W[..., 1] @ yl + W[..., 2] @ xf, cb, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 301, 1024])
+def test_extreme_eigenvalues_match_lapack(shim, n):
+    # Sturm bisection in the planner against LAPACK (the oracle's parity
+    # eigen-decomposition); the largest eigenvalue is O(n^-4), so compare
+    # relatively.
+    out = (ctypes.c_double * 2)()
+    shim.shim_extremes(n, out)
+    lam, _ = square.atilde_eig(n)
+    assert out[0] == pytest.approx(lam.min(), rel=1e-12)
+    assert out[1] == pytest.approx(lam.max(), rel=1e-9)
+
+
+@pytest.mark.parametrize("n", [64, 1024, 4096])
+def test_tight_spectrum_plan_counts(n):
+    # J from (2.9) on the computed spectrum widened by 1e-6 (the enclosure the
+    # flag documents); the counts agree with those of the exact eigenvalues.
+    lam, _ = square.atilde_eig(n) if n <= 1024 else (None, None)
+    p = fps.plan(n, tol=1e-13, host_only=True, tight=True)
+    d = fps.plan(n, tol=1e-13, host_only=True)
+    assert p.J < d.J
+    if lam is not None:
+        a, b = lam.min() * (1 + 1e-6), lam.max() * (1 - 1e-6)
+        assert p.J == oshifts.iteration_count(a, b, -b, -a, 1e-13)
+        J, po, _ = oshifts.zolotarev_shifts(a, b, -b, -a, tol=1e-13)
+        np.testing.assert_allclose(p.shifts(), po, rtol=1e-8)
+    expected = {64: 44, 1024: 78, 4096: 96}
+    assert p.J == expected[n]
