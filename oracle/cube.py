@@ -214,3 +214,54 @@ def kform_outer_closed_form(G: np.ndarray, tol_outer: float) -> np.ndarray:
     for m in range(3):
         Yh = mode_product(Yh, V, m)
     return Yh
+
+
+# --- z-eigenbasis variant: one 2D ADI per z-slice ---------------------------
+
+def zeig_slice_intervals(n: int, mu: float, lam_min: float, lam_max: float):
+    """Intervals of Algorithm 2 for the slice equation in the z-eigenbasis.
+
+    With P = A~ + mu I (mu an eigenvalue of A~), the slice equation
+    P Y P - mu^2 Y = -G^ becomes, for Z = P Y,
+        (-mu^2 P^-1) Z - Z (-P) = -G^,
+    with sigma(-mu^2 P^-1) in [mu^2/(|lmin| + |mu|), mu^2/(|lmax| + |mu|)]
+    and sigma(-P) in [|lmax| + |mu|, |lmin| + |mu|] for sigma(A~) in
+    [lmin, lmax] (both negative): separated by |mu|."""
+    m = abs(mu)
+    return (mu * mu / (abs(lam_min) + m), mu * mu / (abs(lam_max) + m),
+            abs(lam_max) + m, abs(lam_min) + m)
+
+
+def zeig_adi(G: np.ndarray, tol: float, tight: bool = True):
+    """Y of the symmetric cube system through the z-eigenbasis: transform G
+    along z with the eigenvectors of A~, run Algorithm 2 on every slice
+    (A = -mu^2 P^-1 on the left (y), B = -P on the right (x), F = -G^), then
+    Y = P^-1 Z and transform back.  Dense small-n version.  Returns (Y, J per
+    slice)."""
+    from .shifts import square_enclosure, zolotarev_shifts
+    from .square import atilde_dense, atilde_eig
+    n = G.shape[0]
+    A = atilde_dense(n)
+    I = np.eye(n)
+    lam, V = atilde_eig(n)
+    if tight:
+        lmin, lmax = lam.min() * (1 + 1e-6), lam.max() * (1 - 1e-6)
+    else:
+        lmin, lmax = square_enclosure(n)[0:2]
+    Gh = mode_product(G, V.T, 0)
+    Yh = np.empty_like(Gh)
+    counts = []
+    for c, mu in enumerate(lam):
+        P = A + mu * I
+        a, b, cc, d = zeig_slice_intervals(n, mu, lmin, lmax)
+        J, p, q = zolotarev_shifts(a, b, cc, d, tol=tol)
+        counts.append(J)
+        As = -mu * mu * np.linalg.inv(P)
+        Bs = -P
+        F = -Gh[c]
+        Z = np.zeros_like(F)
+        for pj, qj in zip(p, q):
+            Zh = np.linalg.solve((Bs - pj * I).T, (F - (As - pj * I) @ Z).T).T
+            Z = np.linalg.solve(As - qj * I, F - Zh @ (Bs - qj * I))
+        Yh[c] = np.linalg.solve(P, Z)
+    return mode_product(Yh, V, 0), counts

@@ -180,6 +180,76 @@ int64_t sturm_count(int64_t m, int s, long double x) {
 
 }  // namespace
 
+bool tridiag_eigen(std::vector<long double> &d, std::vector<long double> e,
+                   std::vector<long double> &Q) {
+  const int64_t m = (int64_t)d.size();
+  Q.assign((size_t)(m * m), 0.0L);
+  for (int64_t i = 0; i < m; ++i) Q[(size_t)(i * m + i)] = 1.0L;
+  e.resize(m > 0 ? m : 1, 0.0L);
+  const long double eps = std::numeric_limits<long double>::epsilon();
+  auto negligible = [&](int64_t k) {  // coupling of k and k+1
+    return std::fabs(e[k]) <= eps * (std::fabs(d[k]) + std::fabs(d[k + 1]));
+  };
+  int64_t h = m - 1, iters = 0;
+  while (h > 0) {
+    if (negligible(h - 1)) {
+      e[h - 1] = 0.0L;
+      --h;
+      continue;
+    }
+    if (++iters > 60 * m) return false;
+    int64_t l = h - 1;
+    while (l > 0 && !negligible(l - 1)) --l;
+    // Wilkinson shift: eigenvalue of the trailing 2 x 2 block nearer d[h].
+    const long double t = 0.5L * (d[h - 1] - d[h]);
+    const long double eh = e[h - 1];
+    const long double den = t + (t >= 0 ? 1.0L : -1.0L) * std::sqrt(t * t + eh * eh);
+    const long double mu = d[h] - eh * eh / den;
+    // Bulge chase with Givens rotations G = [[c, s], [-s, c]] on (k, k+1):
+    // new basis vectors c v_k - s v_{k+1} and s v_k + c v_{k+1}.
+    long double x = d[l] - mu, z = e[l], bulge = 0.0L;
+    for (int64_t k = l; k < h; ++k) {
+      long double c, sn;
+      if (k == l) {
+        const long double r = std::sqrt(x * x + z * z);
+        c = x / r;
+        sn = -z / r;
+      } else {
+        const long double r = std::sqrt(e[k - 1] * e[k - 1] + bulge * bulge);
+        c = e[k - 1] / r;
+        sn = -bulge / r;
+        e[k - 1] = r;
+      }
+      const long double a = d[k], b = e[k], cc = d[k + 1];
+      d[k] = c * c * a - 2.0L * c * sn * b + sn * sn * cc;
+      d[k + 1] = sn * sn * a + 2.0L * c * sn * b + c * c * cc;
+      e[k] = c * sn * (a - cc) + (c * c - sn * sn) * b;
+      if (k + 1 < h) {
+        bulge = -sn * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+      }
+      for (int64_t i = 0; i < m; ++i) {
+        long double *row = &Q[(size_t)(i * m)];
+        const long double qk = row[k], qk1 = row[k + 1];
+        row[k] = c * qk - sn * qk1;
+        row[k + 1] = sn * qk + c * qk1;
+      }
+    }
+  }
+  // ascending order
+  std::vector<int64_t> idx(m);
+  for (int64_t i = 0; i < m; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return d[a] < d[b]; });
+  std::vector<long double> d2(m), Q2((size_t)(m * m));
+  for (int64_t j = 0; j < m; ++j) {
+    d2[j] = d[idx[j]];
+    for (int64_t i = 0; i < m; ++i) Q2[(size_t)(i * m + j)] = Q[(size_t)(i * m + idx[j])];
+  }
+  d.swap(d2);
+  Q.swap(Q2);
+  return true;
+}
+
 void atilde_extremes(int64_t n, long double *lmin, long double *lmax) {
   // Lemma B.1 encloses the spectrum in [-1, 0); bisect each parity block's
   // extreme eigenvalues inside it.

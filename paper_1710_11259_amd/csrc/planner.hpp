@@ -73,6 +73,14 @@ struct Layout {
 };
 Layout make_layout(int64_t n);
 
+// Eigen-decomposition of a symmetric tridiagonal matrix (diagonal d[0..m-1],
+// off-diagonal e[0..m-2]) by implicit QR steps with Wilkinson shifts and
+// Givens rotations in extended precision.  On return d holds the
+// eigenvalues in ascending order and Q (m x m, row-major) the orthonormal
+// eigenvectors as columns.  Returns false if the iteration does not settle.
+bool tridiag_eigen(std::vector<long double> &d, std::vector<long double> e,
+                   std::vector<long double> &Q);
+
 // Smallest and largest eigenvalue of A~ (n x n, both parity blocks) by
 // Sturm-sequence bisection in extended precision; both are negative.
 void atilde_extremes(int64_t n, long double *lmin, long double *lmax);

@@ -1,5 +1,7 @@
 // Test-only C shim over the host planner (built with g++ by the CPU tests).
 #include <cstring>
+#include <vector>
+
 #include "../paper_1710_11259_amd/csrc/planner.hpp"
 
 extern "C" {
@@ -31,6 +33,18 @@ void shim_conversions(long long n, double *R0, double *R1, double *P0, double *P
   std::memcpy(P0, P[0].data(), P[0].size() * sizeof(double));
   std::memcpy(P1, P[1].data(), P[1].size() * sizeof(double));
 }
+// Eigen-decomposition of the parity-s block of A~: m eigenvalues, m x m vectors.
+int shim_atilde_eigen(long long n, int s, double *lam, double *Q) {
+  const long long m = (n - s + 1) / 2;
+  std::vector<long double> d(m), e(m > 1 ? m - 1 : 0), q;
+  for (long long k = 0; k < m; ++k) d[k] = fps::atilde_diag(2 * k + s);
+  for (long long k = 0; k + 1 < m; ++k) e[k] = fps::atilde_off(2 * k + s);
+  if (!fps::tridiag_eigen(d, e, q)) return 0;
+  for (long long k = 0; k < m; ++k) lam[k] = (double)d[k];
+  for (long long k = 0; k < m * m; ++k) Q[k] = (double)q[k];
+  return 1;
+}
+
 void shim_extremes(long long n, double *out) {
   long double lo, hi;
   fps::atilde_extremes(n, &lo, &hi);

@@ -344,3 +344,28 @@ def test_tight_spectrum_plan_counts(n):
         np.testing.assert_allclose(p.shifts(), po, rtol=1e-8)
     expected = {64: 44, 1024: 78, 4096: 96}
     assert p.J == expected[n]
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 40, 257])
+def test_tridiagonal_eigensolver_matches_lapack(shim, n):
+    # Planner's implicit-QR eigen-decomposition of each parity block of A~:
+    # eigenvalues against LAPACK (relative, they span O(n^-4) .. 0.4), and
+    # an orthonormal eigenbasis that diagonalizes the block.
+    A = square.atilde_dense(n)
+    for s in (0, 1):
+        m = (n - s + 1) // 2
+        if m == 0:
+            continue
+        lam = (ctypes.c_double * m)()
+        Q = (ctypes.c_double * (m * m))()
+        shim.shim_atilde_eigen.argtypes = [ctypes.c_longlong, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]
+        assert shim.shim_atilde_eigen(n, s, lam, Q) == 1
+        lam = np.array(lam)
+        Q = np.array(Q).reshape(m, m)
+        B = A[s::2, s::2]
+        ref = np.linalg.eigvalsh(B)
+        np.testing.assert_allclose(lam, ref, rtol=1e-10, atol=0)
+        assert np.abs(Q.T @ Q - np.eye(m)).max() < 1e-14
+        assert np.abs(Q.T @ B @ Q - np.diag(lam)).max() < 1e-15

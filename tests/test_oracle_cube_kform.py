@@ -72,3 +72,31 @@ def test_nested_kform_adi_matches_exact_solution(n):
     err = np.linalg.norm((Yk - Y) * w) / np.linalg.norm(Y * w)
     assert err <= 1e-12
     assert len(J2) == J1 and min(J2) >= 1
+
+
+@pytest.mark.parametrize("n", [1, 4, 9])
+@pytest.mark.parametrize("tight", [True, False])
+def test_zeig_slice_adi_matches_exact_solution(n, tight):
+    G, Y = _case(n)
+    Yz, counts = cube.zeig_adi(G, 1e-13, tight=tight)
+    s = square.s_diag(n)
+    w = 1.0 / (s[:, None, None] * s[None, :, None] * s[None, None, :])
+    err = np.linalg.norm((Yz - Y) * w) / np.linalg.norm(Y * w)
+    assert err <= 1e-12
+    assert len(counts) == n
+
+
+def test_zeig_slice_intervals_contain_spectra():
+    # sigma(-mu^2 P^-1) and sigma(-P) inside the stated intervals, which are
+    # separated by |mu|.
+    n = 24
+    A = square.atilde_dense(n)
+    lam, _ = square.atilde_eig(n)
+    for mu in lam[:: 5]:
+        P = A + mu * np.eye(n)
+        ea = np.linalg.eigvalsh(-mu * mu * np.linalg.inv(P))
+        eb = np.linalg.eigvalsh(-P)
+        a, b, c, d = cube.zeig_slice_intervals(n, mu, lam.min(), lam.max())
+        assert a * (1 - 1e-12) <= ea.min() and ea.max() <= b * (1 + 1e-12)
+        assert c * (1 - 1e-12) <= eb.min() and eb.max() <= d * (1 + 1e-12)
+        assert b < abs(mu) < c
