@@ -75,6 +75,13 @@ typedef enum { FPS_OUT_CHEB = 0, FPS_OUT_NATIVE = 1 } fps_out;
  * contain the spectra, so the error bound and tol keep their meaning; J
  * drops (121 -> 96 at n = 4096, tol 1e-13). */
 #define FPS_PLAN_TIGHT_SPECTRUM 2u
+/* Cube plans: solve through the eigenbasis of A~ along z (dense MFMA
+ * transforms) and one 2D ADI per z-slice, instead of the two-level nested
+ * ADI.  Each slice equation (A~ + mu) Y (A~ + mu) - mu^2 Y = -G^ (mu an
+ * eigenvalue of A~) is solved for Z = (A~ + mu) Y as
+ * (-mu^2 (A~ + mu)^-1) Z - Z (-(A~ + mu)) = -G^ by Algorithm 2 with the slice's
+ * own Zolotarev shifts; n <= 512. */
+#define FPS_PLAN_CUBE_ZEIG 4u
 
 /*
  * Create a plan for a solve of size n (coefficients per dimension).
@@ -103,11 +110,17 @@ fps_status fps_plan_info(const fps_plan *plan, int *J, int64_t *workspace_bytes,
  * for FPS_FP64).  Either pointer may be null. */
 fps_status fps_plan_refinement(const fps_plan *plan, int *rounds, int *f32_steps);
 
-/* Cube plans (dim = 3): the number of inner ADI steps of each of the J
- * outer steps (the (x, y) half-step of outer step i runs counts[i] inner
- * iterations on every z-slice).  Writes min(J, cap) entries; FPS_E_STATE for
- * a square plan. */
+/* Cube plans (dim = 3, nested ADI): the number of inner ADI steps of each of
+ * the J outer steps (the (x, y) half-step of outer step i runs counts[i]
+ * inner iterations on every z-slice).  Writes min(J, cap) entries;
+ * FPS_E_STATE for square and z-eigenbasis plans. */
 fps_status fps_plan_inner_counts(const fps_plan *plan, int *counts, int cap);
+
+/* Cube plans with FPS_PLAN_CUBE_ZEIG: the number of z-slices solved (*count,
+ * = n) and, if counts is non-null, the ADI steps of each slice (slices
+ * sorted by decreasing count; min(*count, cap) entries).  FPS_E_STATE for
+ * other plans. */
+fps_status fps_plan_slice_counts(const fps_plan *plan, int *counts, int cap, int *count);
 
 /* Copy the plan's shifts p_0..p_{J-1} to host memory (q_j = -p_j for the
  * square, Sec. 3.3 P2 with B~ = -A~; for the cube, the outer shifts p_i in
@@ -165,7 +178,11 @@ fps_status fps_adi_native(fps_plan *plan, const double *G_dev, double *Y_dev, vo
  * ms_host[0..min(count, cap)-1] (ms_host may be null when cap is 0), sets
  * *launches to their count, and resets the count.  Square plans: half-step 1
  * and half-step 2 of Algorithm 2 alternate, starting with half-step 1; cube
- * plans: per outer step one z sweep, then the inner half-steps 1 and 2.
+ * plans: per outer step one z sweep, then the inner half-steps 1 and 2;
+ * z-eigenbasis cube plans: per step j the x solves of all slices still
+ * iterating, then the y solves of the slices with a later step (stencil),
+ * then those of the slices at their last step (each launch only if it has
+ * slices).
  */
 fps_status fps_plan_set_sweep_timing(fps_plan *plan, int capacity);
 fps_status fps_plan_sweep_time(fps_plan *plan, double *ms_host, int64_t cap, int64_t *launches);

@@ -26,6 +26,7 @@ FPS_FP64, FPS_FP32_REFINED = 0, 1
 FPS_OUT_CHEB, FPS_OUT_NATIVE = 0, 1
 FPS_PLAN_HOST_ONLY = 1
 FPS_PLAN_TIGHT_SPECTRUM = 2
+FPS_PLAN_CUBE_ZEIG = 4
 
 _lib = None
 
@@ -54,6 +55,8 @@ def lib() -> ctypes.CDLL:
     L.fps_plan_refinement.argtypes = [vp, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int)]
     L.fps_plan_inner_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+    L.fps_plan_slice_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]
     L.fps_adi_shifts.argtypes = [dbl, dbl, dbl, dbl, dbl, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(dbl),
                                  ctypes.POINTER(dbl)]
@@ -78,7 +81,7 @@ def lib() -> ctypes.CDLL:
     L.fps_last_error.restype = ctypes.c_char_p
     L.fps_version.restype = ctypes.c_char_p
     for name in ("fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_plan_refinement",
-                 "fps_plan_inner_counts",
+                 "fps_plan_inner_counts", "fps_plan_slice_counts",
                  "fps_adi_shifts", "fps_solve", "fps_solve_adjoint", "fps_adi_native",
                  "fps_batch_create", "fps_batch_info", "fps_batch_solve"):
         getattr(L, name).restype = ctypes.c_int
@@ -108,15 +111,17 @@ class Plan:
     """Owning wrapper of an fps_plan."""
 
     def __init__(self, n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
-                 out: str = "cheb", host_only: bool = False, tight: bool = False):
+                 out: str = "cheb", host_only: bool = False, tight: bool = False,
+                 zeig: bool = False):
         prec = {"fp64": FPS_FP64, "fp32_refined": FPS_FP32_REFINED}[precision]
         ob = {"cheb": FPS_OUT_CHEB, "native": FPS_OUT_NATIVE}[out]
         h = ctypes.c_void_p()
-        flags = (FPS_PLAN_HOST_ONLY if host_only else 0) | (FPS_PLAN_TIGHT_SPECTRUM if tight else 0)
+        flags = ((FPS_PLAN_HOST_ONLY if host_only else 0) | (FPS_PLAN_TIGHT_SPECTRUM if tight else 0)
+                 | (FPS_PLAN_CUBE_ZEIG if zeig else 0))
         _check(lib().fps_plan_create(ctypes.byref(h), dim, n, 0, tol, prec, ob, flags))
         self._h = h
         self.n, self.dim, self.tol, self.precision, self.out = n, dim, tol, precision, out
-        self.tight = tight
+        self.tight, self.zeig = tight, zeig
         J, ws, oe = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().fps_plan_info(h, ctypes.byref(J), ctypes.byref(ws), ctypes.byref(oe)))
         self.J, self.workspace_bytes, self.out_entries = J.value, ws.value, oe.value
@@ -132,6 +137,14 @@ class Plan:
         p = (ctypes.c_double * self.J)()
         _check(lib().fps_plan_shifts(self._h, p))
         return list(p)
+
+    def slice_counts(self):
+        """Cube plans with zeig: ADI steps per z-slice (descending)."""
+        k = ctypes.c_int()
+        _check(lib().fps_plan_slice_counts(self._h, None, 0, ctypes.byref(k)))
+        c = (ctypes.c_int * max(k.value, 1))()
+        _check(lib().fps_plan_slice_counts(self._h, c, k.value, ctypes.byref(k)))
+        return list(c)[: k.value]
 
     def inner_counts(self):
         """Cube plans: inner ADI steps per outer step."""
@@ -167,8 +180,9 @@ class Plan:
 
 
 def plan(n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
-         out: str = "cheb", host_only: bool = False, tight: bool = False) -> Plan:
-    return Plan(n, tol, dim, precision, out, host_only, tight)
+         out: str = "cheb", host_only: bool = False, tight: bool = False,
+         zeig: bool = False) -> Plan:
+    return Plan(n, tol, dim, precision, out, host_only, tight, zeig)
 
 
 def _stream_ptr(torch, device):

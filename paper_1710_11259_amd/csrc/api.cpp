@@ -299,7 +299,12 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   if (!(tol > 0.0 && tol < 1.0)) return fail(FPS_E_ARG, "tol must lie in (0, 1)");
   if (prec != FPS_FP64 && prec != FPS_FP32_REFINED) return fail(FPS_E_ARG, "bad precision");
   if (out_basis != FPS_OUT_CHEB && out_basis != FPS_OUT_NATIVE) return fail(FPS_E_ARG, "bad out_basis");
-  if (flags & ~(FPS_PLAN_HOST_ONLY | FPS_PLAN_TIGHT_SPECTRUM)) return fail(FPS_E_ARG, "unknown flags");
+  if (flags & ~(FPS_PLAN_HOST_ONLY | FPS_PLAN_TIGHT_SPECTRUM | FPS_PLAN_CUBE_ZEIG))
+    return fail(FPS_E_ARG, "unknown flags");
+  if ((flags & FPS_PLAN_CUBE_ZEIG) && dim != 3)
+    return fail(FPS_E_ARG, "FPS_PLAN_CUBE_ZEIG applies to cube plans only");
+  if ((flags & FPS_PLAN_CUBE_ZEIG) && n > 512)
+    return fail(FPS_E_UNSUPPORTED, "the z-eigenbasis cube method is limited to n <= 512");
   if (dim == 3 && prec != FPS_FP64)
     return fail(FPS_E_UNSUPPORTED, "the cube solver runs in FP64 only");
   if (dim == 3 && n > 1024) return fail(FPS_E_UNSUPPORTED, "cube solves are limited to n <= 1024");
@@ -447,9 +452,20 @@ fps_status fps_plan_refinement(const fps_plan *pl, int *rounds, int *f32_steps) 
 
 fps_status fps_plan_inner_counts(const fps_plan *pl, int *counts, int cap) {
   if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
-  if (pl->dim != 3) return fail(FPS_E_STATE, "inner counts exist for cube plans only");
+  if (pl->dim != 3 || pl->zeig)
+    return fail(FPS_E_STATE, "inner counts exist for nested-ADI cube plans only");
   if (!counts && cap > 0) return fail(FPS_E_ARG, "null output");
   for (int i = 0; i < pl->shifts.J && i < cap; ++i) counts[i] = pl->inner_J[i];
+  return FPS_OK;
+}
+
+fps_status fps_plan_slice_counts(const fps_plan *pl, int *counts, int cap, int *count) {
+  if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (!pl->zeig) return fail(FPS_E_STATE, "slice counts exist for z-eigenbasis cube plans only");
+  const int K = (int)pl->zJ.size();
+  if (count) *count = K;
+  if (counts)
+    for (int k = 0; k < K && k < cap; ++k) counts[k] = pl->zJ[k];
   return FPS_OK;
 }
 

@@ -104,7 +104,12 @@ Dims full_dims(const fps::Layout &L) {
 
 }  // namespace
 
+fps_status zeig_build(fps_plan *pl);
+fps_status zeig_upload(fps_plan *pl);
+fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStream_t st);
+
 fps_status cube_plan_build(fps_plan *pl) {
+  if (pl->flags & FPS_PLAN_CUBE_ZEIG) return zeig_build(pl);
   const int64_t n = pl->n;
   const double delta = 1.0 / (30.0 * (double)n * (double)n * (double)n * (double)n);
   // sigma(K) = -1 / sigma(A~) in [klo, khi]: [1, 1/delta] from Lemma B.1, or
@@ -186,6 +191,7 @@ fps_status cube_plan_build(fps_plan *pl) {
 }
 
 fps_status cube_plan_upload(fps_plan *pl) {
+  if (pl->zeig) return zeig_upload(pl);
   const fps::Layout &L = pl->L;
   fps_status s;
   // Input map blocks Rb_s = A~_s^-1 (S^-1 R)_s, zero padded to mp x mp, and
@@ -266,6 +272,7 @@ fps_status cube_plan_upload(fps_plan *pl) {
 }
 
 fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStream_t st) {
+  if (pl->zeig) return zeig_solve(pl, F, U, w, st);
   const fps::Layout &L = pl->L;
   const int64_t npad = L.npad, ch = npad * npad, mp0 = L.mp[0];
   double *B = (double *)(w + pl->off_G), *ZR = (double *)(w + pl->off_ZR);
@@ -395,6 +402,386 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
   FPS_HIP(fps::launch_gemm_table((const fps::GemmDesc *)pl->d_gy_out.p,
                                  (const int *)pl->d_gy_map_out.p, pl->gy_tiles[1], w, nullptr, st));
   mode_probs(RX, d2, O0, d3, 0, MA, ldm, MB, ldb, N, K, pz);
+  if ((s = launch_probs(pz, st)) != FPS_OK) return s;
+  FPS_HIP(fps::launch_permute3_out(O0, U, L.n + 2, mq, mb0, nullptr, st));
+  return FPS_OK;
+}
+
+// --- z-eigenbasis method ---------------------------------------------------
+//
+// G^ = G x_z V^T (V: eigenvectors of A~, parity blocks), then on every slice
+// c (eigenvalue mu_c, P = A~ + mu_c) Algorithm 2 for
+//   A_s Z - Z B_s = F_s,  A_s = -mu^2 P^-1 (y, left), B_s = -P (x, right),
+//   F_s = -G^_c,  Z = P Y_c,
+// in pass form: R_0 = -F_s = G^_c;
+//   x solve:  x = (P + p_j)^-1 R along x, out V - F = R - (p_j - q_j) x;
+//   y solve:  x = (q_j P + mu^2)^-1 P V along y (stencil P), V = (V - F) - G^,
+//             out R' = (V - F) - (q_j - p_{j+1}) x;
+//   last y solve without the stencil: Y_c = -(q P + mu^2)^-1 V.
+// Then Y = Y^ x_z V and the output map.
+
+namespace {
+
+void zeig_tables_of(const fps_plan *pl, int k, int j, int *t1, int *t2) {
+  *t1 = pl->ztab0[k] + 2 * j;
+  *t2 = pl->ztab0[k] + 2 * j + 1;
+}
+
+}  // namespace
+
+fps_status zeig_build(fps_plan *pl) {
+  const int64_t n = pl->n;
+  pl->zeig = true;
+  pl->L = fps::make_layout(n);
+  const fps::Layout &L = pl->L;
+  const double delta = 1.0 / (30.0 * (double)n * (double)n * (double)n * (double)n);
+  double ea = -1.0, eb = -delta;
+  if (pl->flags & FPS_PLAN_TIGHT_SPECTRUM) spectrum_tight(n, &ea, &eb);
+  // eigen-decomposition of the parity blocks of A~
+  std::vector<long double> lam[2];
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t m = L.m[sp];
+    pl->zV[sp].assign((size_t)(m * m), 0.0);
+    if (m == 0) continue;
+    std::vector<long double> d(m), e(m > 1 ? m - 1 : 0), Q;
+    for (int64_t k = 0; k < m; ++k) d[k] = fps::atilde_diag(2 * k + sp);
+    for (int64_t k = 0; k + 1 < m; ++k) e[k] = fps::atilde_off(2 * k + sp);
+    if (!fps::tridiag_eigen(d, e, Q)) return fail(FPS_E_STATE, "eigen-decomposition of A~ failed");
+    lam[sp] = d;
+    for (int64_t i = 0; i < m * m; ++i) pl->zV[sp][(size_t)i] = (double)Q[(size_t)i];
+  }
+  // per-slice shifts
+  struct Slice {
+    int slice, J;
+    double mu;
+    fps::ShiftSet sh;
+  };
+  std::vector<Slice> sl;
+  std::string err;
+  for (int sp = 0; sp < 2; ++sp)
+    for (int64_t k = 0; k < L.m[sp]; ++k) {
+      Slice x;
+      x.slice = (int)(sp * L.mp[0] + k);
+      x.mu = (double)lam[sp][(size_t)k];
+      const double am = std::fabs(x.mu);
+      const double a = x.mu * x.mu / (std::fabs(ea) + am), b = x.mu * x.mu / (std::fabs(eb) + am);
+      const double c = std::fabs(eb) + am, d = std::fabs(ea) + am;
+      if (!fps::zolotarev_shifts(a, b, c, d, pl->tol, x.sh, err)) return fail(FPS_E_ARG, err);
+      x.J = x.sh.J;
+      sl.push_back(x);
+    }
+  std::stable_sort(sl.begin(), sl.end(), [](const Slice &u, const Slice &v) { return u.J > v.J; });
+  const int K = (int)sl.size();
+  pl->zslice.resize(K);
+  pl->zJ.resize(K);
+  pl->zmu.resize(K);
+  pl->ztab0.resize(K);
+  pl->zJmax = K > 0 ? sl[0].J : 0;
+  pl->zp.clear();
+  pl->zq.clear();
+  std::vector<double> alpha, beta;
+  for (int k = 0; k < K; ++k) {
+    pl->zslice[k] = sl[k].slice;
+    pl->zJ[k] = sl[k].J;
+    pl->zmu[k] = sl[k].mu;
+    pl->ztab0[k] = (int)alpha.size();
+    const double mu = sl[k].mu;
+    for (int j = 0; j < sl[k].J; ++j) {
+      pl->zp.push_back(sl[k].sh.p[j]);
+      pl->zq.push_back(sl[k].sh.q[j]);
+      alpha.push_back(1.0);  // x solve: A~ + (mu + p)
+      beta.push_back(mu + sl[k].sh.p[j]);
+      alpha.push_back(sl[k].sh.q[j]);  // y solve: q A~ + (mu^2 + q mu)
+      beta.push_back(mu * mu + sl[k].sh.q[j] * mu);
+    }
+  }
+  pl->zactive.assign(pl->zJmax + 1, 0);
+  for (int j = 0; j <= pl->zJmax; ++j)
+    for (int k = 0; k < K; ++k)
+      if (pl->zJ[k] > j) pl->zactive[j] = k + 1;
+  // report the largest slice iteration as the plan's J and its shifts
+  pl->shifts = K > 0 ? sl[0].sh : fps::ShiftSet{};
+  fps::build_sweep_tables_ab(L, alpha, beta, pl->tab, pl->ctab, nullptr, pl->l1);
+  fps::build_conversions(L, pl->Rs, pl->P);
+  for (int s2 = 0; s2 < 2; ++s2) {
+    pl->mop[s2] = (L.mo[s2] + fps::kPad - 1) / fps::kPad * fps::kPad;
+    pl->mqc[s2] = (L.mo[s2] + 1) / 2 * 2;
+  }
+  pl->sinv.resize(n);
+  for (int64_t i = 0; i < n; ++i) pl->sinv[i] = 1.0 / std::sqrt((double)(i + 1) * (double)(i + 2));
+  pl->sdiag.assign(L.npad, 0.0);
+  pl->soff.assign(L.npad, 0.0);
+  for (int sp = 0; sp < 2; ++sp)
+    for (int64_t k = 0; k < L.m[sp]; ++k) {
+      const int64_t r = sp * L.mp[0] + k, i = 2 * k + sp;
+      pl->sdiag[r] = fps::atilde_diag(i);
+      if (k + 1 < L.m[sp]) pl->soff[r] = fps::atilde_off(i);
+    }
+  const int64_t vol = align256(L.npad * L.npad * L.npad * 8);
+  const int64_t ch = L.npad * L.npad;
+  pl->off_G = 0;      // G^ (eigen-z slices, [c][y][x])
+  pl->off_ZR = vol;   // Y^
+  pl->off_RX = 2 * vol;
+  pl->off_RXT = 3 * vol;  // G^ transposed per slice
+  pl->off_O0 = 4 * vol;
+  pl->off_O1 = 5 * vol;
+  pl->off_lv = 6 * vol;
+  pl->off_ab = pl->off_lv + align256(L.ncmax * 4 * ch * 8);
+  pl->ws_bytes = pl->off_ab + align256(2 * L.ncmax * ch * 2 * 8);
+  const int64_t mq = pl->mqc[0] + pl->mqc[1];
+  if (L.npad * L.npad * mq * 8 > 2 * vol || mq * mq * mq * 8 > 2 * vol ||
+      L.npad * mq * mq * 8 > 2 * vol)
+    return fail(FPS_E_STATE, "internal: cube output temporaries exceed the workspace");
+  return FPS_OK;
+}
+
+fps_status zeig_upload(fps_plan *pl) {
+  const fps::Layout &L = pl->L;
+  const int64_t npad = L.npad, ch = npad * npad;
+  fps_status s;
+  // dense map blocks (zero padded): Rs (x, y input), V^T Rs (z input), P (x, y
+  // output), P V (z output), V (z back-transform for native output)
+  std::vector<double> RsA[2], RsB[2], Mz[2], PA[2], PB[2], PV[2], Vz[2];
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t m = L.m[sp], mp = L.mp[sp], mo = L.mo[sp], mop = pl->mop[sp];
+    RsA[sp].assign((size_t)(mp * mp), 0.0);
+    RsB[sp].assign((size_t)(mp * mp), 0.0);
+    Mz[sp].assign((size_t)(mp * mp), 0.0);
+    Vz[sp].assign((size_t)(mp * mp), 0.0);
+    PA[sp].assign((size_t)(mop * mp), 0.0);
+    PB[sp].assign((size_t)(mp * mop), 0.0);
+    PV[sp].assign((size_t)(mop * mp), 0.0);
+    const std::vector<double> &V = pl->zV[sp];  // V[i][k]: component i of eigenvector k
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t k = 0; k < m; ++k) {
+        RsA[sp][(size_t)(i * mp + k)] = pl->Rs[sp][(size_t)(i * m + k)];
+        RsB[sp][(size_t)(k * mp + i)] = pl->Rs[sp][(size_t)(i * m + k)];
+        Vz[sp][(size_t)(i * mp + k)] = V[(size_t)(i * m + k)];
+      }
+    for (int64_t k = 0; k < m; ++k)  // (V^T Rs)[k][b] = sum_i V[i][k] Rs[i][b]
+      for (int64_t b = 0; b < m; ++b) {
+        long double acc = 0.0L;
+        for (int64_t i = 0; i < m; ++i)
+          acc += (long double)V[(size_t)(i * m + k)] * pl->Rs[sp][(size_t)(i * m + b)];
+        Mz[sp][(size_t)(k * mp + b)] = (double)acc;
+      }
+    for (int64_t i = 0; i < mo; ++i) {
+      for (int64_t k = 0; k < m; ++k) {
+        PA[sp][(size_t)(i * mp + k)] = pl->P[sp][(size_t)(i * m + k)];
+        PB[sp][(size_t)(k * mop + i)] = pl->P[sp][(size_t)(i * m + k)];
+      }
+      for (int64_t k = 0; k < m; ++k) {  // (P V)[i][k]
+        long double acc = 0.0L;
+        for (int64_t b = 0; b < m; ++b)
+          acc += (long double)pl->P[sp][(size_t)(i * m + b)] * V[(size_t)(b * m + k)];
+        PV[sp][(size_t)(i * mp + k)] = (double)acc;
+      }
+    }
+  }
+  std::vector<double> pre(pl->sdiag);
+  pre.insert(pre.end(), pl->soff.begin(), pl->soff.end());
+  if ((s = upload(pl->d_tab, pl->tab)) != FPS_OK || (s = upload(pl->d_ctab, pl->ctab)) != FPS_OK ||
+      (s = upload(pl->d_l1, pl->l1)) != FPS_OK || (s = upload(pl->d_sinv, pl->sinv)) != FPS_OK ||
+      (s = upload(pl->d_pre, pre)) != FPS_OK)
+    return s;
+  for (int sp = 0; sp < 2; ++sp)
+    if ((s = upload(pl->d_RsA[sp], RsA[sp])) != FPS_OK ||
+        (s = upload(pl->d_RsB[sp], RsB[sp])) != FPS_OK || (s = upload(pl->d_Mz[sp], Mz[sp])) != FPS_OK ||
+        (s = upload(pl->d_PA[sp], PA[sp])) != FPS_OK || (s = upload(pl->d_PB[sp], PB[sp])) != FPS_OK ||
+        (s = upload(pl->d_PV[sp], PV[sp])) != FPS_OK || (s = upload(pl->d_Vz[sp], Vz[sp])) != FPS_OK)
+      return s;
+  // mode-y GEMM tables (input: Rs; output: P)
+  const Dims full = full_dims(L);
+  const int64_t K2[2] = {L.mp[0], L.mp[1]};
+  const int64_t lda[2] = {L.mp[0], L.mp[1]};
+  {
+    const double *MA[2] = {(const double *)pl->d_RsA[0].p, (const double *)pl->d_RsA[1].p};
+    const int64_t N[2] = {L.m[0] > 0 ? L.mp[0] : 0, L.m[1] > 0 ? L.mp[1] : 0};
+    std::vector<fps::GemmProb> probs;
+    mode_probs((const double *)(intptr_t)pl->off_O1, full, (double *)(intptr_t)pl->off_O0, full, 1,
+               MA, lda, nullptr, lda, N, K2, probs);
+    if ((s = upload_table(probs, pl->d_gy_in, pl->d_gy_map_in, pl->gy_tiles[0])) != FPS_OK) return s;
+  }
+  {
+    const int64_t mq = pl->mqc[0] + pl->mqc[1];
+    const Dims di{{L.npad, L.npad, mq}, {L.mp[0], L.mp[0], pl->mqc[0]}};
+    const Dims dout{{L.npad, mq, mq}, {L.mp[0], pl->mqc[0], pl->mqc[0]}};
+    const double *MA[2] = {(const double *)pl->d_PA[0].p, (const double *)pl->d_PA[1].p};
+    const int64_t N[2] = {L.m[0] > 0 ? L.mo[0] : 0, L.m[1] > 0 ? L.mo[1] : 0};
+    std::vector<fps::GemmProb> probs;
+    mode_probs((const double *)(intptr_t)pl->off_O0, di, (double *)(intptr_t)pl->off_RX, dout, 1,
+               MA, lda, nullptr, lda, N, K2, probs);
+    if ((s = upload_table(probs, pl->d_gy_out, pl->d_gy_map_out, pl->gy_tiles[1])) != FPS_OK)
+      return s;
+  }
+  // per-slice sweep and carry descriptors: [step][half][sorted slice]
+  const int K = (int)pl->zslice.size(), J = pl->zJmax;
+  const int nbx_s = (int)(npad / fps::kCols), nch = (int)(L.nc[0] + L.nc[1]);
+  const int nsw = nbx_s * nch;
+  const int nbx_r = (int)((npad + fps::kReduceThreads - 1) / fps::kReduceThreads);
+  const int nrd = nbx_r * 2;
+  const int64_t lvb = L.ncmax * 4 * npad, abb = 2 * L.ncmax * npad * 2;  // doubles per slice
+  std::vector<fps::BatchSweep> sw((size_t)J * 2 * (K > 0 ? K : 1));
+  std::vector<fps::BatchReduce> rd((size_t)J * 2 * (K > 0 ? K : 1));
+  const double *pre_d = (const double *)pl->d_pre.p;
+  for (int k = 0; k < K; ++k) {
+    const int64_t c = pl->zslice[k];
+    const int64_t so = c * ch * 8;  // slice byte offset in an npad^3 array
+    const int64_t lvo = pl->off_lv + c * lvb * 8, abo = pl->off_ab + c * abb * 8;
+    fps::SweepArgs A{};
+    A.npad = npad;
+    A.ncols = npad;
+    A.ld = npad;
+    A.nbatch = 1;
+    A.mp0 = L.mp[0];
+    A.mp1 = L.mp[1];
+    A.mstride = L.mstride;
+    A.ncmax = L.ncmax;
+    A.nc0 = (int)L.nc[0];
+    A.nc1 = (int)L.nc[1];
+    A.lv = (double *)(intptr_t)lvo;
+    const double mu = pl->zmu[k];
+    for (int j = 0; j < pl->zJ[k]; ++j) {
+      int t1, t2;
+      zeig_tables_of(pl, k, j, &t1, &t2);
+      const bool last = j == pl->zJ[k] - 1;
+      const double pj = pl->zp[(size_t)t1 / 2], qj = pl->zq[(size_t)t1 / 2];
+      const double pn = last ? 0.0 : pl->zp[(size_t)t1 / 2 + 1];
+      fps::SweepArgs a1 = A;
+      a1.in = (const void *)(intptr_t)((j == 0 ? pl->off_RXT : pl->off_O1) + so);
+      a1.in_scale = 1.0;
+      a1.ab_prev = j == 0 ? nullptr : (const double *)(intptr_t)abo;
+      a1.tab_prev = j == 0 ? nullptr : pl->tab_dev(t1 - 1);
+      a1.g = nullptr;
+      a1.tab = pl->tab_dev(t1);
+      a1.l1 = pl->l1_dev(t1);
+      a1.sigma = pj - qj;
+      a1.out = (void *)(intptr_t)(pl->off_O0 + so);
+      a1.out_mode = 0;
+      fps::SweepArgs a2 = A;
+      a2.in = (const void *)(intptr_t)(pl->off_O0 + so);
+      a2.in_scale = 1.0;
+      a2.ab_prev = (const double *)(intptr_t)abo;
+      a2.tab_prev = pl->tab_dev(t1);
+      a2.g = (const void *)(intptr_t)(pl->off_G + so);
+      a2.sg = -1.0;
+      a2.og = 0.0;
+      a2.pre = last ? nullptr : pre_d;
+      a2.pre_shift = mu;
+      a2.tab = pl->tab_dev(t2);
+      a2.l1 = pl->l1_dev(t2);
+      a2.sigma = last ? 0.0 : qj - pn;
+      a2.out = (void *)(intptr_t)(pl->off_O1 + so);
+      a2.out_mode = last ? 1 : 0;
+      const size_t i1 = ((size_t)j * 2 + 0) * K + k, i2 = ((size_t)j * 2 + 1) * K + k;
+      sw[i1] = fps::BatchSweep{a1, k * nsw, nbx_s};
+      sw[i2] = fps::BatchSweep{a2, k * nsw, nbx_s};
+      rd[i1] = fps::BatchReduce{lvo, abo, pl->ctab_dev(t1), -a1.sigma, npad, L.ncmax,
+                                (int)L.nc[0], (int)L.nc[1], k * nrd, nbx_r};
+      rd[i2] = fps::BatchReduce{lvo, abo, pl->ctab_dev(t2), last ? 1.0 : -a2.sigma, npad, L.ncmax,
+                                (int)L.nc[0], (int)L.nc[1], k * nrd, nbx_r};
+    }
+  }
+  std::vector<int> swmap((size_t)(K * nsw)), rdmap((size_t)(K * nrd));
+  for (int k = 0; k < K; ++k) {
+    std::fill(swmap.begin() + (size_t)k * nsw, swmap.begin() + (size_t)(k + 1) * nsw, k);
+    std::fill(rdmap.begin() + (size_t)k * nrd, rdmap.begin() + (size_t)(k + 1) * nrd, k);
+  }
+  std::vector<const double *> fin((size_t)npad, nullptr);
+  for (int k = 0; k < K; ++k) {
+    int t1, t2;
+    zeig_tables_of(pl, k, pl->zJ[k] - 1, &t1, &t2);
+    fin[(size_t)pl->zslice[k]] = pl->tab_dev(t2);
+  }
+  pl->zsw_start.assign(1, nsw);
+  pl->zrd_start.assign(1, nrd);
+  if ((s = upload(pl->d_zsw, sw)) != FPS_OK || (s = upload(pl->d_zrd, rd)) != FPS_OK ||
+      (s = upload(pl->d_zswmap, swmap)) != FPS_OK || (s = upload(pl->d_zrdmap, rdmap)) != FPS_OK ||
+      (s = upload(pl->d_zfin, fin)) != FPS_OK)
+    return s;
+  return FPS_OK;
+}
+
+fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStream_t st) {
+  const fps::Layout &L = pl->L;
+  const int64_t npad = L.npad, mp0 = L.mp[0];
+  double *Gh = (double *)(w + pl->off_G), *GhT = (double *)(w + pl->off_RXT);
+  double *Yh = (double *)(w + pl->off_ZR), *RX = (double *)(w + pl->off_RX);
+  double *O0 = (double *)(w + pl->off_O0), *O1 = (double *)(w + pl->off_O1);
+  const Dims full = full_dims(L);
+  const int64_t K2[2] = {L.mp[0], L.mp[1]};
+  const int64_t ldm[2] = {L.mp[0], L.mp[1]};
+  const int64_t Nfull[2] = {L.m[0] > 0 ? L.mp[0] : 0, L.m[1] > 0 ? L.mp[1] : 0};
+  fps_status s;
+  // Input map: G^ = F_T x_x Rs x_y Rs x_z (V^T Rs), and its per-slice transpose.
+  FPS_HIP(fps::launch_permute3_in(F, O0, L.n, npad, mp0, st));
+  {
+    const double *MB[2] = {(const double *)pl->d_RsB[0].p, (const double *)pl->d_RsB[1].p};
+    const double *MZ[2] = {(const double *)pl->d_Mz[0].p, (const double *)pl->d_Mz[1].p};
+    std::vector<fps::GemmProb> px, pz;
+    mode_probs(O0, full, O1, full, 2, MB, ldm, MB, ldm, Nfull, K2, px);
+    if ((s = launch_probs(px, st)) != FPS_OK) return s;
+    FPS_HIP(fps::launch_gemm_table((const fps::GemmDesc *)pl->d_gy_in.p,
+                                   (const int *)pl->d_gy_map_in.p, pl->gy_tiles[0], w, nullptr, st));
+    mode_probs(O0, full, Gh, full, 0, MZ, ldm, MZ, ldm, Nfull, K2, pz);
+    if ((s = launch_probs(pz, st)) != FPS_OK) return s;
+  }
+  FPS_HIP(fps::launch_transpose(Gh, GhT, npad, st, (int)npad));
+  // Per-slice ADI, all active slices per launch.
+  const int K = (int)pl->zslice.size();
+  const int nsw = pl->zsw_start[0], nrd = pl->zrd_start[0];
+  const fps::BatchSweep *dsw = (const fps::BatchSweep *)pl->d_zsw.p;
+  const fps::BatchReduce *drd = (const fps::BatchReduce *)pl->d_zrd.p;
+  const int *swmap = (const int *)pl->d_zswmap.p, *rdmap = (const int *)pl->d_zrdmap.p;
+  fps::SweepArgs plain{}, stencil{};
+  stencil.pre = (const double *)pl->d_pre.p;
+  // sweep launch, timed with the plan's event pairs while they last
+  auto sweep = [&](const fps::SweepArgs &types, bool with_g, const fps::BatchSweep *d, int nwg,
+                   int wg_base) -> hipError_t {
+    const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
+    const hipError_t e = fps::launch_sweep_batch(
+        types, with_g, d, swmap, nwg, w, st, wg_base, t ? pl->ev[2 * pl->ev_used] : nullptr,
+        t ? pl->ev[2 * pl->ev_used + 1] : nullptr);
+    if (t && e == hipSuccess) ++pl->ev_used;
+    return e;
+  };
+  for (int j = 0; j < pl->zJmax; ++j) {
+    const int k1 = pl->zactive[j], k2 = pl->zactive[j + 1];
+    const size_t o1 = ((size_t)j * 2 + 0) * K, o2 = ((size_t)j * 2 + 1) * K;
+    FPS_HIP(sweep(plain, false, dsw + o1, k1 * nsw, 0));
+    FPS_HIP(fps::launch_reduce_batch(drd + o1, rdmap, k1 * nrd, L.ncmax, w, st));
+    if (k2 > 0)  // slices with a later step: stencil P before the y solve
+      FPS_HIP(sweep(stencil, true, dsw + o2, k2 * nsw, 0));
+    if (k1 > k2)  // slices at their last step: no stencil
+      FPS_HIP(sweep(plain, true, dsw + o2, (k1 - k2) * nsw, k2 * nsw));
+    FPS_HIP(fps::launch_reduce_batch(drd + o2, rdmap, k1 * nrd, L.ncmax, w, st));
+  }
+  FPS_HIP(fps::launch_slice_final(O1, (const double *)(w + pl->off_ab),
+                                  (const double *const *)pl->d_zfin.p, Yh, -1.0, npad, mp0,
+                                  L.mstride, L.ncmax, st));
+  // Output.
+  if (pl->out_basis == FPS_OUT_NATIVE) {
+    const double *MV[2] = {(const double *)pl->d_Vz[0].p, (const double *)pl->d_Vz[1].p};
+    std::vector<fps::GemmProb> pz;
+    mode_probs(Yh, full, O0, full, 0, MV, ldm, MV, ldm, Nfull, K2, pz);
+    if ((s = launch_probs(pz, st)) != FPS_OK) return s;
+    FPS_HIP(fps::launch_permute3_out(O0, U, L.n, npad, mp0, (const double *)pl->d_sinv.p, st));
+    return FPS_OK;
+  }
+  const int64_t mq = pl->mqc[0] + pl->mqc[1], mb0 = pl->mqc[0];
+  const double *MB[2] = {(const double *)pl->d_PB[0].p, (const double *)pl->d_PB[1].p};
+  const double *MPV[2] = {(const double *)pl->d_PV[0].p, (const double *)pl->d_PV[1].p};
+  const int64_t ldb[2] = {pl->mop[0], pl->mop[1]};
+  const int64_t N[2] = {L.m[0] > 0 ? L.mo[0] : 0, L.m[1] > 0 ? L.mo[1] : 0};
+  const Dims d1{{npad, npad, mq}, {mp0, mp0, mb0}};
+  const Dims d2{{npad, mq, mq}, {mp0, mb0, mb0}};
+  const Dims d3{{mq, mq, mq}, {mb0, mb0, mb0}};
+  std::vector<fps::GemmProb> px, pz;
+  mode_probs(Yh, full, O0, d1, 2, MB, ldm, MB, ldb, N, K2, px);
+  if ((s = launch_probs(px, st)) != FPS_OK) return s;
+  FPS_HIP(fps::launch_gemm_table((const fps::GemmDesc *)pl->d_gy_out.p,
+                                 (const int *)pl->d_gy_map_out.p, pl->gy_tiles[1], w, nullptr, st));
+  mode_probs(RX, d2, O0, d3, 0, MPV, ldm, MPV, ldb, N, K2, pz);
   if ((s = launch_probs(pz, st)) != FPS_OK) return s;
   FPS_HIP(fps::launch_permute3_out(O0, U, L.n + 2, mq, mb0, nullptr, st));
   return FPS_OK;

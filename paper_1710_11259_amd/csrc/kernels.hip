@@ -96,6 +96,8 @@ __global__ void k_permute_in(const double *__restrict__ src, double *__restrict_
 __global__ __launch_bounds__(256) void k_transpose(const double *__restrict__ src,
                                                    double *__restrict__ dst, int64_t npad) {
   __shared__ double tile[64][65];
+  src += (int64_t)blockIdx.z * npad * npad;
+  dst += (int64_t)blockIdx.z * npad * npad;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
   const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
   for (int i = ty; i < 64; i += 4) tile[i][tx] = src[(r0 + i) * npad + c0 + tx];
@@ -172,6 +174,28 @@ __global__ __launch_bounds__(256) void k_cube_zfinal(const double *__restrict__ 
   for (int rr = ty; rr < 64; rr += 4) RT[z * plane + (x0 + rr) * npad + y0 + tx] = tile[tx][rr];
 }
 
+// Per-slice finalization (chains = x columns, positions y) with the table
+// of slice z; slices without a table are cleared.
+__global__ void k_slice_final(const double *__restrict__ x, const double *__restrict__ ab,
+                              const double *const *__restrict__ tabs, double *__restrict__ out,
+                              double scale, int64_t npad, int64_t mp0, int64_t mstride,
+                              int64_t ncmax) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t y = blockIdx.y, z = blockIdx.z;
+  if (q >= npad) return;
+  const int64_t i = (z * npad + y) * npad + q;
+  const double *tab = tabs[z];
+  if (tab == nullptr) {
+    out[i] = 0.0;
+    return;
+  }
+  const int s = y >= mp0 ? 1 : 0;
+  const int64_t k = y - (s ? mp0 : 0), c = k / kChunk;
+  const double *tp = tab + (int64_t)s * kNTab * mstride;
+  const double *e = ab + z * (2 * ncmax * npad * 2) + (((int64_t)s * ncmax + c) * npad + q) * 2;
+  out[i] = scale * (x[i] + e[0] * tp[T_BF2 * mstride + k] + e[1] * tp[T_BK2 * mstride + k]);
+}
+
 // After the last inner sweep on every z-slice (chains = x columns, positions
 // y): Y = x + chunk carries; out = cy Y + cr R + cb B (R, B may be null when
 // their coefficient is 0).
@@ -217,6 +241,15 @@ hipError_t launch_cube_zfinal(const double *x, const double *ab, const double *t
   dim3 grid((unsigned)(npad / 64), (unsigned)(npad / 64), (unsigned)npad);
   hipLaunchKernelGGL(k_cube_zfinal, grid, dim3(256), 0, st, x, ab, tab, R, RT, npad, mp0, mstride,
                      ncmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_final(const double *x, const double *ab, const double *const *tabs,
+                              double *out, double scale, int64_t npad, int64_t mp0,
+                              int64_t mstride, int64_t ncmax, hipStream_t st) {
+  dim3 grid((unsigned)((npad + 255) / 256), (unsigned)npad, (unsigned)npad);
+  hipLaunchKernelGGL(k_slice_final, grid, dim3(256), 0, st, x, ab, tabs, out, scale, npad, mp0,
+                     mstride, ncmax);
   return hipGetLastError();
 }
 
@@ -268,9 +301,10 @@ hipError_t launch_permute_out(const double *src, double *dst, int64_t n, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st) {
-  if (npad % 64 != 0) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(npad / 64), (unsigned)(npad / 64));
+hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st,
+                            int nbatch) {
+  if (npad % 64 != 0 || nbatch < 1) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(npad / 64), (unsigned)(npad / 64), (unsigned)nbatch);
   hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, src, dst, npad);
   return hipGetLastError();
 }

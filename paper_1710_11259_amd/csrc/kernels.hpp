@@ -41,6 +41,7 @@ struct SweepArgs {
   void *out;               // storage type out_f32
   double *lv;              // chunk boundary values [ncmax][2][2][ncols]
   const double *pre;       // stencil [2][npad] or nullptr (float64 storage only)
+  double pre_shift;        // added to the stencil's diagonal
   int out_mode;
   int64_t npad, mp0, mp1, mstride, ncmax;
   int64_t ncols, ld;       // chains, row stride (elements)
@@ -61,8 +62,9 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st, hipEvent_t ev0 = nul
 
 // Batched sweeps over several independent problems in one launch.  The
 // workspace pointers of each descriptor's SweepArgs (in, g, out, lv,
-// ab_prev) hold byte offsets from `base`; tab, tab_prev and l1 are device
-// pointers; ab_prev is used iff tab_prev is non-null.  Workgroup g runs
+// ab_prev) hold byte offsets from `base`; tab, tab_prev, l1 and pre are
+// device pointers; ab_prev is used iff tab_prev is non-null.  With a stencil
+// (`types.pre` non-null) every descriptor must carry one.  Workgroup g runs
 // block (local % nbx, local / nbx), local = g - wg_start, of problem
 // wg_prob[g].  Storage types and the presence of g come from `types` /
 // `with_g` and must be those of every descriptor.
@@ -70,8 +72,10 @@ struct BatchSweep {
   SweepArgs a;
   int wg_start, nbx;
 };
+// wg_base: the launch runs workgroups wg_base .. wg_base + nwg - 1 of the map.
 hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSweep *d,
-                              const int *wg_prob, int nwg, char *base, hipStream_t st);
+                              const int *wg_prob, int nwg, char *base, hipStream_t st,
+                              int wg_base = 0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Chunk carries: for every chain, the forward and backward carry into each
 // chunk, scaled by `scale`, into ab [2][ncmax][nchains][2] (ctab: the
@@ -127,7 +131,8 @@ hipError_t launch_permute_in(const double *src, double *dst, int64_t n, int64_t 
 hipError_t launch_permute_out(const double *src, double *dst, int64_t n, int64_t npad, int64_t mp0,
                               const double *sinv, hipStream_t st);
 
-hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st);
+hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st,
+                            int nbatch = 1);
 
 // Cube (npad^3 arrays [z][y][x], every axis parity-blocked):
 // natural n^3 -> parity-blocked npad^3 (zero padding).
@@ -142,6 +147,11 @@ hipError_t launch_permute3_out(const double *src, double *dst, int64_t N, int64_
 hipError_t launch_cube_zfinal(const double *x, const double *ab, const double *tab, double *R,
                               double *RT, int64_t npad, int64_t mp0, int64_t mstride,
                               int64_t ncmax, hipStream_t st);
+// Per-slice finalization with a table per slice: out[z] = scale (x[z] +
+// chunk carries of slice z) when tabs[z] is non-null, else 0.
+hipError_t launch_slice_final(const double *x, const double *ab, const double *const *tabs,
+                              double *out, double scale, int64_t npad, int64_t mp0,
+                              int64_t mstride, int64_t ncmax, hipStream_t st);
 // After the last per-slice sweep (chains = x, positions = y, ab per slice):
 // out = cy (x + chunk carries) + cr R + cb B.
 hipError_t launch_cube_ifinal(const double *x, const double *ab, const double *tab,

@@ -94,6 +94,19 @@ struct fps_plan {
   int gy_tiles[2] = {0, 0};
   fps::detail::DeviceBuf d_gy_map_in, d_gy_map_out;
   int64_t off_ZR = 0, off_RX = 0, off_RXT = 0;
+
+  // Cube, z-eigenbasis method (FPS_PLAN_CUBE_ZEIG): slice k of the sorted
+  // active slices (J descending) is storage slice zslice[k], eigenvalue
+  // zmu[k], zJ[k] ADI steps with table ids ztab0[k] + 2 j (x solve) and
+  // ztab0[k] + 2 j + 1 (y solve).
+  bool zeig = false;
+  std::vector<int> zslice, zJ, ztab0, zactive, zsw_start, zrd_start;
+  std::vector<double> zmu;
+  std::vector<double> zp, zq;  // shifts of step j of sorted slice k at index ztab0[k] / 2 + j
+  int zJmax = 0;
+  fps::detail::DeviceBuf d_zsw, d_zrd, d_zswmap, d_zrdmap, d_zfin;
+  fps::detail::DeviceBuf d_Mz[2], d_PV[2], d_Vz[2];  // z maps: V^T S^-1 R, P V, V
+  std::vector<double> zV[2];  // host eigenvectors of the parity blocks (m x m, columns)
   int64_t ws_bytes = 0;
 
   const double *tab_dev(int j) const {

@@ -244,7 +244,7 @@ __device__ __forceinline__ void compute_store(const SweepArgs &a, const Unit &u,
     for (int i = 0; i < kSeg; ++i) {
       const double lo = i > 0 ? Pe[i - 1] * y[i - 1] : pem * ym;
       const double hi = i < kSeg - 1 ? Pe[i] * y[i + 1] : Pe[kSeg - 1] * yp;
-      t[i] = Pd[i] * y[i] + lo + hi;
+      t[i] = (Pd[i] + a.pre_shift) * y[i] + lo + hi;
     }
 #pragma unroll
     for (int i = 0; i < kSeg; ++i) y[i] = act * t[i];
@@ -369,12 +369,13 @@ __global__ __launch_bounds__(kCols *kWaves, (kPre && kG == 2) ? 4 : 6) void k_sw
 
 // Batched sweep: workgroup g belongs to problem wg_prob[g]; the problem's
 // descriptor holds workspace offsets in place of its workspace pointers.
-template <typename Tin, typename Tg, typename Tout, int kG>
+template <typename Tin, typename Tg, typename Tout, int kG, bool kPre>
 __global__ __launch_bounds__(kCols *kWaves, 6) void k_sweep_batch(const BatchSweep *__restrict__ d,
                                                                   const int *__restrict__ wg_prob,
-                                                                  char *base) {
+                                                                  char *base, int wg_base) {
   __shared__ double lds[kSweepLds];
-  const int k = __builtin_amdgcn_readfirstlane(wg_prob[blockIdx.x]);
+  const int g = (int)blockIdx.x + wg_base;
+  const int k = __builtin_amdgcn_readfirstlane(wg_prob[g]);
   const BatchSweep &e = d[k];
   SweepArgs a = e.a;
   a.in = base + (intptr_t)a.in;
@@ -382,8 +383,8 @@ __global__ __launch_bounds__(kCols *kWaves, 6) void k_sweep_batch(const BatchSwe
   a.out = base + (intptr_t)a.out;
   a.lv = (double *)(base + (intptr_t)a.lv);
   if (a.tab_prev != nullptr) a.ab_prev = (const double *)(base + (intptr_t)a.ab_prev);
-  const int local = (int)blockIdx.x - e.wg_start;
-  sweep_block<Tin, Tg, Tout, kG, false>(a, local % e.nbx, local / e.nbx, lds);
+  const int local = g - e.wg_start;
+  sweep_block<Tin, Tg, Tout, kG, kPre>(a, local % e.nbx, local / e.nbx, lds);
 }
 
 // Chunk carries of one half-sweep: thread (parity s, chain r) runs the
@@ -539,6 +540,7 @@ struct SweepLaunch {
   int nwg;
   hipStream_t st;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // optional: timestamps of this dispatch
+  int wg_base = 0;
   template <typename Tin, typename Tg, typename Tout, int kG, bool kPre = false>
   void go() const {
     const int nch = a.nc0 + a.nc1;
@@ -551,9 +553,13 @@ struct SweepLaunch {
       else
         hipLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kG, kPre>), grid, dim3(kCols * kWaves), 0, st,
                            a);
-    } else if constexpr (!kPre) {
-      hipLaunchKernelGGL((k_sweep_batch<Tin, Tg, Tout, kG>), dim3((unsigned)nwg),
-                         dim3(kCols * kWaves), 0, st, d, wg_prob, base);
+    } else if constexpr (!kPre || kG != 2) {
+      if (ev0 != nullptr)
+        hipExtLaunchKernelGGL((k_sweep_batch<Tin, Tg, Tout, kG, kPre>), dim3((unsigned)nwg),
+                              dim3(kCols * kWaves), 0, st, ev0, ev1, 0, d, wg_prob, base, wg_base);
+      else
+        hipLaunchKernelGGL((k_sweep_batch<Tin, Tg, Tout, kG, kPre>), dim3((unsigned)nwg),
+                           dim3(kCols * kWaves), 0, st, d, wg_prob, base, wg_base);
     }
   }
 };
@@ -564,8 +570,8 @@ hipError_t dispatch_sweep(const SweepLaunch &L, bool with_g) {
   if (with_g && a.og != 0.0 && a.sg != 0.0) return hipErrorInvalidValue;
   const bool g_out = with_g && a.og != 0.0;
   if (a.pre != nullptr) {
-    // stencil passes: float64 storage only, single launches only
-    if (code != 0 || L.d != nullptr) return hipErrorInvalidValue;
+    // stencil passes: float64 storage only; batched ones without g in the output
+    if (code != 0 || (L.d != nullptr && g_out)) return hipErrorInvalidValue;
     if (!with_g)
       L.go<double, double, double, 0, true>();
     else if (g_out)
@@ -605,9 +611,10 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st, hipEvent_t ev0, hipE
 }
 
 hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSweep *d,
-                              const int *wg_prob, int nwg, char *base, hipStream_t st) {
+                              const int *wg_prob, int nwg, char *base, hipStream_t st,
+                              int wg_base, hipEvent_t ev0, hipEvent_t ev1) {
   if (nwg <= 0) return hipSuccess;
-  return dispatch_sweep(SweepLaunch{types, d, wg_prob, base, nwg, st}, with_g);
+  return dispatch_sweep(SweepLaunch{types, d, wg_prob, base, nwg, st, ev0, ev1, wg_base}, with_g);
 }
 
 hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,

@@ -64,3 +64,36 @@ def test_cube_tight_spectrum_matches_exact(n):
     err = np.linalg.norm(U.cpu().numpy() - Uo) / np.linalg.norm(Uo)
     print(f"rel err {err:.3e}", flush=True)
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("n,out,tight", [(1, "cheb", False), (2, "cheb", True), (5, "native", True),
+                                         (16, "cheb", False), (33, "cheb", True),
+                                         (64, "native", True), (100, "cheb", True),
+                                         (256, "cheb", True), (256, "cheb", False)])
+def test_cube_zeig_matches_exact(n, out, tight):
+    # z-eigenbasis method: per-slice ADI after an eigen-transform along z.
+    F = workloads.cube_rhs(n)
+    p = fps.plan(n, tol=1e-13, dim=3, out=out, tight=tight, zeig=True)
+    print(f"cube zeig n={n} out={out} tight={tight} J_max={p.J} "
+          f"slice steps={sum(p.slice_counts())}", flush=True)
+    U = fps.solve(p, torch.from_numpy(F).cuda())
+    torch.cuda.synchronize()
+    Uo = cube.poisson_cube(F, out=out)
+    err = np.linalg.norm(U.cpu().numpy() - Uo) / np.linalg.norm(Uo)
+    print(f"rel err {err:.3e}", flush=True)
+    assert err <= 1e-12
+
+
+def test_cube_zeig_manufactured_solution():
+    n = 24
+    F, u_fun = workloads.manufactured_cube(n, N=40)
+    U = _solve_zeig(n, F)
+    Uex = workloads.cheb_coeffs_3d(u_fun, n + 2)
+    assert np.abs(U - Uex).max() <= 1e-12
+
+
+def _solve_zeig(n, F):
+    p = fps.plan(n, tol=1e-13, dim=3, tight=True, zeig=True)
+    U = fps.solve(p, torch.from_numpy(np.ascontiguousarray(F)).cuda())
+    torch.cuda.synchronize()
+    return U.cpu().numpy()

@@ -369,3 +369,22 @@ def test_tridiagonal_eigensolver_matches_lapack(shim, n):
         np.testing.assert_allclose(lam, ref, rtol=1e-10, atol=0)
         assert np.abs(Q.T @ Q - np.eye(m)).max() < 1e-14
         assert np.abs(Q.T @ B @ Q - np.diag(lam)).max() < 1e-15
+
+
+@pytest.mark.parametrize("n,tight", [(1, False), (5, True), (16, False), (64, True)])
+def test_zeig_cube_plan_slice_counts_match_oracle(n, tight):
+    # One Algorithm 2 per z-slice, J from (2.9) on the slice intervals of the
+    # oracle (eigenvalues from the planner's own eigen-decomposition).
+    from oracle import cube
+    p = fps.plan(n, tol=1e-13, dim=3, host_only=True, tight=tight, zeig=True)
+    lam, _ = square.atilde_eig(n)
+    if tight:
+        lmin, lmax = lam.min() * (1 + 1e-6), lam.max() * (1 - 1e-6)
+    else:
+        lmin, lmax = -1.0, -1.0 / (30.0 * n ** 4)
+    want = sorted((oshifts.iteration_count(*cube.zeig_slice_intervals(n, mu, lmin, lmax), 1e-13)
+                   for mu in lam), reverse=True)
+    assert p.slice_counts() == want
+    assert p.J == want[0]
+    with pytest.raises(fps.FpsError):
+        p.inner_counts()
