@@ -397,10 +397,16 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
   const Dims d2{{npad, mq, mq}, {mp0, mb0, mb0}};
   const Dims d3{{mq, mq, mq}, {mb0, mb0, mb0}};
   std::vector<fps::GemmProb> px, pz;
+  // An empty parity block (n = 1) leaves its output entries to no GEMM: clear
+  // the temporaries first so that they read as zeros.
+  const bool empty_block = L.m[0] == 0 || L.m[1] == 0;
+  if (empty_block) FPS_HIP(fps::launch_fill(O0, npad * npad * mq, 0.0, st));
   mode_probs(ZR, full, O0, d1, 2, MA, ldm, MB, ldb, N, K, px);
   if ((s = launch_probs(px, st)) != FPS_OK) return s;
+  if (empty_block) FPS_HIP(fps::launch_fill(RX, npad * mq * mq, 0.0, st));
   FPS_HIP(fps::launch_gemm_table((const fps::GemmDesc *)pl->d_gy_out.p,
                                  (const int *)pl->d_gy_map_out.p, pl->gy_tiles[1], w, nullptr, st));
+  if (empty_block) FPS_HIP(fps::launch_fill(O0, mq * mq * mq, 0.0, st));
   mode_probs(RX, d2, O0, d3, 0, MA, ldm, MB, ldb, N, K, pz);
   if ((s = launch_probs(pz, st)) != FPS_OK) return s;
   FPS_HIP(fps::launch_permute3_out(O0, U, L.n + 2, mq, mb0, nullptr, st));
@@ -777,10 +783,14 @@ fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
   const Dims d2{{npad, mq, mq}, {mp0, mb0, mb0}};
   const Dims d3{{mq, mq, mq}, {mb0, mb0, mb0}};
   std::vector<fps::GemmProb> px, pz;
+  const bool empty_block = L.m[0] == 0 || L.m[1] == 0;  // n = 1: see cube_solve
+  if (empty_block) FPS_HIP(fps::launch_fill(O0, npad * npad * mq, 0.0, st));
   mode_probs(Yh, full, O0, d1, 2, MB, ldm, MB, ldb, N, K2, px);
   if ((s = launch_probs(px, st)) != FPS_OK) return s;
+  if (empty_block) FPS_HIP(fps::launch_fill(RX, npad * mq * mq, 0.0, st));
   FPS_HIP(fps::launch_gemm_table((const fps::GemmDesc *)pl->d_gy_out.p,
                                  (const int *)pl->d_gy_map_out.p, pl->gy_tiles[1], w, nullptr, st));
+  if (empty_block) FPS_HIP(fps::launch_fill(O0, mq * mq * mq, 0.0, st));
   mode_probs(RX, d2, O0, d3, 0, MPV, ldm, MPV, ldb, N, K2, pz);
   if ((s = launch_probs(pz, st)) != FPS_OK) return s;
   FPS_HIP(fps::launch_permute3_out(O0, U, L.n + 2, mq, mb0, nullptr, st));
