@@ -21,7 +21,7 @@ HBM_PEAK_GBS = 8000.0
 # Calibrated HBM traffic of the sweep kernel per launch at n = 4096 (rocprofv3
 # FETCH_SIZE x2.000 + WRITE_SIZE x1.000, see profiles/sweep_square_n4096.md),
 # valid only for the sweep source with this sha256.
-SWEEP_TRAFFIC = {"sha256": "1ff2cb9befb119d624f372dbca442eda66c211eb63f8dce129e4eb2be2488129",
+SWEEP_TRAFFIC = {"sha256": "63027b2917541e73098d5ff8fa7087fb17d8bacb3520c7982cf92bbac9818a09",
                  "n": 4096, "half_step_1": 278.8e6, "half_step_2": 413.0e6}
 
 

@@ -33,7 +33,7 @@ constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
 
 // One 128 x 128 output tile (column tile bx, row tile by) of problem g.
 __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const int by,
-                                          double (*As)[GBM + GPAD], double (*Bs)[GBN + GPAD]) {
+                                          double (*As)[GBK + 1], double (*Bs)[GBN + GPAD]) {
   const int64_t i0 = (int64_t)by * GBM, j0 = (int64_t)bx * GBN;
   if (i0 >= g.M || j0 >= g.N) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -82,11 +82,14 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
       }
     }
   };
+  // A is kept row-major in LDS ([row][k], one double of padding): the
+  // stash writes each thread's k-run in place and the fragment reads
+  // (16 rows at one k per quarter-wave) hit distinct banks.
   auto stash = [&]() {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      As[ak + 2 * q][ar] = az * ra[q].x;
-      As[ak + 2 * q + 1][ar] = az * ra[q].y;
+      As[ar][ak + 2 * q] = az * ra[q].x;
+      As[ar][ak + 2 * q + 1] = az * ra[q].y;
       *(dbl2 *)&Bs[bk][bc + 2 * q] = rb[q];
     }
   };
@@ -108,7 +111,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
       for (int ks = 0; ks < GBK; ks += 4) {
         double av[4], bv[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = As[ks + (lane >> 4)][wy * 64 + a * 16 + (lane & 15)];
+        for (int a = 0; a < 4; ++a) av[a] = As[wy * 64 + a * 16 + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
         for (int b = 0; b < 4; ++b) bv[b] = Bs[ks + (lane >> 4)][wx * 64 + b * 16 + (lane & 15)];
 #pragma unroll
@@ -137,7 +140,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
 }
 
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmBatch batch) {
-  __shared__ double As[GBK][GBM + GPAD];
+  __shared__ double As[GBM][GBK + 1];
   __shared__ double Bs[GBK][GBN + GPAD];
   gemm_tile(batch.p[blockIdx.z], blockIdx.x, blockIdx.y, As, Bs);
 }
@@ -153,7 +156,7 @@ __device__ __forceinline__ const double *rebase(const double *p, int id, char *w
 __global__ __launch_bounds__(256, 2) void k_gemm_table(const GemmDesc *__restrict__ d,
                                                        const int *__restrict__ tile_prob, char *ws,
                                                        char *out) {
-  __shared__ double As[GBK][GBM + GPAD];
+  __shared__ double As[GBM][GBK + 1];
   __shared__ double Bs[GBK][GBN + GPAD];
   const int k = __builtin_amdgcn_readfirstlane(tile_prob[blockIdx.x]);
   const GemmDesc &e = d[k];
