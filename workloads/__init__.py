@@ -19,6 +19,7 @@ __all__ = [
     "decayed_normal", "square_rhs", "cube_rhs", "batched_problems",
     "adjoint_case", "cheb_coeffs_2d", "cheb_coeffs_3d",
     "manufactured_square", "manufactured_cube", "oscillatory_square_rhs",
+    "rect_dirichlet_case", "manufactured_rect",
 ]
 
 
@@ -158,3 +159,71 @@ def oscillatory_square_rhs(n: int, N: int = 256) -> np.ndarray:
     def f_fun(x, y):
         return -100 * x * np.sin(20 * np.pi * x * x * y) * np.cos(4 * np.pi * (x + y))
     return _pad(cheb_coeffs_2d(f_fun, N), n)
+
+
+# --- Rectangle with Dirichlet data -------------------------------------------
+#
+# Boundary data are four Chebyshev series of length n + 2 in the mapped
+# variables s = (2x - a - b)/(b - a), t = (2y - c - d)/(d - c):
+#   L(t) = u(a, y), R(t) = u(b, y), B(s) = u(x, c), T(s) = u(x, d),
+# stored as the rows of one (4, n + 2) array in that order.
+
+def _cheb_coeffs_1d(vals: np.ndarray) -> np.ndarray:
+    return _dct_coeffs_axis(vals, 0)
+
+
+def _line_fix(v: np.ndarray, lo: float, hi: float) -> np.ndarray:
+    # add alpha T_0 + beta T_1 so that the series takes lo at -1 and hi at +1
+    k = np.arange(v.size)
+    at_m1 = float(((-1.0) ** k) @ v)
+    at_p1 = float(v.sum())
+    out = v.copy()
+    out[0] += ((lo - at_m1) + (hi - at_p1)) / 2
+    out[1] += ((hi - at_p1) - (lo - at_m1)) / 2
+    return out
+
+
+def rect_dirichlet_case(n: int, seed: int = 5, decay: float = 2.0):
+    """(F, bc): random right-hand side as for the square, and four random
+    traces (decayed normal, seed+1) with L and R adjusted in their two
+    leading coefficients so that the four corners agree."""
+    F = decayed_normal(np.random.default_rng(seed), (n, n), decay)
+    rng = np.random.default_rng(seed + 1)
+    L, R, B, T = (decayed_normal(rng, (n + 2,), decay) for _ in range(4))
+    k = np.arange(n + 2)
+    B_m1, B_p1 = float(((-1.0) ** k) @ B), float(B.sum())
+    T_m1, T_p1 = float(((-1.0) ** k) @ T), float(T.sum())
+    L = _line_fix(L, B_m1, T_m1)  # L(-1) = u(a, c) = B(-1), L(1) = u(a, d) = T(-1)
+    R = _line_fix(R, B_p1, T_p1)  # R(-1) = u(b, c) = B(1),  R(1) = u(b, d) = T(1)
+    return F, np.ascontiguousarray(np.stack([L, R, B, T]))
+
+
+def manufactured_rect(n: int, box, N: int = 96):
+    """u = exp(x/2) cos(3y/2) + sin(x y) on the box (a, b, c, d), f = Lap u =
+    -2 exp(x/2) cos(3y/2) - (x^2 + y^2) sin(x y).
+
+    Returns (F, bc, u_fun): F the n x n Chebyshev coefficients of f in the
+    mapped variables, bc the (4, n + 2) boundary traces (interpolants on N
+    points, truncated), u_fun(s, t) the exact solution in mapped variables."""
+    a, b, c, d = box
+
+    def xs(s):
+        return (a + b) / 2 + (b - a) / 2 * s
+
+    def yt(t):
+        return (c + d) / 2 + (d - c) / 2 * t
+
+    def u_fun(s, t):
+        x, y = xs(s), yt(t)
+        return np.exp(x / 2) * np.cos(1.5 * y) + np.sin(x * y)
+
+    def f_fun(s, t):
+        x, y = xs(s), yt(t)
+        return -2 * np.exp(x / 2) * np.cos(1.5 * y) - (x * x + y * y) * np.sin(x * y)
+
+    F = _pad(cheb_coeffs_2d(f_fun, N), n)
+    p = _cheb_points(N)
+    one = np.ones(N)
+    traces = [u_fun(-one, p), u_fun(one, p), u_fun(p, -one), u_fun(p, one)]
+    bc = np.stack([_pad(_cheb_coeffs_1d(v), n + 2) for v in traces])
+    return F, np.ascontiguousarray(bc), u_fun
