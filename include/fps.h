@@ -100,6 +100,25 @@ typedef enum { FPS_OUT_CHEB = 0, FPS_OUT_NATIVE = 1 } fps_out;
 fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double tol,
                            int prec, int out_basis, unsigned flags);
 
+/*
+ * Rectangle plan: u_xx + u_yy = f on [a, b] x [c, d], box_host = {a, b, c, d}
+ * (host array, finite, a < b, c < d).  f, u and the boundary data are
+ * expanded in the mapped variables s = (2x - a - b)/(b - a) and
+ * t = (2y - c - d)/(d - c) (rows of F and U <-> t, as for the square).  The
+ * symmetric form becomes sx2 A~ Y + sy2 Y A~ = G with sx2 = (2/(b-a))^2,
+ * sy2 = (2/(d-c))^2 (the rectangle remark of Sec. 3, with the scalings of
+ * u_ss and u_tt), i.e. A Y - Y B = G with A = sx2 A~ and B = -sy2 A~, whose
+ * spectra lie in sx2 [lo, hi] and sy2 [-hi, -lo] for the enclosure [lo, hi]
+ * of sigma(A~) (Lemma B.1, or the computed one with
+ * FPS_PLAN_TIGHT_SPECTRUM).  Those intervals are not mirror images, so
+ * Algorithm 2 runs with the general shifts (p_j, q_j) of Theorem 2.1 and two
+ * shifted tridiagonal solves per step.  tol, prec, out_basis and flags as for
+ * fps_plan_create (dim 2; FPS_PLAN_CUBE_ZEIG is rejected).  The plan serves
+ * fps_solve, fps_solve_dirichlet, fps_solve_adjoint and fps_adi_native.
+ */
+fps_status fps_plan_create_rect(fps_plan **out, int64_t n, const double *box_host, double tol,
+                                int prec, int out_basis, unsigned flags);
+
 /* J (ADI iterations of the outer level), workspace bytes required by
  * fps_solve / fps_solve_adjoint, and the number of float64 entries of U. */
 fps_status fps_plan_info(const fps_plan *plan, int *J, int64_t *workspace_bytes,
@@ -122,11 +141,20 @@ fps_status fps_plan_inner_counts(const fps_plan *plan, int *counts, int cap);
  * other plans. */
 fps_status fps_plan_slice_counts(const fps_plan *plan, int *counts, int cap, int *count);
 
-/* Copy the plan's shifts p_0..p_{J-1} to host memory (q_j = -p_j for the
- * square, Sec. 3.3 P2 with B~ = -A~; for the cube, the outer shifts p_i in
- * [-2/delta, -2] of the split of (5.2) into H = K_x + K_y and V = K_z,
- * K = -A~^-1, whose partners q_i lie in [1, 1/delta]). */
+/* Copy the plan's shifts p_0..p_{J-1} to host memory, in the order the ADI
+ * applies them (q_j = -p_j for the square, Sec. 3.3 P2 with B~ = -A~; for
+ * the cube, the outer shifts p_i in [-2/delta, -2] of the split of (5.2)
+ * into H = K_x + K_y and V = K_z, K = -A~^-1, whose partners q_i lie in
+ * [1, 1/delta]).  FP64 square and rectangle plans apply the shifts of
+ * Theorem 2.1 in order of increasing |p_j|: the iterate is the same in exact
+ * arithmetic, and the large-shift steps then damp the rounding that the
+ * small-shift solves magnify.  FP32_REFINED plans keep the order of
+ * decreasing |p_j| (their float-stored large-shift steps come first). */
 fps_status fps_plan_shifts(const fps_plan *plan, double *p_host);
+
+/* Copy both shift sequences p_0..p_{J-1} and q_0..q_{J-1} (Theorem 2.1) to
+ * host memory; for a rectangle plan they are not mirror images. */
+fps_status fps_plan_shift_pairs(const fps_plan *plan, double *p_host, double *q_host);
 
 /*
  * Shifts of Theorem 2.1 for sigma(A) in [a,b], sigma(B) in [c,d],
@@ -148,12 +176,31 @@ fps_status fps_solve(fps_plan *plan, const double *F_dev, double *U_dev, void *w
                      void *stream);
 
 /*
+ * Solve with nonhomogeneous Dirichlet data (Sec. 6.1), square or rectangle
+ * plans with FPS_OUT_CHEB.  bc_dev: 4 x (n+2) float64, rows L, R, B, T = the
+ * Chebyshev coefficients of u(a, y) and u(b, y) in t, and of u(x, c) and
+ * u(x, d) in s ([-1, 1]^2 for a square plan).  The corners should agree
+ * (L(-1) = B(-1), L(1) = T(-1), R(-1) = B(1), R(1) = T(1)); the lift's
+ * bilinear corner term takes its values from B and T.  U = U_0 + U_bc with
+ * U_bc the Chebyshev coefficients of the transfinite interpolant
+ * u_bc = (1-s)/2 L + (1+s)/2 R + (1-t)/2 B + (1+t)/2 T - bilinear corners,
+ * and U_0 the zero-data solution for f - Lap u_bc (the C~ projection of
+ * Lap u_bc enters G; it touches only two rows and two columns).  Workspace,
+ * stream and overlap rules as for fps_solve; bc_dev must not overlap ws_dev.
+ */
+fps_status fps_solve_dirichlet(fps_plan *plan, const double *F_dev, const double *bc_dev,
+                               double *U_dev, void *ws_dev, void *stream);
+
+/*
  * Adjoint (vector-Jacobian product) of fps_solve: given Ubar (same layout as
  * U) returns Fbar (n^dim) with <U(F), Ubar> = <F, Fbar> for the J-step ADI
  * map.  The symmetric-shift ADI map is self-adjoint in the Frobenius inner
  * product (every term is phi(A~) G psi(A~) with symmetric phi, psi), so the
- * adjoint runs the same sweeps between transposed coefficient maps.
- * Square only (dim = 2), FPS_FP64 only.
+ * adjoint runs the same sweeps between transposed coefficient maps.  The
+ * same holds for a rectangle plan's general shifts: the J-step error map is
+ * r(A) E r(B)^-1 with r a rational function and A, B symmetric, so the map
+ * is a multiplier in the orthonormal eigenbasis of A~.
+ * Square and rectangle plans (dim = 2), FPS_FP64 only.
  */
 fps_status fps_solve_adjoint(fps_plan *plan, const double *Ubar_dev, double *Fbar_dev,
                              void *ws_dev, void *stream);
@@ -162,8 +209,9 @@ fps_status fps_solve_adjoint(fps_plan *plan, const double *Ubar_dev, double *Fba
  * Stage entry point of the square solve, for testing the ADI sweeps on their
  * own: G_dev (n x n, natural index order) is the right-hand side of the
  * symmetric form A~ Y + Y A~ = G of (3.9); Y_dev (n x n) receives the J-step
- * iterate Y_J of Algorithm 2 (A = A~, B = -A~, q_j = -p_j, X_0 = 0).  Square
- * only; uses the same workspace as fps_solve.
+ * iterate Y_J of Algorithm 2 (A = A~, B = -A~, q_j = -p_j, X_0 = 0).  For a
+ * rectangle plan the equation is sx2 A~ Y + sy2 Y A~ = G with the plan's
+ * (p_j, q_j).  2-D plans; uses the same workspace as fps_solve.
  */
 fps_status fps_adi_native(fps_plan *plan, const double *G_dev, double *Y_dev, void *ws_dev,
                           void *stream);

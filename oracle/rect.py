@@ -106,22 +106,49 @@ def coons_coeffs(bc) -> np.ndarray:
     """Chebyshev coefficients (N x N, N = len of each trace, rows <-> t) of
     the transfinite interpolant
       u_bc = (1-s)/2 L(t) + (1+s)/2 R(t) + (1-t)/2 B(s) + (1+t)/2 T(s)
-             - bilinear interpolant of the four corner values,
-    by sampling on the N x N first-kind grid (u_bc has degree <= N-1 in each
-    variable for N >= 2, so the interpolant is exact)."""
+             - bilinear interpolant of the corner values B(-1), B(1), T(-1), T(1),
+    term by term: a product f(t) g(s) of Chebyshev series has the outer
+    product of their coefficient vectors as its 2-D coefficients, and
+    (1 -+ s)/2 = T_0/2 -+ T_1/2.  (Exact zeros off rows 0, 1 and columns 0, 1:
+    the lift's Laplacian multiplies coefficient k by up to k^4, so a sampled
+    construction's rounding there would be amplified.)"""
     L, R, B, T = (np.asarray(v, dtype=np.float64) for v in bc)
     N = len(L)
-    x = basis.cheb_points(N)
+    hm = np.zeros(N)
+    hp = np.zeros(N)
+    hm[0], hp[0] = 0.5, 0.5
+    if N > 1:
+        hm[1], hp[1] = -0.5, 0.5
+    c00, c10 = npc.chebval(-1.0, B), npc.chebval(1.0, B)  # (s, t) = (-1, -1), (1, -1)
+    c01, c11 = npc.chebval(-1.0, T), npc.chebval(1.0, T)  # (-1, 1), (1, 1)
+    return (np.outer(L, hm) + np.outer(R, hp) + np.outer(hm, B) + np.outer(hp, T)
+            - (c00 * np.outer(hm, hm) + c10 * np.outer(hm, hp) + c01 * np.outer(hp, hm)
+               + c11 * np.outer(hp, hp)))
+
+
+def coons_coeffs_sampled(bc) -> np.ndarray:
+    """The same interpolant by sampling on the first-kind grid of size
+    Ns x Ns, Ns = max(2, leading trace coefficients up to the last nonzero
+    one), and the discrete cosine map (exact in exact arithmetic: u_bc has
+    degree <= Ns - 1 in each variable).  Independent check of coons_coeffs."""
+    L, R, B, T = (np.asarray(v, dtype=np.float64) for v in bc)
+    N = len(L)
+    nz = [np.nonzero(v)[0] for v in (L, R, B, T)]
+    Ns = max([2] + [int(z[-1]) + 1 for z in nz if z.size])
+    L, R, B, T = L[:Ns], R[:Ns], B[:Ns], T[:Ns]
+    x = basis.cheb_points(Ns)
     S, Tt = np.meshgrid(x, x, indexing="xy")  # S varies along columns (s), Tt along rows (t)
     Lv, Rv = npc.chebval(Tt, L), npc.chebval(Tt, R)
     Bv, Tv = npc.chebval(S, B), npc.chebval(S, T)
-    c00, c10 = npc.chebval(-1.0, B), npc.chebval(1.0, B)  # (s, t) = (-1, -1), (1, -1)
-    c01, c11 = npc.chebval(-1.0, T), npc.chebval(1.0, T)  # (-1, 1), (1, 1)
+    c00, c10 = npc.chebval(-1.0, B), npc.chebval(1.0, B)
+    c01, c11 = npc.chebval(-1.0, T), npc.chebval(1.0, T)
     vals = ((1 - S) / 2 * Lv + (1 + S) / 2 * Rv + (1 - Tt) / 2 * Bv + (1 + Tt) / 2 * Tv
             - ((1 - S) * (1 - Tt) * c00 + (1 + S) * (1 - Tt) * c10
                + (1 - S) * (1 + Tt) * c01 + (1 + S) * (1 + Tt) * c11) / 4)
-    D = basis.dct_matrix(N)
-    return D @ vals @ D.T
+    D = basis.dct_matrix(Ns)
+    out = np.zeros((N, N))
+    out[:Ns, :Ns] = D @ vals @ D.T
+    return out
 
 
 def laplacian_coeffs(U: np.ndarray, box) -> np.ndarray:
@@ -145,11 +172,44 @@ def cheb_to_ct_rect(n: int, N: int) -> np.ndarray:
     return (basis.ct_values(n, x) * w[None, :]) @ basis.cheb_T(N, x).T
 
 
+def cheb_to_ct_closed(n: int, N: int) -> np.ndarray:
+    """R (n x N) with R[i, k] = C~_i coefficient of T_k, entrywise to
+    relative accuracy, from the Gegenbauer connection formula (DLMF 18.18.16)
+    in the limit lambda -> 0 that gives T_k (DLMF 18.7.25):
+      T_k = (k/2) sum_l (k-l-1)! (-mu)_l (k - 2l + mu) / ((mu)_{k-l+1} l!) C^(mu)_{k-2l},
+    mu = 3/2, and C^(3/2)_i = C~_i / nu_i with nu_i = sqrt((i+3/2)/((i+1)(i+2)))
+    (footnote of Sec. 3.1).  The factors are accumulated as products of
+    ratios (relative error ~ k eps), unlike the quadrature of cheb_to_ct_rect
+    whose absolute error ~ eps swamps the small far-from-diagonal entries
+    (~ 1/k^2) when they multiply large coefficients."""
+    mu = 1.5
+    R = np.zeros((n, N))
+    if n == 0 or N == 0:
+        return R
+    i_all = np.arange(n, dtype=np.float64)
+    nu = np.sqrt((i_all + 1.5) / ((i_all + 1.0) * (i_all + 2.0)))
+    R[0, 0] = 1.0 / nu[0]  # T_0 = C^(mu)_0
+    k = np.arange(1, N, dtype=np.float64)
+    # t_0(k) = (k-1)! / (mu)_{k+1}, by t_0(1) = 1/(mu (mu+1)) and
+    # t_0(k) / t_0(k-1) = (k-1) / (mu + k)
+    t = np.cumprod(np.concatenate([[1.0 / (mu * (mu + 1.0))], (k[1:] - 1.0) / (mu + k[1:])]))
+    for l in range((N - 1) // 2 + 1):
+        i = k - 2 * l
+        ok = (i >= 0) & (i < n)
+        ii = i[ok].astype(int)
+        R[ii, k[ok].astype(int)] = (k[ok] / 2.0) * t[ok] * (i[ok] + mu) / nu[ii]
+        # t_{l+1} / t_l = (mu + k - l) (l - mu) / ((k - l - 1) (l + 1)); columns
+        # whose last term has passed are never read again
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = t * (mu + k - l) * (l - mu) / ((k - l - 1.0) * (l + 1.0))
+    return R
+
+
 def ct_projection(C_T: np.ndarray, n: int) -> np.ndarray:
     """First n x n C~ x C~ coefficients of a function given by a Chebyshev
-    coefficient array of any size."""
-    Ra = cheb_to_ct_rect(n, C_T.shape[0])
-    Rb = cheb_to_ct_rect(n, C_T.shape[1])
+    coefficient array of any size (the closed-form map on both axes)."""
+    Ra = cheb_to_ct_closed(n, C_T.shape[0])
+    Rb = Ra if C_T.shape[1] == C_T.shape[0] else cheb_to_ct_closed(n, C_T.shape[1])
     return Ra @ C_T @ Rb.T
 
 

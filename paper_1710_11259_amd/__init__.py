@@ -15,7 +15,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["lib", "Plan", "plan", "solve", "solve_adjoint", "solve_fn", "adi_native",
+__all__ = ["lib", "Plan", "plan", "solve", "solve_dirichlet", "solve_adjoint", "solve_fn",
+           "adi_native",
            "adi_shifts", "Batch", "batch", "batch_solve", "BatchGraph", "FpsError", "LIB_PATH"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -51,7 +52,11 @@ def lib() -> ctypes.CDLL:
                                   ctypes.c_int, ctypes.c_int, ctypes.c_uint]
     L.fps_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64),
                                 ctypes.POINTER(i64)]
+    L.fps_plan_create_rect.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(dbl), dbl,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_uint]
     L.fps_plan_shifts.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.fps_plan_shift_pairs.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    L.fps_solve_dirichlet.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fps_plan_refinement.argtypes = [vp, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int)]
     L.fps_plan_inner_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
@@ -80,7 +85,9 @@ def lib() -> ctypes.CDLL:
     L.fps_status_string.restype = ctypes.c_char_p
     L.fps_last_error.restype = ctypes.c_char_p
     L.fps_version.restype = ctypes.c_char_p
-    for name in ("fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_plan_refinement",
+    for name in ("fps_plan_create", "fps_plan_create_rect", "fps_plan_shift_pairs",
+                 "fps_solve_dirichlet",
+                 "fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_plan_refinement",
                  "fps_plan_inner_counts", "fps_plan_slice_counts",
                  "fps_adi_shifts", "fps_solve", "fps_solve_adjoint", "fps_adi_native",
                  "fps_batch_create", "fps_batch_info", "fps_batch_solve"):
@@ -108,20 +115,29 @@ def adi_shifts(a: float, b: float, c: float, d: float, tol: float):
 
 
 class Plan:
-    """Owning wrapper of an fps_plan."""
+    """Owning wrapper of an fps_plan.  With `box` = (a, b, c, d) the plan is
+    a rectangle plan (fps_plan_create_rect, dim 2)."""
 
     def __init__(self, n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
                  out: str = "cheb", host_only: bool = False, tight: bool = False,
-                 zeig: bool = False):
+                 zeig: bool = False, box=None):
         prec = {"fp64": FPS_FP64, "fp32_refined": FPS_FP32_REFINED}[precision]
         ob = {"cheb": FPS_OUT_CHEB, "native": FPS_OUT_NATIVE}[out]
         h = ctypes.c_void_p()
         flags = ((FPS_PLAN_HOST_ONLY if host_only else 0) | (FPS_PLAN_TIGHT_SPECTRUM if tight else 0)
                  | (FPS_PLAN_CUBE_ZEIG if zeig else 0))
-        _check(lib().fps_plan_create(ctypes.byref(h), dim, n, 0, tol, prec, ob, flags))
+        self._h = ctypes.c_void_p()
+        if box is not None:
+            if dim != 2:
+                raise ValueError("a box applies to 2-D plans only")
+            b = (ctypes.c_double * 4)(*[float(v) for v in box])
+            _check(lib().fps_plan_create_rect(ctypes.byref(h), n, b, tol, prec, ob, flags))
+            box = tuple(float(v) for v in box)
+        else:
+            _check(lib().fps_plan_create(ctypes.byref(h), dim, n, 0, tol, prec, ob, flags))
         self._h = h
         self.n, self.dim, self.tol, self.precision, self.out = n, dim, tol, precision, out
-        self.tight, self.zeig = tight, zeig
+        self.tight, self.zeig, self.box = tight, zeig, box
         J, ws, oe = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().fps_plan_info(h, ctypes.byref(J), ctypes.byref(ws), ctypes.byref(oe)))
         self.J, self.workspace_bytes, self.out_entries = J.value, ws.value, oe.value
@@ -137,6 +153,13 @@ class Plan:
         p = (ctypes.c_double * self.J)()
         _check(lib().fps_plan_shifts(self._h, p))
         return list(p)
+
+    def shift_pairs(self):
+        """(p, q) of Theorem 2.1 as the plan's ADI runs them."""
+        p = (ctypes.c_double * self.J)()
+        q = (ctypes.c_double * self.J)()
+        _check(lib().fps_plan_shift_pairs(self._h, p, q))
+        return list(p), list(q)
 
     def slice_counts(self):
         """Cube plans with zeig: ADI steps per z-slice (descending)."""
@@ -181,8 +204,8 @@ class Plan:
 
 def plan(n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
          out: str = "cheb", host_only: bool = False, tight: bool = False,
-         zeig: bool = False) -> Plan:
-    return Plan(n, tol, dim, precision, out, host_only, tight, zeig)
+         zeig: bool = False, box=None) -> Plan:
+    return Plan(n, tol, dim, precision, out, host_only, tight, zeig, box)
 
 
 def _stream_ptr(torch, device):
@@ -208,6 +231,28 @@ def solve(p: Plan, F, out=None, ws=None):
     _check(lib().fps_solve(p.handle, ctypes.c_void_p(F.data_ptr()),
                            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                            _stream_ptr(torch, F.device)))
+    return out
+
+
+def solve_dirichlet(p: Plan, F, bc, out=None, ws=None):
+    """U for f with coefficients F (n x n) and Dirichlet traces bc (4 x (n+2):
+    L, R in t, B, T in s), on a square or rectangle plan with Chebyshev
+    output."""
+    import torch
+    for name, t, shape in (("F", F, (p.n, p.n)), ("bc", bc, (4, p.n + 2))):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor on the GPU")
+        if tuple(t.shape) != shape:
+            raise ValueError(f"{name} must have shape {shape}")
+    if out is None:
+        out = torch.empty(p.out_shape(), dtype=torch.float64, device=F.device)
+    if ws is None:
+        ws = workspace(p, F.device)
+    _check(lib().fps_solve_dirichlet(p.handle, ctypes.c_void_p(F.data_ptr()),
+                                     ctypes.c_void_p(bc.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()),
+                                     _stream_ptr(torch, F.device)))
     return out
 
 
@@ -271,7 +316,8 @@ def solve_fn(F, plan: Plan):
 
 
 def adi_native(p: Plan, G, out=None, ws=None):
-    """Y_J of Algorithm 2 for A~ Y + Y A~ = G (natural order, n x n)."""
+    """Y_J of Algorithm 2 for A~ Y + Y A~ = G (natural order, n x n); for a
+    rectangle plan sx2 A~ Y + sy2 Y A~ = G."""
     import torch
     if G.dtype != torch.float64 or not G.is_cuda or not G.is_contiguous():
         raise ValueError("G must be a contiguous float64 tensor on the GPU")

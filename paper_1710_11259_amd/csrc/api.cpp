@@ -58,12 +58,12 @@ void release_events(fps_plan *pl) {
 // each).  Step j stores its outputs in float when pl->f32step[j] is set, so
 // a step reads its input in the type the previous step wrote it.  Leaves the
 // final chunk-local solution (double) in O1 and its chunk carries in ab, to
-// finalize with the tables of the last shift.
+// finalize with the tables of the last second half-step (pl->tab2(J - 1)).
 fps_status run_adi(fps_plan *pl, const void *Gterm, const void *GTin, int g_f32, void *O0,
                    void *O1, char *ws, hipStream_t st) {
   const fps::Layout &L = pl->L;
   const int J = pl->shifts.J;
-  const std::vector<double> &p = pl->shifts.p;
+  const std::vector<double> &p = pl->shifts.p, &q = pl->shifts.q;
   double *lv = (double *)(ws + pl->off_lv);
   double *ab = (double *)(ws + pl->off_ab);
   const int nc0 = (int)L.nc[0], nc1 = (int)L.nc[1];
@@ -81,47 +81,55 @@ fps_status run_adi(fps_plan *pl, const void *Gterm, const void *GTin, int g_f32,
   A.nc0 = nc0;
   A.nc1 = nc1;
   A.lv = lv;
-  // Half-step 1 of Algorithm 2 (rows of Y): right-hand side R_j =
-  // (A~ - p_j) Y_j - G, output V_j - G = R_j - 2 p_j Y_{j+1/2} (the G of
-  // V_j = G + Y_{j+1/2}(A~ - p_j) cancels against the -G in R_j).
-  // Half-step 2 (columns of Y): right-hand side V_j = (V_j - G) + G, output
-  // R_{j+1} = (A~ - p_{j+1}) Y_{j+1} - G = (V_j - G) - (p_j + p_{j+1}) Y_{j+1}.
-  // So only half-step 2 reads G.  R_0 = -G.  After every half-step the chunk
-  // carries are resolved into `ab`, which the next half-step folds in.
+  // Algorithm 2 for A Y - Y B = G with T1_j = -(B - p_j) (first half-step,
+  // along the columns of Y) and T2_j = A - q_j (second half-step, along the
+  // rows).  Half-step 1: right-hand side R_j = (A - p_j) Y_j - G, solve
+  // Y_{j+1/2} T1_j = R_j, output V_j - G = R_j - (p_j - q_j) Y_{j+1/2}
+  // (V_j = G - Y_{j+1/2}(B - q_j) and Y_{j+1/2}(B - q_j) = -R_j +
+  // (p_j - q_j) Y_{j+1/2}).  Half-step 2: right-hand side V_j = (V_j - G) + G,
+  // solve T2_j Y_{j+1} = V_j, output R_{j+1} = (V_j - G) - (p_{j+1} - q_j)
+  // Y_{j+1}.  So only half-step 2 reads G, and R_0 = -G.  For the square
+  // (q_j = -p_j, T1_j = T2_j = A~ + p_j) the coefficients are 2 p_j and
+  // p_j + p_{j+1}.  After every half-step the chunk carries are resolved
+  // into `ab`, which the next half-step folds in.
   for (int j = 0; j < J; ++j) {
+    const double s1 = pl->rect ? p[j] - q[j] : 2.0 * p[j];
     A.in = j == 0 ? GTin : (const void *)O1;
     A.in_f32 = j == 0 ? g_f32 : f32(j);
     A.in_scale = j == 0 ? -1.0 : 1.0;
     A.ab_prev = j == 0 ? nullptr : ab;
-    A.tab_prev = j == 0 ? nullptr : pl->tab_dev(j - 1);
+    A.tab_prev = j == 0 ? nullptr : pl->tab_dev(pl->tab2(j - 1));
     A.g = nullptr;
     A.g_f32 = 0;
     A.sg = 0.0;
-    A.tab = pl->tab_dev(j);
-    A.l1 = pl->l1_dev(j);
-    A.sigma = 2.0 * p[j];
+    A.tab = pl->tab_dev(pl->tab1(j));
+    A.l1 = pl->l1_dev(pl->tab1(j));
+    A.sigma = s1;
     A.out = O0;
     A.out_f32 = f32(j);
     A.out_mode = 0;
     FPS_HIP(timed_sweep(pl, A, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(j), ab, -A.sigma, L.npad, nc0, nc1, L.ncmax, st));
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab1(j)), ab, -A.sigma, L.npad, nc0, nc1,
+                               L.ncmax, st));
     fps::SweepArgs B = A;
     const bool last = j == J - 1;
     B.in = O0;
     B.in_f32 = f32(j);
     B.in_scale = 1.0;
     B.ab_prev = ab;
-    B.tab_prev = pl->tab_dev(j);
+    B.tab_prev = A.tab;
     B.g = Gterm;
     B.g_f32 = g_f32;
     B.sg = 1.0;
-    B.sigma = last ? 0.0 : p[j] + p[j + 1];
+    B.tab = pl->tab_dev(pl->tab2(j));
+    B.l1 = pl->l1_dev(pl->tab2(j));
+    B.sigma = last ? 0.0 : (pl->rect ? p[j + 1] - q[j] : p[j] + p[j + 1]);
     B.out = O1;
     B.out_f32 = last ? 0 : f32(j + 1);
     B.out_mode = last ? 1 : 0;
     FPS_HIP(timed_sweep(pl, B, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(j), ab, last ? 1.0 : -B.sigma, L.npad, nc0, nc1,
-                               L.ncmax, st));
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab2(j)), ab, last ? 1.0 : -B.sigma, L.npad,
+                               nc0, nc1, L.ncmax, st));
   }
   return FPS_OK;
 }
@@ -139,7 +147,7 @@ fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout)
   if (pl->prec == FPS_FP64) {
     double *GT = (double *)(w + pl->off_GT);
     if ((s = run_adi(pl, G, GT, 0, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK) return s;
-    FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, pl->tab_dev(J - 1),
+    FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, pl->tab_dev(pl->tab2(J - 1)),
                                          G, 0, nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax,
                                          st));
     *Yout = G;  // G is no longer needed
@@ -152,9 +160,10 @@ fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout)
   float *r = (float *)(w + pl->off_R), *rT = r + L.npad * L.npad;
   for (int k = 0; k < pl->rounds; ++k) {
     FPS_HIP(fps::launch_residual(G, k == 0 ? nullptr : Y, (const double *)pl->d_sdiag.p,
-                                 (const double *)pl->d_soff.p, r, rT, L.npad, st));
+                                 (const double *)pl->d_soff.p, r, rT, L.npad, st, pl->sx2,
+                                 pl->sy2));
     if ((s = run_adi(pl, r, rT, 1, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK) return s;
-    FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, pl->tab_dev(J - 1),
+    FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, pl->tab_dev(pl->tab2(J - 1)),
                                          Y, k == 0 ? 0 : 2, nullptr, L.n, L.npad, L.mp[0],
                                          L.mstride, L.ncmax, st));
   }
@@ -198,7 +207,21 @@ int rhs_gemms(const fps_plan *pl, char *ws, fps::GemmProb *g1, fps::GemmProb *g2
   return cnt;
 }
 
-fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st) {
+// Constants of the Dirichlet lift.  C~_0 = sqrt(3)/2 and C~_1(t) =
+// sqrt(5/12) 3t (normalization of Sec. 3.1), so under the weight (1 - t^2)
+// <1, C~_0> = 2/sqrt(3) and <t, C~_1> = 2/sqrt(15): (1 -+ t)/2 has C~
+// coefficients 1/sqrt(3) and -+1/sqrt(15).
+fps::BcLiftConst bc_lift_const() {
+  fps::BcLiftConst k;
+  k.sinv[0] = 1.0 / std::sqrt(2.0);
+  k.sinv[1] = 1.0 / std::sqrt(6.0);
+  k.am[0] = k.ap[0] = 1.0 / std::sqrt(3.0);
+  k.ap[1] = 1.0 / std::sqrt(15.0);
+  k.am[1] = -k.ap[1];
+  return k;
+}
+
+fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st, const double *bc) {
   const fps::Layout &L = pl->L;
   // F in the parity-blocked layout (zero padded), staged in the GT region.
   FPS_HIP(fps::launch_permute_in(F, (double *)(ws + pl->off_GT), L.n, L.npad, L.mp[0], st));
@@ -206,6 +229,11 @@ fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st
   const int cnt = rhs_gemms(pl, ws, g1, g2);
   FPS_HIP(fps::launch_gemm(g1, cnt, st));
   FPS_HIP(fps::launch_gemm(g2, cnt, st));
+  if (bc)
+    FPS_HIP(fps::launch_bc_lift_rhs(bc, (const double *)pl->d_RsA[0].p,
+                                    (const double *)pl->d_RsA[1].p, (double *)(ws + pl->off_G),
+                                    (double *)(ws + pl->off_bc), L, pl->sx2, pl->sy2,
+                                    bc_lift_const(), st));
   FPS_HIP(fps::launch_transpose((const double *)(ws + pl->off_G), (double *)(ws + pl->off_GT),
                                 L.npad, st));
   return FPS_OK;
@@ -249,49 +277,9 @@ fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hip
   return FPS_OK;
 }
 
-}  // namespace detail
-}  // namespace fps
-
-using namespace fps::detail;
-
-extern "C" {
-
-const char *fps_version(void) { return "fps 0.1 (gfx950)"; }
-
-const char *fps_status_string(fps_status s) {
-  switch (s) {
-    case FPS_OK: return "ok";
-    case FPS_E_ARG: return "invalid argument";
-    case FPS_E_UNSUPPORTED: return "unsupported";
-    case FPS_E_NOMEM: return "out of memory";
-    case FPS_E_HIP: return "HIP runtime error";
-    case FPS_E_STATE: return "invalid state";
-  }
-  return "unknown status";
-}
-
-const char *fps_last_error(void) { return last_error(); }
-
-fps_status fps_adi_shifts(double a, double b, double c, double d, double tol, int cap, int *J,
-                          double *p, double *q) {
-  if (!J) return fail(FPS_E_ARG, "J must not be null");
-  fps::ShiftSet S;
-  std::string err;
-  if (!fps::zolotarev_shifts(a, b, c, d, tol, S, err)) return fail(FPS_E_ARG, err);
-  *J = S.J;
-  if (cap < S.J) return fail(FPS_E_STATE, "cap smaller than J");
-  if (!p || !q) return fail(FPS_E_ARG, "null output arrays");
-  for (int j = 0; j < S.J; ++j) {
-    p[j] = S.p[j];
-    q[j] = S.q[j];
-  }
-  return FPS_OK;
-}
-
-fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double tol, int prec,
-                           int out_basis, unsigned flags) {
-  if (!out) return fail(FPS_E_ARG, "out must not be null");
-  *out = nullptr;
+// Validates the arguments shared by every plan kind and allocates the plan.
+fps_status plan_common(fps_plan **out, int dim, int64_t n, int bc, double tol, int prec,
+                       int out_basis, unsigned flags) {
   if (dim != 2 && dim != 3) return fail(FPS_E_ARG, "dim must be 2 or 3");
   if (n < 1) return fail(FPS_E_ARG, "n must be >= 1");
   if (n > 200000) return fail(FPS_E_ARG, "n too large");
@@ -308,7 +296,6 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   if (dim == 3 && prec != FPS_FP64)
     return fail(FPS_E_UNSUPPORTED, "the cube solver runs in FP64 only");
   if (dim == 3 && n > 1024) return fail(FPS_E_UNSUPPORTED, "cube solves are limited to n <= 1024");
-
   fps_plan *pl = new (std::nothrow) fps_plan();
   if (!pl) return fail(FPS_E_NOMEM, "plan allocation failed");
   pl->dim = dim;
@@ -317,27 +304,28 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   pl->prec = prec;
   pl->out_basis = out_basis;
   pl->flags = flags;
-  if (dim == 3) {
-    fps_status s = cube_plan_build(pl);
-    if (s == FPS_OK && !(flags & FPS_PLAN_HOST_ONLY)) s = cube_plan_upload(pl);
-    if (s != FPS_OK) {
-      delete pl;
-      return s;
-    }
-    pl->on_device = !(flags & FPS_PLAN_HOST_ONLY);
-    *out = pl;
-    return FPS_OK;
-  }
+  *out = pl;
+  return FPS_OK;
+}
+
+// Square or rectangle plan (common fields, and for a rectangle rect / box /
+// sx2 / sy2, already set): shifts, sweep tables, coefficient maps,
+// workspace layout, and the device copies unless host-only.
+fps_status plan2d_build(fps_plan *pl) {
+  const int64_t n = pl->n;
+  const int prec = pl->prec;
+  const unsigned flags = pl->flags;
+  const double tol = pl->tol;
   // Lemma B.1: sigma(A~) in [-1, -1/(30 n^4)]; sigma(B~) = sigma(-A~).
   const double delta = 1.0 / (30.0 * (double)n * (double)n * (double)n * (double)n);
   // FP32_REFINED: each refinement round runs an ADI to kInnerTol and the
   // round count is the least R with kRoundFactor^R <= tol.  Float storage is
-  // used only by the steps with |p_j| >= kF32MinShift: a stored value enters
-  // the next solve through (A~ + p_j I)^-1, which magnifies its rounding
-  // error by up to about 1/|p_j| in the modes near the bottom of the
-  // spectrum; storing the small-shift steps in float stalls or reverses the
-  // refinement for n >= 256, while this split contracts the error by <= 1e-7
-  // per round.
+  // used only by the steps with large shifts (|p_j| >= kF32MinShift for the
+  // square): a stored value enters the next solve through (A~ + p_j I)^-1,
+  // which magnifies its rounding error by up to about 1/|p_j| against the
+  // top modes of the residual the round corrects; storing the small-shift
+  // steps in float stalls or reverses the refinement for n >= 256, while
+  // this split contracts the error by <= 1e-7 per round.
   constexpr double kInnerTol = 1e-7, kRoundFactor = 3e-7, kF32MinShift = 1e-2;
   double adi_tol = tol;
   if (prec == FPS_FP32_REFINED) {
@@ -348,20 +336,52 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   std::string err;
   double ea = -1.0, eb = -delta;  // enclosure of sigma(A~)
   if (flags & FPS_PLAN_TIGHT_SPECTRUM) spectrum_tight(n, &ea, &eb);
-  if (!fps::zolotarev_shifts(ea, eb, -eb, -ea, adi_tol, pl->shifts, err)) {
-    delete pl;
+  // Theorem 2.1 intervals: sigma(A) in sx2 [ea, eb], sigma(B) in sy2 [-eb, -ea].
+  if (!fps::zolotarev_shifts(pl->sx2 * ea, pl->sx2 * eb, -pl->sy2 * eb, -pl->sy2 * ea, adi_tol,
+                             pl->shifts, err))
     return fail(FPS_E_ARG, err);
+  // FP64: apply the steps in order of increasing |p_j| (the reverse of the
+  // planner's order).  The J-step result does not depend on the order in
+  // exact arithmetic (the error factors commute), but rounding does: a
+  // small-shift step magnifies the rounding of its inputs by up to
+  // ~ (sx2 + sy2) / |shift| in some modes, and the large-shift steps that
+  // follow it damp those modes.  In the opposite order the symmetrized
+  // iterate carries ~1e-10 relative error on Dirichlet-lift right-hand
+  // sides (rows 0, 1 spanning every column mode) instead of ~1e-13.
+  // FP32_REFINED keeps the planner's order: its float-stored large-shift
+  // steps need the later small-shift steps to damp their float rounding,
+  // and each round's residual is formed afresh in FP64.
+  if (prec == FPS_FP64) {
+    std::reverse(pl->shifts.p.begin(), pl->shifts.p.end());
+    std::reverse(pl->shifts.q.begin(), pl->shifts.q.end());
   }
+  const fps::ShiftSet &sh = pl->shifts;
   pl->f32step.assign((size_t)pl->shifts.J + 1, 0);
   if (prec == FPS_FP32_REFINED)
-    for (int j = 0; j < pl->shifts.J; ++j)
-      if (std::fabs(pl->shifts.p[j]) >= kF32MinShift) {
+    for (int j = 0; j < sh.J; ++j)
+      // Step j's stored arrays enter the solves with sy2 A~ + p_j and
+      // sx2 A~ - q_j, which magnify their rounding error in the top modes
+      // (|alpha - beta| up to sx2 + sy2) by about (sx2 + sy2) / |shift|;
+      // for the square this is the |p_j| >= kF32MinShift rule.
+      if (std::fabs(sh.p[j]) >= kF32MinShift * 0.5 * (pl->sx2 + pl->sy2) &&
+          std::fabs(sh.q[j]) >= kF32MinShift * 0.5 * (pl->sx2 + pl->sy2)) {
         pl->f32step[j] = 1;
         ++pl->n_f32;
       }
   pl->L = fps::make_layout(n);
-  fps::build_sweep_tables_ab(pl->L, std::vector<double>(pl->shifts.p.size(), 1.0), pl->shifts.p,
-                             pl->tab, pl->ctab, nullptr, pl->l1);
+  if (pl->rect) {  // tables 2j: sy2 A~ + p_j, 2j + 1: sx2 A~ - q_j
+    std::vector<double> alpha, beta;
+    for (int j = 0; j < sh.J; ++j) {
+      alpha.push_back(pl->sy2);
+      beta.push_back(sh.p[j]);
+      alpha.push_back(pl->sx2);
+      beta.push_back(-sh.q[j]);
+    }
+    fps::build_sweep_tables_ab(pl->L, alpha, beta, pl->tab, pl->ctab, nullptr, pl->l1);
+  } else {
+    fps::build_sweep_tables_ab(pl->L, std::vector<double>(sh.p.size(), 1.0), sh.p, pl->tab,
+                               pl->ctab, nullptr, pl->l1);
+  }
   fps::build_conversions(pl->L, pl->Rs, pl->P);
   std::vector<double> RsA[2], RsB[2], PA[2], PB[2];
   for (int s = 0; s < 2; ++s) {
@@ -412,6 +432,8 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
     pl->off_R = pl->ws_bytes;  // r and r^T, npad^2 floats each
     pl->ws_bytes += sq;
   }
+  pl->off_bc = pl->ws_bytes;
+  pl->ws_bytes += align256((4 * (n + 2) + 4 * n + 4 * L.npad + 8) * 8);
 
   if (!(flags & FPS_PLAN_HOST_ONLY)) {
     fps_status s;
@@ -422,11 +444,97 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
         (s = upload(pl->d_PA[0], PA[0])) != FPS_OK || (s = upload(pl->d_PA[1], PA[1])) != FPS_OK ||
         (s = upload(pl->d_PB[0], PB[0])) != FPS_OK || (s = upload(pl->d_PB[1], PB[1])) != FPS_OK ||
         (s = upload(pl->d_sinv, pl->sinv)) != FPS_OK || (s = upload(pl->d_sdiag, pl->sdiag)) != FPS_OK ||
-        (s = upload(pl->d_soff, pl->soff)) != FPS_OK) {
-      delete pl;
+        (s = upload(pl->d_soff, pl->soff)) != FPS_OK)
       return s;
-    }
     pl->on_device = true;
+  }
+  return FPS_OK;
+}
+
+}  // namespace detail
+}  // namespace fps
+
+using namespace fps::detail;
+
+extern "C" {
+
+const char *fps_version(void) { return "fps 0.1 (gfx950)"; }
+
+const char *fps_status_string(fps_status s) {
+  switch (s) {
+    case FPS_OK: return "ok";
+    case FPS_E_ARG: return "invalid argument";
+    case FPS_E_UNSUPPORTED: return "unsupported";
+    case FPS_E_NOMEM: return "out of memory";
+    case FPS_E_HIP: return "HIP runtime error";
+    case FPS_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char *fps_last_error(void) { return last_error(); }
+
+fps_status fps_adi_shifts(double a, double b, double c, double d, double tol, int cap, int *J,
+                          double *p, double *q) {
+  if (!J) return fail(FPS_E_ARG, "J must not be null");
+  fps::ShiftSet S;
+  std::string err;
+  if (!fps::zolotarev_shifts(a, b, c, d, tol, S, err)) return fail(FPS_E_ARG, err);
+  *J = S.J;
+  if (cap < S.J) return fail(FPS_E_STATE, "cap smaller than J");
+  if (!p || !q) return fail(FPS_E_ARG, "null output arrays");
+  for (int j = 0; j < S.J; ++j) {
+    p[j] = S.p[j];
+    q[j] = S.q[j];
+  }
+  return FPS_OK;
+}
+
+fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double tol, int prec,
+                           int out_basis, unsigned flags) {
+  if (!out) return fail(FPS_E_ARG, "out must not be null");
+  *out = nullptr;
+  fps_plan *pl = nullptr;
+  fps_status s = plan_common(&pl, dim, n, bc, tol, prec, out_basis, flags);
+  if (s != FPS_OK) return s;
+  if (dim == 3) {
+    s = cube_plan_build(pl);
+    if (s == FPS_OK && !(flags & FPS_PLAN_HOST_ONLY)) s = cube_plan_upload(pl);
+    pl->on_device = s == FPS_OK && !(flags & FPS_PLAN_HOST_ONLY);
+  } else {
+    s = plan2d_build(pl);
+  }
+  if (s != FPS_OK) {
+    delete pl;
+    return s;
+  }
+  *out = pl;
+  return FPS_OK;
+}
+
+fps_status fps_plan_create_rect(fps_plan **out, int64_t n, const double *box, double tol, int prec,
+                                int out_basis, unsigned flags) {
+  if (!out) return fail(FPS_E_ARG, "out must not be null");
+  *out = nullptr;
+  if (!box) return fail(FPS_E_ARG, "box must not be null");
+  const double a = box[0], b = box[1], c = box[2], d = box[3];
+  if (!(std::isfinite(a) && std::isfinite(b) && std::isfinite(c) && std::isfinite(d)) ||
+      !(b > a) || !(d > c))
+    return fail(FPS_E_ARG, "box must be finite with a < b and c < d");
+  const double sx = 2.0 / (b - a), sy = 2.0 / (d - c);
+  if (!(std::isfinite(sx * sx) && std::isfinite(sy * sy) && sx * sx > 0.0 && sy * sy > 0.0))
+    return fail(FPS_E_ARG, "box side lengths out of range");
+  if (flags & FPS_PLAN_CUBE_ZEIG) return fail(FPS_E_ARG, "FPS_PLAN_CUBE_ZEIG applies to cube plans only");
+  fps_plan *pl = nullptr;
+  fps_status s = plan_common(&pl, 2, n, FPS_BC_DIRICHLET_ZERO, tol, prec, out_basis, flags);
+  if (s != FPS_OK) return s;
+  pl->rect = true;
+  for (int i = 0; i < 4; ++i) pl->box[i] = box[i];
+  pl->sx2 = sx * sx;
+  pl->sy2 = sy * sy;
+  if ((s = plan2d_build(pl)) != FPS_OK) {
+    delete pl;
+    return s;
   }
   *out = pl;
   return FPS_OK;
@@ -476,6 +584,34 @@ fps_status fps_plan_shifts(const fps_plan *pl, double *p) {
   return FPS_OK;
 }
 
+fps_status fps_plan_shift_pairs(const fps_plan *pl, double *p, double *q) {
+  if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (!p || !q) return fail(FPS_E_ARG, "null output");
+  for (int j = 0; j < pl->shifts.J; ++j) {
+    p[j] = pl->shifts.p[j];
+    q[j] = pl->shifts.q[j];
+  }
+  return FPS_OK;
+}
+
+fps_status fps_solve_dirichlet(fps_plan *pl, const double *F, const double *bc, double *U, void *ws,
+                               void *stream) {
+  fps_status s = check_solve_args(pl, F, U, ws);
+  if (s != FPS_OK) return s;
+  if (!bc) return fail(FPS_E_ARG, "null pointer argument");
+  if (pl->dim != 2) return fail(FPS_E_UNSUPPORTED, "Dirichlet data: square and rectangle plans only");
+  if (pl->out_basis != FPS_OUT_CHEB)
+    return fail(FPS_E_UNSUPPORTED, "Dirichlet data need the Chebyshev output basis");
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  if ((s = rhs_transform(pl, F, w, st, bc)) != FPS_OK) return s;
+  double *Y = nullptr;
+  if ((s = solve_symmetric(pl, w, st, &Y)) != FPS_OK) return s;
+  if ((s = out_transform(pl, Y, U, w, st)) != FPS_OK) return s;
+  FPS_HIP(fps::launch_bc_lift_out(U, bc, (const double *)(w + pl->off_bc), pl->L.n, pl->L.npad, st));
+  return FPS_OK;
+}
+
 fps_status fps_solve(fps_plan *pl, const double *F, double *U, void *ws, void *stream) {
   fps_status s = check_solve_args(pl, F, U, ws);
   if (s != FPS_OK) return s;
@@ -508,7 +644,7 @@ fps_status fps_adi_native(fps_plan *pl, const double *G, double *Y, void *ws, vo
   if ((s = run_adi(pl, Gp, GT, 0, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK) return s;
   const int J = pl->shifts.J;
   FPS_HIP(fps::launch_finalize<double>((double *)(w + pl->off_O1), (double *)(w + pl->off_ab),
-                                       pl->tab_dev(J - 1), Y, 1, nullptr, L.n, L.npad, L.mp[0],
+                                       pl->tab_dev(pl->tab2(J - 1)), Y, 1, nullptr, L.n, L.npad, L.mp[0],
                                        L.mstride, L.ncmax, st));
   return FPS_OK;
 }

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ G,
                                                   const double *__restrict__ dv,
                                                   const double *__restrict__ ev,
                                                   float *__restrict__ r, float *__restrict__ rT,
-                                                  int64_t npad) {
+                                                  int64_t npad, double ax, double ay) {
   __shared__ float tile[64][65];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ G,
       const double yu = i > 0 ? y[-npad] : 0.0, yd = i + 1 < npad ? y[npad] : 0.0;
       const double yl = q > 0 ? y[-1] : 0.0, yr = q + 1 < npad ? y[1] : 0.0;
       const double eil = i > 0 ? ev[i - 1] : 0.0;
-      res -= (dv[i] + dq) * yc + eil * yu + ev[i] * yd + eql * yl + eq * yr;
+      res -= ax * (dv[i] * yc + eil * yu + ev[i] * yd) + ay * (dq * yc + eql * yl + eq * yr);
     }
     r[i * npad + q] = (float)res;
     tile[rr][tx] = (float)res;
@@ -280,10 +280,11 @@ template hipError_t launch_finalize<float>(const float *, const double *, const 
                                            int64_t, hipStream_t);
 
 hipError_t launch_residual(const double *G, const double *Y, const double *dv, const double *ev,
-                           float *r, float *rT, int64_t npad, hipStream_t st) {
+                           float *r, float *rT, int64_t npad, hipStream_t st, double ax,
+                           double ay) {
   if (npad % 64 != 0) return hipErrorInvalidValue;
   dim3 grid((unsigned)(npad / 64), (unsigned)(npad / 64));
-  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, st, G, Y, dv, ev, r, rT, npad);
+  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, st, G, Y, dv, ev, r, rT, npad, ax, ay);
   return hipGetLastError();
 }
 

@@ -118,8 +118,10 @@ hipError_t launch_finalize(const T *x, const double *ab, const double *tab, doub
 // r = G - (A~ Y + Y A~) (Y null: r = G), in FP64, stored in float as r and
 // r^T.  A~ acts along each parity block as a tridiagonal stencil with
 // diagonal dv[] and coupling ev[] (ev[k] couples positions k and k+1).
+// For a rectangle the operator is ax A~ Y + ay Y A~ (ax = sx2, ay = sy2).
 hipError_t launch_residual(const double *G, const double *Y, const double *dv, const double *ev,
-                           float *r, float *rT, int64_t npad, hipStream_t st);
+                           float *r, float *rT, int64_t npad, hipStream_t st, double ax = 1.0,
+                           double ay = 1.0);
 
 // natural n x n (ld n) -> parity-blocked npad x npad (zero padding); with
 // `sinv` non-null, entry (i, j) is multiplied by sinv[i] * sinv[j].
@@ -159,6 +161,25 @@ hipError_t launch_cube_ifinal(const double *x, const double *ab, const double *t
                               double cb, int64_t npad, int64_t mp0, int64_t mstride, int64_t ncmax,
                               hipStream_t st);
 hipError_t launch_fill(double *dst, int64_t count, double v, hipStream_t st);
+
+// Nonhomogeneous Dirichlet data (Sec. 6.1), traces bc = [L; R; B; T], each
+// n + 2 Chebyshev coefficients in the mapped variable (L, R in t; B, T in s).
+// Constants of the lift: sinv[i] = 1/sqrt((i+1)(i+2)) and the C~
+// coefficients am / ap of (1 - t)/2 and (1 + t)/2 at degrees 0 and 1.
+struct BcLiftConst {
+  double sinv[2], am[2], ap[2];
+};
+// G (parity-blocked, row stride npad) -= S^-1 C~(Lap u_bc) S^-1, touching
+// rows 0, 1 and columns 0, 1 only.  Rs0 / Rs1: the Chebyshev -> C~ blocks
+// S^-1 R (row stride mp_s, upper triangular).  scratch: [4][n+2] + [4][n] +
+// [4][npad] + [8] doubles; its last 8 entries keep the traces' values at
+// -1 and +1 for launch_bc_lift_out.
+hipError_t launch_bc_lift_rhs(const double *bc, const double *Rs0, const double *Rs1, double *G,
+                              double *scratch, const Layout &L, double sx2, double sy2,
+                              const BcLiftConst &k, hipStream_t st);
+// U ((n+2) x (n+2) Chebyshev, natural order) += coefficients of u_bc.
+hipError_t launch_bc_lift_out(double *U, const double *bc, const double *scratch, int64_t n,
+                              int64_t npad, hipStream_t st);
 
 // FP64 GEMM on MFMA, up to 4 independent problems per launch:
 //   C(i,j) = sum_k A(i,k) B(k,j),  A(i,k) = A[i*sai + k], B(k,j) = B[k*sbk + j],

@@ -58,6 +58,18 @@ struct fps_plan {
   // (FP32_REFINED, |p_j| >= kF32MinShift); f32step[J] = 0.
   std::vector<char> f32step;
   int n_f32 = 0;
+
+  // Rectangle [a, b] x [c, d] (rect plans): the symmetric form reads
+  // sx2 A~ Y + sy2 Y A~ = G with sx2 = (2/(b-a))^2, sy2 = (2/(d-c))^2, i.e.
+  // A Y - Y B = G for A = sx2 A~ (rows), B = -sy2 A~ (columns).  ADI step j
+  // then solves with two matrices: table 2j holds sy2 A~ + p_j (first
+  // half-step), table 2j + 1 holds sx2 A~ - q_j (second half-step).  The
+  // square uses one table per step (A~ + p_j, q_j = -p_j) and sx2 = sy2 = 1.
+  bool rect = false;
+  double box[4] = {-1.0, 1.0, -1.0, 1.0};
+  double sx2 = 1.0, sy2 = 1.0;
+  int tab1(int j) const { return rect ? 2 * j : j; }
+  int tab2(int j) const { return rect ? 2 * j + 1 : j; }
   fps::Layout L;
   std::vector<double> tab, ctab, l1;  // host sweep tables
   std::vector<double> sdiag, soff;          // A~ stencil in the parity-blocked layout
@@ -79,6 +91,10 @@ struct fps_plan {
   int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab = 0;
   int64_t off_X = 0;  // adjoint: the output cotangent in the parity-blocked layout
   int64_t off_R = 0;  // FP32_REFINED: the float residual and its transpose
+  // Dirichlet lift (2-D plans): second derivatives of the four traces
+  // [4][n], their mapped C~ coefficients [4][npad] (parity-blocked), and the
+  // corner values [8].
+  int64_t off_bc = 0;
 
   // Cube (dim 3), two-level nested ADI: `shifts` holds the outer shifts
   // (p in [-2/delta, -2], q in [1, 1/delta]); inner step (i, j) has shift
@@ -136,9 +152,12 @@ fps_status upload(DeviceBuf &b, const std::vector<T> &h) {
   FPS_HIP(hipMemcpy(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   return FPS_OK;
 }
-// Input map of one square problem: F (n x n, natural order) -> G and G^T in
-// the plan's workspace `ws`.
-fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st);
+// Input map of one square or rectangle problem: F (n x n, natural order) ->
+// G and G^T in the plan's workspace `ws`; with `bc` non-null, G also takes
+// the Dirichlet lift's correction (the traces' values at -1 and +1 are kept
+// in the workspace for the output correction).
+fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st,
+                         const double *bc = nullptr);
 // The coefficient-map GEMMs of one problem (up to 4 parity-block products
 // per stage; returns their count), operands formed from the workspace base
 // `ws` (and Y, U); rhs: g1 then g2 after k_permute_in of F into the GT

@@ -42,7 +42,8 @@ def test_plan_shifts_match_oracle(n):
     p = fps.plan(n, tol=1e-13, host_only=True)
     J, po, _ = oshifts.square_shifts(n, 1e-13)
     assert p.J == J
-    assert np.allclose(p.shifts(), po, rtol=2e-14, atol=0)
+    # applied in order of increasing |p_j|, the reverse of Theorem 2.1's indexing
+    assert np.allclose(p.shifts(), po[::-1], rtol=2e-14, atol=0)
 
 
 @pytest.mark.parametrize("iv", [(-5.0, -0.5, 0.2, 3.0), (-1.0, -1e-3, 1e-3, 1.0), (-2.0, -1.0, 3.0, 100.0)])
@@ -86,7 +87,7 @@ def test_workspace_and_extent_queries():
 def test_refinement_structure(n):
     # FP64: one pass, no float steps.  FP32_REFINED to 1e-13: two rounds of
     # an inner ADI to 1e-7 whose float-stored steps are exactly those with
-    # |p_j| >= 1e-2 (a prefix, since |p_j| decreases with j).
+    # |p_j| >= 1e-2 (|p_j| decreases with j in Theorem 2.1's indexing).
     d = fps.plan(n, tol=1e-13, host_only=True)
     assert (d.rounds, d.f32_steps) == (1, 0)
     r = fps.plan(n, tol=1e-13, precision="fp32_refined", host_only=True)
@@ -341,7 +342,7 @@ def test_tight_spectrum_plan_counts(n):
         a, b = lam.min() * (1 + 1e-6), lam.max() * (1 - 1e-6)
         assert p.J == oshifts.iteration_count(a, b, -b, -a, 1e-13)
         J, po, _ = oshifts.zolotarev_shifts(a, b, -b, -a, tol=1e-13)
-        np.testing.assert_allclose(p.shifts(), po, rtol=1e-8)
+        np.testing.assert_allclose(p.shifts(), po[::-1], rtol=1e-8)
     expected = {64: 44, 1024: 78, 4096: 96}
     assert p.J == expected[n]
 
@@ -388,3 +389,60 @@ def test_zeig_cube_plan_slice_counts_match_oracle(n, tight):
     assert p.J == want[0]
     with pytest.raises(fps.FpsError):
         p.inner_counts()
+
+
+RECT_BOXES = [(0.0, 2.5, -1.0, 0.25), (0.0, 10.0, 0.0, 1.0), (-3.0, 3.0, -3.0, 3.0)]
+
+
+@pytest.mark.parametrize("box", RECT_BOXES)
+@pytest.mark.parametrize("n", [1, 5, 64, 4096])
+def test_rect_plan_shifts_match_oracle(n, box):
+    from oracle import rect
+    p = fps.plan(n, tol=1e-13, box=box, host_only=True)
+    J, po, qo = rect.rect_shifts(n, box, 1e-13)
+    assert p.J == J
+    pl, ql = p.shift_pairs()
+    scale = max(abs(v) for v in rect.rect_enclosure(n, box))
+    np.testing.assert_allclose(pl, po[::-1], rtol=1e-13, atol=1e-15 * scale)
+    np.testing.assert_allclose(ql, qo[::-1], rtol=1e-13, atol=1e-15 * scale)
+    assert np.all(np.diff(np.abs(pl)) >= 0)
+    assert p.out_entries == (n + 2) ** 2
+
+
+def test_rect_plan_tight_and_refined():
+    from oracle import rect
+    box = RECT_BOXES[1]
+    n = 256
+    lam, _ = square.atilde_eig(n)
+    lo, hi = lam.min() * (1 + 1e-6), lam.max() * (1 - 1e-6)
+    p = fps.plan(n, tol=1e-13, box=box, host_only=True, tight=True)
+    J, po, qo = rect.rect_shifts(n, box, 1e-13, lam=(lo, hi))
+    assert p.J == J < fps.plan(n, tol=1e-13, box=box, host_only=True).J
+    pl, ql = p.shift_pairs()
+    np.testing.assert_allclose(pl, po[::-1], rtol=1e-8)
+    np.testing.assert_allclose(ql, qo[::-1], rtol=1e-8)
+    r = fps.plan(n, tol=1e-13, box=box, precision="fp32_refined", host_only=True)
+    assert r.rounds == 2 and 0 < r.f32_steps < r.J
+    rp = r.shift_pairs()[0]
+    assert np.all(np.diff(np.abs(rp)) <= 0)  # refined: decreasing |p_j|
+    # a unit box is the square plan
+    u = fps.plan(n, tol=1e-13, box=(-1.0, 1.0, -1.0, 1.0), host_only=True)
+    s = fps.plan(n, tol=1e-13, host_only=True)
+    assert u.J == s.J
+    np.testing.assert_allclose(u.shift_pairs()[0], s.shifts(), rtol=0, atol=0)
+
+
+def test_rect_and_dirichlet_argument_errors():
+    L = fps.lib()
+    h = ctypes.c_void_p()
+    for box in [(1.0, 1.0, 0.0, 1.0), (0.0, 1.0, 2.0, -2.0), (0.0, float("inf"), 0.0, 1.0),
+                (float("nan"), 1.0, 0.0, 1.0)]:
+        b = (ctypes.c_double * 4)(*box)
+        assert L.fps_plan_create_rect(ctypes.byref(h), 16, b, 1e-13, 0, 0, 1) == 1, box
+    b = (ctypes.c_double * 4)(0.0, 1.0, 0.0, 2.0)
+    assert L.fps_plan_create_rect(ctypes.byref(h), 16, None, 1e-13, 0, 0, 1) == 1
+    assert L.fps_plan_create_rect(ctypes.byref(h), 16, b, 1e-13, 0, 0, 4 | 1) == 1  # cube flag
+    assert L.fps_plan_create_rect(ctypes.byref(h), 0, b, 1e-13, 0, 0, 1) == 1
+    p = fps.plan(16, box=(0.0, 1.0, 0.0, 2.0), host_only=True)
+    assert L.fps_solve_dirichlet(p.handle, None, None, None, None, None) == 5  # host-only
+    assert L.fps_solve_dirichlet(None, None, None, None, None, None) == 5

@@ -180,3 +180,55 @@ def test_rect_shifts_lie_in_their_intervals():
     assert np.all((q >= c) & (q <= d))
     # the unequal scalings break the p = -q symmetry of the square
     assert np.abs(p + q).max() > 1e-3 * np.abs(p).max()
+
+
+def test_coons_coefficients_match_sampled_interpolant():
+    for n, seed in ((1, 1), (6, 2), (30, 3)):
+        _, bc = workloads.rect_dirichlet_case(n, seed=seed)
+        assert np.abs(rect.coons_coeffs(bc) - rect.coons_coeffs_sampled(bc)).max() < 1e-14
+    # traces with trailing zeros: the sampled version uses a small grid
+    n = 20
+    _, small = workloads.rect_dirichlet_case(6, seed=2)
+    bc = np.zeros((4, n + 2))
+    bc[:, :8] = small
+    assert np.abs(rect.coons_coeffs(bc) - rect.coons_coeffs_sampled(bc)).max() < 1e-14
+
+
+def test_closed_form_ct_map():
+    # against the Gauss-Jacobi quadrature map (absolute accuracy)
+    for n in (1, 5, 40, 200):
+        Rq = rect.cheb_to_ct_rect(n, n + 2)
+        Rc = rect.cheb_to_ct_closed(n, n + 2)
+        assert np.abs(Rq - Rc).max() < 1e-13
+    # entrywise relative accuracy through the three-term recurrences:
+    # x T_k = (T_{k+1} + T_{k-1})/2 and x C~_i = b_i C~_{i+1} + b_{i-1} C~_{i-1}
+    # (b_i = sqrt((i+1)(i+3)/((2i+3)(2i+5))), the C~ Jacobi matrix)
+    n = 1024
+    Rc = rect.cheb_to_ct_closed(n + 1, n + 2)
+    i = np.arange(n + 1, dtype=np.float64)
+    b = np.sqrt((i + 1) * (i + 3) / ((2 * i + 3) * (2 * i + 5)))
+    worst = 0.0
+    for k in range(1, n + 1):
+        c = Rc[:, k]
+        xc = np.zeros(n + 1)
+        xc[1:] += b[:-1] * c[:-1]
+        xc[:-1] += b[:-1] * c[1:]
+        rhs = 0.5 * (Rc[:, k + 1] + Rc[:, k - 1])
+        sc = np.zeros(n + 1)
+        sc[1:] += np.abs(b[:-1] * c[:-1])
+        sc[:-1] += np.abs(b[:-1] * c[1:])
+        sc += 0.5 * (np.abs(Rc[:, k + 1]) + np.abs(Rc[:, k - 1]))
+        m = sc[:n] > 0
+        worst = max(worst, float((np.abs(xc - rhs)[:n][m] / sc[:n][m]).max()))
+    assert worst < 1e-13
+    assert np.abs(Rc[Rc != 0]).min() < 1e-10  # tiny entries are resolved too
+
+
+def test_lift_correction_is_confined_to_two_rows_and_columns():
+    # Lap u_bc = sx2 [(1-t)/2 B'' + (1+t)/2 T''] + sy2 [(1-s)/2 L'' + (1+s)/2 R'']:
+    # its C~ coefficients vanish off rows 0, 1 and columns 0, 1
+    n = 512
+    _, bc = workloads.rect_dirichlet_case(n, seed=5)
+    C = rect.ct_projection(rect.laplacian_coeffs(rect.coons_coeffs(bc), BOX), n)
+    assert np.abs(C[2:, 2:]).max() == 0.0
+    assert np.abs(C[:2, :]).max() > 1.0
