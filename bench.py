@@ -213,6 +213,50 @@ def bench_cube_zeig(fps, workloads, torch, tol, n=256, steps=3, check=True, tigh
     return res
 
 
+def bench_rect_dirichlet(fps, workloads, torch, tol, n=4096, box=(0.0, 2.5, -1.0, 0.25), steps=5,
+                         check=True, tight=True):
+    """Rectangle [0, 2.5] x [-1, 0.25] with nonzero Dirichlet data (four random
+    traces, corners matched), FP64: time per solve with the device-side lift,
+    and the same plan's zero-data solve for the lift's overhead."""
+    import numpy as np
+    F_host, bc_host = workloads.rect_dirichlet_case(n, seed=5)
+    F = torch.from_numpy(F_host).cuda()
+    bc = torch.from_numpy(bc_host).cuda()
+    p = fps.plan(n, tol=tol, box=box, tight=tight, dirichlet=True)
+    ws = fps.workspace(p, "cuda")
+    U = torch.empty(p.out_shape(), dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_d = timed(lambda: fps.solve_dirichlet(p, F, bc, out=U, ws=ws))
+    Ud = U.cpu().numpy()
+    ms_0 = timed(lambda: fps.solve(p, F, out=U, ws=ws))
+    res = {"n": n, "box": list(box), "dof": float(n) ** 2, "J": p.J,
+           "ms_per_solve": ms_d, "dof_per_s": n * n / (ms_d * 1e-3),
+           "ms_zero_data_same_plan": ms_0, "lift_overhead_ms": ms_d - ms_0,
+           "enclosure": "computed spectrum" if tight else "Lemma B.1",
+           "shifts": "general (p_j != -q_j): two tables per step"}
+    if check:
+        from oracle import rect
+        Uo = rect.poisson_rect_dirichlet(F_host, bc_host, box)
+        res["rel_frobenius_err_vs_oracle"] = float(np.linalg.norm(Ud - Uo) / np.linalg.norm(Uo))
+        tr = rect.boundary_traces(Ud)
+        res["max_trace_err"] = float(max(np.abs(a - b).max() for a, b in zip(tr, bc_host)))
+    del ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,8 +269,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the FP32-refined, batched and cube timings")
-    ap.add_argument("--only", choices=["fp32_refined", "batched", "cube", "cube_zeig"],
+                    help="skip the FP32-refined, batched, cube and rectangle timings")
+    ap.add_argument("--only", choices=["fp32_refined", "batched", "cube", "cube_zeig",
+                                       "rect_dirichlet"],
                     help="run only this form and print its figures (profiling)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
@@ -244,7 +289,7 @@ def main() -> int:
 
     n = args.n
     dev = torch.device("cuda:0")
-    if args.only in ("batched", "cube", "cube_zeig"):
+    if args.only in ("batched", "cube", "cube_zeig", "rect_dirichlet"):
         if args.copy_calib_mib:
             calibration_copy(torch, dev, args.copy_calib_mib)
         tight = args.enclosure == "tight"
@@ -253,6 +298,10 @@ def main() -> int:
         elif args.only == "cube":
             res = bench_cube(fps, workloads, torch, args.tol, steps=max(1, args.steps),
                              check=not args.no_check, tight=tight)
+        elif args.only == "rect_dirichlet":
+            res = bench_rect_dirichlet(fps, workloads, torch, args.tol, n=n,
+                                       steps=max(1, args.steps), check=not args.no_check,
+                                       tight=tight)
         else:
             res = bench_cube_zeig(fps, workloads, torch, args.tol, steps=max(1, args.steps),
                                   check=not args.no_check, tight=tight)
@@ -390,6 +439,8 @@ def main() -> int:
                                        tight=tight)
             forms["cube_zeig"] = bench_cube_zeig(fps, workloads, torch, args.tol,
                                                  check=not args.no_check, tight=tight)
+            forms["rect_dirichlet"] = bench_rect_dirichlet(fps, workloads, torch, args.tol, n=n,
+                                                           check=not args.no_check, tight=tight)
     if forms:
         out["forms"] = forms
 

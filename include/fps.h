@@ -82,6 +82,11 @@ typedef enum { FPS_OUT_CHEB = 0, FPS_OUT_NATIVE = 1 } fps_out;
  * (-mu^2 (A~ + mu)^-1) Z - Z (-(A~ + mu)) = -G^ by Algorithm 2 with the slice's
  * own Zolotarev shifts; n <= 512. */
 #define FPS_PLAN_CUBE_ZEIG 4u
+/* Square and rectangle plans: also build the lift map that
+ * fps_solve_dirichlet needs (the scaled C~ coefficients of every T_k'', two
+ * parity blocks of about (n/2)^2 float64 each: 67 MB at n = 4096) and the
+ * workspace room for the lift (4 n + 8 float64). */
+#define FPS_PLAN_DIRICHLET 8u
 
 /*
  * Create a plan for a solve of size n (coefficients per dimension).
@@ -93,8 +98,9 @@ typedef enum { FPS_OUT_CHEB = 0, FPS_OUT_NATIVE = 1 } fps_out;
  *              (Theorem 2.1).
  *   prec       fps_prec.
  *   out_basis  fps_out.
- *   flags      0 or a combination of FPS_PLAN_HOST_ONLY and
- *              FPS_PLAN_TIGHT_SPECTRUM.
+ *   flags      0 or a combination of FPS_PLAN_HOST_ONLY,
+ *              FPS_PLAN_TIGHT_SPECTRUM, FPS_PLAN_CUBE_ZEIG (dim 3) and
+ *              FPS_PLAN_DIRICHLET (dim 2).
  * On success *out receives a plan to release with fps_plan_destroy.
  */
 fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double tol,
@@ -177,7 +183,8 @@ fps_status fps_solve(fps_plan *plan, const double *F_dev, double *U_dev, void *w
 
 /*
  * Solve with nonhomogeneous Dirichlet data (Sec. 6.1), square or rectangle
- * plans with FPS_OUT_CHEB.  bc_dev: 4 x (n+2) float64, rows L, R, B, T = the
+ * plans created with FPS_PLAN_DIRICHLET and FPS_OUT_CHEB (FPS_E_STATE
+ * without the flag, FPS_E_UNSUPPORTED for other plans).  bc_dev: 4 x (n+2) float64, rows L, R, B, T = the
  * Chebyshev coefficients of u(a, y) and u(b, y) in t, and of u(x, c) and
  * u(x, d) in s ([-1, 1]^2 for a square plan).  The corners should agree
  * (L(-1) = B(-1), L(1) = T(-1), R(-1) = B(1), R(1) = T(1)); the lift's
@@ -185,7 +192,10 @@ fps_status fps_solve(fps_plan *plan, const double *F_dev, double *U_dev, void *w
  * U_bc the Chebyshev coefficients of the transfinite interpolant
  * u_bc = (1-s)/2 L + (1+s)/2 R + (1-t)/2 B + (1+t)/2 T - bilinear corners,
  * and U_0 the zero-data solution for f - Lap u_bc (the C~ projection of
- * Lap u_bc enters G; it touches only two rows and two columns).  Workspace,
+ * Lap u_bc enters G; it touches only two rows and two columns, and is formed
+ * from the traces by the plan's lift map, which maps Chebyshev coefficients
+ * straight to C~ coefficients of the second derivative: forming g'' first
+ * and projecting it cancels by up to ~4e3 for rough traces).  Workspace,
  * stream and overlap rules as for fps_solve; bc_dev must not overlap ws_dev.
  */
 fps_status fps_solve_dirichlet(fps_plan *plan, const double *F_dev, const double *bc_dev,

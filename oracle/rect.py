@@ -172,7 +172,7 @@ def cheb_to_ct_rect(n: int, N: int) -> np.ndarray:
     return (basis.ct_values(n, x) * w[None, :]) @ basis.cheb_T(N, x).T
 
 
-def cheb_to_ct_closed(n: int, N: int) -> np.ndarray:
+def cheb_to_ct_closed(n: int, N: int, dtype=np.float64) -> np.ndarray:
     """R (n x N) with R[i, k] = C~_i coefficient of T_k, entrywise to
     relative accuracy, from the Gegenbauer connection formula (DLMF 18.18.16)
     in the limit lambda -> 0 that gives T_k (DLMF 18.7.25):
@@ -181,27 +181,29 @@ def cheb_to_ct_closed(n: int, N: int) -> np.ndarray:
     (footnote of Sec. 3.1).  The factors are accumulated as products of
     ratios (relative error ~ k eps), unlike the quadrature of cheb_to_ct_rect
     whose absolute error ~ eps swamps the small far-from-diagonal entries
-    (~ 1/k^2) when they multiply large coefficients."""
-    mu = 1.5
-    R = np.zeros((n, N))
+    when they multiply large coefficients.  dtype=np.longdouble evaluates in
+    extended precision."""
+    mu = dtype(1.5)
+    R = np.zeros((n, N), dtype=dtype)
     if n == 0 or N == 0:
         return R
-    i_all = np.arange(n, dtype=np.float64)
-    nu = np.sqrt((i_all + 1.5) / ((i_all + 1.0) * (i_all + 2.0)))
-    R[0, 0] = 1.0 / nu[0]  # T_0 = C^(mu)_0
-    k = np.arange(1, N, dtype=np.float64)
+    i_all = np.arange(n, dtype=dtype)
+    nu = np.sqrt((i_all + dtype(1.5)) / ((i_all + 1) * (i_all + 2)))
+    R[0, 0] = 1 / nu[0]  # T_0 = C^(mu)_0
+    k = np.arange(1, N, dtype=dtype)
     # t_0(k) = (k-1)! / (mu)_{k+1}, by t_0(1) = 1/(mu (mu+1)) and
     # t_0(k) / t_0(k-1) = (k-1) / (mu + k)
-    t = np.cumprod(np.concatenate([[1.0 / (mu * (mu + 1.0))], (k[1:] - 1.0) / (mu + k[1:])]))
+    t = np.cumprod(np.concatenate([np.array([1 / (mu * (mu + 1))], dtype=dtype),
+                                   (k[1:] - 1) / (mu + k[1:])]))
     for l in range((N - 1) // 2 + 1):
         i = k - 2 * l
         ok = (i >= 0) & (i < n)
         ii = i[ok].astype(int)
-        R[ii, k[ok].astype(int)] = (k[ok] / 2.0) * t[ok] * (i[ok] + mu) / nu[ii]
+        R[ii, k[ok].astype(int)] = (k[ok] / 2) * t[ok] * (i[ok] + mu) / nu[ii]
         # t_{l+1} / t_l = (mu + k - l) (l - mu) / ((k - l - 1) (l + 1)); columns
         # whose last term has passed are never read again
         with np.errstate(divide="ignore", invalid="ignore"):
-            t = t * (mu + k - l) * (l - mu) / ((k - l - 1.0) * (l + 1.0))
+            t = t * (mu + k - l) * (l - mu) / ((k - l - 1) * (l + 1))
     return R
 
 
@@ -213,17 +215,59 @@ def ct_projection(C_T: np.ndarray, n: int) -> np.ndarray:
     return Ra @ C_T @ Rb.T
 
 
+def cheb_second_derivative(c: np.ndarray) -> np.ndarray:
+    """Chebyshev coefficients of g'' for g = sum c_k T_k, by the derivative
+    recurrence d_{k-1} = d_{k+1} + 2 k c_k (d_0 halved) applied twice, in the
+    dtype of c."""
+    def der(c):
+        N = len(c)
+        d = np.zeros(max(N - 1, 0), dtype=c.dtype)
+        for k in range(N - 1, 0, -1):
+            d[k - 1] = (d[k + 1] if k + 1 < N - 1 else 0) + 2 * k * c[k]
+        if N > 1:
+            d[0] = d[0] / 2
+        return d
+    return der(der(np.asarray(c)))
+
+
+def lift_correction(bc, box, n: int) -> np.ndarray:
+    """C~ x C~ coefficients (n x n) of Lap u_bc for the transfinite lift:
+    differentiating each product term of u_bc,
+      Lap u_bc = sx2 [(1-t)/2 B''(s) + (1+t)/2 T''(s)] + sy2 [(1-s)/2 L''(t) + (1+s)/2 R''(t)],
+    so the 2-D projection is a sum of outer products of 1-D C~ coefficient
+    vectors.  The 1-D projections C~(g'') are evaluated in extended precision
+    (np.longdouble): for rough traces the sum R g'' cancels by up to ~4e3
+    (moduli over result at n = 1024-4096, coefficients ~ k^-2), which in
+    float64 leaves ~1e-11 relative error in U."""
+    ld = np.longdouble
+    sx2, sy2 = scalings(box)
+    R = cheb_to_ct_closed(n, n, dtype=ld)
+    w = [R @ cheb_second_derivative(np.asarray(g, dtype=ld)) for g in bc]
+    lin = cheb_to_ct_closed(n, 2, dtype=ld)  # C~ coefficients of T_0, T_1
+    am = lin @ np.array([0.5, -0.5], dtype=ld)  # (1 - t)/2
+    ap = lin @ np.array([0.5, 0.5], dtype=ld)   # (1 + t)/2
+    L, Rt, B, T = w
+    C = (ld(sx2) * (np.outer(am, B) + np.outer(ap, T))
+         + ld(sy2) * (np.outer(L, am) + np.outer(Rt, ap)))
+    return C.astype(np.float64)
+
+
+def lift_correction_2d(bc, box, n: int) -> np.ndarray:
+    """The same correction from its definition in two dimensions, in float64:
+    the C~ projection of the Chebyshev coefficients of Lap u_bc (accurate for
+    smooth traces and small n; the cross-check of lift_correction)."""
+    return ct_projection(laplacian_coeffs(coons_coeffs(bc), box), n)
+
+
 def poisson_rect_dirichlet(F_T: np.ndarray, bc, box) -> np.ndarray:
     """U ((n+2) x (n+2) Chebyshev coefficients) of Lap u = f on the box with
     u = the given traces on the boundary (Sec. 6.1): u = u0 + u_bc with
     u_bc the transfinite interpolant of the traces and u0 the zero-data
-    discrete solution for the right-hand side f - Lap u_bc, whose C~
-    coefficients are those of f less the projection of Lap u_bc (a
-    polynomial of degree n+1, so the projection is exact)."""
+    discrete solution for the right-hand side f - Lap u_bc."""
     n = F_T.shape[0]
     Ubc = coons_coeffs(bc)
     assert Ubc.shape == (n + 2, n + 2)
-    F_C = rhs_ct(F_T) - ct_projection(laplacian_coeffs(Ubc, box), n)
+    F_C = rhs_ct(F_T) - lift_correction(bc, box, n)
     U0 = to_chebyshev(solve_native_rect(F_C, box))
     return U0 + Ubc
 

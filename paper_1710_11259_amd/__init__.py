@@ -28,6 +28,7 @@ FPS_OUT_CHEB, FPS_OUT_NATIVE = 0, 1
 FPS_PLAN_HOST_ONLY = 1
 FPS_PLAN_TIGHT_SPECTRUM = 2
 FPS_PLAN_CUBE_ZEIG = 4
+FPS_PLAN_DIRICHLET = 8
 
 _lib = None
 
@@ -116,16 +117,17 @@ def adi_shifts(a: float, b: float, c: float, d: float, tol: float):
 
 class Plan:
     """Owning wrapper of an fps_plan.  With `box` = (a, b, c, d) the plan is
-    a rectangle plan (fps_plan_create_rect, dim 2)."""
+    a rectangle plan (fps_plan_create_rect, dim 2); `dirichlet` builds the lift
+    map that solve_dirichlet needs (FPS_PLAN_DIRICHLET)."""
 
     def __init__(self, n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
                  out: str = "cheb", host_only: bool = False, tight: bool = False,
-                 zeig: bool = False, box=None):
+                 zeig: bool = False, box=None, dirichlet: bool = False):
         prec = {"fp64": FPS_FP64, "fp32_refined": FPS_FP32_REFINED}[precision]
         ob = {"cheb": FPS_OUT_CHEB, "native": FPS_OUT_NATIVE}[out]
         h = ctypes.c_void_p()
         flags = ((FPS_PLAN_HOST_ONLY if host_only else 0) | (FPS_PLAN_TIGHT_SPECTRUM if tight else 0)
-                 | (FPS_PLAN_CUBE_ZEIG if zeig else 0))
+                 | (FPS_PLAN_CUBE_ZEIG if zeig else 0) | (FPS_PLAN_DIRICHLET if dirichlet else 0))
         self._h = ctypes.c_void_p()
         if box is not None:
             if dim != 2:
@@ -137,7 +139,7 @@ class Plan:
             _check(lib().fps_plan_create(ctypes.byref(h), dim, n, 0, tol, prec, ob, flags))
         self._h = h
         self.n, self.dim, self.tol, self.precision, self.out = n, dim, tol, precision, out
-        self.tight, self.zeig, self.box = tight, zeig, box
+        self.tight, self.zeig, self.box, self.dirichlet = tight, zeig, box, dirichlet
         J, ws, oe = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().fps_plan_info(h, ctypes.byref(J), ctypes.byref(ws), ctypes.byref(oe)))
         self.J, self.workspace_bytes, self.out_entries = J.value, ws.value, oe.value
@@ -204,8 +206,8 @@ class Plan:
 
 def plan(n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
          out: str = "cheb", host_only: bool = False, tight: bool = False,
-         zeig: bool = False, box=None) -> Plan:
-    return Plan(n, tol, dim, precision, out, host_only, tight, zeig, box)
+         zeig: bool = False, box=None, dirichlet: bool = False) -> Plan:
+    return Plan(n, tol, dim, precision, out, host_only, tight, zeig, box, dirichlet)
 
 
 def _stream_ptr(torch, device):
@@ -236,8 +238,8 @@ def solve(p: Plan, F, out=None, ws=None):
 
 def solve_dirichlet(p: Plan, F, bc, out=None, ws=None):
     """U for f with coefficients F (n x n) and Dirichlet traces bc (4 x (n+2):
-    L, R in t, B, T in s), on a square or rectangle plan with Chebyshev
-    output."""
+    L, R in t, B, T in s), on a square or rectangle plan created with
+    dirichlet=True and Chebyshev output."""
     import torch
     for name, t, shape in (("F", F, (p.n, p.n)), ("bc", bc, (4, p.n + 2))):
         if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():

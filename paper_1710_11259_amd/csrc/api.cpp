@@ -230,8 +230,8 @@ fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st
   FPS_HIP(fps::launch_gemm(g1, cnt, st));
   FPS_HIP(fps::launch_gemm(g2, cnt, st));
   if (bc)
-    FPS_HIP(fps::launch_bc_lift_rhs(bc, (const double *)pl->d_RsA[0].p,
-                                    (const double *)pl->d_RsA[1].p, (double *)(ws + pl->off_G),
+    FPS_HIP(fps::launch_bc_lift_rhs(bc, (const double *)pl->d_lift[0].p,
+                                    (const double *)pl->d_lift[1].p, (double *)(ws + pl->off_G),
                                     (double *)(ws + pl->off_bc), L, pl->sx2, pl->sy2,
                                     bc_lift_const(), st));
   FPS_HIP(fps::launch_transpose((const double *)(ws + pl->off_G), (double *)(ws + pl->off_GT),
@@ -287,8 +287,11 @@ fps_status plan_common(fps_plan **out, int dim, int64_t n, int bc, double tol, i
   if (!(tol > 0.0 && tol < 1.0)) return fail(FPS_E_ARG, "tol must lie in (0, 1)");
   if (prec != FPS_FP64 && prec != FPS_FP32_REFINED) return fail(FPS_E_ARG, "bad precision");
   if (out_basis != FPS_OUT_CHEB && out_basis != FPS_OUT_NATIVE) return fail(FPS_E_ARG, "bad out_basis");
-  if (flags & ~(FPS_PLAN_HOST_ONLY | FPS_PLAN_TIGHT_SPECTRUM | FPS_PLAN_CUBE_ZEIG))
+  if (flags & ~(FPS_PLAN_HOST_ONLY | FPS_PLAN_TIGHT_SPECTRUM | FPS_PLAN_CUBE_ZEIG |
+                FPS_PLAN_DIRICHLET))
     return fail(FPS_E_ARG, "unknown flags");
+  if ((flags & FPS_PLAN_DIRICHLET) && dim != 2)
+    return fail(FPS_E_UNSUPPORTED, "FPS_PLAN_DIRICHLET applies to square and rectangle plans");
   if ((flags & FPS_PLAN_CUBE_ZEIG) && dim != 3)
     return fail(FPS_E_ARG, "FPS_PLAN_CUBE_ZEIG applies to cube plans only");
   if ((flags & FPS_PLAN_CUBE_ZEIG) && n > 512)
@@ -432,8 +435,12 @@ fps_status plan2d_build(fps_plan *pl) {
     pl->off_R = pl->ws_bytes;  // r and r^T, npad^2 floats each
     pl->ws_bytes += sq;
   }
-  pl->off_bc = pl->ws_bytes;
-  pl->ws_bytes += align256((4 * (n + 2) + 4 * n + 4 * L.npad + 8) * 8);
+  std::vector<double> lift[2];
+  if (flags & FPS_PLAN_DIRICHLET) {
+    fps::build_lift_map(L, lift);
+    pl->off_bc = pl->ws_bytes;
+    pl->ws_bytes += align256((4 * L.npad + 8) * 8);
+  }
 
   if (!(flags & FPS_PLAN_HOST_ONLY)) {
     fps_status s;
@@ -444,7 +451,9 @@ fps_status plan2d_build(fps_plan *pl) {
         (s = upload(pl->d_PA[0], PA[0])) != FPS_OK || (s = upload(pl->d_PA[1], PA[1])) != FPS_OK ||
         (s = upload(pl->d_PB[0], PB[0])) != FPS_OK || (s = upload(pl->d_PB[1], PB[1])) != FPS_OK ||
         (s = upload(pl->d_sinv, pl->sinv)) != FPS_OK || (s = upload(pl->d_sdiag, pl->sdiag)) != FPS_OK ||
-        (s = upload(pl->d_soff, pl->soff)) != FPS_OK)
+        (s = upload(pl->d_soff, pl->soff)) != FPS_OK ||
+        (s = upload(pl->d_lift[0], lift[0])) != FPS_OK ||
+        (s = upload(pl->d_lift[1], lift[1])) != FPS_OK)
       return s;
     pl->on_device = true;
   }
@@ -602,6 +611,8 @@ fps_status fps_solve_dirichlet(fps_plan *pl, const double *F, const double *bc, 
   if (pl->dim != 2) return fail(FPS_E_UNSUPPORTED, "Dirichlet data: square and rectangle plans only");
   if (pl->out_basis != FPS_OUT_CHEB)
     return fail(FPS_E_UNSUPPORTED, "Dirichlet data need the Chebyshev output basis");
+  if (!(pl->flags & FPS_PLAN_DIRICHLET))
+    return fail(FPS_E_STATE, "the plan was created without FPS_PLAN_DIRICHLET");
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   if ((s = rhs_transform(pl, F, w, st, bc)) != FPS_OK) return s;

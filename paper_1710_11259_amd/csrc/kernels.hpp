@@ -170,11 +170,11 @@ struct BcLiftConst {
   double sinv[2], am[2], ap[2];
 };
 // G (parity-blocked, row stride npad) -= S^-1 C~(Lap u_bc) S^-1, touching
-// rows 0, 1 and columns 0, 1 only.  Rs0 / Rs1: the Chebyshev -> C~ blocks
-// S^-1 R (row stride mp_s, upper triangular).  scratch: [4][n+2] + [4][n] +
-// [4][npad] + [8] doubles; its last 8 entries keep the traces' values at
-// -1 and +1 for launch_bc_lift_out.
-hipError_t launch_bc_lift_rhs(const double *bc, const double *Rs0, const double *Rs1, double *G,
+// rows 0, 1 and columns 0, 1 only.  Ms0 / Ms1: the lift map S^-1 C~(T_k'')
+// by parity (m_s x mo_s, row-major, build_lift_map).  scratch: [4][npad] +
+// [8] doubles; its last 8 entries keep the traces' values at -1 and +1 for
+// launch_bc_lift_out.
+hipError_t launch_bc_lift_rhs(const double *bc, const double *Ms0, const double *Ms1, double *G,
                               double *scratch, const Layout &L, double sx2, double sy2,
                               const BcLiftConst &k, hipStream_t st);
 // U ((n+2) x (n+2) Chebyshev, natural order) += coefficients of u_bc.

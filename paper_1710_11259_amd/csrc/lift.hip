@@ -8,9 +8,10 @@
 //   Lap u_bc = sx2 [(1-t)/2 B''(s) + (1+t)/2 T''(s)]
 //            + sy2 [(1-s)/2 L''(t) + (1+s)/2 R''(t)],
 // whose C~ x C~ coefficients live in rows 0, 1 and columns 0, 1 only (a
-// linear function has C~ coefficients at degrees 0 and 1).  All work here is
-// O(n) except the C~ map of the four second derivatives (4 matrix-vector
-// products with the upper-triangular Chebyshev -> C~ blocks).
+// linear function has C~ coefficients at degrees 0 and 1).  The 1-D factors
+// S^-1 C~(g'') come from the plan's lift map applied to the traces' Chebyshev
+// coefficients (4 matrix-vector products with its parity blocks); all other
+// work is O(n).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -19,113 +20,63 @@ namespace fps {
 
 namespace {
 
-constexpr int kD2Threads = 256;
+constexpr int kCornerThreads = 256;
 
-// Chebyshev derivative by same-parity suffix sums: for c of length N,
-//   d_j = (2 / kappa_j) sum_{m > j, m - j odd} m c_m,  j < N - 1,
-// kappa_0 = 2, kappa_j = 1 otherwise (the coefficient form of the
-// derivative of sum c_m T_m; the classical backward recurrence
-// d_{m-1} = d_{m+1} + 2 m c_m summed out).  Each thread owns a contiguous
-// segment; segment totals per parity are suffix-scanned across the
-// workgroup in LDS.  Ends with a barrier (d visible to the workgroup).
-__device__ void cheb_derivative(const double *c, double *d, int64_t N, double *lds) {
-  const int t = threadIdx.x;
-  const int64_t seg = (N + kD2Threads - 1) / kD2Threads;
-  const int64_t lo = t * seg < N ? t * seg : N;
-  const int64_t hi = lo + seg < N ? lo + seg : N;
-  double s0 = 0.0, s1 = 0.0;
-  for (int64_t m = lo; m < hi; ++m) {
-    const double a = (double)m * c[m];
-    if (m & 1)
-      s1 += a;
-    else
-      s0 += a;
-  }
-  lds[t] = s0;
-  lds[kD2Threads + t] = s1;
-  __syncthreads();
-  if (t < 2) {  // exclusive suffix over the segments, one parity per thread
-    double run = 0.0;
-    for (int u = kD2Threads - 1; u >= 0; --u) {
-      const double v = lds[t * kD2Threads + u];
-      lds[t * kD2Threads + u] = run;
-      run += v;
-    }
-  }
-  __syncthreads();
-  double run0 = lds[t], run1 = lds[kD2Threads + t];
-  for (int64_t m = hi - 1; m >= lo; --m) {
-    const double a = (double)m * c[m];
-    double Q;
-    if (m & 1) {
-      run1 += a;
-      Q = run1;
-    } else {
-      run0 += a;
-      Q = run0;
-    }
-    if (m >= 1) d[m - 1] = (m == 1 ? 1.0 : 2.0) * Q;
-  }
-  __syncthreads();
-}
-
-// One workgroup per trace (L, R, B, T): first derivative into d1 [4][N],
-// second derivative into d2 [4][n], and the trace's values at -1 and +1
-// into corner[2 tr], corner[2 tr + 1].
-__global__ __launch_bounds__(kD2Threads) void k_bc_d2(const double *__restrict__ bc,
-                                                      double *__restrict__ d1,
-                                                      double *__restrict__ d2,
-                                                      double *__restrict__ corner, int64_t n) {
-  __shared__ double lds[2 * kD2Threads];
+// One workgroup per trace (L, R, B, T): its values at -1 and +1 into
+// corner[2 tr], corner[2 tr + 1].
+__global__ __launch_bounds__(kCornerThreads) void k_bc_corner(const double *__restrict__ bc,
+                                                              double *__restrict__ corner,
+                                                              int64_t n) {
+  __shared__ double lds[2 * kCornerThreads];
   const int tr = blockIdx.x, t = threadIdx.x;
   const int64_t N = n + 2;
   const double *c = bc + tr * N;
-  cheb_derivative(c, d1 + tr * N, N, lds);
-  cheb_derivative(d1 + tr * N, d2 + tr * n, N - 1, lds);
   double vm = 0.0, vp = 0.0;
-  for (int64_t k = t; k < N; k += kD2Threads) {
+  for (int64_t k = t; k < N; k += kCornerThreads) {
     vp += c[k];
     vm += (k & 1) ? -c[k] : c[k];
   }
   lds[t] = vm;
-  lds[kD2Threads + t] = vp;
+  lds[kCornerThreads + t] = vp;
   __syncthreads();
-  for (int h = kD2Threads / 2; h > 0; h >>= 1) {
+  for (int h = kCornerThreads / 2; h > 0; h >>= 1) {
     if (t < h) {
       lds[t] += lds[t + h];
-      lds[kD2Threads + t] += lds[kD2Threads + t + h];
+      lds[kCornerThreads + t] += lds[kCornerThreads + t + h];
     }
     __syncthreads();
   }
   if (t == 0) {
     corner[2 * tr] = lds[0];
-    corner[2 * tr + 1] = lds[kD2Threads];
+    corner[2 * tr + 1] = lds[kCornerThreads];
   }
 }
 
-// w[X][pos] = (S^-1 R e_X) at the parity-blocked position of natural index
-// i = 2k + s: sum over l >= k of Rs_s[k][l] e_X[2l + s] (Rs_s upper
-// triangular, row stride mp_s).  One wavefront per output row.
-__global__ __launch_bounds__(256) void k_bc_cmap(const double *__restrict__ Rs0,
-                                                 const double *__restrict__ Rs1,
-                                                 const double *__restrict__ e,
+// w[X][pos] = S^-1 C~(g_X'') at the parity-blocked position of natural index
+// i = 2a + s: sum over b > a of Ms_s[a][b] g_X[2b + s] (Ms_s has row length
+// mo_s; T''_k has C~ components only below degree k - 1).  One wavefront per
+// output row.
+__global__ __launch_bounds__(256) void k_bc_cmap(const double *__restrict__ Ms0,
+                                                 const double *__restrict__ Ms1,
+                                                 const double *__restrict__ bc,
                                                  double *__restrict__ w, int64_t n, int64_t npad,
-                                                 int64_t m0, int64_t mp0, int64_t mp1) {
+                                                 int64_t m0, int64_t mp0, int64_t mo0,
+                                                 int64_t mo1) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;  // uniform per wavefront
   const int s = row < m0 ? 0 : 1;
-  const int64_t k = s ? row - m0 : row;
-  const int64_t m = s ? n - m0 : m0;
-  const double *Rrow = (s ? Rs1 : Rs0) + k * (s ? mp1 : mp0);
+  const int64_t a = s ? row - m0 : row;
+  const int64_t mo = s ? mo1 : mo0, N = n + 2;
+  const double *Mrow = (s ? Ms1 : Ms0) + a * mo;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  for (int64_t l = k + lane; l < m; l += 64) {
-    const double r = Rrow[l];
-    const int64_t i = 2 * l + s;
-    a0 += r * e[i];
-    a1 += r * e[n + i];
-    a2 += r * e[2 * n + i];
-    a3 += r * e[3 * n + i];
+  for (int64_t b = a + 1 + lane; b < mo; b += 64) {
+    const double m = Mrow[b];
+    const int64_t k = 2 * b + s;
+    a0 += m * bc[k];
+    a1 += m * bc[N + k];
+    a2 += m * bc[2 * N + k];
+    a3 += m * bc[3 * N + k];
   }
   for (int off = 32; off > 0; off >>= 1) {
     a0 += __shfl_xor(a0, off, 64);
@@ -134,7 +85,7 @@ __global__ __launch_bounds__(256) void k_bc_cmap(const double *__restrict__ Rs0,
     a3 += __shfl_xor(a3, off, 64);
   }
   if (lane == 0) {
-    const int64_t pos = s * mp0 + k;
+    const int64_t pos = s * mp0 + a;
     w[pos] = a0;
     w[npad + pos] = a1;
     w[2 * npad + pos] = a2;
@@ -200,16 +151,16 @@ __global__ void k_bc_out(double *__restrict__ U, const double *__restrict__ bc,
 
 }  // namespace
 
-hipError_t launch_bc_lift_rhs(const double *bc, const double *Rs0, const double *Rs1, double *G,
+hipError_t launch_bc_lift_rhs(const double *bc, const double *Ms0, const double *Ms1, double *G,
                               double *scratch, const Layout &L, double sx2, double sy2,
                               const BcLiftConst &k, hipStream_t st) {
-  const int64_t n = L.n, N = n + 2;
-  double *d1 = scratch, *d2 = d1 + 4 * N, *w = d2 + 4 * n, *corner = w + 4 * L.npad;
-  hipLaunchKernelGGL(k_bc_d2, dim3(4), dim3(kD2Threads), 0, st, bc, d1, d2, corner, n);
+  const int64_t n = L.n;
+  double *w = scratch, *corner = w + 4 * L.npad;
+  hipLaunchKernelGGL(k_bc_corner, dim3(4), dim3(kCornerThreads), 0, st, bc, corner, n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bc_cmap, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Rs0, Rs1, d2, w, n,
-                     L.npad, L.m[0], L.mp[0], L.mp[1]);
+  hipLaunchKernelGGL(k_bc_cmap, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Ms0, Ms1, bc, w,
+                     n, L.npad, L.m[0], L.mp[0], L.mo[0], L.mo[1]);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t n2 = n < 2 ? n : 2, total = n2 * n + (n - n2) * n2;
   hipLaunchKernelGGL(k_bc_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, G, w, n,
@@ -220,7 +171,7 @@ hipError_t launch_bc_lift_rhs(const double *bc, const double *Rs0, const double 
 hipError_t launch_bc_lift_out(double *U, const double *bc, const double *scratch, int64_t n,
                               int64_t npad, hipStream_t st) {
   const int64_t N = n + 2, total = 2 * N + (N - 2) * 2;
-  const double *corner = scratch + 4 * N + 4 * n + 4 * npad;
+  const double *corner = scratch + 4 * npad;
   hipLaunchKernelGGL(k_bc_out, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, U, bc,
                      corner, n);
   return hipGetLastError();

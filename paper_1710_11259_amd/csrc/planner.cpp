@@ -498,4 +498,33 @@ void build_conversions(const Layout &L, std::vector<double> Rs[2], std::vector<d
   }
 }
 
+void build_lift_map(const Layout &L, std::vector<double> Ms[2]) {
+  const int64_t n = L.n, N = n + 2;
+  for (int s = 0; s < 2; ++s) Ms[s].assign((size_t)L.m[s] * L.mo[s], 0.0);
+  // T''_k = 2k C^(2)_{k-2} (d/dx T_k = k C^(1)_{k-1}, d/dx C^(l)_j = 2l C^(l+1)_{j-1});
+  // C^(lam)_j = sum_l c_{j,l} C^(mu)_{j-2l} with (DLMF 18.18.16)
+  //   c_{j,l} = (lam-mu)_l (lam)_{j-l} (mu + j - 2l) / ((mu)_{j-l+1} l!),
+  // lam = 2, mu = 3/2; C^(3/2)_i = C~_i / nu_i, nu_i = sqrt((i+3/2)/((i+1)(i+2))).
+  const long double lam = 2.0L, mu = 1.5L;
+  long double u0 = 1.0L / mu;  // (lam)_j / (mu)_{j+1} at j = 0
+  for (int64_t k = 2; k < N; ++k) {
+    const int64_t j = k - 2;
+    if (j > 0) u0 *= (lam + (long double)(j - 1)) / (mu + (long double)j);
+    const int s = (int)(k & 1);
+    long double u = u0;
+    for (int64_t l = 0; 2 * l <= j; ++l) {
+      const int64_t i = j - 2 * l;
+      if (i < n) {
+        const long double x = (long double)i;
+        const long double nu = std::sqrt((x + 1.5L) / ((x + 1.0L) * (x + 2.0L)));
+        const long double sc = std::sqrt((x + 1.0L) * (x + 2.0L));
+        Ms[s][(size_t)(i >> 1) * L.mo[s] + (k >> 1)] =
+            (double)(2.0L * (long double)k * u * (mu + x) / (nu * sc));
+      }
+      u *= (lam - mu + (long double)l) / (long double)(l + 1) * (mu + (long double)(j - l)) /
+           (lam + (long double)(j - l - 1));
+    }
+  }
+}
+
 }  // namespace fps

@@ -120,4 +120,14 @@ void build_sweep_tables_ab(const Layout &L, const std::vector<double> &alpha,
 //          (1-x^2) C~_{2b+s}(x) / sqrt((2b+s+1)(2b+s+2)).
 void build_conversions(const Layout &L, std::vector<double> Rs[2], std::vector<double> P[2]);
 
+// Dirichlet lift map (Sec. 6.1): the scaled C~ coefficients of the second
+// derivative of each Chebyshev polynomial, split by parity (row-major,
+// float64, m[s] x mo[s]):
+//   Ms[s][a][b] = C~_{2a+s} coefficient of T''_{2b+s} / sqrt((2a+s+1)(2a+s+2)),
+// nonzero only for b > a.  From T''_k = 2k C^(2)_{k-2} and the Gegenbauer
+// connection C^(2) -> C^(3/2) (all coefficients positive), accumulated in
+// extended precision.  Applying it to a trace g gives S^-1 C~(g'') without
+// forming g'' (whose C~ projection cancels heavily for rough g).
+void build_lift_map(const Layout &L, std::vector<double> Ms[2]);
+
 }  // namespace fps

@@ -82,6 +82,9 @@ struct fps_plan {
   // GEMM operands, zero-padded to multiples of 64: RsA = Rs (mp x mp),
   // RsB = Rs^T (mp x mp), PA = P (mop x mp), PB = P^T (mp x mop).
   fps::detail::DeviceBuf d_RsA[2], d_RsB[2], d_PA[2], d_PB[2];
+  // Lift map S^-1 C~(T_k'') by parity (m[s] x mo[s], row-major), only with
+  // FPS_PLAN_DIRICHLET.
+  fps::detail::DeviceBuf d_lift[2];
 
   // sweep timing diagnostics
   std::vector<hipEvent_t> ev;  // pairs
@@ -91,9 +94,9 @@ struct fps_plan {
   int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab = 0;
   int64_t off_X = 0;  // adjoint: the output cotangent in the parity-blocked layout
   int64_t off_R = 0;  // FP32_REFINED: the float residual and its transpose
-  // Dirichlet lift (2-D plans): second derivatives of the four traces
-  // [4][n], their mapped C~ coefficients [4][npad] (parity-blocked), and the
-  // corner values [8].
+  // Dirichlet lift (2-D plans with FPS_PLAN_DIRICHLET): the traces' scaled
+  // C~ second-derivative coefficients [4][npad] (parity-blocked) and their
+  // values at -1 and +1 [8].
   int64_t off_bc = 0;
 
   // Cube (dim 3), two-level nested ADI: `shifts` holds the outer shifts

@@ -33,6 +33,13 @@ void shim_conversions(long long n, double *R0, double *R1, double *P0, double *P
   std::memcpy(P0, P[0].data(), P[0].size() * sizeof(double));
   std::memcpy(P1, P[1].data(), P[1].size() * sizeof(double));
 }
+void shim_lift_map(long long n, double *M0, double *M1) {
+  fps::Layout L = fps::make_layout(n);
+  std::vector<double> Ms[2];
+  fps::build_lift_map(L, Ms);
+  std::memcpy(M0, Ms[0].data(), Ms[0].size() * sizeof(double));
+  std::memcpy(M1, Ms[1].data(), Ms[1].size() * sizeof(double));
+}
 // Eigen-decomposition of the parity-s block of A~: m eigenvalues, m x m vectors.
 int shim_atilde_eigen(long long n, int s, double *lam, double *Q) {
   const long long m = (n - s + 1) / 2;

@@ -63,3 +63,18 @@ def test_adjoint_ignores_stale_workspace():
     torch.cuda.synchronize()
     Fo = adjoint.vjp_square(Ub)
     assert np.linalg.norm(Fb.cpu().numpy() - Fo) <= 1e-12 * np.linalg.norm(Fo)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64])
+@pytest.mark.parametrize("box", [None, (0.0, 2.5, -1.0, 0.25)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_dirichlet_ignores_stale_workspace(n, box, precision):
+    from oracle import rect
+    F, bc = workloads.rect_dirichlet_case(n, seed=5)
+    p = fps.plan(n, tol=1e-13, box=box, precision=precision, dirichlet=True)
+    U = fps.solve_dirichlet(p, torch.from_numpy(F).cuda(), torch.from_numpy(bc).cuda(),
+                            ws=_nan_ws(p))
+    torch.cuda.synchronize()
+    Uo = rect.poisson_rect_dirichlet(F, bc, box or (-1.0, 1.0, -1.0, 1.0))
+    err = np.linalg.norm(U.cpu().numpy() - Uo) / np.linalg.norm(Uo)
+    assert err <= 1e-12

@@ -61,7 +61,7 @@ def test_argument_errors():
     for args, code in [((2, 0, 0, 1e-13, 0, 0, 1), 1), ((2, 16, 0, 0.0, 0, 0, 1), 1),
                        ((2, 16, 0, 1.0, 0, 0, 1), 1), ((4, 16, 0, 1e-13, 0, 0, 1), 1),
                        ((2, 16, 7, 1e-13, 0, 0, 1), 2), ((2, 16, 0, 1e-13, 9, 0, 1), 1),
-                       ((2, 16, 0, 1e-13, 0, 5, 1), 1), ((2, 16, 0, 1e-13, 0, 0, 8), 1)]:
+                       ((2, 16, 0, 1e-13, 0, 5, 1), 1), ((2, 16, 0, 1e-13, 0, 0, 16), 1)]:
         assert L.fps_plan_create(ctypes.byref(h), *args) == code, args
         assert len(L.fps_last_error()) > 0
     J = ctypes.c_int()
@@ -160,6 +160,7 @@ def shim(tmp_path_factory):
     L.shim_conversions.argtypes = [ctypes.c_longlong, P, P, P, P]
     L.shim_dn.argtypes = [ctypes.c_double, ctypes.c_int, P]
     L.shim_extremes.argtypes = [ctypes.c_longlong, P]
+    L.shim_lift_map.argtypes = [ctypes.c_longlong, P, P]
     return L
 
 
@@ -443,6 +444,38 @@ def test_rect_and_dirichlet_argument_errors():
     assert L.fps_plan_create_rect(ctypes.byref(h), 16, None, 1e-13, 0, 0, 1) == 1
     assert L.fps_plan_create_rect(ctypes.byref(h), 16, b, 1e-13, 0, 0, 4 | 1) == 1  # cube flag
     assert L.fps_plan_create_rect(ctypes.byref(h), 0, b, 1e-13, 0, 0, 1) == 1
-    p = fps.plan(16, box=(0.0, 1.0, 0.0, 2.0), host_only=True)
+    assert L.fps_plan_create(ctypes.byref(h), 3, 16, 0, 1e-13, 0, 0, 8 | 1) == 2  # cube + lift
+    p = fps.plan(16, box=(0.0, 1.0, 0.0, 2.0), host_only=True, dirichlet=True)
     assert L.fps_solve_dirichlet(p.handle, None, None, None, None, None) == 5  # host-only
     assert L.fps_solve_dirichlet(None, None, None, None, None, None) == 5
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 201])
+def test_lift_map_matches_oracle(shim, n):
+    # Ms[s][a][b] = C~_{2a+s} coefficient of T''_{2b+s} / sqrt((i+1)(i+2)):
+    # against the oracle's extended-precision projection of each T_k''
+    from oracle import rect
+    m = [(n + 1) // 2, n // 2]
+    mo = [(n + 3) // 2, (n + 2) // 2]
+    M0 = np.zeros(m[0] * mo[0])
+    M1 = np.zeros(max(m[1] * mo[1], 1))
+    P = ctypes.POINTER(ctypes.c_double)
+    shim.shim_lift_map(n, M0.ctypes.data_as(P), M1.ctypes.data_as(P))
+    N = n + 2
+    R = rect.cheb_to_ct_closed(n, n, dtype=np.longdouble)
+    full = np.zeros((n, N))
+    for k in range(N):
+        e = np.zeros(N, dtype=np.longdouble)
+        e[k] = 1
+        d2 = rect.cheb_second_derivative(e)
+        full[:, k] = (R @ d2[:n] if len(d2) >= n else R[:, :len(d2)] @ d2).astype(np.float64)
+    i = np.arange(n)
+    full /= np.sqrt((i + 1.0) * (i + 2.0))[:, None]
+    for s, Ms in ((0, M0), (1, M1)):
+        if m[s] == 0:
+            continue
+        got = Ms[: m[s] * mo[s]].reshape(m[s], mo[s])
+        want = full[s::2, s::2]
+        # the oracle side projects each T_k'' (coefficients up to ~k^3) in
+        # extended precision, cancelling by up to ~1e6: 1e-12 relative
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=0)

@@ -232,3 +232,22 @@ def test_lift_correction_is_confined_to_two_rows_and_columns():
     C = rect.ct_projection(rect.laplacian_coeffs(rect.coons_coeffs(bc), BOX), n)
     assert np.abs(C[2:, 2:]).max() == 0.0
     assert np.abs(C[:2, :]).max() > 1.0
+
+
+def test_second_derivative_recurrence_matches_numpy():
+    g = workloads.decayed_normal(np.random.default_rng(1), (41,), 2.0)
+    from numpy.polynomial import chebyshev as npc
+    assert np.abs(rect.cheb_second_derivative(g) - npc.chebder(g, 2)).max() < 1e-13
+    gl = rect.cheb_second_derivative(g.astype(np.longdouble))
+    assert gl.dtype == np.longdouble
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 30, 120])
+def test_separable_lift_correction_matches_2d_definition(n):
+    # the extended-precision separable form against the float64 projection of
+    # the 2-D Chebyshev coefficients of Lap u_bc (smooth-enough traces at
+    # these sizes for the latter to be accurate)
+    _, bc = workloads.rect_dirichlet_case(n, seed=3)
+    a = rect.lift_correction(bc, BOX, n)
+    b = rect.lift_correction_2d(bc, BOX, n)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
