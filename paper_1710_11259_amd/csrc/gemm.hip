@@ -25,8 +25,13 @@ namespace {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
+// order: tile dispatch order of a triangular batch, longest k-range first
+// (0: natural; 1 / 2: column tile slowest, ascending / descending; 3 / 4:
+// row tile slowest, ascending / descending).  Workgroups start in id order,
+// so the short tiles fill the tail instead of the long ones.
 struct GemmBatch {
   GemmProb p[4];
+  int order;
 };
 
 constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
@@ -142,7 +147,23 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmBatch batch) {
   __shared__ double As[GBM][GBK + 1];
   __shared__ double Bs[GBK][GBN + GPAD];
-  gemm_tile(batch.p[blockIdx.z], blockIdx.x, blockIdx.y, As, Bs);
+  int bx = blockIdx.x, by = blockIdx.y, z = blockIdx.z;
+  if (batch.order != 0) {
+    const int nt = gridDim.x, mt = gridDim.y, nz = gridDim.z;
+    const int L = blockIdx.x + nt * (blockIdx.y + mt * blockIdx.z);
+    if (batch.order <= 2) {
+      const int c = L / (mt * nz), rem = L % (mt * nz);
+      bx = batch.order == 1 ? c : nt - 1 - c;
+      z = rem / mt;
+      by = rem % mt;
+    } else {
+      const int r = L / (nt * nz), rem = L % (nt * nz);
+      by = batch.order == 3 ? r : mt - 1 - r;
+      z = rem / nt;
+      bx = rem % nt;
+    }
+  }
+  gemm_tile(batch.p[z], bx, by, As, Bs);
 }
 
 // Table-driven GEMM: workgroup g computes tile (local % ntx, local / ntx),
@@ -201,6 +222,22 @@ hipError_t launch_gemm(const GemmProb *probs, int count, hipStream_t st) {
     mt = probs[i].M > mt * GBM ? (probs[i].M + GBM - 1) / GBM : mt;
     nt = probs[i].N > nt * GBN ? (probs[i].N + GBN - 1) / GBN : nt;
   }
+  // Longest-first order when every problem has the same one-sided
+  // triangular structure: the k-range of a tile then shrinks along one tile
+  // index (triB: klo grows with the column tile, triBu: khi grows with it;
+  // triA / triAu likewise with the row tile).
+  const GemmProb &f = probs[0];
+  bool same = true;
+  for (int i = 1; i < count; ++i) {
+    const GemmProb &q = probs[i];
+    same = same && q.triA == f.triA && q.triB == f.triB && q.triAu == f.triAu &&
+           q.triBu == f.triBu;
+  }
+  const bool rowwise = f.triA || f.triAu, colwise = f.triB || f.triBu;
+  if (same && colwise && !rowwise && !(f.triB && f.triBu))
+    b.order = f.triB ? 1 : 2;
+  else if (same && rowwise && !colwise && !(f.triA && f.triAu))
+    b.order = f.triA ? 3 : 4;
   dim3 grid((unsigned)nt, (unsigned)mt, (unsigned)count);
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, b);
   return hipGetLastError();
