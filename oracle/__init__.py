@@ -30,6 +30,9 @@ paper's definitions as plainly as possible:
                  sides, general-interval shifts of Theorem 2.1, the closed
                  form of Algorithm 2's iterate) and nonhomogeneous Dirichlet
                  data by a transfinite lift (Sec. 6.1).
+* ``cylinder`` -- the cylinder (Sec. 4.1): DFS-doubled Chebyshev-Fourier-
+                 Chebyshev data, one Galerkin system per Fourier mode (three
+                 cases of partial regularity), Bartels-Stewart or Kronecker.
 * ``adjoint`` -- the transpose of the whole linear map F_T -> U.
 * ``fd``      -- the five-point finite-difference Sylvester equation (1.2)
                  and its sine-transform solution (1.3), used to check the
@@ -40,4 +43,4 @@ listed in the design notes (iteration count (2.9) rather than the square-case
 display of Sec. 3.3; congruence in (3.9); rectangular M on output; cube
 right-hand side scaled by D^-1 in each mode).
 """
-from . import basis, shifts, square, cube, adjoint, fd, rect  # noqa: F401
+from . import basis, shifts, square, cube, adjoint, fd, rect, cylinder  # noqa: F401

@@ -19,7 +19,8 @@ __all__ = [
     "decayed_normal", "square_rhs", "cube_rhs", "batched_problems",
     "adjoint_case", "cheb_coeffs_2d", "cheb_coeffs_3d",
     "manufactured_square", "manufactured_cube", "oscillatory_square_rhs",
-    "rect_dirichlet_case", "manufactured_rect",
+    "rect_dirichlet_case", "manufactured_rect", "cylinder_rhs", "cylinder_coeffs",
+    "manufactured_cylinder",
 ]
 
 
@@ -227,3 +228,63 @@ def manufactured_rect(n: int, box, N: int = 96):
     traces = [u_fun(-one, p), u_fun(one, p), u_fun(p, -one), u_fun(p, one)]
     bc = np.stack([_pad(_cheb_coeffs_1d(v), n + 2) for v in traces])
     return F, np.ascontiguousarray(bc), u_fun
+
+
+# --- Cylinder (DFS doubling, Chebyshev(r) x Fourier(theta) x Chebyshev(z)) ---
+#
+# Arrays F[idx, i, j], idx = k + n_theta/2 for Fourier modes
+# k = -n_theta/2 .. n_theta/2 - 1, i <-> T_i(r) on the doubled r in [-1, 1],
+# j <-> T_j(z); complex128.
+
+def cylinder_rhs(n: int, n_theta: int, seed: int = 7, decay: float = 2.0) -> np.ndarray:
+    """Random doubled-up right-hand side: real and imaginary parts N(0,1)
+    (1+i)^-decay (1+j)^-decay (1+|k|)^-decay, with the r-parity of a doubled
+    function (mode k has only coefficients i = k mod 2)."""
+    rng = np.random.default_rng(seed)
+    F = decayed_normal(rng, (n_theta, n, n), decay) + 1j * decayed_normal(rng, (n_theta, n, n), decay)
+    ks = np.arange(n_theta) - n_theta // 2
+    w = (1.0 + np.abs(ks)) ** (-decay)
+    i = np.arange(n)
+    mask = (i[None, :] % 2) == (np.abs(ks)[:, None] % 2)
+    F *= (w[:, None] * mask)[:, :, None]
+    return np.ascontiguousarray(F)
+
+
+def cylinder_coeffs(fun, n: int, n_theta: int, N: int) -> np.ndarray:
+    """Chebyshev-Fourier-Chebyshev coefficients (n_theta, n, n) of the
+    doubled-up f~(r, theta, z) = fun(r cos theta, r sin theta, z): sampled on
+    N first-kind points in r and z and n_theta points theta_l = -pi + 2 pi
+    l / n_theta, transformed by the discrete cosine map and the FFT
+    (f~_k = (1/n_theta) sum_l f~(theta_l) e^{-i k theta_l})."""
+    r = _cheb_points(N)
+    th = -np.pi + 2 * np.pi * np.arange(n_theta) / n_theta
+    R, TH, Z = np.meshgrid(r, th, r, indexing="ij")  # [r, theta, z]
+    v = fun(R * np.cos(TH), R * np.sin(TH), Z)
+    v = _dct_coeffs_axis(_dct_coeffs_axis(v, 0), 2)
+    ks = np.arange(n_theta) - n_theta // 2
+    E = np.exp(-1j * np.outer(ks, th)) / n_theta  # [k, l]
+    C = np.einsum("kl,ilj->kij", E, v)
+    out = np.zeros((n_theta, n, n), dtype=np.complex128)
+    m = min(n, N)
+    out[:, :m, :m] = C[:, :m, :m]
+    return out
+
+
+def manufactured_cylinder(n: int, n_theta: int, N: int = 64):
+    """u = (1 - x^2 - y^2)(1 - z^2)(z cos x^2 + cos yz) on the unit cylinder
+    (the paper's cylinder example with the frequencies lowered), f = Lap u
+    written out.  Returns (F, u_fun)."""
+    def u_fun(x, y, z):
+        return (1 - x * x - y * y) * (1 - z * z) * (z * np.cos(x * x) + np.cos(y * z))
+
+    def f_fun(x, y, z):
+        x2, y2, z2 = x * x, y * y, z * z
+        return ((-4 * x2 * y * z - 4 * y ** 3 * z - 4 * y * z ** 3 + 8 * y * z) * np.sin(y * z)
+                + (-10 * x2 * z ** 3 + 10 * x2 * z - 2 * y2 * z ** 3 + 2 * y2 * z + 2 * z ** 3 - 2 * z)
+                * np.sin(x2)
+                + (-4 * x2 * x2 * z ** 3 + 4 * x2 * x2 * z - 4 * x2 * y2 * z ** 3 + 4 * x2 * y2 * z
+                   + 4 * x2 * z ** 3 + 2 * x2 * z + 6 * y2 * z + 4 * z ** 3 - 10 * z) * np.cos(x2)
+                + (-x2 * y2 * z2 + x2 * y2 - x2 * z2 * z2 + x2 * z2 + 2 * x2 - y2 * y2 * z2 + y2 * y2
+                   - y2 * z2 * z2 + 2 * y2 * z2 + y2 + z2 * z2 + 3 * z2 - 6) * np.cos(y * z))
+
+    return cylinder_coeffs(f_fun, n, n_theta, N), u_fun, f_fun
