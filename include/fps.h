@@ -125,6 +125,35 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
 fps_status fps_plan_create_rect(fps_plan **out, int64_t n, const double *box_host, double tol,
                                 int prec, int out_basis, unsigned flags);
 
+/*
+ * Cylinder plan (Sec. 4.1): Poisson on x^2 + y^2 <= 1, |z| <= 1 with zero
+ * Dirichlet data, through the DFS doubling (r over [-1, 1]) and a
+ * Chebyshev (r) x Fourier (theta) x Chebyshev (z) expansion (4.4).
+ *   n        even, 2 <= n <= 512: Chebyshev coefficients in r and in z.
+ *   n_theta  even, 2 <= n_theta <= 1024: Fourier modes k = -n_theta/2 ..
+ *            n_theta/2 - 1 (index k + n_theta/2).
+ *   flags    0 or FPS_PLAN_HOST_ONLY.
+ * fps_solve then takes F_dev = the doubled-up right-hand side as split
+ * complex float64 [n_theta][2][n][n] (index 1: real, imaginary part; rows
+ * <-> T_i(r), columns <-> T_j(z)) and writes U_dev [n_theta][2][n+4][n+2],
+ * the Chebyshev coefficients of each mode u~_k(r, z) (r-degree up to n+3
+ * from the partial-regularity factor r^min(|k|,2) (1-r^2)(1-z^2) of (4.7)).
+ * Each mode solves the Galerkin system of its case of Sec. 4.1 ((4.8) for
+ * |k| >= 2, the displayed operators for |k| = 1 and k = 0) exactly up to
+ * rounding: in the eigenbasis of A~ along z every mode splits into banded
+ * systems in r, factored by the plan (no ADI, so J = 0 and no tolerance).
+ * The mode's right-hand side rows of the wrong r-parity (zero for
+ * doubled-up data) are ignored.  fps_solve_adjoint, fps_adi_native and
+ * fps_solve_dirichlet reject cylinder plans.
+ */
+fps_status fps_plan_create_cylinder(fps_plan **out, int64_t n, int64_t n_theta, unsigned flags);
+
+/* Inspection: the band of mode k's r-operators in the parity-restricted index
+ * (rows of the right-hand side parity, columns of w's parity), offsets
+ * -2..2: P_host[a*5 + c], Q_host[a*5 + c] for a < n/2, the entry at column
+ * a + c - 2 (host arrays of 5 n/2 doubles).  Host-only. */
+fps_status fps_cylinder_mode_bands(int64_t n, int64_t k, double *P_host, double *Q_host);
+
 /* J (ADI iterations of the outer level), workspace bytes required by
  * fps_solve / fps_solve_adjoint, and the number of float64 entries of U. */
 fps_status fps_plan_info(const fps_plan *plan, int *J, int64_t *workspace_bytes,

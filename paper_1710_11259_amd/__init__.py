@@ -15,7 +15,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["lib", "Plan", "plan", "solve", "solve_dirichlet", "solve_adjoint", "solve_fn",
+__all__ = ["lib", "Plan", "plan", "plan_cylinder", "cylinder_mode_bands", "solve",
+           "solve_dirichlet", "solve_adjoint", "solve_fn",
            "adi_native",
            "adi_shifts", "Batch", "batch", "batch_solve", "BatchGraph", "FpsError", "LIB_PATH"]
 
@@ -58,6 +59,8 @@ def lib() -> ctypes.CDLL:
     L.fps_plan_shifts.argtypes = [vp, ctypes.POINTER(dbl)]
     L.fps_plan_shift_pairs.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.fps_solve_dirichlet.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.fps_plan_create_cylinder.argtypes = [ctypes.POINTER(vp), i64, i64, ctypes.c_uint]
+    L.fps_cylinder_mode_bands.argtypes = [i64, i64, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.fps_plan_refinement.argtypes = [vp, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int)]
     L.fps_plan_inner_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
@@ -86,7 +89,8 @@ def lib() -> ctypes.CDLL:
     L.fps_status_string.restype = ctypes.c_char_p
     L.fps_last_error.restype = ctypes.c_char_p
     L.fps_version.restype = ctypes.c_char_p
-    for name in ("fps_plan_create", "fps_plan_create_rect", "fps_plan_shift_pairs",
+    for name in ("fps_plan_create_cylinder", "fps_cylinder_mode_bands",
+                 "fps_plan_create", "fps_plan_create_rect", "fps_plan_shift_pairs",
                  "fps_solve_dirichlet",
                  "fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_plan_refinement",
                  "fps_plan_inner_counts", "fps_plan_slice_counts",
@@ -122,14 +126,19 @@ class Plan:
 
     def __init__(self, n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
                  out: str = "cheb", host_only: bool = False, tight: bool = False,
-                 zeig: bool = False, box=None, dirichlet: bool = False):
+                 zeig: bool = False, box=None, dirichlet: bool = False, n_theta=None):
         prec = {"fp64": FPS_FP64, "fp32_refined": FPS_FP32_REFINED}[precision]
         ob = {"cheb": FPS_OUT_CHEB, "native": FPS_OUT_NATIVE}[out]
         h = ctypes.c_void_p()
         flags = ((FPS_PLAN_HOST_ONLY if host_only else 0) | (FPS_PLAN_TIGHT_SPECTRUM if tight else 0)
                  | (FPS_PLAN_CUBE_ZEIG if zeig else 0) | (FPS_PLAN_DIRICHLET if dirichlet else 0))
         self._h = ctypes.c_void_p()
-        if box is not None:
+        self.n_theta = n_theta
+        if n_theta is not None:
+            _check(lib().fps_plan_create_cylinder(ctypes.byref(h), n, int(n_theta),
+                                                  FPS_PLAN_HOST_ONLY if host_only else 0))
+            dim = 3
+        elif box is not None:
             if dim != 2:
                 raise ValueError("a box applies to 2-D plans only")
             b = (ctypes.c_double * 4)(*[float(v) for v in box])
@@ -189,8 +198,15 @@ class Plan:
         return list(buf[: min(cnt.value, cap)])
 
     def out_shape(self):
+        if self.n_theta is not None:
+            return (self.n_theta, 2, self.n + 4, self.n + 2)
         e = self.n if self.out == "native" else self.n + 2
         return (e,) * self.dim
+
+    def in_shape(self):
+        if self.n_theta is not None:
+            return (self.n_theta, 2, self.n, self.n)
+        return (self.n,) * self.dim
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -210,6 +226,22 @@ def plan(n: int, tol: float = 1e-13, dim: int = 2, precision: str = "fp64",
     return Plan(n, tol, dim, precision, out, host_only, tight, zeig, box, dirichlet)
 
 
+def plan_cylinder(n: int, n_theta: int, host_only: bool = False) -> Plan:
+    """Cylinder plan (fps_plan_create_cylinder): solve() then takes the
+    doubled-up right-hand side as split complex [n_theta][2][n][n]."""
+    return Plan(n, host_only=host_only, n_theta=n_theta)
+
+
+def cylinder_mode_bands(n: int, k: int):
+    """(P, Q) bands of mode k's r-operators, each (n/2, 5), offsets -2..2."""
+    import numpy as np
+    P = np.zeros((n // 2, 5))
+    Q = np.zeros((n // 2, 5))
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().fps_cylinder_mode_bands(n, k, P.ctypes.data_as(dp), Q.ctypes.data_as(dp)))
+    return P, Q
+
+
 def _stream_ptr(torch, device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -224,8 +256,8 @@ def solve(p: Plan, F, out=None, ws=None):
     import torch
     if F.dtype != torch.float64 or not F.is_cuda or not F.is_contiguous():
         raise ValueError("F must be a contiguous float64 tensor on the GPU")
-    if tuple(F.shape) != (p.n,) * p.dim:
-        raise ValueError(f"F must have shape {(p.n,) * p.dim}")
+    if tuple(F.shape) != p.in_shape():
+        raise ValueError(f"F must have shape {p.in_shape()}")
     if out is None:
         out = torch.empty(p.out_shape(), dtype=torch.float64, device=F.device)
     if ws is None:

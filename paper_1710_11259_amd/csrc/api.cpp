@@ -521,6 +521,34 @@ fps_status fps_plan_create(fps_plan **out, int dim, int64_t n, int bc, double to
   return FPS_OK;
 }
 
+fps_status fps_plan_create_cylinder(fps_plan **out, int64_t n, int64_t n_theta, unsigned flags) {
+  if (!out) return fail(FPS_E_ARG, "out must not be null");
+  *out = nullptr;
+  if (flags & ~FPS_PLAN_HOST_ONLY) return fail(FPS_E_ARG, "cylinder plans take FPS_PLAN_HOST_ONLY only");
+  fps_plan *pl = nullptr;
+  fps_status s = plan_common(&pl, 3, n, FPS_BC_DIRICHLET_ZERO, 0.5, FPS_FP64, FPS_OUT_CHEB, flags);
+  if (s != FPS_OK) return s;
+  if ((s = cyl_plan_build(pl, n_theta)) == FPS_OK && !(flags & FPS_PLAN_HOST_ONLY))
+    s = cyl_plan_upload(pl);
+  if (s != FPS_OK) {
+    delete pl;
+    return s;
+  }
+  pl->on_device = !(flags & FPS_PLAN_HOST_ONLY);
+  *out = pl;
+  return FPS_OK;
+}
+
+fps_status fps_cylinder_mode_bands(int64_t n, int64_t k, double *P_host, double *Q_host) {
+  if (n < 2 || (n & 1) || n > 512) return fail(FPS_E_ARG, "n must be even, 2 <= n <= 512");
+  if (!P_host || !Q_host) return fail(FPS_E_ARG, "null output");
+  std::vector<double> P, Q;
+  cyl_mode_bands(n, k < 0 ? -k : k, P, Q);
+  std::copy(P.begin(), P.end(), P_host);
+  std::copy(Q.begin(), Q.end(), Q_host);
+  return FPS_OK;
+}
+
 fps_status fps_plan_create_rect(fps_plan **out, int64_t n, const double *box, double tol, int prec,
                                 int out_basis, unsigned flags) {
   if (!out) return fail(FPS_E_ARG, "out must not be null");
@@ -551,6 +579,12 @@ fps_status fps_plan_create_rect(fps_plan **out, int64_t n, const double *box, do
 
 fps_status fps_plan_info(const fps_plan *pl, int *J, int64_t *ws_bytes, int64_t *out_entries) {
   if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (pl->cyl) {
+    if (J) *J = 0;
+    if (ws_bytes) *ws_bytes = cyl_ws_bytes(pl);
+    if (out_entries) *out_entries = cyl_out_entries(pl);
+    return FPS_OK;
+  }
   if (J) *J = pl->shifts.J;
   if (ws_bytes) *ws_bytes = pl->ws_bytes;
   if (out_entries) {
@@ -629,6 +663,7 @@ fps_status fps_solve(fps_plan *pl, const double *F, double *U, void *ws, void *s
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   const fps::Layout &L = pl->L;
+  if (pl->cyl) return cyl_solve(pl, F, U, w, st);
   if (pl->dim == 3) return cube_solve(pl, F, U, w, st);
   if ((s = rhs_transform(pl, F, w, st)) != FPS_OK) return s;
   double *Y = nullptr;

@@ -177,6 +177,17 @@ struct BcLiftConst {
 hipError_t launch_bc_lift_rhs(const double *bc, const double *Ms0, const double *Ms1, double *G,
                               double *scratch, const Layout &L, double sx2, double sy2,
                               const BcLiftConst &k, hipStream_t st);
+// Cylinder: F [mode][part][n][n] -> X0 [slot][part][r][z] parity-blocked
+// (slot -> mode through slot_idx), zero padded to npad = 2 mp per axis.
+hipError_t launch_cyl_permute_in(const double *F, double *X0, const int *slot_idx, int64_t n,
+                                 int64_t nt, int64_t mp, hipStream_t st);
+// Cylinder: the banded r-solves of every (slot, part, z column) with the
+// plan's LU factors (see cylinder.cpp); X0 holds the right-hand sides (rows
+// of parity rp, overwritten), X1 receives yhat (rows of parity wp).
+hipError_t launch_cyl_solve(double *X0, double *X1, const double *fac, const int *slot_kabs,
+                            const int *slot_rp, const int *slot_wp, int64_t m, int64_t mp,
+                            int64_t nt, hipStream_t st);
+
 // U ((n+2) x (n+2) Chebyshev, natural order) += coefficients of u_bc.
 hipError_t launch_bc_lift_out(double *U, const double *bc, const double *scratch, int64_t n,
                               int64_t npad, hipStream_t st);

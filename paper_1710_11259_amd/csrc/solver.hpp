@@ -41,8 +41,15 @@ struct DeviceBuf {
 }  // namespace detail
 }  // namespace fps
 
+struct CylPlan;  // cylinder plans (cylinder.cpp)
+
 struct fps_plan {
   uint64_t magic = fps::detail::kMagic;
+  CylPlan *cyl = nullptr;  // non-null for cylinder plans
+  fps_plan() = default;
+  fps_plan(const fps_plan &) = delete;
+  fps_plan &operator=(const fps_plan &) = delete;
+  ~fps_plan();
   int dim = 2;
   int64_t n = 0;
   double tol = 0;
@@ -178,6 +185,14 @@ fps_status cube_plan_build(fps_plan *pl);
 fps_status cube_plan_upload(fps_plan *pl);
 fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *ws, hipStream_t st);
 hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st);
+// Cylinder (Sec. 4.1): host tables and workspace layout, their upload, the
+// solve, and the band of one mode's r-operators (inspection).
+fps_status cyl_plan_build(fps_plan *pl, int64_t nt);
+fps_status cyl_plan_upload(fps_plan *pl);
+fps_status cyl_solve(fps_plan *pl, const double *F, double *U, char *ws, hipStream_t st);
+int64_t cyl_ws_bytes(const fps_plan *pl);
+int64_t cyl_out_entries(const fps_plan *pl);
+void cyl_mode_bands(int64_t n, int64_t kabs, std::vector<double> &Pb, std::vector<double> &Qb);
 
 }  // namespace detail
 }  // namespace fps

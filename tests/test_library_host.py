@@ -479,3 +479,38 @@ def test_lift_map_matches_oracle(shim, n):
         # the oracle side projects each T_k'' (coefficients up to ~k^3) in
         # extended precision, cancelling by up to ~1e6: 1e-12 relative
         np.testing.assert_allclose(got, want, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("n", [2, 8, 20, 64])
+def test_cylinder_mode_bands_match_oracle(n):
+    # closed-form derivative matrices and powers of the C~ Jacobi matrix in
+    # the library against the oracle's quadrature Galerkin matrices
+    from oracle import cylinder
+    for k in (0, 1, -1, 2, 3, 6, 17):
+        P, Q = fps.cylinder_mode_bands(n, k)
+        Po, Qo, _, _, wp, rp = cylinder.mode_operators(n, k)
+        ri, wi = np.arange(rp, n, 2), np.arange(wp, n, 2)
+        Pr, Qr = Po[np.ix_(ri, wi)], Qo[np.ix_(ri, wi)]
+        m = n // 2
+        Pd, Qd = np.zeros((m, m)), np.zeros((m, m))
+        for a in range(m):
+            for c in range(5):
+                b = a + c - 2
+                if 0 <= b < m:
+                    Pd[a, b], Qd[a, b] = P[a, c], Q[a, c]
+        assert np.abs(Pd - Pr).max() <= 1e-12 * np.abs(Pr).max(), (n, k)
+        assert np.abs(Qd - Qr).max() <= 1e-12 * np.abs(Qr).max(), (n, k)
+
+
+def test_cylinder_plan_queries_and_errors():
+    p = fps.plan_cylinder(16, 8, host_only=True)
+    assert p.J == 0
+    assert p.out_entries == 8 * 2 * 20 * 18
+    assert p.out_shape() == (8, 2, 20, 18) and p.in_shape() == (8, 2, 16, 16)
+    L = fps.lib()
+    h = ctypes.c_void_p()
+    assert L.fps_plan_create_cylinder(ctypes.byref(h), 15, 8, 1) == 1  # odd n
+    assert L.fps_plan_create_cylinder(ctypes.byref(h), 16, 7, 1) == 1  # odd n_theta
+    assert L.fps_plan_create_cylinder(ctypes.byref(h), 16, 8, 2) == 1  # flags
+    assert L.fps_plan_create_cylinder(ctypes.byref(h), 1024, 8, 1) == 2
+    assert L.fps_solve_adjoint(p.handle, None, None, None, None) == 5  # host-only
