@@ -257,6 +257,51 @@ def bench_rect_dirichlet(fps, workloads, torch, tol, n=4096, box=(0.0, 2.5, -1.0
     return res
 
 
+def bench_cylinder(fps, workloads, torch, n=256, n_theta=256, steps=5, check=True):
+    """Cylinder (Sec. 4.1), n Chebyshev coefficients in r and z, n_theta
+    Fourier modes, FP64: time per solve (the per-mode systems solved
+    exactly in the z-eigenbasis), plan time, and the oracle's per-mode
+    solution on a sample of modes covering the three cases."""
+    import time as _t
+    import numpy as np
+    F_host = workloads.cylinder_rhs(n, n_theta, seed=9)
+    F = torch.from_numpy(np.ascontiguousarray(np.stack([F_host.real, F_host.imag], axis=1))).cuda()
+    t0 = _t.perf_counter()
+    p = fps.plan_cylinder(n, n_theta)
+    t_plan = _t.perf_counter() - t0
+    ws = fps.workspace(p, "cuda")
+    U = torch.empty(p.out_shape(), dtype=torch.float64, device="cuda")
+    fps.solve(p, F, out=U, ws=ws)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fps.solve(p, F, out=U, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    dof = float(n) * n * n_theta
+    res = {"n": n, "n_theta": n_theta, "dof": dof, "ms_per_solve": ms,
+           "dof_per_s": dof / (ms * 1e-3), "plan_s": round(t_plan, 2),
+           "method": "z-eigenbasis of A~, host-factored banded r-solves per (mode, z column), "
+                     "MFMA GEMM maps"}
+    if check:
+        from oracle import cylinder
+        Ug = U.cpu().numpy()
+        worst = 0.0
+        for k in (0, 1, -1, 2, -3, 17, n_theta // 4, -(n_theta // 2), n_theta // 2 - 1):
+            idx = k + n_theta // 2
+            Uo = (cylinder.solve_mode(np.ascontiguousarray(F_host[idx].real), k)
+                  + 1j * cylinder.solve_mode(np.ascontiguousarray(F_host[idx].imag), k))
+            Uk = Ug[idx, 0] + 1j * Ug[idx, 1]
+            worst = max(worst, float(np.linalg.norm(Uk - Uo) / np.linalg.norm(Uo)))
+        res["rel_err_vs_oracle_sampled_modes"] = worst
+    del ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,9 +314,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the FP32-refined, batched, cube and rectangle timings")
+                    help="skip the FP32-refined, batched, cube, rectangle and cylinder timings")
     ap.add_argument("--only", choices=["fp32_refined", "batched", "cube", "cube_zeig",
-                                       "rect_dirichlet"],
+                                       "rect_dirichlet", "cylinder"],
                     help="run only this form and print its figures (profiling)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
@@ -289,7 +334,7 @@ def main() -> int:
 
     n = args.n
     dev = torch.device("cuda:0")
-    if args.only in ("batched", "cube", "cube_zeig", "rect_dirichlet"):
+    if args.only in ("batched", "cube", "cube_zeig", "rect_dirichlet", "cylinder"):
         if args.copy_calib_mib:
             calibration_copy(torch, dev, args.copy_calib_mib)
         tight = args.enclosure == "tight"
@@ -298,6 +343,9 @@ def main() -> int:
         elif args.only == "cube":
             res = bench_cube(fps, workloads, torch, args.tol, steps=max(1, args.steps),
                              check=not args.no_check, tight=tight)
+        elif args.only == "cylinder":
+            res = bench_cylinder(fps, workloads, torch, steps=max(1, args.steps),
+                                 check=not args.no_check)
         elif args.only == "rect_dirichlet":
             res = bench_rect_dirichlet(fps, workloads, torch, args.tol, n=n,
                                        steps=max(1, args.steps), check=not args.no_check,
@@ -441,6 +489,7 @@ def main() -> int:
                                                  check=not args.no_check, tight=tight)
             forms["rect_dirichlet"] = bench_rect_dirichlet(fps, workloads, torch, args.tol, n=n,
                                                            check=not args.no_check, tight=tight)
+            forms["cylinder"] = bench_cylinder(fps, workloads, torch, check=not args.no_check)
     if forms:
         out["forms"] = forms
 
