@@ -85,11 +85,7 @@ fps_status build_gemm_tables(fps_batch *bt) {
     }
   }
   for (int t = 0; t < 4; ++t) {
-    std::vector<int> map(bt->gtiles[t]);
-    for (size_t k = 0; k < tab[t].size(); ++k) {
-      const int end = k + 1 < tab[t].size() ? tab[t][k + 1].tile_start : bt->gtiles[t];
-      std::fill(map.begin() + tab[t][k].tile_start, map.begin() + end, (int)k);
-    }
+    const std::vector<int> map = fps::gemm_table_map(tab[t]);
     fps_status s;
     if ((s = upload(bt->d_gd[t], tab[t])) != FPS_OK || (s = upload(bt->d_gmap[t], map)) != FPS_OK)
       return s;
@@ -130,7 +126,7 @@ fps_status build_descriptors(fps_batch *bt) {
     A.nc1 = (int)L.nc[1];
     A.lv = off_ptr<double *>(lv);
     const int nbx_s = (int)(L.npad / fps::kCols);
-    const int nbx_r = (int)((L.npad + fps::kReduceThreads - 1) / fps::kReduceThreads);
+    const int nbx_r = (int)((L.npad + fps::kReduceChains - 1) / fps::kReduceChains);
     for (int j = 0; j < J; ++j) {
       const bool last = j == J - 1;
       // half-step 1
@@ -281,7 +277,7 @@ fps_status fps_batch_create(fps_batch **out, int dim, int count, const int64_t *
   for (int k = 0; k < count; ++k) {
     const fps::Layout &L = bt->plan_of(bt->order[k])->L;
     const int64_t nsw = (L.npad / fps::kCols) * (L.nc[0] + L.nc[1]);
-    const int64_t nrd = ((L.npad + fps::kReduceThreads - 1) / fps::kReduceThreads) * 2;
+    const int64_t nrd = ((L.npad + fps::kReduceChains - 1) / fps::kReduceChains) * 2;
     if ((int64_t)bt->sw_start[k] + nsw > (int64_t)1 << 30 ||
         (int64_t)bt->rd_start[k] + nrd > (int64_t)1 << 30) {
       delete bt;

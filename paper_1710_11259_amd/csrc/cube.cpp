@@ -88,13 +88,9 @@ fps_status upload_table(const std::vector<fps::GemmProb> &probs, DeviceBuf &d, D
     tiles += fps::gemm_tiles(q, &e.ntx);
     tab.push_back(e);
   }
-  std::vector<int> m(tiles);
-  for (size_t k = 0; k < tab.size(); ++k) {
-    const int end = k + 1 < tab.size() ? tab[k + 1].tile_start : tiles;
-    std::fill(m.begin() + tab[k].tile_start, m.begin() + end, (int)k);
-  }
   fps_status s;
-  if ((s = upload(d, tab)) != FPS_OK || (s = upload(map, m)) != FPS_OK) return s;
+  if ((s = upload(d, tab)) != FPS_OK || (s = upload(map, fps::gemm_table_map(tab))) != FPS_OK)
+    return s;
   return FPS_OK;
 }
 
@@ -624,7 +620,7 @@ fps_status zeig_upload(fps_plan *pl) {
   const int K = (int)pl->zslice.size(), J = pl->zJmax;
   const int nbx_s = (int)(npad / fps::kCols), nch = (int)(L.nc[0] + L.nc[1]);
   const int nsw = nbx_s * nch;
-  const int nbx_r = (int)((npad + fps::kReduceThreads - 1) / fps::kReduceThreads);
+  const int nbx_r = (int)((npad + fps::kReduceChains - 1) / fps::kReduceChains);
   const int nrd = nbx_r * 2;
   const int64_t lvb = L.ncmax * 4 * npad, abb = 2 * L.ncmax * npad * 2;  // doubles per slice
   std::vector<fps::BatchSweep> sw((size_t)J * 2 * (K > 0 ? K : 1));

@@ -1,7 +1,7 @@
 // gfx950 kernels of the cylinder solve: the input permutation into the
 // parity-blocked per-mode layout and the banded solves in r (one thread per
-// mode, real/imaginary part and z column, applying LU factors computed by
-// the plan with partial pivoting).
+// |k| and z column, applying the LU factors computed by the plan with
+// partial pivoting to the modes k and -k, real and imaginary parts).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -10,110 +10,173 @@ namespace fps {
 
 namespace {
 
-__device__ inline int64_t natural_of(int64_t pos, int64_t m, int64_t mp) {
-  // parity-blocked position -> natural index, or -1 for padding
-  const int s = pos >= mp ? 1 : 0;
-  const int64_t a = pos - (s ? mp : 0);
-  return a < m ? 2 * a + s : -1;
-}
-
 // X0[((slot * 2 + part) * npad + rpos) * npad + zpos] = F[idx][part][i][j]
-// (zero at padded positions); grid (npad / 64, npad, nt * 2).
-__global__ __launch_bounds__(64) void k_cyl_permute_in(const double *__restrict__ F,
-                                                       double *__restrict__ X0,
-                                                       const int *__restrict__ slot_idx,
-                                                       int64_t n, int64_t mp) {
-  const int64_t npad = 2 * mp, m = n / 2;
-  const int64_t zpos = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const int64_t rpos = blockIdx.y;
-  const int64_t sp = blockIdx.z;  // slot * 2 + part
-  if (zpos >= npad) return;
-  const int64_t i = natural_of(rpos, m, mp), j = natural_of(zpos, m, mp);
-  const int64_t idx = slot_idx[sp >> 1], part = sp & 1;
-  double v = 0.0;
-  if (i >= 0 && j >= 0) v = F[((idx * 2 + part) * n + i) * n + j];
-  X0[(sp * npad + rpos) * npad + zpos] = v;
+// (zero at padded positions).  Thread e = ((sp * npad) + rpos) * mp + a
+// reads the pair F[..][i][2a], F[..][i][2a + 1] (adjacent lanes read
+// adjacent pairs) and writes the even-parity position a and the odd-parity
+// position mp + a of row rpos.
+__global__ __launch_bounds__(256) void k_cyl_permute_in(const double *__restrict__ F,
+                                                        double *__restrict__ X0,
+                                                        const int *__restrict__ slot_idx,
+                                                        uint32_t n, uint32_t mp, uint32_t total) {
+  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if (e >= total) return;
+  const uint32_t npad = 2 * mp, m = n / 2;
+  const uint32_t a = e % mp, row = e / mp;
+  const uint32_t rpos = row % npad, sp = row / npad;
+  const uint32_t rs = rpos >= mp ? 1u : 0u, ra = rpos - (rs ? mp : 0u);
+  double v0 = 0.0, v1 = 0.0;
+  if (ra < m && a < m) {
+    const int64_t i = 2 * (int64_t)ra + rs;
+    const double *src = F + (((int64_t)slot_idx[sp >> 1] * 2 + (sp & 1)) * n + i) * n + 2 * (int64_t)a;
+    v0 = src[0];
+    v1 = src[1];
+  }
+  double *dst = X0 + ((int64_t)sp * npad + rpos) * npad;
+  dst[a] = v0;
+  dst[mp + a] = v1;
 }
 
-// One banded system (Q_k + lambda_j P_k) yhat = rhs per thread.  rhs: X0 rows
+// One z column of one |k| group: the banded systems (Q_k + lambda_j P_k)
+// yhat = rhs of the group's right-hand sides (up to kCylRhs), sharing the
+// factors fac[((kabs * 8 + t) * mp + a) * npad + zpos], t: pivot offset,
+// two multipliers, 1/u_aa, four superdiagonal entries of U.  rhs: X0 rows
 // of parity rp (column zpos, stride npad), overwritten by the forward
 // substitution; yhat: X1 rows of parity wp (zeros beyond m and for padded
-// columns).  Factors fac[((kabs * 8 + t) * mp + a) * npad + zpos], t: pivot
-// offset, two multipliers, 1/u_aa, four superdiagonal entries of U.
+// columns).  The factors and right-hand sides of kCylStep consecutive steps
+// are loaded before they are used.
+constexpr int kCylStep = 8;
+
 __global__ __launch_bounds__(64) void k_cyl_solve(double *__restrict__ X0,
                                                   double *__restrict__ X1,
                                                   const double *__restrict__ fac,
-                                                  const int *__restrict__ slot_kabs,
-                                                  const int *__restrict__ slot_rp,
-                                                  const int *__restrict__ slot_wp, int64_t m,
+                                                  const CylSolveGroup *__restrict__ grp, int64_t m,
                                                   int64_t mp) {
   const int64_t npad = 2 * mp;
   const int64_t zpos = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const int64_t sp = blockIdx.y;
   if (zpos >= npad) return;
-  const int64_t slot = sp >> 1;
-  const int64_t kabs = slot_kabs[slot], rp = slot_rp[slot], wp = slot_wp[slot];
-  double *b = X0 + (sp * npad + rp * mp) * npad + zpos;
-  double *x = X1 + (sp * npad + wp * mp) * npad + zpos;
+  const CylSolveGroup &e = grp[blockIdx.y];
+  double *b[kCylRhs], *x[kCylRhs];
+  bool use[kCylRhs];
+#pragma unroll
+  for (int r = 0; r < kCylRhs; ++r) {
+    use[r] = e.sp[r] >= 0;
+    const int64_t sp = use[r] ? e.sp[r] : e.sp[0];  // unused: recomputed, never stored
+    b[r] = X0 + (sp * npad + e.rp * mp) * npad + zpos;
+    x[r] = X1 + (sp * npad + e.wp * mp) * npad + zpos;
+  }
   const int s = zpos >= mp ? 1 : 0;
-  const bool valid = zpos - (s ? mp : 0) < m;
-  if (!valid) {
-    for (int64_t a = 0; a < mp; ++a) x[a * npad] = 0.0;
+  if (zpos - (s ? mp : 0) >= m) {
+    for (int64_t a = 0; a < mp; ++a)
+#pragma unroll
+      for (int r = 0; r < kCylRhs; ++r)
+        if (use[r]) x[r][a * npad] = 0.0;
     return;
   }
-  const double *f0 = fac + ((kabs * 8 + 0) * mp) * npad + zpos;
+  const double *f0 = fac + ((int64_t)e.kabs * 8 * mp) * npad + zpos;
   const int64_t fs = mp * npad;  // between factor fields
-  double w0 = b[0], w1 = m > 1 ? b[npad] : 0.0, w2 = m > 2 ? b[2 * npad] : 0.0;
-  for (int64_t a = 0; a < m; ++a) {
-    const double *f = f0 + a * npad;
-    const int p = (int)f[0];
-    if (p == 1) {
-      const double t = w0;
-      w0 = w1;
-      w1 = t;
-    } else if (p == 2) {
-      const double t = w0;
-      w0 = w2;
-      w2 = t;
+  double w0[kCylRhs], w1[kCylRhs], w2[kCylRhs];
+#pragma unroll
+  for (int r = 0; r < kCylRhs; ++r) {
+    w0[r] = b[r][0];
+    w1[r] = m > 1 ? b[r][npad] : 0.0;
+    w2[r] = m > 2 ? b[r][2 * npad] : 0.0;
+  }
+  for (int64_t a0 = 0; a0 < m; a0 += kCylStep) {
+    double pv[kCylStep], l1[kCylStep], l2[kCylStep], nb[kCylRhs][kCylStep];
+#pragma unroll
+    for (int t = 0; t < kCylStep; ++t) {
+      const int64_t a = a0 + t;
+      const double *f = f0 + (a < m ? a : 0) * npad;
+      pv[t] = f[0];
+      l1[t] = f[fs];
+      l2[t] = f[2 * fs];
+#pragma unroll
+      for (int r = 0; r < kCylRhs; ++r) nb[r][t] = a + 3 < m ? b[r][(a + 3) * npad] : 0.0;
     }
-    w1 -= f[fs] * w0;
-    w2 -= f[2 * fs] * w0;
-    b[a * npad] = w0;
-    w0 = w1;
-    w1 = w2;
-    w2 = a + 3 < m ? b[(a + 3) * npad] : 0.0;
+#pragma unroll
+    for (int t = 0; t < kCylStep; ++t) {
+      const int64_t a = a0 + t;
+      if (a >= m) break;
+      const int p = (int)pv[t];
+#pragma unroll
+      for (int r = 0; r < kCylRhs; ++r) {
+        if (p == 1) {
+          const double tt = w0[r];
+          w0[r] = w1[r];
+          w1[r] = tt;
+        } else if (p == 2) {
+          const double tt = w0[r];
+          w0[r] = w2[r];
+          w2[r] = tt;
+        }
+        w1[r] -= l1[t] * w0[r];
+        w2[r] -= l2[t] * w0[r];
+        if (use[r]) b[r][a * npad] = w0[r];
+        w0[r] = w1[r];
+        w1[r] = w2[r];
+        w2[r] = nb[r][t];
+      }
+    }
   }
-  double x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0;
-  for (int64_t a = m - 1; a >= 0; --a) {
-    const double *f = f0 + a * npad;
-    const double v = (b[a * npad] - f[4 * fs] * x1 - f[5 * fs] * x2 - f[6 * fs] * x3 -
-                      f[7 * fs] * x4) * f[3 * fs];
-    x[a * npad] = v;
-    x4 = x3;
-    x3 = x2;
-    x2 = x1;
-    x1 = v;
+  double x1[kCylRhs], x2[kCylRhs], x3[kCylRhs], x4[kCylRhs];
+#pragma unroll
+  for (int r = 0; r < kCylRhs; ++r) x1[r] = x2[r] = x3[r] = x4[r] = 0.0;
+  for (int64_t a1 = m - 1; a1 >= 0; a1 -= kCylStep) {
+    double iu[kCylStep], u1[kCylStep], u2[kCylStep], u3[kCylStep], u4[kCylStep];
+    double bv[kCylRhs][kCylStep];
+#pragma unroll
+    for (int t = 0; t < kCylStep; ++t) {
+      const int64_t a = a1 - t >= 0 ? a1 - t : 0;
+      const double *f = f0 + a * npad;
+      iu[t] = f[3 * fs];
+      u1[t] = f[4 * fs];
+      u2[t] = f[5 * fs];
+      u3[t] = f[6 * fs];
+      u4[t] = f[7 * fs];
+#pragma unroll
+      for (int r = 0; r < kCylRhs; ++r) bv[r][t] = b[r][a * npad];
+    }
+#pragma unroll
+    for (int t = 0; t < kCylStep; ++t) {
+      const int64_t a = a1 - t;
+      if (a < 0) break;
+#pragma unroll
+      for (int r = 0; r < kCylRhs; ++r) {
+        const double v =
+            (bv[r][t] - u1[t] * x1[r] - u2[t] * x2[r] - u3[t] * x3[r] - u4[t] * x4[r]) * iu[t];
+        if (use[r]) x[r][a * npad] = v;
+        x4[r] = x3[r];
+        x3[r] = x2[r];
+        x2[r] = x1[r];
+        x1[r] = v;
+      }
+    }
   }
-  for (int64_t a = m; a < mp; ++a) x[a * npad] = 0.0;
+  for (int64_t a = m; a < mp; ++a)
+#pragma unroll
+    for (int r = 0; r < kCylRhs; ++r)
+      if (use[r]) x[r][a * npad] = 0.0;
 }
 
 }  // namespace
 
 hipError_t launch_cyl_permute_in(const double *F, double *X0, const int *slot_idx, int64_t n,
                                  int64_t nt, int64_t mp, hipStream_t st) {
-  const int64_t npad = 2 * mp;
-  dim3 grid((unsigned)((npad + 63) / 64), (unsigned)npad, (unsigned)(nt * 2));
-  hipLaunchKernelGGL(k_cyl_permute_in, grid, dim3(64), 0, st, F, X0, slot_idx, n, mp);
+  const int64_t total = nt * 2 * (2 * mp) * mp;
+  if (total <= 0) return hipSuccess;
+  if (total >= ((int64_t)1 << 32) - 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cyl_permute_in, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, F,
+                     X0, slot_idx, (uint32_t)n, (uint32_t)mp, (uint32_t)total);
   return hipGetLastError();
 }
 
-hipError_t launch_cyl_solve(double *X0, double *X1, const double *fac, const int *slot_kabs,
-                            const int *slot_rp, const int *slot_wp, int64_t m, int64_t mp,
-                            int64_t nt, hipStream_t st) {
+hipError_t launch_cyl_solve(double *X0, double *X1, const double *fac, const CylSolveGroup *grp,
+                            int ngroups, int64_t m, int64_t mp, hipStream_t st) {
   const int64_t npad = 2 * mp;
-  dim3 grid((unsigned)((npad + 63) / 64), (unsigned)(nt * 2));
-  hipLaunchKernelGGL(k_cyl_solve, grid, dim3(64), 0, st, X0, X1, fac, slot_kabs, slot_rp, slot_wp,
-                     m, mp);
+  if (ngroups <= 0) return hipSuccess;
+  dim3 grid((unsigned)((npad + 63) / 64), (unsigned)ngroups);
+  hipLaunchKernelGGL(k_cyl_solve, grid, dim3(64), 0, st, X0, X1, fac, grp, m, mp);
   return hipGetLastError();
 }
 

@@ -33,7 +33,9 @@ struct CylPlan {
   int64_t ro = 0;                      // r output rows per parity ((n + 4) / 2)
   int64_t nk = 0;                      // distinct |k|: 0 .. nt/2
   std::vector<int> slot_idx, slot_group, slot_kabs;  // internal slot -> mode
-  fps::detail::DeviceBuf d_slot_idx, d_slot_kabs, d_slot_rp, d_slot_wp;
+  fps::detail::DeviceBuf d_slot_idx;
+  fps::detail::DeviceBuf d_groups;  // fps::CylSolveGroup per |k| present
+  int ngroups = 0;
   fps::detail::DeviceBuf d_fac;               // [nk][8][mp][npad]
   fps::detail::DeviceBuf d_win[2], d_wout[2];  // z maps (mp x mp, mp x mop)
   fps::detail::DeviceBuf d_rin[4], d_rout[4];  // r maps per group (mp x mp, ro x mp)
@@ -352,16 +354,34 @@ fps_status cyl_plan_upload(fps_plan *pl) {
     }
     if ((st = upload(c->d_fac, fac)) != FPS_OK) return st;
   }
-  // slot tables
-  std::vector<int> rp_of, wp_of;
-  for (int g : c->slot_group) {
-    int rp, wp, mpow;
-    group_par(g, &rp, &wp, &mpow);
-    rp_of.push_back(rp);
-    wp_of.push_back(wp);
+  // slot table, and the solve groups: the (slot, part) rows sharing one |k|
+  std::vector<fps::CylSolveGroup> groups;
+  {
+    std::vector<int> gid(c->nk, -1);
+    for (size_t sl = 0; sl < c->slot_idx.size(); ++sl) {
+      const int kabs = c->slot_kabs[sl];
+      if (gid[kabs] < 0) {
+        fps::CylSolveGroup e;
+        for (int r = 0; r < fps::kCylRhs; ++r) e.sp[r] = -1;
+        int rp, wp, mpow;
+        group_par(c->slot_group[sl], &rp, &wp, &mpow);
+        e.kabs = kabs;
+        e.rp = rp;
+        e.wp = wp;
+        gid[kabs] = (int)groups.size();
+        groups.push_back(e);
+      }
+      fps::CylSolveGroup &e = groups[gid[kabs]];
+      for (int part = 0; part < 2; ++part) {
+        int r = 0;
+        while (r < fps::kCylRhs && e.sp[r] >= 0) ++r;
+        if (r == fps::kCylRhs) return fail(FPS_E_STATE, "internal: cylinder solve group overflow");
+        e.sp[r] = (int)sl * 2 + part;
+      }
+    }
   }
-  if ((st = upload(c->d_slot_idx, c->slot_idx)) != FPS_OK || (st = upload(c->d_slot_kabs, c->slot_kabs)) != FPS_OK ||
-      (st = upload(c->d_slot_rp, rp_of)) != FPS_OK || (st = upload(c->d_slot_wp, wp_of)) != FPS_OK)
+  c->ngroups = (int)groups.size();
+  if ((st = upload(c->d_slot_idx, c->slot_idx)) != FPS_OK || (st = upload(c->d_groups, groups)) != FPS_OK)
     return st;
   // r-map GEMM tables (workspace / output offsets)
   const int64_t nt = c->nt, N2 = (n + 4) * (n + 2);
@@ -408,17 +428,10 @@ fps_status cyl_plan_upload(fps_plan *pl) {
       }
   }
   c->tiles_out = tiles;
-  auto tile_map = [](const std::vector<fps::GemmDesc> &t, int total) {
-    std::vector<int> mm((size_t)total);
-    for (size_t k = 0; k < t.size(); ++k) {
-      const int end = k + 1 < t.size() ? t[k + 1].tile_start : total;
-      std::fill(mm.begin() + t[k].tile_start, mm.begin() + end, (int)k);
-    }
-    return mm;
-  };
-  if ((st = upload(c->d_tin, tin)) != FPS_OK || (st = upload(c->d_tin_map, tile_map(tin, c->tiles_in))) != FPS_OK ||
+  if ((st = upload(c->d_tin, tin)) != FPS_OK ||
+      (st = upload(c->d_tin_map, fps::gemm_table_map(tin))) != FPS_OK ||
       (st = upload(c->d_tout, tout)) != FPS_OK ||
-      (st = upload(c->d_tout_map, tile_map(tout, c->tiles_out))) != FPS_OK)
+      (st = upload(c->d_tout_map, fps::gemm_table_map(tout))) != FPS_OK)
     return st;
   (void)nt;
   return FPS_OK;
@@ -448,9 +461,8 @@ fps_status cyl_solve(fps_plan *pl, const double *F, double *U, char *w, hipStrea
   FPS_HIP(fps::launch_gemm_table((const fps::GemmDesc *)c->d_tin.p, (const int *)c->d_tin_map.p,
                                  c->tiles_in, w, nullptr, st));
   // 4. banded solves: X1[wp block] = yhat
-  FPS_HIP(fps::launch_cyl_solve(X0, X1, (const double *)c->d_fac.p, (const int *)c->d_slot_kabs.p,
-                                (const int *)c->d_slot_rp.p, (const int *)c->d_slot_wp.p, c->m, mp,
-                                nt, st));
+  FPS_HIP(fps::launch_cyl_solve(X0, X1, (const double *)c->d_fac.p,
+                                (const fps::CylSolveGroup *)c->d_groups.p, c->ngroups, c->m, mp, st));
   // 5. z output map: X0 [slot][part][r][zout] = X1 W_out
   {
     fps::GemmProb q[2];

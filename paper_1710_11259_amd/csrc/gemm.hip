@@ -2,6 +2,9 @@
 // Poisson solver (Chebyshev <-> C~^(3/2) maps of Sec. 3.4 and Table 1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "kernels.hpp"
 
 namespace fps {
@@ -36,14 +39,10 @@ struct GemmBatch {
 
 constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
 
-// One 128 x 128 output tile (column tile bx, row tile by) of problem g.
-__device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const int by,
-                                          double (*As)[GBK + 1], double (*Bs)[GBN + GPAD]) {
+// k-range [klo, khi) of tile (bx, by) after the triangular skips.
+__host__ __device__ inline void tile_krange(const GemmProb &g, int bx, int by, int64_t *klo_out,
+                                            int64_t *khi_out) {
   const int64_t i0 = (int64_t)by * GBM, j0 = (int64_t)bx * GBN;
-  if (i0 >= g.M || j0 >= g.N) return;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wy = wid >> 1, wx = wid & 1;
-
   int64_t klo = 0;
   if (g.triA) klo = i0 + g.offA > klo ? i0 + g.offA : klo;
   if (g.triB) klo = j0 + g.offB > klo ? j0 + g.offB : klo;
@@ -59,6 +58,19 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
   }
   khi = (khi + GBK - 1) / GBK * GBK;
   if (khi > g.K) khi = g.K;
+  *klo_out = klo;
+  *khi_out = khi;
+}
+
+// One 128 x 128 output tile (column tile bx, row tile by) of problem g.
+__device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const int by,
+                                          double (*As)[GBK + 1], double (*Bs)[GBN + GPAD]) {
+  const int64_t i0 = (int64_t)by * GBM, j0 = (int64_t)bx * GBN;
+  if (i0 >= g.M || j0 >= g.N) return;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wy = wid >> 1, wx = wid & 1;
+  int64_t klo, khi;
+  tile_krange(g, bx, by, &klo, &khi);
 
   // Loader mapping.  A tile 128 x 16: thread t reads row t/2, k-run (t%2)*8..+8.
   // B tile 16 x 128: thread t reads k-row t/16, column run (t%16)*8..+8.
@@ -167,7 +179,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmBatch batch) {
 }
 
 // Table-driven GEMM: workgroup g computes tile (local % ntx, local / ntx),
-// local = g - tile_start, of problem tile_prob[g]; operand pointers are
+// local = tile_map[2g + 1], of problem tile_map[2g]; operand pointers are
 // rebased per GemmDesc base ids.
 __device__ __forceinline__ const double *rebase(const double *p, int id, char *ws, char *out) {
   return id == 1 ? (const double *)(ws + (intptr_t)p)
@@ -175,17 +187,17 @@ __device__ __forceinline__ const double *rebase(const double *p, int id, char *w
 }
 
 __global__ __launch_bounds__(256, 2) void k_gemm_table(const GemmDesc *__restrict__ d,
-                                                       const int *__restrict__ tile_prob, char *ws,
+                                                       const int *__restrict__ tile_map, char *ws,
                                                        char *out) {
   __shared__ double As[GBM][GBK + 1];
   __shared__ double Bs[GBK][GBN + GPAD];
-  const int k = __builtin_amdgcn_readfirstlane(tile_prob[blockIdx.x]);
+  const int k = __builtin_amdgcn_readfirstlane(tile_map[2 * blockIdx.x]);
+  const int local = __builtin_amdgcn_readfirstlane(tile_map[2 * blockIdx.x + 1]);
   const GemmDesc &e = d[k];
   GemmProb g = e.p;
   g.A = rebase(g.A, e.abase, ws, out);
   g.B = rebase(g.B, e.bbase, ws, out);
   g.C = (double *)rebase(g.C, e.cbase, ws, out);
-  const int local = (int)blockIdx.x - e.tile_start;
   gemm_tile(g, local % e.ntx, local / e.ntx, As, Bs);
 }
 
@@ -201,12 +213,39 @@ int gemm_tiles(const GemmProb &q, int *ntx) {
   return *ntx * (int)((q.M + GBM - 1) / GBM);
 }
 
-hipError_t launch_gemm_table(const GemmDesc *d, const int *tile_prob, int ntiles, char *ws,
+hipError_t launch_gemm_table(const GemmDesc *d, const int *tile_map, int ntiles, char *ws,
                              char *out, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm_table, dim3((unsigned)ntiles), dim3(256), 0, st, d, tile_prob, ws,
+  hipLaunchKernelGGL(k_gemm_table, dim3((unsigned)ntiles), dim3(256), 0, st, d, tile_map, ws,
                      out);
   return hipGetLastError();
+}
+
+std::vector<int> gemm_table_map(const std::vector<GemmDesc> &tab) {
+  // every tile of every problem, longest k-range first (workgroups start in
+  // id order, so the short tiles fill the tail); ties keep table order
+  struct T {
+    int64_t work;
+    int prob, local;
+  };
+  std::vector<T> tiles;
+  for (size_t k = 0; k < tab.size(); ++k) {
+    int ntx = 0;
+    const int nt = gemm_tiles(tab[k].p, &ntx);
+    for (int l = 0; l < nt; ++l) {
+      int64_t klo, khi;
+      tile_krange(tab[k].p, l % ntx, l / ntx, &klo, &khi);
+      tiles.push_back(T{khi > klo ? khi - klo : 0, (int)k, l});
+    }
+  }
+  std::stable_sort(tiles.begin(), tiles.end(), [](const T &a, const T &b) { return a.work > b.work; });
+  std::vector<int> map;
+  map.reserve(2 * tiles.size());
+  for (const T &t : tiles) {
+    map.push_back(t.prob);
+    map.push_back(t.local);
+  }
+  return map;
 }
 
 hipError_t launch_gemm(const GemmProb *probs, int count, hipStream_t st) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "planner.hpp"
 
@@ -85,13 +86,14 @@ hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, doubl
                          int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
                          int nbatch = 1, int64_t lvb = 0, int64_t abb = 0);
 
-// Threads per workgroup of the chunk-carry kernels (one chain per thread).
-constexpr int kReduceThreads = 64;
+// Chains per workgroup of the chunk-carry kernels (each chain on a segment
+// of 8 to 64 lanes, by the chunk count).
+constexpr int kReduceChains = 16;
 
 // Batched launch_reduce: lv_off / ab_off are byte offsets from `base`; the
 // workgroups of one problem are (chain block b, parity s) -> local index
-// s * nbx + b with nbx = ceil(npad / kReduceThreads), flattened as for
-// BatchSweep; ncmax_max bounds every problem's ncmax (LDS size).
+// s * nbx + b with nbx = ceil(npad / kReduceChains), flattened as for
+// BatchSweep; ncmax_max bounds every problem's ncmax (lanes per chain).
 struct BatchReduce {
   int64_t lv_off, ab_off;
   const double *ctab;
@@ -181,12 +183,21 @@ hipError_t launch_bc_lift_rhs(const double *bc, const double *Ms0, const double 
 // (slot -> mode through slot_idx), zero padded to npad = 2 mp per axis.
 hipError_t launch_cyl_permute_in(const double *F, double *X0, const int *slot_idx, int64_t n,
                                  int64_t nt, int64_t mp, hipStream_t st);
-// Cylinder: the banded r-solves of every (slot, part, z column) with the
-// plan's LU factors (see cylinder.cpp); X0 holds the right-hand sides (rows
-// of parity rp, overwritten), X1 receives yhat (rows of parity wp).
-hipError_t launch_cyl_solve(double *X0, double *X1, const double *fac, const int *slot_kabs,
-                            const int *slot_rp, const int *slot_wp, int64_t m, int64_t mp,
-                            int64_t nt, hipStream_t st);
+// Cylinder: the right-hand sides that share one |k| (modes k and -k, real
+// and imaginary parts): up to kCylRhs (slot * 2 + part) rows of X0 / X1,
+// unused entries -1; rp / wp the row parities of the right-hand side and of
+// the solution.
+constexpr int kCylRhs = 4;
+struct CylSolveGroup {
+  int sp[kCylRhs];
+  int kabs, rp, wp;
+};
+// Cylinder: the banded r-solves of every (|k| group, z column) with the
+// plan's LU factors (see cylinder.cpp), one thread applying them to all the
+// group's right-hand sides; X0 holds the right-hand sides (rows of parity
+// rp, overwritten), X1 receives yhat (rows of parity wp).
+hipError_t launch_cyl_solve(double *X0, double *X1, const double *fac, const CylSolveGroup *grp,
+                            int ngroups, int64_t m, int64_t mp, hipStream_t st);
 
 // U ((n+2) x (n+2) Chebyshev, natural order) += coefficients of u_bc.
 hipError_t launch_bc_lift_out(double *U, const double *bc, const double *scratch, int64_t n,
@@ -220,13 +231,17 @@ int gemm_tiles(const GemmProb &q, int *ntx);
 // Table-driven GEMM over many problems in one launch.  Each pointer of a
 // descriptor's GemmProb is absolute (base id 0), a byte offset from `ws`
 // (1) or from `out` (2).  Workgroup g computes tile (local % ntx, local /
-// ntx), local = g - tile_start, of problem tile_prob[g].
+// ntx) of problem tile_map[2g], local = tile_map[2g + 1].
 struct GemmDesc {
   GemmProb p;
   int abase, bbase, cbase;
-  int tile_start, ntx;
+  int tile_start;  // first tile of this problem in table order (host bookkeeping)
+  int ntx;
 };
-hipError_t launch_gemm_table(const GemmDesc *d, const int *tile_prob, int ntiles, char *ws,
+hipError_t launch_gemm_table(const GemmDesc *d, const int *tile_map, int ntiles, char *ws,
                              char *out, hipStream_t st);
+// Host: the tile map of a table, (problem, local tile) pairs for every tile
+// of every problem, longest k-range (after the triangular skips) first.
+std::vector<int> gemm_table_map(const std::vector<GemmDesc> &tab);
 
 }  // namespace fps

@@ -9,8 +9,8 @@
 //     the recurrences: each piece runs with zero carries and the true carry
 //     enters through precomputed multiplier products;
 //   * carries between the segments of a chunk go through LDS; carries
-//     between chunks are left in a small array, resolved by k_reduce, and
-//     folded into the next pass when it reads its input;
+//     between chunks are left in a small array, resolved by k_reduce
+//     (reduce.hip), and folded into the next pass when it reads its input;
 //   * the multiply by (A~ - p' I) that Algorithm 2 applies after each solve
 //     along the same direction is r - (p + p') x, so no neighbour access is
 //     needed; the pass output is stored transposed so that the next pass,
@@ -404,147 +404,6 @@ __global__ __launch_bounds__(kCols *kWaves, 6) void k_sweep_batch(const BatchSwe
   sweep_block<Tin, Tg, Tout, kG, kPre>(a, local % e.nbx, local / e.nbx, lds);
 }
 
-// Chunk carries of one half-sweep: thread (parity s, chain r) runs the
-// chunk-level recurrences of its chain on the chunk boundary values
-//   cf[0] = 0,        cf[c+1] = ylast[c] + F2last[c] cf[c],
-//   cb[nc-1] = 0,     cb[c] = xfirst[c+1] + BF2first[c+1] cf[c+1]
-//                            + Bk2first[c+1] cb[c+1],
-// (per-chunk coefficients ctab of the producing pass's shift, staged in LDS)
-// and writes ab[s][c][r] = scale (cf[c], cb[c]).  cf is parked in ab between
-// the two sweeps over the chunks (each thread rereads only what it wrote).
-__device__ __forceinline__ void reduce_chain(const double *__restrict__ lv,
-                                             const double *__restrict__ ct, double *__restrict__ ab,
-                                             double scale, int64_t nchains, int nc, int64_t ncmax,
-                                             int s, int64_t r) {
-  const double *__restrict__ yl = lv + (int64_t)s * 2 * nchains + r;  // chunk q at q * 4 nchains
-  const double *__restrict__ xf = yl + nchains;
-  double *__restrict__ o = ab + ((int64_t)s * ncmax * nchains + r) * 2;  // chunk c at c * 2 nchains
-  // forward: cf[c] parked (unscaled) in o[c][0]
-  double cf = 0.0;
-  for (int c0 = 0; c0 < nc; c0 += 8) {
-    double y8[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) y8[k] = c0 + k < nc ? yl[(int64_t)(c0 + k) * 4 * nchains] : 0.0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int c = c0 + k;
-      if (c < nc) {
-        o[(int64_t)c * 2 * nchains] = cf;
-        cf = y8[k] + ct[C_F2LAST * ncmax + c] * cf;
-      }
-    }
-  }
-  // backward, chunks nc-1 .. 0; cfn = unscaled cf of chunk c + 1
-  double cb = 0.0, cfn = 0.0;
-  for (int c1 = nc - 1; c1 >= 0; c1 -= 8) {
-    double f8[8], x8[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int c = c1 - k;
-      f8[k] = c >= 0 ? o[(int64_t)c * 2 * nchains] : 0.0;
-      x8[k] = c >= 0 && c + 1 < nc ? xf[(int64_t)(c + 1) * 4 * nchains] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int c = c1 - k;
-      if (c >= 0) {
-        cb = c + 1 < nc ? x8[k] + ct[C_BF2FIRST * ncmax + c + 1] * cfn +
-                              ct[C_BK2FIRST * ncmax + c + 1] * cb
-                        : 0.0;
-        double *oc = o + (int64_t)c * 2 * nchains;
-        oc[0] = scale * f8[k];
-        oc[1] = scale * cb;
-        cfn = f8[k];
-      }
-    }
-  }
-}
-
-// The same recurrences with every boundary value of the chain loaded at
-// once into registers (nc <= NC chunks): one round of memory latency.
-template <int NC>
-__device__ __forceinline__ void reduce_chain_reg(const double *__restrict__ lv,
-                                                 const double *__restrict__ ct,
-                                                 double *__restrict__ ab, double scale,
-                                                 int64_t nchains, int nc, int64_t ncmax, int s,
-                                                 int64_t r) {
-  const double *__restrict__ yl = lv + (int64_t)s * 2 * nchains + r;
-  const double *__restrict__ xf = yl + nchains;
-  double *__restrict__ o = ab + ((int64_t)s * ncmax * nchains + r) * 2;
-  double y[NC], x[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    y[c] = c < nc ? yl[(int64_t)c * 4 * nchains] : 0.0;
-    x[c] = c < nc ? xf[(int64_t)c * 4 * nchains] : 0.0;
-  }
-  double cf = 0.0;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {  // y[c] <- cf[c]
-    const double next = y[c] + ct[C_F2LAST * ncmax + c] * cf;
-    y[c] = cf;
-    cf = next;
-  }
-  double cb = 0.0;
-#pragma unroll
-  for (int c = NC - 1; c >= 0; --c) {
-    if (c < nc) {
-      cb = c + 1 < nc ? x[c + 1] + ct[C_BF2FIRST * ncmax + c + 1] * y[c + 1] +
-                            ct[C_BK2FIRST * ncmax + c + 1] * cb
-                      : 0.0;
-      double *oc = o + (int64_t)c * 2 * nchains;
-      oc[0] = scale * y[c];
-      oc[1] = scale * cb;
-    }
-  }
-}
-
-__device__ __forceinline__ void reduce_any(const double *lv, const double *ct, double *ab,
-                                           double scale, int64_t nchains, int nc, int64_t ncmax,
-                                           int s, int64_t r) {
-  if (nc <= 8)
-    reduce_chain_reg<8>(lv, ct, ab, scale, nchains, nc, ncmax, s, r);
-  else if (nc <= 32)
-    reduce_chain_reg<32>(lv, ct, ab, scale, nchains, nc, ncmax, s, r);
-  else
-    reduce_chain(lv, ct, ab, scale, nchains, nc, ncmax, s, r);
-}
-
-// Grid: (ceil(nchains / kReduceThreads), 2 parities, batch).
-__global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restrict__ lv,
-                                                           const double *__restrict__ ctab,
-                                                           double *__restrict__ ab, double scale,
-                                                           int64_t nchains, int nc0, int nc1,
-                                                           int64_t ncmax, int64_t lvb,
-                                                           int64_t abb) {
-  extern __shared__ double ct[];  // [kNCTab][ncmax] of this parity
-  const int s = blockIdx.y;
-  const int nc = s ? nc1 : nc0;
-  for (int e = threadIdx.x; e < kNCTab * ncmax; e += blockDim.x)
-    ct[e] = ctab[(int64_t)s * kNCTab * ncmax + e];
-  __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nchains || nc == 0) return;
-  const int64_t z = blockIdx.z;
-  reduce_any(lv + z * lvb, ct, ab + z * abb, scale, nchains, nc, ncmax, s, r);
-}
-
-__global__ __launch_bounds__(kReduceThreads) void k_reduce_batch(
-    const BatchReduce *__restrict__ d, const int *__restrict__ wg_prob, char *base) {
-  extern __shared__ double ct[];
-  const int k = __builtin_amdgcn_readfirstlane(wg_prob[blockIdx.x]);
-  const BatchReduce &e = d[k];
-  const int local = (int)blockIdx.x - e.wg_start;
-  const int s = local / e.nbx;
-  const int nc = s ? e.nc1 : e.nc0;
-  for (int i = threadIdx.x; i < kNCTab * e.ncmax; i += blockDim.x)
-    ct[i] = e.ctab[(int64_t)s * kNCTab * e.ncmax + i];
-  __syncthreads();
-  const int64_t r = (int64_t)(local % e.nbx) * blockDim.x + threadIdx.x;
-  if (r >= e.npad || nc == 0) return;
-  reduce_any((const double *)(base + e.lv_off), ct, (double *)(base + e.ab_off), e.scale, e.npad,
-             nc, e.ncmax, s, r);
-}
-
 }  // namespace
 
 // Launches one sweep (single: d == nullptr, grid from `a`; batched: `nwg`
@@ -632,28 +491,6 @@ hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSw
                               int wg_base, hipEvent_t ev0, hipEvent_t ev1) {
   if (nwg <= 0) return hipSuccess;
   return dispatch_sweep(SweepLaunch{types, d, wg_prob, base, nwg, st, ev0, ev1, wg_base}, with_g);
-}
-
-hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,
-                         int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
-                         int nbatch, int64_t lvb, int64_t abb) {
-  dim3 grid((unsigned)((nchains + kReduceThreads - 1) / kReduceThreads), 2u,
-            (unsigned)(nbatch > 0 ? nbatch : 1));
-  const size_t shm = (size_t)ncmax * kNCTab * sizeof(double);
-  if (shm > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce, grid, dim3(kReduceThreads), shm, st, lv, ctab, ab, scale, nchains, nc0, nc1,
-                     ncmax, lvb, abb);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce_batch(const BatchReduce *d, const int *wg_prob, int nwg, int64_t ncmax_max,
-                               char *base, hipStream_t st) {
-  if (nwg <= 0) return hipSuccess;
-  const size_t shm = (size_t)ncmax_max * kNCTab * sizeof(double);
-  if (shm > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)nwg), dim3(kReduceThreads), shm, st, d, wg_prob,
-                     base);
-  return hipGetLastError();
 }
 
 }  // namespace fps

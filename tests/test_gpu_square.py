@@ -36,6 +36,28 @@ def test_adi_iterate_matches_closed_form(n, tol):
     assert _rel(Y.cpu().numpy(), Yo) < 1e-12
 
 
+def test_long_chains_iterate_matches_closed_form():
+    # n = 8200: 4100 positions per parity chain, i.e. 65 chunks, more than the
+    # 64 lanes the chunk-carry scan gives one chain, so the carries take the
+    # sequential form.  The rounding of the J-step iterate grows with n
+    # (relative error measured 1.7e-11 at n = 6000 and 1.2e-11 at n = 8192,
+    # both with the scan, 2.4e-11 here), so the bound is 1e-10; a wrong carry
+    # gives errors of order one.
+    n, tol = 8200, 1e-13
+    rng = np.random.default_rng(n)
+    G = rng.standard_normal((n, n)) / np.outer(np.arange(1, n + 1), np.arange(1, n + 1))
+    p = fps.plan(n, tol=tol)
+    J, po, _ = oshifts.square_shifts(n, tol)
+    assert p.J == J
+    print(f"adi_native n={n} J={J}", flush=True)
+    Y = fps.adi_native(p, _dev(G)).cpu().numpy()
+    print("closed form", flush=True)
+    Yo = square.adi_exact_iterate(G, po)
+    err = _rel(Y, Yo)
+    print(f"rel err {err:.3e}", flush=True)
+    assert err < 1e-10
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 8, 64, 130, 513, 1024])
 def test_solve_matches_exact_discrete_solution(n):
     F = workloads.square_rhs(n, seed=0)
