@@ -21,7 +21,7 @@ HBM_PEAK_GBS = 8000.0
 # Calibrated HBM traffic of the sweep kernel per launch at n = 4096 (rocprofv3
 # FETCH_SIZE x2.000 + WRITE_SIZE x1.000, see profiles/sweep_square_n4096.md),
 # valid only for the sweep source with this sha256.
-SWEEP_TRAFFIC = {"sha256": "e8f7bda39359fdd10ec2cc22e13c9945c21b7718fd8d1663579a83bb56467ebc",
+SWEEP_TRAFFIC = {"sha256": "b1bff1e4d1acd93bd6e6fc03628d9fc64d820a735a8b6b8015a46395c87bc3f3",
                  "n": 4096, "half_step_1": 278.8e6, "half_step_2": 413.0e6}
 
 
