@@ -18,6 +18,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "dof/s, square Poisson n=4096 at rel err ≤1e-12; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6  # dense FP64 matrix peak of MI355X
 # Calibrated HBM traffic of the sweep kernel per launch at n = 4096 (rocprofv3
 # FETCH_SIZE x2.000 + WRITE_SIZE x1.000, see profiles/sweep_square_n4096.md),
 # valid only for the sweep source with this sha256.
@@ -282,10 +283,33 @@ def bench_cylinder(fps, workloads, torch, n=256, n_theta=256, steps=5, check=Tru
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     dof = float(n) * n * n_theta
+    # Whole-solve rooflines.  MFMA: the four maps, 6 n_theta n^3 flops (z in and
+    # out 2 n_theta n^3 each, r in and out n_theta n^3 each, parity blocks).
+    # HBM: every stage reads its operands and writes its result once: the
+    # permutation (F, X), the z and r input maps (2 X each), the banded solves
+    # (factor table + 2 X), the z output map (X + X_out), the r output map
+    # (X_out + U) and the fill of U; X = 2 n_theta npad^2 doubles, X_out with
+    # the padded z output width.
+    m = n // 2
+    mp = (m + 63) // 64 * 64
+    npad = 2 * mp
+    mobar = 2 * ((m + 1 + 63) // 64 * 64)
+    X = 2.0 * n_theta * npad * npad * 8
+    Xo = X * mobar / npad
+    Fb = 2.0 * n_theta * n * n * 8
+    Ub = 2.0 * n_theta * (n + 4) * (n + 2) * 8
+    fac = (n_theta // 2 + 1) * 8.0 * mp * npad * 8
+    hbm = (Fb + X) + 2 * X + 2 * X + (fac + 2 * X) + (X + Xo) + (Xo + Ub) + Ub
+    flops = 6.0 * n_theta * float(n) ** 3
     res = {"n": n, "n_theta": n_theta, "dof": dof, "ms_per_solve": ms,
            "dof_per_s": dof / (ms * 1e-3), "plan_s": round(t_plan, 2),
            "method": "z-eigenbasis of A~, host-factored banded r-solves per (mode, z column), "
-                     "MFMA GEMM maps"}
+                     "MFMA GEMM maps",
+           "roofline_whole_solve": {
+               "hbm_bytes_algorithmic": hbm, "hbm_GBs": round(hbm / (ms * 1e-3) / 1e9, 1),
+               "hbm_frac": round(hbm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "mfma_flops": flops, "TFLOPs": round(flops / (ms * 1e-3) / 1e12, 2),
+               "fp64_mfma_frac": round(flops / (ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4)}}
     if check:
         from oracle import cylinder
         Ug = U.cpu().numpy()

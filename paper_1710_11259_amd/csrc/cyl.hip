@@ -159,6 +159,72 @@ __global__ __launch_bounds__(64) void k_cyl_solve(double *__restrict__ X0,
       if (use[r]) x[r][a * npad] = 0.0;
 }
 
+// Thin edges of the r output map (see launch_cyl_redge).  The edge
+// columns of X0_blk and the edge rows of Pr are staged in LDS.  Tasks: the rows i < ro_main of the
+// column edge (reading PrT coalesced, threads over rows) and the columns
+// j < mo of the row edge (reading X0_blk coalesced, threads over columns),
+// one task per thread; the
+// k loops load kCylEdgeB values before using them.
+constexpr int kCylEdgeMax = 8, kCylEdgeK = 256, kCylEdgeB = 16, kCylEdgeThreads = 320;
+
+__global__ __launch_bounds__(kCylEdgeThreads) void k_cyl_redge(
+    const CylEdge *__restrict__ d, char *ws, double *__restrict__ U, int64_t mp, int64_t ro,
+    int64_t ro_main, int64_t mo, int64_t mo_main, int64_t mobar, int64_t ldc) {
+  __shared__ double xs[kCylEdgeMax][kCylEdgeK];  // X0_blk columns mo_main..
+  __shared__ double ps[kCylEdgeMax][kCylEdgeK];  // Pr rows ro_main..
+  const CylEdge &e = d[blockIdx.x];
+  const double *__restrict__ B = (const double *)(ws + e.b_off);
+  double *__restrict__ C = U + e.c_off;
+  const int ne_c = (int)(mo - mo_main), ne_r = (int)(ro - ro_main);
+  const int tid = threadIdx.x;
+  for (int64_t t = tid; t < ne_c * mp; t += kCylEdgeThreads) {
+    const int64_t c = t / mp, k = t % mp;
+    xs[c][k] = B[k * mobar + mo_main + c];
+  }
+  for (int64_t t = tid; t < ne_r * mp; t += kCylEdgeThreads) {
+    const int64_t r = t / mp, k = t % mp;
+    ps[r][k] = e.Pr[(ro_main + r) * mp + k];
+  }
+  __syncthreads();
+  const int64_t ntask = (ne_c > 0 ? ro_main : 0) + (ne_r > 0 ? mo : 0);
+  for (int64_t task = tid; task < ntask; task += kCylEdgeThreads) {
+    double acc[kCylEdgeMax];
+#pragma unroll
+    for (int r = 0; r < kCylEdgeMax; ++r) acc[r] = 0.0;
+    if (ne_c > 0 && task < ro_main) {  // column edge, row i
+      const int64_t i = task;
+      for (int64_t k0 = 0; k0 < mp; k0 += kCylEdgeB) {
+        double a[kCylEdgeB];
+#pragma unroll
+        for (int u = 0; u < kCylEdgeB; ++u) a[u] = e.PrT[(k0 + u) * ro + i];
+#pragma unroll
+        for (int u = 0; u < kCylEdgeB; ++u)
+#pragma unroll
+          for (int c = 0; c < kCylEdgeMax; ++c)
+            if (c < ne_c) acc[c] = fma(a[u], xs[c][k0 + u], acc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < kCylEdgeMax; ++c)
+        if (c < ne_c) C[i * ldc + (mo_main + c) * 2] = acc[c];
+    } else {  // row edge, column j
+      const int64_t j = task - (ne_c > 0 ? ro_main : 0);
+      for (int64_t k0 = 0; k0 < mp; k0 += kCylEdgeB) {
+        double b[kCylEdgeB];
+#pragma unroll
+        for (int u = 0; u < kCylEdgeB; ++u) b[u] = B[(k0 + u) * mobar + j];
+#pragma unroll
+        for (int u = 0; u < kCylEdgeB; ++u)
+#pragma unroll
+          for (int r = 0; r < kCylEdgeMax; ++r)
+            if (r < ne_r) acc[r] = fma(ps[r][k0 + u], b[u], acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < kCylEdgeMax; ++r)
+        if (r < ne_r) C[(ro_main + r) * ldc + j * 2] = acc[r];
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_cyl_permute_in(const double *F, double *X0, const int *slot_idx, int64_t n,
@@ -177,6 +243,18 @@ hipError_t launch_cyl_solve(double *X0, double *X1, const double *fac, const Cyl
   if (ngroups <= 0) return hipSuccess;
   dim3 grid((unsigned)((npad + 63) / 64), (unsigned)ngroups);
   hipLaunchKernelGGL(k_cyl_solve, grid, dim3(64), 0, st, X0, X1, fac, grp, m, mp);
+  return hipGetLastError();
+}
+
+hipError_t launch_cyl_redge(const CylEdge *d, int nprob, char *ws, double *U, int64_t mp,
+                            int64_t ro, int64_t ro_main, int64_t mo, int64_t mo_main,
+                            int64_t mobar, int64_t ldc, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  if (mp > kCylEdgeK || mp % kCylEdgeB != 0 || mo - mo_main > kCylEdgeMax ||
+      ro - ro_main > kCylEdgeMax || mo_main > mo || ro_main > ro)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cyl_redge, dim3((unsigned)nprob), dim3(kCylEdgeThreads), 0, st, d, ws, U, mp,
+                     ro, ro_main, mo, mo_main, mobar, ldc);
   return hipGetLastError();
 }
 

@@ -39,8 +39,16 @@ struct CylPlan {
   fps::detail::DeviceBuf d_fac;               // [nk][8][mp][npad]
   fps::detail::DeviceBuf d_win[2], d_wout[2];  // z maps (mp x mp, mp x mop)
   fps::detail::DeviceBuf d_rin[4], d_rout[4];  // r maps per group (mp x mp, ro x mp)
+  fps::detail::DeviceBuf d_routT[4];           // transposed r output maps (mp x ro)
   fps::detail::DeviceBuf d_tin, d_tin_map, d_tout, d_tout_map;
   int tiles_in = 0, tiles_out = 0;
+  // output maps split into whole MFMA tiles and thin edges: leading extents
+  // of the z output (columns per parity) and the r output (rows per parity),
+  // the edge descriptors (d_tout_edge: fps::CylEdge per r output problem;
+  // d_zedge: the two z output problems at full size)
+  int64_t mo_main = 0, ro_main = 0;
+  fps::detail::DeviceBuf d_tout_edge, d_zedge;
+  int n_tout = 0;
   int64_t off_X0 = 0, off_X1 = 0, ws_bytes = 0;
   int64_t x0_elems = 0;
 };
@@ -335,7 +343,12 @@ fps_status cyl_plan_upload(fps_plan *pl) {
       }
       for (int64_t o = 0; o < c->ro; ++o) rout[(size_t)(o * mp + b)] = (double)t[(size_t)(2 * o + outp)];
     }
-    if ((st = upload(c->d_rin[g], rin)) != FPS_OK || (st = upload(c->d_rout[g], rout)) != FPS_OK) return st;
+    std::vector<double> routT((size_t)(mp * c->ro), 0.0);
+    for (int64_t o = 0; o < c->ro; ++o)
+      for (int64_t b = 0; b < mp; ++b) routT[(size_t)(b * c->ro + o)] = rout[(size_t)(o * mp + b)];
+    if ((st = upload(c->d_rin[g], rin)) != FPS_OK || (st = upload(c->d_rout[g], rout)) != FPS_OK ||
+        (st = upload(c->d_routT[g], routT)) != FPS_OK)
+      return st;
   }
   // banded LU factors per (|k|, z column)
   {
@@ -428,10 +441,49 @@ fps_status cyl_plan_upload(fps_plan *pl) {
       }
   }
   c->tiles_out = tiles;
+  // main table: whole tiles only; the edge kernel reads the full problems
+  c->mo_main = fps::gemm_main_extent(c->mo);
+  c->ro_main = fps::gemm_main_extent(c->ro);
+  c->n_tout = (int)tout.size();
+  std::vector<fps::GemmDesc> tout_main = tout;
+  tiles = 0;
+  for (fps::GemmDesc &e : tout_main) {
+    e.p.M = c->ro_main;
+    e.p.N = c->mo_main;
+    e.tile_start = tiles;
+    tiles += fps::gemm_tiles(e.p, &e.ntx);
+  }
+  c->tiles_out = tiles;
+  if (c->mo_main != c->mo || c->ro_main != c->ro) {
+    // one edge descriptor per r output problem, in the same order as tout
+    std::vector<fps::CylEdge> edges;
+    for (size_t sl = 0; sl < c->slot_idx.size(); ++sl)
+      for (int part = 0; part < 2; ++part)
+        for (int s = 0; s < 2; ++s) {
+          const fps::GemmDesc &e = tout[edges.size()];
+          edges.push_back(fps::CylEdge{(const double *)c->d_rout[c->slot_group[sl]].p,
+                                       (const double *)c->d_routT[c->slot_group[sl]].p,
+                                       (int64_t)(intptr_t)e.p.B, (int64_t)(intptr_t)e.p.C / 8});
+        }
+    if ((st = upload(c->d_tout_edge, edges)) != FPS_OK) return st;
+  }
+  {
+    // z output problems (workspace offsets: X1 -> X0) for the edge columns
+    std::vector<fps::GemmDesc> z;
+    const int64_t rows = c->nt * 2 * npad;
+    for (int s = 0; s < 2; ++s) {
+      const fps::GemmProb q{(const double *)(intptr_t)(c->off_X1 + s * mp * 8),
+                            (const double *)c->d_wout[s].p,
+                            (double *)(intptr_t)(c->off_X0 + s * c->mop * 8), rows, c->mo, mp, npad, 1,
+                            c->mop, 1, c->mobar, 1, 0, 0, 0, 0, 0, 0, 0, 0};
+      z.push_back(fps::GemmDesc{q, 1, 0, 1, 0, 0});
+    }
+    if (c->mo_main != c->mo && (st = upload(c->d_zedge, z)) != FPS_OK) return st;
+  }
   if ((st = upload(c->d_tin, tin)) != FPS_OK ||
       (st = upload(c->d_tin_map, fps::gemm_table_map(tin))) != FPS_OK ||
-      (st = upload(c->d_tout, tout)) != FPS_OK ||
-      (st = upload(c->d_tout_map, fps::gemm_table_map(tout))) != FPS_OK)
+      (st = upload(c->d_tout, tout_main)) != FPS_OK ||
+      (st = upload(c->d_tout_map, fps::gemm_table_map(tout_main))) != FPS_OK)
     return st;
   (void)nt;
   return FPS_OK;
@@ -467,14 +519,21 @@ fps_status cyl_solve(fps_plan *pl, const double *F, double *U, char *w, hipStrea
   {
     fps::GemmProb q[2];
     for (int s = 0; s < 2; ++s)
-      q[s] = fps::GemmProb{X1 + s * mp, (const double *)c->d_wout[s].p, X0 + s * c->mop, rows, c->mo,
-                           mp, npad, 1, c->mop, 1, c->mobar, 1, 0, 0, 0, 0, 0, 0, 0, 0};
+      q[s] = fps::GemmProb{X1 + s * mp, (const double *)c->d_wout[s].p, X0 + s * c->mop, rows,
+                           c->mo_main, mp, npad, 1, c->mop, 1, c->mobar, 1, 0, 0, 0, 0, 0, 0, 0, 0};
     FPS_HIP(fps::launch_gemm(q, 2, st));
+    if (c->mo_main != c->mo)  // the last z column of every row: one wavefront per row
+      FPS_HIP(fps::launch_gemm_edge_cols((const fps::GemmDesc *)c->d_zedge.p, 2, c->mo_main,
+                                         (int)std::min<int64_t>(2048, (rows + 15) / 16), w, nullptr,
+                                         st));
   }
   // 6. r output map into U (rows of the other parity stay zero)
   FPS_HIP(fps::launch_fill(U, nt * 2 * (n + 4) * (n + 2), 0.0, st));
   FPS_HIP(fps::launch_gemm_table((const fps::GemmDesc *)c->d_tout.p, (const int *)c->d_tout_map.p,
                                  c->tiles_out, w, (char *)U, st));
+  if (c->mo_main != c->mo || c->ro_main != c->ro)
+    FPS_HIP(fps::launch_cyl_redge((const fps::CylEdge *)c->d_tout_edge.p, c->n_tout, w, U, mp, c->ro,
+                                  c->ro_main, c->mo, c->mo_main, c->mobar, 2 * (n + 2), st));
   return FPS_OK;
 }
 

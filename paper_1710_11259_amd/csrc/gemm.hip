@@ -38,6 +38,7 @@ struct GemmBatch {
 };
 
 constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
+static_assert(GBM == kGemmTile && GBN == kGemmTile, "tile size shared with the edge split");
 
 // k-range [klo, khi) of tile (bx, by) after the triangular skips.
 __host__ __device__ inline void tile_krange(const GemmProb &g, int bx, int by, int64_t *klo_out,
@@ -201,7 +202,55 @@ __global__ __launch_bounds__(256, 2) void k_gemm_table(const GemmDesc *__restric
   gemm_tile(g, local % e.ntx, local / e.ntx, As, Bs);
 }
 
+// Columns tn.. of every row of a table problem: one wavefront per row,
+// lanes striding over k with coalesced loads of the row, then a butterfly
+// sum across the wavefront (fixed order, so the result is reproducible).
+// kRows rows per wavefront iteration keep their loads in flight together.
+__global__ __launch_bounds__(256) void k_gemm_edge_cols(const GemmDesc *__restrict__ d, int64_t tn,
+                                                        char *ws, char *out) {
+  constexpr int kRows = 4;
+  const GemmDesc &e = d[blockIdx.y];
+  const double *__restrict__ A = rebase(e.p.A, e.abase, ws, out);
+  const double *__restrict__ B = rebase(e.p.B, e.bbase, ws, out);
+  double *__restrict__ C = (double *)rebase(e.p.C, e.cbase, ws, out);
+  const int64_t M = e.p.M, N = e.p.N, K = e.p.K;
+  const int64_t nn = N < tn ? N : tn;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t i0 = wave * kRows; i0 < M; i0 += nwaves * kRows) {
+    for (int64_t j = nn; j < N; ++j) {
+      double acc[kRows];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) acc[r] = 0.0;
+      for (int64_t k = lane; k < K; k += 64) {
+        const double b = B[k * e.p.sbk + j * e.p.sbj];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+          const int64_t i = i0 + r < M ? i0 + r : M - 1;
+          acc[r] = fma(A[i * e.p.sai + k * e.p.sak], b, acc[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {
+        double v = acc[r];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0 && i0 + r < M) C[(i0 + r) * e.p.sci + j * e.p.scj] = v;
+      }
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_gemm_edge_cols(const GemmDesc *d, int nprob, int64_t tn, int nblk, char *ws,
+                                 char *out, hipStream_t st) {
+  if (nprob <= 0 || nblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemm_edge_cols, dim3((unsigned)nblk, (unsigned)nprob), dim3(256), 0, st, d,
+                     tn, ws, out);
+  return hipGetLastError();
+}
 
 bool gemm_operands_ok(const GemmProb &q) {
   return q.sak == 1 && q.sbj == 1 && q.K % GBK == 0 && !(q.sai & 1) && !(q.sbk & 1) &&

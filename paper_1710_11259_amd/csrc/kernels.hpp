@@ -198,6 +198,19 @@ struct CylSolveGroup {
 // rp, overwritten), X1 receives yhat (rows of parity wp).
 hipError_t launch_cyl_solve(double *X0, double *X1, const double *fac, const CylSolveGroup *grp,
                             int ngroups, int64_t m, int64_t mp, hipStream_t st);
+// Cylinder: the thin edges of the r output map of one (slot, part, z parity)
+// problem U_blk = Pr X0_blk (Pr ro x mp row-major, PrT its transpose, X0_blk
+// rows of stride mobar in the workspace at byte offset b_off, U_blk at
+// element offset c_off with row stride ldc and column stride 2): the rows
+// ro_main.. (every column) and the columns mo_main.. of the rows above
+// ro_main, at most 8 of each, mp <= 256.  One workgroup per problem.
+struct CylEdge {
+  const double *Pr, *PrT;
+  int64_t b_off, c_off;
+};
+hipError_t launch_cyl_redge(const CylEdge *d, int nprob, char *ws, double *U, int64_t mp,
+                            int64_t ro, int64_t ro_main, int64_t mo, int64_t mo_main,
+                            int64_t mobar, int64_t ldc, hipStream_t st);
 
 // U ((n+2) x (n+2) Chebyshev, natural order) += coefficients of u_bc.
 hipError_t launch_bc_lift_out(double *U, const double *bc, const double *scratch, int64_t n,
@@ -243,5 +256,20 @@ hipError_t launch_gemm_table(const GemmDesc *d, const int *tile_map, int ntiles,
 // Host: the tile map of a table, (problem, local tile) pairs for every tile
 // of every problem, longest k-range (after the triangular skips) first.
 std::vector<int> gemm_table_map(const std::vector<GemmDesc> &tab);
+// Output tile of the MFMA GEMMs (rows and columns).
+constexpr int kGemmTile = 128;
+// The columns tn.. (a thin edge past whole tiles, whose MFMA tiles would be
+// almost empty) of every row of each table problem, in plain FP64 FMAs:
+// one wavefront per row with coalesced loads along k and a fixed-order sum
+// across the wavefront; problems without triangular structure only; grid
+// (nblk workgroups of 4 wavefronts, 4 rows each per iteration; nprob).
+hipError_t launch_gemm_edge_cols(const GemmDesc *d, int nprob, int64_t tn, int nblk, char *ws,
+                                 char *out, hipStream_t st);
+// Leading extent of a dimension split off a thin edge: x less its last
+// partial tile when that tile holds at most 8 rows or columns, else x.
+inline int64_t gemm_main_extent(int64_t x) {
+  const int64_t r = x % kGemmTile;
+  return x > kGemmTile && r != 0 && r <= 8 ? x - r : x;
+}
 
 }  // namespace fps
