@@ -326,6 +326,56 @@ def bench_cylinder(fps, workloads, torch, n=256, n_theta=256, steps=5, check=Tru
     return res
 
 
+def bench_adjoint(fps, workloads, torch, tol, n=2048, batch=16, steps=3, check=True, tight=True):
+    """Differentiation form: one forward and one backward pass of the autograd
+    solve over a batch of 16 right-hand sides at n = 2048, for the quadratic
+    loss ||U(F) - U*||^2 (U* the solution for a fixed target right-hand side).
+    The backward pass is the adjoint solve (the same ADI sweeps between the
+    transposed coefficient maps); nothing is stored from the forward pass."""
+    import numpy as np
+    F_host, Fstar, _ = workloads.adjoint_case(n, batch, n_dirs=1)
+    p = fps.plan(n, tol=tol, tight=tight)
+    Ustar = fps.solve(p, torch.from_numpy(Fstar).cuda())
+    F = torch.from_numpy(F_host).cuda().requires_grad_(True)
+
+    def step():
+        F.grad = None
+        U = fps.solve_fn(F, p)
+        loss = ((U - Ustar) ** 2).sum()
+        loss.backward()
+        return U
+
+    step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        U = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    dof = float(batch) * n * n
+    # algorithmic sweep bytes: 40 B per dof per ADI iteration, forward and backward
+    sweep_bytes = 2.0 * batch * p.J * 40.0 * n * n
+    res = {"n": n, "batch": batch, "J": p.J, "ms_per_fwd_bwd": ms,
+           "dof_per_s": dof / (ms * 1e-3),
+           "sweep_bytes_algorithmic": sweep_bytes,
+           "sweep_bytes_rate_GBs": round(sweep_bytes / (ms * 1e-3) / 1e9, 1),
+           "method": "autograd Function over one fps_batch: forward fps_batch_solve, backward "
+                     "fps_batch_solve_adjoint (the sweeps of all problems in one launch per "
+                     "half-step)"}
+    if check:
+        from oracle import adjoint
+        Ub = (2.0 * (U[0] - Ustar)).detach().cpu().numpy()
+        ref = adjoint.vjp_square(Ub, np.asarray(p.shifts(), dtype=float))
+        got = F.grad[0].cpu().numpy()
+        res["rel_err_vs_oracle_vjp_problem0"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    del F, U, Ustar
+    torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -340,7 +390,7 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP32-refined, batched, cube, rectangle and cylinder timings")
     ap.add_argument("--only", choices=["fp32_refined", "batched", "cube", "cube_zeig",
-                                       "rect_dirichlet", "cylinder"],
+                                       "rect_dirichlet", "cylinder", "adjoint"],
                     help="run only this form and print its figures (profiling)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
@@ -358,7 +408,7 @@ def main() -> int:
 
     n = args.n
     dev = torch.device("cuda:0")
-    if args.only in ("batched", "cube", "cube_zeig", "rect_dirichlet", "cylinder"):
+    if args.only in ("batched", "cube", "cube_zeig", "rect_dirichlet", "cylinder", "adjoint"):
         if args.copy_calib_mib:
             calibration_copy(torch, dev, args.copy_calib_mib)
         tight = args.enclosure == "tight"
@@ -374,6 +424,9 @@ def main() -> int:
             res = bench_rect_dirichlet(fps, workloads, torch, args.tol, n=n,
                                        steps=max(1, args.steps), check=not args.no_check,
                                        tight=tight)
+        elif args.only == "adjoint":
+            res = bench_adjoint(fps, workloads, torch, args.tol, steps=max(1, args.steps),
+                                check=not args.no_check, tight=tight)
         else:
             res = bench_cube_zeig(fps, workloads, torch, args.tol, steps=max(1, args.steps),
                                   check=not args.no_check, tight=tight)
@@ -514,6 +567,8 @@ def main() -> int:
             forms["rect_dirichlet"] = bench_rect_dirichlet(fps, workloads, torch, args.tol, n=n,
                                                            check=not args.no_check, tight=tight)
             forms["cylinder"] = bench_cylinder(fps, workloads, torch, check=not args.no_check)
+            forms["adjoint"] = bench_adjoint(fps, workloads, torch, args.tol,
+                                             check=not args.no_check, tight=tight)
     if forms:
         out["forms"] = forms
 

@@ -303,6 +303,15 @@ fps_status fps_batch_info(const fps_batch *batch, int64_t *workspace_bytes, int6
                           int64_t *out_entries, int *max_J);
 fps_status fps_batch_solve(fps_batch *batch, const double *F_dev, double *U_dev, void *ws_dev,
                            void *stream);
+/* Adjoint (vector-Jacobian product) of fps_batch_solve, the batched form of
+ * fps_solve_adjoint: Ubar_dev in the batch's output layout, Fbar_dev
+ * (written) in its input layout.  Each problem's symmetric-shift ADI map is
+ * self-adjoint (App. D.5), so the adjoint runs the same batched sweeps
+ * between the transposed coefficient maps; every problem's result equals
+ * fps_solve_adjoint on that problem.  FP64 batches only (FPS_E_UNSUPPORTED
+ * otherwise); same workspace and stream rules as fps_batch_solve. */
+fps_status fps_batch_solve_adjoint(fps_batch *batch, const double *Ubar_dev, double *Fbar_dev,
+                                   void *ws_dev, void *stream);
 void fps_batch_destroy(fps_batch *batch);
 
 const char *fps_status_string(fps_status s);

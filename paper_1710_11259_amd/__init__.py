@@ -18,7 +18,8 @@ import os
 __all__ = ["lib", "Plan", "plan", "plan_cylinder", "cylinder_mode_bands", "solve",
            "solve_dirichlet", "solve_adjoint", "solve_fn",
            "adi_native",
-           "adi_shifts", "Batch", "batch", "batch_solve", "BatchGraph", "FpsError", "LIB_PATH"]
+           "adi_shifts", "Batch", "batch", "batch_solve", "batch_solve_adjoint", "BatchGraph",
+           "FpsError", "LIB_PATH"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfps.so")
@@ -77,6 +78,7 @@ def lib() -> ctypes.CDLL:
     L.fps_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                  ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int)]
     L.fps_batch_solve.argtypes = [vp, vp, vp, vp, vp]
+    L.fps_batch_solve_adjoint.argtypes = [vp, vp, vp, vp, vp]
     L.fps_batch_destroy.argtypes = [vp]
     L.fps_batch_destroy.restype = None
     L.fps_plan_set_sweep_timing.argtypes = [vp, ctypes.c_int]
@@ -95,7 +97,8 @@ def lib() -> ctypes.CDLL:
                  "fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_plan_refinement",
                  "fps_plan_inner_counts", "fps_plan_slice_counts",
                  "fps_adi_shifts", "fps_solve", "fps_solve_adjoint", "fps_adi_native",
-                 "fps_batch_create", "fps_batch_info", "fps_batch_solve"):
+                 "fps_batch_create", "fps_batch_info", "fps_batch_solve",
+                 "fps_batch_solve_adjoint"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -311,30 +314,54 @@ def solve_adjoint(p: Plan, Ubar, out=None, ws=None):
 def _solve_fn_class():
     import torch
 
+    def batch_of(plan, count):
+        # a batch of `count` problems of the plan's size (square FP64 plans),
+        # built once per count and kept on the plan
+        if (plan.dim != 2 or plan.box is not None or plan.dirichlet or plan.n_theta is not None
+                or plan.precision != "fp64" or count < 2):
+            return None
+        cache = plan.__dict__.setdefault("_batches", {})
+        if count not in cache:
+            cache[count] = Batch([plan.n] * count, tol=plan.tol, out=plan.out, tight=plan.tight)
+        return cache[count]
+
     class SolveFn(torch.autograd.Function):
         """Differentiable square solve.  forward: U = solve(F) for F of shape
         (n, n) or (batch, n, n); backward: the adjoint solve (same ADI sweeps
         between transposed coefficient maps), nothing stored from the forward
-        pass because the map is linear in F."""
+        pass because the map is linear in F.  A batch of square FP64 problems
+        runs as one fps_batch (sweeps of all problems in one launch per
+        half-step, forward and backward); its results equal the per-problem
+        solves."""
 
         @staticmethod
         def forward(ctx, F, plan):
             ctx.plan = plan
-            ws = workspace(plan, F.device)
             Fc = F.contiguous()
             if Fc.dim() == 2:
-                return solve(plan, Fc, ws=ws)
-            return torch.stack([solve(plan, Fc[b], ws=ws) for b in range(Fc.shape[0])])
+                return solve(plan, Fc, ws=workspace(plan, F.device))
+            b = batch_of(plan, Fc.shape[0])
+            if b is not None:
+                e = plan.n if plan.out == "native" else plan.n + 2
+                ws = torch.empty(max(b.workspace_bytes, 256), dtype=torch.uint8, device=F.device)
+                return batch_solve(b, Fc.reshape(-1), ws=ws).view(Fc.shape[0], e, e)
+            ws = workspace(plan, F.device)
+            return torch.stack([solve(plan, Fc[i], ws=ws) for i in range(Fc.shape[0])])
 
         @staticmethod
         def backward(ctx, Ubar):
             plan = ctx.plan
-            ws = workspace(plan, Ubar.device)
             Uc = Ubar.contiguous()
             if Uc.dim() == 2:
-                return solve_adjoint(plan, Uc, ws=ws), None
-            return torch.stack([solve_adjoint(plan, Uc[b], ws=ws)
-                                for b in range(Uc.shape[0])]), None
+                return solve_adjoint(plan, Uc, ws=workspace(plan, Ubar.device)), None
+            b = batch_of(plan, Uc.shape[0])
+            if b is not None:
+                ws = torch.empty(max(b.workspace_bytes, 256), dtype=torch.uint8, device=Ubar.device)
+                Fb = batch_solve_adjoint(b, Uc.reshape(-1), ws=ws)
+                return Fb.view(Uc.shape[0], plan.n, plan.n), None
+            ws = workspace(plan, Ubar.device)
+            return torch.stack([solve_adjoint(plan, Uc[i], ws=ws)
+                                for i in range(Uc.shape[0])]), None
 
     return SolveFn
 
@@ -444,6 +471,27 @@ def batch_solve(b: Batch, F, out=None, ws=None):
     _check(lib().fps_batch_solve(b.handle, ctypes.c_void_p(F.data_ptr()),
                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                  _stream_ptr(torch, F.device)))
+    return out
+
+
+def batch_solve_adjoint(b: Batch, Ubar, out=None, ws=None):
+    """Packed Fbar (the VJP of batch_solve) for the packed float64 CUDA
+    tensor Ubar in the batch's output layout."""
+    import torch
+    if Ubar.dtype != torch.float64 or not Ubar.is_cuda or not Ubar.is_contiguous():
+        raise ValueError("Ubar must be a contiguous float64 tensor on the GPU")
+    if Ubar.numel() != b.out_entries:
+        raise ValueError(f"Ubar must hold {b.out_entries} entries")
+    if out is None:
+        out = torch.empty(b.in_entries, dtype=torch.float64, device=Ubar.device)
+    if out.numel() != b.in_entries or not out.is_contiguous():
+        raise ValueError(f"out must be contiguous with {b.in_entries} entries")
+    if ws is None:
+        ws = torch.empty(max(b.workspace_bytes, 256), dtype=torch.uint8, device=Ubar.device)
+    _check(lib().fps_batch_solve_adjoint(b.handle, ctypes.c_void_p(Ubar.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(ws.data_ptr()),
+                                         _stream_ptr(torch, Ubar.device)))
     return out
 
 

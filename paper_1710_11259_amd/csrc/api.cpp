@@ -695,20 +695,21 @@ fps_status fps_adi_native(fps_plan *pl, const double *G, double *Y, void *ws, vo
   return FPS_OK;
 }
 
-fps_status fps_solve_adjoint(fps_plan *pl, const double *Ubar, double *Fbar, void *ws,
-                             void *stream) {
-  fps_status s = check_solve_args(pl, Ubar, Fbar, ws);
-  if (s != FPS_OK) return s;
-  if (pl->dim != 2 || pl->prec != FPS_FP64)
-    return fail(FPS_E_UNSUPPORTED, "adjoint: square FP64 plans only");
-  hipStream_t st = (hipStream_t)stream;
-  char *w = (char *)ws;
+}  // extern "C"
+
+namespace fps {
+namespace detail {
+
+// The adjoint's steps around the ADI map (Frobenius transposes of the input
+// and output maps, Sec. 3.4 and Table 1 read backwards).
+// adjoint_in: Ybar = P^T Ubar P (Chebyshev output) or S^-1 Xbar S^-1
+// (native) into G, and its transpose into GT.
+fps_status adjoint_in(const fps_plan *pl, const double *Ubar, char *w, hipStream_t st) {
   const fps::Layout &L = pl->L;
   const int64_t n = L.n, npad = L.npad, N = n + 2;
   double *G = (double *)(w + pl->off_G);
   double *GT = (double *)(w + pl->off_GT);
   double *Tb = (double *)(w + pl->off_O0);  // O0 and O1 (contiguous) as temporaries
-  // 1. Ybar = P^T Ubar P (Chebyshev output) or S^-1 Xbar S^-1 (native), in G.
   if (pl->out_basis == FPS_OUT_NATIVE) {
     FPS_HIP(fps::launch_permute_in(Ubar, G, n, npad, L.mp[0], st, (const double *)pl->d_sinv.p));
   } else {
@@ -740,11 +741,17 @@ fps_status fps_solve_adjoint(fps_plan *pl, const double *Ubar, double *Fbar, voi
     FPS_HIP(fps::launch_gemm(g1, cnt, st));
     FPS_HIP(fps::launch_gemm(g2, cnt, st));
   }
-  // 2. The same J-step ADI map (self-adjoint for symmetric shifts).
   FPS_HIP(fps::launch_transpose(G, GT, npad, st));
-  double *Yb = nullptr;
-  if ((s = solve_symmetric(pl, w, st, &Yb)) != FPS_OK) return s;  // Gbar, in G
-  // 3. Fbar = R^T S^-1 Gbar S^-1 R, blockwise Rs_s^T Gbar_st Rs_t into the strided view of Fbar.
+  return FPS_OK;
+}
+
+// adjoint_out: Fbar = R^T S^-1 Gbar S^-1 R, blockwise Rs_s^T Gbar_st Rs_t into
+// the strided view of Fbar (Gbar: the ADI output, parity-blocked).
+fps_status adjoint_out(const fps_plan *pl, const double *Yb, double *Fbar, char *w,
+                       hipStream_t st) {
+  const fps::Layout &L = pl->L;
+  const int64_t n = L.n, npad = L.npad;
+  double *Tb = (double *)(w + pl->off_O0);
   fps::GemmProb g1[4], g2[4];
   int cnt = 0;
   int64_t toff = 0;
@@ -765,6 +772,25 @@ fps_status fps_solve_adjoint(fps_plan *pl, const double *Ubar, double *Fbar, voi
   FPS_HIP(fps::launch_gemm(g1, cnt, st));
   FPS_HIP(fps::launch_gemm(g2, cnt, st));
   return FPS_OK;
+}
+
+}  // namespace detail
+}  // namespace fps
+
+extern "C" {
+
+fps_status fps_solve_adjoint(fps_plan *pl, const double *Ubar, double *Fbar, void *ws,
+                             void *stream) {
+  fps_status s = check_solve_args(pl, Ubar, Fbar, ws);
+  if (s != FPS_OK) return s;
+  if (pl->dim != 2 || pl->prec != FPS_FP64)
+    return fail(FPS_E_UNSUPPORTED, "adjoint: square FP64 plans only");
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  if ((s = fps::detail::adjoint_in(pl, Ubar, w, st)) != FPS_OK) return s;
+  double *Yb = nullptr;
+  if ((s = solve_symmetric(pl, w, st, &Yb)) != FPS_OK) return s;  // Gbar, in G
+  return fps::detail::adjoint_out(pl, Yb, Fbar, w, st);
 }
 
 fps_status fps_plan_set_sweep_timing(fps_plan *pl, int capacity) {

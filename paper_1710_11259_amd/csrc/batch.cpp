@@ -380,6 +380,38 @@ fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, 
   return FPS_OK;
 }
 
+fps_status fps_batch_solve_adjoint(fps_batch *bt, const double *Ubar, double *Fbar, void *ws,
+                                   void *stream) {
+  if (!valid_batch(bt)) return fail(FPS_E_STATE, "invalid or destroyed batch");
+  if (!bt->on_device) return fail(FPS_E_STATE, "batch was created host-only");
+  if (!Ubar || !Fbar || !ws) return fail(FPS_E_ARG, "null pointer argument");
+  if (((uintptr_t)ws) % 256 != 0) return fail(FPS_E_ARG, "workspace must be 256-byte aligned");
+  if (bt->prec != FPS_FP64) return fail(FPS_E_UNSUPPORTED, "batched adjoint: FP64 batches only");
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  const int C = bt->count;
+  fps_status s;
+  // Ybar of every problem into its G (and G^T) region, then the same ADI
+  // map as the forward solve (self-adjoint for symmetric shifts), batched.
+  for (int b = 0; b < C; ++b)
+    if ((s = fps::detail::adjoint_in(bt->plan_of(b), Ubar + bt->u_off[b], w + bt->ws_off[b], st)) !=
+        FPS_OK)
+      return s;
+  if ((s = run_adi_batch(bt, w, st)) != FPS_OK) return s;
+  for (int b = 0; b < C; ++b) {
+    const fps_plan *pl = bt->plan_of(b);
+    const fps::Layout &L = pl->L;
+    char *wb = w + bt->ws_off[b];
+    double *Gb = (double *)(wb + pl->off_G);
+    FPS_HIP(fps::launch_finalize<double>((const double *)(wb + pl->off_O1),
+                                         (const double *)(wb + pl->off_ab),
+                                         pl->tab_dev(pl->shifts.J - 1), Gb, 0, nullptr, L.n,
+                                         L.npad, L.mp[0], L.mstride, L.ncmax, st));
+    if ((s = fps::detail::adjoint_out(pl, Gb, Fbar + bt->f_off[b], wb, st)) != FPS_OK) return s;
+  }
+  return FPS_OK;
+}
+
 void fps_batch_destroy(fps_batch *bt) {
   if (!valid_batch(bt)) return;
   bt->magic = 0;

@@ -179,6 +179,12 @@ int out_gemms(const fps_plan *pl, const double *Y, double *U, char *ws, fps::Gem
 fps_status out_transform(fps_plan *pl, const double *Y, double *U, char *ws, hipStream_t st);
 // Y of A~ Y + Y A~ = G for G in the workspace (FP64 or refined).
 fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout);
+// The adjoint's maps around the ADI (transposes of the input and output
+// maps): adjoint_in forms Ybar from Ubar into the G region (and G^T);
+// adjoint_out forms Fbar from the ADI output Gbar.  FP64 plans.
+fps_status adjoint_in(const fps_plan *pl, const double *Ubar, char *w, hipStream_t st);
+fps_status adjoint_out(const fps_plan *pl, const double *Gbar, double *Fbar, char *w,
+                       hipStream_t st);
 // Cube: host tables and workspace layout (after the common fields are set),
 // their upload, and the solve.
 fps_status cube_plan_build(fps_plan *pl);

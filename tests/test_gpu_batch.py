@@ -46,6 +46,25 @@ def test_batch_equals_single_solves_bitwise(out):
             assert err <= 1e-12, f"n={n}: rel err {err:.3e}"
 
 
+@pytest.mark.parametrize("out", ["cheb", "native"])
+def test_batch_adjoint_equals_single_adjoints_bitwise(out):
+    # the batched adjoint (fps_batch_solve_adjoint): per-problem transposed
+    # maps around the batched ADI, so each problem equals fps_solve_adjoint
+    rng = np.random.default_rng(11)
+    Ubs = [rng.standard_normal((n + 2, n + 2) if out == "cheb" else (n, n)) for n in MIXED]
+    b = fps.batch(MIXED, tol=1e-13, out=out)
+    print(f"batch adjoint {out}: {len(MIXED)} problems", flush=True)
+    Ub_packed = torch.cat([torch.from_numpy(u).reshape(-1) for u in Ubs]).cuda()
+    Fb = fps.batch_solve_adjoint(b, Ub_packed)
+    torch.cuda.synchronize()
+    Fb = Fb.cpu().numpy()
+    for i, (n, Ub) in enumerate(zip(MIXED, Ubs)):
+        p = fps.plan(n, tol=1e-13, out=out)
+        ref = fps.solve_adjoint(p, torch.from_numpy(Ub).cuda()).cpu().numpy()
+        got = Fb[b.in_offsets[i]:b.in_offsets[i + 1]].reshape(n, n)
+        assert np.array_equal(got, ref), f"n={n}: batched adjoint differs from the single adjoint"
+
+
 def test_batch_refined_matches_oracle():
     ns = [1, 5, 64, 129, 544, 1024, 32]
     Fs = _rhs(ns, seed=8)

@@ -141,6 +141,8 @@ def test_batch_queries_and_errors():
     assert L.fps_batch_solve(None, None, None, None, None) == fps.FPS_E_STATE
     hb = fps.batch([8], host_only=True)
     assert L.fps_batch_solve(hb.handle, None, None, None, None) == fps.FPS_E_STATE
+    assert L.fps_batch_solve_adjoint(None, None, None, None, None) == fps.FPS_E_STATE
+    assert L.fps_batch_solve_adjoint(hb.handle, None, None, None, None) == fps.FPS_E_STATE
 
 
 # --- host planner internals through a g++-built shim -----------------------
