@@ -702,57 +702,45 @@ namespace detail {
 
 // The adjoint's steps around the ADI map (Frobenius transposes of the input
 // and output maps, Sec. 3.4 and Table 1 read backwards).
-// adjoint_in: Ybar = P^T Ubar P (Chebyshev output) or S^-1 Xbar S^-1
-// (native) into G, and its transpose into GT.
-fps_status adjoint_in(const fps_plan *pl, const double *Ubar, char *w, hipStream_t st) {
+//
+// GEMMs of the adjoint's input map (Chebyshev output basis): Ybar_st =
+// P_s^T Ubar_st P_t per parity block, from Ubar in the parity-blocked
+// layout (X region, mobar x mobar) through temporaries in O0/O1, into G.
+int adj_in_gemms(const fps_plan *pl, char *w, fps::GemmProb *g1, fps::GemmProb *g2) {
   const fps::Layout &L = pl->L;
-  const int64_t n = L.n, npad = L.npad, N = n + 2;
+  const int64_t npad = L.npad;
+  const int64_t mo0 = pl->mop[0], mobar = pl->mop[0] + pl->mop[1];
+  const double *Up = (const double *)(w + pl->off_X);
   double *G = (double *)(w + pl->off_G);
-  double *GT = (double *)(w + pl->off_GT);
-  double *Tb = (double *)(w + pl->off_O0);  // O0 and O1 (contiguous) as temporaries
-  if (pl->out_basis == FPS_OUT_NATIVE) {
-    FPS_HIP(fps::launch_permute_in(Ubar, G, n, npad, L.mp[0], st, (const double *)pl->d_sinv.p));
-  } else {
-    const int64_t mo0 = pl->mop[0], mobar = pl->mop[0] + pl->mop[1];
-    if (npad * mobar * 8 > pl->off_lv - pl->off_O0)
-      return fail(FPS_E_STATE, "internal: adjoint temporaries exceed workspace");
-    double *Up = (double *)(w + pl->off_X);  // Ubar in the parity-blocked layout, mobar x mobar
-    double *Tt = Tb;                          // temporaries mop_s x mp_t
-    FPS_HIP(fps::launch_permute_in(Ubar, Up, N, mobar, mo0, st));
-    fps::GemmProb g1[4], g2[4];
-    int cnt = 0;
-    int64_t toff = 0;
-    for (int s2 = 0; s2 < 2; ++s2)
-      for (int t = 0; t < 2; ++t) {
-        const int64_t ms = L.mp[s2], mt = L.mp[t], mos = pl->mop[s2], mot = pl->mop[t];
-        if (L.m[s2] == 0 || L.m[t] == 0) continue;
-        double *Tst = Tt + toff;
-        toff += mos * mt;
-        // T_st = Ubar_st P_t; B(k, j) = P_t[k][j] = 0 for k > j + 1.
-        g1[cnt] = fps::GemmProb{Up + (s2 * mo0) * mobar + t * mo0, (const double *)pl->d_PA[t].p,
-                                Tst, mos, mt, mot, mobar, 1, mt, 1, mt, 1, 0, 0, 0, 0, 0, 0, 1, 1};
-        // Ybar_st = P_s^T T_st; A(i, k) = P_s[k][i] = 0 for k > i + 1.
-        g2[cnt] = fps::GemmProb{(const double *)pl->d_PB[s2].p, Tst,
-                                G + (s2 * L.mp[0]) * npad + t * L.mp[0], ms, mt, mos, mos, 1, mt, 1,
-                                npad, 1, 0, 0, 0, 0, 1, 1, 0, 0};
-        ++cnt;
-      }
-    FPS_HIP(fps::launch_fill(G, npad * npad, 0.0, st));
-    FPS_HIP(fps::launch_gemm(g1, cnt, st));
-    FPS_HIP(fps::launch_gemm(g2, cnt, st));
-  }
-  FPS_HIP(fps::launch_transpose(G, GT, npad, st));
-  return FPS_OK;
+  double *Tt = (double *)(w + pl->off_O0);  // temporaries mop_s x mp_t
+  int cnt = 0;
+  int64_t toff = 0;
+  for (int s2 = 0; s2 < 2; ++s2)
+    for (int t = 0; t < 2; ++t) {
+      const int64_t ms = L.mp[s2], mt = L.mp[t], mos = pl->mop[s2], mot = pl->mop[t];
+      if (L.m[s2] == 0 || L.m[t] == 0) continue;
+      double *Tst = Tt + toff;
+      toff += mos * mt;
+      // T_st = Ubar_st P_t; B(k, j) = P_t[k][j] = 0 for k > j + 1.
+      g1[cnt] = fps::GemmProb{Up + (s2 * mo0) * mobar + t * mo0, (const double *)pl->d_PA[t].p,
+                              Tst, mos, mt, mot, mobar, 1, mt, 1, mt, 1, 0, 0, 0, 0, 0, 0, 1, 1};
+      // Ybar_st = P_s^T T_st; A(i, k) = P_s[k][i] = 0 for k > i + 1.
+      g2[cnt] = fps::GemmProb{(const double *)pl->d_PB[s2].p, Tst,
+                              G + (s2 * L.mp[0]) * npad + t * L.mp[0], ms, mt, mos, mos, 1, mt, 1,
+                              npad, 1, 0, 0, 0, 0, 1, 1, 0, 0};
+      ++cnt;
+    }
+  return cnt;
 }
 
-// adjoint_out: Fbar = R^T S^-1 Gbar S^-1 R, blockwise Rs_s^T Gbar_st Rs_t into
-// the strided view of Fbar (Gbar: the ADI output, parity-blocked).
-fps_status adjoint_out(const fps_plan *pl, const double *Yb, double *Fbar, char *w,
-                       hipStream_t st) {
+// GEMMs of the adjoint's output map: Fbar = R^T S^-1 Gbar S^-1 R, blockwise
+// Rs_s^T Gbar_st Rs_t into the strided view of Fbar (Gbar: the ADI output,
+// parity-blocked), through temporaries in O0/O1.
+int adj_out_gemms(const fps_plan *pl, const double *Yb, double *Fbar, char *w, fps::GemmProb *g1,
+                  fps::GemmProb *g2) {
   const fps::Layout &L = pl->L;
   const int64_t n = L.n, npad = L.npad;
   double *Tb = (double *)(w + pl->off_O0);
-  fps::GemmProb g1[4], g2[4];
   int cnt = 0;
   int64_t toff = 0;
   for (int s2 = 0; s2 < 2; ++s2)
@@ -769,6 +757,48 @@ fps_status adjoint_out(const fps_plan *pl, const double *Yb, double *Fbar, char 
                               L.m[t], ms, ms, 1, mt, 1, 2 * n, 2, 0, 0, 0, 0, 1, 0, 0, 0};
       ++cnt;
     }
+  return cnt;
+}
+
+// The adjoint's input map up to its GEMMs: Ubar permuted into the
+// parity-blocked layout and G cleared (Chebyshev output), or Ybar = S^-1
+// Xbar S^-1 straight into G (native output).
+fps_status adjoint_in_pre(const fps_plan *pl, const double *Ubar, char *w, hipStream_t st) {
+  const fps::Layout &L = pl->L;
+  const int64_t n = L.n, npad = L.npad, N = n + 2;
+  double *G = (double *)(w + pl->off_G);
+  if (pl->out_basis == FPS_OUT_NATIVE) {
+    FPS_HIP(fps::launch_permute_in(Ubar, G, n, npad, L.mp[0], st, (const double *)pl->d_sinv.p));
+    return FPS_OK;
+  }
+  const int64_t mo0 = pl->mop[0], mobar = pl->mop[0] + pl->mop[1];
+  if (npad * mobar * 8 > pl->off_lv - pl->off_O0)
+    return fail(FPS_E_STATE, "internal: adjoint temporaries exceed workspace");
+  FPS_HIP(fps::launch_permute_in(Ubar, (double *)(w + pl->off_X), N, mobar, mo0, st));
+  FPS_HIP(fps::launch_fill(G, npad * npad, 0.0, st));
+  return FPS_OK;
+}
+
+// adjoint_in: Ybar into G (and its transpose into GT) from Ubar.
+fps_status adjoint_in(const fps_plan *pl, const double *Ubar, char *w, hipStream_t st) {
+  fps_status s;
+  if ((s = adjoint_in_pre(pl, Ubar, w, st)) != FPS_OK) return s;
+  if (pl->out_basis != FPS_OUT_NATIVE) {
+    fps::GemmProb g1[4], g2[4];
+    const int cnt = adj_in_gemms(pl, w, g1, g2);
+    FPS_HIP(fps::launch_gemm(g1, cnt, st));
+    FPS_HIP(fps::launch_gemm(g2, cnt, st));
+  }
+  FPS_HIP(fps::launch_transpose((const double *)(w + pl->off_G), (double *)(w + pl->off_GT),
+                                pl->L.npad, st));
+  return FPS_OK;
+}
+
+// adjoint_out: Fbar from the ADI output Gbar.
+fps_status adjoint_out(const fps_plan *pl, const double *Yb, double *Fbar, char *w,
+                       hipStream_t st) {
+  fps::GemmProb g1[4], g2[4];
+  const int cnt = adj_out_gemms(pl, Yb, Fbar, w, g1, g2);
   FPS_HIP(fps::launch_gemm(g1, cnt, st));
   FPS_HIP(fps::launch_gemm(g2, cnt, st));
   return FPS_OK;

@@ -37,9 +37,10 @@ struct fps_batch {
   std::vector<int> sw_start, rd_start;  // workgroup prefix sums over the sorted problems
   int64_t ncmax_max = 0;
   DeviceBuf d_sw, d_rd, d_swmap, d_rdmap;
-  // coefficient-map GEMMs of all problems: input map g1, g2; output map g1, g2
-  DeviceBuf d_gd[4], d_gmap[4];
-  int gtiles[4] = {0, 0, 0, 0};
+  // coefficient-map GEMMs of all problems: input map g1, g2; output map g1,
+  // g2; (FP64 batches) the adjoint's input map g1, g2 and output map g1, g2
+  DeviceBuf d_gd[8], d_gmap[8];
+  int gtiles[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   ~fps_batch() {
     for (fps_plan *p : sub) fps_plan_destroy(p);
@@ -61,20 +62,31 @@ P off_ptr(int64_t off) {
 // synthetic base pointers (the problem's workspace offset, its U offset in
 // bytes), so every workspace or output operand comes out as an offset.
 fps_status build_gemm_tables(fps_batch *bt) {
-  std::vector<fps::GemmDesc> tab[4];
+  std::vector<fps::GemmDesc> tab[8];
   const bool refined = bt->prec == FPS_FP32_REFINED;
   for (int b = 0; b < bt->count; ++b) {
     const fps_plan *pl = bt->plan_of(b);
     char *wsyn = (char *)(intptr_t)bt->ws_off[b];
-    fps::GemmProb g[4][4];
+    fps::GemmProb g[8][4];
     const int c_in = rhs_gemms(pl, wsyn, g[0], g[1]);
     const double *Ysyn = (const double *)(wsyn + (refined ? pl->off_GT : pl->off_G));
     double *Usyn = (double *)(intptr_t)(bt->u_off[b] * (int64_t)sizeof(double));
-    const int c_out = bt->out_basis == FPS_OUT_CHEB ? out_gemms(pl, Ysyn, Usyn, wsyn, g[2], g[3]) : 0;
+    const bool cheb = bt->out_basis == FPS_OUT_CHEB;
+    const int c_out = cheb ? out_gemms(pl, Ysyn, Usyn, wsyn, g[2], g[3]) : 0;
+    // adjoint (FP64): Ubar -> Ybar (Chebyshev output), Gbar (in G) -> Fbar,
+    // Fbar as an offset into the input layout
+    int c_ain = 0, c_aout = 0;
+    if (!refined) {
+      c_ain = cheb ? adj_in_gemms(pl, wsyn, g[4], g[5]) : 0;
+      double *Fsyn = (double *)(intptr_t)(bt->f_off[b] * (int64_t)sizeof(double));
+      c_aout = adj_out_gemms(pl, (const double *)(wsyn + pl->off_G), Fsyn, wsyn, g[6], g[7]);
+    }
     // base ids (A, B, C): ws-relative 1, absolute 0, output-relative 2
-    static const int ids[4][3] = {{1, 0, 1}, {0, 1, 1}, {1, 0, 1}, {0, 1, 2}};
-    for (int t = 0; t < 4; ++t) {
-      const int cnt = t < 2 ? c_in : c_out;
+    static const int ids[8][3] = {{1, 0, 1}, {0, 1, 1}, {1, 0, 1}, {0, 1, 2},
+                                  {1, 0, 1}, {0, 1, 1}, {1, 0, 1}, {0, 1, 2}};
+    const int counts[8] = {c_in, c_in, c_out, c_out, c_ain, c_ain, c_aout, c_aout};
+    for (int t = 0; t < 8; ++t) {
+      const int cnt = counts[t];
       for (int i = 0; i < cnt; ++i) {
         if (!fps::gemm_operands_ok(g[t][i]))
           return fail(FPS_E_STATE, "internal: batched GEMM operand layout");
@@ -84,7 +96,8 @@ fps_status build_gemm_tables(fps_batch *bt) {
       }
     }
   }
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < 8; ++t) {
+    if (tab[t].empty()) continue;
     const std::vector<int> map = fps::gemm_table_map(tab[t]);
     fps_status s;
     if ((s = upload(bt->d_gd[t], tab[t])) != FPS_OK || (s = upload(bt->d_gmap[t], map)) != FPS_OK)
@@ -391,24 +404,39 @@ fps_status fps_batch_solve_adjoint(fps_batch *bt, const double *Ubar, double *Fb
   char *w = (char *)ws;
   const int C = bt->count;
   fps_status s;
-  // Ybar of every problem into its G (and G^T) region, then the same ADI
-  // map as the forward solve (self-adjoint for symmetric shifts), batched.
+  auto gemm = [&](int t, char *out) {
+    return fps::launch_gemm_table((const fps::GemmDesc *)bt->d_gd[t].p,
+                                  (const int *)bt->d_gmap[t].p, bt->gtiles[t], w, out, st);
+  };
+  // Ybar of every problem into its G (and G^T) region: the permutations, the
+  // input-map GEMMs of all problems (two table launches), the transposes.
   for (int b = 0; b < C; ++b)
-    if ((s = fps::detail::adjoint_in(bt->plan_of(b), Ubar + bt->u_off[b], w + bt->ws_off[b], st)) !=
-        FPS_OK)
+    if ((s = fps::detail::adjoint_in_pre(bt->plan_of(b), Ubar + bt->u_off[b], w + bt->ws_off[b],
+                                         st)) != FPS_OK)
       return s;
+  FPS_HIP(gemm(4, nullptr));
+  FPS_HIP(gemm(5, nullptr));
+  for (int b = 0; b < C; ++b) {
+    const fps_plan *pl = bt->plan_of(b);
+    char *wb = w + bt->ws_off[b];
+    FPS_HIP(fps::launch_transpose((const double *)(wb + pl->off_G), (double *)(wb + pl->off_GT),
+                                  pl->L.npad, st));
+  }
+  // The same ADI map as the forward solve (self-adjoint for symmetric
+  // shifts), batched; Gbar lands in each problem's G region.
   if ((s = run_adi_batch(bt, w, st)) != FPS_OK) return s;
   for (int b = 0; b < C; ++b) {
     const fps_plan *pl = bt->plan_of(b);
     const fps::Layout &L = pl->L;
     char *wb = w + bt->ws_off[b];
-    double *Gb = (double *)(wb + pl->off_G);
     FPS_HIP(fps::launch_finalize<double>((const double *)(wb + pl->off_O1),
                                          (const double *)(wb + pl->off_ab),
-                                         pl->tab_dev(pl->shifts.J - 1), Gb, 0, nullptr, L.n,
-                                         L.npad, L.mp[0], L.mstride, L.ncmax, st));
-    if ((s = fps::detail::adjoint_out(pl, Gb, Fbar + bt->f_off[b], wb, st)) != FPS_OK) return s;
+                                         pl->tab_dev(pl->shifts.J - 1), (double *)(wb + pl->off_G), 0,
+                                         nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
   }
+  // Fbar of every problem: the output-map GEMMs (two table launches).
+  FPS_HIP(gemm(6, (char *)Fbar));
+  FPS_HIP(gemm(7, (char *)Fbar));
   return FPS_OK;
 }
 

@@ -183,6 +183,14 @@ fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout)
 // maps): adjoint_in forms Ybar from Ubar into the G region (and G^T);
 // adjoint_out forms Fbar from the ADI output Gbar.  FP64 plans.
 fps_status adjoint_in(const fps_plan *pl, const double *Ubar, char *w, hipStream_t st);
+// Pieces of the two for the batched adjoint: the input map up to its GEMMs
+// (permutation, clear of G; native: the whole map), and the GEMMs of the
+// input map (Chebyshev output only) and of the output map, built like
+// rhs_gemms / out_gemms.
+fps_status adjoint_in_pre(const fps_plan *pl, const double *Ubar, char *w, hipStream_t st);
+int adj_in_gemms(const fps_plan *pl, char *w, fps::GemmProb *g1, fps::GemmProb *g2);
+int adj_out_gemms(const fps_plan *pl, const double *Yb, double *Fbar, char *w, fps::GemmProb *g1,
+                  fps::GemmProb *g2);
 fps_status adjoint_out(const fps_plan *pl, const double *Gbar, double *Fbar, char *w,
                        hipStream_t st);
 // Cube: host tables and workspace layout (after the common fields are set),
