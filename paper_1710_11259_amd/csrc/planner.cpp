@@ -164,6 +164,10 @@ namespace {
 int64_t sturm_count(int64_t m, int s, long double x) {
   int64_t cnt = 0;
   long double q = 1.0L;
+  // a zero pivot counts as negative (x just above an eigenvalue): replaced by
+  // a tiny negative value, 2^-13000 (about 1e-3913, far below any pivot but
+  // with e^2 / q still finite in extended precision)
+  const long double tiny = std::ldexp(1.0L, -13000);
   for (int64_t k = 0; k < m; ++k) {
     const long double d = (long double)atilde_diag(2 * k + s) - x;
     if (k == 0) {
@@ -172,7 +176,7 @@ int64_t sturm_count(int64_t m, int s, long double x) {
       const long double e = atilde_off(2 * (k - 1) + s);
       q = d - e * e / q;
     }
-    if (q == 0.0L) q = -1e-4000L;  // a zero pivot counts as negative (x just above an eigenvalue)
+    if (q == 0.0L) q = -tiny;
     if (q < 0.0L) ++cnt;
   }
   return cnt;
