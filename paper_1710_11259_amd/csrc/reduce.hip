@@ -19,138 +19,225 @@ namespace {
 // (per-chunk coefficients ctab of the producing pass's shift), written as
 // ab[s][c][r] = scale (cf[c], cb[c]).
 //
-// Sequential form (one thread per chain; used when a chain has more chunks
-// than the lanes given to it).  cf is parked in ab between the two sweeps
-// over the chunks (each thread rereads only what it wrote).
-__device__ __forceinline__ void reduce_chain(const double *__restrict__ lv,
-                                             const double *__restrict__ ct, double *__restrict__ ab,
-                                             double scale, int64_t nchains, int nc, int64_t ncmax,
-                                             int s, int64_t r) {
-  const double *__restrict__ yl = lv + (int64_t)s * 2 * nchains + r;  // chunk q at q * 4 nchains
-  const double *__restrict__ xf = yl + nchains;
-  double *__restrict__ o = ab + ((int64_t)s * ncmax * nchains + r) * 2;  // chunk c at c * 2 nchains
-  // forward: cf[c] parked (unscaled) in o[c][0]
-  double cf = 0.0;
-  for (int c0 = 0; c0 < nc; c0 += 8) {
-    double y8[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) y8[k] = c0 + k < nc ? yl[(int64_t)(c0 + k) * 4 * nchains] : 0.0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int c = c0 + k;
-      if (c < nc) {
-        o[(int64_t)c * 2 * nchains] = cf;
-        cf = y8[k] + ct[C_F2LAST * ncmax + c] * cf;
-      }
-    }
-  }
-  // backward, chunks nc-1 .. 0; cfn = unscaled cf of chunk c + 1
-  double cb = 0.0, cfn = 0.0;
-  for (int c1 = nc - 1; c1 >= 0; c1 -= 8) {
-    double f8[8], x8[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int c = c1 - k;
-      f8[k] = c >= 0 ? o[(int64_t)c * 2 * nchains] : 0.0;
-      x8[k] = c >= 0 && c + 1 < nc ? xf[(int64_t)(c + 1) * 4 * nchains] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int c = c1 - k;
-      if (c >= 0) {
-        cb = c + 1 < nc ? x8[k] + ct[C_BF2FIRST * ncmax + c + 1] * cfn +
-                              ct[C_BK2FIRST * ncmax + c + 1] * cb
-                        : 0.0;
-        double *oc = o + (int64_t)c * 2 * nchains;
-        oc[0] = scale * f8[k];
-        oc[1] = scale * cb;
-        cfn = f8[k];
-      }
-    }
-  }
+// Both recurrences are affine in the carry, so each is a prefix composition
+// of affine maps z -> a z + b.  A chain gets a segment of kL lanes; lane l
+// owns the q = ceil(nc / 16) consecutive chunks [l q, l q + q) and composes
+// their maps serially, a Hillis-Steele scan over the segment (log2 kL
+// shuffle steps each way) gives every lane the carry at its first chunk,
+// and the lane expands its chunks serially from there.  Lanes without
+// chunks hold the identity, so a chunk's result does not depend on kL.
+// (A few chunks per lane keep the scan short: 4 shuffle steps at most,
+// and a quarter of the wavefronts of one lane per chunk.)  The forward pass
+// parks the unscaled cf in ab for the backward pass (each lane rereads only
+// what it wrote).
+// Lanes that a chain's scan spans at most, and the chunks each lane owns:
+// a function of the chain's own chunk count only, so batched launches (whose
+// segment width kL covers their longest chain) compute every chain exactly
+// as its single launch does.
+constexpr int kScanLanes = 16;
+__device__ __forceinline__ int chunks_per_lane(int nc) {
+  return (nc + kScanLanes - 1) / kScanLanes;
 }
 
-// Both recurrences are affine in the carry, so each is a prefix composition
-// of affine maps z -> a z + b: lane c of the chain's kL-lane segment holds
-// chunk c's map, and a Hillis-Steele scan over the segment (log2 kL
-// shuffle steps each way) gives every chunk its carry with one round of
-// loads and one of stores.  Lanes at and beyond nc hold the identity, so
-// the result of a chunk does not depend on kL.
 template <int kL>
 __device__ __forceinline__ void reduce_chain_scan(const double *__restrict__ lv,
                                                   const double *__restrict__ ct,
                                                   double *__restrict__ ab, double scale,
                                                   int64_t nchains, int nc, int64_t ncmax, int s,
-                                                  int64_t r, int c) {
-  const double *__restrict__ yl = lv + (int64_t)s * 2 * nchains + r;  // chunk q at q * 4 nchains
+                                                  int64_t r, int lane) {
+  const double *__restrict__ yl = lv + (int64_t)s * 2 * nchains + r;  // chunk k at k * 4 nchains
   const double *__restrict__ xf = yl + nchains;
-  double fa = 1.0, fb = 0.0;  // cf[c+1] = fa cf[c] + fb
-  double xn = 0.0, bf = 0.0, bk = 1.0;
-  if (c < nc) {
-    fa = ct[C_F2LAST * ncmax + c];
-    fb = yl[(int64_t)c * 4 * nchains];
-  }
-  const bool inner = c + 1 < nc;
-  if (inner) {
-    xn = xf[(int64_t)(c + 1) * 4 * nchains];
-    bf = ct[C_BF2FIRST * ncmax + c + 1];
-    bk = ct[C_BK2FIRST * ncmax + c + 1];
+  double *__restrict__ o = ab + ((int64_t)s * ncmax * nchains + r) * 2;  // chunk k at k * 2 nchains
+  const int q = chunks_per_lane(nc);
+  const int lo = lane * q < nc ? lane * q : nc;
+  const int hi = lo + q < nc ? lo + q : nc;
+  // forward: this lane's composed map, cf[hi] = fa cf[lo] + fb
+  double fa = 1.0, fb = 0.0;
+  for (int k = lo; k < hi; ++k) {
+    const double a = ct[C_F2LAST * ncmax + k];
+    fb = a * fb + yl[(int64_t)k * 4 * nchains];
+    fa = a * fa;
   }
 #pragma unroll
-  for (int d = 1; d < kL; d <<= 1) {  // fb <- cf[c+1]
+  for (int d = 1; d < kL; d <<= 1) {  // fb <- cf[hi]
     const double pa = __shfl_up(fa, d, kL), pb = __shfl_up(fb, d, kL);
-    if (c >= d) {
+    if (lane >= d) {
+      fb = fa * pb + fb;
+      fa = fa * pa;
+    }
+  }
+  double cf = __shfl_up(fb, 1, kL);  // cf[lo]
+  if (lane == 0) cf = 0.0;
+  // forward expansion (cf parked unscaled) and this lane's composed backward
+  // map, cb[lo] = ba cb[hi] + bb; the last chunk's map is the identity
+  double ba = 1.0, bb = 0.0;
+  for (int k = lo; k < hi; ++k) {
+    o[(int64_t)k * 2 * nchains] = cf;
+    cf = k + 1 == hi ? fb : ct[C_F2LAST * ncmax + k] * cf + yl[(int64_t)k * 4 * nchains];
+    if (k + 1 < nc) {
+      const double b = ct[C_BK2FIRST * ncmax + k + 1];
+      const double c = xf[(int64_t)(k + 1) * 4 * nchains] + ct[C_BF2FIRST * ncmax + k + 1] * cf;
+      bb = ba * c + bb;
+      ba = ba * b;
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < kL; d <<= 1) {  // bb <- cb[lo]
+    const double na = __shfl_down(ba, d, kL), nb = __shfl_down(bb, d, kL);
+    if (lane + d < kL) {
+      bb = ba * nb + bb;
+      ba = ba * na;
+    }
+  }
+  double cb = __shfl_down(bb, 1, kL);  // cb[hi]
+  if (lane + 1 >= kL) cb = 0.0;
+  // backward expansion, chunks hi-1 .. lo; cfn = unscaled cf of chunk k + 1
+  double cfn = fb;
+  for (int k = hi - 1; k >= lo; --k) {
+    const double cfk = o[(int64_t)k * 2 * nchains];
+    if (k == lo)
+      cb = bb;
+    else if (k + 1 < nc)
+      cb = ct[C_BK2FIRST * ncmax + k + 1] * cb +
+           (xf[(int64_t)(k + 1) * 4 * nchains] + ct[C_BF2FIRST * ncmax + k + 1] * cfn);
+    else
+      cb = 0.0;
+    o[(int64_t)k * 2 * nchains] = scale * cfk;
+    o[(int64_t)k * 2 * nchains + 1] = scale * cb;
+    cfn = cfk;
+  }
+}
+
+// Where one chain's chunk data sits: boundary values y (last forward value)
+// and x (first backward value) of chunk k at k * ystride, coefficient slot
+// j of chunk k at ct[j * ctstride + k]; global memory or the LDS stage.
+struct ChainSrc {
+  const double *y, *x;
+  int64_t ystride;
+  const double *ct;
+  int64_t ctstride;
+};
+
+// The same computation with at most kQ chunks per lane held in registers:
+// every load is issued before the first use (one round of memory latency)
+// and cf stays in registers.  Identical arithmetic in the same order, so a
+// chunk's result does not depend on which form ran.  o: the chain's
+// output, chunk k at k * ostride (cf, cb).
+template <int kL, int kQ>
+__device__ __forceinline__ void reduce_chain_scan_reg(const ChainSrc &src, double *__restrict__ o,
+                                                      int64_t ostride, double scale, int nc,
+                                                      int lane) {
+  const int q = chunks_per_lane(nc);  // <= kQ
+  const int lo = lane * q < nc ? lane * q : nc;
+  const int hi = lo + q < nc ? lo + q : nc;
+  const double *__restrict__ ct = src.ct;
+  const int64_t cs = src.ctstride, ys = src.ystride;
+  double a[kQ], y[kQ], xn[kQ], bfn[kQ], bkn[kQ];
+#pragma unroll
+  for (int t = 0; t < kQ; ++t) {
+    const int k = lo + t;
+    const bool in = k < hi, nx = in && k + 1 < nc;
+    a[t] = in ? ct[C_F2LAST * cs + k] : 1.0;
+    y[t] = in ? src.y[(int64_t)k * ys] : 0.0;
+    xn[t] = nx ? src.x[(int64_t)(k + 1) * ys] : 0.0;
+    bfn[t] = nx ? ct[C_BF2FIRST * cs + k + 1] : 0.0;
+    bkn[t] = nx ? ct[C_BK2FIRST * cs + k + 1] : 1.0;
+  }
+  double fa = 1.0, fb = 0.0;
+#pragma unroll
+  for (int t = 0; t < kQ; ++t)
+    if (lo + t < hi) {
+      fb = a[t] * fb + y[t];
+      fa = a[t] * fa;
+    }
+#pragma unroll
+  for (int d = 1; d < kL; d <<= 1) {
+    const double pa = __shfl_up(fa, d, kL), pb = __shfl_up(fb, d, kL);
+    if (lane >= d) {
       fb = fa * pb + fb;
       fa = fa * pa;
     }
   }
   double cf = __shfl_up(fb, 1, kL);
-  if (c == 0) cf = 0.0;
-  // cb[c] = ba cb[c+1] + bb; the last chunk's map is the identity (cb = 0)
-  double ba = bk, bb = inner ? xn + bf * fb : 0.0;
+  if (lane == 0) cf = 0.0;
+  double cfv[kQ];
+  double ba = 1.0, bb = 0.0;
 #pragma unroll
-  for (int d = 1; d < kL; d <<= 1) {  // bb <- cb[c]
+  for (int t = 0; t < kQ; ++t) {
+    const int k = lo + t;
+    cfv[t] = cf;
+    if (k < hi) {
+      cf = k + 1 == hi ? fb : a[t] * cf + y[t];
+      if (k + 1 < nc) {
+        const double c = xn[t] + bfn[t] * cf;
+        bb = ba * c + bb;
+        ba = ba * bkn[t];
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < kL; d <<= 1) {
     const double na = __shfl_down(ba, d, kL), nb = __shfl_down(bb, d, kL);
-    if (c + d < kL) {
+    if (lane + d < kL) {
       bb = ba * nb + bb;
       ba = ba * na;
     }
   }
-  if (c < nc) {
-    double *oc = ab + (((int64_t)s * ncmax + c) * nchains + r) * 2;
-    oc[0] = scale * cf;
-    oc[1] = scale * bb;
+  double cb = __shfl_down(bb, 1, kL);
+  if (lane + 1 >= kL) cb = 0.0;
+  double cfn = fb;
+#pragma unroll
+  for (int t = kQ - 1; t >= 0; --t) {
+    const int k = lo + t;
+    if (k < hi) {
+      const double cfk = cfv[t];
+      if (k == lo)
+        cb = bb;
+      else if (k + 1 < nc)
+        cb = bkn[t] * cb + (xn[t] + bfn[t] * cfn);
+      else
+        cb = 0.0;
+      o[(int64_t)k * ostride] = scale * cfk;
+      o[(int64_t)k * ostride + 1] = scale * cb;
+      cfn = cfk;
+    }
   }
 }
 
-// One chain on kL lanes: the scan when its chunks fit, else lane 0 runs the
-// sequential form.
-template <int kL>
-__device__ __forceinline__ void reduce_one(const double *lv, const double *ct, double *ab,
-                                           double scale, int64_t nchains, int nc, int64_t ncmax,
-                                           int s, int64_t r, int c) {
-  if (nc <= kL)
-    reduce_chain_scan<kL>(lv, ct, ab, scale, nchains, nc, ncmax, s, r, c);
-  else if (c == 0)
-    reduce_chain(lv, ct, ab, scale, nchains, nc, ncmax, s, r);
+// The carries of the workgroup's kReduceChains chains (r0 ..) of parity s.
+template <int kL, int kQ>
+__device__ __forceinline__ void reduce_block(const double *__restrict__ lv,
+                                             const double *__restrict__ ct,
+                                             double *__restrict__ ab, double scale,
+                                             int64_t nchains, int nc, int64_t ncmax, int s,
+                                             int64_t r0) {
+  const int ch = threadIdx.x / kL, lane = threadIdx.x % kL;
+  const int64_t r = r0 + ch;
+  if (r >= nchains || nc == 0) return;  // whole kL-lane segments leave together
+  if constexpr (kQ > 0) {
+    const double *yl = lv + (int64_t)s * 2 * nchains + r;
+    const ChainSrc src{yl, yl + nchains, 4 * nchains, ct, ncmax};
+    reduce_chain_scan_reg<kL, kQ>(src, ab + ((int64_t)s * ncmax * nchains + r) * 2, 2 * nchains,
+                                  scale, nc, lane);
+  } else {
+    reduce_chain_scan<kL>(lv, ct, ab, scale, nchains, nc, ncmax, s, r, lane);
+  }
 }
 
 // Grid: (ceil(nchains / kReduceChains), 2 parities, batch); workgroup of
 // kReduceChains x kL threads, chain-major.
-template <int kL>
+template <int kL, int kQ>
 __global__ __launch_bounds__(kReduceChains * kL) void k_reduce(
     const double *__restrict__ lv, const double *__restrict__ ctab, double *__restrict__ ab,
     double scale, int64_t nchains, int nc0, int nc1, int64_t ncmax, int64_t lvb, int64_t abb) {
   const int s = blockIdx.y;
   const int nc = s ? nc1 : nc0;
-  const int64_t r = (int64_t)blockIdx.x * kReduceChains + threadIdx.x / kL;
-  if (r >= nchains || nc == 0) return;  // whole kL-lane segments leave together
   const int64_t z = blockIdx.z;
-  reduce_one<kL>(lv + z * lvb, ctab + (int64_t)s * kNCTab * ncmax, ab + z * abb, scale, nchains,
-                 nc, ncmax, s, r, (int)(threadIdx.x % kL));
+  reduce_block<kL, kQ>(lv + z * lvb, ctab + (int64_t)s * kNCTab * ncmax, ab + z * abb, scale,
+                       nchains, nc, ncmax, s, (int64_t)blockIdx.x * kReduceChains);
 }
 
-template <int kL>
+template <int kL, int kQ>
 __global__ __launch_bounds__(kReduceChains * kL) void k_reduce_batch(
     const BatchReduce *__restrict__ d, const int *__restrict__ wg_prob, char *base) {
   const int k = __builtin_amdgcn_readfirstlane(wg_prob[blockIdx.x]);
@@ -158,69 +245,78 @@ __global__ __launch_bounds__(kReduceChains * kL) void k_reduce_batch(
   const int local = (int)blockIdx.x - e.wg_start;
   const int s = local / e.nbx;
   const int nc = s ? e.nc1 : e.nc0;
-  const int64_t r = (int64_t)(local % e.nbx) * kReduceChains + threadIdx.x / kL;
-  if (r >= e.npad || nc == 0) return;
-  reduce_one<kL>((const double *)(base + e.lv_off), e.ctab + (int64_t)s * kNCTab * e.ncmax,
-                 (double *)(base + e.ab_off), e.scale, e.npad, nc, e.ncmax, s, r,
-                 (int)(threadIdx.x % kL));
+  reduce_block<kL, kQ>((const double *)(base + e.lv_off), e.ctab + (int64_t)s * kNCTab * e.ncmax,
+                       (double *)(base + e.ab_off), e.scale, e.npad, nc, e.ncmax, s,
+                       (int64_t)(local % e.nbx) * kReduceChains);
 }
 
-// Lanes per chain: the least power of two from 2 to 64 that holds ncmax
-// chunks (64 beyond; chains longer than that take the sequential form).
+// Lanes per chain: the least power of two from 2 to kScanLanes that holds
+// the active lanes of a chain of ncmax chunks.
 int reduce_lanes(int64_t ncmax) {
   int l = 2;
-  while (l < 64 && l < ncmax) l <<= 1;
+  while (l < kScanLanes && l < ncmax) l <<= 1;
   return l;
 }
 
+// Kernel shape for chains of up to ncmax chunks: lanes per chain, and the
+// bound kQ of chunks per lane held in registers (0: more than 8, memory form).
+void reduce_shape(int64_t ncmax, int *lanes, int *kq) {
+  *lanes = reduce_lanes(ncmax);
+  const int64_t q = (ncmax + kScanLanes - 1) / kScanLanes;
+  *kq = q <= 1 ? 1 : q <= 2 ? 2 : q <= 4 ? 4 : q <= 8 ? 8 : 0;
+}
+
 }  // namespace
+
+// Expands LAUNCH(L, Q) for the instantiated shape (lanes, kq).
+#define FPS_WITH_REDUCE_SHAPE(lanes, kq, LAUNCH) \
+  do {                                           \
+    if ((lanes) == 2)                            \
+      LAUNCH(2, 1);                              \
+    else if ((lanes) == 4)                       \
+      LAUNCH(4, 1);                              \
+    else if ((lanes) == 8)                       \
+      LAUNCH(8, 1);                              \
+    else if ((kq) == 1)                          \
+      LAUNCH(16, 1);                             \
+    else if ((kq) == 2)                          \
+      LAUNCH(16, 2);                             \
+    else if ((kq) == 4)                          \
+      LAUNCH(16, 4);                             \
+    else if ((kq) == 8)                          \
+      LAUNCH(16, 8);                             \
+    else                                         \
+      LAUNCH(16, 0);                             \
+  } while (0)
 
 hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,
                          int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
                          int nbatch, int64_t lvb, int64_t abb) {
   dim3 grid((unsigned)((nchains + kReduceChains - 1) / kReduceChains), 2u,
             (unsigned)(nbatch > 0 ? nbatch : 1));
-  const int lanes = reduce_lanes(ncmax);
-#define FPS_REDUCE(L)                                                                        \
-  hipLaunchKernelGGL(k_reduce<L>, grid, dim3(kReduceChains * L), 0, st, lv, ctab, ab, scale, \
-                     nchains, nc0, nc1, ncmax, lvb, abb)
-  if (lanes == 2)
-    FPS_REDUCE(2);
-  else if (lanes == 4)
-    FPS_REDUCE(4);
-  else if (lanes == 8)
-    FPS_REDUCE(8);
-  else if (lanes == 16)
-    FPS_REDUCE(16);
-  else if (lanes == 32)
-    FPS_REDUCE(32);
-  else
-    FPS_REDUCE(64);
-#undef FPS_REDUCE
+  int lanes, kq;
+  reduce_shape(ncmax, &lanes, &kq);
+#define FPS_LAUNCH(L, Q)                                                                    \
+  hipLaunchKernelGGL((k_reduce<L, Q>), grid, dim3(kReduceChains * L), 0, st, lv, ctab, ab, \
+                     scale, nchains, nc0, nc1, ncmax, lvb, abb)
+  FPS_WITH_REDUCE_SHAPE(lanes, kq, FPS_LAUNCH);
+#undef FPS_LAUNCH
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_batch(const BatchReduce *d, const int *wg_prob, int nwg, int64_t ncmax_max,
                                char *base, hipStream_t st) {
   if (nwg <= 0) return hipSuccess;
-  const int lanes = reduce_lanes(ncmax_max);
-#define FPS_REDUCE(L)                                                                      \
-  hipLaunchKernelGGL(k_reduce_batch<L>, dim3((unsigned)nwg), dim3(kReduceChains * L), 0, st, d, \
-                     wg_prob, base)
-  if (lanes == 2)
-    FPS_REDUCE(2);
-  else if (lanes == 4)
-    FPS_REDUCE(4);
-  else if (lanes == 8)
-    FPS_REDUCE(8);
-  else if (lanes == 16)
-    FPS_REDUCE(16);
-  else if (lanes == 32)
-    FPS_REDUCE(32);
-  else
-    FPS_REDUCE(64);
-#undef FPS_REDUCE
+  int lanes, kq;
+  reduce_shape(ncmax_max, &lanes, &kq);
+#define FPS_LAUNCH(L, Q)                                                                     \
+  hipLaunchKernelGGL((k_reduce_batch<L, Q>), dim3((unsigned)nwg), dim3(kReduceChains * L), 0, \
+                     st, d, wg_prob, base)
+  FPS_WITH_REDUCE_SHAPE(lanes, kq, FPS_LAUNCH);
+#undef FPS_LAUNCH
   return hipGetLastError();
 }
+
+#undef FPS_WITH_REDUCE_SHAPE
 
 }  // namespace fps
