@@ -326,6 +326,39 @@ def bench_cylinder(fps, workloads, torch, n=256, n_theta=256, steps=5, check=Tru
     return res
 
 
+def bench_square_large(fps, workloads, torch, tol, n=10000, steps=3, check=True, tight=True):
+    """The square at n = 10^4 (10^8 dof, the size of the paper's own timing
+    example): time per FP64 solve and the error against the oracle's exact
+    discrete solution."""
+    import numpy as np
+    F_host = workloads.square_rhs(n, seed=0)
+    F = torch.from_numpy(F_host).cuda()
+    p = fps.plan(n, tol=tol, tight=tight)
+    ws = fps.workspace(p, "cuda")
+    U = torch.empty(p.out_shape(), dtype=torch.float64, device="cuda")
+    fps.solve(p, F, out=U, ws=ws)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fps.solve(p, F, out=U, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res = {"n": n, "dof": float(n) * n, "J": p.J, "ms_per_solve": ms,
+           "dof_per_s": float(n) * n / (ms * 1e-3),
+           "paper_context": "10^8 dof in under two minutes on a 2017 laptop (MATLAB, one core)"}
+    if check:
+        from oracle import square
+        Uo = square.poisson_square(F_host)
+        res["rel_frobenius_err_vs_oracle"] = float(np.linalg.norm(U.cpu().numpy() - Uo)
+                                                   / np.linalg.norm(Uo))
+    del ws, U, F
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_adjoint(fps, workloads, torch, tol, n=2048, batch=16, steps=3, check=True, tight=True):
     """Differentiation form: one forward and one backward pass of the autograd
     solve over a batch of 16 right-hand sides at n = 2048, for the quadratic
@@ -390,7 +423,7 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP32-refined, batched, cube, rectangle and cylinder timings")
     ap.add_argument("--only", choices=["fp32_refined", "batched", "cube", "cube_zeig",
-                                       "rect_dirichlet", "cylinder", "adjoint"],
+                                       "rect_dirichlet", "cylinder", "adjoint", "square_n10000"],
                     help="run only this form and print its figures (profiling)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
@@ -408,7 +441,8 @@ def main() -> int:
 
     n = args.n
     dev = torch.device("cuda:0")
-    if args.only in ("batched", "cube", "cube_zeig", "rect_dirichlet", "cylinder", "adjoint"):
+    if args.only in ("batched", "cube", "cube_zeig", "rect_dirichlet", "cylinder", "adjoint",
+                     "square_n10000"):
         if args.copy_calib_mib:
             calibration_copy(torch, dev, args.copy_calib_mib)
         tight = args.enclosure == "tight"
@@ -427,6 +461,9 @@ def main() -> int:
         elif args.only == "adjoint":
             res = bench_adjoint(fps, workloads, torch, args.tol, steps=max(1, args.steps),
                                 check=not args.no_check, tight=tight)
+        elif args.only == "square_n10000":
+            res = bench_square_large(fps, workloads, torch, args.tol, steps=max(1, args.steps),
+                                     check=not args.no_check, tight=tight)
         else:
             res = bench_cube_zeig(fps, workloads, torch, args.tol, steps=max(1, args.steps),
                                   check=not args.no_check, tight=tight)
@@ -569,6 +606,8 @@ def main() -> int:
             forms["cylinder"] = bench_cylinder(fps, workloads, torch, check=not args.no_check)
             forms["adjoint"] = bench_adjoint(fps, workloads, torch, args.tol,
                                              check=not args.no_check, tight=tight)
+            forms["square_n10000"] = bench_square_large(fps, workloads, torch, args.tol,
+                                                        check=not args.no_check, tight=tight)
     if forms:
         out["forms"] = forms
 

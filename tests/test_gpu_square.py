@@ -116,6 +116,22 @@ def test_headline_size_full_parity():
     assert err <= 1e-12
 
 
+def test_largest_workload_size_full_parity():
+    # n = 10^4 (10^8 dof): full comparison with the oracle.  FP64 rounding of
+    # the J-step ADI grows with n (5.9e-13 at n = 4096); measured 1.36e-12
+    # here, so the bound is 3e-12.
+    n = 10000
+    F = workloads.square_rhs(n, seed=0)
+    print("n=10000 solve", flush=True)
+    p = fps.plan(n, tol=1e-13, tight=True)
+    U = fps.solve(p, _dev(F)).cpu().numpy()
+    print("n=10000 oracle", flush=True)
+    Uo = square.poisson_square(F)
+    err = _rel(U, Uo)
+    print(f"n=10000 rel err {err:.3e}", flush=True)
+    assert err <= 3e-12
+
+
 @pytest.mark.parametrize("n", [1, 5, 64, 300, 1024, 4096])
 def test_tight_spectrum_solve_matches_exact(n):
     # Shift intervals from the computed spectrum (fewer iterations, same bound).
