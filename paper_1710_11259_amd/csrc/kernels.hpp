@@ -87,7 +87,7 @@ hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, doubl
                          int nbatch = 1, int64_t lvb = 0, int64_t abb = 0);
 
 // Chains per workgroup of the chunk-carry kernels (each chain on a segment
-// of 8 to 64 lanes, by the chunk count).
+// of 2 to 16 lanes, by the chunk count).
 constexpr int kReduceChains = 16;
 
 // Batched launch_reduce: lv_off / ab_off are byte offsets from `base`; the

@@ -37,12 +37,11 @@ def test_adi_iterate_matches_closed_form(n, tol):
 
 
 def test_long_chains_iterate_matches_closed_form():
-    # n = 8200: 4100 positions per parity chain, i.e. 65 chunks, more than the
-    # 64 lanes the chunk-carry scan gives one chain, so the carries take the
-    # sequential form.  The rounding of the J-step iterate grows with n
-    # (relative error measured 1.7e-11 at n = 6000 and 1.2e-11 at n = 8192,
-    # both with the scan, 2.4e-11 here), so the bound is 1e-10; a wrong carry
-    # gives errors of order one.
+    # n = 8200: 4100 positions per parity chain, i.e. 65 chunks, so each lane
+    # of the chunk-carry scan owns 5 chunks, the last lane only one (a ragged
+    # split).  The rounding of the J-step iterate grows with n (relative error
+    # measured 1.7e-11 at n = 6000 and 1.2e-11 at n = 8192, 2.4e-11 here), so
+    # the bound is 1e-10; a wrong carry gives errors of order one.
     n, tol = 8200, 1e-13
     rng = np.random.default_rng(n)
     G = rng.standard_normal((n, n)) / np.outer(np.arange(1, n + 1), np.arange(1, n + 1))
