@@ -26,6 +26,28 @@ SWEEP_TRAFFIC = {"sha256": "b1bff1e4d1acd93bd6e6fc03628d9fc64d820a735a8b6b8015a4
                  "n": 4096, "half_step_1": 278.8e6, "half_step_2": 413.0e6}
 
 
+def copy_rate(torch, dev, mib=1024, reps=5):
+    """Achievable HBM rate of a plain copy kernel: GB/s (bytes read plus
+    bytes written) of a device-to-device copy of `mib` MiB, far larger than
+    the last-level cache."""
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def calibration_copy(torch, dev, mib):
     """One device-to-device copy of a known size (HBM counter calibration)."""
     nbytes = mib << 20
@@ -547,6 +569,19 @@ def main() -> int:
                           "(hipExtLaunchKernelGGL), separate pass of the same solves "
                           f"({instr_ms / args.steps:.2f} ms per solve with the events)",
                 "sweep_share_of_step": round(sum(sweep_list) / instr_ms, 4)}
+    # Beside the sweep roofline: the rate a plain copy kernel achieves, and the
+    # whole solve's algorithmic bytes (sweeps 40 B per dof per ADI iteration;
+    # the map stages each read their input and write their output once:
+    # permutation, two GEMM stages and transpose on the input side, finalize,
+    # fill of U and two GEMM stages on the output side, 136 B per dof).
+    copy_gbs = copy_rate(torch, dev)
+    solve_bytes = (40.0 * J + 136.0) * dof
+    roofline["copy_kernel_GBs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy_kernel"] = round(achieved / copy_gbs, 4)
+    roofline["whole_solve"] = {
+        "bytes_algorithmic": solve_bytes,
+        "achieved_GBs": round(solve_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "frac": round(solve_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     out = {"metric": METRIC, "value": value, "unit": "dof/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
