@@ -139,7 +139,8 @@ fps_status build_descriptors(fps_batch *bt) {
     A.nc1 = (int)L.nc[1];
     A.lv = off_ptr<double *>(lv);
     const int nbx_s = (int)(L.npad / fps::kCols);
-    const int nbx_r = (int)((L.npad + fps::kReduceChains - 1) / fps::kReduceChains);
+    const int rchains = fps::reduce_chains(bt->ncmax_max);
+    const int nbx_r = (int)((L.npad + rchains - 1) / rchains);
     for (int j = 0; j < J; ++j) {
       const bool last = j == J - 1;
       // half-step 1
@@ -287,10 +288,13 @@ fps_status fps_batch_create(fps_batch **out, int dim, int count, const int64_t *
       if (bt->plan_of(bt->order[k])->shifts.J > j) bt->active[j] = k + 1;
   bt->sw_start.assign(count + 1, 0);
   bt->rd_start.assign(count + 1, 0);
+  for (int k = 0; k < count; ++k)
+    bt->ncmax_max = std::max(bt->ncmax_max, bt->plan_of(bt->order[k])->L.ncmax);
+  const int rchains = fps::reduce_chains(bt->ncmax_max);  // chains per carry workgroup
   for (int k = 0; k < count; ++k) {
     const fps::Layout &L = bt->plan_of(bt->order[k])->L;
     const int64_t nsw = (L.npad / fps::kCols) * (L.nc[0] + L.nc[1]);
-    const int64_t nrd = ((L.npad + fps::kReduceChains - 1) / fps::kReduceChains) * 2;
+    const int64_t nrd = ((L.npad + rchains - 1) / rchains) * 2;
     if ((int64_t)bt->sw_start[k] + nsw > (int64_t)1 << 30 ||
         (int64_t)bt->rd_start[k] + nrd > (int64_t)1 << 30) {
       delete bt;
@@ -298,7 +302,6 @@ fps_status fps_batch_create(fps_batch **out, int dim, int count, const int64_t *
     }
     bt->sw_start[k + 1] = bt->sw_start[k] + (int)nsw;
     bt->rd_start[k + 1] = bt->rd_start[k] + (int)nrd;
-    bt->ncmax_max = std::max(bt->ncmax_max, L.ncmax);
   }
   if (!(flags & FPS_PLAN_HOST_ONLY)) {
     fps_status s = build_descriptors(bt);

@@ -620,7 +620,8 @@ fps_status zeig_upload(fps_plan *pl) {
   const int K = (int)pl->zslice.size(), J = pl->zJmax;
   const int nbx_s = (int)(npad / fps::kCols), nch = (int)(L.nc[0] + L.nc[1]);
   const int nsw = nbx_s * nch;
-  const int nbx_r = (int)((npad + fps::kReduceChains - 1) / fps::kReduceChains);
+  const int rchains = fps::reduce_chains(L.ncmax);  // as launch_reduce_batch(ncmax_max = L.ncmax)
+  const int nbx_r = (int)((npad + rchains - 1) / rchains);
   const int nrd = nbx_r * 2;
   const int64_t lvb = L.ncmax * 4 * npad, abb = 2 * L.ncmax * npad * 2;  // doubles per slice
   std::vector<fps::BatchSweep> sw((size_t)J * 2 * (K > 0 ? K : 1));

@@ -86,13 +86,21 @@ hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, doubl
                          int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
                          int nbatch = 1, int64_t lvb = 0, int64_t abb = 0);
 
-// Chains per workgroup of the chunk-carry kernels (each chain on a segment
-// of 2 to 16 lanes, by the chunk count).
-constexpr int kReduceChains = 16;
+// Shape of the chunk-carry kernels for chains of up to ncmax chunks: each
+// chain on a segment of 2 to 16 lanes (the least power of two that holds
+// min(ncmax, 16) lanes), and 256 / lanes chains per workgroup (256 threads).
+constexpr int kReduceThreads = 256;
+constexpr int kReduceMaxLanes = 16;
+inline int reduce_lanes(int64_t ncmax) {
+  int l = 2;
+  while (l < kReduceMaxLanes && l < ncmax) l <<= 1;
+  return l;
+}
+inline int reduce_chains(int64_t ncmax) { return kReduceThreads / reduce_lanes(ncmax); }
 
 // Batched launch_reduce: lv_off / ab_off are byte offsets from `base`; the
 // workgroups of one problem are (chain block b, parity s) -> local index
-// s * nbx + b with nbx = ceil(npad / kReduceChains), flattened as for
+// s * nbx + b with nbx = ceil(npad / reduce_chains(ncmax_max)), flattened as for
 // BatchSweep; ncmax_max bounds every problem's ncmax (lanes per chain).
 struct BatchReduce {
   int64_t lv_off, ab_off;

@@ -34,7 +34,7 @@ namespace {
 // a function of the chain's own chunk count only, so batched launches (whose
 // segment width kL covers their longest chain) compute every chain exactly
 // as its single launch does.
-constexpr int kScanLanes = 16;
+constexpr int kScanLanes = kReduceMaxLanes;
 __device__ __forceinline__ int chunks_per_lane(int nc) {
   return (nc + kScanLanes - 1) / kScanLanes;
 }
@@ -204,7 +204,8 @@ __device__ __forceinline__ void reduce_chain_scan_reg(const ChainSrc &src, doubl
   }
 }
 
-// The carries of the workgroup's kReduceChains chains (r0 ..) of parity s.
+// The carries of the workgroup's kReduceThreads / kL chains (r0 ..) of
+// parity s.
 template <int kL, int kQ>
 __device__ __forceinline__ void reduce_block(const double *__restrict__ lv,
                                              const double *__restrict__ ct,
@@ -224,21 +225,21 @@ __device__ __forceinline__ void reduce_block(const double *__restrict__ lv,
   }
 }
 
-// Grid: (ceil(nchains / kReduceChains), 2 parities, batch); workgroup of
-// kReduceChains x kL threads, chain-major.
+// Grid: (ceil(nchains / (kReduceThreads / kL)), 2 parities, batch);
+// workgroup of kReduceThreads threads, chain-major.
 template <int kL, int kQ>
-__global__ __launch_bounds__(kReduceChains * kL) void k_reduce(
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(
     const double *__restrict__ lv, const double *__restrict__ ctab, double *__restrict__ ab,
     double scale, int64_t nchains, int nc0, int nc1, int64_t ncmax, int64_t lvb, int64_t abb) {
   const int s = blockIdx.y;
   const int nc = s ? nc1 : nc0;
   const int64_t z = blockIdx.z;
   reduce_block<kL, kQ>(lv + z * lvb, ctab + (int64_t)s * kNCTab * ncmax, ab + z * abb, scale,
-                       nchains, nc, ncmax, s, (int64_t)blockIdx.x * kReduceChains);
+                       nchains, nc, ncmax, s, (int64_t)blockIdx.x * (kReduceThreads / kL));
 }
 
 template <int kL, int kQ>
-__global__ __launch_bounds__(kReduceChains * kL) void k_reduce_batch(
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_batch(
     const BatchReduce *__restrict__ d, const int *__restrict__ wg_prob, char *base) {
   const int k = __builtin_amdgcn_readfirstlane(wg_prob[blockIdx.x]);
   const BatchReduce &e = d[k];
@@ -247,15 +248,7 @@ __global__ __launch_bounds__(kReduceChains * kL) void k_reduce_batch(
   const int nc = s ? e.nc1 : e.nc0;
   reduce_block<kL, kQ>((const double *)(base + e.lv_off), e.ctab + (int64_t)s * kNCTab * e.ncmax,
                        (double *)(base + e.ab_off), e.scale, e.npad, nc, e.ncmax, s,
-                       (int64_t)(local % e.nbx) * kReduceChains);
-}
-
-// Lanes per chain: the least power of two from 2 to kScanLanes that holds
-// the active lanes of a chain of ncmax chunks.
-int reduce_lanes(int64_t ncmax) {
-  int l = 2;
-  while (l < kScanLanes && l < ncmax) l <<= 1;
-  return l;
+                       (int64_t)(local % e.nbx) * (kReduceThreads / kL));
 }
 
 // Kernel shape for chains of up to ncmax chunks: lanes per chain, and the
@@ -292,12 +285,12 @@ void reduce_shape(int64_t ncmax, int *lanes, int *kq) {
 hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,
                          int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
                          int nbatch, int64_t lvb, int64_t abb) {
-  dim3 grid((unsigned)((nchains + kReduceChains - 1) / kReduceChains), 2u,
-            (unsigned)(nbatch > 0 ? nbatch : 1));
+  const int chains = reduce_chains(ncmax);
+  dim3 grid((unsigned)((nchains + chains - 1) / chains), 2u, (unsigned)(nbatch > 0 ? nbatch : 1));
   int lanes, kq;
   reduce_shape(ncmax, &lanes, &kq);
 #define FPS_LAUNCH(L, Q)                                                                    \
-  hipLaunchKernelGGL((k_reduce<L, Q>), grid, dim3(kReduceChains * L), 0, st, lv, ctab, ab, \
+  hipLaunchKernelGGL((k_reduce<L, Q>), grid, dim3(kReduceThreads), 0, st, lv, ctab, ab, \
                      scale, nchains, nc0, nc1, ncmax, lvb, abb)
   FPS_WITH_REDUCE_SHAPE(lanes, kq, FPS_LAUNCH);
 #undef FPS_LAUNCH
@@ -310,7 +303,7 @@ hipError_t launch_reduce_batch(const BatchReduce *d, const int *wg_prob, int nwg
   int lanes, kq;
   reduce_shape(ncmax_max, &lanes, &kq);
 #define FPS_LAUNCH(L, Q)                                                                     \
-  hipLaunchKernelGGL((k_reduce_batch<L, Q>), dim3((unsigned)nwg), dim3(kReduceChains * L), 0, \
+  hipLaunchKernelGGL((k_reduce_batch<L, Q>), dim3((unsigned)nwg), dim3(kReduceThreads), 0, \
                      st, d, wg_prob, base)
   FPS_WITH_REDUCE_SHAPE(lanes, kq, FPS_LAUNCH);
 #undef FPS_LAUNCH
