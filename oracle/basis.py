@@ -108,13 +108,38 @@ def dct_matrix(N: int) -> np.ndarray:
 
 
 def recombined_to_cheb(n: int) -> np.ndarray:
-    """P (n+2) x n with column i = Chebyshev coefficients of (1-x^2) C~_i(x),
-    obtained by sampling on n+2 first-kind points and applying dct_matrix
-    (exact: the functions have degree i+2 <= n+1)."""
+    """P (n+2) x n with column i = Chebyshev coefficients of (1-x^2) C~_i(x)
+    (the expansion (3.2)), entrywise from a closed form:
+      * C^(3/2)_i = P'_{i+1} (NIST 18.9.19 with lambda = 1/2) and
+        (1-x^2) P'_{i+1} = (i+1)(i+2)/(2i+3) (P_i - P_{i+2}) (Legendre P),
+      * P_m = sum_{k <= m, k = m mod 2} (2 - [k = 0])/pi L((m-k)/2) L((m+k)/2) T_k
+        with L(z) = Gamma(z + 1/2)/Gamma(z + 1) (the Legendre-to-Chebyshev
+        connection, DLMF 18.18.16 at lambda = 1/2 in the limit mu -> 0),
+      * L(z + 1) = L(z) (z + 1/2)/(z + 1), so for k <= i, a = (i-k)/2,
+        b = (i+k)/2 the two terms combine without cancellation:
+          coefficient = nu_i (i+1)(i+2)/4 (2 - [k = 0])/pi L(a) L(b) / ((a+1)(b+1)),
+        and T_{i+2} takes -nu_i (i+1)(i+2)/(2i+3) (2/pi) L(0) L(i+2),
+    with C~_i = nu_i C^(3/2)_i (footnote of Sec. 3.1).  Every factor is
+    positive, so each entry has relative accuracy of a few eps (sampling at
+    n+2 points and a float64 DCT gives the same matrix with rounding that
+    grows with n: 3.4e-14 relative at n = 512)."""
     N = n + 2
-    x = cheb_points(N)
-    E = ((1 - x * x)[None, :] * ct_values(n, x)).T  # (N, n)
-    return dct_matrix(N) @ E
+    if n == 0:
+        return np.zeros((N, n))
+    # L(m) for integer m = 0 .. n+1 by the ratio recurrence, in extended precision
+    ld = np.longdouble
+    m = np.arange(n + 2)
+    ratios = (m[:-1].astype(ld) + ld(0.5)) / (m[:-1].astype(ld) + 1)
+    L = np.concatenate([[np.sqrt(ld(np.pi))], np.sqrt(ld(np.pi)) * np.cumprod(ratios)]).astype(np.float64)
+    PT = np.zeros((n, N))  # row i holds column i (returned transposed, no copy)
+    for i in range(n):
+        nu = np.sqrt((i + 1.5) / ((i + 1) * (i + 2)))
+        k = np.arange(i % 2, i + 1, 2)
+        a, b = (i - k) // 2, (i + k) // 2
+        w = np.where(k == 0, 1.0, 2.0) / np.pi
+        PT[i, k] = nu * (i + 1) * (i + 2) / 4 * w * L[a] * L[b] / ((a + 1.0) * (b + 1.0))
+        PT[i, i + 2] = -nu * (i + 1) * (i + 2) / (2 * i + 3) * (2 / np.pi) * L[0] * L[i + 2]
+    return PT.T
 
 
 def cheb_eval_2d(U: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarray:
