@@ -86,10 +86,35 @@ def cheb_T(n: int, x: np.ndarray) -> np.ndarray:
 def cheb_to_ct(n: int) -> np.ndarray:
     """R with R[i, k] = int T_k(x) C~_i(x) (1-x^2) dx, i.e. column k holds the
     C~ coefficients of T_k (orthonormality of C~ under (1-x^2), footnote of
-    Sec. 3.1).  The integrand has degree <= 2n-2, so n+1 Gauss-Jacobi nodes
-    integrate it exactly."""
-    x, w = gauss_jacobi11(n + 1)
-    return (ct_values(n, x) * w[None, :]) @ cheb_T(n, x).T
+    Sec. 3.1), for i, k < n, entrywise from the Gegenbauer connection formula
+    (DLMF 18.18.16) in the limit that gives T_k (DLMF 18.7.25), mu = 3/2:
+      T_k = (k/2) sum_l A(k-l) B(l) (k - 2l + mu) C^(mu)_{k-2l},
+      A(j) = (j-1)! / (mu)_{j+1},  B(l) = (-mu)_l / l!,
+    with C^(mu)_i = C~_i / nu_i.  A and B are tabulated once in extended
+    precision by their ratio recurrences, so every entry is a product of a
+    few accurately known factors (relative accuracy of a few eps; Gauss-Jacobi
+    quadrature of the integrals in float64 leaves absolute errors ~ eps that
+    grow relative to the small entries with n: 9e-14 relative at n = 512)."""
+    R = np.zeros((n, n))
+    if n == 0:
+        return R
+    ld = np.longdouble
+    mu = ld(1.5)
+    j = np.arange(1, n + 1).astype(ld)
+    # A(1) = 1/(mu (mu+1)), A(j+1)/A(j) = j/(mu + j + 1); index j - 1
+    A = np.cumprod(np.concatenate([[1 / (mu * (mu + 1))], j[:-1] / (mu + j[:-1] + 1)])).astype(np.float64)
+    l_ = np.arange(n).astype(ld)
+    # B(0) = 1, B(l+1)/B(l) = (l - mu)/(l + 1)
+    B = np.cumprod(np.concatenate([[ld(1)], (l_[:-1] - mu) / (l_[:-1] + 1)])).astype(np.float64)
+    i_all = np.arange(n, dtype=np.float64)
+    nu = np.sqrt((i_all + 1.5) / ((i_all + 1) * (i_all + 2)))
+    RT = np.zeros((n, n))  # row k holds column k (returned transposed, no copy)
+    RT[0, 0] = 1 / nu[0]   # T_0 = C^(mu)_0
+    for k in range(1, n):
+        l = np.arange(k // 2 + 1)
+        i = k - 2 * l
+        RT[k, i] = (k / 2) * A[k - l - 1] * B[l] * (i + 1.5) / nu[i]
+    return RT.T
 
 
 def cheb_points(N: int) -> np.ndarray:
