@@ -133,12 +133,21 @@ def solve_mode_bs(P, Q, Mz, Dz, R):
 
 
 def r_output_map(n: int, m: int, N: int) -> np.ndarray:
-    """Chebyshev coefficients (N rows) of r^m (1 - r^2) C~_i(r), i < n, by
-    sampling on N first-kind points and the discrete cosine map (exact for
-    degree i + m + 2 <= N - 1)."""
-    x = basis.cheb_points(N)
-    vals = (x ** m * (1 - x * x))[None, :] * basis.ct_values(n, x)
-    return basis.dct_matrix(N) @ vals.T
+    """Chebyshev coefficients (N rows) of r^m (1 - r^2) C~_i(r), i < n: those
+    of (1 - r^2) C~_i (basis.recombined_to_cheb, exact entrywise) multiplied
+    by r m times in coefficient space, x T_0 = T_1 and
+    x T_k = (T_{k+1} + T_{k-1})/2 (degree i + m + 2 <= N - 1)."""
+    if N < n + 2 + m:
+        raise ValueError("N too small for r^m (1 - r^2) C~_i")
+    P = np.zeros((N, n))
+    P[:n + 2] = basis.recombined_to_cheb(n)
+    for _ in range(m):
+        Q = np.zeros_like(P)
+        Q[1] += P[0]
+        Q[2:] += P[1:-1] / 2
+        Q[:-1] += P[1:] / 2
+        P = Q
+    return P
 
 
 def solve_mode(F_T: np.ndarray, k: int, method: str = "bs") -> np.ndarray:
