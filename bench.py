@@ -451,8 +451,8 @@ def main() -> int:
                     help="run one device-to-device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU "
-                                   "sharding is described in the design notes but not built"}))
+        print(json.dumps({"error": "the solver runs on one GPU; sharding across GPUs is not "
+                                   "implemented"}))
         return 2
 
     import numpy as np

@@ -38,9 +38,10 @@ paper's definitions as plainly as possible:
                  and its sine-transform solution (1.3), used to check the
                  shift machinery on a textbook problem.
 
-Where the paper is ambiguous or in error, the oracle takes the readings
-listed in the design notes (iteration count (2.9) rather than the square-case
-display of Sec. 3.3; congruence in (3.9); rectangular M on output; cube
-right-hand side scaled by D^-1 in each mode).
+Where the paper is ambiguous or in error, the oracle takes these readings:
+the iteration count (2.9) rather than the square-case display of Sec. 3.3;
+the congruence in (3.9); the rectangular M on output; the cube right-hand
+side scaled by D^-1 in each mode; and the further readings stated in the
+docstrings of the rect and cylinder modules.
 """
 from . import basis, shifts, square, cube, adjoint, fd, rect, cylinder  # noqa: F401
