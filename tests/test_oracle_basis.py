@@ -85,3 +85,24 @@ def test_recombined_to_cheb_matches_direct_expansion():
     lhs = (1 - x ** 2)[None, :] * basis.ct_values(n, x)
     rhs = P.T @ basis.cheb_T(n + 2, x)
     assert np.abs(lhs - rhs).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64])
+def test_cheb_to_ct_equals_its_integral_definition(n):
+    # R[i, k] = int T_k C~_i (1 - x^2) dx by Gauss-Jacobi quadrature (exact for
+    # the degree 2n - 2 integrand at these n): the closed form must agree
+    x, w = basis.gauss_jacobi11(n + 1)
+    Rq = (basis.ct_values(n, x) * w[None, :]) @ basis.cheb_T(n, x).T
+    R = basis.cheb_to_ct(n)
+    assert np.abs(R - Rq).max() < 1e-14 * max(1.0, np.abs(Rq).max())
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64])
+def test_recombined_to_cheb_equals_interpolation(n):
+    # the degree-(n+1) functions (1 - x^2) C~_i are interpolated exactly on
+    # n + 2 first-kind points: sampling + discrete cosine map gives P too
+    N = n + 2
+    x = basis.cheb_points(N)
+    Ps = basis.dct_matrix(N) @ ((1 - x * x)[None, :] * basis.ct_values(n, x)).T
+    P = basis.recombined_to_cheb(n)
+    assert np.abs(P - Ps).max() < 1e-14 * max(1.0, np.abs(Ps).max())
