@@ -65,6 +65,14 @@ def test_batch_adjoint_equals_single_adjoints_bitwise(out):
         assert np.array_equal(got, ref), f"n={n}: batched adjoint differs from the single adjoint"
 
 
+def test_batch_adjoint_rejects_refined_batch():
+    b = fps.batch([8, 16], tol=1e-13, precision="fp32_refined")
+    Ub = torch.zeros(b.out_entries, dtype=torch.float64, device="cuda")
+    with pytest.raises(fps.FpsError) as e:
+        fps.batch_solve_adjoint(b, Ub)
+    assert e.value.status == fps.FPS_E_UNSUPPORTED
+
+
 def test_batch_refined_matches_oracle():
     ns = [1, 5, 64, 129, 544, 1024, 32]
     Fs = _rhs(ns, seed=8)
