@@ -48,6 +48,29 @@ def copy_rate(torch, dev, mib=1024, reps=5):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def graph_timing(fps, torch, p, F, U_eager, steps):
+    """The same solve captured into one HIP graph (fps.SolveGraph): ms per
+    replay and whether the replay equals the eager result bit for bit.  The
+    capture removes the host's per-launch cost, which shows where a solve
+    issues many short launches."""
+    g = fps.SolveGraph(p)
+    g.F.copy_(F)
+    g.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(g.U, U_eager))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del g
+    torch.cuda.empty_cache()
+    return ms, same
+
+
 def calibration_copy(torch, dev, mib):
     """One device-to-device copy of a known size (HBM counter calibration)."""
     nbytes = mib << 20
@@ -216,6 +239,7 @@ def bench_cube_zeig(fps, workloads, torch, tol, n=256, steps=3, check=True, tigh
     ms_instr = e0.elapsed_time(e1)
     t = p.sweep_time()
     p.set_sweep_timing(0)
+    ms_g, same_g = graph_timing(fps, torch, p, F, U, steps)
     dof = float(n) ** 3
     tot_b = sum(k * b * n * n for k, b in seq[:len(t)])
     tot_t = sum(t) * 1e-3
@@ -225,7 +249,9 @@ def bench_cube_zeig(fps, workloads, torch, tol, n=256, steps=3, check=True, tigh
            "slice_steps": sum(counts), "max_slice_J": Jmax, "sweep_launches": len(seq),
            "sweep_achieved_GBs": round(tot_b / tot_t / 1e9, 1),
            "sweep_frac_of_8TBs": round(tot_b / tot_t / 8e12, 4),
-           "sweep_share_of_solve": round(sum(t) / ms_instr, 4)}
+           "sweep_share_of_solve": round(sum(t) / ms_instr, 4),
+           "hip_graph": {"ms_per_solve": ms_g, "dof_per_s": dof / (ms_g * 1e-3),
+                         "equals_eager": same_g}}
     if check:
         from oracle import cube
         Uo = cube.poisson_cube(F_host)
@@ -304,6 +330,7 @@ def bench_cylinder(fps, workloads, torch, n=256, n_theta=256, steps=5, check=Tru
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    ms_g, same_g = graph_timing(fps, torch, p, F, U, steps)
     dof = float(n) * n * n_theta
     # Whole-solve rooflines.  MFMA: the four maps, 6 n_theta n^3 flops (z in and
     # out 2 n_theta n^3 each, r in and out n_theta n^3 each, parity blocks).
@@ -325,6 +352,8 @@ def bench_cylinder(fps, workloads, torch, n=256, n_theta=256, steps=5, check=Tru
     flops = 6.0 * n_theta * float(n) ** 3
     res = {"n": n, "n_theta": n_theta, "dof": dof, "ms_per_solve": ms,
            "dof_per_s": dof / (ms * 1e-3), "plan_s": round(t_plan, 2),
+           "hip_graph": {"ms_per_solve": ms_g, "dof_per_s": dof / (ms_g * 1e-3),
+                         "equals_eager": same_g},
            "method": "z-eigenbasis of A~, host-factored banded r-solves per (mode, z column), "
                      "MFMA GEMM maps",
            "roofline_whole_solve": {

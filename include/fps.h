@@ -206,6 +206,10 @@ fps_status fps_adi_shifts(double a, double b, double c, double d, double tol, in
  * ((n+2)^dim, or n^dim with FPS_OUT_NATIVE).  ws_dev: workspace of at least
  * fps_plan_info's workspace_bytes, 256-byte aligned.  Enqueued on `stream`;
  * returns without synchronizing.  F_dev and U_dev must not overlap ws_dev.
+ * The enqueue is kernel launches only (no allocation, memset, memcpy or
+ * synchronization), so it may be captured into a HIP graph for every plan
+ * kind; capture with sweep timing off (fps_plan_set_sweep_timing(plan, 0)),
+ * since timed launches record events.
  */
 fps_status fps_solve(fps_plan *plan, const double *F_dev, double *U_dev, void *ws_dev,
                      void *stream);

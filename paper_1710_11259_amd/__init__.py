@@ -520,3 +520,33 @@ class BatchGraph:
     def replay(self):
         self.graph.replay()
         return self.U
+
+
+class SolveGraph:
+    """One solve of plan `p` (any shape: square, rectangle, cube, cylinder)
+    captured into a HIP graph and replayed with one launch.  fps_solve
+    enqueues kernels only, so the capture holds no memset or memcpy nodes.
+    F, U and the workspace are fixed device buffers: write new inputs into
+    `self.F` before `replay()`.  Capture with the plan's sweep timing off
+    (set_sweep_timing(0)): timed launches record events."""
+
+    def __init__(self, p: Plan, device="cuda"):
+        import torch
+        self.plan = p
+        self.F = torch.zeros(p.in_shape(), dtype=torch.float64, device=device)
+        self.U = torch.empty(p.out_shape(), dtype=torch.float64, device=device)
+        self.ws = workspace(p, device)
+        side = torch.cuda.Stream(device)
+        side.wait_stream(torch.cuda.current_stream(device))
+        with torch.cuda.stream(side):  # one eager run before capture
+            solve(p, self.F, out=self.U, ws=self.ws)
+        torch.cuda.current_stream(device).wait_stream(side)
+        torch.cuda.synchronize(device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            solve(p, self.F, out=self.U, ws=self.ws)
+        torch.cuda.synchronize(device)
+
+    def replay(self):
+        self.graph.replay()
+        return self.U
