@@ -856,6 +856,9 @@ fps_status fps_plan_sweep_time(fps_plan *pl, double *ms_host, int64_t cap, int64
 void fps_plan_destroy(fps_plan *pl) {
   if (!valid_plan(pl)) return;
   release_events(pl);
+  if (pl->zside) (void)hipStreamDestroy(pl->zside);
+  if (pl->zfork) (void)hipEventDestroy(pl->zfork);
+  if (pl->zjoin) (void)hipEventDestroy(pl->zjoin);
   pl->magic = 0;
   delete pl;
 }

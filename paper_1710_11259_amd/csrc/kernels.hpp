@@ -110,8 +110,9 @@ struct BatchReduce {
   int nc0, nc1;
   int wg_start, nbx;
 };
+// wg_base: the launch runs workgroups wg_base .. wg_base + nwg - 1 of the map.
 hipError_t launch_reduce_batch(const BatchReduce *d, const int *wg_prob, int nwg, int64_t ncmax_max,
-                               char *base, hipStream_t st);
+                               char *base, hipStream_t st, int wg_base = 0);
 
 // Y_perm[r][col] = x[r][col] + carries (final pass, non-transposed; x of
 // storage type T).

@@ -240,10 +240,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(
 
 template <int kL, int kQ>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_batch(
-    const BatchReduce *__restrict__ d, const int *__restrict__ wg_prob, char *base) {
-  const int k = __builtin_amdgcn_readfirstlane(wg_prob[blockIdx.x]);
+    const BatchReduce *__restrict__ d, const int *__restrict__ wg_prob, char *base, int wg_base) {
+  const int g = (int)blockIdx.x + wg_base;
+  const int k = __builtin_amdgcn_readfirstlane(wg_prob[g]);
   const BatchReduce &e = d[k];
-  const int local = (int)blockIdx.x - e.wg_start;
+  const int local = g - e.wg_start;
   const int s = local / e.nbx;
   const int nc = s ? e.nc1 : e.nc0;
   reduce_block<kL, kQ>((const double *)(base + e.lv_off), e.ctab + (int64_t)s * kNCTab * e.ncmax,
@@ -298,13 +299,13 @@ hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, doubl
 }
 
 hipError_t launch_reduce_batch(const BatchReduce *d, const int *wg_prob, int nwg, int64_t ncmax_max,
-                               char *base, hipStream_t st) {
+                               char *base, hipStream_t st, int wg_base) {
   if (nwg <= 0) return hipSuccess;
   int lanes, kq;
   reduce_shape(ncmax_max, &lanes, &kq);
 #define FPS_LAUNCH(L, Q)                                                                     \
   hipLaunchKernelGGL((k_reduce_batch<L, Q>), dim3((unsigned)nwg), dim3(kReduceThreads), 0, \
-                     st, d, wg_prob, base)
+                     st, d, wg_prob, base, wg_base)
   FPS_WITH_REDUCE_SHAPE(lanes, kq, FPS_LAUNCH);
 #undef FPS_LAUNCH
   return hipGetLastError();

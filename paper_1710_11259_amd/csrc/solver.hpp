@@ -131,6 +131,12 @@ struct fps_plan {
   std::vector<double> zp, zq;  // shifts of step j of sorted slice k at index ztab0[k] / 2 + j
   int zJmax = 0;
   fps::detail::DeviceBuf d_zsw, d_zrd, d_zswmap, d_zrdmap, d_zfin;
+  // Sorted slices 0 .. zsplit-1 (the longest) iterate on the plan's own
+  // stream zside, the others on the caller's stream, joined by the events
+  // zfork / zjoin (zsplit 0: one stream).
+  int zsplit = 0;
+  hipStream_t zside = nullptr;
+  hipEvent_t zfork = nullptr, zjoin = nullptr;
   fps::detail::DeviceBuf d_Mz[2], d_PV[2], d_Vz[2];  // z maps: V^T S^-1 R, P V, V
   std::vector<double> zV[2];  // host eigenvectors of the parity blocks (m x m, columns)
   int64_t ws_bytes = 0;

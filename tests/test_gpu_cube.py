@@ -97,3 +97,23 @@ def _solve_zeig(n, F):
     U = fps.solve(p, torch.from_numpy(np.ascontiguousarray(F)).cuda())
     torch.cuda.synchronize()
     return U.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [9, 64, 256])
+def test_cube_zeig_two_streams_equal_one(n):
+    # The plan runs its longest slices on a second stream; with per-launch
+    # timing on, every launch goes to the caller's stream.  Each slice's
+    # arithmetic is the same either way, so the results agree bit for bit.
+    F = torch.from_numpy(workloads.cube_rhs(n)).cuda()
+    p = fps.plan(n, tol=1e-13, dim=3, tight=True, zeig=True)
+    print(f"cube zeig streams n={n}", flush=True)
+    U2 = fps.solve(p, F)
+    p.set_sweep_timing(4 * max(p.slice_counts()))
+    U1 = fps.solve(p, F)
+    torch.cuda.synchronize()
+    p.sweep_time()
+    p.set_sweep_timing(0)
+    U3 = fps.solve(p, F)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)
+    assert torch.equal(U3, U2)
