@@ -80,7 +80,13 @@ typedef enum { FPS_OUT_CHEB = 0, FPS_OUT_NATIVE = 1 } fps_out;
  * ADI.  Each slice equation (A~ + mu) Y (A~ + mu) - mu^2 Y = -G^ (mu an
  * eigenvalue of A~) is solved for Z = (A~ + mu) Y as
  * (-mu^2 (A~ + mu)^-1) Z - Z (-(A~ + mu)) = -G^ by Algorithm 2 with the slice's
- * own Zolotarev shifts; n <= 512. */
+ * own Zolotarev shifts; n <= 512.  Where a plan-time model predicts a gain
+ * (n = 256: 78 of 256 slices), the slices with the most steps iterate on a
+ * default-priority stream the plan owns, forked from and joined back to the
+ * solve's stream with events, so the solve still completes in order on
+ * that stream (and captures into a graph).  Solves of one plan on several
+ * streams at once share that stream, and therefore also share its part of
+ * the work in order. */
 #define FPS_PLAN_CUBE_ZEIG 4u
 /* Square and rectangle plans: also build the lift map that
  * fps_solve_dirichlet needs (the scaled C~ coefficients of every T_k'', two
