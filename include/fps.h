@@ -84,9 +84,9 @@ typedef enum { FPS_OUT_CHEB = 0, FPS_OUT_NATIVE = 1 } fps_out;
  * (n = 256: 78 of 256 slices), the slices with the most steps iterate on a
  * default-priority stream the plan owns, forked from and joined back to the
  * solve's stream with events, so the solve still completes in order on
- * that stream (and captures into a graph).  Solves of one plan on several
- * streams at once share that stream, and therefore also share its part of
- * the work in order. */
+ * that stream (and captures into a graph).  Solves of one plan issued on
+ * several streams queue their side-stream work on that one stream, one
+ * after another. */
 #define FPS_PLAN_CUBE_ZEIG 4u
 /* Square and rectangle plans: also build the lift map that
  * fps_solve_dirichlet needs (the scaled C~ coefficients of every T_k'', two
