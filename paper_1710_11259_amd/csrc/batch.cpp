@@ -41,6 +41,12 @@ struct fps_batch {
   // g2; (FP64 batches) the adjoint's input map g1, g2 and output map g1, g2
   DeviceBuf d_gd[8], d_gmap[8];
   int gtiles[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // permute-in (0), transpose (1), finalize (2) and, for refined batches,
+  // residual (3, on the transpose's map) of all problems as one launch each
+  // (elem_ok; else, for very large batches, one launch per problem)
+  bool elem_ok = false;
+  DeviceBuf d_ed[4], d_emap[3];
+  int ewg[3] = {0, 0, 0};
 
   ~fps_batch() {
     for (fps_plan *p : sub) fps_plan_destroy(p);
@@ -105,6 +111,8 @@ fps_status build_gemm_tables(fps_batch *bt) {
   }
   return FPS_OK;
 }
+
+fps_status build_elem_tables(fps_batch *bt);
 
 // Builds the per-step descriptors of every problem (sorted order) and the
 // workgroup -> problem maps.
@@ -188,7 +196,117 @@ fps_status build_descriptors(fps_batch *bt) {
   if ((s = upload(bt->d_sw, sw)) != FPS_OK || (s = upload(bt->d_rd, rd)) != FPS_OK ||
       (s = upload(bt->d_swmap, swmap)) != FPS_OK || (s = upload(bt->d_rdmap, rdmap)) != FPS_OK)
     return s;
-  return build_gemm_tables(bt);
+  if ((s = build_gemm_tables(bt)) != FPS_OK) return s;
+  return build_elem_tables(bt);
+}
+
+// Tables of the batched element-wise launches (sorted order, largest
+// problems first).  Left unbuilt (elem_ok false) when a launch would exceed
+// kElemMaxWg workgroups, where the maps would take hundreds of MB.
+constexpr int64_t kElemMaxWg = (int64_t)1 << 25;
+
+fps_status build_elem_tables(fps_batch *bt) {
+  const int C = bt->count;
+  const bool refined = bt->prec == FPS_FP32_REFINED;
+  std::vector<fps::ElemDesc> ed[4];
+  int64_t tot[3] = {0, 0, 0};
+  for (int k = 0; k < C; ++k) {
+    const int b = bt->order[k];
+    const fps_plan *pl = bt->plan_of(b);
+    const fps::Layout &L = pl->L;
+    const int64_t W = bt->ws_off[b], rowb = (L.npad + 255) / 256, tb = L.npad / 64;
+    const int64_t nwg[3] = {rowb * L.npad, tb * tb, rowb * L.npad};
+    for (int t = 0; t < 3; ++t)
+      if (tot[t] + nwg[t] > kElemMaxWg) return FPS_OK;  // elem_ok stays false
+    fps::ElemDesc e{};
+    e.n = L.n;
+    e.npad = L.npad;
+    e.mp0 = L.mp[0];
+    e.mstride = L.mstride;
+    e.ncmax = L.ncmax;
+    e.sbase = e.dbase = 1;
+    fps::ElemDesc pin = e;  // F -> the G^T region
+    pin.src = bt->f_off[b] * (int64_t)sizeof(double);
+    pin.sbase = 2;
+    pin.dst = W + pl->off_GT;
+    pin.nbx = (int)rowb;
+    fps::ElemDesc tr = e;  // G -> G^T
+    tr.src = W + pl->off_G;
+    tr.dst = W + pl->off_GT;
+    tr.nbx = (int)tb;
+    fps::ElemDesc fin = e;  // O1 and its carries -> Y
+    fin.src = W + pl->off_O1;
+    fin.ab = W + pl->off_ab;
+    fin.tab = pl->tab_dev(pl->shifts.J - 1);
+    fin.dst = W + (refined ? pl->off_GT : pl->off_G);
+    fin.nbx = (int)rowb;
+    fps::ElemDesc *all[3] = {&pin, &tr, &fin};
+    for (int t = 0; t < 3; ++t) {
+      all[t]->wg_start = (int)tot[t];
+      tot[t] += nwg[t];
+      ed[t].push_back(*all[t]);
+    }
+    if (refined) {  // r = G - (A~ Y + Y A~) into the float residual region
+      fps::ElemDesc res = tr;
+      res.src = W + pl->off_G;
+      res.ab = W + pl->off_GT;
+      res.dst = W + pl->off_R;
+      res.tab = (const double *)pl->d_sdiag.p;
+      res.ev = (const double *)pl->d_soff.p;
+      ed[3].push_back(res);
+    }
+  }
+  fps_status s;
+  for (int t = 0; t < 3; ++t) {
+    std::vector<int> map((size_t)tot[t]);
+    for (int k = 0; k < C; ++k) {
+      const int64_t lo = ed[t][(size_t)k].wg_start;
+      const int64_t hi = k + 1 < C ? ed[t][(size_t)k + 1].wg_start : tot[t];
+      std::fill(map.begin() + lo, map.begin() + hi, k);
+    }
+    if ((s = upload(bt->d_ed[t], ed[t])) != FPS_OK || (s = upload(bt->d_emap[t], map)) != FPS_OK)
+      return s;
+    bt->ewg[t] = (int)tot[t];
+  }
+  if (refined && (s = upload(bt->d_ed[3], ed[3])) != FPS_OK) return s;
+  bt->elem_ok = true;
+  return FPS_OK;
+}
+
+// G -> G^T of every problem.
+hipError_t transpose_all(const fps_batch *bt, char *w, hipStream_t st) {
+  if (bt->elem_ok)
+    return fps::launch_transpose_batch((const fps::ElemDesc *)bt->d_ed[1].p,
+                                       (const int *)bt->d_emap[1].p, bt->ewg[1], w, st);
+  for (int b = 0; b < bt->count; ++b) {
+    const fps_plan *pl = bt->plan_of(b);
+    char *wb = w + bt->ws_off[b];
+    const hipError_t e = fps::launch_transpose((const double *)(wb + pl->off_G),
+                                               (double *)(wb + pl->off_GT), pl->L.npad, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Final pass of every problem into Y (its G region, or G^T for a refined
+// batch): mode 0 stores, mode 2 adds.
+hipError_t finalize_all(const fps_batch *bt, char *w, int mode, hipStream_t st) {
+  if (bt->elem_ok)
+    return fps::launch_finalize_batch((const fps::ElemDesc *)bt->d_ed[2].p,
+                                      (const int *)bt->d_emap[2].p, bt->ewg[2], mode, w, st);
+  const bool refined = bt->prec == FPS_FP32_REFINED;
+  for (int b = 0; b < bt->count; ++b) {
+    const fps_plan *pl = bt->plan_of(b);
+    const fps::Layout &L = pl->L;
+    char *wb = w + bt->ws_off[b];
+    double *Y = (double *)(wb + (refined ? pl->off_GT : pl->off_G));
+    const hipError_t e = fps::launch_finalize<double>(
+        (const double *)(wb + pl->off_O1), (const double *)(wb + pl->off_ab),
+        pl->tab_dev(pl->shifts.J - 1), Y, mode, nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax,
+        st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // The 2 J_max batched half-steps (and their carry reductions).  At step j the
@@ -340,25 +458,27 @@ fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, 
   };
   // Input maps: F into each problem's GT region, the two GEMM stages of all
   // problems, then G^T.
-  for (int b = 0; b < C; ++b) {
-    const fps_plan *pl = bt->plan_of(b);
-    FPS_HIP(fps::launch_permute_in(F + bt->f_off[b], (double *)(w + bt->ws_off[b] + pl->off_GT),
-                                   pl->L.n, pl->L.npad, pl->L.mp[0], st));
-  }
+  if (bt->elem_ok)
+    FPS_HIP(fps::launch_permute_in_batch((const fps::ElemDesc *)bt->d_ed[0].p,
+                                         (const int *)bt->d_emap[0].p, bt->ewg[0], F, w, st));
+  else
+    for (int b = 0; b < C; ++b) {
+      const fps_plan *pl = bt->plan_of(b);
+      FPS_HIP(fps::launch_permute_in(F + bt->f_off[b], (double *)(w + bt->ws_off[b] + pl->off_GT),
+                                     pl->L.n, pl->L.npad, pl->L.mp[0], st));
+    }
   FPS_HIP(gemm(0));
   FPS_HIP(gemm(1));
-  for (int b = 0; b < C; ++b) {
-    const fps_plan *pl = bt->plan_of(b);
-    char *wb = w + bt->ws_off[b];
-    FPS_HIP(fps::launch_transpose((const double *)(wb + pl->off_G), (double *)(wb + pl->off_GT),
-                                  pl->L.npad, st));
-  }
+  FPS_HIP(transpose_all(bt, w, st));
   // Y of every problem: FP64 lands in its G region, refined in its GT region
   // (as the single-problem solve places it).
   const bool refined = bt->prec == FPS_FP32_REFINED;
   const int rounds = refined ? bt->sub[0]->rounds : 1;
   for (int k = 0; k < rounds; ++k) {
-    if (refined)
+    if (refined && bt->elem_ok)
+      FPS_HIP(fps::launch_residual_batch((const fps::ElemDesc *)bt->d_ed[3].p,
+                                         (const int *)bt->d_emap[1].p, bt->ewg[1], k != 0, w, st));
+    else if (refined)
       for (int b = 0; b < C; ++b) {
         fps_plan *pl = bt->sub[bt->which[b]];
         char *wb = w + bt->ws_off[b];
@@ -369,16 +489,7 @@ fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, 
                                      r, r + pl->L.npad * pl->L.npad, pl->L.npad, st));
       }
     if ((s = run_adi_batch(bt, w, st)) != FPS_OK) return s;
-    for (int b = 0; b < C; ++b) {
-      fps_plan *pl = bt->sub[bt->which[b]];
-      const fps::Layout &L = pl->L;
-      char *wb = w + bt->ws_off[b];
-      double *Y = (double *)(wb + (refined ? pl->off_GT : pl->off_G));
-      FPS_HIP(fps::launch_finalize<double>((const double *)(wb + pl->off_O1),
-                                           (const double *)(wb + pl->off_ab),
-                                           pl->tab_dev(pl->shifts.J - 1), Y, k == 0 ? 0 : 2,
-                                           nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
-    }
+    FPS_HIP(finalize_all(bt, w, k == 0 ? 0 : 2, st));
   }
   if (bt->out_basis == FPS_OUT_NATIVE) {
     for (int b = 0; b < C; ++b) {
@@ -419,24 +530,11 @@ fps_status fps_batch_solve_adjoint(fps_batch *bt, const double *Ubar, double *Fb
       return s;
   FPS_HIP(gemm(4, nullptr));
   FPS_HIP(gemm(5, nullptr));
-  for (int b = 0; b < C; ++b) {
-    const fps_plan *pl = bt->plan_of(b);
-    char *wb = w + bt->ws_off[b];
-    FPS_HIP(fps::launch_transpose((const double *)(wb + pl->off_G), (double *)(wb + pl->off_GT),
-                                  pl->L.npad, st));
-  }
+  FPS_HIP(transpose_all(bt, w, st));
   // The same ADI map as the forward solve (self-adjoint for symmetric
-  // shifts), batched; Gbar lands in each problem's G region.
+  // shifts), batched; Gbar lands in each problem's G region (FP64 batch).
   if ((s = run_adi_batch(bt, w, st)) != FPS_OK) return s;
-  for (int b = 0; b < C; ++b) {
-    const fps_plan *pl = bt->plan_of(b);
-    const fps::Layout &L = pl->L;
-    char *wb = w + bt->ws_off[b];
-    FPS_HIP(fps::launch_finalize<double>((const double *)(wb + pl->off_O1),
-                                         (const double *)(wb + pl->off_ab),
-                                         pl->tab_dev(pl->shifts.J - 1), (double *)(wb + pl->off_G), 0,
-                                         nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
-  }
+  FPS_HIP(finalize_all(bt, w, 0, st));
   // Fbar of every problem: the output-map GEMMs (two table launches).
   FPS_HIP(gemm(6, (char *)Fbar));
   FPS_HIP(gemm(7, (char *)Fbar));

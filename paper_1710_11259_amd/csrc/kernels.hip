@@ -8,13 +8,14 @@ namespace fps {
 
 namespace {
 
+// Entry (r, col) of the final pass (k_finalize's grid: col = x thread
+// index, r = row).
 template <typename T>
-__global__ void k_finalize(const T *__restrict__ x, const double *__restrict__ ab,
-                           const double *__restrict__ tab, double *__restrict__ out, int mode,
-                           const double *__restrict__ sinv, int64_t n, int64_t npad, int64_t mp0,
-                           int64_t mstride, int64_t ncmax) {
-  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t r = blockIdx.y;
+__device__ __forceinline__ void finalize_at(const T *__restrict__ x, const double *__restrict__ ab,
+                                            const double *__restrict__ tab, double *__restrict__ out,
+                                            int mode, const double *__restrict__ sinv, int64_t n,
+                                            int64_t npad, int64_t mp0, int64_t mstride,
+                                            int64_t ncmax, int64_t col, int64_t r) {
   if (col >= npad) return;
   const int s = r >= mp0 ? 1 : 0;
   const int64_t k = r - (s ? mp0 : 0);
@@ -38,15 +39,25 @@ __global__ void k_finalize(const T *__restrict__ x, const double *__restrict__ a
   out[i * n + j] = sinv ? v * sinv[i] * sinv[j] : v;
 }
 
-__global__ __launch_bounds__(256) void k_residual(const double *__restrict__ G,
-                                                  const double *__restrict__ Y,
-                                                  const double *__restrict__ dv,
-                                                  const double *__restrict__ ev,
-                                                  float *__restrict__ r, float *__restrict__ rT,
-                                                  int64_t npad, double ax, double ay) {
-  __shared__ float tile[64][65];
+template <typename T>
+__global__ void k_finalize(const T *__restrict__ x, const double *__restrict__ ab,
+                           const double *__restrict__ tab, double *__restrict__ out, int mode,
+                           const double *__restrict__ sinv, int64_t n, int64_t npad, int64_t mp0,
+                           int64_t mstride, int64_t ncmax) {
+  finalize_at<T>(x, ab, tab, out, mode, sinv, n, npad, mp0, mstride, ncmax,
+                 (int64_t)blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+}
+
+// 64 x 64 tile (column tile bx, row tile by) of the residual; 256 threads.
+__device__ __forceinline__ void residual_tile(const double *__restrict__ G,
+                                              const double *__restrict__ Y,
+                                              const double *__restrict__ dv,
+                                              const double *__restrict__ ev,
+                                              float *__restrict__ r, float *__restrict__ rT,
+                                              int64_t npad, double ax, double ay, int64_t bx,
+                                              int64_t by, float (*tile)[65]) {
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int64_t r0 = by * 64, c0 = bx * 64;
   const int64_t q = c0 + tx;
   const double dq = dv[q], eq = ev[q], eql = q > 0 ? ev[q - 1] : 0.0;
   for (int rr = ty; rr < 64; rr += 4) {
@@ -67,6 +78,16 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ G,
   for (int rr = ty; rr < 64; rr += 4) rT[(c0 + rr) * npad + r0 + tx] = tile[tx][rr];
 }
 
+__global__ __launch_bounds__(256) void k_residual(const double *__restrict__ G,
+                                                  const double *__restrict__ Y,
+                                                  const double *__restrict__ dv,
+                                                  const double *__restrict__ ev,
+                                                  float *__restrict__ r, float *__restrict__ rT,
+                                                  int64_t npad, double ax, double ay) {
+  __shared__ float tile[64][65];
+  residual_tile(G, Y, dv, ev, r, rT, npad, ax, ay, blockIdx.x, blockIdx.y, tile);
+}
+
 __global__ void k_permute_out(const double *__restrict__ src, double *__restrict__ dst, int64_t n,
                               int64_t npad, int64_t mp0, const double *__restrict__ sinv) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,10 +99,12 @@ __global__ void k_permute_out(const double *__restrict__ src, double *__restrict
   dst[i * n + j] = v;
 }
 
-__global__ void k_permute_in(const double *__restrict__ src, double *__restrict__ dst, int64_t n,
-                             int64_t npad, int64_t mp0, const double *__restrict__ sinv) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t r = blockIdx.y;
+// Entry (r, q) of the parity-blocked copy of F (k_permute_in's grid: q = x
+// thread index, r = row).
+__device__ __forceinline__ void permute_in_at(const double *__restrict__ src,
+                                              double *__restrict__ dst, int64_t n, int64_t npad,
+                                              int64_t mp0, const double *__restrict__ sinv,
+                                              int64_t q, int64_t r) {
   if (q >= npad) return;
   const int s = r >= mp0 ? 1 : 0, t = q >= mp0 ? 1 : 0;
   const int64_t i = 2 * (r - (s ? mp0 : 0)) + s, j = 2 * (q - (t ? mp0 : 0)) + t;
@@ -93,16 +116,85 @@ __global__ void k_permute_in(const double *__restrict__ src, double *__restrict_
   dst[r * npad + q] = v;
 }
 
+__global__ void k_permute_in(const double *__restrict__ src, double *__restrict__ dst, int64_t n,
+                             int64_t npad, int64_t mp0, const double *__restrict__ sinv) {
+  permute_in_at(src, dst, n, npad, mp0, sinv, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                blockIdx.y);
+}
+
+// 64 x 64 tile (column tile bx, row tile by) of an npad x npad transpose;
+// 256 threads.
+__device__ __forceinline__ void transpose_tile(const double *__restrict__ src,
+                                               double *__restrict__ dst, int64_t npad, int64_t bx,
+                                               int64_t by, double (*tile)[65]) {
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  const int64_t r0 = by * 64, c0 = bx * 64;
+  for (int i = ty; i < 64; i += 4) tile[i][tx] = src[(r0 + i) * npad + c0 + tx];
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) dst[(c0 + i) * npad + r0 + tx] = tile[tx][i];
+}
+
 __global__ __launch_bounds__(256) void k_transpose(const double *__restrict__ src,
                                                    double *__restrict__ dst, int64_t npad) {
   __shared__ double tile[64][65];
   src += (int64_t)blockIdx.z * npad * npad;
   dst += (int64_t)blockIdx.z * npad * npad;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-  for (int i = ty; i < 64; i += 4) tile[i][tx] = src[(r0 + i) * npad + c0 + tx];
-  __syncthreads();
-  for (int i = ty; i < 64; i += 4) dst[(c0 + i) * npad + r0 + tx] = tile[tx][i];
+  transpose_tile(src, dst, npad, blockIdx.x, blockIdx.y, tile);
+}
+
+// --- batched forms: workgroup g works for problem wg_prob[g] -------------
+
+__device__ __forceinline__ intptr_t elem_base(int id, char *ws, const double *in) {
+  return id == 1 ? (intptr_t)ws : id == 2 ? (intptr_t)in : 0;
+}
+
+__global__ __launch_bounds__(256) void k_permute_in_batch(const ElemDesc *__restrict__ d,
+                                                          const int *__restrict__ wg_prob,
+                                                          const double *in, char *ws) {
+  const int g = blockIdx.x;
+  const ElemDesc &e = d[__builtin_amdgcn_readfirstlane(wg_prob[g])];
+  const int local = g - e.wg_start;
+  const double *src = (const double *)(elem_base(e.sbase, ws, in) + e.src);
+  double *dst = (double *)(elem_base(e.dbase, ws, in) + e.dst);
+  permute_in_at(src, dst, e.n, e.npad, e.mp0, nullptr,
+                (int64_t)(local % e.nbx) * 256 + threadIdx.x, local / e.nbx);
+}
+
+__global__ __launch_bounds__(256) void k_transpose_batch(const ElemDesc *__restrict__ d,
+                                                         const int *__restrict__ wg_prob,
+                                                         char *ws) {
+  __shared__ double tile[64][65];
+  const int g = blockIdx.x;
+  const ElemDesc &e = d[__builtin_amdgcn_readfirstlane(wg_prob[g])];
+  const int local = g - e.wg_start;
+  const double *src = (const double *)(elem_base(e.sbase, ws, nullptr) + e.src);
+  double *dst = (double *)(elem_base(e.dbase, ws, nullptr) + e.dst);
+  transpose_tile(src, dst, e.npad, local % e.nbx, local / e.nbx, tile);
+}
+
+__global__ __launch_bounds__(256) void k_residual_batch(const ElemDesc *__restrict__ d,
+                                                        const int *__restrict__ wg_prob,
+                                                        int with_y, char *ws) {
+  __shared__ float tile[64][65];
+  const int g = blockIdx.x;
+  const ElemDesc &e = d[__builtin_amdgcn_readfirstlane(wg_prob[g])];
+  const int local = g - e.wg_start;
+  float *r = (float *)(ws + e.dst);
+  residual_tile((const double *)(ws + e.src), with_y ? (const double *)(ws + e.ab) : nullptr, e.tab,
+                e.ev, r, r + e.npad * e.npad, e.npad, 1.0, 1.0, local % e.nbx, local / e.nbx, tile);
+}
+
+__global__ __launch_bounds__(256) void k_finalize_batch(const ElemDesc *__restrict__ d,
+                                                        const int *__restrict__ wg_prob, int mode,
+                                                        char *ws) {
+  const int g = blockIdx.x;
+  const ElemDesc &e = d[__builtin_amdgcn_readfirstlane(wg_prob[g])];
+  const int local = g - e.wg_start;
+  const double *x = (const double *)(elem_base(e.sbase, ws, nullptr) + e.src);
+  double *out = (double *)(elem_base(e.dbase, ws, nullptr) + e.dst);
+  finalize_at<double>(x, (const double *)(ws + e.ab), e.tab, out, mode, nullptr, e.n, e.npad,
+                      e.mp0, e.mstride, e.ncmax, (int64_t)(local % e.nbx) * 256 + threadIdx.x,
+                      local / e.nbx);
 }
 
 __global__ void k_fill(double *__restrict__ dst, int64_t count, double v) {
@@ -307,6 +399,36 @@ hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStr
   if (npad % 64 != 0 || nbatch < 1) return hipErrorInvalidValue;
   dim3 grid((unsigned)(npad / 64), (unsigned)(npad / 64), (unsigned)nbatch);
   hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, src, dst, npad);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_in_batch(const ElemDesc *d, const int *wg_prob, int nwg, const double *in,
+                                   char *ws, hipStream_t st) {
+  if (nwg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute_in_batch, dim3((unsigned)nwg), dim3(256), 0, st, d, wg_prob, in, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_batch(const ElemDesc *d, const int *wg_prob, int nwg, char *ws,
+                                  hipStream_t st) {
+  if (nwg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_batch, dim3((unsigned)nwg), dim3(256), 0, st, d, wg_prob, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_batch(const ElemDesc *d, const int *wg_prob, int nwg, bool with_y,
+                                 char *ws, hipStream_t st) {
+  if (nwg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_residual_batch, dim3((unsigned)nwg), dim3(256), 0, st, d, wg_prob,
+                     with_y ? 1 : 0, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const ElemDesc *d, const int *wg_prob, int nwg, int mode, char *ws,
+                                 hipStream_t st) {
+  if (nwg <= 0) return hipSuccess;
+  if (mode != 0 && mode != 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finalize_batch, dim3((unsigned)nwg), dim3(256), 0, st, d, wg_prob, mode, ws);
   return hipGetLastError();
 }
 
