@@ -205,19 +205,51 @@ __global__ __launch_bounds__(256, 2) void k_gemm_table(const GemmDesc *__restric
 // Columns tn.. of every row of a table problem: one wavefront per row,
 // lanes striding over k with coalesced loads of the row, then a butterfly
 // sum across the wavefront (fixed order, so the result is reproducible).
-// kRows rows per wavefront iteration keep their loads in flight together.
-__global__ __launch_bounds__(256) void k_gemm_edge_cols(const GemmDesc *__restrict__ d, int64_t tn,
-                                                        char *ws, char *out) {
-  constexpr int kRows = 4;
-  const GemmDesc &e = d[blockIdx.y];
+// kRows rows per wavefront iteration keep their loads in flight together;
+// rows with k contiguous, even K and a 16-byte aligned start are read two
+// k at a time (kVecRows rows in flight).  Workgroup b serves problem
+// b % nprob, so problems that read different parts of the same rows (the
+// parity blocks of one array) read them at the same time.
+__global__ __launch_bounds__(256) void k_gemm_edge_cols(const GemmDesc *__restrict__ d, int nprob,
+                                                        int64_t tn, char *ws, char *out) {
+  constexpr int kRows = 4, kVecRows = 8;
+  const GemmDesc &e = d[blockIdx.x % nprob];
   const double *__restrict__ A = rebase(e.p.A, e.abase, ws, out);
   const double *__restrict__ B = rebase(e.p.B, e.bbase, ws, out);
   double *__restrict__ C = (double *)rebase(e.p.C, e.cbase, ws, out);
   const int64_t M = e.p.M, N = e.p.N, K = e.p.K;
   const int64_t nn = N < tn ? N : tn;
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  const int64_t wave = (int64_t)(blockIdx.x / nprob) * 4 + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)(gridDim.x / nprob) * 4;
+  if (e.p.sak == 1 && !(e.p.sai & 1) && !(K & 1) && !((uintptr_t)A & 15)) {
+    for (int64_t i0 = wave * kVecRows; i0 < M; i0 += nwaves * kVecRows) {
+      for (int64_t j = nn; j < N; ++j) {
+        double acc[kVecRows];
+#pragma unroll
+        for (int r = 0; r < kVecRows; ++r) acc[r] = 0.0;
+        for (int64_t k = 2 * lane; k < K; k += 128) {
+          const double b0 = B[k * e.p.sbk + j * e.p.sbj], b1 = B[(k + 1) * e.p.sbk + j * e.p.sbj];
+          dbl2 a[kVecRows];
+#pragma unroll
+          for (int r = 0; r < kVecRows; ++r) {
+            const int64_t i = i0 + r < M ? i0 + r : M - 1;
+            a[r] = *(const dbl2 *)(A + i * e.p.sai + k);
+          }
+#pragma unroll
+          for (int r = 0; r < kVecRows; ++r) acc[r] = fma(a[r].y, b1, fma(a[r].x, b0, acc[r]));
+        }
+#pragma unroll
+        for (int r = 0; r < kVecRows; ++r) {
+          double v = acc[r];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+          if (lane == 0 && i0 + r < M) C[(i0 + r) * e.p.sci + j * e.p.scj] = v;
+        }
+      }
+    }
+    return;
+  }
   for (int64_t i0 = wave * kRows; i0 < M; i0 += nwaves * kRows) {
     for (int64_t j = nn; j < N; ++j) {
       double acc[kRows];
@@ -247,7 +279,7 @@ __global__ __launch_bounds__(256) void k_gemm_edge_cols(const GemmDesc *__restri
 hipError_t launch_gemm_edge_cols(const GemmDesc *d, int nprob, int64_t tn, int nblk, char *ws,
                                  char *out, hipStream_t st) {
   if (nprob <= 0 || nblk <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm_edge_cols, dim3((unsigned)nblk, (unsigned)nprob), dim3(256), 0, st, d,
+  hipLaunchKernelGGL(k_gemm_edge_cols, dim3((unsigned)(nblk * nprob)), dim3(256), 0, st, d, nprob,
                      tn, ws, out);
   return hipGetLastError();
 }

@@ -300,8 +300,10 @@ constexpr int kGemmTile = 128;
 // The columns tn.. (a thin edge past whole tiles, whose MFMA tiles would be
 // almost empty) of every row of each table problem, in plain FP64 FMAs:
 // one wavefront per row with coalesced loads along k and a fixed-order sum
-// across the wavefront; problems without triangular structure only; grid
-// (nblk workgroups of 4 wavefronts, 4 rows each per iteration; nprob).
+// across the wavefront; problems without triangular structure only; nblk
+// workgroups of 4 wavefronts per problem, interleaved (workgroup b serves
+// problem b % nprob), 4 rows per wavefront iteration (8 on the vector path
+// for k-contiguous, 16-byte aligned rows).
 hipError_t launch_gemm_edge_cols(const GemmDesc *d, int nprob, int64_t tn, int nblk, char *ws,
                                  char *out, hipStream_t st);
 // Leading extent of a dimension split off a thin edge: x less its last
