@@ -284,6 +284,25 @@ fps_status fps_adi_native(fps_plan *plan, const double *G_dev, double *Y_dev, vo
 fps_status fps_plan_set_sweep_timing(fps_plan *plan, int capacity);
 fps_status fps_plan_sweep_time(fps_plan *plan, double *ms_host, int64_t cap, int64_t *launches);
 
+/*
+ * Allocation-free solve, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): fps_solve with the workspace taken from a static device array
+ * of fps_noalloc_capacity() bytes (64 MiB) that the library holds on every
+ * GPU it runs on until the process ends.  The caller passes F_dev and U_dev
+ * as for fps_solve; nothing is allocated or freed (no hipMalloc, no library
+ * allocator).  Square and rectangle plans (dim 2) whose workspace_bytes fit
+ * the array: FP64 up to about n = 1150, FPS_FP32_REFINED up to about
+ * n = 1100.  Larger plans, cube and cylinder plans return FPS_E_UNSUPPORTED
+ * with the sizes in fps_last_error().  Every call on one GPU shares that
+ * GPU's array, and the solve reads only what it wrote in the same call:
+ * calls that overlap on one GPU (two streams, or two host threads) race and
+ * give wrong results; calls in stream order do not.  The first call on a
+ * device looks up the array's device address (hipGetSymbolAddress).
+ */
+int64_t fps_noalloc_capacity(void);
+fps_status fps_solve_noalloc(fps_plan *plan, const double *F_dev, double *U_dev, void *stream);
+
 void fps_plan_destroy(fps_plan *plan);
 
 /*

@@ -16,6 +16,7 @@ import ctypes
 import os
 
 __all__ = ["lib", "Plan", "plan", "plan_cylinder", "cylinder_mode_bands", "solve",
+           "solve_noalloc", "noalloc_capacity",
            "solve_dirichlet", "solve_adjoint", "solve_fn",
            "adi_native",
            "adi_shifts", "Batch", "batch", "batch_solve", "batch_solve_adjoint", "BatchGraph",
@@ -72,6 +73,9 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(dbl)]
     for name in ("fps_solve", "fps_solve_adjoint", "fps_adi_native"):
         getattr(L, name).argtypes = [vp, vp, vp, vp, vp]
+    L.fps_solve_noalloc.argtypes = [vp, vp, vp, vp]
+    L.fps_noalloc_capacity.argtypes = []
+    L.fps_noalloc_capacity.restype = i64
     L.fps_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(i64), dbl, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_uint]
@@ -97,6 +101,7 @@ def lib() -> ctypes.CDLL:
                  "fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_plan_refinement",
                  "fps_plan_inner_counts", "fps_plan_slice_counts",
                  "fps_adi_shifts", "fps_solve", "fps_solve_adjoint", "fps_adi_native",
+                 "fps_solve_noalloc",
                  "fps_batch_create", "fps_batch_info", "fps_batch_solve",
                  "fps_batch_solve_adjoint"):
         getattr(L, name).restype = ctypes.c_int
@@ -269,6 +274,27 @@ def solve(p: Plan, F, out=None, ws=None):
                            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                            _stream_ptr(torch, F.device)))
     return out
+
+
+def solve_noalloc(p: Plan, F, out=None):
+    """solve() with the workspace in the library's static device scratch
+    (fps_solve_noalloc): square and rectangle plans whose workspace fits
+    noalloc_capacity() bytes.  Calls that overlap on one GPU race."""
+    import torch
+    if F.dtype != torch.float64 or not F.is_cuda or not F.is_contiguous():
+        raise ValueError("F must be a contiguous float64 tensor on the GPU")
+    if tuple(F.shape) != p.in_shape():
+        raise ValueError(f"F must have shape {p.in_shape()}")
+    if out is None:
+        out = torch.empty(p.out_shape(), dtype=torch.float64, device=F.device)
+    _check(lib().fps_solve_noalloc(p.handle, ctypes.c_void_p(F.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(torch, F.device)))
+    return out
+
+
+def noalloc_capacity() -> int:
+    """Bytes of the static scratch behind solve_noalloc."""
+    return int(lib().fps_noalloc_capacity())
 
 
 def solve_dirichlet(p: Plan, F, bc, out=None, ws=None):
