@@ -654,10 +654,16 @@ def main() -> int:
         e1.record(stream)
         torch.cuda.synchronize()
         ms_r = e0.elapsed_time(e1) / args.steps
+        rsteps, rtols = pr.round_steps()
         forms["fp32_refined"] = {"ms_per_step": ms_r, "dof_per_s": dof / (ms_r * 1e-3),
                                  "speedup_vs_fp64": ms_per_step / ms_r,
-                                 "inner_J": pr.J, "rounds": pr.rounds,
-                                 "f32_steps_per_round": pr.f32_steps}
+                                 "rounds": pr.rounds, "round_steps": rsteps, "round_tols": rtols,
+                                 "f32_steps": pr.f32_steps,
+                                 "fp64_J": J,
+                                 "sweep_bytes_per_dof": {
+                                     "fp32_refined": 20 * pr.f32_steps
+                                     + 40 * (sum(rsteps) - pr.f32_steps),
+                                     "fp64": 40 * J}}
         del wsr
         if args.only is None:
             forms["batched"] = bench_batch(fps, workloads, torch, args.tol, tight=tight)

@@ -59,10 +59,18 @@ typedef enum { FPS_BC_DIRICHLET_ZERO = 0 } fps_bc;
 /* FPS_FP64: every ADI half-sweep stores and computes in float64.
  * FPS_FP32_REFINED: iterative refinement (precision form; not in the paper).
  * Each round forms the residual r = G - (A~ Y + Y A~) in float64, stores it
- * in float32, runs an inner ADI to 1e-7 and adds its result to the float64
- * Y.  The inner ADI's steps with |p_j| >= 1e-2 store their sweep arrays in
- * float32, the small-shift steps in float64 (float storage there stalls the
- * refinement); every arithmetic operation and every table stays float64. */
+ * in float32, runs an inner ADI on A~ dY + dY A~ = r that stores every sweep
+ * array (and its result dY) in float32, and adds dY to the float64 Y.  Every
+ * arithmetic operation and every table stays float64.  The inner ADI applies
+ * its shifts in order of increasing |p_j| (with the opposite order float
+ * storage stalls or diverges from n ~ 256 on).  Rounds: inner tolerance 1e-5
+ * (on smooth data a round contracts the error by about 1e-5) until one more
+ * such round would pass tol, then a last round to 0.1 tol / (error
+ * reached); at tol = 1e-13: 1e-5, 1e-5, 1e-4 (fps_plan_rounds).  Plans
+ * created with FPS_PLAN_DIRICHLET, whose lift puts O(1) content into the
+ * highest modes of G's first two rows and columns, run two float rounds
+ * and then one round with float64 storage (float rounds contract such data
+ * by only ~1e-3). */
 typedef enum { FPS_FP64 = 0, FPS_FP32_REFINED = 1 } fps_prec;
 
 typedef enum { FPS_OUT_CHEB = 0, FPS_OUT_NATIVE = 1 } fps_out;
@@ -166,9 +174,15 @@ fps_status fps_plan_info(const fps_plan *plan, int *J, int64_t *workspace_bytes,
                          int64_t *out_entries);
 
 /* Refinement structure of a plan: the number of rounds (1 for FPS_FP64) and
- * the number of inner ADI steps that store their sweep arrays in float32 (0
- * for FPS_FP64).  Either pointer may be null. */
+ * the number of inner ADI steps, summed over the rounds, that store their
+ * sweep arrays in float32 (0 for FPS_FP64).  Either pointer may be null. */
 fps_status fps_plan_refinement(const fps_plan *plan, int *rounds, int *f32_steps);
+
+/* The ADI steps and the inner tolerance of each refinement round (host
+ * arrays, min(rounds, cap) entries; either may be null).  FPS_FP64 square
+ * and rectangle plans have one round: J and tol.  FPS_E_STATE for cube and
+ * cylinder plans. */
+fps_status fps_plan_rounds(const fps_plan *plan, int *steps_host, double *tol_host, int cap);
 
 /* Cube plans (dim = 3, nested ADI): the number of inner ADI steps of each of
  * the J outer steps (the (x, y) half-step of outer step i runs counts[i]
@@ -186,11 +200,11 @@ fps_status fps_plan_slice_counts(const fps_plan *plan, int *counts, int cap, int
  * applies them (q_j = -p_j for the square, Sec. 3.3 P2 with B~ = -A~; for
  * the cube, the outer shifts p_i in [-2/delta, -2] of the split of (5.2)
  * into H = K_x + K_y and V = K_z, K = -A~^-1, whose partners q_i lie in
- * [1, 1/delta]).  FP64 square and rectangle plans apply the shifts of
+ * [1, 1/delta]).  Square and rectangle plans apply the shifts of
  * Theorem 2.1 in order of increasing |p_j|: the iterate is the same in exact
  * arithmetic, and the large-shift steps then damp the rounding that the
- * small-shift solves magnify.  FP32_REFINED plans keep the order of
- * decreasing |p_j| (their float-stored large-shift steps come first). */
+ * small-shift solves magnify.  FP32_REFINED plans: the shifts of round 0
+ * (J = fps_plan_info's J). */
 fps_status fps_plan_shifts(const fps_plan *plan, double *p_host);
 
 /* Copy both shift sequences p_0..p_{J-1} and q_0..q_{J-1} (Theorem 2.1) to
@@ -314,10 +328,9 @@ void fps_plan_destroy(fps_plan *plan);
  * problems still iterating at that step), so a batch enqueues about 4 J_max
  * sweep/carry launches plus a fixed number of map launches per problem.
  *   dim must be 2; 1 <= count <= 65536; every n in [1, 65536]; tol, prec,
- *   out_basis and flags as for fps_plan_create.  For FPS_FP32_REFINED the
- *   inner ADI step j stores in float for every problem iff j < the least
- *   float-step count of the problems' own plans (so each problem keeps the
- *   convergence of its own plan).
+ *   out_basis and flags as for fps_plan_create.  FPS_FP32_REFINED batches
+ *   run the rounds of their plans (the same round tolerances for every
+ *   problem), one batched inner ADI per round.
  * Data: F_dev packs the problems' n x n inputs back to back in the given
  * order (row-major each, offsets sum of n_b^2); U_dev packs the outputs
  * ((n_b+2)^2 or n_b^2 entries each).  fps_batch_info gives the totals and the

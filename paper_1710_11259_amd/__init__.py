@@ -66,6 +66,8 @@ def lib() -> ctypes.CDLL:
     L.fps_plan_refinement.argtypes = [vp, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int)]
     L.fps_plan_inner_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+    L.fps_plan_rounds.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(dbl),
+                                  ctypes.c_int]
     L.fps_plan_slice_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]
     L.fps_adi_shifts.argtypes = [dbl, dbl, dbl, dbl, dbl, ctypes.c_int,
@@ -99,7 +101,7 @@ def lib() -> ctypes.CDLL:
                  "fps_plan_create", "fps_plan_create_rect", "fps_plan_shift_pairs",
                  "fps_solve_dirichlet",
                  "fps_plan_create", "fps_plan_info", "fps_plan_shifts", "fps_plan_refinement",
-                 "fps_plan_inner_counts", "fps_plan_slice_counts",
+                 "fps_plan_inner_counts", "fps_plan_slice_counts", "fps_plan_rounds",
                  "fps_adi_shifts", "fps_solve", "fps_solve_adjoint", "fps_adi_native",
                  "fps_solve_noalloc",
                  "fps_batch_create", "fps_batch_info", "fps_batch_solve",
@@ -187,6 +189,14 @@ class Plan:
         c = (ctypes.c_int * max(k.value, 1))()
         _check(lib().fps_plan_slice_counts(self._h, c, k.value, ctypes.byref(k)))
         return list(c)[: k.value]
+
+    def round_steps(self):
+        """Square and rectangle plans: (steps, inner tolerance) of each
+        refinement round (one round for FP64 plans)."""
+        st = (ctypes.c_int * self.rounds)()
+        tl = (ctypes.c_double * self.rounds)()
+        _check(lib().fps_plan_rounds(self._h, st, tl, self.rounds))
+        return list(st), list(tl)
 
     def inner_counts(self):
         """Cube plans: inner ADI steps per outer step."""

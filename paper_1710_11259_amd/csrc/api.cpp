@@ -52,22 +52,25 @@ void release_events(fps_plan *pl) {
   pl->ev_used = 0;
 }
 
-// Runs the 2J half-sweeps of Algorithm 2.  `Gterm` is the right-hand side G
+// Runs the 2J half-sweeps of Algorithm 2 with the shifts `sh`, whose step j
+// uses the plan's tables of step base + j.  `Gterm` is the right-hand side G
 // (parity-blocked, npad x npad) and `GTin` its transpose, both of storage
 // type g_f32; O0, O1 are the ping-pong arrays (room for npad^2 doubles
-// each).  Step j stores its outputs in float when pl->f32step[j] is set, so
-// a step reads its input in the type the previous step wrote it.  Leaves the
-// final chunk-local solution (double) in O1 and its chunk carries in ab, to
-// finalize with the tables of the last second half-step (pl->tab2(J - 1)).
-fps_status run_adi(fps_plan *pl, const void *Gterm, const void *GTin, int g_f32, void *O0,
-                   void *O1, char *ws, hipStream_t st) {
+// each).  With f32 set every step stores its outputs in float (refinement
+// rounds, including the final chunk-local solution: a later round corrects
+// its rounding, and the last round's correction is small), else in double.
+// Leaves the final chunk-local solution in O1 and its chunk carries in ab,
+// to finalize with the tables of the last second half-step
+// (pl->tab2(base + J - 1)).
+fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *Gterm,
+                   const void *GTin, int g_f32, int f32, void *O0, void *O1, char *ws,
+                   hipStream_t st) {
   const fps::Layout &L = pl->L;
-  const int J = pl->shifts.J;
-  const std::vector<double> &p = pl->shifts.p, &q = pl->shifts.q;
+  const int J = sh.J;
+  const std::vector<double> &p = sh.p, &q = sh.q;
   double *lv = (double *)(ws + pl->off_lv);
   double *ab = (double *)(ws + pl->off_ab);
   const int nc0 = (int)L.nc[0], nc1 = (int)L.nc[1];
-  auto f32 = [&](int j) { return j < (int)pl->f32step.size() && pl->f32step[j] ? 1 : 0; };
 
   fps::SweepArgs A{};
   A.npad = L.npad;
@@ -95,77 +98,88 @@ fps_status run_adi(fps_plan *pl, const void *Gterm, const void *GTin, int g_f32,
   for (int j = 0; j < J; ++j) {
     const double s1 = pl->rect ? p[j] - q[j] : 2.0 * p[j];
     A.in = j == 0 ? GTin : (const void *)O1;
-    A.in_f32 = j == 0 ? g_f32 : f32(j);
+    A.in_f32 = j == 0 ? g_f32 : f32;
     A.in_scale = j == 0 ? -1.0 : 1.0;
     A.ab_prev = j == 0 ? nullptr : ab;
-    A.tab_prev = j == 0 ? nullptr : pl->tab_dev(pl->tab2(j - 1));
+    A.tab_prev = j == 0 ? nullptr : pl->tab_dev(pl->tab2(base + j - 1));
     A.g = nullptr;
     A.g_f32 = 0;
     A.sg = 0.0;
-    A.tab = pl->tab_dev(pl->tab1(j));
-    A.l1 = pl->l1_dev(pl->tab1(j));
+    A.tab = pl->tab_dev(pl->tab1(base + j));
+    A.l1 = pl->l1_dev(pl->tab1(base + j));
     A.sigma = s1;
     A.out = O0;
-    A.out_f32 = f32(j);
+    A.out_f32 = f32;
     A.out_mode = 0;
     FPS_HIP(timed_sweep(pl, A, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab1(j)), ab, -A.sigma, L.npad, nc0, nc1,
-                               L.ncmax, st));
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab1(base + j)), ab, -A.sigma, L.npad, nc0,
+                               nc1, L.ncmax, st));
     fps::SweepArgs B = A;
     const bool last = j == J - 1;
     B.in = O0;
-    B.in_f32 = f32(j);
+    B.in_f32 = f32;
     B.in_scale = 1.0;
     B.ab_prev = ab;
     B.tab_prev = A.tab;
     B.g = Gterm;
     B.g_f32 = g_f32;
     B.sg = 1.0;
-    B.tab = pl->tab_dev(pl->tab2(j));
-    B.l1 = pl->l1_dev(pl->tab2(j));
+    B.tab = pl->tab_dev(pl->tab2(base + j));
+    B.l1 = pl->l1_dev(pl->tab2(base + j));
     B.sigma = last ? 0.0 : (pl->rect ? p[j + 1] - q[j] : p[j] + p[j + 1]);
     B.out = O1;
-    B.out_f32 = last ? 0 : f32(j + 1);
+    B.out_f32 = f32;
     B.out_mode = last ? 1 : 0;
     FPS_HIP(timed_sweep(pl, B, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab2(j)), ab, last ? 1.0 : -B.sigma, L.npad,
-                               nc0, nc1, L.ncmax, st));
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab2(base + j)), ab, last ? 1.0 : -B.sigma,
+                               L.npad, nc0, nc1, L.ncmax, st));
   }
   return FPS_OK;
 }
 
 // The symmetric-form solution Y (parity-blocked FP64, npad x npad) of
 // A~ Y + Y A~ = G for G in ws.G (and G^T in ws.GT): plain FP64 ADI, or
-// iterative refinement whose inner ADI stores its sweep arrays in float.
+// iterative refinement whose inner ADIs store their sweep arrays in float.
 // Returns Y's location.
 fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout) {
   const fps::Layout &L = pl->L;
-  const int J = pl->shifts.J;
   double *G = (double *)(w + pl->off_G);
   double *ab = (double *)(w + pl->off_ab);
   fps_status s;
   if (pl->prec == FPS_FP64) {
+    const int J = pl->shifts.J;
     double *GT = (double *)(w + pl->off_GT);
-    if ((s = run_adi(pl, G, GT, 0, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK) return s;
+    if ((s = run_adi(pl, pl->shifts, 0, G, GT, 0, 0, w + pl->off_O0, w + pl->off_O1, w, st)) !=
+        FPS_OK)
+      return s;
     FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, pl->tab_dev(pl->tab2(J - 1)),
                                          G, 0, nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax,
                                          st));
     *Yout = G;  // G is no longer needed
     return FPS_OK;
   }
-  // Refinement: Y <- Y + ADI_inner(G - (A~ Y + Y A~)); the residual is formed
-  // in FP64 and stored in float (with its transpose), the inner ADI stores
-  // its large-shift steps in float.
+  // Refinement: Y <- Y + ADI_k(G - (A~ Y + Y A~)) for the rounds k; the
+  // residual is formed in FP64 and stored in float (with its transpose),
+  // and the inner sweeps of a float round store their arrays in float.
   double *Y = (double *)(w + pl->off_GT);
   float *r = (float *)(w + pl->off_R), *rT = r + L.npad * L.npad;
   for (int k = 0; k < pl->rounds; ++k) {
+    const fps::ShiftSet &sh = pl->rsh[(size_t)k];
+    const int f32 = pl->rf32[(size_t)k];
+    const double *tab = pl->tab_dev(pl->tab2(pl->rbase[(size_t)k] + sh.J - 1));
     FPS_HIP(fps::launch_residual(G, k == 0 ? nullptr : Y, (const double *)pl->d_sdiag.p,
                                  (const double *)pl->d_soff.p, r, rT, L.npad, st, pl->sx2,
                                  pl->sy2));
-    if ((s = run_adi(pl, r, rT, 1, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK) return s;
-    FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, pl->tab_dev(pl->tab2(J - 1)),
-                                         Y, k == 0 ? 0 : 2, nullptr, L.n, L.npad, L.mp[0],
-                                         L.mstride, L.ncmax, st));
+    if ((s = run_adi(pl, sh, pl->rbase[(size_t)k], r, rT, 1, f32, w + pl->off_O0,
+                     w + pl->off_O1, w, st)) != FPS_OK)
+      return s;
+    const int mode = k == 0 ? 0 : 2;
+    if (f32)
+      FPS_HIP(fps::launch_finalize<float>((const float *)(w + pl->off_O1), ab, tab, Y, mode,
+                                          nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
+    else
+      FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, tab, Y, mode,
+                                           nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
   }
   *Yout = Y;
   return FPS_OK;
@@ -311,6 +325,36 @@ fps_status plan_common(fps_plan **out, int dim, int64_t n, int bc, double tol, i
   return FPS_OK;
 }
 
+std::vector<RefineRound> refine_schedule(double tol, bool dirichlet) {
+  // Float rounds solve A~ dY + dY A~ = r_k to kRoundTol with every sweep
+  // array stored in float.  On smooth right-hand sides such a round
+  // contracts the error by about kContract (emulated at n = 64 .. 4096:
+  // 5e-6 to 8e-6 per round, down to the FP64 level near 1e-14); the last
+  // round only needs to take the error reached so far to tol, with a
+  // factor 10 of margin.
+  constexpr double kRoundTol = 1e-5, kContract = 1e-5;
+  std::vector<RefineRound> t;
+  double reached = 1.0;
+  if (dirichlet && tol < kRoundTol) {
+    // A Dirichlet lift puts O(1) content into every column of rows 0, 1 and
+    // every row of columns 0, 1 of G; float rounds then contract by only
+    // ~1e-3 after the first two (emulated: n = 1024, relative U error
+    // 7.7e-6, 1.3e-9, 3.2e-12; the [0, 10] x [0, 1] box 5.9e-6, 9.6e-9, 1.9e-11).
+    // Two float rounds leave <= ~5e-8 (symmetrized Y), and one FP64 round
+    // finishes.
+    t.push_back({kRoundTol, true});
+    if (tol < 1e-9) t.push_back({kRoundTol, true});
+    t.push_back({std::max(tol, std::min(kRoundTol, tol / 5e-8)), false});
+    return t;
+  }
+  while (reached * kContract > tol * (1.0 + 1e-9)) {
+    t.push_back({kRoundTol, true});
+    reached *= kContract;
+  }
+  t.push_back({std::min(0.1, std::max(0.1 * tol / reached, tol)), true});
+  return t;
+}
+
 // Square or rectangle plan (common fields, and for a rectangle rect / box /
 // sx2 / sy2, already set): shifts, sweep tables, coefficient maps,
 // workspace layout, and the device copies unless host-only.
@@ -321,70 +365,64 @@ fps_status plan2d_build(fps_plan *pl) {
   const double tol = pl->tol;
   // Lemma B.1: sigma(A~) in [-1, -1/(30 n^4)]; sigma(B~) = sigma(-A~).
   const double delta = 1.0 / (30.0 * (double)n * (double)n * (double)n * (double)n);
-  // FP32_REFINED: each refinement round runs an ADI to kInnerTol and the
-  // round count is the least R with kRoundFactor^R <= tol.  Float storage is
-  // used only by the steps with large shifts (|p_j| >= kF32MinShift for the
-  // square): a stored value enters the next solve through (A~ + p_j I)^-1,
-  // which magnifies its rounding error by up to about 1/|p_j| against the
-  // top modes of the residual the round corrects; storing the small-shift
-  // steps in float stalls or reverses the refinement for n >= 256, while
-  // this split contracts the error by <= 1e-7 per round.
-  constexpr double kInnerTol = 1e-7, kRoundFactor = 3e-7, kF32MinShift = 1e-2;
-  double adi_tol = tol;
-  if (prec == FPS_FP32_REFINED) {
-    pl->inner_tol = tol > kInnerTol ? tol : kInnerTol;
-    adi_tol = pl->inner_tol;
-    pl->rounds = std::max(1, (int)std::ceil(std::log(tol) / std::log(kRoundFactor) - 1e-9));
-  }
   std::string err;
   double ea = -1.0, eb = -delta;  // enclosure of sigma(A~)
   if (flags & FPS_PLAN_TIGHT_SPECTRUM) spectrum_tight(n, &ea, &eb);
   // Theorem 2.1 intervals: sigma(A) in sx2 [ea, eb], sigma(B) in sy2 [-eb, -ea].
-  if (!fps::zolotarev_shifts(pl->sx2 * ea, pl->sx2 * eb, -pl->sy2 * eb, -pl->sy2 * ea, adi_tol,
-                             pl->shifts, err))
-    return fail(FPS_E_ARG, err);
-  // FP64: apply the steps in order of increasing |p_j| (the reverse of the
-  // planner's order).  The J-step result does not depend on the order in
-  // exact arithmetic (the error factors commute), but rounding does: a
-  // small-shift step magnifies the rounding of its inputs by up to
-  // ~ (sx2 + sy2) / |shift| in some modes, and the large-shift steps that
-  // follow it damp those modes.  In the opposite order the symmetrized
-  // iterate carries ~1e-10 relative error on Dirichlet-lift right-hand
-  // sides (rows 0, 1 spanning every column mode) instead of ~1e-13.
-  // FP32_REFINED keeps the planner's order: its float-stored large-shift
-  // steps need the later small-shift steps to damp their float rounding,
-  // and each round's residual is formed afresh in FP64.
-  if (prec == FPS_FP64) {
-    std::reverse(pl->shifts.p.begin(), pl->shifts.p.end());
-    std::reverse(pl->shifts.q.begin(), pl->shifts.q.end());
+  // FP64: one ADI to tol.  FP32_REFINED: the rounds of refine_schedule(tol),
+  // each an ADI to its own tolerance.
+  const std::vector<RefineRound> sched =
+      prec == FPS_FP32_REFINED ? refine_schedule(tol, (flags & FPS_PLAN_DIRICHLET) != 0)
+                               : std::vector<RefineRound>{{tol, false}};
+  pl->rtol.clear();
+  pl->rf32.clear();
+  for (const RefineRound &r : sched) {
+    pl->rtol.push_back(r.tol);
+    pl->rf32.push_back(r.f32 ? 1 : 0);
   }
-  const fps::ShiftSet &sh = pl->shifts;
-  pl->f32step.assign((size_t)pl->shifts.J + 1, 0);
-  if (prec == FPS_FP32_REFINED)
-    for (int j = 0; j < sh.J; ++j)
-      // Step j's stored arrays enter the solves with sy2 A~ + p_j and
-      // sx2 A~ - q_j, which magnify their rounding error in the top modes
-      // (|alpha - beta| up to sx2 + sy2) by about (sx2 + sy2) / |shift|;
-      // for the square this is the |p_j| >= kF32MinShift rule.
-      if (std::fabs(sh.p[j]) >= kF32MinShift * 0.5 * (pl->sx2 + pl->sy2) &&
-          std::fabs(sh.q[j]) >= kF32MinShift * 0.5 * (pl->sx2 + pl->sy2)) {
-        pl->f32step[j] = 1;
-        ++pl->n_f32;
-      }
-  pl->L = fps::make_layout(n);
-  if (pl->rect) {  // tables 2j: sy2 A~ + p_j, 2j + 1: sx2 A~ - q_j
-    std::vector<double> alpha, beta;
+  pl->rounds = (int)pl->rtol.size();
+  pl->rsh.assign(pl->rtol.size(), fps::ShiftSet{});
+  pl->rbase.assign(pl->rtol.size(), 0);
+  int steps = 0;
+  for (size_t k = 0; k < pl->rtol.size(); ++k) {
+    fps::ShiftSet &sh = pl->rsh[k];
+    if (!fps::zolotarev_shifts(pl->sx2 * ea, pl->sx2 * eb, -pl->sy2 * eb, -pl->sy2 * ea,
+                               pl->rtol[k], sh, err))
+      return fail(FPS_E_ARG, err);
+    // Apply the steps in order of increasing |p_j| (the reverse of the
+    // planner's order).  The J-step result does not depend on the order in
+    // exact arithmetic (the error factors commute), but rounding does: a
+    // small-shift step magnifies the rounding of its inputs by up to
+    // ~ (sx2 + sy2) / |shift| in some modes, and the large-shift steps that
+    // follow it damp those modes.  In the opposite order the symmetrized
+    // iterate carries ~1e-10 relative error on Dirichlet-lift right-hand
+    // sides (rows 0, 1 spanning every column mode) instead of ~1e-13, and
+    // float storage (refinement rounds) stalls or diverges from n ~ 256 on.
+    std::reverse(sh.p.begin(), sh.p.end());
+    std::reverse(sh.q.begin(), sh.q.end());
+    pl->rbase[k] = steps;
+    steps += sh.J;
+  }
+  pl->shifts = pl->rsh[0];
+  pl->n_f32 = 0;
+  for (size_t k = 0; k < pl->rsh.size(); ++k)
+    if (pl->rf32[k]) pl->n_f32 += pl->rsh[k].J;
+  // Tables of every step of every round (a rectangle has two per step).
+  std::vector<double> alpha, beta;
+  for (const fps::ShiftSet &sh : pl->rsh)
     for (int j = 0; j < sh.J; ++j) {
-      alpha.push_back(pl->sy2);
-      beta.push_back(sh.p[j]);
-      alpha.push_back(pl->sx2);
-      beta.push_back(-sh.q[j]);
+      if (pl->rect) {  // tables 2j: sy2 A~ + p_j, 2j + 1: sx2 A~ - q_j
+        alpha.push_back(pl->sy2);
+        beta.push_back(sh.p[j]);
+        alpha.push_back(pl->sx2);
+        beta.push_back(-sh.q[j]);
+      } else {
+        alpha.push_back(1.0);
+        beta.push_back(sh.p[j]);
+      }
     }
-    fps::build_sweep_tables_ab(pl->L, alpha, beta, pl->tab, pl->ctab, nullptr, pl->l1);
-  } else {
-    fps::build_sweep_tables_ab(pl->L, std::vector<double>(sh.p.size(), 1.0), sh.p, pl->tab,
-                               pl->ctab, nullptr, pl->l1);
-  }
+  pl->L = fps::make_layout(n);
+  fps::build_sweep_tables_ab(pl->L, alpha, beta, pl->tab, pl->ctab, nullptr, pl->l1);
   fps::build_conversions(pl->L, pl->Rs, pl->P);
   std::vector<double> RsA[2], RsB[2], PA[2], PB[2];
   for (int s = 0; s < 2; ++s) {
@@ -601,6 +639,16 @@ fps_status fps_plan_refinement(const fps_plan *pl, int *rounds, int *f32_steps) 
   return FPS_OK;
 }
 
+fps_status fps_plan_rounds(const fps_plan *pl, int *steps, double *tols, int cap) {
+  if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
+  if (pl->dim != 2 || pl->cyl) return fail(FPS_E_STATE, "rounds exist for square and rectangle plans");
+  for (int k = 0; k < pl->rounds && k < cap; ++k) {
+    if (steps) steps[k] = pl->rsh[(size_t)k].J;
+    if (tols) tols[k] = pl->rtol[(size_t)k];
+  }
+  return FPS_OK;
+}
+
 fps_status fps_plan_inner_counts(const fps_plan *pl, int *counts, int cap) {
   if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
   if (pl->dim != 3 || pl->zeig)
@@ -687,7 +735,9 @@ fps_status fps_adi_native(fps_plan *pl, const double *G, double *Y, void *ws, vo
   double *GT = (double *)(w + pl->off_GT);
   FPS_HIP(fps::launch_permute_in(G, Gp, L.n, L.npad, L.mp[0], st));
   FPS_HIP(fps::launch_transpose(Gp, GT, L.npad, st));
-  if ((s = run_adi(pl, Gp, GT, 0, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK) return s;
+  if ((s = run_adi(pl, pl->shifts, 0, Gp, GT, 0, 0, w + pl->off_O0, w + pl->off_O1, w, st)) !=
+      FPS_OK)
+    return s;
   const int J = pl->shifts.J;
   FPS_HIP(fps::launch_finalize<double>((double *)(w + pl->off_O1), (double *)(w + pl->off_ab),
                                        pl->tab_dev(pl->tab2(J - 1)), Y, 1, nullptr, L.n, L.npad, L.mp[0],

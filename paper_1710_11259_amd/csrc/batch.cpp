@@ -31,9 +31,14 @@ struct fps_batch {
   std::vector<int> order;            // sorted position -> problem (J descending)
   std::vector<int64_t> f_off, u_off, ws_off;  // per problem: F / U entries, workspace bytes
   int64_t in_entries = 0, out_entries = 0, ws_bytes = 0;
-  int J_max = 0;
-  int n_f32 = 0;                     // inner steps j < n_f32 store in float (refined)
-  std::vector<int> active;           // per step: problems (a sorted prefix) still iterating
+  int J_max = 0;                     // steps of the longest ADI (over all rounds)
+  // Refinement rounds (1 for FP64; the storage type of each round is its
+  // plans' rf32[r]).  Round r has J_r[r] steps at most; at its step j the
+  // problems still iterating are the sorted prefix active[r][j]; its
+  // descriptors start at step row row0[r] of the sweep / carry tables.
+  int rounds = 1;
+  std::vector<int> J_r, row0;
+  std::vector<std::vector<int>> active;
   std::vector<int> sw_start, rd_start;  // workgroup prefix sums over the sorted problems
   int64_t ncmax_max = 0;
   DeviceBuf d_sw, d_rd, d_swmap, d_rdmap;
@@ -120,9 +125,9 @@ fps_status build_descriptors(fps_batch *bt) {
   const int C = bt->count;
   const bool refined = bt->prec == FPS_FP32_REFINED;
   const int gf = refined ? 1 : 0;
-  auto f32 = [&](int j) { return j < bt->n_f32 ? 1 : 0; };
-  std::vector<fps::BatchSweep> sw((size_t)bt->J_max * 2 * C);
-  std::vector<fps::BatchReduce> rd((size_t)bt->J_max * 2 * C);
+  const int rows = bt->row0.back() + bt->J_r.back();
+  std::vector<fps::BatchSweep> sw((size_t)rows * 2 * C);
+  std::vector<fps::BatchReduce> rd((size_t)rows * 2 * C);
   for (int k = 0; k < C; ++k) {
     const int b = bt->order[k];
     const fps_plan *pl = bt->plan_of(b);
@@ -132,8 +137,6 @@ fps_status build_descriptors(fps_batch *bt) {
     const int64_t GTin = refined ? W + pl->off_R + L.npad * L.npad * 4 : W + pl->off_GT;
     const int64_t O0 = W + pl->off_O0, O1 = W + pl->off_O1, lv = W + pl->off_lv,
                   ab = W + pl->off_ab;
-    const int J = pl->shifts.J;
-    const std::vector<double> &p = pl->shifts.p;
     fps::SweepArgs A{};
     A.npad = L.npad;
     A.ncols = L.npad;
@@ -149,42 +152,49 @@ fps_status build_descriptors(fps_batch *bt) {
     const int nbx_s = (int)(L.npad / fps::kCols);
     const int rchains = fps::reduce_chains(bt->ncmax_max);
     const int nbx_r = (int)((L.npad + rchains - 1) / rchains);
-    for (int j = 0; j < J; ++j) {
-      const bool last = j == J - 1;
-      // half-step 1
-      fps::SweepArgs a1 = A;
-      a1.in = off_ptr<const void *>(j == 0 ? GTin : O1);
-      a1.in_f32 = j == 0 ? gf : f32(j);
-      a1.in_scale = j == 0 ? -1.0 : 1.0;
-      a1.ab_prev = j == 0 ? nullptr : off_ptr<const double *>(ab);
-      a1.tab_prev = j == 0 ? nullptr : pl->tab_dev(j - 1);
-      a1.g = nullptr;
-      a1.tab = pl->tab_dev(j);
-      a1.l1 = pl->l1_dev(j);
-      a1.sigma = 2.0 * p[j];
-      a1.out = off_ptr<void *>(O0);
-      a1.out_f32 = f32(j);
-      // half-step 2
-      fps::SweepArgs a2 = a1;
-      a2.in = off_ptr<const void *>(O0);
-      a2.in_f32 = f32(j);
-      a2.in_scale = 1.0;
-      a2.ab_prev = off_ptr<const double *>(ab);
-      a2.tab_prev = pl->tab_dev(j);
-      a2.g = off_ptr<const void *>(Gterm);
-      a2.g_f32 = gf;
-      a2.sg = 1.0;
-      a2.sigma = last ? 0.0 : p[j] + p[j + 1];
-      a2.out = off_ptr<void *>(O1);
-      a2.out_f32 = last ? 0 : f32(j + 1);
-      a2.out_mode = last ? 1 : 0;
-      const size_t i1 = ((size_t)j * 2 + 0) * C + k, i2 = ((size_t)j * 2 + 1) * C + k;
-      sw[i1] = fps::BatchSweep{a1, bt->sw_start[k], nbx_s};
-      sw[i2] = fps::BatchSweep{a2, bt->sw_start[k], nbx_s};
-      rd[i1] = fps::BatchReduce{lv, ab, pl->ctab_dev(j), -a1.sigma, L.npad, L.ncmax,
-                                (int)L.nc[0], (int)L.nc[1], bt->rd_start[k], nbx_r};
-      rd[i2] = rd[i1];
-      rd[i2].scale = last ? 1.0 : -a2.sigma;
+    for (int r = 0; r < bt->rounds; ++r) {
+      const fps::ShiftSet &sh = pl->rsh[(size_t)r];
+      const int J = sh.J, base = pl->rbase[(size_t)r];
+      const int f = pl->rf32[(size_t)r];
+      const std::vector<double> &p = sh.p;
+      for (int j = 0; j < J; ++j) {
+        const bool last = j == J - 1;
+        // half-step 1
+        fps::SweepArgs a1 = A;
+        a1.in = off_ptr<const void *>(j == 0 ? GTin : O1);
+        a1.in_f32 = j == 0 ? gf : f;
+        a1.in_scale = j == 0 ? -1.0 : 1.0;
+        a1.ab_prev = j == 0 ? nullptr : off_ptr<const double *>(ab);
+        a1.tab_prev = j == 0 ? nullptr : pl->tab_dev(base + j - 1);
+        a1.g = nullptr;
+        a1.tab = pl->tab_dev(base + j);
+        a1.l1 = pl->l1_dev(base + j);
+        a1.sigma = 2.0 * p[j];
+        a1.out = off_ptr<void *>(O0);
+        a1.out_f32 = f;
+        // half-step 2
+        fps::SweepArgs a2 = a1;
+        a2.in = off_ptr<const void *>(O0);
+        a2.in_f32 = f;
+        a2.in_scale = 1.0;
+        a2.ab_prev = off_ptr<const double *>(ab);
+        a2.tab_prev = pl->tab_dev(base + j);
+        a2.g = off_ptr<const void *>(Gterm);
+        a2.g_f32 = gf;
+        a2.sg = 1.0;
+        a2.sigma = last ? 0.0 : p[j] + p[j + 1];
+        a2.out = off_ptr<void *>(O1);
+        a2.out_f32 = f;
+        a2.out_mode = last ? 1 : 0;
+        const int row = bt->row0[(size_t)r] + j;
+        const size_t i1 = ((size_t)row * 2 + 0) * C + k, i2 = ((size_t)row * 2 + 1) * C + k;
+        sw[i1] = fps::BatchSweep{a1, bt->sw_start[k], nbx_s};
+        sw[i2] = fps::BatchSweep{a2, bt->sw_start[k], nbx_s};
+        rd[i1] = fps::BatchReduce{lv, ab, pl->ctab_dev(base + j), -a1.sigma, L.npad, L.ncmax,
+                                  (int)L.nc[0], (int)L.nc[1], bt->rd_start[k], nbx_r};
+        rd[i2] = rd[i1];
+        rd[i2].scale = last ? 1.0 : -a2.sigma;
+      }
     }
   }
   std::vector<int> swmap(bt->sw_start[C]), rdmap(bt->rd_start[C]);
@@ -234,10 +244,10 @@ fps_status build_elem_tables(fps_batch *bt) {
     tr.src = W + pl->off_G;
     tr.dst = W + pl->off_GT;
     tr.nbx = (int)tb;
-    fps::ElemDesc fin = e;  // O1 and its carries -> Y
+    fps::ElemDesc fin = e;  // O1 and its carries -> Y (round 0's tables)
     fin.src = W + pl->off_O1;
     fin.ab = W + pl->off_ab;
-    fin.tab = pl->tab_dev(pl->shifts.J - 1);
+    fin.tab = pl->tab_dev(pl->rbase[0] + pl->rsh[0].J - 1);
     fin.dst = W + (refined ? pl->off_GT : pl->off_G);
     fin.nbx = (int)rowb;
     fps::ElemDesc *all[3] = {&pin, &tr, &fin};
@@ -269,6 +279,21 @@ fps_status build_elem_tables(fps_batch *bt) {
     bt->ewg[t] = (int)tot[t];
   }
   if (refined && (s = upload(bt->d_ed[3], ed[3])) != FPS_OK) return s;
+  // The finalize descriptors of the later refinement rounds (the tables of
+  // each round's last step; same workgroup map).
+  if (bt->rounds > 1) {
+    std::vector<fps::ElemDesc> fr;
+    for (int r = 0; r < bt->rounds; ++r)
+      for (int k = 0; k < C; ++k) {
+        fps::ElemDesc f = ed[2][(size_t)k];
+        const fps_plan *pl = bt->plan_of(bt->order[k]);
+        f.tab = pl->tab_dev(pl->rbase[(size_t)r] + pl->rsh[(size_t)r].J - 1);
+        fr.push_back(f);
+      }
+    bt->d_ed[2].~DeviceBuf();
+    new (&bt->d_ed[2]) DeviceBuf();
+    if ((s = upload(bt->d_ed[2], fr)) != FPS_OK) return s;
+  }
   bt->elem_ok = true;
   return FPS_OK;
 }
@@ -289,47 +314,57 @@ hipError_t transpose_all(const fps_batch *bt, char *w, hipStream_t st) {
 }
 
 // Final pass of every problem into Y (its G region, or G^T for a refined
-// batch): mode 0 stores, mode 2 adds.
-hipError_t finalize_all(const fps_batch *bt, char *w, int mode, hipStream_t st) {
+// batch) after refinement round `round`: mode 0 stores, mode 2 adds.
+hipError_t finalize_all(const fps_batch *bt, char *w, int mode, int round, hipStream_t st) {
   if (bt->elem_ok)
-    return fps::launch_finalize_batch((const fps::ElemDesc *)bt->d_ed[2].p,
-                                      (const int *)bt->d_emap[2].p, bt->ewg[2], mode, w, st);
+    return fps::launch_finalize_batch((const fps::ElemDesc *)bt->d_ed[2].p + (size_t)round * bt->count,
+                                      (const int *)bt->d_emap[2].p, bt->ewg[2], mode, w, st,
+                                      bt->sub[0]->rf32[(size_t)round]);
   const bool refined = bt->prec == FPS_FP32_REFINED;
+  const bool xf = bt->sub[0]->rf32[(size_t)round] != 0;
   for (int b = 0; b < bt->count; ++b) {
     const fps_plan *pl = bt->plan_of(b);
     const fps::Layout &L = pl->L;
     char *wb = w + bt->ws_off[b];
     double *Y = (double *)(wb + (refined ? pl->off_GT : pl->off_G));
-    const hipError_t e = fps::launch_finalize<double>(
-        (const double *)(wb + pl->off_O1), (const double *)(wb + pl->off_ab),
-        pl->tab_dev(pl->shifts.J - 1), Y, mode, nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax,
-        st);
+    const double *tab = pl->tab_dev(pl->rbase[(size_t)round] + pl->rsh[(size_t)round].J - 1);
+    const double *ab = (const double *)(wb + pl->off_ab);
+    const hipError_t e =
+        xf ? fps::launch_finalize<float>((const float *)(wb + pl->off_O1), ab, tab, Y, mode,
+                                              nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st)
+                : fps::launch_finalize<double>((const double *)(wb + pl->off_O1), ab, tab, Y, mode,
+                                               nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax,
+                                               st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-// The 2 J_max batched half-steps (and their carry reductions).  At step j the
-// problems with J > j form a prefix of the sorted order; a problem's last
-// step writes its final chunk-local solution to its O1 and its carries to
-// its ab, which later steps leave alone.
-fps_status run_adi_batch(fps_batch *bt, char *ws, hipStream_t st) {
+// The batched half-steps of refinement round `round` (and their carry
+// reductions).  At step j the problems with J > j form a prefix of the
+// sorted order; a problem's last step writes its final chunk-local solution
+// to its O1 and its carries to its ab, which later steps leave alone.
+fps_status run_adi_batch(fps_batch *bt, int round, char *ws, hipStream_t st) {
   const int C = bt->count;
-  const bool refined = bt->prec == FPS_FP32_REFINED;
+  const int f = bt->sub[0]->rf32[(size_t)round];
+  const int gf = bt->prec == FPS_FP32_REFINED ? 1 : 0;  // the residual r is stored in float
   const fps::BatchSweep *dsw = (const fps::BatchSweep *)bt->d_sw.p;
   const fps::BatchReduce *drd = (const fps::BatchReduce *)bt->d_rd.p;
   const int *swmap = (const int *)bt->d_swmap.p, *rdmap = (const int *)bt->d_rdmap.p;
-  for (int j = 0; j < bt->J_max; ++j) {
-    const int k = bt->active[j];
-    const bool next_f32 = j + 1 < bt->n_f32;
+  const std::vector<int> &act = bt->active[(size_t)round];
+  for (int j = 0; j < bt->J_r[(size_t)round]; ++j) {
+    const int k = act[(size_t)j];
+    // the storage types of every descriptor of the launch (a problem's last
+    // step writes double, and its later steps are not launched)
     fps::SweepArgs t1{};
-    t1.in_f32 = j == 0 ? (refined ? 1 : 0) : (j < bt->n_f32 ? 1 : 0);
-    t1.out_f32 = j < bt->n_f32 ? 1 : 0;
+    t1.in_f32 = j == 0 ? gf : f;
+    t1.out_f32 = f;
     fps::SweepArgs t2{};
-    t2.in_f32 = t1.out_f32;
-    t2.g_f32 = refined ? 1 : 0;
-    t2.out_f32 = next_f32 ? 1 : 0;
-    const size_t o1 = ((size_t)j * 2 + 0) * C, o2 = ((size_t)j * 2 + 1) * C;
+    t2.in_f32 = f;
+    t2.g_f32 = gf;
+    t2.out_f32 = f;
+    const int row = bt->row0[(size_t)round] + j;
+    const size_t o1 = ((size_t)row * 2 + 0) * C, o2 = ((size_t)row * 2 + 1) * C;
     FPS_HIP(fps::launch_sweep_batch(t1, false, dsw + o1, swmap, bt->sw_start[k], ws, st));
     FPS_HIP(fps::launch_reduce_batch(drd + o1, rdmap, bt->rd_start[k], bt->ncmax_max, ws, st));
     FPS_HIP(fps::launch_sweep_batch(t2, true, dsw + o2, swmap, bt->sw_start[k], ws, st));
@@ -393,17 +428,32 @@ fps_status fps_batch_create(fps_batch **out, int dim, int count, const int64_t *
     const int Ja = bt->plan_of(a)->shifts.J, Jc = bt->plan_of(c)->shifts.J;
     return Ja != Jc ? Ja > Jc : n[a] > n[c];
   });
-  bt->J_max = bt->plan_of(bt->order[0])->shifts.J;
-  int J_min = bt->J_max, f_min = 1 << 30;
-  for (const fps_plan *pl : bt->sub) {
-    J_min = std::min(J_min, pl->shifts.J);
-    f_min = std::min(f_min, pl->n_f32);
+  // Every plan of the batch has the same round structure (the schedule
+  // depends on tol only); within a round J grows with n, so the problems
+  // still iterating at any step form a prefix of the sorted order.
+  bt->rounds = bt->sub[0]->rounds;
+  bt->J_r.assign(bt->rounds, 0);
+  bt->row0.assign(bt->rounds, 0);
+  bt->active.assign(bt->rounds, std::vector<int>());
+  for (int r = 0; r < bt->rounds; ++r) {
+    int prev = 1 << 30;
+    for (int k = 0; k < count; ++k) {
+      const fps_plan *pl = bt->plan_of(bt->order[k]);
+      const int J = (int)pl->rsh.size() == bt->rounds ? pl->rsh[(size_t)r].J : -1;
+      if (J < 0 || J > prev) {
+        delete bt;
+        return fail(FPS_E_STATE, "internal: batch round structure");
+      }
+      prev = J;
+      bt->J_r[(size_t)r] = std::max(bt->J_r[(size_t)r], J);
+    }
+    bt->active[(size_t)r].assign(bt->J_r[(size_t)r], 0);
+    for (int j = 0; j < bt->J_r[(size_t)r]; ++j)
+      for (int k = 0; k < count; ++k)
+        if (bt->plan_of(bt->order[k])->rsh[(size_t)r].J > j) bt->active[(size_t)r][j] = k + 1;
+    if (r > 0) bt->row0[(size_t)r] = bt->row0[(size_t)r - 1] + bt->J_r[(size_t)r - 1];
+    bt->J_max = std::max(bt->J_max, bt->J_r[(size_t)r]);
   }
-  bt->n_f32 = prec == FPS_FP32_REFINED ? std::max(0, std::min(f_min, J_min - 1)) : 0;
-  bt->active.assign(bt->J_max, 0);
-  for (int j = 0; j < bt->J_max; ++j)
-    for (int k = 0; k < count; ++k)
-      if (bt->plan_of(bt->order[k])->shifts.J > j) bt->active[j] = k + 1;
   bt->sw_start.assign(count + 1, 0);
   bt->rd_start.assign(count + 1, 0);
   for (int k = 0; k < count; ++k)
@@ -473,8 +523,7 @@ fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, 
   // Y of every problem: FP64 lands in its G region, refined in its GT region
   // (as the single-problem solve places it).
   const bool refined = bt->prec == FPS_FP32_REFINED;
-  const int rounds = refined ? bt->sub[0]->rounds : 1;
-  for (int k = 0; k < rounds; ++k) {
+  for (int k = 0; k < bt->rounds; ++k) {
     if (refined && bt->elem_ok)
       FPS_HIP(fps::launch_residual_batch((const fps::ElemDesc *)bt->d_ed[3].p,
                                          (const int *)bt->d_emap[1].p, bt->ewg[1], k != 0, w, st));
@@ -488,8 +537,8 @@ fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, 
                                      (const double *)pl->d_sdiag.p, (const double *)pl->d_soff.p,
                                      r, r + pl->L.npad * pl->L.npad, pl->L.npad, st));
       }
-    if ((s = run_adi_batch(bt, w, st)) != FPS_OK) return s;
-    FPS_HIP(finalize_all(bt, w, k == 0 ? 0 : 2, st));
+    if ((s = run_adi_batch(bt, k, w, st)) != FPS_OK) return s;
+    FPS_HIP(finalize_all(bt, w, k == 0 ? 0 : 2, k, st));
   }
   if (bt->out_basis == FPS_OUT_NATIVE) {
     for (int b = 0; b < C; ++b) {
@@ -533,8 +582,8 @@ fps_status fps_batch_solve_adjoint(fps_batch *bt, const double *Ubar, double *Fb
   FPS_HIP(transpose_all(bt, w, st));
   // The same ADI map as the forward solve (self-adjoint for symmetric
   // shifts), batched; Gbar lands in each problem's G region (FP64 batch).
-  if ((s = run_adi_batch(bt, w, st)) != FPS_OK) return s;
-  FPS_HIP(finalize_all(bt, w, 0, st));
+  if ((s = run_adi_batch(bt, 0, w, st)) != FPS_OK) return s;
+  FPS_HIP(finalize_all(bt, w, 0, 0, st));
   // Fbar of every problem: the output-map GEMMs (two table launches).
   FPS_HIP(gemm(6, (char *)Fbar));
   FPS_HIP(gemm(7, (char *)Fbar));

@@ -184,17 +184,17 @@ __global__ __launch_bounds__(256) void k_residual_batch(const ElemDesc *__restri
                 e.ev, r, r + e.npad * e.npad, e.npad, 1.0, 1.0, local % e.nbx, local / e.nbx, tile);
 }
 
+template <typename T>
 __global__ __launch_bounds__(256) void k_finalize_batch(const ElemDesc *__restrict__ d,
                                                         const int *__restrict__ wg_prob, int mode,
                                                         char *ws) {
   const int g = blockIdx.x;
   const ElemDesc &e = d[__builtin_amdgcn_readfirstlane(wg_prob[g])];
   const int local = g - e.wg_start;
-  const double *x = (const double *)(elem_base(e.sbase, ws, nullptr) + e.src);
+  const T *x = (const T *)(elem_base(e.sbase, ws, nullptr) + e.src);
   double *out = (double *)(elem_base(e.dbase, ws, nullptr) + e.dst);
-  finalize_at<double>(x, (const double *)(ws + e.ab), e.tab, out, mode, nullptr, e.n, e.npad,
-                      e.mp0, e.mstride, e.ncmax, (int64_t)(local % e.nbx) * 256 + threadIdx.x,
-                      local / e.nbx);
+  finalize_at<T>(x, (const double *)(ws + e.ab), e.tab, out, mode, nullptr, e.n, e.npad, e.mp0,
+                 e.mstride, e.ncmax, (int64_t)(local % e.nbx) * 256 + threadIdx.x, local / e.nbx);
 }
 
 __global__ void k_fill(double *__restrict__ dst, int64_t count, double v) {
@@ -425,10 +425,15 @@ hipError_t launch_residual_batch(const ElemDesc *d, const int *wg_prob, int nwg,
 }
 
 hipError_t launch_finalize_batch(const ElemDesc *d, const int *wg_prob, int nwg, int mode, char *ws,
-                                 hipStream_t st) {
+                                 hipStream_t st, int x_f32) {
   if (nwg <= 0) return hipSuccess;
   if (mode != 0 && mode != 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_finalize_batch, dim3((unsigned)nwg), dim3(256), 0, st, d, wg_prob, mode, ws);
+  if (x_f32)
+    hipLaunchKernelGGL(k_finalize_batch<float>, dim3((unsigned)nwg), dim3(256), 0, st, d, wg_prob,
+                       mode, ws);
+  else
+    hipLaunchKernelGGL(k_finalize_batch<double>, dim3((unsigned)nwg), dim3(256), 0, st, d, wg_prob,
+                       mode, ws);
   return hipGetLastError();
 }
 

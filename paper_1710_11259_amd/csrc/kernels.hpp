@@ -173,9 +173,10 @@ hipError_t launch_transpose_batch(const ElemDesc *d, const int *wg_prob, int nwg
 // launch_residual (ax = ay = 1) for every problem; with_y false: r = G.
 hipError_t launch_residual_batch(const ElemDesc *d, const int *wg_prob, int nwg, bool with_y,
                                  char *ws, hipStream_t st);
-// launch_finalize with a double input and mode 0 or 2 (no sinv).
+// launch_finalize with mode 0 or 2 (no sinv), the input x in float when
+// x_f32 is set, else in double.
 hipError_t launch_finalize_batch(const ElemDesc *d, const int *wg_prob, int nwg, int mode, char *ws,
-                                 hipStream_t st);
+                                 hipStream_t st, int x_f32 = 0);
 
 // Cube (npad^3 arrays [z][y][x], every axis parity-blocked):
 // natural n^3 -> parity-blocked npad^3 (zero padding).

@@ -58,12 +58,16 @@ struct fps_plan {
   unsigned flags = 0;
   bool on_device = false;
 
-  fps::ShiftSet shifts;     // shifts of the ADI the sweeps run (inner ADI for FP32_REFINED)
-  int rounds = 1;           // refinement rounds (FP32_REFINED), 1 for FP64
-  double inner_tol = 0.0;   // ADI tolerance of one refinement round
-  // f32step[j] != 0: ADI step j stores its sweep outputs in float
-  // (FP32_REFINED, |p_j| >= kF32MinShift); f32step[J] = 0.
-  std::vector<char> f32step;
+  fps::ShiftSet shifts;     // shifts of the ADI the sweeps run (FP32_REFINED: of round 0)
+  // Refinement rounds (FP32_REFINED; FP64 plans have one round, the plain
+  // ADI): round k runs an ADI to rtol[k] with the shifts rsh[k], whose step j
+  // uses the tables of step rbase[k] + j; with rf32[k] set it stores every
+  // sweep array in float.  n_f32 counts the steps of the float rounds.
+  int rounds = 1;
+  std::vector<fps::ShiftSet> rsh;
+  std::vector<int> rbase;
+  std::vector<double> rtol;
+  std::vector<char> rf32;
   int n_f32 = 0;
 
   // Rectangle [a, b] x [c, d] (rect plans): the symmetric form reads
@@ -168,6 +172,14 @@ fps_status upload(DeviceBuf &b, const std::vector<T> &h) {
   FPS_HIP(hipMemcpy(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   return FPS_OK;
 }
+// The refinement rounds of an FP32_REFINED plan with target tolerance tol:
+// each round's inner ADI tolerance and whether it stores its sweep arrays in
+// float (Dirichlet plans end with an FP64 round).
+struct RefineRound {
+  double tol;
+  bool f32;
+};
+std::vector<RefineRound> refine_schedule(double tol, bool dirichlet);
 // Input map of one square or rectangle problem: F (n x n, natural order) ->
 // G and G^T in the plan's workspace `ws`; with `bc` non-null, G also takes
 // the Dirichlet lift's correction (the traces' values at -1 and +1 are kept

@@ -27,23 +27,25 @@ def _single(n, F, **kw):
     return U.cpu().numpy()
 
 
-@pytest.mark.parametrize("out", ["cheb", "native"])
-def test_batch_equals_single_solves_bitwise(out):
+@pytest.mark.parametrize("out,precision", [("cheb", "fp64"), ("native", "fp64"),
+                                           ("cheb", "fp32_refined"), ("native", "fp32_refined")])
+def test_batch_equals_single_solves_bitwise(out, precision):
     Fs = _rhs(MIXED)
-    b = fps.batch(MIXED, tol=1e-13, out=out)
-    print(f"batch fp64 {out}: {len(MIXED)} problems, max J {b.max_J}", flush=True)
+    b = fps.batch(MIXED, tol=1e-13, out=out, precision=precision)
+    print(f"batch {precision} {out}: {len(MIXED)} problems, max J {b.max_J}", flush=True)
     U = fps.batch_solve(b, b.pack(Fs))
     torch.cuda.synchronize()
     Us = [u.cpu().numpy() for u in b.unpack(U)]
     for n, F, Ub in zip(MIXED, Fs, Us):
-        Ur = _single(n, F, tol=1e-13, out=out)
+        Ur = _single(n, F, tol=1e-13, out=out, precision=precision)
         assert Ub.shape == Ur.shape
         assert np.array_equal(Ub, Ur), f"n={n}: batched result differs from the single solve"
     for n, F, Ub in zip(MIXED, Fs, Us):
         if n <= 300:
             Uo = square.poisson_square(F, out=out)
             err = np.linalg.norm(Ub - Uo) / np.linalg.norm(Uo)
-            assert err <= 1e-12, f"n={n}: rel err {err:.3e}"
+            emax = np.abs(Ub - Uo).max() / np.abs(Uo).max()
+            assert err <= 1e-12 and emax <= 1e-12, f"n={n}: rel err {err:.3e} / {emax:.3e}"
 
 
 @pytest.mark.parametrize("out", ["cheb", "native"])
@@ -82,9 +84,11 @@ def test_batch_refined_matches_oracle():
     torch.cuda.synchronize()
     for n, F, Ub in zip(ns, Fs, b.unpack(U)):
         Uo = square.poisson_square(F)
-        err = np.linalg.norm(Ub.cpu().numpy() - Uo) / np.linalg.norm(Uo)
-        print(f"refined n={n} rel err {err:.3e}", flush=True)
-        assert err <= 1e-12
+        Ub = Ub.cpu().numpy()
+        err = np.linalg.norm(Ub - Uo) / np.linalg.norm(Uo)
+        emax = np.abs(Ub - Uo).max() / np.abs(Uo).max()
+        print(f"refined n={n} rel err {err:.3e} max-abs {emax:.3e}", flush=True)
+        assert err <= 1e-12 and emax <= 1e-12
 
 
 def test_batch_workload_256_problems():

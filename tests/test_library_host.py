@@ -85,19 +85,30 @@ def test_workspace_and_extent_queries():
 
 @pytest.mark.parametrize("n", [64, 512, 4096])
 def test_refinement_structure(n):
-    # FP64: one pass, no float steps.  FP32_REFINED to 1e-13: two rounds of
-    # an inner ADI to 1e-7 whose float-stored steps are exactly those with
-    # |p_j| >= 1e-2 (|p_j| decreases with j in Theorem 2.1's indexing).
+    # FP64: one round, no float steps.  FP32_REFINED to 1e-13: rounds to
+    # 1e-5, 1e-5 and a last one to 0.1 * 1e-13 / 1e-10 = 1e-4, every step
+    # storing in float, each round's J from (2.9) and its shifts applied in
+    # order of increasing |p_j|.
     d = fps.plan(n, tol=1e-13, host_only=True)
     assert (d.rounds, d.f32_steps) == (1, 0)
+    assert d.round_steps() == ([d.J], [1e-13])
     r = fps.plan(n, tol=1e-13, precision="fp32_refined", host_only=True)
-    _, p, _ = oshifts.square_shifts(n, 1e-7)
-    assert r.J == len(p)
-    assert r.rounds == 2
-    assert r.f32_steps == int(np.sum(np.abs(p) >= 1e-2))
-    assert 0 < r.f32_steps < r.J
-    assert np.all(np.diff(np.abs(p)) < 0)
+    steps, tols = r.round_steps()
+    assert r.rounds == 3
+    np.testing.assert_allclose(tols, [1e-5, 1e-5, 1e-4], rtol=1e-12)
+    for J, t in zip(steps, tols):
+        assert J == oshifts.square_shifts(n, t)[0]
+    assert r.f32_steps == sum(steps)
+    _, p, _ = oshifts.square_shifts(n, 1e-5)
+    assert r.J == steps[0] == len(p)
+    np.testing.assert_allclose(r.shifts(), p[::-1], rtol=2e-14)
+    assert np.all(np.diff(np.abs(r.shifts())) > 0)
     assert r.workspace_bytes > d.workspace_bytes
+    # looser targets take fewer rounds
+    r10 = fps.plan(n, tol=1e-10, precision="fp32_refined", host_only=True)
+    np.testing.assert_allclose(r10.round_steps()[1], [1e-5, 1e-6], rtol=1e-12)
+    r3 = fps.plan(n, tol=1e-3, precision="fp32_refined", host_only=True)
+    np.testing.assert_allclose(r3.round_steps()[1], [1e-3], rtol=1e-12)
 
 
 @pytest.mark.parametrize("n", [1, 16, 256])
@@ -425,9 +436,9 @@ def test_rect_plan_tight_and_refined():
     np.testing.assert_allclose(pl, po[::-1], rtol=1e-8)
     np.testing.assert_allclose(ql, qo[::-1], rtol=1e-8)
     r = fps.plan(n, tol=1e-13, box=box, precision="fp32_refined", host_only=True)
-    assert r.rounds == 2 and 0 < r.f32_steps < r.J
+    assert r.rounds == 3 and r.f32_steps == sum(r.round_steps()[0])
     rp = r.shift_pairs()[0]
-    assert np.all(np.diff(np.abs(rp)) <= 0)  # refined: decreasing |p_j|
+    assert np.all(np.diff(np.abs(rp)) >= 0)  # increasing |p_j|, as FP64 plans
     # a unit box is the square plan
     u = fps.plan(n, tol=1e-13, box=(-1.0, 1.0, -1.0, 1.0), host_only=True)
     s = fps.plan(n, tol=1e-13, host_only=True)

@@ -1,0 +1,215 @@
+"""CPU emulation of the precision form (FP32 storage + FP64 refinement) that
+pins its two design choices against the exact solution of the symmetric
+form A~ Y + Y A~ = G of (3.9):
+
+* the inner ADI of every round stores every sweep array in float32 and
+  applies the shifts of Theorem 2.1 in order of increasing |p_j|: the
+  rounds then converge to the FP64 level;
+* with the opposite order (largest |p_j| first) the same float storage
+  stalls or diverges from n ~ 256 on.
+
+The emulation runs Algorithm 2 in the pass form the library's sweeps use
+(per step: a solve along one index with A~ + p_j, output V - G = R - 2 p_j Y;
+a solve along the other index on V, output R' = (V - G) - (p_j + p_{j+1}) Y),
+with FP64 arithmetic (banded LAPACK solves of the parity blocks) and every
+stored array rounded to float32, as the kernels store them.  The round
+tolerances are the library plan's (fps_plan_rounds); the shifts are the
+oracle's.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import paper_1710_11259_amd as fps
+import workloads
+from oracle import shifts as oshifts
+from oracle import square
+
+
+def _f32(x):
+    return x.astype(np.float32).astype(np.float64)
+
+
+class _ParityOp:
+    """A~ split into its two tridiagonal parity blocks (App. B)."""
+
+    def __init__(self, n):
+        A = square.atilde_dense(n)
+        self.idx = [np.arange(par, n, 2) for par in (0, 1)]
+        self.blocks = [A[np.ix_(i, i)] for i in self.idx]
+        self.dg = np.diag(A)
+        self.e2 = np.diag(A, 2)
+
+    def solve_rows(self, p, R):
+        """(A~ + p I) X = R (solve along the first index)."""
+        X = np.empty_like(R)
+        for i, B in zip(self.idx, self.blocks):
+            if i.size == 0:
+                continue
+            ab = np.zeros((3, i.size))
+            ab[1] = np.diag(B) + p
+            if i.size > 1:
+                ab[0, 1:] = np.diag(B, 1)
+                ab[2, :-1] = np.diag(B, 1)
+            X[i] = sla.solve_banded((1, 1), ab, R[i])
+        return X
+
+    def lap(self, Y):
+        """A~ Y + Y A~ from the pentadiagonal structure (zero +-1 diagonals)."""
+        def left(Z):
+            out = self.dg[:, None] * Z
+            out[:-2] += self.e2[:, None] * Z[2:]
+            out[2:] += self.e2[:, None] * Z[:-2]
+            return out
+        return left(Y) + left(Y.T).T
+
+
+def _inner_adi(op, r, p, store):
+    """One inner ADI on A~ dY + dY A~ = r in pass form; `store` rounds every
+    array a sweep writes (its last output included)."""
+    R = -r
+    for j in range(len(p)):
+        Yh = op.solve_rows(p[j], R.T).T          # Y_{j+1/2} (A~ + p_j) = R_j
+        VmG = store(R - 2.0 * p[j] * Yh)
+        Y1 = op.solve_rows(p[j], VmG + r)        # (A~ + p_j) Y_{j+1} = V_j
+        if j == len(p) - 1:
+            return store(Y1)
+        R = store(VmG - (p[j] + p[j + 1]) * Y1)
+
+
+def _refine(n, tols, increasing, store=_f32, seed=0):
+    op = _ParityOp(n)
+    F = workloads.square_rhs(n, seed)
+    s = square.s_diag(n)
+    G = square.rhs_ct(F) / np.outer(s, s)
+    Ys = square.solve_symmetric_sylvester(G)
+    lo, hi = oshifts.square_enclosure(n)[:2]
+    Y = np.zeros_like(G)
+    errs = []
+    for k, t in enumerate(tols):
+        _, p, _ = oshifts.zolotarev_shifts(lo, hi, -hi, -lo, tol=t)
+        p = p[np.argsort(np.abs(p))] if increasing else p[np.argsort(-np.abs(p))]
+        r = store(G - op.lap(Y)) if k else store(G)
+        Y = Y + _inner_adi(op, r, p, store)
+        errs.append(np.linalg.norm(Y - Ys) / np.linalg.norm(Ys))
+    return errs
+
+
+def test_pass_form_in_fp64_is_algorithm_2():
+    # Without float rounding the emulated pass form is Algorithm 2: its
+    # J-step iterate equals the oracle's closed form.
+    n = 40
+    F = workloads.square_rhs(n, 0)
+    s = square.s_diag(n)
+    G = square.rhs_ct(F) / np.outer(s, s)
+    _, p, _ = oshifts.square_shifts(n, 1e-6)
+    p = p[np.argsort(np.abs(p))]
+    Yj = _inner_adi(_ParityOp(n), G, p, lambda x: x)
+    Yc = square.adi_exact_iterate(G, p)
+    assert np.linalg.norm(Yj - Yc) <= 1e-12 * np.linalg.norm(Yc)
+
+
+@pytest.mark.parametrize("n", [64, 256, 512])
+def test_library_schedule_converges_with_float_storage(n):
+    plan = fps.plan(n, tol=1e-13, precision="fp32_refined", host_only=True)
+    steps, tols = plan.round_steps()
+    errs = _refine(n, tols, increasing=True)
+    # every round contracts the error; the last reaches the FP64 level
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[0] <= 3e-5
+    assert errs[-1] <= 1e-13
+
+
+@pytest.mark.parametrize("n", [256, 512])
+def test_largest_shift_first_stalls_with_float_storage(n):
+    tols = [1e-5, 1e-5, 1e-5]
+    inc = _refine(n, tols, increasing=True)
+    dec = _refine(n, tols, increasing=False)
+    assert inc[-1] <= 1e-13
+    # the reversed order gains less than a factor 1e-3 over its three rounds
+    # (stall or divergence) and ends many orders of magnitude above
+    assert dec[-1] >= 1e-3 * dec[0]
+    assert dec[-1] >= 1e5 * inc[-1]
+
+
+def _dirichlet_case(n, box, seed=9):
+    """G, the exact Y and the maps to U for a Dirichlet-lift right-hand side
+    (rectangle reading: sx2 A~ Y + sy2 Y A~ = G)."""
+    from oracle import basis, rect
+    sx2, sy2 = rect.scalings(box)
+    F, bc = workloads.rect_dirichlet_case(n, seed=seed)
+    s = square.s_diag(n)
+    G = (square.rhs_ct(F) - rect.lift_correction(bc, box, n)) / np.outer(s, s)
+    lam, V = square.atilde_eig(n)
+    Ys = V @ ((V.T @ G @ V) / (sx2 * lam[:, None] + sy2 * lam[None, :])) @ V.T
+    P = basis.recombined_to_cheb(n)
+    return G, Ys, sx2, sy2, lambda Y: P @ (Y / np.outer(s, s)) @ P.T
+
+
+def _refine_rect(op, G, sx2, sy2, rounds, n):
+    """Rounds (tol, float storage) of the rectangle pass form: half-step 1
+    solves with sy2 A~ + p_j, half-step 2 with sx2 A~ - q_j."""
+    def solve(a, p, R):
+        X = np.empty_like(R)
+        for i, B in zip(op.idx, op.blocks):
+            ab = np.zeros((3, i.size))
+            ab[1] = a * np.diag(B) + p
+            if i.size > 1:
+                ab[0, 1:] = a * np.diag(B, 1)
+                ab[2, :-1] = a * np.diag(B, 1)
+            X[i] = sla.solve_banded((1, 1), ab, R[i])
+        return X
+
+    def lap(Y):
+        def left(Z):
+            out = op.dg[:, None] * Z
+            out[:-2] += op.e2[:, None] * Z[2:]
+            out[2:] += op.e2[:, None] * Z[:-2]
+            return out
+        return sx2 * left(Y) + sy2 * left(Y.T).T
+
+    lo, hi = oshifts.square_enclosure(n)[:2]
+    Y = np.zeros_like(G)
+    out = []
+    for k, (t, f32) in enumerate(rounds):
+        store = _f32 if f32 else (lambda x: x)
+        _, p, q = oshifts.zolotarev_shifts(sx2 * lo, sx2 * hi, -sy2 * hi, -sy2 * lo, tol=t)
+        o = np.argsort(np.abs(p))
+        p, q = p[o], q[o]
+        r = _f32(G - lap(Y)) if k else _f32(G)
+        R = -r
+        for j in range(len(p)):
+            Yh = solve(sy2, p[j], R.T).T
+            VmG = store(R - (p[j] - q[j]) * Yh)
+            Y1 = solve(sx2, -q[j], VmG + r)
+            if j == len(p) - 1:
+                Y = Y + store(Y1)
+                break
+            R = store(VmG - (p[j + 1] - q[j]) * Y1)
+        out.append(Y.copy())
+    return out
+
+
+@pytest.mark.parametrize("box", [(-1.0, 1.0, -1.0, 1.0), (0.0, 10.0, 0.0, 1.0)])
+def test_dirichlet_lift_data_contract_slowly_in_float(box):
+    # Float rounds contract a Dirichlet-lift right-hand side by only ~1e-3
+    # per round after the first; the schedule of Dirichlet plans (two float
+    # rounds, then one FP64 round) reaches the 1e-12 bar on U.
+    n = 512
+    G, Ys, sx2, sy2, to_u = _dirichlet_case(n, box)
+    Uex = to_u(Ys)
+    op = _ParityOp(n)
+
+    def uerr(Y):
+        U = to_u(Y)
+        return np.linalg.norm(U - Uex) / np.linalg.norm(Uex)
+
+    floats = [uerr(Y) for Y in _refine_rect(op, G, sx2, sy2, [(1e-5, True)] * 3, n)]
+    assert floats[2] / floats[1] >= 1e-4   # slow contraction in float
+    kw = {} if box[1] - box[0] == 2.0 and box[3] - box[2] == 2.0 else {"box": box}
+    plan = fps.plan(n, tol=1e-13, precision="fp32_refined", dirichlet=True, host_only=True, **kw)
+    steps, tols = plan.round_steps()
+    assert plan.rounds == 3 and plan.f32_steps == steps[0] + steps[1]
+    sched = [(tols[0], True), (tols[1], True), (tols[2], False)]
+    errs = [uerr(Y) for Y in _refine_rect(op, G, sx2, sy2, sched, n)]
+    assert errs[-1] <= 1e-13
