@@ -310,8 +310,9 @@ fps_status plan_common(fps_plan **out, int dim, int64_t n, int bc, double tol, i
     return fail(FPS_E_ARG, "FPS_PLAN_CUBE_ZEIG applies to cube plans only");
   if ((flags & FPS_PLAN_CUBE_ZEIG) && n > 512)
     return fail(FPS_E_UNSUPPORTED, "the z-eigenbasis cube method is limited to n <= 512");
-  if (dim == 3 && prec != FPS_FP64)
-    return fail(FPS_E_UNSUPPORTED, "the cube solver runs in FP64 only");
+  if (dim == 3 && prec != FPS_FP64 && !(flags & FPS_PLAN_CUBE_ZEIG))
+    return fail(FPS_E_UNSUPPORTED,
+                "FP32_REFINED cube plans need the z-eigenbasis method (FPS_PLAN_CUBE_ZEIG)");
   if (dim == 3 && n > 1024) return fail(FPS_E_UNSUPPORTED, "cube solves are limited to n <= 1024");
   fps_plan *pl = new (std::nothrow) fps_plan();
   if (!pl) return fail(FPS_E_NOMEM, "plan allocation failed");
@@ -641,9 +642,11 @@ fps_status fps_plan_refinement(const fps_plan *pl, int *rounds, int *f32_steps) 
 
 fps_status fps_plan_rounds(const fps_plan *pl, int *steps, double *tols, int cap) {
   if (!valid_plan(pl)) return fail(FPS_E_STATE, "invalid or destroyed plan");
-  if (pl->dim != 2 || pl->cyl) return fail(FPS_E_STATE, "rounds exist for square and rectangle plans");
+  const bool zr = pl->zeig && pl->prec == FPS_FP32_REFINED;
+  if (!zr && (pl->dim != 2 || pl->cyl))
+    return fail(FPS_E_STATE, "rounds exist for square, rectangle and refined z-eigenbasis plans");
   for (int k = 0; k < pl->rounds && k < cap; ++k) {
-    if (steps) steps[k] = pl->rsh[(size_t)k].J;
+    if (steps) steps[k] = zr ? pl->zrJmax[(size_t)k] : pl->rsh[(size_t)k].J;
     if (tols) tols[k] = pl->rtol[(size_t)k];
   }
   return FPS_OK;

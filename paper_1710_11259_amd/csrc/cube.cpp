@@ -455,6 +455,97 @@ int zeig_split(const std::vector<int> &J, int64_t npad) {
 
 }  // namespace
 
+fps_status zeig_common(fps_plan *pl);
+
+// Refined plans: the schedule of refinement rounds, and per round and slice
+// the shifts of the K-form slice equation
+//   (|mu| K + 1/2) dY + dY (|mu| K + 1/2) = K q K,   K = -A~^-1,
+// (multiply A~ dY A~ + mu (A~ dY + dY A~) = -q by K on both sides; K A~ = -I,
+// mu < 0).  sigma(|mu| K + 1/2) lies in [|mu| / |ea| + 1/2, |mu| / |eb| + 1/2]
+// for sigma(A~) in [ea, eb], so Algorithm 2 runs in the square's symmetric
+// pass form with -(|mu| K + 1/2) in place of A~, its shifts p in
+// [-b, -a] applied by increasing |p|.  The shifted solve is
+// (-(|mu| K + 1/2) + p)^-1 = (|mu| - s A~)^-1 A~ with s = 1/2 - p: the A~
+// stencil, then a tridiagonal solve with the table of (p - 1/2) A~ + |mu|.
+// Every sweep array stores in float: in this form a round contracts the
+// error by ~1e-5 (emulated at n = 32 .. 256; the slice equations' own form
+// (-mu^2 P^-1) Z - Z (-P) contracts by only 1e-2 .. 1e-4 per round with float
+// storage, worse as n grows).
+fps_status zeigr_build(fps_plan *pl, const std::vector<long double> lam[2], double ea, double eb) {
+  const fps::Layout &L = pl->L;
+  struct S {
+    int slice;
+    double mu;
+  };
+  std::vector<S> sl;
+  for (int sp = 0; sp < 2; ++sp)
+    for (int64_t k = 0; k < L.m[sp]; ++k)
+      sl.push_back(S{(int)(sp * L.mp[0] + k), (double)lam[sp][(size_t)k]});
+  // |mu| descending: J of every round is then non-increasing along the order
+  std::stable_sort(sl.begin(), sl.end(),
+                   [](const S &u, const S &v) { return std::fabs(u.mu) > std::fabs(v.mu); });
+  const int K = (int)sl.size();
+  const std::vector<RefineRound> sched = refine_schedule(pl->tol, false);
+  pl->rounds = (int)sched.size();
+  pl->rtol.clear();
+  pl->rf32.clear();
+  for (const RefineRound &r : sched) {
+    pl->rtol.push_back(r.tol);
+    pl->rf32.push_back(1);
+  }
+  pl->zrslice.resize(K);
+  pl->zrmu_slice.assign((size_t)L.npad, 0.0);
+  for (int k = 0; k < K; ++k) {
+    pl->zrslice[k] = sl[k].slice;
+    pl->zrmu_slice[(size_t)sl[k].slice] = sl[k].mu;
+  }
+  pl->zrJ.assign(pl->rounds, std::vector<int>(K, 0));
+  pl->zrtab0.assign(pl->rounds, std::vector<int>(K, 0));
+  pl->zractive.assign(pl->rounds, std::vector<int>());
+  pl->zrJmax.assign(pl->rounds, 0);
+  pl->zrrow0.assign(pl->rounds, 0);
+  std::vector<double> alpha{1.0}, beta{0.0};  // table 0: A~
+  pl->zp.assign(1, 0.0);                       // shift of each table (by table id)
+  std::string err;
+  pl->n_f32 = 0;
+  for (int r = 0; r < pl->rounds; ++r) {
+    for (int k = 0; k < K; ++k) {
+      const double am = std::fabs(sl[k].mu);
+      const double a = am / std::fabs(ea) + 0.5, b = am / std::fabs(eb) + 0.5;
+      fps::ShiftSet sh;
+      if (!fps::zolotarev_shifts(-b, -a, a, b, pl->rtol[(size_t)r], sh, err))
+        return fail(FPS_E_ARG, err);
+      std::reverse(sh.p.begin(), sh.p.end());  // increasing |p|
+      std::reverse(sh.q.begin(), sh.q.end());
+      if (r == 0 && k == 0) pl->shifts = sh;
+      pl->zrJ[(size_t)r][(size_t)k] = sh.J;
+      pl->zrtab0[(size_t)r][(size_t)k] = (int)alpha.size();
+      for (int j = 0; j < sh.J; ++j) {
+        alpha.push_back(sh.p[j] - 0.5);
+        beta.push_back(am);
+        pl->zp.push_back(sh.p[j]);
+      }
+      if (k > 0 && sh.J > pl->zrJ[(size_t)r][(size_t)k - 1])
+        return fail(FPS_E_STATE, "internal: refined slice steps not sorted");
+    }
+    const int Jm = K > 0 ? pl->zrJ[(size_t)r][0] : 0;
+    pl->zrJmax[(size_t)r] = Jm;
+    pl->zractive[(size_t)r].assign((size_t)Jm, 0);
+    for (int j = 0; j < Jm; ++j)
+      for (int k = 0; k < K; ++k)
+        if (pl->zrJ[(size_t)r][(size_t)k] > j) pl->zractive[(size_t)r][(size_t)j] = k + 1;
+    if (r > 0) pl->zrrow0[(size_t)r] = pl->zrrow0[(size_t)r - 1] + pl->zrJmax[(size_t)r - 1];
+    pl->n_f32 += Jm;
+  }
+  // the slice-count query reports round 0
+  pl->zslice = pl->zrslice;
+  pl->zJ = K > 0 ? pl->zrJ[0] : std::vector<int>();
+  pl->zJmax = K > 0 ? pl->zrJmax[0] : 0;
+  pl->zsplit = 0;
+  fps::build_sweep_tables_ab(L, alpha, beta, pl->tab, pl->ctab, nullptr, pl->l1);
+  return FPS_OK;
+}
+
 fps_status zeig_build(fps_plan *pl) {
   const int64_t n = pl->n;
   pl->zeig = true;
@@ -475,6 +566,11 @@ fps_status zeig_build(fps_plan *pl) {
     if (!fps::tridiag_eigen(d, e, Q)) return fail(FPS_E_STATE, "eigen-decomposition of A~ failed");
     lam[sp] = d;
     for (int64_t i = 0; i < m * m; ++i) pl->zV[sp][(size_t)i] = (double)Q[(size_t)i];
+  }
+  if (pl->prec == FPS_FP32_REFINED) {
+    fps_status s = zeigr_build(pl, lam, ea, eb);
+    if (s != FPS_OK) return s;
+    return zeig_common(pl);
   }
   // per-slice shifts
   struct Slice {
@@ -529,6 +625,14 @@ fps_status zeig_build(fps_plan *pl) {
   // report the largest slice iteration as the plan's J and its shifts
   pl->shifts = K > 0 ? sl[0].sh : fps::ShiftSet{};
   fps::build_sweep_tables_ab(L, alpha, beta, pl->tab, pl->ctab, nullptr, pl->l1);
+  return zeig_common(pl);
+}
+
+// Maps, stencil and workspace layout shared by the FP64 and refined
+// z-eigenbasis plans.
+fps_status zeig_common(fps_plan *pl) {
+  const int64_t n = pl->n;
+  const fps::Layout &L = pl->L;
   fps::build_conversions(L, pl->Rs, pl->P);
   for (int s2 = 0; s2 < 2; ++s2) {
     pl->mop[s2] = (L.mo[s2] + fps::kPad - 1) / fps::kPad * fps::kPad;
@@ -559,6 +663,100 @@ fps_status zeig_build(fps_plan *pl) {
   if (L.npad * L.npad * mq * 8 > 2 * vol || mq * mq * mq * 8 > 2 * vol ||
       L.npad * mq * mq * 8 > 2 * vol)
     return fail(FPS_E_STATE, "internal: cube output temporaries exceed the workspace");
+  return FPS_OK;
+}
+
+// Refined plans: per-slice mu (residual kernel), and the sweep and carry
+// descriptors of every round, [row][half][sorted slice] with row =
+// zrrow0[r] + j (see zeigr_build for the pass form).
+fps_status zeigr_upload(fps_plan *pl) {
+  const fps::Layout &L = pl->L;
+  const int64_t npad = L.npad, ch = npad * npad;
+  const int K = (int)pl->zrslice.size();
+  fps_status s;
+  const int nbx_s = (int)(npad / fps::kCols), nch = (int)(L.nc[0] + L.nc[1]);
+  const int nsw = nbx_s * nch;
+  const int rchains = fps::reduce_chains(L.ncmax);
+  const int nbx_r = (int)((npad + rchains - 1) / rchains);
+  const int nrd = nbx_r * 2;
+  const int64_t lvb = L.ncmax * 4 * npad, abb = 2 * L.ncmax * npad * 2;  // doubles per slice
+  const int rows = pl->zrrow0.back() + pl->zrJmax.back();
+  const size_t Kc = (size_t)(K > 0 ? K : 1);
+  std::vector<fps::BatchSweep> sw((size_t)rows * 2 * Kc);
+  std::vector<fps::BatchReduce> rd((size_t)rows * 2 * Kc);
+  std::vector<const double *> fin((size_t)pl->rounds * npad, nullptr);
+  const double *pre_d = (const double *)pl->d_pre.p;
+  for (int k = 0; k < K; ++k) {
+    const int64_t c = pl->zrslice[k];
+    const int64_t so = c * ch * 4;  // the float arrays hold slices at a stride of npad^2 floats
+    const int64_t lvo = pl->off_lv + c * lvb * 8, abo = pl->off_ab + c * abb * 8;
+    fps::SweepArgs A{};
+    A.npad = npad;
+    A.ncols = npad;
+    A.ld = npad;
+    A.nbatch = 1;
+    A.mp0 = L.mp[0];
+    A.mp1 = L.mp[1];
+    A.mstride = L.mstride;
+    A.ncmax = L.ncmax;
+    A.nc0 = (int)L.nc[0];
+    A.nc1 = (int)L.nc[1];
+    A.lv = (double *)(intptr_t)lvo;
+    A.pre = pre_d;
+    A.pre_shift = 0.0;
+    A.in_f32 = A.out_f32 = 1;
+    for (int r = 0; r < pl->rounds; ++r) {
+      const int J = pl->zrJ[(size_t)r][(size_t)k], t0 = pl->zrtab0[(size_t)r][(size_t)k];
+      for (int j = 0; j < J; ++j) {
+        const int t = t0 + j;
+        const bool last = j == J - 1;
+        const double pj = pl->zp[(size_t)t], pn = last ? 0.0 : pl->zp[(size_t)t + 1];
+        fps::SweepArgs a1 = A;
+        a1.in = (const void *)(intptr_t)((j == 0 ? pl->off_RXT : pl->off_O1) + so);
+        a1.in_scale = j == 0 ? -1.0 : 1.0;
+        a1.ab_prev = j == 0 ? nullptr : (const double *)(intptr_t)abo;
+        a1.tab_prev = j == 0 ? nullptr : pl->tab_dev(t - 1);
+        a1.g = nullptr;
+        a1.tab = pl->tab_dev(t);
+        a1.l1 = pl->l1_dev(t);
+        a1.sigma = 2.0 * pj;
+        a1.out = (void *)(intptr_t)(pl->off_O0 + so);
+        a1.out_mode = 0;
+        fps::SweepArgs a2 = a1;
+        a2.in = (const void *)(intptr_t)(pl->off_O0 + so);
+        a2.in_scale = 1.0;
+        a2.ab_prev = (const double *)(intptr_t)abo;
+        a2.tab_prev = pl->tab_dev(t);
+        a2.g = (const void *)(intptr_t)(pl->off_RX + so);
+        a2.g_f32 = 1;
+        a2.sg = 1.0;
+        a2.og = 0.0;
+        a2.sigma = last ? 0.0 : pj + pn;
+        a2.out = (void *)(intptr_t)(pl->off_O1 + so);
+        a2.out_mode = last ? 1 : 0;
+        const size_t row = (size_t)pl->zrrow0[(size_t)r] + (size_t)j;
+        const size_t i1 = (row * 2 + 0) * Kc + k, i2 = (row * 2 + 1) * Kc + k;
+        sw[i1] = fps::BatchSweep{a1, k * nsw, nbx_s};
+        sw[i2] = fps::BatchSweep{a2, k * nsw, nbx_s};
+        rd[i1] = fps::BatchReduce{lvo, abo, pl->ctab_dev(t), -a1.sigma, npad, L.ncmax,
+                                  (int)L.nc[0], (int)L.nc[1], k * nrd, nbx_r};
+        rd[i2] = fps::BatchReduce{lvo, abo, pl->ctab_dev(t), last ? 1.0 : -a2.sigma, npad,
+                                  L.ncmax, (int)L.nc[0], (int)L.nc[1], k * nrd, nbx_r};
+      }
+      fin[(size_t)r * npad + c] = J > 0 ? pl->tab_dev(t0 + J - 1) : nullptr;
+    }
+  }
+  std::vector<int> swmap((size_t)K * nsw), rdmap((size_t)K * nrd);
+  for (int k = 0; k < K; ++k) {
+    std::fill(swmap.begin() + (size_t)k * nsw, swmap.begin() + (size_t)(k + 1) * nsw, k);
+    std::fill(rdmap.begin() + (size_t)k * nrd, rdmap.begin() + (size_t)(k + 1) * nrd, k);
+  }
+  pl->zsw_start.assign(1, nsw);
+  pl->zrd_start.assign(1, nrd);
+  if ((s = upload(pl->d_zrsw, sw)) != FPS_OK || (s = upload(pl->d_zrrd, rd)) != FPS_OK ||
+      (s = upload(pl->d_zswmap, swmap)) != FPS_OK || (s = upload(pl->d_zrdmap, rdmap)) != FPS_OK ||
+      (s = upload(pl->d_zrfin, fin)) != FPS_OK || (s = upload(pl->d_zmu, pl->zrmu_slice)) != FPS_OK)
+    return s;
   return FPS_OK;
 }
 
@@ -641,6 +839,7 @@ fps_status zeig_upload(fps_plan *pl) {
     if ((s = upload_table(probs, pl->d_gy_out, pl->d_gy_map_out, pl->gy_tiles[1])) != FPS_OK)
       return s;
   }
+  if (pl->prec == FPS_FP32_REFINED) return zeigr_upload(pl);
   // per-slice sweep and carry descriptors: [step][half][sorted slice]
   const int K = (int)pl->zslice.size(), J = pl->zJmax;
   const int nbx_s = (int)(npad / fps::kCols), nch = (int)(L.nc[0] + L.nc[1]);
@@ -742,6 +941,101 @@ fps_status zeig_upload(fps_plan *pl) {
   return FPS_OK;
 }
 
+// Refined plans: the rounds of Y^ <- Y^ + dY on every slice.  Round r: the
+// negated residual q = G^ + A~ Y^ A~ + mu (A~ Y^ + Y^ A~) (FP64, stored in
+// float, in O0); H = K q K = A~^-1 q A~^-1 by two shift-0 solves along the
+// rows (the first stores x transposed, the second in place, so the second
+// leaves H^T), its carries applied and H^T, H stored in float (RXT, RX);
+// then the K-form Algorithm 2 of every slice in float (stencil passes on
+// tables (p - 1/2) A~ + |mu|; step 0 reads -H^T, every second half-step adds
+// H), and dY (float, carries pending) is added into Y^.
+fps_status zeigr_adi(fps_plan *pl, char *w, hipStream_t st) {
+  const fps::Layout &L = pl->L;
+  const int64_t npad = L.npad, mp0 = L.mp[0];
+  double *Gh = (double *)(w + pl->off_G), *Yh = (double *)(w + pl->off_ZR);
+  float *q = (float *)(w + pl->off_O0), *x1 = (float *)(w + pl->off_O1);
+  float *HT = (float *)(w + pl->off_RXT), *H = (float *)(w + pl->off_RX);
+  double *lv = (double *)(w + pl->off_lv), *ab = (double *)(w + pl->off_ab);
+  const double *dv = (const double *)pl->d_pre.p, *ev = dv + npad;
+  const int64_t lvb = L.ncmax * 4 * npad, abb = 2 * L.ncmax * npad * 2;
+  const int K = (int)pl->zrslice.size();
+  const size_t Kc = (size_t)(K > 0 ? K : 1);
+  const int nsw = pl->zsw_start[0], nrd = pl->zrd_start[0];
+  const fps::BatchSweep *dsw = (const fps::BatchSweep *)pl->d_zrsw.p;
+  const fps::BatchReduce *drd = (const fps::BatchReduce *)pl->d_zrrd.p;
+  const int *swmap = (const int *)pl->d_zswmap.p, *rdmap = (const int *)pl->d_zrdmap.p;
+  const double *const *fin = (const double *const *)pl->d_zrfin.p;
+  fps::SweepArgs t1{}, t2{};
+  t1.pre = t2.pre = dv;
+  t1.in_f32 = t1.out_f32 = 1;
+  t2.in_f32 = t2.g_f32 = t2.out_f32 = 1;
+  auto sweep = [&](const fps::SweepArgs &types, bool with_g, const fps::BatchSweep *d,
+                   int nwg) -> hipError_t {
+    const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
+    const hipError_t e = fps::launch_sweep_batch(types, with_g, d, swmap, nwg, w, st, 0,
+                                                 t ? pl->ev[2 * pl->ev_used] : nullptr,
+                                                 t ? pl->ev[2 * pl->ev_used + 1] : nullptr);
+    if (t && e == hipSuccess) ++pl->ev_used;
+    return e;
+  };
+  for (int r = 0; r < pl->rounds; ++r) {
+    FPS_HIP(fps::launch_zeig_residual(Gh, r == 0 ? nullptr : Yh, dv, ev,
+                                      (const double *)pl->d_zmu.p, q, npad, npad, st));
+    // H = K q K on every slice (table 0 is A~): x = A~^-1 q stored
+    // transposed, then A~^-1 x^T in place = H^T
+    fps::SweepArgs S{};
+    S.npad = npad;
+    S.ncols = npad;
+    S.ld = npad;
+    S.nbatch = (int)npad;
+    S.bstride = npad * npad;
+    S.lvb = lvb;
+    S.abb = abb;
+    S.mp0 = L.mp[0];
+    S.mp1 = L.mp[1];
+    S.mstride = L.mstride;
+    S.ncmax = L.ncmax;
+    S.nc0 = (int)L.nc[0];
+    S.nc1 = (int)L.nc[1];
+    S.lv = lv;
+    S.in = q;
+    S.in_f32 = 1;
+    S.in_scale = 1.0;
+    S.tab = pl->tab_dev(0);
+    S.l1 = pl->l1_dev(0);
+    S.sigma = 0.0;
+    S.out = x1;
+    S.out_f32 = 1;
+    S.out_mode = 3;
+    FPS_HIP(fps::launch_sweep(S, st));
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(0), ab, 1.0, npad, S.nc0, S.nc1, L.ncmax, st,
+                               (int)npad, lvb, abb));
+    S.in = x1;
+    S.ab_prev = ab;
+    S.tab_prev = pl->tab_dev(0);
+    S.out = q;
+    S.out_mode = 1;
+    FPS_HIP(fps::launch_sweep(S, st));
+    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(0), ab, 1.0, npad, S.nc0, S.nc1, L.ncmax, st,
+                               (int)npad, lvb, abb));
+    FPS_HIP(fps::launch_slice_xfinal(q, ab, pl->tab_dev(0), HT, H, npad, mp0, L.mstride, L.ncmax,
+                                     npad, st));
+    // the K-form ADI of every slice, the active ones a prefix of the order
+    for (int j = 0; j < pl->zrJmax[(size_t)r]; ++j) {
+      const int k1 = pl->zractive[(size_t)r][(size_t)j];
+      const size_t row = (size_t)pl->zrrow0[(size_t)r] + (size_t)j;
+      const size_t o1 = (row * 2 + 0) * Kc, o2 = (row * 2 + 1) * Kc;
+      FPS_HIP(sweep(t1, false, dsw + o1, k1 * nsw));
+      FPS_HIP(fps::launch_reduce_batch(drd + o1, rdmap, k1 * nrd, L.ncmax, w, st));
+      FPS_HIP(sweep(t2, true, dsw + o2, k1 * nsw));
+      FPS_HIP(fps::launch_reduce_batch(drd + o2, rdmap, k1 * nrd, L.ncmax, w, st));
+    }
+    FPS_HIP(fps::launch_slice_final<float>(x1, ab, fin + (size_t)r * npad, Yh, 1.0, r > 0 ? 1 : 0,
+                                           npad, mp0, L.mstride, L.ncmax, st));
+  }
+  return FPS_OK;
+}
+
 fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStream_t st) {
   const fps::Layout &L = pl->L;
   const int64_t npad = L.npad, mp0 = L.mp[0];
@@ -766,61 +1060,65 @@ fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
     mode_probs(O0, full, Gh, full, 0, MZ, ldm, MZ, ldm, Nfull, K2, pz);
     if ((s = launch_probs(pz, st)) != FPS_OK) return s;
   }
-  FPS_HIP(fps::launch_transpose(Gh, GhT, npad, st, (int)npad));
-  // Per-slice ADI, all active slices per launch.
-  const int K = (int)pl->zslice.size();
-  const int nsw = pl->zsw_start[0], nrd = pl->zrd_start[0];
-  const fps::BatchSweep *dsw = (const fps::BatchSweep *)pl->d_zsw.p;
-  const fps::BatchReduce *drd = (const fps::BatchReduce *)pl->d_zrd.p;
-  const int *swmap = (const int *)pl->d_zswmap.p, *rdmap = (const int *)pl->d_zrdmap.p;
-  fps::SweepArgs plain{}, stencil{};
-  stencil.pre = (const double *)pl->d_pre.p;
-  // sweep launch, timed with the plan's event pairs while they last
-  auto sweep = [&](const fps::SweepArgs &types, bool with_g, const fps::BatchSweep *d, int nwg,
-                   int wg_base, hipStream_t s2) -> hipError_t {
-    const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
-    const hipError_t e = fps::launch_sweep_batch(
-        types, with_g, d, swmap, nwg, w, s2, wg_base, t ? pl->ev[2 * pl->ev_used] : nullptr,
-        t ? pl->ev[2 * pl->ev_used + 1] : nullptr);
-    if (t && e == hipSuccess) ++pl->ev_used;
-    return e;
-  };
-  // All steps of sorted slices lo .. hi-1 on stream s2: at step j the
-  // active ones are lo .. min(zactive[j], hi) - 1 (J descending).
-  auto run_group = [&](int lo, int hi, hipStream_t s2) -> hipError_t {
-    hipError_t e = hipSuccess;
-    for (int j = 0; j < pl->zJmax && e == hipSuccess; ++j) {
-      const int k1 = std::min(pl->zactive[j], hi), k2 = std::max(std::min(pl->zactive[j + 1], hi), lo);
-      if (k1 <= lo) break;
-      const size_t o1 = ((size_t)j * 2 + 0) * K, o2 = ((size_t)j * 2 + 1) * K;
-      e = sweep(plain, false, dsw + o1, (k1 - lo) * nsw, lo * nsw, s2);
-      if (e == hipSuccess)
-        e = fps::launch_reduce_batch(drd + o1, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
-      if (e == hipSuccess && k2 > lo)  // slices with a later step: stencil P before the y solve
-        e = sweep(stencil, true, dsw + o2, (k2 - lo) * nsw, lo * nsw, s2);
-      if (e == hipSuccess && k1 > k2)  // slices at their last step: no stencil
-        e = sweep(plain, true, dsw + o2, (k1 - k2) * nsw, k2 * nsw, s2);
-      if (e == hipSuccess)
-        e = fps::launch_reduce_batch(drd + o2, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
-    }
-    return e;
-  };
-  // The longest slices iterate on the plan's side stream beside the rest, so
-  // their short launches at the end overlap the bulk; launches timed per
-  // dispatch all go to the caller's stream.
-  if (pl->zsplit > 0 && pl->zsplit < K && pl->zside && pl->ev.empty()) {
-    FPS_HIP(hipEventRecord(pl->zfork, st));
-    FPS_HIP(hipStreamWaitEvent(pl->zside, pl->zfork, 0));
-    FPS_HIP(run_group(0, pl->zsplit, pl->zside));
-    FPS_HIP(run_group(pl->zsplit, K, st));
-    FPS_HIP(hipEventRecord(pl->zjoin, pl->zside));
-    FPS_HIP(hipStreamWaitEvent(st, pl->zjoin, 0));
+  if (pl->prec == FPS_FP32_REFINED) {
+    if ((s = zeigr_adi(pl, w, st)) != FPS_OK) return s;
   } else {
-    FPS_HIP(run_group(0, K, st));
+    FPS_HIP(fps::launch_transpose(Gh, GhT, npad, st, (int)npad));
+    // Per-slice ADI, all active slices per launch.
+    const int K = (int)pl->zslice.size();
+    const int nsw = pl->zsw_start[0], nrd = pl->zrd_start[0];
+    const fps::BatchSweep *dsw = (const fps::BatchSweep *)pl->d_zsw.p;
+    const fps::BatchReduce *drd = (const fps::BatchReduce *)pl->d_zrd.p;
+    const int *swmap = (const int *)pl->d_zswmap.p, *rdmap = (const int *)pl->d_zrdmap.p;
+    fps::SweepArgs plain{}, stencil{};
+    stencil.pre = (const double *)pl->d_pre.p;
+    // sweep launch, timed with the plan's event pairs while they last
+    auto sweep = [&](const fps::SweepArgs &types, bool with_g, const fps::BatchSweep *d, int nwg,
+                     int wg_base, hipStream_t s2) -> hipError_t {
+      const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
+      const hipError_t e = fps::launch_sweep_batch(
+          types, with_g, d, swmap, nwg, w, s2, wg_base, t ? pl->ev[2 * pl->ev_used] : nullptr,
+          t ? pl->ev[2 * pl->ev_used + 1] : nullptr);
+      if (t && e == hipSuccess) ++pl->ev_used;
+      return e;
+    };
+    // All steps of sorted slices lo .. hi-1 on stream s2: at step j the
+    // active ones are lo .. min(zactive[j], hi) - 1 (J descending).
+    auto run_group = [&](int lo, int hi, hipStream_t s2) -> hipError_t {
+      hipError_t e = hipSuccess;
+      for (int j = 0; j < pl->zJmax && e == hipSuccess; ++j) {
+        const int k1 = std::min(pl->zactive[j], hi), k2 = std::max(std::min(pl->zactive[j + 1], hi), lo);
+        if (k1 <= lo) break;
+        const size_t o1 = ((size_t)j * 2 + 0) * K, o2 = ((size_t)j * 2 + 1) * K;
+        e = sweep(plain, false, dsw + o1, (k1 - lo) * nsw, lo * nsw, s2);
+        if (e == hipSuccess)
+          e = fps::launch_reduce_batch(drd + o1, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
+        if (e == hipSuccess && k2 > lo)  // slices with a later step: stencil P before the y solve
+          e = sweep(stencil, true, dsw + o2, (k2 - lo) * nsw, lo * nsw, s2);
+        if (e == hipSuccess && k1 > k2)  // slices at their last step: no stencil
+          e = sweep(plain, true, dsw + o2, (k1 - k2) * nsw, k2 * nsw, s2);
+        if (e == hipSuccess)
+          e = fps::launch_reduce_batch(drd + o2, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
+      }
+      return e;
+    };
+    // The longest slices iterate on the plan's side stream beside the rest, so
+    // their short launches at the end overlap the bulk; launches timed per
+    // dispatch all go to the caller's stream.
+    if (pl->zsplit > 0 && pl->zsplit < K && pl->zside && pl->ev.empty()) {
+      FPS_HIP(hipEventRecord(pl->zfork, st));
+      FPS_HIP(hipStreamWaitEvent(pl->zside, pl->zfork, 0));
+      FPS_HIP(run_group(0, pl->zsplit, pl->zside));
+      FPS_HIP(run_group(pl->zsplit, K, st));
+      FPS_HIP(hipEventRecord(pl->zjoin, pl->zside));
+      FPS_HIP(hipStreamWaitEvent(st, pl->zjoin, 0));
+    } else {
+      FPS_HIP(run_group(0, K, st));
+    }
+    FPS_HIP(fps::launch_slice_final<double>(O1, (const double *)(w + pl->off_ab),
+                                            (const double *const *)pl->d_zfin.p, Yh, -1.0, 0, npad,
+                                            mp0, L.mstride, L.ncmax, st));
   }
-  FPS_HIP(fps::launch_slice_final(O1, (const double *)(w + pl->off_ab),
-                                  (const double *const *)pl->d_zfin.p, Yh, -1.0, npad, mp0,
-                                  L.mstride, L.ncmax, st));
   // Output.
   if (pl->out_basis == FPS_OUT_NATIVE) {
     const double *MV[2] = {(const double *)pl->d_Vz[0].p, (const double *)pl->d_Vz[1].p};

@@ -268,9 +268,10 @@ __global__ __launch_bounds__(256) void k_cube_zfinal(const double *__restrict__ 
 
 // Per-slice finalization (chains = x columns, positions y) with the table
 // of slice z; slices without a table are cleared.
-__global__ void k_slice_final(const double *__restrict__ x, const double *__restrict__ ab,
+template <typename T>
+__global__ void k_slice_final(const T *__restrict__ x, const double *__restrict__ ab,
                               const double *const *__restrict__ tabs, double *__restrict__ out,
-                              double scale, int64_t npad, int64_t mp0, int64_t mstride,
+                              double scale, int add, int64_t npad, int64_t mp0, int64_t mstride,
                               int64_t ncmax) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t y = blockIdx.y, z = blockIdx.z;
@@ -278,14 +279,105 @@ __global__ void k_slice_final(const double *__restrict__ x, const double *__rest
   const int64_t i = (z * npad + y) * npad + q;
   const double *tab = tabs[z];
   if (tab == nullptr) {
-    out[i] = 0.0;
+    if (!add) out[i] = 0.0;
     return;
   }
   const int s = y >= mp0 ? 1 : 0;
   const int64_t k = y - (s ? mp0 : 0), c = k / kChunk;
   const double *tp = tab + (int64_t)s * kNTab * mstride;
   const double *e = ab + z * (2 * ncmax * npad * 2) + (((int64_t)s * ncmax + c) * npad + q) * 2;
-  out[i] = scale * (x[i] + e[0] * tp[T_BF2 * mstride + k] + e[1] * tp[T_BK2 * mstride + k]);
+  const double v =
+      scale * ((double)x[i] + e[0] * tp[T_BF2 * mstride + k] + e[1] * tp[T_BK2 * mstride + k]);
+  if (add)
+    out[i] += v;
+  else
+    out[i] = v;
+}
+
+// Residual of the slice equations of the z-eigenbasis cube, negated:
+// q_z = G_z + A~ Y_z A~ + mu_z (A~ Y_z + Y_z A~) on every slice z (Y null:
+// q = G), in FP64, stored in float.  A~ acts along each parity block as the
+// tridiagonal stencil (dv, ev) of launch_residual.  Each thread walks 16
+// rows of one column keeping the row-direction products of three
+// consecutive rows, so A~ (Y A~) needs no second pass; 256 threads = 64
+// columns x 4 row groups of a 64 x 64 tile.
+__global__ __launch_bounds__(256) void k_zeig_residual(const double *__restrict__ G,
+                                                       const double *__restrict__ Y,
+                                                       const double *__restrict__ dv,
+                                                       const double *__restrict__ ev,
+                                                       const double *__restrict__ mu,
+                                                       float *__restrict__ q, int64_t npad) {
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t z = blockIdx.z;
+  const int64_t j = (int64_t)blockIdx.x * 64 + tx;
+  const int64_t i0 = (int64_t)blockIdx.y * 64 + ty * 16;
+  const int64_t so = z * npad * npad;
+  const double *Gz = G + so;
+  float *qz = q + so;
+  if (Y == nullptr) {
+    for (int64_t i = i0; i < i0 + 16; ++i) qz[i * npad + j] = (float)Gz[i * npad + j];
+    return;
+  }
+  const double *Yz = Y + so;
+  const double m = mu[z];
+  const double dj = dv[j], ej = ev[j], ejl = j > 0 ? ev[j - 1] : 0.0;
+  // y(i) and (Y A~)(i) at column j; rows outside [0, npad) are zero
+  auto yrow = [&](int64_t i, double *yv, double *ya) {
+    if (i < 0 || i >= npad) {
+      *yv = 0.0;
+      *ya = 0.0;
+      return;
+    }
+    const double *r = Yz + i * npad + j;
+    const double yc = r[0];
+    const double yl = j > 0 ? r[-1] : 0.0, yr = j + 1 < npad ? r[1] : 0.0;
+    *yv = yc;
+    *ya = dj * yc + ejl * yl + ej * yr;
+  };
+  double ym, yam, y0, ya0, yp, yap;
+  yrow(i0 - 1, &ym, &yam);
+  yrow(i0, &y0, &ya0);
+  for (int64_t i = i0; i < i0 + 16; ++i) {
+    yrow(i + 1, &yp, &yap);
+    const double di = dv[i], ei = ev[i], eil = i > 0 ? ev[i - 1] : 0.0;
+    const double ay = di * y0 + eil * ym + ei * yp;      // (A~ Y)(i, j)
+    const double aya = di * ya0 + eil * yam + ei * yap;  // (A~ Y A~)(i, j)
+    qz[i * npad + j] = (float)(Gz[i * npad + j] + aya + m * (ay + ya0));
+    ym = y0;
+    yam = ya0;
+    y0 = yp;
+    ya0 = yap;
+  }
+}
+
+// After a solve along the rows of every slice that left x (float, chunk
+// carries pending in ab with the tables tab, shared by the slices): v = x +
+// carries, stored as outT[z][i][j] = v and out[z][j][i] = v (float) through
+// a 64 x 64 LDS tile.
+__global__ __launch_bounds__(256) void k_slice_xfinal(const float *__restrict__ x,
+                                                      const double *__restrict__ ab,
+                                                      const double *__restrict__ tab,
+                                                      float *__restrict__ outT,
+                                                      float *__restrict__ out, int64_t npad,
+                                                      int64_t mp0, int64_t mstride, int64_t ncmax) {
+  __shared__ float tile[64][65];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t z = blockIdx.z, r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int64_t so = z * npad * npad;
+  const double *abz = ab + z * (2 * ncmax * npad * 2);
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t y = r0 + rr, col = c0 + tx;
+    const int s = y >= mp0 ? 1 : 0;
+    const int64_t k = y - (s ? mp0 : 0), c = k / kChunk;
+    const double *tp = tab + (int64_t)s * kNTab * mstride;
+    const double *e = abz + (((int64_t)s * ncmax + c) * npad + col) * 2;
+    const float v = (float)((double)x[so + y * npad + col] + e[0] * tp[T_BF2 * mstride + k] +
+                            e[1] * tp[T_BK2 * mstride + k]);
+    outT[so + y * npad + col] = v;
+    tile[rr][tx] = v;
+  }
+  __syncthreads();
+  for (int rr = ty; rr < 64; rr += 4) out[so + (c0 + rr) * npad + r0 + tx] = tile[tx][rr];
 }
 
 // After the last inner sweep on every z-slice (chains = x columns, positions
@@ -336,11 +428,37 @@ hipError_t launch_cube_zfinal(const double *x, const double *ab, const double *t
   return hipGetLastError();
 }
 
-hipError_t launch_slice_final(const double *x, const double *ab, const double *const *tabs,
-                              double *out, double scale, int64_t npad, int64_t mp0,
-                              int64_t mstride, int64_t ncmax, hipStream_t st) {
+template <typename T>
+hipError_t launch_slice_final(const T *x, const double *ab, const double *const *tabs, double *out,
+                              double scale, int add, int64_t npad, int64_t mp0, int64_t mstride,
+                              int64_t ncmax, hipStream_t st) {
   dim3 grid((unsigned)((npad + 255) / 256), (unsigned)npad, (unsigned)npad);
-  hipLaunchKernelGGL(k_slice_final, grid, dim3(256), 0, st, x, ab, tabs, out, scale, npad, mp0,
+  hipLaunchKernelGGL(k_slice_final<T>, grid, dim3(256), 0, st, x, ab, tabs, out, scale, add, npad,
+                     mp0, mstride, ncmax);
+  return hipGetLastError();
+}
+template hipError_t launch_slice_final<double>(const double *, const double *, const double *const *,
+                                               double *, double, int, int64_t, int64_t, int64_t,
+                                               int64_t, hipStream_t);
+template hipError_t launch_slice_final<float>(const float *, const double *, const double *const *,
+                                              double *, double, int, int64_t, int64_t, int64_t,
+                                              int64_t, hipStream_t);
+
+hipError_t launch_zeig_residual(const double *G, const double *Y, const double *dv, const double *ev,
+                                const double *mu, float *q, int64_t npad, int64_t nslices,
+                                hipStream_t st) {
+  if (npad % 64 != 0 || nslices <= 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(npad / 64), (unsigned)(npad / 64), (unsigned)nslices);
+  hipLaunchKernelGGL(k_zeig_residual, grid, dim3(256), 0, st, G, Y, dv, ev, mu, q, npad);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_xfinal(const float *x, const double *ab, const double *tab, float *outT,
+                               float *out, int64_t npad, int64_t mp0, int64_t mstride,
+                               int64_t ncmax, int64_t nslices, hipStream_t st) {
+  if (npad % 64 != 0 || nslices <= 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(npad / 64), (unsigned)(npad / 64), (unsigned)nslices);
+  hipLaunchKernelGGL(k_slice_xfinal, grid, dim3(256), 0, st, x, ab, tab, outT, out, npad, mp0,
                      mstride, ncmax);
   return hipGetLastError();
 }

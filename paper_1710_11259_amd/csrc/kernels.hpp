@@ -23,7 +23,8 @@ namespace fps {
 //   output out_mode 0: v + og * g - sigma x stored transposed (requires
 //          ncols == ld == npad; the next pass then solves along the other
 //          index); 1: x in place orientation; 2: v + og * g - sigma x in place
-//          orientation.  Chunk-level carries are not applied by the
+//          orientation; 3: x stored transposed (as mode 0).  Chunk-level
+//          carries are not applied by the
 //          producer: it leaves its chunk boundary values in `lv`;
 //          launch_reduce turns them into carries, which the consumer (the
 //          next sweep, or a finalize kernel) folds in.
@@ -52,7 +53,9 @@ struct SweepArgs {
   int nc0, nc1;
   // Storage types (0: double, 1: float; arithmetic is double throughout).
   // Supported: without g, in/out = d/d, f/d, f/f; with g, in/g/out =
-  // d/d/d, d/f/d, f/f/d, f/f/f.
+  // d/d/d, d/f/d, f/f/d, f/f/f.  Stencil passes: d/d or f/f without g,
+  // d/d/d or f/f/f with g in the right-hand side, d/d/d with g in the
+  // output base.
   int in_f32, g_f32, out_f32;
 };
 
@@ -191,11 +194,27 @@ hipError_t launch_permute3_out(const double *src, double *dst, int64_t N, int64_
 hipError_t launch_cube_zfinal(const double *x, const double *ab, const double *tab, double *R,
                               double *RT, int64_t npad, int64_t mp0, int64_t mstride,
                               int64_t ncmax, hipStream_t st);
-// Per-slice finalization with a table per slice: out[z] = scale (x[z] +
-// chunk carries of slice z) when tabs[z] is non-null, else 0.
-hipError_t launch_slice_final(const double *x, const double *ab, const double *const *tabs,
-                              double *out, double scale, int64_t npad, int64_t mp0,
-                              int64_t mstride, int64_t ncmax, hipStream_t st);
+// Per-slice finalization with a table per slice: v = scale (x[z] + chunk
+// carries of slice z) when tabs[z] is non-null, else 0; out[z] = v, or
+// out[z] += v with `add` (x of storage type T).
+template <typename T>
+hipError_t launch_slice_final(const T *x, const double *ab, const double *const *tabs, double *out,
+                              double scale, int add, int64_t npad, int64_t mp0, int64_t mstride,
+                              int64_t ncmax, hipStream_t st);
+// z-eigenbasis cube, refinement: the negated residual of every slice
+// equation, q_z = G_z + A~ Y_z A~ + mu[z] (A~ Y_z + Y_z A~) (Y null: q = G),
+// FP64 arithmetic, stored in float; dv / ev the A~ stencil of
+// launch_residual; nslices arrays of npad x npad at stride npad^2.
+hipError_t launch_zeig_residual(const double *G, const double *Y, const double *dv, const double *ev,
+                                const double *mu, float *q, int64_t npad, int64_t nslices,
+                                hipStream_t st);
+// After a row solve of every slice that left x in place (float, chunk
+// carries pending in ab at the per-slice stride 2 ncmax npad 2, tables tab
+// shared by the slices): v = x + carries stored in float both as outT (x's
+// orientation) and out (transposed).
+hipError_t launch_slice_xfinal(const float *x, const double *ab, const double *tab, float *outT,
+                               float *out, int64_t npad, int64_t mp0, int64_t mstride,
+                               int64_t ncmax, int64_t nslices, hipStream_t st);
 // After the last per-slice sweep (chains = x, positions = y, ab per slice):
 // out = cy (x + chunk carries) + cr R + cb B.
 hipError_t launch_cube_ifinal(const double *x, const double *ab, const double *tab,

@@ -142,6 +142,18 @@ struct fps_plan {
   hipStream_t zside = nullptr;
   hipEvent_t zfork = nullptr, zjoin = nullptr;
   fps::detail::DeviceBuf d_Mz[2], d_PV[2], d_Vz[2];  // z maps: V^T S^-1 R, P V, V
+  // Refined z-eigenbasis plans (FPS_FP32_REFINED): round r corrects Y^ by
+  // solving, on every slice, (|mu| K + 1/2) dY + dY (|mu| K + 1/2) = K q K
+  // (K = -A~^-1, q the negated slice residual) with its own shifts; sorted
+  // slice k (|mu| descending) is storage slice zrslice[k] with zrJ[r][k]
+  // steps on tables zrtab0[r][k] + j; step j of round r has descriptor row
+  // zrrow0[r] + j and zractive[r][j] slices still iterating.  Table 0 is A~
+  // itself (the two solves that form K q K).
+  std::vector<int> zrslice;
+  std::vector<double> zrmu_slice;  // mu of every storage slice (0 for padding)
+  std::vector<std::vector<int>> zrJ, zrtab0, zractive;
+  std::vector<int> zrJmax, zrrow0;
+  fps::detail::DeviceBuf d_zrsw, d_zrrd, d_zrfin, d_zmu;
   std::vector<double> zV[2];  // host eigenvectors of the parity blocks (m x m, columns)
   int64_t ws_bytes = 0;
 

@@ -73,8 +73,8 @@ static_assert(T_L == 0 && T_IB == 1 && T_U == 2 && T_F1 == 3 && T_BK1 == 4, "tab
 //         tridiagonal stencil P (diagonal a.pre[r], coupling a.pre[npad + r]
 //         of rows r and r + 1) applied along the chain;
 //   x   = T^-1 rhs with T the pass's tridiagonal (tables);
-//   out = x (out_mode 1) or b - sigma x (out_mode 0, 2) with the output base
-//         b = v + og * g (kG == 2) or v.
+//   out = x (out_mode 1, 3) or b - sigma x (out_mode 0, 2) with the output
+//         base b = v + og * g (kG == 2) or v; modes 0 and 3 store transposed.
 // kG selects how a g array enters: 0 none, 1 the right-hand side, 2 the
 // output base (the two are kept apart to keep register pressure low).
 
@@ -285,7 +285,7 @@ __device__ __forceinline__ void compute_store(const SweepArgs &a, const Unit &u,
   // live on.
   constexpr bool kKeepV = kG != 0 || kPre;
   const double sigma = a.sigma;
-  const bool out_x = a.out_mode == 1;
+  const bool out_x = a.out_mode == 1 || a.out_mode == 3;
   double xnext = 0.0, xfirst = 0.0;
 #pragma unroll
   for (int i = kSeg - 1; i >= 0; --i) {
@@ -314,7 +314,7 @@ __device__ __forceinline__ void compute_store(const SweepArgs &a, const Unit &u,
   if (w == 0) a.lv[(((int64_t)u.c * 2 + u.s) * 2 + 1) * ncols + q.col] = xfirst + Tbk1[0] * cb1;
 
   Tout *__restrict__ out = (Tout *)a.out;
-  if (a.out_mode != 0) {
+  if (a.out_mode == 1 || a.out_mode == 2) {
     if (u.active) {
 #pragma unroll
       for (int i = 0; i < kSeg; ++i) out[(u.row0 + i) * ld + q.col] = (Tout)y[i];
@@ -446,14 +446,24 @@ hipError_t dispatch_sweep(const SweepLaunch &L, bool with_g) {
   if (with_g && a.og != 0.0 && a.sg != 0.0) return hipErrorInvalidValue;
   const bool g_out = with_g && a.og != 0.0;
   if (a.pre != nullptr) {
-    // stencil passes: float64 storage only; batched ones without g in the output
-    if (code != 0 || (L.d != nullptr && g_out)) return hipErrorInvalidValue;
-    if (!with_g)
-      L.go<double, double, double, 0, true>();
-    else if (g_out)
-      L.go<double, double, double, 2, true>();
-    else
-      L.go<double, double, double, 1, true>();
+    // stencil passes: float64 storage, or float storage without g (in/out
+    // f/f) and with g in the right-hand side (f/f/f); batched ones without g
+    // in the output
+    if (L.d != nullptr && g_out) return hipErrorInvalidValue;
+    if (code == 0) {
+      if (!with_g)
+        L.go<double, double, double, 0, true>();
+      else if (g_out)
+        L.go<double, double, double, 2, true>();
+      else
+        L.go<double, double, double, 1, true>();
+    } else if (!with_g && (code & 5) == 5) {
+      L.go<float, double, float, 0, true>();
+    } else if (with_g && !g_out && code == 7) {
+      L.go<float, float, float, 1, true>();
+    } else {
+      return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   if (g_out) return hipErrorInvalidValue;  // g in the output base: stencil passes only
@@ -481,7 +491,9 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st, hipEvent_t ev0, hipE
   if (a.npad % kCols != 0 || a.ncols % kCols != 0 || nchunks <= 0 || a.in == nullptr)
     return hipErrorInvalidValue;
   if ((a.ab_prev == nullptr) != (a.tab_prev == nullptr)) return hipErrorInvalidValue;
-  if (a.out_mode == 0 && (a.ncols != a.npad || a.ld != a.npad)) return hipErrorInvalidValue;
+  if ((a.out_mode == 0 || a.out_mode == 3) && (a.ncols != a.npad || a.ld != a.npad))
+    return hipErrorInvalidValue;
+  if (a.out_mode < 0 || a.out_mode > 3) return hipErrorInvalidValue;
   if (a.ld < a.ncols) return hipErrorInvalidValue;
   return dispatch_sweep(SweepLaunch{a, nullptr, nullptr, nullptr, 0, st, ev0, ev1}, a.g != nullptr);
 }

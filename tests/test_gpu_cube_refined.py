@@ -1,0 +1,58 @@
+"""GPU parity of the FP32-refined cube (z-eigenbasis method, refinement in
+the K-form of the slice equations) against the oracle's exact solution of the
+cube system (5.2): relative Frobenius and max-abs / max-abs error of U (or
+X) <= 1e-12."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import cube
+
+torch = pytest.importorskip("torch")
+import paper_1710_11259_amd as fps  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _errs(U, Uo):
+    return (np.linalg.norm(U - Uo) / np.linalg.norm(Uo), np.abs(U - Uo).max() / np.abs(Uo).max())
+
+
+def _plan(n, out="cheb", tight=True):
+    return fps.plan(n, tol=1e-13, dim=3, out=out, tight=tight, zeig=True, precision="fp32_refined")
+
+
+@pytest.mark.parametrize("n,out,tight", [(1, "cheb", True), (2, "native", False), (5, "cheb", True),
+                                         (16, "cheb", False), (33, "native", True),
+                                         (64, "cheb", True), (100, "cheb", False),
+                                         (256, "cheb", True)])
+def test_cube_refined_matches_exact(n, out, tight):
+    F = workloads.cube_rhs(n)
+    p = _plan(n, out, tight)
+    print(f"cube refined n={n} out={out} tight={tight} rounds {p.round_steps()}", flush=True)
+    U = fps.solve(p, torch.from_numpy(F).cuda())
+    torch.cuda.synchronize()
+    err, emax = _errs(U.cpu().numpy(), cube.poisson_cube(F, out=out))
+    print(f"rel err {err:.3e} max-abs {emax:.3e}", flush=True)
+    assert err <= 1e-12 and emax <= 1e-12
+
+
+def test_cube_refined_manufactured_solution():
+    n = 24
+    F, u_fun = workloads.manufactured_cube(n, N=40)
+    p = _plan(n)
+    U = fps.solve(p, torch.from_numpy(np.ascontiguousarray(F)).cuda())
+    torch.cuda.synchronize()
+    Uex = workloads.cheb_coeffs_3d(u_fun, n + 2)
+    assert np.abs(U.cpu().numpy() - Uex).max() <= 1e-12
+
+
+def test_cube_refined_deterministic_and_stale_workspace():
+    n = 40
+    F = torch.from_numpy(workloads.cube_rhs(n)).cuda()
+    p = _plan(n)
+    U1 = fps.solve(p, F)
+    ws = torch.full((p.workspace_bytes,), 0xFF, dtype=torch.uint8, device="cuda")
+    U2 = fps.solve(p, F, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)

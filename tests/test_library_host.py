@@ -126,9 +126,19 @@ def test_cube_plan_outer_shifts_match_oracle(n):
     assert p.inner_counts() == want
 
 
-def test_cube_plan_rejects_refined():
-    with pytest.raises(fps.FpsError):
+def test_cube_plan_refined_needs_zeig():
+    # the nested method has no refined form; the z-eigenbasis method does
+    with pytest.raises(fps.FpsError) as e:
         fps.plan(8, dim=3, precision="fp32_refined", host_only=True)
+    assert e.value.status == fps.FPS_E_UNSUPPORTED
+    p = fps.plan(64, tol=1e-13, dim=3, zeig=True, tight=True, precision="fp32_refined",
+                 host_only=True)
+    steps, tols = p.round_steps()
+    np.testing.assert_allclose(tols, [1e-5, 1e-5, 1e-4], rtol=1e-12)
+    assert p.rounds == 3 and p.f32_steps == sum(steps)
+    # slices sorted by |mu| descending: step counts of round 0 non-increasing
+    c = p.slice_counts()
+    assert len(c) == 64 and all(a >= b for a, b in zip(c, c[1:])) and c[0] == steps[0]
 
 
 def test_batch_queries_and_errors():
