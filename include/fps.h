@@ -105,12 +105,16 @@ typedef enum { FPS_OUT_CHEB = 0, FPS_OUT_NATIVE = 1 } fps_out;
 /*
  * Create a plan for a solve of size n (coefficients per dimension).
  *   dim        2 (square, Sec. 3) or 3 (cube, Sec. 5).
- *   n          >= 1.
+ *   n          >= 1; square plans n <= 16384 (chains of up to 128 chunks,
+ *              the chunk-carry scan's register form), cube plans n <= 384
+ *              (nested method) or n <= 512 (FPS_PLAN_CUBE_ZEIG);
+ *              FPS_E_UNSUPPORTED beyond.
  *   bc         FPS_BC_DIRICHLET_ZERO (the only value).
  *   tol        0 < tol < 1; the ADI count J follows (2.9), so that the
  *              symmetrized iterate satisfies ||Y - Y_J||_2 <= tol ||Y||_2
  *              (Theorem 2.1).
- *   prec       fps_prec.
+ *   prec       a value of fps_prec; cube plans take FPS_FP32_REFINED with
+ *              FPS_PLAN_CUBE_ZEIG only.
  *   out_basis  fps_out.
  *   flags      0 or a combination of FPS_PLAN_HOST_ONLY,
  *              FPS_PLAN_TIGHT_SPECTRUM, FPS_PLAN_CUBE_ZEIG (dim 3) and
@@ -327,7 +331,7 @@ void fps_plan_destroy(fps_plan *plan);
  * The ADI half-sweeps of all problems run as one launch per half-step (the
  * problems still iterating at that step), so a batch enqueues about 4 J_max
  * sweep/carry launches plus a fixed number of map launches per problem.
- *   dim must be 2; 1 <= count <= 65536; every n in [1, 65536]; tol, prec,
+ *   dim must be 2; 1 <= count <= 65536; every n in [1, 16384]; tol, prec,
  *   out_basis and flags as for fps_plan_create.  FPS_FP32_REFINED batches
  *   run the rounds of their plans (the same round tolerances for every
  *   problem), one batched inner ADI per round.
@@ -347,8 +351,10 @@ fps_status fps_batch_solve(fps_batch *batch, const double *F_dev, double *U_dev,
                            void *stream);
 /* Adjoint (vector-Jacobian product) of fps_batch_solve, the batched form of
  * fps_solve_adjoint: Ubar_dev in the batch's output layout, Fbar_dev
- * (written) in its input layout.  Each problem's symmetric-shift ADI map is
- * self-adjoint (App. D.5), so the adjoint runs the same batched sweeps
+ * (written) in its input layout.  Each problem's symmetric-shift ADI map of
+ * Algorithm 2 (shifts of Theorem 2.1) is self-adjoint in the Frobenius inner
+ * product (derived here: every term is phi(A~) G psi(A~) with symmetric
+ * phi, psi), so the adjoint runs the same batched sweeps
  * between the transposed coefficient maps; every problem's result equals
  * fps_solve_adjoint on that problem.  FP64 batches only (FPS_E_UNSUPPORTED
  * otherwise); same workspace and stream rules as fps_batch_solve. */

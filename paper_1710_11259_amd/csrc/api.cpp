@@ -297,6 +297,9 @@ fps_status plan_common(fps_plan **out, int dim, int64_t n, int bc, double tol, i
   if (dim != 2 && dim != 3) return fail(FPS_E_ARG, "dim must be 2 or 3");
   if (n < 1) return fail(FPS_E_ARG, "n must be >= 1");
   if (n > 200000) return fail(FPS_E_ARG, "n too large");
+  // Square and rectangle plans: chains of up to 8192 positions per parity
+  // (128 chunks), the largest the chunk-carry scan keeps in registers.
+  if (dim == 2 && n > 16384) return fail(FPS_E_UNSUPPORTED, "square and rectangle plans need n <= 16384");
   if (bc != FPS_BC_DIRICHLET_ZERO) return fail(FPS_E_UNSUPPORTED, "only zero Dirichlet data");
   if (!(tol > 0.0 && tol < 1.0)) return fail(FPS_E_ARG, "tol must lie in (0, 1)");
   if (prec != FPS_FP64 && prec != FPS_FP32_REFINED) return fail(FPS_E_ARG, "bad precision");
@@ -313,7 +316,8 @@ fps_status plan_common(fps_plan **out, int dim, int64_t n, int bc, double tol, i
   if (dim == 3 && prec != FPS_FP64 && !(flags & FPS_PLAN_CUBE_ZEIG))
     return fail(FPS_E_UNSUPPORTED,
                 "FP32_REFINED cube plans need the z-eigenbasis method (FPS_PLAN_CUBE_ZEIG)");
-  if (dim == 3 && n > 1024) return fail(FPS_E_UNSUPPORTED, "cube solves are limited to n <= 1024");
+  if (dim == 3 && !(flags & FPS_PLAN_CUBE_ZEIG) && n > 384)
+    return fail(FPS_E_UNSUPPORTED, "the nested cube method is limited to n <= 384");
   fps_plan *pl = new (std::nothrow) fps_plan();
   if (!pl) return fail(FPS_E_NOMEM, "plan allocation failed");
   pl->dim = dim;

@@ -11,6 +11,7 @@
 #include <numeric>
 #include <vector>
 
+#include "launch_limits.hpp"
 #include "solver.hpp"
 
 using namespace fps::detail;
@@ -211,9 +212,9 @@ fps_status build_descriptors(fps_batch *bt) {
 }
 
 // Tables of the batched element-wise launches (sorted order, largest
-// problems first).  Left unbuilt (elem_ok false) when a launch would exceed
-// kElemMaxWg workgroups, where the maps would take hundreds of MB.
-constexpr int64_t kElemMaxWg = (int64_t)1 << 25;
+// problems first).  Left unbuilt (elem_ok false) when a launch would not fit
+// one 1-D grid of 256-thread workgroups (elem_launch_fits); such batches
+// keep the per-problem launches.
 
 fps_status build_elem_tables(fps_batch *bt) {
   const int C = bt->count;
@@ -227,7 +228,7 @@ fps_status build_elem_tables(fps_batch *bt) {
     const int64_t W = bt->ws_off[b], rowb = (L.npad + 255) / 256, tb = L.npad / 64;
     const int64_t nwg[3] = {rowb * L.npad, tb * tb, rowb * L.npad};
     for (int t = 0; t < 3; ++t)
-      if (tot[t] + nwg[t] > kElemMaxWg) return FPS_OK;  // elem_ok stays false
+      if (!fps::elem_launch_fits(tot[t] + nwg[t])) return FPS_OK;  // elem_ok stays false
     fps::ElemDesc e{};
     e.n = L.n;
     e.npad = L.npad;
@@ -386,7 +387,7 @@ fps_status fps_batch_create(fps_batch **out, int dim, int count, const int64_t *
   if (count < 1 || count > 65536) return fail(FPS_E_ARG, "count must lie in [1, 65536]");
   if (!n) return fail(FPS_E_ARG, "n must not be null");
   for (int b = 0; b < count; ++b)
-    if (n[b] < 1 || n[b] > 65536) return fail(FPS_E_ARG, "every n must lie in [1, 65536]");
+    if (n[b] < 1 || n[b] > 16384) return fail(FPS_E_ARG, "every n must lie in [1, 16384]");
   fps_batch *bt = new (std::nothrow) fps_batch();
   if (!bt) return fail(FPS_E_NOMEM, "batch allocation failed");
   bt->count = count;

@@ -1106,12 +1106,21 @@ fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
     // their short launches at the end overlap the bulk; launches timed per
     // dispatch all go to the caller's stream.
     if (pl->zsplit > 0 && pl->zsplit < K && pl->zside && pl->ev.empty()) {
+      // One solve at a time forks onto the side stream, so the event
+      // records and waits of concurrent host threads do not interleave.  The
+      // join is enqueued whatever the groups returned, so the side stream
+      // (or a graph being captured) is never left forked.
+      std::lock_guard<std::mutex> lk(pl->zlock);
       FPS_HIP(hipEventRecord(pl->zfork, st));
       FPS_HIP(hipStreamWaitEvent(pl->zside, pl->zfork, 0));
-      FPS_HIP(run_group(0, pl->zsplit, pl->zside));
-      FPS_HIP(run_group(pl->zsplit, K, st));
-      FPS_HIP(hipEventRecord(pl->zjoin, pl->zside));
-      FPS_HIP(hipStreamWaitEvent(st, pl->zjoin, 0));
+      const hipError_t e1 = run_group(0, pl->zsplit, pl->zside);
+      const hipError_t e2 = e1 == hipSuccess ? run_group(pl->zsplit, K, st) : hipSuccess;
+      const hipError_t e3 = hipEventRecord(pl->zjoin, pl->zside);
+      const hipError_t e4 = e3 == hipSuccess ? hipStreamWaitEvent(st, pl->zjoin, 0) : e3;
+      FPS_HIP(e1);
+      FPS_HIP(e2);
+      FPS_HIP(e3);
+      FPS_HIP(e4);
     } else {
       FPS_HIP(run_group(0, K, st));
     }

@@ -84,20 +84,13 @@ bool zolotarev_shifts(double a, double b, double c, double d, double tol, ShiftS
   const long double g = cross_ratio(a, b, c, d);
   const long double alpha = -1.0L + 2.0L * g + 2.0L * std::sqrt(g * g - g);
   const long double m1 = 1.0L / (alpha * alpha);
+  // K and dn in the complementary parameter m1 = 1/alpha^2 for every alpha:
+  // neither forms 1 - m1, so no separate large-alpha evaluation is needed
+  // (m1 reaches ~1e-41 for the square enclosure at n = 2e5, far inside the
+  // extended-precision range).
   std::vector<long double> dn(J);
-  if (alpha < 1e7L) {
-    const long double K = ellip_K_comp(m1);
-    for (int j = 0; j < J; ++j) dn[j] = ellip_dn_comp((j + 0.5L) * K / J, m1, K);
-  } else {
-    // App. A: leading terms of K and dn in the complementary parameter.
-    const long double la = std::log(alpha), l2 = std::log(2.0L);
-    const long double K = (2 * l2 + la) + (-1 + 2 * l2 + la) * m1 / 4;
-    for (int j = 0; j < J; ++j) {
-      long double u = (j + 0.5L) * K / J;
-      long double sech = 1.0L / std::cosh(u);
-      dn[j] = sech + 0.25L * m1 * (std::sinh(u) * std::cosh(u) + u) * std::tanh(u) * sech;
-    }
-  }
+  const long double K = ellip_K_comp(m1);
+  for (int j = 0; j < J; ++j) dn[j] = ellip_dn_comp((j + 0.5L) * K / J, m1, K);
   out.J = J;
   out.p.resize(J);
   out.q.resize(J);

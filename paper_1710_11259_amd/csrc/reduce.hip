@@ -1,8 +1,9 @@
 // gfx950 chunk-carry kernels of the ADI half-sweeps.  A sweep solves every
 // chunk of every chain with zero carry-in and leaves two boundary values per
 // chain and chunk; these kernels run the chunk-level recurrences of each
-// chain (App. D.4 systems, partitioned) and write the carries that the next
-// sweep folds into its input.
+// chain (the shifted tridiagonal solves of Algorithm 2, one chain per parity
+// block, partitioned into chunks) and write the carries that the next sweep
+// folds into its input.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -27,9 +28,9 @@ namespace {
 // and the lane expands its chunks serially from there.  Lanes without
 // chunks hold the identity, so a chunk's result does not depend on kL.
 // (A few chunks per lane keep the scan short: 4 shuffle steps at most,
-// and a quarter of the wavefronts of one lane per chunk.)  The forward pass
-// parks the unscaled cf in ab for the backward pass (each lane rereads only
-// what it wrote).
+// and a quarter of the wavefronts of one lane per chunk.)  A lane keeps its
+// chunks' data and forward carries in registers (at most 8 chunks per lane:
+// chains of up to 128 chunks).
 // Lanes that a chain's scan spans at most, and the chunks each lane owns:
 // a function of the chain's own chunk count only, so batched launches (whose
 // segment width kL covers their longest chain) compute every chain exactly
@@ -37,75 +38,6 @@ namespace {
 constexpr int kScanLanes = kReduceMaxLanes;
 __device__ __forceinline__ int chunks_per_lane(int nc) {
   return (nc + kScanLanes - 1) / kScanLanes;
-}
-
-template <int kL>
-__device__ __forceinline__ void reduce_chain_scan(const double *__restrict__ lv,
-                                                  const double *__restrict__ ct,
-                                                  double *__restrict__ ab, double scale,
-                                                  int64_t nchains, int nc, int64_t ncmax, int s,
-                                                  int64_t r, int lane) {
-  const double *__restrict__ yl = lv + (int64_t)s * 2 * nchains + r;  // chunk k at k * 4 nchains
-  const double *__restrict__ xf = yl + nchains;
-  double *__restrict__ o = ab + ((int64_t)s * ncmax * nchains + r) * 2;  // chunk k at k * 2 nchains
-  const int q = chunks_per_lane(nc);
-  const int lo = lane * q < nc ? lane * q : nc;
-  const int hi = lo + q < nc ? lo + q : nc;
-  // forward: this lane's composed map, cf[hi] = fa cf[lo] + fb
-  double fa = 1.0, fb = 0.0;
-  for (int k = lo; k < hi; ++k) {
-    const double a = ct[C_F2LAST * ncmax + k];
-    fb = a * fb + yl[(int64_t)k * 4 * nchains];
-    fa = a * fa;
-  }
-#pragma unroll
-  for (int d = 1; d < kL; d <<= 1) {  // fb <- cf[hi]
-    const double pa = __shfl_up(fa, d, kL), pb = __shfl_up(fb, d, kL);
-    if (lane >= d) {
-      fb = fa * pb + fb;
-      fa = fa * pa;
-    }
-  }
-  double cf = __shfl_up(fb, 1, kL);  // cf[lo]
-  if (lane == 0) cf = 0.0;
-  // forward expansion (cf parked unscaled) and this lane's composed backward
-  // map, cb[lo] = ba cb[hi] + bb; the last chunk's map is the identity
-  double ba = 1.0, bb = 0.0;
-  for (int k = lo; k < hi; ++k) {
-    o[(int64_t)k * 2 * nchains] = cf;
-    cf = k + 1 == hi ? fb : ct[C_F2LAST * ncmax + k] * cf + yl[(int64_t)k * 4 * nchains];
-    if (k + 1 < nc) {
-      const double b = ct[C_BK2FIRST * ncmax + k + 1];
-      const double c = xf[(int64_t)(k + 1) * 4 * nchains] + ct[C_BF2FIRST * ncmax + k + 1] * cf;
-      bb = ba * c + bb;
-      ba = ba * b;
-    }
-  }
-#pragma unroll
-  for (int d = 1; d < kL; d <<= 1) {  // bb <- cb[lo]
-    const double na = __shfl_down(ba, d, kL), nb = __shfl_down(bb, d, kL);
-    if (lane + d < kL) {
-      bb = ba * nb + bb;
-      ba = ba * na;
-    }
-  }
-  double cb = __shfl_down(bb, 1, kL);  // cb[hi]
-  if (lane + 1 >= kL) cb = 0.0;
-  // backward expansion, chunks hi-1 .. lo; cfn = unscaled cf of chunk k + 1
-  double cfn = fb;
-  for (int k = hi - 1; k >= lo; --k) {
-    const double cfk = o[(int64_t)k * 2 * nchains];
-    if (k == lo)
-      cb = bb;
-    else if (k + 1 < nc)
-      cb = ct[C_BK2FIRST * ncmax + k + 1] * cb +
-           (xf[(int64_t)(k + 1) * 4 * nchains] + ct[C_BF2FIRST * ncmax + k + 1] * cfn);
-    else
-      cb = 0.0;
-    o[(int64_t)k * 2 * nchains] = scale * cfk;
-    o[(int64_t)k * 2 * nchains + 1] = scale * cb;
-    cfn = cfk;
-  }
 }
 
 // Where one chain's chunk data sits: boundary values y (last forward value)
@@ -118,11 +50,9 @@ struct ChainSrc {
   int64_t ctstride;
 };
 
-// The same computation with at most kQ chunks per lane held in registers:
-// every load is issued before the first use (one round of memory latency)
-// and cf stays in registers.  Identical arithmetic in the same order, so a
-// chunk's result does not depend on which form ran.  o: the chain's
-// output, chunk k at k * ostride (cf, cb).
+// The scan with at most kQ chunks per lane held in registers: every load is
+// issued before the first use (one round of memory latency) and cf stays in
+// registers.  o: the chain's output, chunk k at k * ostride (cf, cb).
 template <int kL, int kQ>
 __device__ __forceinline__ void reduce_chain_scan_reg(const ChainSrc &src, double *__restrict__ o,
                                                       int64_t ostride, double scale, int nc,
@@ -215,14 +145,10 @@ __device__ __forceinline__ void reduce_block(const double *__restrict__ lv,
   const int ch = threadIdx.x / kL, lane = threadIdx.x % kL;
   const int64_t r = r0 + ch;
   if (r >= nchains || nc == 0) return;  // whole kL-lane segments leave together
-  if constexpr (kQ > 0) {
-    const double *yl = lv + (int64_t)s * 2 * nchains + r;
-    const ChainSrc src{yl, yl + nchains, 4 * nchains, ct, ncmax};
-    reduce_chain_scan_reg<kL, kQ>(src, ab + ((int64_t)s * ncmax * nchains + r) * 2, 2 * nchains,
-                                  scale, nc, lane);
-  } else {
-    reduce_chain_scan<kL>(lv, ct, ab, scale, nchains, nc, ncmax, s, r, lane);
-  }
+  const double *yl = lv + (int64_t)s * 2 * nchains + r;
+  const ChainSrc src{yl, yl + nchains, 4 * nchains, ct, ncmax};
+  reduce_chain_scan_reg<kL, kQ>(src, ab + ((int64_t)s * ncmax * nchains + r) * 2, 2 * nchains,
+                                scale, nc, lane);
 }
 
 // Grid: (ceil(nchains / (kReduceThreads / kL)), 2 parities, batch);
@@ -253,7 +179,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_batch(
 }
 
 // Kernel shape for chains of up to ncmax chunks: lanes per chain, and the
-// bound kQ of chunks per lane held in registers (0: more than 8, memory form).
+// bound kQ of chunks per lane held in registers (0: more than 8 chunks per
+// lane, i.e. more than 128 per chain, which no plan creates).
 void reduce_shape(int64_t ncmax, int *lanes, int *kq) {
   *lanes = reduce_lanes(ncmax);
   const int64_t q = (ncmax + kScanLanes - 1) / kScanLanes;
@@ -280,7 +207,7 @@ void reduce_shape(int64_t ncmax, int *lanes, int *kq) {
     else if ((kq) == 8)                          \
       LAUNCH(16, 8);                             \
     else                                         \
-      LAUNCH(16, 0);                             \
+      return hipErrorInvalidValue;               \
   } while (0)
 
 hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -141,6 +142,9 @@ struct fps_plan {
   int zsplit = 0;
   hipStream_t zside = nullptr;
   hipEvent_t zfork = nullptr, zjoin = nullptr;
+  // Held while one solve enqueues its fork, both slice groups and its join,
+  // so concurrent host threads' solves do not interleave on zside.
+  std::mutex zlock;
   fps::detail::DeviceBuf d_Mz[2], d_PV[2], d_Vz[2];  // z maps: V^T S^-1 R, P V, V
   // Refined z-eigenbasis plans (FPS_FP32_REFINED): round r corrects Y^ by
   // solving, on every slice, (|mu| K + 1/2) dY + dY (|mu| K + 1/2) = K q K

@@ -2,9 +2,11 @@
 #include <cstring>
 #include <vector>
 
+#include "../paper_1710_11259_amd/csrc/launch_limits.hpp"
 #include "../paper_1710_11259_amd/csrc/planner.hpp"
 
 extern "C" {
+int shim_elem_launch_fits(long long workgroups) { return fps::elem_launch_fits(workgroups) ? 1 : 0; }
 void shim_layout(long long n, long long *out) {
   fps::Layout L = fps::make_layout(n);
   long long v[] = {L.m[0], L.m[1], L.mp[0], L.mp[1], L.npad, L.nc[0], L.nc[1], L.ncmax,

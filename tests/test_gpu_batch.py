@@ -4,6 +4,7 @@ per-problem arithmetic), and the exact discrete solution of the oracle."""
 import numpy as np
 import pytest
 
+import parity
 import workloads
 from oracle import square
 
@@ -43,9 +44,7 @@ def test_batch_equals_single_solves_bitwise(out, precision):
     for n, F, Ub in zip(MIXED, Fs, Us):
         if n <= 300:
             Uo = square.poisson_square(F, out=out)
-            err = np.linalg.norm(Ub - Uo) / np.linalg.norm(Uo)
-            emax = np.abs(Ub - Uo).max() / np.abs(Uo).max()
-            assert err <= 1e-12 and emax <= 1e-12, f"n={n}: rel err {err:.3e} / {emax:.3e}"
+            parity.check(Ub, Uo, 1e-12, f"n={n}")
 
 
 @pytest.mark.parametrize("out", ["cheb", "native"])
@@ -85,10 +84,7 @@ def test_batch_refined_matches_oracle():
     for n, F, Ub in zip(ns, Fs, b.unpack(U)):
         Uo = square.poisson_square(F)
         Ub = Ub.cpu().numpy()
-        err = np.linalg.norm(Ub - Uo) / np.linalg.norm(Uo)
-        emax = np.abs(Ub - Uo).max() / np.abs(Uo).max()
-        print(f"refined n={n} rel err {err:.3e} max-abs {emax:.3e}", flush=True)
-        assert err <= 1e-12 and emax <= 1e-12
+        parity.check(Ub, Uo, 1e-12, f"refined n={n}")
 
 
 def test_batch_workload_256_problems():
@@ -111,8 +107,30 @@ def test_batch_workload_256_problems():
     order = np.argsort(ns)
     for i in order[:: max(1, len(ns) // 8)]:
         Uo = square.poisson_square(Fs[i])
-        err = np.linalg.norm(Us[i].cpu().numpy() - Uo) / np.linalg.norm(Uo)
-        assert err <= 1e-12, f"problem {i} (n={ns[i]}): rel err {err:.3e}"
+        parity.check(Us[i].cpu().numpy(), Uo, 1e-12)
+
+
+def test_batch_workload_256_problems_refined():
+    # The FP32-refined batch of the 256-problem workload: bit-identical to the
+    # refined single solves for one problem of every size, and against the
+    # oracle on a sample spanning the sizes.
+    ns, Fs = workloads.batched_problems()
+    b = fps.batch(ns, tol=1e-13, precision="fp32_refined")
+    print(f"256-problem refined batch, max J {b.max_J}", flush=True)
+    U = fps.batch_solve(b, b.pack(Fs))
+    torch.cuda.synchronize()
+    Us = b.unpack(U)
+    seen = set()
+    for i, n in enumerate(ns):
+        if n in seen or len(seen) >= 8:
+            continue
+        seen.add(n)
+        Ur = _single(n, Fs[i], tol=1e-13, precision="fp32_refined")
+        assert np.array_equal(Us[i].cpu().numpy(), Ur), f"problem {i} (n={n})"
+    order = np.argsort(ns)
+    for i in order[:: max(1, len(ns) // 10)]:
+        parity.check(Us[i].cpu().numpy(), square.poisson_square(Fs[i]), 1e-12,
+                     f"refined problem {i} n={ns[i]}")
 
 
 def test_batch_graph_replays_match_eager():

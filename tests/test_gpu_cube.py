@@ -3,6 +3,7 @@ oracle's exact eigen-decomposition solution of the cube system (5.2)."""
 import numpy as np
 import pytest
 
+import parity
 import workloads
 from oracle import cube
 
@@ -27,9 +28,7 @@ def test_cube_matches_exact_discrete_solution(n, out):
     F = workloads.cube_rhs(n)
     U = _solve(n, F, out)
     Uo = cube.poisson_cube(F, out=out)
-    err = np.linalg.norm(U - Uo) / np.linalg.norm(Uo)
-    print(f"rel err {err:.3e}", flush=True)
-    assert err <= 1e-12
+    parity.check(U, Uo, 1e-12)
 
 
 def test_cube_manufactured_solution():
@@ -48,9 +47,7 @@ def test_cube_headline_size():
     F = workloads.cube_rhs(n)
     U = _solve(n, F)
     Uo = cube.poisson_cube(F)
-    err = np.linalg.norm(U - Uo) / np.linalg.norm(Uo)
-    print(f"cube n=256 rel err {err:.3e}", flush=True)
-    assert err <= 1e-12
+    parity.check(U, Uo, 1e-12)
 
 
 @pytest.mark.parametrize("n", [5, 64, 256])
@@ -61,9 +58,7 @@ def test_cube_tight_spectrum_matches_exact(n):
     U = fps.solve(p, torch.from_numpy(F).cuda())
     torch.cuda.synchronize()
     Uo = cube.poisson_cube(F)
-    err = np.linalg.norm(U.cpu().numpy() - Uo) / np.linalg.norm(Uo)
-    print(f"rel err {err:.3e}", flush=True)
-    assert err <= 1e-12
+    parity.check(U.cpu().numpy(), Uo, 1e-12)
 
 
 @pytest.mark.parametrize("n,out,tight", [(1, "cheb", False), (2, "cheb", True), (5, "native", True),
@@ -79,9 +74,7 @@ def test_cube_zeig_matches_exact(n, out, tight):
     U = fps.solve(p, torch.from_numpy(F).cuda())
     torch.cuda.synchronize()
     Uo = cube.poisson_cube(F, out=out)
-    err = np.linalg.norm(U.cpu().numpy() - Uo) / np.linalg.norm(Uo)
-    print(f"rel err {err:.3e}", flush=True)
-    assert err <= 1e-12
+    parity.check(U.cpu().numpy(), Uo, 1e-12)
 
 
 def test_cube_zeig_manufactured_solution():
@@ -117,3 +110,29 @@ def test_cube_zeig_two_streams_equal_one(n):
     torch.cuda.synchronize()
     assert torch.equal(U1, U2)
     assert torch.equal(U3, U2)
+
+
+_ORACLE = {}
+
+
+def _oracle(n):
+    if n not in _ORACLE:
+        print(f"oracle n={n}", flush=True)
+        _ORACLE[n] = cube.poisson_cube(workloads.cube_rhs(n))
+    return _ORACLE[n]
+
+
+@pytest.mark.parametrize("n,zeig,precision", [(384, False, "fp64"), (384, True, "fp64"),
+                                              (384, True, "fp32_refined"), (512, True, "fp64"),
+                                              (512, True, "fp32_refined")])
+def test_cube_largest_sizes_match_exact(n, zeig, precision):
+    # the largest sizes each cube method accepts (nested 384, z-eigenbasis
+    # 512, whose two-stream split puts the most slices on the second stream)
+    F = torch.from_numpy(workloads.cube_rhs(n)).cuda()
+    p = fps.plan(n, tol=1e-13, dim=3, tight=True, zeig=zeig, precision=precision)
+    print(f"cube n={n} zeig={zeig} {precision} ws={p.workspace_bytes / 2**30:.2f} GiB", flush=True)
+    U = fps.solve(p, F).cpu().numpy()
+    del p, F
+    torch.cuda.empty_cache()
+    parity.check(U, _oracle(n), 1e-12, f"cube n={n} zeig={zeig} {precision}")
+

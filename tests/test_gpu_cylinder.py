@@ -3,6 +3,7 @@ per-mode Galerkin solutions."""
 import numpy as np
 import pytest
 
+import parity
 import workloads
 from oracle import cylinder
 
@@ -21,10 +22,6 @@ def _join(U):
     return u[:, 0] + 1j * u[:, 1]
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
 # n = 254, 258 and 260: the output maps have 0 / 2 / 3 z columns and 1 / 3 / 4
 # r rows past a whole 128 x 128 tile, which the edge kernels compute.
 @pytest.mark.parametrize("n,nt", [(2, 2), (4, 4), (6, 8), (16, 16), (32, 24), (64, 64), (128, 96),
@@ -36,9 +33,7 @@ def test_cylinder_matches_oracle(n, nt):
     U = fps.solve(p, _split(F))
     torch.cuda.synchronize()
     Uo = cylinder.poisson_cylinder(F)
-    err = _rel(_join(U), Uo)
-    print(f"rel err {err:.3e}", flush=True)
-    assert err <= 1e-12
+    parity.check(_join(U), Uo, 1e-12, f"cylinder n={n}")
 
 
 def test_cylinder_manufactured_solution():
@@ -62,7 +57,7 @@ def test_cylinder_stale_workspace_and_determinism():
     torch.cuda.synchronize()
     assert torch.equal(U1, U2)
     Uo = cylinder.poisson_cylinder(workloads.cylinder_rhs(n, nt, seed=2))
-    assert _rel(_join(U1), Uo) <= 1e-12
+    parity.check(_join(U1), Uo, 1e-12)
 
 
 def test_cylinder_full_size_sampled_modes():
@@ -76,6 +71,4 @@ def test_cylinder_full_size_sampled_modes():
         idx = k + nt // 2
         Uo = (cylinder.solve_mode(np.ascontiguousarray(F[idx].real), k)
               + 1j * cylinder.solve_mode(np.ascontiguousarray(F[idx].imag), k))
-        err = _rel(U[idx], Uo)
-        print(f"mode {k}: rel err {err:.3e}", flush=True)
-        assert err <= 1e-12
+        parity.check(U[idx], Uo, 1e-12, f"mode {k}")

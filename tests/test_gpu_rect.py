@@ -3,6 +3,7 @@ per ADI step) and of nonhomogeneous Dirichlet data against the oracle."""
 import numpy as np
 import pytest
 
+import parity
 import workloads
 from oracle import basis, rect, square
 
@@ -13,10 +14,6 @@ pytestmark = pytest.mark.gpu
 
 BOXES = [(0.0, 2.5, -1.0, 0.25), (0.0, 10.0, 0.0, 1.0)]
 UNIT = (-1.0, 1.0, -1.0, 1.0)
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def _dev(x):
@@ -39,9 +36,7 @@ def test_rect_adi_iterate_matches_closed_form(n, tol, box):
     Y = fps.adi_native(p, _dev(G))
     torch.cuda.synchronize()
     Yo = rect.adi_iterate_rect(G, box, po, qo)
-    err = _rel(Y.cpu().numpy(), Yo)
-    print(f"rel err {err:.3e}", flush=True)
-    assert err < 1e-12
+    parity.check(Y.cpu().numpy(), Yo, 1e-12, f"rect adi_native n={n}")
 
 
 @pytest.mark.parametrize("box", BOXES)
@@ -51,7 +46,7 @@ def test_rect_solve_matches_exact_discrete_solution(n, box):
     print(f"rect solve n={n} box={box}", flush=True)
     U = fps.solve(fps.plan(n, tol=1e-13, box=box), _dev(F))
     torch.cuda.synchronize()
-    assert _rel(U.cpu().numpy(), rect.poisson_rect(F, box)) <= 1e-12
+    parity.check(U.cpu().numpy(), rect.poisson_rect(F, box), 1e-12)
 
 
 @pytest.mark.parametrize("box", BOXES)
@@ -66,7 +61,7 @@ def test_rect_native_tight_and_refined(box):
         print(f"rect n={n} box={box} {kw}", flush=True)
         U = fps.solve(fps.plan(n, tol=1e-13, box=box, **kw), _dev(F))
         torch.cuda.synchronize()
-        assert _rel(U.cpu().numpy(), ref) <= 1e-12, kw
+        parity.check(U.cpu().numpy(), ref, 1e-12)
 
 
 def test_rect_full_size():
@@ -76,7 +71,7 @@ def test_rect_full_size():
     print("rect n=4096 fp64 tight", flush=True)
     U = fps.solve(fps.plan(n, tol=1e-13, box=box, tight=True), _dev(F))
     torch.cuda.synchronize()
-    assert _rel(U.cpu().numpy(), rect.poisson_rect(F, box)) <= 1e-12
+    parity.check(U.cpu().numpy(), rect.poisson_rect(F, box), 1e-12)
 
 
 @pytest.mark.parametrize("box", [None] + BOXES)
@@ -89,8 +84,7 @@ def test_dirichlet_matches_oracle(n, box):
     torch.cuda.synchronize()
     Uo = rect.poisson_rect_dirichlet(F, bc, box or UNIT)
     Ug = U.cpu().numpy()
-    print(f"rel err {_rel(Ug, Uo):.3e}", flush=True)
-    assert _rel(Ug, Uo) <= 1e-12
+    parity.check(Ug, Uo, 1e-12, f"dirichlet n={n}")
     for got, want in zip(rect.boundary_traces(Ug), bc):
         assert np.abs(got - want).max() <= 1e-12 * np.abs(bc).max()
 
@@ -105,10 +99,7 @@ def test_dirichlet_refined_and_tight(box, n):
         U = fps.solve_dirichlet(fps.plan(n, tol=1e-13, box=box, dirichlet=True, **kw), _dev(F),
                                 _dev(bc))
         torch.cuda.synchronize()
-        Ug = U.cpu().numpy()
-        err, emax = _rel(Ug, Uo), np.abs(Ug - Uo).max() / np.abs(Uo).max()
-        print(f"rel err {err:.3e} max-abs {emax:.3e}", flush=True)
-        assert err <= 1e-12 and emax <= 1e-12, kw
+        parity.check(U.cpu().numpy(), Uo, 1e-12, f"dirichlet n={n} {kw}")
 
 
 def test_dirichlet_full_size():
@@ -124,9 +115,7 @@ def test_dirichlet_full_size():
     for got, want in zip(rect.boundary_traces(Ug), bc):
         assert np.abs(got - want).max() <= 1e-12 * np.abs(bc).max()
     Uo = rect.poisson_rect_dirichlet(F, bc, box)
-    err = _rel(Ug, Uo)
-    print(f"rel err {err:.3e}", flush=True)
-    assert err <= 1e-12
+    parity.check(Ug, Uo, 1e-12, "dirichlet n=4096")
 
 
 def test_dirichlet_manufactured_solution():
@@ -187,7 +176,7 @@ def test_rect_adjoint_matches_oracle_vjp(n):
     R = basis.cheb_to_ct(n)
     Gb = rect.adi_iterate_rect((P.T @ Ub @ P) / np.outer(s, s), box, po, qo) / np.outer(s, s)
     ref = R.T @ Gb @ R
-    assert _rel(Fb.cpu().numpy(), ref) < 1e-12
+    parity.check(Fb.cpu().numpy(), ref, 1e-12)
 
 
 def test_rect_dot_product_identity():

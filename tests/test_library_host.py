@@ -83,6 +83,22 @@ def test_workspace_and_extent_queries():
     assert q.out_entries == 100 * 100
 
 
+def test_size_limits():
+    # square/rectangle plans up to n = 16384 (the register form of the
+    # chunk-carry scan), nested cubes to 384, z-eigenbasis cubes to 512
+    with pytest.raises(fps.FpsError) as e:
+        fps.plan(16385, host_only=True)
+    assert e.value.status == fps.FPS_E_UNSUPPORTED
+    with pytest.raises(fps.FpsError) as e:
+        fps.plan(385, dim=3, host_only=True)
+    assert e.value.status == fps.FPS_E_UNSUPPORTED
+    with pytest.raises(fps.FpsError) as e:
+        fps.plan(513, dim=3, zeig=True, host_only=True)
+    assert e.value.status == fps.FPS_E_UNSUPPORTED
+    with pytest.raises(fps.FpsError):
+        fps.batch([64, 16385], host_only=True)
+
+
 @pytest.mark.parametrize("n", [64, 512, 4096])
 def test_refinement_structure(n):
     # FP64: one round, no float steps.  FP32_REFINED to 1e-13: rounds to
@@ -199,12 +215,36 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-@pytest.mark.parametrize("alpha", [30.0, 480.0, 7680.0, 1.2e5, 2e6, 9.9e6])
-def test_agm_dn_branch_matches_exact(shim, alpha):
+@pytest.mark.parametrize("alpha", [30.0, 480.0, 7680.0, 1.2e5, 2e6, 9.9e6, 1e7, 3.1e9, 4.8e13,
+                                   7.7e17, 1e20])
+def test_complementary_parameter_dn_matches_exact(shim, alpha):
+    # K and dn from Carlson's R_F and Newton inversion in m1 = 1/alpha^2, for
+    # every alpha (the square enclosure at n = 10^4 reaches alpha ~ 1e18)
     J = 40
     dn = np.zeros(J)
     shim.shim_dn(alpha, J, _ptr(dn))
     assert np.allclose(dn, oshifts.exact_dn(alpha, J), rtol=1e-14)
+
+
+@pytest.mark.parametrize("delta", [1e-9, 1e-14, 1e-20])
+def test_library_shifts_large_alpha_match_exact(delta):
+    # symmetric intervals [-1, -delta], [delta, 1]: p_j = -dn_j, so the
+    # library's shifts pin its dn at the huge alpha of tiny delta
+    p, q = fps.adi_shifts(-1.0, -delta, delta, 1.0, 1e-10)
+    g = oshifts.cross_ratio(-1.0, -delta, delta, 1.0)
+    alpha = -1.0 + 2.0 * g + 2.0 * np.sqrt(g * g - g)
+    assert alpha > 1e8
+    np.testing.assert_allclose(-np.array(p), oshifts.exact_dn(alpha, len(p)), rtol=1e-13)
+    np.testing.assert_allclose(q, -np.array(p), rtol=0, atol=0)
+
+
+def test_elem_launch_cap(shim):
+    # a 1-D grid of 256-thread workgroups holds at most (2^32 - 1) / 256
+    shim.shim_elem_launch_fits.argtypes = [ctypes.c_longlong]
+    cap = (2 ** 32 - 1) // 256
+    assert shim.shim_elem_launch_fits(cap) == 1
+    assert shim.shim_elem_launch_fits(cap + 1) == 0
+    assert shim.shim_elem_launch_fits(1 << 25) == 0
 
 
 def _emulate_partitioned_solve(T, C, lay, s, r):
