@@ -71,6 +71,13 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
   double *lv = (double *)(ws + pl->off_lv);
   double *ab = (double *)(ws + pl->off_ab);
   const int nc0 = (int)L.nc[0], nc1 = (int)L.nc[1];
+  // Chains of at most two chunks: each sweep forms its producer's carries
+  // itself from the boundary values (first half-steps write lv, second ones
+  // lv2), and only the last half-step's carries are launched (for the final
+  // pass).
+  const bool fused = L.ncmax <= 2;
+  double *lv2 = fused ? (double *)(ws + pl->off_lv2) : lv;
+  double sigma_prev = 0.0;
 
   fps::SweepArgs A{};
   A.npad = L.npad;
@@ -111,9 +118,17 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
     A.out = O0;
     A.out_f32 = f32;
     A.out_mode = 0;
+    if (fused && j > 0) {
+      A.ab_prev = nullptr;
+      A.lv_prev = lv2;
+      A.ctab_prev = pl->ctab_dev(pl->tab2(base + j - 1));
+      A.carry_scale = -sigma_prev;
+    }
+    A.lv = lv;
     FPS_HIP(timed_sweep(pl, A, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab1(base + j)), ab, -A.sigma, L.npad, nc0,
-                               nc1, L.ncmax, st));
+    if (!fused)
+      FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab1(base + j)), ab, -A.sigma, L.npad, nc0,
+                                 nc1, L.ncmax, st));
     fps::SweepArgs B = A;
     const bool last = j == J - 1;
     B.in = O0;
@@ -121,6 +136,13 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
     B.in_scale = 1.0;
     B.ab_prev = ab;
     B.tab_prev = A.tab;
+    if (fused) {
+      B.ab_prev = nullptr;
+      B.lv_prev = lv;
+      B.ctab_prev = pl->ctab_dev(pl->tab1(base + j));
+      B.carry_scale = -A.sigma;
+      B.lv = lv2;
+    }
     B.g = Gterm;
     B.g_f32 = g_f32;
     B.sg = 1.0;
@@ -131,8 +153,10 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
     B.out_f32 = f32;
     B.out_mode = last ? 1 : 0;
     FPS_HIP(timed_sweep(pl, B, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab2(base + j)), ab, last ? 1.0 : -B.sigma,
-                               L.npad, nc0, nc1, L.ncmax, st));
+    if (!fused || last)
+      FPS_HIP(fps::launch_reduce(B.lv, pl->ctab_dev(pl->tab2(base + j)), ab, last ? 1.0 : -B.sigma,
+                                 L.npad, nc0, nc1, L.ncmax, st));
+    sigma_prev = B.sigma;
   }
   return FPS_OK;
 }
@@ -473,6 +497,9 @@ fps_status plan2d_build(fps_plan *pl) {
   pl->off_ab = 4 * sq + lvb;
   const int64_t mobar = pl->mop[0] + pl->mop[1];
   pl->off_X = 4 * sq + lvb + abb;
+  // second boundary-value buffer for sweeps that form their own carries
+  // (chains of at most two chunks); after everything else
+  const bool fused = L.ncmax <= 2;
   pl->ws_bytes = pl->off_X + align256(mobar * mobar * 8);
   if (prec == FPS_FP32_REFINED) {
     pl->off_R = pl->ws_bytes;  // r and r^T, npad^2 floats each
@@ -483,6 +510,11 @@ fps_status plan2d_build(fps_plan *pl) {
     fps::build_lift_map(L, lift);
     pl->off_bc = pl->ws_bytes;
     pl->ws_bytes += align256((4 * L.npad + 8) * 8);
+  }
+  pl->off_lv2 = pl->off_lv;
+  if (fused) {
+    pl->off_lv2 = pl->ws_bytes;
+    pl->ws_bytes += lvb;
   }
 
   if (!(flags & FPS_PLAN_HOST_ONLY)) {

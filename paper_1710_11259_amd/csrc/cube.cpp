@@ -657,7 +657,9 @@ fps_status zeig_common(fps_plan *pl) {
   pl->off_O0 = 4 * vol;
   pl->off_O1 = 5 * vol;
   pl->off_lv = 6 * vol;
-  pl->off_ab = pl->off_lv + align256(L.ncmax * 4 * ch * 8);
+  pl->off_lv2 = pl->off_lv + align256(L.ncmax * 4 * ch * 8);
+  pl->zfused = L.ncmax <= 2;
+  pl->off_ab = pl->off_lv2 + (pl->zfused ? align256(L.ncmax * 4 * ch * 8) : 0);
   pl->ws_bytes = pl->off_ab + align256(2 * L.ncmax * ch * 2 * 8);
   const int64_t mq = pl->mqc[0] + pl->mqc[1];
   if (L.npad * L.npad * mq * 8 > 2 * vol || mq * mq * mq * 8 > 2 * vol ||
@@ -686,10 +688,13 @@ fps_status zeigr_upload(fps_plan *pl) {
   std::vector<fps::BatchReduce> rd((size_t)rows * 2 * Kc);
   std::vector<const double *> fin((size_t)pl->rounds * npad, nullptr);
   const double *pre_d = (const double *)pl->d_pre.p;
+  const bool fused = pl->zfused;
+  std::vector<fps::BatchReduce> rdfin((size_t)pl->rounds * Kc);
   for (int k = 0; k < K; ++k) {
     const int64_t c = pl->zrslice[k];
     const int64_t so = c * ch * 4;  // the float arrays hold slices at a stride of npad^2 floats
     const int64_t lvo = pl->off_lv + c * lvb * 8, abo = pl->off_ab + c * abb * 8;
+    const int64_t lvo2 = fused ? pl->off_lv2 + c * lvb * 8 : lvo;
     fps::SweepArgs A{};
     A.npad = npad;
     A.ncols = npad;
@@ -734,6 +739,23 @@ fps_status zeigr_upload(fps_plan *pl) {
         a2.sigma = last ? 0.0 : pj + pn;
         a2.out = (void *)(intptr_t)(pl->off_O1 + so);
         a2.out_mode = last ? 1 : 0;
+        if (fused) {  // carries from the producer's boundary values, no carry launch
+          a2.lv = (double *)(intptr_t)lvo2;
+          if (j > 0) {
+            a1.ab_prev = nullptr;
+            a1.lv_prev = (const double *)(intptr_t)lvo2;
+            a1.ctab_prev = pl->ctab_dev(t - 1);
+            a1.carry_scale = -(pl->zp[(size_t)t - 1] + pj);  // the previous second half-step
+          }
+          a2.ab_prev = nullptr;
+          a2.lv_prev = (const double *)(intptr_t)lvo;
+          a2.ctab_prev = pl->ctab_dev(t);
+          a2.carry_scale = -a1.sigma;
+          if (last)
+            rdfin[(size_t)r * Kc + k] =
+                fps::BatchReduce{lvo2, abo, pl->ctab_dev(t), 1.0, npad, L.ncmax, (int)L.nc[0],
+                                 (int)L.nc[1], k * nrd, nbx_r};
+        }
         const size_t row = (size_t)pl->zrrow0[(size_t)r] + (size_t)j;
         const size_t i1 = (row * 2 + 0) * Kc + k, i2 = (row * 2 + 1) * Kc + k;
         sw[i1] = fps::BatchSweep{a1, k * nsw, nbx_s};
@@ -755,7 +777,8 @@ fps_status zeigr_upload(fps_plan *pl) {
   pl->zrd_start.assign(1, nrd);
   if ((s = upload(pl->d_zrsw, sw)) != FPS_OK || (s = upload(pl->d_zrrd, rd)) != FPS_OK ||
       (s = upload(pl->d_zswmap, swmap)) != FPS_OK || (s = upload(pl->d_zrdmap, rdmap)) != FPS_OK ||
-      (s = upload(pl->d_zrfin, fin)) != FPS_OK || (s = upload(pl->d_zmu, pl->zrmu_slice)) != FPS_OK)
+      (s = upload(pl->d_zrfin, fin)) != FPS_OK || (s = upload(pl->d_zmu, pl->zrmu_slice)) != FPS_OK ||
+      (fused && (s = upload(pl->d_zrdfin, rdfin)) != FPS_OK))
     return s;
   return FPS_OK;
 }
@@ -851,10 +874,14 @@ fps_status zeig_upload(fps_plan *pl) {
   std::vector<fps::BatchSweep> sw((size_t)J * 2 * (K > 0 ? K : 1));
   std::vector<fps::BatchReduce> rd((size_t)J * 2 * (K > 0 ? K : 1));
   const double *pre_d = (const double *)pl->d_pre.p;
+  const bool fused = pl->zfused;
+  std::vector<fps::BatchReduce> rdfin((size_t)(K > 0 ? K : 1));
   for (int k = 0; k < K; ++k) {
     const int64_t c = pl->zslice[k];
     const int64_t so = c * ch * 8;  // slice byte offset in an npad^3 array
     const int64_t lvo = pl->off_lv + c * lvb * 8, abo = pl->off_ab + c * abb * 8;
+    const int64_t lvo2 = fused ? pl->off_lv2 + c * lvb * 8 : lvo;
+    double sigma2_prev = 0.0;  // the second half-step's sigma of the previous step
     fps::SweepArgs A{};
     A.npad = npad;
     A.ncols = npad;
@@ -900,6 +927,23 @@ fps_status zeig_upload(fps_plan *pl) {
       a2.sigma = last ? 0.0 : qj - pn;
       a2.out = (void *)(intptr_t)(pl->off_O1 + so);
       a2.out_mode = last ? 1 : 0;
+      if (fused) {  // carries from the producer's boundary values, no carry launch
+        a2.lv = (double *)(intptr_t)lvo2;
+        if (j > 0) {
+          a1.ab_prev = nullptr;
+          a1.lv_prev = (const double *)(intptr_t)lvo2;
+          a1.ctab_prev = pl->ctab_dev(t1 - 1);
+          a1.carry_scale = -sigma2_prev;
+        }
+        a2.ab_prev = nullptr;
+        a2.lv_prev = (const double *)(intptr_t)lvo;
+        a2.ctab_prev = pl->ctab_dev(t1);
+        a2.carry_scale = -a1.sigma;
+        sigma2_prev = a2.sigma;
+        if (last)
+          rdfin[(size_t)k] = fps::BatchReduce{lvo2, abo, pl->ctab_dev(t2), 1.0, npad, L.ncmax,
+                                              (int)L.nc[0], (int)L.nc[1], k * nrd, nbx_r};
+      }
       const size_t i1 = ((size_t)j * 2 + 0) * K + k, i2 = ((size_t)j * 2 + 1) * K + k;
       sw[i1] = fps::BatchSweep{a1, k * nsw, nbx_s};
       sw[i2] = fps::BatchSweep{a2, k * nsw, nbx_s};
@@ -924,7 +968,8 @@ fps_status zeig_upload(fps_plan *pl) {
   pl->zrd_start.assign(1, nrd);
   if ((s = upload(pl->d_zsw, sw)) != FPS_OK || (s = upload(pl->d_zrd, rd)) != FPS_OK ||
       (s = upload(pl->d_zswmap, swmap)) != FPS_OK || (s = upload(pl->d_zrdmap, rdmap)) != FPS_OK ||
-      (s = upload(pl->d_zfin, fin)) != FPS_OK)
+      (s = upload(pl->d_zfin, fin)) != FPS_OK ||
+      (fused && (s = upload(pl->d_zrdfin, rdfin)) != FPS_OK))
     return s;
   if (pl->zsplit > 0) {  // default-priority side stream and its fork / join events
     if (hipStreamCreateWithFlags(&pl->zside, hipStreamNonBlocking) != hipSuccess ||
@@ -956,6 +1001,7 @@ fps_status zeigr_adi(fps_plan *pl, char *w, hipStream_t st) {
   float *q = (float *)(w + pl->off_O0), *x1 = (float *)(w + pl->off_O1);
   float *HT = (float *)(w + pl->off_RXT), *H = (float *)(w + pl->off_RX);
   double *lv = (double *)(w + pl->off_lv), *ab = (double *)(w + pl->off_ab);
+  double *lv2 = (double *)(w + pl->off_lv2);
   const double *dv = (const double *)pl->d_pre.p, *ev = dv + npad;
   const int64_t lvb = L.ncmax * 4 * npad, abb = 2 * L.ncmax * npad * 2;
   const int K = (int)pl->zrslice.size();
@@ -1008,15 +1054,22 @@ fps_status zeigr_adi(fps_plan *pl, char *w, hipStream_t st) {
     S.out_f32 = 1;
     S.out_mode = 3;
     FPS_HIP(fps::launch_sweep(S, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(0), ab, 1.0, npad, S.nc0, S.nc1, L.ncmax, st,
-                               (int)npad, lvb, abb));
     S.in = x1;
-    S.ab_prev = ab;
     S.tab_prev = pl->tab_dev(0);
+    if (pl->zfused) {  // the second solve forms the first one's carries itself
+      S.lv_prev = lv;
+      S.ctab_prev = pl->ctab_dev(0);
+      S.carry_scale = 1.0;
+      S.lv = lv2;
+    } else {
+      FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(0), ab, 1.0, npad, S.nc0, S.nc1, L.ncmax, st,
+                                 (int)npad, lvb, abb));
+      S.ab_prev = ab;
+    }
     S.out = q;
     S.out_mode = 1;
     FPS_HIP(fps::launch_sweep(S, st));
-    FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(0), ab, 1.0, npad, S.nc0, S.nc1, L.ncmax, st,
+    FPS_HIP(fps::launch_reduce(S.lv, pl->ctab_dev(0), ab, 1.0, npad, S.nc0, S.nc1, L.ncmax, st,
                                (int)npad, lvb, abb));
     FPS_HIP(fps::launch_slice_xfinal(q, ab, pl->tab_dev(0), HT, H, npad, mp0, L.mstride, L.ncmax,
                                      npad, st));
@@ -1026,10 +1079,13 @@ fps_status zeigr_adi(fps_plan *pl, char *w, hipStream_t st) {
       const size_t row = (size_t)pl->zrrow0[(size_t)r] + (size_t)j;
       const size_t o1 = (row * 2 + 0) * Kc, o2 = (row * 2 + 1) * Kc;
       FPS_HIP(sweep(t1, false, dsw + o1, k1 * nsw));
-      FPS_HIP(fps::launch_reduce_batch(drd + o1, rdmap, k1 * nrd, L.ncmax, w, st));
+      if (!pl->zfused) FPS_HIP(fps::launch_reduce_batch(drd + o1, rdmap, k1 * nrd, L.ncmax, w, st));
       FPS_HIP(sweep(t2, true, dsw + o2, k1 * nsw));
-      FPS_HIP(fps::launch_reduce_batch(drd + o2, rdmap, k1 * nrd, L.ncmax, w, st));
+      if (!pl->zfused) FPS_HIP(fps::launch_reduce_batch(drd + o2, rdmap, k1 * nrd, L.ncmax, w, st));
     }
+    if (pl->zfused)  // the carries of every slice's last half-step of the round
+      FPS_HIP(fps::launch_reduce_batch((const fps::BatchReduce *)pl->d_zrdfin.p + (size_t)r * Kc,
+                                       rdmap, K * nrd, L.ncmax, w, st));
     FPS_HIP(fps::launch_slice_final<float>(x1, ab, fin + (size_t)r * npad, Yh, 1.0, r > 0 ? 1 : 0,
                                            npad, mp0, L.mstride, L.ncmax, st));
   }
@@ -1091,13 +1147,13 @@ fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
         if (k1 <= lo) break;
         const size_t o1 = ((size_t)j * 2 + 0) * K, o2 = ((size_t)j * 2 + 1) * K;
         e = sweep(plain, false, dsw + o1, (k1 - lo) * nsw, lo * nsw, s2);
-        if (e == hipSuccess)
+        if (e == hipSuccess && !pl->zfused)
           e = fps::launch_reduce_batch(drd + o1, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
         if (e == hipSuccess && k2 > lo)  // slices with a later step: stencil P before the y solve
           e = sweep(stencil, true, dsw + o2, (k2 - lo) * nsw, lo * nsw, s2);
         if (e == hipSuccess && k1 > k2)  // slices at their last step: no stencil
           e = sweep(plain, true, dsw + o2, (k1 - k2) * nsw, k2 * nsw, s2);
-        if (e == hipSuccess)
+        if (e == hipSuccess && !pl->zfused)
           e = fps::launch_reduce_batch(drd + o2, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
       }
       return e;
@@ -1124,6 +1180,9 @@ fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
     } else {
       FPS_HIP(run_group(0, K, st));
     }
+    if (pl->zfused)  // the carries of every slice's last half-step, in one launch
+      FPS_HIP(fps::launch_reduce_batch((const fps::BatchReduce *)pl->d_zrdfin.p, rdmap, K * nrd,
+                                       L.ncmax, w, st));
     FPS_HIP(fps::launch_slice_final<double>(O1, (const double *)(w + pl->off_ab),
                                             (const double *const *)pl->d_zfin.p, Yh, -1.0, 0, npad,
                                             mp0, L.mstride, L.ncmax, st));

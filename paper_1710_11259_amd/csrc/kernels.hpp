@@ -35,6 +35,14 @@ struct SweepArgs {
   double in_scale;
   const double *ab_prev;   // producer's chunk carries [2][ncmax][npad][2] (producer chains = npad), or null
   const double *tab_prev;  // producer's per-position tables (its shift) [2][kNTab][mstride]
+  // Carries formed in the sweep itself (ctab_prev non-null; chains of at
+  // most two chunks per parity, ncmax <= 2): from the producer's chunk
+  // boundary values lv_prev (its lv, [ncmax][2][2][npad]) and chunk tables
+  // ctab_prev ([2][kNCTab][ncmax]), times carry_scale (the scale launch_reduce
+  // would apply); ab_prev is then unused.
+  const double *lv_prev;
+  const double *ctab_prev;
+  double carry_scale;
   const void *g;           // G term, same layout as `in`, or nullptr
   double sg, og;
   const double *tab;       // this pass's tables [2][kNTab][mstride]

@@ -104,6 +104,9 @@ struct fps_plan {
 
   // workspace layout (byte offsets)
   int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab = 0;
+  // second chunk-boundary-value buffer (z-eigenbasis cube plans whose sweeps
+  // form their carries themselves: first half-steps write lv, second ones lv2)
+  int64_t off_lv2 = 0;
   int64_t off_X = 0;  // adjoint: the output cotangent in the parity-blocked layout
   int64_t off_R = 0;  // FP32_REFINED: the float residual and its transpose
   // Dirichlet lift (2-D plans with FPS_PLAN_DIRICHLET): the traces' scaled
@@ -132,6 +135,11 @@ struct fps_plan {
   // ztab0[k] + 2 j + 1 (y solve).
   bool zeig = false;
   std::vector<int> zslice, zJ, ztab0, zactive, zsw_start, zrd_start;
+  // Sweeps form their own chunk carries (chains of at most two chunks,
+  // ncmax <= 2): no carry launch between half-steps, one per solve (FP64) or
+  // per round (refined) before the final pass, from the descriptors d_zrdfin.
+  bool zfused = false;
+  fps::detail::DeviceBuf d_zrdfin;
   std::vector<double> zmu;
   std::vector<double> zp, zq;  // shifts of step j of sorted slice k at index ztab0[k] / 2 + j
   int zJmax = 0;

@@ -122,6 +122,23 @@ __device__ __forceinline__ Cols cols_of(const SweepArgs &a, int bx, int lane) {
   return q;
 }
 
+// Component k (0: forward, 1: backward) of the producer's chunk carry of its
+// chain r at chunk cp of parity sp, formed from its chunk boundary values
+// for chains of at most two chunks: with one chunk there is no carry; with
+// two, cf[1] = ylast[0] and cb[0] = xfirst[1] + BF2first[1] ylast[0] (the
+// chunk-level recurrences of launch_reduce, cf[0] = cb[1] = 0).
+__device__ __forceinline__ double fused_carry(const SweepArgs &a, int sp, int64_t cp, int64_t r,
+                                              int k) {
+  const int ncs = sp ? a.nc1 : a.nc0;
+  if (ncs < 2 || (cp == 0) == (k == 0)) return 0.0;
+  const int64_t nch = a.npad;
+  const double y0 = a.lv_prev[((int64_t)(0 * 2 + sp) * 2 + 0) * nch + r];
+  if (k == 0) return a.carry_scale * y0;
+  const double x1 = a.lv_prev[((int64_t)(1 * 2 + sp) * 2 + 1) * nch + r];
+  const double bf = a.ctab_prev[((int64_t)sp * kNCTab + C_BF2FIRST) * a.ncmax + 1];
+  return a.carry_scale * (x1 + bf * y0);
+}
+
 // Per-unit small values, loaded before the unit's streaming loads without
 // divergent branches (addresses are clamped), so that waiting for them does
 // not wait for the streaming loads.
@@ -145,7 +162,10 @@ __device__ __forceinline__ void load_small(const SweepArgs &a, const Unit &u, co
   const bool has_prev = a.tab_prev != nullptr;
   if (has_prev) {
     const int e2 = tid < 2 * kChunk ? tid : 2 * kChunk - 1;
-    m.abv = a.ab_prev[(((int64_t)q.sp * ncmax + q.cp) * npad + u.rbase) * 2 + e2];
+    if (a.ctab_prev != nullptr)
+      m.abv = fused_carry(a, q.sp, q.cp, u.rbase + (e2 >> 1), e2 & 1);
+    else
+      m.abv = a.ab_prev[(((int64_t)q.sp * ncmax + q.cp) * npad + u.rbase) * 2 + e2];
   }
   m.prv = m.prev_r = m.next_r = m.pe_before = 0.0;
   if constexpr (kPre) {
@@ -160,7 +180,10 @@ __device__ __forceinline__ void load_small(const SweepArgs &a, const Unit &u, co
     if ((w == 0 && has_before) || (w == kWaves - 1 && has_after)) {
       const int64_t r = w == 0 ? u.rbase - 1 : u.rbase + kChunk;
       double e0 = 0.0, e1 = 0.0;
-      if (has_prev) {
+      if (has_prev && a.ctab_prev != nullptr) {
+        e0 = fused_carry(a, q.sp, q.cp, r, 0);
+        e1 = fused_carry(a, q.sp, q.cp, r, 1);
+      } else if (has_prev) {
         const double *ep = a.ab_prev + (((int64_t)q.sp * ncmax + q.cp) * npad + r) * 2;
         e0 = ep[0];
         e1 = ep[1];
@@ -379,7 +402,8 @@ __global__ __launch_bounds__(kCols *kWaves, (kPre && kG == 2) ? 4 : 6) void k_sw
     if (kG != 0) a.g = (const Tg *)a.g + z * a.bstride;
     a.out = (Tout *)a.out + z * a.bstride;
     a.lv += z * a.lvb;
-    if (a.tab_prev != nullptr) a.ab_prev += z * a.abb;
+    if (a.tab_prev != nullptr && a.ctab_prev == nullptr) a.ab_prev += z * a.abb;
+    if (a.ctab_prev != nullptr) a.lv_prev += z * a.lvb;
   }
   sweep_block<Tin, Tg, Tout, kG, kPre>(a, blockIdx.x, blockIdx.y, lds);
 }
@@ -399,7 +423,10 @@ __global__ __launch_bounds__(kCols *kWaves, 6) void k_sweep_batch(const BatchSwe
   if (kG != 0) a.g = base + (intptr_t)a.g;
   a.out = base + (intptr_t)a.out;
   a.lv = (double *)(base + (intptr_t)a.lv);
-  if (a.tab_prev != nullptr) a.ab_prev = (const double *)(base + (intptr_t)a.ab_prev);
+  if (a.ctab_prev != nullptr)
+    a.lv_prev = (const double *)(base + (intptr_t)a.lv_prev);
+  else if (a.tab_prev != nullptr)
+    a.ab_prev = (const double *)(base + (intptr_t)a.ab_prev);
   const int local = g - e.wg_start;
   sweep_block<Tin, Tg, Tout, kG, kPre>(a, local % e.nbx, local / e.nbx, lds);
 }
@@ -490,7 +517,11 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st, hipEvent_t ev0, hipE
   const int nchunks = a.nc0 + a.nc1;
   if (a.npad % kCols != 0 || a.ncols % kCols != 0 || nchunks <= 0 || a.in == nullptr)
     return hipErrorInvalidValue;
-  if ((a.ab_prev == nullptr) != (a.tab_prev == nullptr)) return hipErrorInvalidValue;
+  if (a.ctab_prev != nullptr) {  // carries formed in the sweep: at most two chunks per chain
+    if (a.tab_prev == nullptr || a.lv_prev == nullptr || a.ncmax > 2) return hipErrorInvalidValue;
+  } else if ((a.ab_prev == nullptr) != (a.tab_prev == nullptr)) {
+    return hipErrorInvalidValue;
+  }
   if ((a.out_mode == 0 || a.out_mode == 3) && (a.ncols != a.npad || a.ld != a.npad))
     return hipErrorInvalidValue;
   if (a.out_mode < 0 || a.out_mode > 3) return hipErrorInvalidValue;
