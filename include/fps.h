@@ -321,6 +321,17 @@ fps_status fps_plan_sweep_time(fps_plan *plan, double *ms_host, int64_t cap, int
 int64_t fps_noalloc_capacity(void);
 fps_status fps_solve_noalloc(fps_plan *plan, const double *F_dev, double *U_dev, void *stream);
 
+/*
+ * Measurement aid, not part of the solver: c[i] = a[i] + b[i] for i < n, a
+ * pure streaming pass (two reads and one write of 8 bytes per element, in
+ * 16-byte accesses) whose rate on arrays far larger than the last-level
+ * cache is the HBM rate a kernel of the sweeps' access pattern can reach.
+ * a, b, c: device arrays of n doubles, 16-byte aligned, c not overlapping a
+ * or b; n >= 0 (n = 0 does nothing).  Enqueued on `stream`; FPS_E_ARG for a
+ * null or misaligned array or n < 0.
+ */
+fps_status fps_probe_stream(const double *a, const double *b, double *c, int64_t n, void *stream);
+
 void fps_plan_destroy(fps_plan *plan);
 
 /*

@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
         getattr(L, name).argtypes = [vp, vp, vp, vp, vp]
     L.fps_solve_noalloc.argtypes = [vp, vp, vp, vp]
     L.fps_noalloc_capacity.argtypes = []
+    L.fps_probe_stream.argtypes = [vp, vp, vp, i64, vp]
     L.fps_noalloc_capacity.restype = i64
     L.fps_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(i64), dbl, ctypes.c_int, ctypes.c_int,
@@ -300,6 +301,20 @@ def solve_noalloc(p: Plan, F, out=None):
     _check(lib().fps_solve_noalloc(p.handle, ctypes.c_void_p(F.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(torch, F.device)))
     return out
+
+
+def probe_stream(a, b, c):
+    """c = a + b over float64 device tensors of one length (the streaming
+    pass that measures the achievable HBM rate), on the current stream."""
+    import torch
+    for t in (a, b, c):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise FpsError("probe_stream takes contiguous float64 device tensors")
+    if not (a.numel() == b.numel() == c.numel()):
+        raise FpsError("probe_stream: tensors of different lengths")
+    _check(lib().fps_probe_stream(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                  ctypes.c_void_p(c.data_ptr()), a.numel(),
+                                  _stream_ptr(torch, a.device)))
 
 
 def noalloc_capacity() -> int:
