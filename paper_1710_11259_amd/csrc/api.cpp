@@ -38,10 +38,11 @@ void spectrum_tight(int64_t n, double *a, double *b) {
 
 int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
-hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st) {
+hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st, bool rows) {
+  const auto launch = rows ? fps::launch_sweep_rows : fps::launch_sweep;
   const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
-  if (!t) return fps::launch_sweep(a, st);
-  const hipError_t e = fps::launch_sweep(a, st, pl->ev[2 * pl->ev_used], pl->ev[2 * pl->ev_used + 1]);
+  if (!t) return launch(a, st, nullptr, nullptr);
+  const hipError_t e = launch(a, st, pl->ev[2 * pl->ev_used], pl->ev[2 * pl->ev_used + 1]);
   if (e == hipSuccess) ++pl->ev_used;
   return e;
 }
@@ -54,17 +55,15 @@ void release_events(fps_plan *pl) {
 
 // Runs the 2J half-sweeps of Algorithm 2 with the shifts `sh`, whose step j
 // uses the plan's tables of step base + j.  `Gterm` is the right-hand side G
-// (parity-blocked, npad x npad) and `GTin` its transpose, both of storage
-// type g_f32; O0, O1 are the ping-pong arrays (room for npad^2 doubles
-// each).  With f32 set every step stores its outputs in float (refinement
+// (parity-blocked, npad x npad) of storage type g_f32; O0, O1 are the
+// ping-pong arrays (room for npad^2 doubles each), in G's layout.  With f32 set every step stores its outputs in float (refinement
 // rounds, including the final chunk-local solution: a later round corrects
 // its rounding, and the last round's correction is small), else in double.
 // Leaves the final chunk-local solution in O1 and its chunk carries in ab,
 // to finalize with the tables of the last second half-step
 // (pl->tab2(base + J - 1)).
-fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *Gterm,
-                   const void *GTin, int g_f32, int f32, void *O0, void *O1, char *ws,
-                   hipStream_t st) {
+fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *Gterm, int g_f32,
+                   int f32, void *O0, void *O1, char *ws, hipStream_t st) {
   const fps::Layout &L = pl->L;
   const int J = sh.J;
   const std::vector<double> &p = sh.p, &q = sh.q;
@@ -91,6 +90,10 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
   A.nc0 = nc0;
   A.nc1 = nc1;
   A.lv = lv;
+  // Every array keeps one layout (that of G): half-step 1 solves along its
+  // storage rows (launch_sweep_rows), half-step 2 along its storage columns
+  // (launch_sweep), and both store their outputs in place of their inputs'
+  // layout.
   // Algorithm 2 for A Y - Y B = G with T1_j = -(B - p_j) (first half-step,
   // along the columns of Y) and T2_j = A - q_j (second half-step, along the
   // rows).  Half-step 1: right-hand side R_j = (A - p_j) Y_j - G, solve
@@ -104,7 +107,7 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
   // into `ab`, which the next half-step folds in.
   for (int j = 0; j < J; ++j) {
     const double s1 = pl->rect ? p[j] - q[j] : 2.0 * p[j];
-    A.in = j == 0 ? GTin : (const void *)O1;
+    A.in = j == 0 ? Gterm : (const void *)O1;
     A.in_f32 = j == 0 ? g_f32 : f32;
     A.in_scale = j == 0 ? -1.0 : 1.0;
     A.ab_prev = j == 0 ? nullptr : ab;
@@ -117,7 +120,7 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
     A.sigma = s1;
     A.out = O0;
     A.out_f32 = f32;
-    A.out_mode = 0;
+    A.out_mode = 2;
     if (fused && j > 0) {
       A.ab_prev = nullptr;
       A.lv_prev = lv2;
@@ -125,7 +128,7 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
       A.carry_scale = -sigma_prev;
     }
     A.lv = lv;
-    FPS_HIP(timed_sweep(pl, A, st));
+    FPS_HIP(timed_sweep(pl, A, st, true));
     if (!fused)
       FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab1(base + j)), ab, -A.sigma, L.npad, nc0,
                                  nc1, L.ncmax, st));
@@ -151,7 +154,7 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
     B.sigma = last ? 0.0 : (pl->rect ? p[j + 1] - q[j] : p[j] + p[j + 1]);
     B.out = O1;
     B.out_f32 = f32;
-    B.out_mode = last ? 1 : 0;
+    B.out_mode = last ? 1 : 2;
     FPS_HIP(timed_sweep(pl, B, st));
     if (!fused || last)
       FPS_HIP(fps::launch_reduce(B.lv, pl->ctab_dev(pl->tab2(base + j)), ab, last ? 1.0 : -B.sigma,
@@ -162,7 +165,7 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
 }
 
 // The symmetric-form solution Y (parity-blocked FP64, npad x npad) of
-// A~ Y + Y A~ = G for G in ws.G (and G^T in ws.GT): plain FP64 ADI, or
+// A~ Y + Y A~ = G for G in ws.G: plain FP64 ADI, or
 // iterative refinement whose inner ADIs store their sweep arrays in float.
 // Returns Y's location.
 fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout) {
@@ -172,9 +175,7 @@ fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout)
   fps_status s;
   if (pl->prec == FPS_FP64) {
     const int J = pl->shifts.J;
-    double *GT = (double *)(w + pl->off_GT);
-    if ((s = run_adi(pl, pl->shifts, 0, G, GT, 0, 0, w + pl->off_O0, w + pl->off_O1, w, st)) !=
-        FPS_OK)
+    if ((s = run_adi(pl, pl->shifts, 0, G, 0, 0, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK)
       return s;
     FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, pl->tab_dev(pl->tab2(J - 1)),
                                          G, 0, nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax,
@@ -186,16 +187,16 @@ fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout)
   // residual is formed in FP64 and stored in float (with its transpose),
   // and the inner sweeps of a float round store their arrays in float.
   double *Y = (double *)(w + pl->off_GT);
-  float *r = (float *)(w + pl->off_R), *rT = r + L.npad * L.npad;
+  float *r = (float *)(w + pl->off_R);
   for (int k = 0; k < pl->rounds; ++k) {
     const fps::ShiftSet &sh = pl->rsh[(size_t)k];
     const int f32 = pl->rf32[(size_t)k];
     const double *tab = pl->tab_dev(pl->tab2(pl->rbase[(size_t)k] + sh.J - 1));
     FPS_HIP(fps::launch_residual(G, k == 0 ? nullptr : Y, (const double *)pl->d_sdiag.p,
-                                 (const double *)pl->d_soff.p, r, rT, L.npad, st, pl->sx2,
+                                 (const double *)pl->d_soff.p, r, nullptr, L.npad, st, pl->sx2,
                                  pl->sy2));
-    if ((s = run_adi(pl, sh, pl->rbase[(size_t)k], r, rT, 1, f32, w + pl->off_O0,
-                     w + pl->off_O1, w, st)) != FPS_OK)
+    if ((s = run_adi(pl, sh, pl->rbase[(size_t)k], r, 1, f32, w + pl->off_O0, w + pl->off_O1, w,
+                     st)) != FPS_OK)
       return s;
     const int mode = k == 0 ? 0 : 2;
     if (f32)
@@ -217,7 +218,7 @@ fps_status check_solve_args(fps_plan *pl, const void *a, const void *b, void *ws
   return FPS_OK;
 }
 
-// Input map: G_perm = Rs_s F_st Rs_t^T for the four parity blocks, then GT.
+// Input map: G_perm = Rs_s F_st Rs_t^T for the four parity blocks.
 int rhs_gemms(const fps_plan *pl, char *ws, fps::GemmProb *g1, fps::GemmProb *g2) {
   const fps::Layout &L = pl->L;
   const int64_t npad = L.npad;
@@ -272,8 +273,6 @@ fps_status rhs_transform(fps_plan *pl, const double *F, char *ws, hipStream_t st
                                     (const double *)pl->d_lift[1].p, (double *)(ws + pl->off_G),
                                     (double *)(ws + pl->off_bc), L, pl->sx2, pl->sy2,
                                     bc_lift_const(), st));
-  FPS_HIP(fps::launch_transpose((const double *)(ws + pl->off_G), (double *)(ws + pl->off_GT),
-                                L.npad, st));
   return FPS_OK;
 }
 
@@ -502,7 +501,7 @@ fps_status plan2d_build(fps_plan *pl) {
   const bool fused = L.ncmax <= 2;
   pl->ws_bytes = pl->off_X + align256(mobar * mobar * 8);
   if (prec == FPS_FP32_REFINED) {
-    pl->off_R = pl->ws_bytes;  // r and r^T, npad^2 floats each
+    pl->off_R = pl->ws_bytes;  // r and r^T (batched solves), npad^2 floats each
     pl->ws_bytes += sq;
   }
   std::vector<double> lift[2];
@@ -771,11 +770,8 @@ fps_status fps_adi_native(fps_plan *pl, const double *G, double *Y, void *ws, vo
   char *w = (char *)ws;
   const fps::Layout &L = pl->L;
   double *Gp = (double *)(w + pl->off_G);
-  double *GT = (double *)(w + pl->off_GT);
   FPS_HIP(fps::launch_permute_in(G, Gp, L.n, L.npad, L.mp[0], st));
-  FPS_HIP(fps::launch_transpose(Gp, GT, L.npad, st));
-  if ((s = run_adi(pl, pl->shifts, 0, Gp, GT, 0, 0, w + pl->off_O0, w + pl->off_O1, w, st)) !=
-      FPS_OK)
+  if ((s = run_adi(pl, pl->shifts, 0, Gp, 0, 0, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK)
     return s;
   const int J = pl->shifts.J;
   FPS_HIP(fps::launch_finalize<double>((double *)(w + pl->off_O1), (double *)(w + pl->off_ab),
@@ -868,7 +864,7 @@ fps_status adjoint_in_pre(const fps_plan *pl, const double *Ubar, char *w, hipSt
   return FPS_OK;
 }
 
-// adjoint_in: Ybar into G (and its transpose into GT) from Ubar.
+// adjoint_in: Ybar into G from Ubar.
 fps_status adjoint_in(const fps_plan *pl, const double *Ubar, char *w, hipStream_t st) {
   fps_status s;
   if ((s = adjoint_in_pre(pl, Ubar, w, st)) != FPS_OK) return s;
@@ -878,8 +874,6 @@ fps_status adjoint_in(const fps_plan *pl, const double *Ubar, char *w, hipStream
     FPS_HIP(fps::launch_gemm(g1, cnt, st));
     FPS_HIP(fps::launch_gemm(g2, cnt, st));
   }
-  FPS_HIP(fps::launch_transpose((const double *)(w + pl->off_G), (double *)(w + pl->off_GT),
-                                pl->L.npad, st));
   return FPS_OK;
 }
 

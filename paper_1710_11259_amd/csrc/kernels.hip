@@ -74,6 +74,7 @@ __device__ __forceinline__ void residual_tile(const double *__restrict__ G,
     r[i * npad + q] = (float)res;
     tile[rr][tx] = (float)res;
   }
+  if (rT == nullptr) return;  // uniform: no transposed copy wanted
   __syncthreads();
   for (int rr = ty; rr < 64; rr += 4) rT[(c0 + rr) * npad + r0 + tx] = tile[tx][rr];
 }

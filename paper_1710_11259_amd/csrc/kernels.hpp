@@ -72,6 +72,16 @@ struct SweepArgs {
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 
+// Row-chain half-sweep (sweep_rows.hip): the same pass along the storage
+// rows of `in` (chains = rows, positions = columns, ncols = npad chains),
+// stored in the same layout (out_mode 1: x, 2: v - sigma x); no g term or
+// stencil, single arrays; in/out storage d/d, f/d or f/f.  The producer's
+// carries fold in as in launch_sweep with the producer's chains along the
+// columns; its chunk boundary values go to lv ([ncmax][2][2][npad], chains
+// = rows).
+hipError_t launch_sweep_rows(const SweepArgs &a, hipStream_t st, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
+
 // Batched sweeps over several independent problems in one launch.  The
 // workspace pointers of each descriptor's SweepArgs (in, g, out, lv,
 // ab_prev) hold byte offsets from `base`; tab, tab_prev, l1 and pre are
@@ -137,8 +147,8 @@ hipError_t launch_finalize(const T *x, const double *ab, const double *tab, doub
                            int64_t mstride, int64_t ncmax, hipStream_t st);
 
 // Residual of the symmetric Sylvester equation in the parity-blocked layout,
-// r = G - (A~ Y + Y A~) (Y null: r = G), in FP64, stored in float as r and
-// r^T.  A~ acts along each parity block as a tridiagonal stencil with
+// r = G - (A~ Y + Y A~) (Y null: r = G), in FP64, stored in float as r and,
+// with rT non-null, r^T.  A~ acts along each parity block as a tridiagonal stencil with
 // diagonal dv[] and coupling ev[] (ev[k] couples positions k and k+1).
 // For a rectangle the operator is ax A~ Y + ay Y A~ (ax = sx2, ay = sy2).
 hipError_t launch_residual(const double *G, const double *Y, const double *dv, const double *ev,

@@ -240,7 +240,7 @@ fps_status adjoint_out(const fps_plan *pl, const double *Gbar, double *Fbar, cha
 fps_status cube_plan_build(fps_plan *pl);
 fps_status cube_plan_upload(fps_plan *pl);
 fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *ws, hipStream_t st);
-hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st);
+hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st, bool rows = false);
 // Cylinder (Sec. 4.1): host tables and workspace layout, their upload, the
 // solve, and the band of one mode's r-operators (inspection).
 fps_status cyl_plan_build(fps_plan *pl, int64_t nt);
