@@ -19,11 +19,33 @@ sys.path.insert(0, ROOT)
 METRIC = "dof/s, square Poisson n=4096 at rel err ≤1e-12; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6  # dense FP64 matrix peak of MI355X
-# Calibrated HBM traffic of the sweep kernel per launch at n = 4096 (rocprofv3
-# FETCH_SIZE x2.000 + WRITE_SIZE x1.000, see profiles/sweep_square_n4096.md),
-# valid only for the sweep source with this sha256.
-SWEEP_TRAFFIC = {"sha256": "b1bff1e4d1acd93bd6e6fc03628d9fc64d820a735a8b6b8015a46395c87bc3f3",
-                 "n": 4096, "half_step_1": 278.8e6, "half_step_2": 413.0e6}
+# Calibrated HBM traffic of the sweep kernels per launch (rocprofv3
+# FETCH_SIZE x1.9999 + WRITE_SIZE x1.0000, see profiles/sweep_square_n4096.md
+# and profiles/sweep_square_n10000.md), valid only for the sweep sources
+# (sweep.hip, then sweep_rows.hip) with this combined sha256.
+SWEEP_SOURCES = ("sweep.hip", "sweep_rows.hip")
+SWEEP_TRAFFIC = {"sha256": "74ed83037d6cdcc8ef671fca5511f9e29862df0ea41324aeec8dfe5819d5d0ff",
+                 4096: {"half_step_1": 278.2e6, "half_step_2": 413.0e6},
+                 10000: {"half_step_1": 1748.1e6, "half_step_2": 2529.8e6}}
+
+
+def sweep_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1710_11259_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def sweep_traffic(n):
+    """Counter-measured HBM bytes per sweep launch at size n, mean of the two
+    half-steps, or None when the sources changed since the counters were
+    taken (or no counters exist for n)."""
+    if sweep_sources_sha() != SWEEP_TRAFFIC["sha256"] or n not in SWEEP_TRAFFIC:
+        return None
+    t = SWEEP_TRAFFIC[n]
+    return (t["half_step_1"] + t["half_step_2"]) / 2.0
 
 
 def copy_rate(torch, dev, mib=1024, reps=5):
@@ -526,6 +548,7 @@ def bench_square_large(fps, workloads, torch, tol, n=10000, steps=3, check=True,
                                        "half_step_2": round(t2 * 1e6, 2)},
                      "achieved_GBs": round((b1 + b2) / (t1 + t2) / 1e9, 1),
                      "frac": round((b1 + b2) / (t1 + t2) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": sweep_traffic(n),
                      "launches_timed": len(t)}}
     if check:
         from oracle import square
@@ -704,18 +727,14 @@ def main() -> int:
     t2 = sum(hs2) / max(len(hs2), 1) * 1e-3
     b1, b2 = 16.0 * dof, 24.0 * dof
     achieved = (b1 + b2) / (t1 + t2) / 1e9
-    import hashlib
-    with open(os.path.join(ROOT, "paper_1710_11259_amd", "csrc", "sweep.hip"), "rb") as fh:
-        sweep_sha = hashlib.sha256(fh.read()).hexdigest()
-    traffic = None
-    if sweep_sha == SWEEP_TRAFFIC["sha256"] and n == SWEEP_TRAFFIC["n"]:
-        traffic = (SWEEP_TRAFFIC["half_step_1"] + SWEEP_TRAFFIC["half_step_2"]) / 2.0
+    traffic = sweep_traffic(n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_note": "calibrated HBM bytes per launch, mean of the two half-steps "
-                                "(algorithmic mean 335.5e6)" if traffic else
-                                "null: sweep source changed since the counters were taken",
-                "kernel": "k_sweep (ADI half-sweeps; both variants, byte-weighted)",
+                                f"(algorithmic mean {(b1 + b2) / 2:.4g})" if traffic else
+                                "null: sweep sources changed since the counters were taken",
+                "kernel": "ADI half-sweeps (k_sweep_rows: half-step 1, k_sweep: half-step 2), "
+                          "byte-weighted",
                 "bytes_per_launch": {"half_step_1": b1, "half_step_2": b2},
                 "avg_launch_us": {"half_step_1": round(t1 * 1e6, 2),
                                   "half_step_2": round(t2 * 1e6, 2)},
