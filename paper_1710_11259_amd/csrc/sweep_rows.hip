@@ -31,7 +31,7 @@ constexpr int kChainsPerWave = 64 / kRSegs;
 static_assert(kRSegs == kWaves, "segment-carry combinations are indexed by segment");
 constexpr int kRChains = kChainsPerWave * kRWaves;  // chains (rows) per workgroup
 static_assert(kChunk % kRChains == 0, "a workgroup's rows lie in one chunk of the producer");
-static_assert(kSeg % 4 == 0, "segments of whole 16-byte vectors");
+static_assert(kSeg * kRWaves == kRChains, "the column-wise phases cover the tile's rows");
 
 // LDS (doubles): the chunk's per-position tables and segment-carry
 // combinations, one exchange row per wavefront, and the tile.
@@ -69,8 +69,10 @@ __device__ __forceinline__ double fused_carry_rows(const SweepArgs &a, int sp, i
 
 // One workgroup: chunk `by` = blockIdx.x of the columns (parity-0 chunks
 // first) of the chains (rows) bx * 32 .. bx * 32 + 31, bx = blockIdx.y.  Per
-// lane: chain bx * 32 + w * 8 + lane / 8, segment lane % 8 (kSeg columns).  Four wavefronts per workgroup
-// keep the register-bound occupancy in whole workgroups.
+// lane in the row phase: chain bx * 32 + w * 8 + lane / 8, segment lane % 8
+// (kSeg columns); in the load and store phases: column lane, rows w * 8 ..
+// w * 8 + 7.  Four wavefronts per workgroup keep the register- and
+// LDS-bound occupancy in whole workgroups.
 //   v   = in_scale * in + (chunk carries of the producing pass)
 //   x   = T^-1 v with T the pass's tridiagonal (tables)
 //   out = x (out_mode 1) or v - sigma x (out_mode 2), stored like `in`.
