@@ -118,6 +118,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 
+  // 16 x 16 blocks of this wavefront's 64 x 64 quarter that hold output
+  // entries: a thin last tile (a few rows or columns past whole tiles) skips
+  // the products of its empty blocks (uniform per wavefront).
+  const int64_t mrem = g.M - (i0 + wy * 64), nrem = g.N - (j0 + wx * 64);
+  const int na = mrem >= 64 ? 4 : mrem <= 0 ? 0 : (int)((mrem + 15) / 16);
+  const int nb = nrem >= 64 ? 4 : nrem <= 0 ? 0 : (int)((nrem + 15) / 16);
+  const bool full = na == 4 && nb == 4;
   if (klo < khi) {
     fetch(klo);
     stash();
@@ -132,11 +139,20 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
         for (int a = 0; a < 4; ++a) av[a] = As[wy * 64 + a * 16 + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
         for (int b = 0; b < 4; ++b) bv[b] = Bs[ks + (lane >> 4)][wx * 64 + b * 16 + (lane & 15)];
+        if (full) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+          for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 4; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        } else {
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              if (a < na && b < nb)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
       }
       __syncthreads();
       if (more) {
