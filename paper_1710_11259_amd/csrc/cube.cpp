@@ -439,10 +439,10 @@ void zeig_tables_of(const fps_plan *pl, int k, int j, int *t1, int *t2) {
 // 78 of 256 slices; measured 5.65 ms per solve against 6.07 on one stream,
 // 5.91 with 128 and 6.15 with 196 leading slices).  Latency-bound runs
 // (small n) keep one stream.
-int zeig_split(const std::vector<int> &J, int64_t npad) {
+int zeig_split(const std::vector<int> &J, int64_t npad, double bytes_per_dof = 40.0) {
   const int K = (int)J.size();
-  const double lat = 17.0;                                              // us per step
-  const double b = 40.0 * (double)npad * (double)npad / 5.6e12 * 1e6;  // us per slice step
+  const double lat = 17.0;                                                        // us per step
+  const double b = bytes_per_dof * (double)npad * (double)npad / 5.6e12 * 1e6;  // us per slice step
   double tot = 0.0, lead = 0.0;
   for (int k = 0; k < K; ++k) tot += J[k];
   int nl = 0;
@@ -542,6 +542,11 @@ fps_status zeigr_build(fps_plan *pl, const std::vector<long double> lam[2], doub
   pl->zJ = K > 0 ? pl->zrJ[0] : std::vector<int>();
   pl->zJmax = K > 0 ? pl->zrJmax[0] : 0;
   pl->zsplit = 0;
+  // every round splits its longest slices off like the FP64 plan (float
+  // storage: 8 + 12 bytes per dof and step)
+  pl->zrsplit.assign((size_t)pl->rounds, 0);
+  for (int r = 0; r < pl->rounds; ++r)
+    pl->zrsplit[(size_t)r] = zeig_split(pl->zrJ[(size_t)r], L.npad, 20.0);
   fps::build_sweep_tables_ab(L, alpha, beta, pl->tab, pl->ctab, nullptr, pl->l1);
   return FPS_OK;
 }
@@ -671,6 +676,23 @@ fps_status zeig_common(fps_plan *pl) {
 // Refined plans: per-slice mu (residual kernel), and the sweep and carry
 // descriptors of every round, [row][half][sorted slice] with row =
 // zrrow0[r] + j (see zeigr_build for the pass form).
+// The plan's default-priority side stream and its fork / join events (z-
+// eigenbasis plans that split their slices over two streams).
+fps_status create_side_stream(fps_plan *pl) {
+  if (pl->zside != nullptr) return FPS_OK;
+  if (hipStreamCreateWithFlags(&pl->zside, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->zfork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->zjoin, hipEventDisableTiming) != hipSuccess) {
+    if (pl->zside) (void)hipStreamDestroy(pl->zside);
+    if (pl->zfork) (void)hipEventDestroy(pl->zfork);
+    if (pl->zjoin) (void)hipEventDestroy(pl->zjoin);
+    pl->zside = nullptr;
+    pl->zfork = pl->zjoin = nullptr;
+    return fail(FPS_E_HIP, "creating the slice side stream failed");
+  }
+  return FPS_OK;
+}
+
 fps_status zeigr_upload(fps_plan *pl) {
   const fps::Layout &L = pl->L;
   const int64_t npad = L.npad, ch = npad * npad;
@@ -780,6 +802,8 @@ fps_status zeigr_upload(fps_plan *pl) {
       (s = upload(pl->d_zrfin, fin)) != FPS_OK || (s = upload(pl->d_zmu, pl->zrmu_slice)) != FPS_OK ||
       (fused && (s = upload(pl->d_zrdfin, rdfin)) != FPS_OK))
     return s;
+  for (int sp : pl->zrsplit)
+    if (sp > 0) return create_side_stream(pl);
   return FPS_OK;
 }
 
@@ -971,18 +995,7 @@ fps_status zeig_upload(fps_plan *pl) {
       (s = upload(pl->d_zfin, fin)) != FPS_OK ||
       (fused && (s = upload(pl->d_zrdfin, rdfin)) != FPS_OK))
     return s;
-  if (pl->zsplit > 0) {  // default-priority side stream and its fork / join events
-    if (hipStreamCreateWithFlags(&pl->zside, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->zfork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->zjoin, hipEventDisableTiming) != hipSuccess) {
-      if (pl->zside) (void)hipStreamDestroy(pl->zside);
-      if (pl->zfork) (void)hipEventDestroy(pl->zfork);
-      if (pl->zjoin) (void)hipEventDestroy(pl->zjoin);
-      pl->zside = nullptr;
-      pl->zfork = pl->zjoin = nullptr;
-      return fail(FPS_E_HIP, "creating the slice side stream failed");
-    }
-  }
+  if (pl->zsplit > 0) return create_side_stream(pl);
   return FPS_OK;
 }
 
@@ -1015,10 +1028,10 @@ fps_status zeigr_adi(fps_plan *pl, char *w, hipStream_t st) {
   t1.pre = t2.pre = dv;
   t1.in_f32 = t1.out_f32 = 1;
   t2.in_f32 = t2.g_f32 = t2.out_f32 = 1;
-  auto sweep = [&](const fps::SweepArgs &types, bool with_g, const fps::BatchSweep *d,
-                   int nwg) -> hipError_t {
+  auto sweep = [&](const fps::SweepArgs &types, bool with_g, const fps::BatchSweep *d, int nwg,
+                   int wg_base, hipStream_t s2) -> hipError_t {
     const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
-    const hipError_t e = fps::launch_sweep_batch(types, with_g, d, swmap, nwg, w, st, 0,
+    const hipError_t e = fps::launch_sweep_batch(types, with_g, d, swmap, nwg, w, s2, wg_base,
                                                  t ? pl->ev[2 * pl->ev_used] : nullptr,
                                                  t ? pl->ev[2 * pl->ev_used + 1] : nullptr);
     if (t && e == hipSuccess) ++pl->ev_used;
@@ -1073,15 +1086,41 @@ fps_status zeigr_adi(fps_plan *pl, char *w, hipStream_t st) {
                                (int)npad, lvb, abb));
     FPS_HIP(fps::launch_slice_xfinal(q, ab, pl->tab_dev(0), HT, H, npad, mp0, L.mstride, L.ncmax,
                                      npad, st));
-    // the K-form ADI of every slice, the active ones a prefix of the order
-    for (int j = 0; j < pl->zrJmax[(size_t)r]; ++j) {
-      const int k1 = pl->zractive[(size_t)r][(size_t)j];
-      const size_t row = (size_t)pl->zrrow0[(size_t)r] + (size_t)j;
-      const size_t o1 = (row * 2 + 0) * Kc, o2 = (row * 2 + 1) * Kc;
-      FPS_HIP(sweep(t1, false, dsw + o1, k1 * nsw));
-      if (!pl->zfused) FPS_HIP(fps::launch_reduce_batch(drd + o1, rdmap, k1 * nrd, L.ncmax, w, st));
-      FPS_HIP(sweep(t2, true, dsw + o2, k1 * nsw));
-      if (!pl->zfused) FPS_HIP(fps::launch_reduce_batch(drd + o2, rdmap, k1 * nrd, L.ncmax, w, st));
+    // The K-form ADI of sorted slices lo .. hi-1 on stream s2: at step j
+    // the active ones are lo .. min(zractive[r][j], hi) - 1 (J descending).
+    auto run_group = [&](int lo, int hi, hipStream_t s2) -> hipError_t {
+      hipError_t e = hipSuccess;
+      for (int j = 0; j < pl->zrJmax[(size_t)r] && e == hipSuccess; ++j) {
+        const int k1 = std::min(pl->zractive[(size_t)r][(size_t)j], hi);
+        if (k1 <= lo) break;
+        const size_t row = (size_t)pl->zrrow0[(size_t)r] + (size_t)j;
+        const size_t o1 = (row * 2 + 0) * Kc, o2 = (row * 2 + 1) * Kc;
+        e = sweep(t1, false, dsw + o1, (k1 - lo) * nsw, lo * nsw, s2);
+        if (e == hipSuccess && !pl->zfused)
+          e = fps::launch_reduce_batch(drd + o1, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
+        if (e == hipSuccess) e = sweep(t2, true, dsw + o2, (k1 - lo) * nsw, lo * nsw, s2);
+        if (e == hipSuccess && !pl->zfused)
+          e = fps::launch_reduce_batch(drd + o2, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
+      }
+      return e;
+    };
+    // The round's longest slices iterate on the plan's side stream beside the
+    // rest (as in the FP64 solve); per-dispatch timing keeps one stream.
+    const int split = pl->zrsplit.empty() ? 0 : pl->zrsplit[(size_t)r];
+    if (split > 0 && split < K && pl->zside && pl->ev.empty()) {
+      std::lock_guard<std::mutex> lk(pl->zlock);
+      FPS_HIP(hipEventRecord(pl->zfork, st));
+      FPS_HIP(hipStreamWaitEvent(pl->zside, pl->zfork, 0));
+      const hipError_t e1 = run_group(0, split, pl->zside);
+      const hipError_t e2 = e1 == hipSuccess ? run_group(split, K, st) : hipSuccess;
+      const hipError_t e3 = hipEventRecord(pl->zjoin, pl->zside);
+      const hipError_t e4 = e3 == hipSuccess ? hipStreamWaitEvent(st, pl->zjoin, 0) : e3;
+      FPS_HIP(e1);
+      FPS_HIP(e2);
+      FPS_HIP(e3);
+      FPS_HIP(e4);
+    } else {
+      FPS_HIP(run_group(0, K, st));
     }
     if (pl->zfused)  // the carries of every slice's last half-step of the round
       FPS_HIP(fps::launch_reduce_batch((const fps::BatchReduce *)pl->d_zrdfin.p + (size_t)r * Kc,

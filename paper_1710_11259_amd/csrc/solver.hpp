@@ -165,6 +165,9 @@ struct fps_plan {
   std::vector<double> zrmu_slice;  // mu of every storage slice (0 for padding)
   std::vector<std::vector<int>> zrJ, zrtab0, zractive;
   std::vector<int> zrJmax, zrrow0;
+  // per round: sorted slices 0 .. zrsplit[r]-1 iterate on the side stream
+  // (zside / zfork / zjoin, as zsplit for FP64 plans); 0: one stream
+  std::vector<int> zrsplit;
   fps::detail::DeviceBuf d_zrsw, d_zrrd, d_zrfin, d_zmu;
   std::vector<double> zV[2];  // host eigenvectors of the parity blocks (m x m, columns)
   int64_t ws_bytes = 0;

@@ -56,3 +56,23 @@ def test_cube_refined_deterministic_and_stale_workspace():
     U2 = fps.solve(p, F, ws=ws)
     torch.cuda.synchronize()
     assert torch.equal(U1, U2)
+
+
+@pytest.mark.parametrize("n", [16, 64, 256])
+def test_cube_refined_two_streams_equal_one(n):
+    # Every round runs its longest slices on the plan's second stream; with
+    # per-launch timing on, every launch goes to the caller's stream.  Each
+    # slice's arithmetic is the same either way: the results agree bit for bit.
+    F = torch.from_numpy(workloads.cube_rhs(n)).cuda()
+    p = _plan(n)
+    print(f"cube refined streams n={n}", flush=True)
+    U2 = fps.solve(p, F)
+    p.set_sweep_timing(8 * sum(p.round_steps()[0]))
+    U1 = fps.solve(p, F)
+    torch.cuda.synchronize()
+    p.sweep_time()
+    p.set_sweep_timing(0)
+    U3 = fps.solve(p, F)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)
+    assert torch.equal(U3, U2)
