@@ -329,12 +329,8 @@ def bench_cube_zeig(fps, workloads, torch, tol, n=256, steps=3, check=True, tigh
     Jmax = max(counts) if counts else 0
     for j in range(Jmax):
         k1 = sum(1 for c in counts if c > j)
-        k2 = sum(1 for c in counts if c > j + 1)
         seq.append((k1, 16.0))
-        if k2 > 0:
-            seq.append((k2, 24.0))
-        if k1 > k2:
-            seq.append((k1 - k2, 24.0))
+        seq.append((k1, 24.0))
     p.set_sweep_timing(len(seq))
     e0.record()
     fps.solve(p, F, out=U, ws=ws)

@@ -295,9 +295,7 @@ fps_status fps_adi_native(fps_plan *plan, const double *G_dev, double *Y_dev, vo
  * and half-step 2 of Algorithm 2 alternate, starting with half-step 1; cube
  * plans: per outer step one z sweep, then the inner half-steps 1 and 2;
  * z-eigenbasis cube plans: per step j the x solves of all slices still
- * iterating, then the y solves of the slices with a later step (stencil),
- * then those of the slices at their last step (each launch only if it has
- * slices).
+ * iterating, then their y solves (one launch each).
  */
 fps_status fps_plan_set_sweep_timing(fps_plan *plan, int capacity);
 fps_status fps_plan_sweep_time(fps_plan *plan, double *ms_host, int64_t cap, int64_t *launches);

@@ -850,8 +850,13 @@ fps_status zeig_upload(fps_plan *pl) {
       }
     }
   }
+  // the stencil A~ (diagonal, coupling), then the identity stencil (ones,
+  // zeros) that the y solves of slices at their last step take, so that they
+  // run in the same launch as the stencil y solves of the others
   std::vector<double> pre(pl->sdiag);
   pre.insert(pre.end(), pl->soff.begin(), pl->soff.end());
+  pre.insert(pre.end(), (size_t)npad, 1.0);
+  pre.insert(pre.end(), (size_t)npad, 0.0);
   if ((s = upload(pl->d_tab, pl->tab)) != FPS_OK || (s = upload(pl->d_ctab, pl->ctab)) != FPS_OK ||
       (s = upload(pl->d_l1, pl->l1)) != FPS_OK || (s = upload(pl->d_sinv, pl->sinv)) != FPS_OK ||
       (s = upload(pl->d_pre, pre)) != FPS_OK)
@@ -944,8 +949,9 @@ fps_status zeig_upload(fps_plan *pl) {
       a2.g = (const void *)(intptr_t)(pl->off_G + so);
       a2.sg = -1.0;
       a2.og = 0.0;
-      a2.pre = last ? nullptr : pre_d;
-      a2.pre_shift = mu;
+      // last step: the identity stencil (P = I: the plain y solve, exactly)
+      a2.pre = last ? pre_d + 2 * npad : pre_d;
+      a2.pre_shift = last ? 0.0 : mu;
       a2.tab = pl->tab_dev(t2);
       a2.l1 = pl->l1_dev(t2);
       a2.sigma = last ? 0.0 : qj - pn;
@@ -1182,16 +1188,15 @@ fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
     auto run_group = [&](int lo, int hi, hipStream_t s2) -> hipError_t {
       hipError_t e = hipSuccess;
       for (int j = 0; j < pl->zJmax && e == hipSuccess; ++j) {
-        const int k1 = std::min(pl->zactive[j], hi), k2 = std::max(std::min(pl->zactive[j + 1], hi), lo);
+        const int k1 = std::min(pl->zactive[j], hi);
         if (k1 <= lo) break;
         const size_t o1 = ((size_t)j * 2 + 0) * K, o2 = ((size_t)j * 2 + 1) * K;
         e = sweep(plain, false, dsw + o1, (k1 - lo) * nsw, lo * nsw, s2);
         if (e == hipSuccess && !pl->zfused)
           e = fps::launch_reduce_batch(drd + o1, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
-        if (e == hipSuccess && k2 > lo)  // slices with a later step: stencil P before the y solve
-          e = sweep(stencil, true, dsw + o2, (k2 - lo) * nsw, lo * nsw, s2);
-        if (e == hipSuccess && k1 > k2)  // slices at their last step: no stencil
-          e = sweep(plain, true, dsw + o2, (k1 - k2) * nsw, k2 * nsw, s2);
+        // y solves: stencil P = A~ + mu before the solve, the identity for
+        // the slices at their last step, all in one launch
+        if (e == hipSuccess) e = sweep(stencil, true, dsw + o2, (k1 - lo) * nsw, lo * nsw, s2);
         if (e == hipSuccess && !pl->zfused)
           e = fps::launch_reduce_batch(drd + o2, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
       }
