@@ -21,10 +21,10 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6  # dense FP64 matrix peak of MI355X
 # Calibrated HBM traffic of the sweep kernels per launch (rocprofv3
 # FETCH_SIZE x1.9999 + WRITE_SIZE x1.0000, see profiles/sweep_square_n4096.md
-# and profiles/sweep_square_n10000.md), valid only for the sweep sources
-# (sweep.hip, then sweep_rows.hip) with this combined sha256 (the counters were
-# taken on the same device code; later edits touched comments only).
-SWEEP_SOURCES = ("sweep.hip", "sweep_rows.hip")
+# and profiles/sweep_square_n10000.md), valid only for the sweep source
+# (sweep.hip) with this sha256 (the counters were taken on the same device
+# code).
+SWEEP_SOURCES = ("sweep.hip",)
 SWEEP_TRAFFIC = {"sha256": "19b1d2ca50672f539ebec0e6026583baacd03a6896469529490e16a068070fb8",
                  4096: {"half_step_1": 278.2e6, "half_step_2": 413.0e6},
                  10000: {"half_step_1": 1748.1e6, "half_step_2": 2529.8e6}}

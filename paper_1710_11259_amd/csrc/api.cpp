@@ -67,29 +67,27 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
   const fps::Layout &L = pl->L;
   const int J = sh.J;
   const std::vector<double> &p = sh.p, &q = sh.q;
-  double *lv = (double *)(ws + pl->off_lv);
-  double *ab = (double *)(ws + pl->off_ab);
+  double *lv = (double *)(ws + pl->off_lv), *lv2 = (double *)(ws + pl->off_lv2);
+  double *ab = (double *)(ws + pl->off_ab), *ab2 = (double *)(ws + pl->off_ab2);
   const int nc0 = (int)L.nc[0], nc1 = (int)L.nc[1];
   // Chains of at most two chunks: each sweep forms its producer's carries
   // itself from the boundary values (first half-steps write lv, second ones
   // lv2), and only the last half-step's carries are launched (for the final
-  // pass).
+  // pass).  Longer chains: a carry launch after every half-step (first
+  // half-steps' carries into ab2, second ones' into ab).
   const bool fused = L.ncmax <= 2;
-  double *lv2 = fused ? (double *)(ws + pl->off_lv2) : lv;
-  double sigma_prev = 0.0;
 
-  fps::SweepArgs A{};
-  A.npad = L.npad;
-  A.ncols = L.npad;
-  A.ld = L.npad;
-  A.nbatch = 1;
-  A.mp0 = L.mp[0];
-  A.mp1 = L.mp[1];
-  A.mstride = L.mstride;
-  A.ncmax = L.ncmax;
-  A.nc0 = nc0;
-  A.nc1 = nc1;
-  A.lv = lv;
+  fps::SweepArgs A0{};
+  A0.npad = L.npad;
+  A0.ncols = L.npad;
+  A0.ld = L.npad;
+  A0.nbatch = 1;
+  A0.mp0 = L.mp[0];
+  A0.mp1 = L.mp[1];
+  A0.mstride = L.mstride;
+  A0.ncmax = L.ncmax;
+  A0.nc0 = nc0;
+  A0.nc1 = nc1;
   // Every array keeps one layout (that of G): half-step 1 solves along its
   // storage rows (launch_sweep_rows), half-step 2 along its storage columns
   // (launch_sweep), and both store their outputs in place of their inputs'
@@ -103,64 +101,108 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
   // solve T2_j Y_{j+1} = V_j, output R_{j+1} = (V_j - G) - (p_{j+1} - q_j)
   // Y_{j+1}.  So only half-step 2 reads G, and R_0 = -G.  For the square
   // (q_j = -p_j, T1_j = T2_j = A~ + p_j) the coefficients are 2 p_j and
-  // p_j + p_{j+1}.  After every half-step the chunk carries are resolved
-  // into `ab`, which the next half-step folds in.
-  for (int j = 0; j < J; ++j) {
-    const double s1 = pl->rect ? p[j] - q[j] : 2.0 * p[j];
-    A.in = j == 0 ? Gterm : (const void *)O1;
-    A.in_f32 = j == 0 ? g_f32 : f32;
-    A.in_scale = j == 0 ? -1.0 : 1.0;
-    A.ab_prev = j == 0 ? nullptr : ab;
-    A.tab_prev = j == 0 ? nullptr : pl->tab_dev(pl->tab2(base + j - 1));
-    A.g = nullptr;
-    A.g_f32 = 0;
-    A.sg = 0.0;
-    A.tab = pl->tab_dev(pl->tab1(base + j));
-    A.l1 = pl->l1_dev(pl->tab1(base + j));
-    A.sigma = s1;
-    A.out = O0;
-    A.out_f32 = f32;
-    A.out_mode = 2;
-    if (fused && j > 0) {
-      A.ab_prev = nullptr;
-      A.lv_prev = lv2;
-      A.ctab_prev = pl->ctab_dev(pl->tab2(base + j - 1));
-      A.carry_scale = -sigma_prev;
-    }
-    A.lv = lv;
-    FPS_HIP(timed_sweep(pl, A, st, true));
-    if (!fused)
-      FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(pl->tab1(base + j)), ab, -A.sigma, L.npad, nc0,
-                                 nc1, L.ncmax, st));
-    fps::SweepArgs B = A;
-    const bool last = j == J - 1;
-    B.in = O0;
-    B.in_f32 = f32;
-    B.in_scale = 1.0;
-    B.ab_prev = ab;
-    B.tab_prev = A.tab;
-    if (fused) {
-      B.ab_prev = nullptr;
-      B.lv_prev = lv;
-      B.ctab_prev = pl->ctab_dev(pl->tab1(base + j));
-      B.carry_scale = -A.sigma;
+  // p_j + p_{j+1}.  After every half-step the chunk carries are resolved,
+  // and the next half-step folds them in.
+  //
+  // A~ is block diagonal in the parity-blocked layout, so the storage rows of
+  // one parity block (rows r0 .. r1-1) iterate independently of the other
+  // block's: the first half-step solves along those rows (chain blocks
+  // r0 / 64 ..), the second along every column but only over those rows (the
+  // chunk rows c0 .. c1-1 of row parity s), and each half-step's carries
+  // are those of its own chains and positions.  `part` runs the J steps of
+  // one such block (or, with the whole ranges, of the array).
+  auto part = [&](int64_t r0, int64_t r1, int c0, int c1, int s, hipStream_t s2) -> hipError_t {
+    const bool whole = r0 == 0 && r1 == L.npad;
+    double sigma_prev = 0.0;
+    for (int j = 0; j < J; ++j) {
+      const double s1 = pl->rect ? p[j] - q[j] : 2.0 * p[j];
+      fps::SweepArgs A = A0;
+      if (!whole) {
+        A.blk0 = (int)(r0 / 64);
+        A.blk1 = (int)(r1 / 64);
+      }
+      A.in = j == 0 ? Gterm : (const void *)O1;
+      A.in_f32 = j == 0 ? g_f32 : f32;
+      A.in_scale = j == 0 ? -1.0 : 1.0;
+      A.ab_prev = j == 0 ? nullptr : ab;
+      A.tab_prev = j == 0 ? nullptr : pl->tab_dev(pl->tab2(base + j - 1));
+      A.tab = pl->tab_dev(pl->tab1(base + j));
+      A.l1 = pl->l1_dev(pl->tab1(base + j));
+      A.sigma = s1;
+      A.out = O0;
+      A.out_f32 = f32;
+      A.out_mode = 2;
+      if (fused && j > 0) {
+        A.ab_prev = nullptr;
+        A.lv_prev = lv2;
+        A.ctab_prev = pl->ctab_dev(pl->tab2(base + j - 1));
+        A.carry_scale = -sigma_prev;
+      }
+      A.lv = lv;
+      hipError_t e = timed_sweep(pl, A, s2, true);
+      if (e == hipSuccess && !fused)
+        e = fps::launch_reduce(lv, pl->ctab_dev(pl->tab1(base + j)), ab2, -A.sigma, L.npad, nc0,
+                               nc1, L.ncmax, s2, 1, 0, 0, r0, r1, 0, 2);
+      if (e != hipSuccess) return e;
+      fps::SweepArgs B = A0;
+      if (!whole) {
+        B.chk0 = c0;
+        B.chk1 = c1;
+      }
+      const bool last = j == J - 1;
+      B.in = O0;
+      B.in_f32 = f32;
+      B.in_scale = 1.0;
+      B.ab_prev = ab2;
+      B.tab_prev = A.tab;
+      if (fused) {
+        B.ab_prev = nullptr;
+        B.lv_prev = lv;
+        B.ctab_prev = pl->ctab_dev(pl->tab1(base + j));
+        B.carry_scale = -A.sigma;
+      }
       B.lv = lv2;
+      B.g = Gterm;
+      B.g_f32 = g_f32;
+      B.sg = 1.0;
+      B.tab = pl->tab_dev(pl->tab2(base + j));
+      B.l1 = pl->l1_dev(pl->tab2(base + j));
+      B.sigma = last ? 0.0 : (pl->rect ? p[j + 1] - q[j] : p[j] + p[j + 1]);
+      B.out = O1;
+      B.out_f32 = f32;
+      B.out_mode = last ? 1 : 2;
+      e = timed_sweep(pl, B, s2);
+      if (e == hipSuccess && (!fused || last))
+        e = fps::launch_reduce(lv2, pl->ctab_dev(pl->tab2(base + j)), ab, last ? 1.0 : -B.sigma,
+                               L.npad, nc0, nc1, L.ncmax, s2, 1, 0, 0, 0, L.npad,
+                               whole ? 0 : s, whole ? 2 : s + 1);
+      if (e != hipSuccess) return e;
+      sigma_prev = B.sigma;
     }
-    B.g = Gterm;
-    B.g_f32 = g_f32;
-    B.sg = 1.0;
-    B.tab = pl->tab_dev(pl->tab2(base + j));
-    B.l1 = pl->l1_dev(pl->tab2(base + j));
-    B.sigma = last ? 0.0 : (pl->rect ? p[j + 1] - q[j] : p[j] + p[j + 1]);
-    B.out = O1;
-    B.out_f32 = f32;
-    B.out_mode = last ? 1 : 2;
-    FPS_HIP(timed_sweep(pl, B, st));
-    if (!fused || last)
-      FPS_HIP(fps::launch_reduce(B.lv, pl->ctab_dev(pl->tab2(base + j)), ab, last ? 1.0 : -B.sigma,
-                                 L.npad, nc0, nc1, L.ncmax, st));
-    sigma_prev = B.sigma;
+    return hipSuccess;
+  };
+  // Two streams for the two row-parity blocks when the plan has its side
+  // stream (chains of more than two chunks, both blocks non-empty), unless
+  // every sweep is being timed on the caller's stream.
+  if (pl->zside == nullptr || fused || L.m[1] == 0 || !pl->ev.empty()) {
+    FPS_HIP(part(0, L.npad, 0, nc0 + nc1, 0, st));
+    return FPS_OK;
   }
+  // One solve at a time forks onto the side stream (its event record and
+  // wait must not interleave with another host thread's); the join is
+  // enqueued whatever the parts returned, so the side stream (or a graph
+  // being captured) is never left forked.
+  std::lock_guard<std::mutex> lk(pl->zlock);
+  FPS_HIP(hipEventRecord(pl->zfork, st));
+  FPS_HIP(hipStreamWaitEvent(pl->zside, pl->zfork, 0));
+  const hipError_t e1 = part(L.mp[0], L.npad, nc0, nc0 + nc1, 1, pl->zside);
+  const hipError_t e2 = e1 == hipSuccess ? part(0, L.mp[0], 0, nc0, 0, st) : hipSuccess;
+  const hipError_t e3 = hipEventRecord(pl->zjoin, pl->zside);
+  const hipError_t e4 = e3 == hipSuccess ? hipStreamWaitEvent(st, pl->zjoin, 0) : e3;
+  FPS_HIP(e1);
+  FPS_HIP(e2);
+  FPS_HIP(e3);
+  FPS_HIP(e4);
   return FPS_OK;
 }
 
@@ -510,10 +552,12 @@ fps_status plan2d_build(fps_plan *pl) {
     pl->off_bc = pl->ws_bytes;
     pl->ws_bytes += align256((4 * L.npad + 8) * 8);
   }
-  pl->off_lv2 = pl->off_lv;
-  if (fused) {
-    pl->off_lv2 = pl->ws_bytes;
-    pl->ws_bytes += lvb;
+  pl->off_lv2 = pl->ws_bytes;
+  pl->ws_bytes += lvb;
+  pl->off_ab2 = pl->off_ab;
+  if (!fused) {
+    pl->off_ab2 = pl->ws_bytes;
+    pl->ws_bytes += abb;
   }
 
   if (!(flags & FPS_PLAN_HOST_ONLY)) {
@@ -529,6 +573,9 @@ fps_status plan2d_build(fps_plan *pl) {
         (s = upload(pl->d_lift[0], lift[0])) != FPS_OK ||
         (s = upload(pl->d_lift[1], lift[1])) != FPS_OK)
       return s;
+    // chains of more than two chunks: the two row-parity halves of the ADI
+    // run on two streams (run_adi)
+    if (!fused && L.m[1] > 0 && (s = create_side_stream(pl)) != FPS_OK) return s;
     pl->on_device = true;
   }
   return FPS_OK;

@@ -673,11 +673,9 @@ fps_status zeig_common(fps_plan *pl) {
   return FPS_OK;
 }
 
-// Refined plans: per-slice mu (residual kernel), and the sweep and carry
-// descriptors of every round, [row][half][sorted slice] with row =
-// zrrow0[r] + j (see zeigr_build for the pass form).
-// The plan's default-priority side stream and its fork / join events (z-
-// eigenbasis plans that split their slices over two streams).
+// The plan's default-priority side stream and its fork / join events
+// (z-eigenbasis plans that split their slices over two streams; 2-D plans
+// that split their ADI by row parity).
 fps_status create_side_stream(fps_plan *pl) {
   if (pl->zside != nullptr) return FPS_OK;
   if (hipStreamCreateWithFlags(&pl->zside, hipStreamNonBlocking) != hipSuccess ||
@@ -693,6 +691,9 @@ fps_status create_side_stream(fps_plan *pl) {
   return FPS_OK;
 }
 
+// Refined plans: per-slice mu (residual kernel), and the sweep and carry
+// descriptors of every round, [row][half][sorted slice] with row =
+// zrrow0[r] + j (see zeigr_build for the pass form).
 fps_status zeigr_upload(fps_plan *pl) {
   const fps::Layout &L = pl->L;
   const int64_t npad = L.npad, ch = npad * npad;

@@ -65,6 +65,10 @@ struct SweepArgs {
   // d/d/d or f/f/f with g in the right-hand side, d/d/d with g in the
   // output base.
   int in_f32, g_f32, out_f32;
+  // Single launches: the chain blocks (64 chains) blk0 .. blk1-1 and chunk
+  // rows (parity-0 chunks first) chk0 .. chk1-1 only; blk1 = 0 / chk1 = 0
+  // take all of them.  Batched launches take all.
+  int blk0, blk1, chk0, chk1;
 };
 
 // With ev0 / ev1 non-null the launch records the dispatch's own start and
@@ -72,13 +76,13 @@ struct SweepArgs {
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 
-// Row-chain half-sweep (sweep_rows.hip): the same pass along the storage
-// rows of `in` (chains = rows, positions = columns, ncols = npad chains),
-// stored in the same layout (out_mode 1: x, 2: v - sigma x); no g term or
-// stencil, single arrays; in/out storage d/d, f/d or f/f.  The producer's
-// carries fold in as in launch_sweep with the producer's chains along the
-// columns; its chunk boundary values go to lv ([ncmax][2][2][npad], chains
-// = rows).
+// Row-chain half-sweep: the same pass along the storage rows of `in`
+// (chains = rows, positions = columns, ncols = npad chains), stored in the
+// same layout (out_mode 1: x, 2: v - sigma x); no g term or stencil, single
+// arrays; in/out storage d/d, f/d or f/f.  The producer's carries fold in
+// as in launch_sweep with the producer's chains along the columns; its
+// chunk boundary values go to lv ([ncmax][2][2][npad], chains = rows).
+// Equals launch_sweep on the transposed arrays bit for bit.
 hipError_t launch_sweep_rows(const SweepArgs &a, hipStream_t st, hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr);
 
@@ -103,9 +107,12 @@ hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSw
 // chunk, scaled by `scale`, into ab [2][ncmax][nchains][2] (ctab: the
 // per-chunk coefficients [2][kNCTab][ncmax] of the producing pass's shift);
 // nbatch blocks of lv / ab at strides lvb / abb.
+// Only the chains r_lo .. r_hi-1 (r_hi < 0: all) of the parities s_lo ..
+// s_hi-1 are resolved.
 hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,
                          int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
-                         int nbatch = 1, int64_t lvb = 0, int64_t abb = 0);
+                         int nbatch = 1, int64_t lvb = 0, int64_t abb = 0, int64_t r_lo = 0,
+                         int64_t r_hi = -1, int s_lo = 0, int s_hi = 2);
 
 // Shape of the chunk-carry kernels for chains of up to ncmax chunks: each
 // chain on a segment of 2 to 16 lanes (the least power of two that holds

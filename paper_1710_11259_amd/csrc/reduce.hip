@@ -134,34 +134,36 @@ __device__ __forceinline__ void reduce_chain_scan_reg(const ChainSrc &src, doubl
   }
 }
 
-// The carries of the workgroup's kReduceThreads / kL chains (r0 ..) of
-// parity s.
+// The carries of the workgroup's kReduceThreads / kL chains (r0 .., below
+// rend) of parity s.
 template <int kL, int kQ>
 __device__ __forceinline__ void reduce_block(const double *__restrict__ lv,
                                              const double *__restrict__ ct,
                                              double *__restrict__ ab, double scale,
                                              int64_t nchains, int nc, int64_t ncmax, int s,
-                                             int64_t r0) {
+                                             int64_t r0, int64_t rend) {
   const int ch = threadIdx.x / kL, lane = threadIdx.x % kL;
   const int64_t r = r0 + ch;
-  if (r >= nchains || nc == 0) return;  // whole kL-lane segments leave together
+  if (r >= rend || nc == 0) return;  // whole kL-lane segments leave together
   const double *yl = lv + (int64_t)s * 2 * nchains + r;
   const ChainSrc src{yl, yl + nchains, 4 * nchains, ct, ncmax};
   reduce_chain_scan_reg<kL, kQ>(src, ab + ((int64_t)s * ncmax * nchains + r) * 2, 2 * nchains,
                                 scale, nc, lane);
 }
 
-// Grid: (ceil(nchains / (kReduceThreads / kL)), 2 parities, batch);
-// workgroup of kReduceThreads threads, chain-major.
+// Grid: (ceil((r_hi - r_lo) / (kReduceThreads / kL)), parities s_lo ..,
+// batch); workgroup of kReduceThreads threads, chain-major.
 template <int kL, int kQ>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(
     const double *__restrict__ lv, const double *__restrict__ ctab, double *__restrict__ ab,
-    double scale, int64_t nchains, int nc0, int nc1, int64_t ncmax, int64_t lvb, int64_t abb) {
-  const int s = blockIdx.y;
+    double scale, int64_t nchains, int nc0, int nc1, int64_t ncmax, int64_t lvb, int64_t abb,
+    int64_t r_lo, int64_t r_hi, int s_lo) {
+  const int s = (int)blockIdx.y + s_lo;
   const int nc = s ? nc1 : nc0;
   const int64_t z = blockIdx.z;
   reduce_block<kL, kQ>(lv + z * lvb, ctab + (int64_t)s * kNCTab * ncmax, ab + z * abb, scale,
-                       nchains, nc, ncmax, s, (int64_t)blockIdx.x * (kReduceThreads / kL));
+                       nchains, nc, ncmax, s,
+                       r_lo + (int64_t)blockIdx.x * (kReduceThreads / kL), r_hi);
 }
 
 template <int kL, int kQ>
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_batch(
   const int nc = s ? e.nc1 : e.nc0;
   reduce_block<kL, kQ>((const double *)(base + e.lv_off), e.ctab + (int64_t)s * kNCTab * e.ncmax,
                        (double *)(base + e.ab_off), e.scale, e.npad, nc, e.ncmax, s,
-                       (int64_t)(local % e.nbx) * (kReduceThreads / kL));
+                       (int64_t)(local % e.nbx) * (kReduceThreads / kL), e.npad);
 }
 
 // Kernel shape for chains of up to ncmax chunks: lanes per chain, and the
@@ -212,14 +214,19 @@ void reduce_shape(int64_t ncmax, int *lanes, int *kq) {
 
 hipError_t launch_reduce(const double *lv, const double *ctab, double *ab, double scale,
                          int64_t nchains, int nc0, int nc1, int64_t ncmax, hipStream_t st,
-                         int nbatch, int64_t lvb, int64_t abb) {
+                         int nbatch, int64_t lvb, int64_t abb, int64_t r_lo, int64_t r_hi,
+                         int s_lo, int s_hi) {
+  if (r_hi < 0) r_hi = nchains;
+  if (r_lo < 0 || r_hi > nchains || s_lo < 0 || s_hi > 2) return hipErrorInvalidValue;
+  if (r_lo >= r_hi || s_lo >= s_hi) return hipSuccess;
   const int chains = reduce_chains(ncmax);
-  dim3 grid((unsigned)((nchains + chains - 1) / chains), 2u, (unsigned)(nbatch > 0 ? nbatch : 1));
+  dim3 grid((unsigned)((r_hi - r_lo + chains - 1) / chains), (unsigned)(s_hi - s_lo),
+            (unsigned)(nbatch > 0 ? nbatch : 1));
   int lanes, kq;
   reduce_shape(ncmax, &lanes, &kq);
 #define FPS_LAUNCH(L, Q)                                                                    \
   hipLaunchKernelGGL((k_reduce<L, Q>), grid, dim3(kReduceThreads), 0, st, lv, ctab, ab, \
-                     scale, nchains, nc0, nc1, ncmax, lvb, abb)
+                     scale, nchains, nc0, nc1, ncmax, lvb, abb, r_lo, r_hi, s_lo)
   FPS_WITH_REDUCE_SHAPE(lanes, kq, FPS_LAUNCH);
 #undef FPS_LAUNCH
   return hipGetLastError();

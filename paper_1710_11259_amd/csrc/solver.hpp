@@ -104,9 +104,13 @@ struct fps_plan {
 
   // workspace layout (byte offsets)
   int64_t off_G = 0, off_GT = 0, off_O0 = 0, off_O1 = 0, off_lv = 0, off_ab = 0;
-  // second chunk-boundary-value buffer (z-eigenbasis cube plans whose sweeps
-  // form their carries themselves: first half-steps write lv, second ones lv2)
-  int64_t off_lv2 = 0;
+  // Second chunk-boundary-value buffer: 2-D plans' second half-steps write
+  // lv2 and first ones lv; z-eigenbasis cube plans whose sweeps form their
+  // carries themselves use it the same way.  2-D plans: the carries of first
+  // half-steps go to ab2, those of second ones (and the final pass's) to ab,
+  // so that the two row-parity halves of the ADI can run on two streams
+  // without sharing a buffer element.
+  int64_t off_lv2 = 0, off_ab2 = 0;
   int64_t off_X = 0;  // adjoint: the output cotangent in the parity-blocked layout
   int64_t off_R = 0;  // FP32_REFINED: the float residual and its transpose
   // Dirichlet lift (2-D plans with FPS_PLAN_DIRICHLET): the traces' scaled
@@ -244,6 +248,9 @@ fps_status cube_plan_build(fps_plan *pl);
 fps_status cube_plan_upload(fps_plan *pl);
 fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *ws, hipStream_t st);
 hipError_t timed_sweep(fps_plan *pl, const fps::SweepArgs &a, hipStream_t st, bool rows = false);
+// The plan's default-priority side stream and its fork / join events
+// (zside / zfork / zjoin), created once.
+fps_status create_side_stream(fps_plan *pl);
 // Cylinder (Sec. 4.1): host tables and workspace layout, their upload, the
 // solve, and the band of one mode's r-operators (inspection).
 fps_status cyl_plan_build(fps_plan *pl, int64_t nt);

@@ -1,8 +1,13 @@
 // gfx950 kernels of the spectral Poisson solver.
 //
 // Sweep design (one launch per ADI half-sweep of Algorithm 2):
-//   * every lane owns one chain (storage column) and kSeg consecutive
-//     positions of it; kWaves wavefronts stacked along the chain form a chunk;
+//   * every lane owns one chain and kSeg consecutive positions of it;
+//     kWaves wavefronts stacked along the chain form a chunk.  Chains run
+//     along the storage columns (k_sweep), or along the storage rows
+//     (k_sweep_rows: the workgroup's 64 x 64 tile is read and written row
+//     by row, one 64-position run per instruction, and turned around in LDS
+//     on load and on store), with the same arithmetic: a row-chain pass on
+//     an array equals a column-chain pass on its transpose bit for bit;
 //   * the Thomas recurrences y_k = r_k - l_k y_{k-1} and
 //     x_k = ib_k y_k - u_k x_{k+1} use factors of the whole chain (computed
 //     once per shift on the host), so splitting a chain only re-associates
@@ -13,8 +18,10 @@
 //     (reduce.hip), and folded into the next pass when it reads its input;
 //   * the multiply by (A~ - p' I) that Algorithm 2 applies after each solve
 //     along the same direction is r - (p + p') x, so no neighbour access is
-//     needed; the pass output is stored transposed so that the next pass,
-//     which solves along the other direction, again reads whole rows;
+//     needed; a column-chain pass can store its output transposed (the
+//     batched form alternates column-chain passes on transposed arrays),
+//     and the single-problem form alternates row- and column-chain passes
+//     on one layout;
 //   * the right-hand side G enters only the column half-step: the row
 //     half-step's output V - G = R - 2p Y_{1/2} needs no G, and the column
 //     half-step adds G to its right-hand side but not to its output.
@@ -147,6 +154,16 @@ struct Small {
   double l1v, abv, prv, prev_r, next_r, pe_before;
 };
 
+// This thread's value of the producer's chunk carries at the unit's
+// positions (two per position, for the first 2 * kChunk threads).
+__device__ __forceinline__ double load_abv(const SweepArgs &a, const Unit &u, const Cols &q,
+                                           int tid) {
+  if (a.tab_prev == nullptr) return 0.0;
+  const int e2 = tid < 2 * kChunk ? tid : 2 * kChunk - 1;
+  if (a.ctab_prev != nullptr) return fused_carry(a, q.sp, q.cp, u.rbase + (e2 >> 1), e2 & 1);
+  return a.ab_prev[(((int64_t)q.sp * a.ncmax + q.cp) * a.npad + u.rbase) * 2 + e2];
+}
+
 template <typename Tin, typename Tg, int kG, bool kPre>
 __device__ __forceinline__ void load_small(const SweepArgs &a, const Unit &u, const Cols &q,
                                            int tid, int w, Small &m) {
@@ -158,15 +175,8 @@ __device__ __forceinline__ void load_small(const SweepArgs &a, const Unit &u, co
     m.tv[k] = tab[(e / kChunk) * ms + (e % kChunk)];
   }
   m.l1v = a.l1[((int64_t)u.s * ncmax + u.c) * kL1 + (tid < kL1 ? tid : kL1 - 1)];
-  m.abv = 0.0;
+  m.abv = load_abv(a, u, q, tid);
   const bool has_prev = a.tab_prev != nullptr;
-  if (has_prev) {
-    const int e2 = tid < 2 * kChunk ? tid : 2 * kChunk - 1;
-    if (a.ctab_prev != nullptr)
-      m.abv = fused_carry(a, q.sp, q.cp, u.rbase + (e2 >> 1), e2 & 1);
-    else
-      m.abv = a.ab_prev[(((int64_t)q.sp * ncmax + q.cp) * npad + u.rbase) * 2 + e2];
-  }
   m.prv = m.prev_r = m.next_r = m.pe_before = 0.0;
   if constexpr (kPre) {
     // The stencil rows of the chunk, and the right-hand side one row before
@@ -220,15 +230,38 @@ __device__ __forceinline__ void load_stream(const SweepArgs &a, const Unit &u, c
   }
 }
 
+// Streaming loads of a row-chain unit (chains are the array's rows): wave w
+// reads rows col0 + w * kSeg + i, one position per lane, so that every
+// instruction moves one 64-position run of a row; compute_store turns the
+// tile around in LDS.
+template <typename Tin>
+__device__ __forceinline__ void load_stream_rows(const SweepArgs &a, const Unit &u, const Cols &q,
+                                                 int lane, int w, double *v) {
+  const Tin *__restrict__ in = (const Tin *)a.in + (q.col0 + (int64_t)w * kSeg) * a.ld + u.rbase + lane;
+#pragma unroll
+  for (int i = 0; i < kSeg; ++i) v[i] = ld_as_double(in + i * a.ld);
+}
+
 // Elimination and store of one unit (lead_sync: synchronize before the LDS
 // early region is written, for a workgroup that reuses its LDS).
-template <typename Tin, typename Tg, typename Tout, int kG, bool kPre>
+template <typename Tin, typename Tg, typename Tout, int kG, bool kPre, bool kTL = false>
 __device__ __forceinline__ void compute_store(const SweepArgs &a, const Unit &u, const Cols &q,
                                               const Small &m, double *v, double *y, double *lds,
                                               int tid, int lane, int w, bool lead_sync) {
   const int64_t ncols = a.ncols, ld = a.ld;
   const bool has_prev = a.tab_prev != nullptr;
   if (lead_sync) __syncthreads();
+  if constexpr (kTL) {
+    // Row chains: wave w holds rows (chains) w * kSeg + i with one position
+    // per lane; after the turnaround lane holds chain `lane` at the
+    // positions of segment w, as in the column-chain pass.
+#pragma unroll
+    for (int i = 0; i < kSeg; ++i) lds[(w * kSeg + i) * (kChunk + 1) + lane] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSeg; ++i) v[i] = lds[lane * (kChunk + 1) + w * kSeg + i];
+    __syncthreads();
+  }
 #pragma unroll
   for (int k = 0; k < kTabLoads; ++k)
     if (tid + k * kThreads < kTabN) lds[OFF_TAB + tid + k * kThreads] = m.tv[k];
@@ -369,14 +402,14 @@ __device__ __forceinline__ void compute_store(const SweepArgs &a, const Unit &u,
         typedef double dbl2v __attribute__((ext_vector_type(2)));
         *(dbl2v *)dst = dbl2v{v0, v1};
       } else {
-        dst[0] = (Tout)v0;
-        dst[1] = (Tout)v1;
+        typedef float flt2v __attribute__((ext_vector_type(2)));
+        *(flt2v *)dst = flt2v{(float)v0, (float)v1};
       }
     }
   }
 }
 
-template <typename Tin, typename Tg, typename Tout, int kG, bool kPre>
+template <typename Tin, typename Tg, typename Tout, int kG, bool kPre, bool kTL = false>
 __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, const int by,
                                             double *lds) {
   const int tid = threadIdx.x;
@@ -387,8 +420,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int bx, co
   Small m;
   load_small<Tin, Tg, kG, kPre>(a, u, q, tid, w, m);
   double v[kSeg], y[kSeg];
-  load_stream<Tin, Tg, kG>(a, u, q, v, y);
-  compute_store<Tin, Tg, Tout, kG, kPre>(a, u, q, m, v, y, lds, tid, lane, w, false);
+  if constexpr (kTL)
+    load_stream_rows<Tin>(a, u, q, lane, w, v);
+  else
+    load_stream<Tin, Tg, kG>(a, u, q, v, y);
+  compute_store<Tin, Tg, Tout, kG, kPre, kTL>(a, u, q, m, v, y, lds, tid, lane, w, false);
 }
 
 // Six wavefronts per SIMD (three workgroups per compute unit) fit every
@@ -405,7 +441,17 @@ __global__ __launch_bounds__(kCols *kWaves, (kPre && kG == 2) ? 4 : 6) void k_sw
     if (a.tab_prev != nullptr && a.ctab_prev == nullptr) a.ab_prev += z * a.abb;
     if (a.ctab_prev != nullptr) a.lv_prev += z * a.lvb;
   }
-  sweep_block<Tin, Tg, Tout, kG, kPre>(a, blockIdx.x, blockIdx.y, lds);
+  sweep_block<Tin, Tg, Tout, kG, kPre>(a, blockIdx.x + a.blk0, blockIdx.y + a.chk0, lds);
+}
+
+// Row-chain sweep (chains along the array's rows, stored in place of the
+// input's layout): the column-chain arithmetic on tiles turned around in
+// LDS on load and on store.  The chunks of a row block run fastest in the
+// grid, so the workgroups in flight together cover whole rows.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kCols *kWaves, 6) void k_sweep_rows(SweepArgs a) {
+  __shared__ double lds[kSweepLds];
+  sweep_block<Tin, double, Tout, 0, false, true>(a, blockIdx.y + a.blk0, blockIdx.x + a.chk0, lds);
 }
 
 // Batched sweep: workgroup g belongs to problem wg_prob[g]; the problem's
@@ -448,8 +494,9 @@ struct SweepLaunch {
   void go() const {
     const int nch = a.nc0 + a.nc1;
     if (d == nullptr) {
-      dim3 grid((unsigned)(a.ncols / kCols), (unsigned)nch,
-                (unsigned)(a.nbatch > 0 ? a.nbatch : 1));
+      const int nbx = a.blk1 > 0 ? a.blk1 - a.blk0 : (int)(a.ncols / kCols);
+      const int nby = a.chk1 > 0 ? a.chk1 - a.chk0 : nch;
+      dim3 grid((unsigned)nbx, (unsigned)nby, (unsigned)(a.nbatch > 0 ? a.nbatch : 1));
       if (ev0 != nullptr)
         hipExtLaunchKernelGGL((k_sweep<Tin, Tg, Tout, kG, kPre>), grid, dim3(kCols * kWaves), 0, st,
                               ev0, ev1, 0, a);
@@ -513,10 +560,20 @@ hipError_t dispatch_sweep(const SweepLaunch &L, bool with_g) {
   return hipGetLastError();
 }
 
+// Chain-block and chunk-row ranges of a single launch: within the array,
+// non-empty when given (blk0 = chk0 = 0 when not).
+static bool ranges_ok(const SweepArgs &a) {
+  const int64_t nbx = a.ncols / kCols, nch = a.nc0 + a.nc1;
+  if (a.blk1 > 0 ? !(a.blk0 >= 0 && a.blk0 < a.blk1 && a.blk1 <= nbx) : a.blk0 != 0) return false;
+  if (a.chk1 > 0 ? !(a.chk0 >= 0 && a.chk0 < a.chk1 && a.chk1 <= nch) : a.chk0 != 0) return false;
+  return true;
+}
+
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const int nchunks = a.nc0 + a.nc1;
   if (a.npad % kCols != 0 || a.ncols % kCols != 0 || nchunks <= 0 || a.in == nullptr)
     return hipErrorInvalidValue;
+  if (!ranges_ok(a)) return hipErrorInvalidValue;
   if (a.ctab_prev != nullptr) {  // carries formed in the sweep: at most two chunks per chain
     if (a.tab_prev == nullptr || a.lv_prev == nullptr || a.ncmax > 2) return hipErrorInvalidValue;
   } else if ((a.ab_prev == nullptr) != (a.tab_prev == nullptr)) {
@@ -529,10 +586,49 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st, hipEvent_t ev0, hipE
   return dispatch_sweep(SweepLaunch{a, nullptr, nullptr, nullptr, 0, st, ev0, ev1}, a.g != nullptr);
 }
 
+hipError_t launch_sweep_rows(const SweepArgs &a0, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int nchunks = a0.nc0 + a0.nc1;
+  if (a0.npad % kCols != 0 || a0.ncols % kCols != 0 || nchunks <= 0 || a0.in == nullptr ||
+      a0.out == nullptr)
+    return hipErrorInvalidValue;
+  if (a0.ncols != a0.npad || a0.ld < a0.npad || a0.ld % 4 != 0) return hipErrorInvalidValue;
+  if (a0.out_mode != 1 && a0.out_mode != 2) return hipErrorInvalidValue;
+  if (a0.g != nullptr || a0.pre != nullptr || a0.nbatch > 1) return hipErrorInvalidValue;
+  if (a0.ctab_prev != nullptr) {
+    if (a0.tab_prev == nullptr || a0.lv_prev == nullptr || a0.ncmax > 2) return hipErrorInvalidValue;
+  } else if ((a0.ab_prev == nullptr) != (a0.tab_prev == nullptr)) {
+    return hipErrorInvalidValue;
+  }
+  if (!ranges_ok(a0)) return hipErrorInvalidValue;
+  SweepArgs a = a0;
+  a.out_mode = a0.out_mode == 1 ? 3 : 0;  // the same outputs, stored along rows
+  const int nbx = a.blk1 > 0 ? a.blk1 - a.blk0 : (int)(a.ncols / kCols);
+  const int nby = a.chk1 > 0 ? a.chk1 - a.chk0 : nchunks;
+  const dim3 grid((unsigned)nby, (unsigned)nbx, 1u);
+  const int code = (a.in_f32 ? 2 : 0) | (a.out_f32 ? 1 : 0);
+#define FPS_ROWS(TI, TO)                                                                         \
+  do {                                                                                           \
+    if (ev0 != nullptr)                                                                          \
+      hipExtLaunchKernelGGL((k_sweep_rows<TI, TO>), grid, dim3(kCols * kWaves), 0, st, ev0, ev1, \
+                            0, a);                                                               \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_sweep_rows<TI, TO>), grid, dim3(kCols * kWaves), 0, st, a);          \
+  } while (0)
+  switch (code) {
+    case 0: FPS_ROWS(double, double); break;
+    case 2: FPS_ROWS(float, double); break;
+    case 3: FPS_ROWS(float, float); break;
+    default: return hipErrorInvalidValue;  // a float output from a double input
+  }
+#undef FPS_ROWS
+  return hipGetLastError();
+}
+
 hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSweep *d,
                               const int *wg_prob, int nwg, char *base, hipStream_t st,
                               int wg_base, hipEvent_t ev0, hipEvent_t ev1) {
   if (nwg <= 0) return hipSuccess;
+  if (types.blk1 != 0 || types.chk1 != 0) return hipErrorInvalidValue;  // whole problems only
   return dispatch_sweep(SweepLaunch{types, d, wg_prob, base, nwg, st, ev0, ev1, wg_base}, with_g);
 }
 

@@ -111,6 +111,32 @@ def test_bitwise_deterministic_and_reusable_workspace():
     assert torch.equal(U1, U2)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_row_parity_streams_equal_one_stream(precision):
+    # Chains of more than two chunks (n > 256): the ADI runs its two
+    # row-parity blocks on two streams; with sweep timing on, every launch
+    # goes to the caller's stream instead.  The same kernels see the same
+    # data either way, so the results agree bit for bit.
+    for n in (300, 1030, 2100):
+        print(f"streams n={n} {precision}", flush=True)
+        p = fps.plan(n, tol=1e-13, precision=precision)
+        F = _dev(workloads.square_rhs(n, seed=3, decay=0.0))
+        U2 = fps.solve(p, F).clone()
+        p.set_sweep_timing(2)
+        U1 = fps.solve(p, F)
+        torch.cuda.synchronize()
+        p.set_sweep_timing(0)
+        assert torch.equal(U1, U2)
+        if precision != "fp64":
+            continue
+        Y2 = fps.adi_native(p, F).clone()
+        p.set_sweep_timing(2)
+        Y1 = fps.adi_native(p, F)
+        torch.cuda.synchronize()
+        p.set_sweep_timing(0)
+        assert torch.equal(Y1, Y2)
+
+
 def test_headline_size_full_parity():
     # n = 4096 (the benchmark workload): full comparison with the oracle.
     n = 4096
