@@ -53,17 +53,56 @@ void release_events(fps_plan *pl) {
   pl->ev_used = 0;
 }
 
-// Runs the 2J half-sweeps of Algorithm 2 with the shifts `sh`, whose step j
-// uses the plan's tables of step base + j.  `Gterm` is the right-hand side G
-// (parity-blocked, npad x npad) of storage type g_f32; O0, O1 are the
-// ping-pong arrays (room for npad^2 doubles each), in G's layout.  With f32 set every step stores its outputs in float (refinement
-// rounds, including the final chunk-local solution: a later round corrects
-// its rounding, and the last round's correction is small), else in double.
-// Leaves the final chunk-local solution in O1 and its chunk carries in ab,
-// to finalize with the tables of the last second half-step
-// (pl->tab2(base + J - 1)).
-fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *Gterm, int g_f32,
-                   int f32, void *O0, void *O1, char *ws, hipStream_t st) {
+// Whether the 2-D plan's solves run their two row-parity blocks on two
+// streams: the plan has its side stream (chains of more than two chunks and
+// both blocks non-empty), and sweep timing (every launch on the caller's
+// stream) is off.
+bool row_split(const fps_plan *pl) {
+  return pl->zside != nullptr && pl->dim == 2 && pl->L.ncmax > 2 && pl->L.m[1] > 0 &&
+         pl->ev.empty();
+}
+
+// Runs body(r0, r1, c0, c1, s, stream) -- a part of a solve restricted to
+// the storage rows r0 .. r1-1 of row-parity block s (chunk rows c0 .. c1-1
+// of that block), returning a hipError_t -- once on the whole array on st,
+// or, with row_split(pl), for block 1 on the plan's side stream and block 0
+// on st.  One solve at a time forks onto the side stream (its event record
+// and wait must not interleave with another host thread's); the join is
+// enqueued whatever the parts returned, so the side stream (or a graph being
+// captured) is never left forked.
+template <typename Body>
+fps_status for_row_blocks(fps_plan *pl, hipStream_t st, Body body) {
+  const fps::Layout &L = pl->L;
+  const int nc0 = (int)L.nc[0], nc1 = (int)L.nc[1];
+  if (!row_split(pl)) {
+    FPS_HIP(body(0, L.npad, 0, nc0 + nc1, 0, st));
+    return FPS_OK;
+  }
+  std::lock_guard<std::mutex> lk(pl->zlock);
+  FPS_HIP(hipEventRecord(pl->zfork, st));
+  FPS_HIP(hipStreamWaitEvent(pl->zside, pl->zfork, 0));
+  const hipError_t e1 = body(L.mp[0], L.npad, nc0, nc0 + nc1, 1, pl->zside);
+  const hipError_t e2 = e1 == hipSuccess ? body(0, L.mp[0], 0, nc0, 0, st) : hipSuccess;
+  const hipError_t e3 = hipEventRecord(pl->zjoin, pl->zside);
+  const hipError_t e4 = e3 == hipSuccess ? hipStreamWaitEvent(st, pl->zjoin, 0) : e3;
+  FPS_HIP(e1);
+  FPS_HIP(e2);
+  FPS_HIP(e3);
+  FPS_HIP(e4);
+  return FPS_OK;
+}
+
+// The J steps of Algorithm 2 (see run_adi) on the storage rows r0 .. r1-1
+// of one row-parity block s (chunk rows c0 .. c1-1 of the second
+// half-steps), or with r0 = 0, r1 = npad on the whole array, enqueued on s2.
+// A~ is block diagonal in the parity-blocked layout, so the rows of one
+// parity block iterate independently of the other block's: the first
+// half-step solves along those rows (chain blocks r0 / 64 ..), the second
+// along every column but only over those rows, and each half-step's carries
+// are those of its own chains and positions.
+hipError_t adi_part(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *Gterm, int g_f32,
+                    int f32, void *O0, void *O1, char *ws, int64_t r0, int64_t r1, int c0, int c1,
+                    int s, hipStream_t s2) {
   const fps::Layout &L = pl->L;
   const int J = sh.J;
   const std::vector<double> &p = sh.p, &q = sh.q;
@@ -76,7 +115,6 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
   // pass).  Longer chains: a carry launch after every half-step (first
   // half-steps' carries into ab2, second ones' into ab).
   const bool fused = L.ncmax <= 2;
-
   fps::SweepArgs A0{};
   A0.npad = L.npad;
   A0.ncols = L.npad;
@@ -88,167 +126,166 @@ fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *
   A0.ncmax = L.ncmax;
   A0.nc0 = nc0;
   A0.nc1 = nc1;
-  // Every array keeps one layout (that of G): half-step 1 solves along its
-  // storage rows (launch_sweep_rows), half-step 2 along its storage columns
-  // (launch_sweep), and both store their outputs in place of their inputs'
-  // layout.
-  // Algorithm 2 for A Y - Y B = G with T1_j = -(B - p_j) (first half-step,
-  // along the columns of Y) and T2_j = A - q_j (second half-step, along the
-  // rows).  Half-step 1: right-hand side R_j = (A - p_j) Y_j - G, solve
-  // Y_{j+1/2} T1_j = R_j, output V_j - G = R_j - (p_j - q_j) Y_{j+1/2}
-  // (V_j = G - Y_{j+1/2}(B - q_j) and Y_{j+1/2}(B - q_j) = -R_j +
-  // (p_j - q_j) Y_{j+1/2}).  Half-step 2: right-hand side V_j = (V_j - G) + G,
-  // solve T2_j Y_{j+1} = V_j, output R_{j+1} = (V_j - G) - (p_{j+1} - q_j)
-  // Y_{j+1}.  So only half-step 2 reads G, and R_0 = -G.  For the square
-  // (q_j = -p_j, T1_j = T2_j = A~ + p_j) the coefficients are 2 p_j and
-  // p_j + p_{j+1}.  After every half-step the chunk carries are resolved,
-  // and the next half-step folds them in.
-  //
-  // A~ is block diagonal in the parity-blocked layout, so the storage rows of
-  // one parity block (rows r0 .. r1-1) iterate independently of the other
-  // block's: the first half-step solves along those rows (chain blocks
-  // r0 / 64 ..), the second along every column but only over those rows (the
-  // chunk rows c0 .. c1-1 of row parity s), and each half-step's carries
-  // are those of its own chains and positions.  `part` runs the J steps of
-  // one such block (or, with the whole ranges, of the array).
-  auto part = [&](int64_t r0, int64_t r1, int c0, int c1, int s, hipStream_t s2) -> hipError_t {
-    const bool whole = r0 == 0 && r1 == L.npad;
-    double sigma_prev = 0.0;
-    for (int j = 0; j < J; ++j) {
-      const double s1 = pl->rect ? p[j] - q[j] : 2.0 * p[j];
-      fps::SweepArgs A = A0;
-      if (!whole) {
-        A.blk0 = (int)(r0 / 64);
-        A.blk1 = (int)(r1 / 64);
-      }
-      A.in = j == 0 ? Gterm : (const void *)O1;
-      A.in_f32 = j == 0 ? g_f32 : f32;
-      A.in_scale = j == 0 ? -1.0 : 1.0;
-      A.ab_prev = j == 0 ? nullptr : ab;
-      A.tab_prev = j == 0 ? nullptr : pl->tab_dev(pl->tab2(base + j - 1));
-      A.tab = pl->tab_dev(pl->tab1(base + j));
-      A.l1 = pl->l1_dev(pl->tab1(base + j));
-      A.sigma = s1;
-      A.out = O0;
-      A.out_f32 = f32;
-      A.out_mode = 2;
-      if (fused && j > 0) {
-        A.ab_prev = nullptr;
-        A.lv_prev = lv2;
-        A.ctab_prev = pl->ctab_dev(pl->tab2(base + j - 1));
-        A.carry_scale = -sigma_prev;
-      }
-      A.lv = lv;
-      hipError_t e = timed_sweep(pl, A, s2, true);
-      if (e == hipSuccess && !fused)
-        e = fps::launch_reduce(lv, pl->ctab_dev(pl->tab1(base + j)), ab2, -A.sigma, L.npad, nc0,
-                               nc1, L.ncmax, s2, 1, 0, 0, r0, r1, 0, 2);
-      if (e != hipSuccess) return e;
-      fps::SweepArgs B = A0;
-      if (!whole) {
-        B.chk0 = c0;
-        B.chk1 = c1;
-      }
-      const bool last = j == J - 1;
-      B.in = O0;
-      B.in_f32 = f32;
-      B.in_scale = 1.0;
-      B.ab_prev = ab2;
-      B.tab_prev = A.tab;
-      if (fused) {
-        B.ab_prev = nullptr;
-        B.lv_prev = lv;
-        B.ctab_prev = pl->ctab_dev(pl->tab1(base + j));
-        B.carry_scale = -A.sigma;
-      }
-      B.lv = lv2;
-      B.g = Gterm;
-      B.g_f32 = g_f32;
-      B.sg = 1.0;
-      B.tab = pl->tab_dev(pl->tab2(base + j));
-      B.l1 = pl->l1_dev(pl->tab2(base + j));
-      B.sigma = last ? 0.0 : (pl->rect ? p[j + 1] - q[j] : p[j] + p[j + 1]);
-      B.out = O1;
-      B.out_f32 = f32;
-      B.out_mode = last ? 1 : 2;
-      e = timed_sweep(pl, B, s2);
-      if (e == hipSuccess && (!fused || last))
-        e = fps::launch_reduce(lv2, pl->ctab_dev(pl->tab2(base + j)), ab, last ? 1.0 : -B.sigma,
-                               L.npad, nc0, nc1, L.ncmax, s2, 1, 0, 0, 0, L.npad,
-                               whole ? 0 : s, whole ? 2 : s + 1);
-      if (e != hipSuccess) return e;
-      sigma_prev = B.sigma;
+  const bool whole = r0 == 0 && r1 == L.npad;
+  double sigma_prev = 0.0;
+  for (int j = 0; j < J; ++j) {
+    const double s1 = pl->rect ? p[j] - q[j] : 2.0 * p[j];
+    fps::SweepArgs A = A0;
+    if (!whole) {
+      A.blk0 = (int)(r0 / 64);
+      A.blk1 = (int)(r1 / 64);
     }
-    return hipSuccess;
-  };
-  // Two streams for the two row-parity blocks when the plan has its side
-  // stream (chains of more than two chunks, both blocks non-empty), unless
-  // every sweep is being timed on the caller's stream.
-  if (pl->zside == nullptr || fused || L.m[1] == 0 || !pl->ev.empty()) {
-    FPS_HIP(part(0, L.npad, 0, nc0 + nc1, 0, st));
-    return FPS_OK;
+    A.in = j == 0 ? Gterm : (const void *)O1;
+    A.in_f32 = j == 0 ? g_f32 : f32;
+    A.in_scale = j == 0 ? -1.0 : 1.0;
+    A.ab_prev = j == 0 ? nullptr : ab;
+    A.tab_prev = j == 0 ? nullptr : pl->tab_dev(pl->tab2(base + j - 1));
+    A.tab = pl->tab_dev(pl->tab1(base + j));
+    A.l1 = pl->l1_dev(pl->tab1(base + j));
+    A.sigma = s1;
+    A.out = O0;
+    A.out_f32 = f32;
+    A.out_mode = 2;
+    if (fused && j > 0) {
+      A.ab_prev = nullptr;
+      A.lv_prev = lv2;
+      A.ctab_prev = pl->ctab_dev(pl->tab2(base + j - 1));
+      A.carry_scale = -sigma_prev;
+    }
+    A.lv = lv;
+    hipError_t e = timed_sweep(pl, A, s2, true);
+    if (e == hipSuccess && !fused)
+      e = fps::launch_reduce(lv, pl->ctab_dev(pl->tab1(base + j)), ab2, -A.sigma, L.npad, nc0,
+                             nc1, L.ncmax, s2, 1, 0, 0, r0, r1, 0, 2);
+    if (e != hipSuccess) return e;
+    fps::SweepArgs B = A0;
+    if (!whole) {
+      B.chk0 = c0;
+      B.chk1 = c1;
+    }
+    const bool last = j == J - 1;
+    B.in = O0;
+    B.in_f32 = f32;
+    B.in_scale = 1.0;
+    B.ab_prev = ab2;
+    B.tab_prev = A.tab;
+    if (fused) {
+      B.ab_prev = nullptr;
+      B.lv_prev = lv;
+      B.ctab_prev = pl->ctab_dev(pl->tab1(base + j));
+      B.carry_scale = -A.sigma;
+    }
+    B.lv = lv2;
+    B.g = Gterm;
+    B.g_f32 = g_f32;
+    B.sg = 1.0;
+    B.tab = pl->tab_dev(pl->tab2(base + j));
+    B.l1 = pl->l1_dev(pl->tab2(base + j));
+    B.sigma = last ? 0.0 : (pl->rect ? p[j + 1] - q[j] : p[j] + p[j + 1]);
+    B.out = O1;
+    B.out_f32 = f32;
+    B.out_mode = last ? 1 : 2;
+    e = timed_sweep(pl, B, s2);
+    if (e == hipSuccess && (!fused || last))
+      e = fps::launch_reduce(lv2, pl->ctab_dev(pl->tab2(base + j)), ab, last ? 1.0 : -B.sigma,
+                             L.npad, nc0, nc1, L.ncmax, s2, 1, 0, 0, 0, L.npad,
+                             whole ? 0 : s, whole ? 2 : s + 1);
+    if (e != hipSuccess) return e;
+    sigma_prev = B.sigma;
   }
-  // One solve at a time forks onto the side stream (its event record and
-  // wait must not interleave with another host thread's); the join is
-  // enqueued whatever the parts returned, so the side stream (or a graph
-  // being captured) is never left forked.
-  std::lock_guard<std::mutex> lk(pl->zlock);
-  FPS_HIP(hipEventRecord(pl->zfork, st));
-  FPS_HIP(hipStreamWaitEvent(pl->zside, pl->zfork, 0));
-  const hipError_t e1 = part(L.mp[0], L.npad, nc0, nc0 + nc1, 1, pl->zside);
-  const hipError_t e2 = e1 == hipSuccess ? part(0, L.mp[0], 0, nc0, 0, st) : hipSuccess;
-  const hipError_t e3 = hipEventRecord(pl->zjoin, pl->zside);
-  const hipError_t e4 = e3 == hipSuccess ? hipStreamWaitEvent(st, pl->zjoin, 0) : e3;
-  FPS_HIP(e1);
-  FPS_HIP(e2);
-  FPS_HIP(e3);
-  FPS_HIP(e4);
-  return FPS_OK;
+  return hipSuccess;
+}
+
+// Runs the 2J half-sweeps of Algorithm 2 with the shifts `sh`, whose step j
+// uses the plan's tables of step base + j.  `Gterm` is the right-hand side G
+// (parity-blocked, npad x npad) of storage type g_f32; O0, O1 are the
+// ping-pong arrays (room for npad^2 doubles each), in G's layout.  With f32 set every step stores its outputs in float (refinement
+// rounds, including the final chunk-local solution: a later round corrects
+// its rounding, and the last round's correction is small), else in double.
+// Leaves the final chunk-local solution in O1 and its chunk carries in ab,
+// to finalize with the tables of the last second half-step
+// (pl->tab2(base + J - 1)).
+//
+// Every array keeps one layout (that of G): half-step 1 solves along its
+// storage rows (launch_sweep_rows), half-step 2 along its storage columns
+// (launch_sweep), and both store their outputs in place of their inputs'
+// layout.
+// Algorithm 2 for A Y - Y B = G with T1_j = -(B - p_j) (first half-step,
+// along the columns of Y) and T2_j = A - q_j (second half-step, along the
+// rows).  Half-step 1: right-hand side R_j = (A - p_j) Y_j - G, solve
+// Y_{j+1/2} T1_j = R_j, output V_j - G = R_j - (p_j - q_j) Y_{j+1/2}
+// (V_j = G - Y_{j+1/2}(B - q_j) and Y_{j+1/2}(B - q_j) = -R_j +
+// (p_j - q_j) Y_{j+1/2}).  Half-step 2: right-hand side V_j = (V_j - G) + G,
+// solve T2_j Y_{j+1} = V_j, output R_{j+1} = (V_j - G) - (p_{j+1} - q_j)
+// Y_{j+1}.  So only half-step 2 reads G, and R_0 = -G.  For the square
+// (q_j = -p_j, T1_j = T2_j = A~ + p_j) the coefficients are 2 p_j and
+// p_j + p_{j+1}.  After every half-step the chunk carries are resolved,
+// and the next half-step folds them in.
+fps_status run_adi(fps_plan *pl, const fps::ShiftSet &sh, int base, const void *Gterm, int g_f32,
+                   int f32, void *O0, void *O1, char *ws, hipStream_t st) {
+  return for_row_blocks(pl, st, [&](int64_t r0, int64_t r1, int c0, int c1, int s, hipStream_t s2) {
+    return adi_part(pl, sh, base, Gterm, g_f32, f32, O0, O1, ws, r0, r1, c0, c1, s, s2);
+  });
 }
 
 // The symmetric-form solution Y (parity-blocked FP64, npad x npad) of
-// A~ Y + Y A~ = G for G in ws.G: plain FP64 ADI, or
-// iterative refinement whose inner ADIs store their sweep arrays in float.
-// Returns Y's location.
-fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout) {
+// A~ Y + Y A~ = G for G in ws.G, on the rows r0 .. r1-1 of row-parity block
+// s (see adi_part; the whole array with r0 = 0, r1 = npad): plain FP64 ADI
+// (Y left in G), or iterative refinement whose inner ADIs store their sweep
+// arrays in float (Y in the GT region).  A~ is block diagonal, so the
+// residual of a row block needs only that block's rows.
+hipError_t symmetric_part(fps_plan *pl, char *w, int64_t r0, int64_t r1, int c0, int c1, int s,
+                          hipStream_t s2) {
   const fps::Layout &L = pl->L;
   double *G = (double *)(w + pl->off_G);
   double *ab = (double *)(w + pl->off_ab);
-  fps_status s;
+  hipError_t e;
   if (pl->prec == FPS_FP64) {
     const int J = pl->shifts.J;
-    if ((s = run_adi(pl, pl->shifts, 0, G, 0, 0, w + pl->off_O0, w + pl->off_O1, w, st)) != FPS_OK)
-      return s;
-    FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, pl->tab_dev(pl->tab2(J - 1)),
-                                         G, 0, nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax,
-                                         st));
-    *Yout = G;  // G is no longer needed
-    return FPS_OK;
+    e = adi_part(pl, pl->shifts, 0, G, 0, 0, w + pl->off_O0, w + pl->off_O1, w, r0, r1, c0, c1, s,
+                 s2);
+    if (e != hipSuccess) return e;
+    return fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab,
+                                        pl->tab_dev(pl->tab2(J - 1)), G, 0, nullptr, L.n, L.npad,
+                                        L.mp[0], L.mstride, L.ncmax, s2, r0, r1);
   }
   // Refinement: Y <- Y + ADI_k(G - (A~ Y + Y A~)) for the rounds k; the
-  // residual is formed in FP64 and stored in float (with its transpose),
-  // and the inner sweeps of a float round store their arrays in float.
+  // residual is formed in FP64 and stored in float, and the inner sweeps of
+  // a float round store their arrays in float.
   double *Y = (double *)(w + pl->off_GT);
   float *r = (float *)(w + pl->off_R);
   for (int k = 0; k < pl->rounds; ++k) {
     const fps::ShiftSet &sh = pl->rsh[(size_t)k];
     const int f32 = pl->rf32[(size_t)k];
     const double *tab = pl->tab_dev(pl->tab2(pl->rbase[(size_t)k] + sh.J - 1));
-    FPS_HIP(fps::launch_residual(G, k == 0 ? nullptr : Y, (const double *)pl->d_sdiag.p,
-                                 (const double *)pl->d_soff.p, r, nullptr, L.npad, st, pl->sx2,
-                                 pl->sy2));
-    if ((s = run_adi(pl, sh, pl->rbase[(size_t)k], r, 1, f32, w + pl->off_O0, w + pl->off_O1, w,
-                     st)) != FPS_OK)
-      return s;
+    void *O0 = w + pl->off_O0, *O1 = w + pl->off_O1;
+    e = fps::launch_residual(G, k == 0 ? nullptr : Y, (const double *)pl->d_sdiag.p,
+                             (const double *)pl->d_soff.p, r, nullptr, L.npad, s2, pl->sx2,
+                             pl->sy2, r0, r1);
+    if (e == hipSuccess)
+      e = adi_part(pl, sh, pl->rbase[(size_t)k], r, 1, f32, O0, O1, w, r0, r1, c0, c1, s, s2);
+    if (e != hipSuccess) return e;
     const int mode = k == 0 ? 0 : 2;
     if (f32)
-      FPS_HIP(fps::launch_finalize<float>((const float *)(w + pl->off_O1), ab, tab, Y, mode,
-                                          nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
+      e = fps::launch_finalize<float>((const float *)O1, ab, tab, Y, mode, nullptr, L.n, L.npad,
+                                      L.mp[0], L.mstride, L.ncmax, s2, r0, r1);
     else
-      FPS_HIP(fps::launch_finalize<double>((const double *)(w + pl->off_O1), ab, tab, Y, mode,
-                                           nullptr, L.n, L.npad, L.mp[0], L.mstride, L.ncmax, st));
+      e = fps::launch_finalize<double>((const double *)O1, ab, tab, Y, mode, nullptr, L.n, L.npad,
+                                       L.mp[0], L.mstride, L.ncmax, s2, r0, r1);
+    if (e != hipSuccess) return e;
   }
-  *Yout = Y;
+  return hipSuccess;
+}
+
+// Y of A~ Y + Y A~ = G for G in ws.G (both row-parity blocks, on two streams
+// when the plan splits them).  Returns Y's location.
+fps_status solve_symmetric(fps_plan *pl, char *w, hipStream_t st, double **Yout) {
+  const fps_status s =
+      for_row_blocks(pl, st, [&](int64_t r0, int64_t r1, int c0, int c1, int sp, hipStream_t s2) {
+        return symmetric_part(pl, w, r0, r1, c0, c1, sp, s2);
+      });
+  if (s != FPS_OK) return s;
+  *Yout = (double *)(w + (pl->prec == FPS_FP64 ? pl->off_G : pl->off_GT));
   return FPS_OK;
 }
 

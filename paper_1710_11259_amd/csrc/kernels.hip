@@ -43,9 +43,9 @@ template <typename T>
 __global__ void k_finalize(const T *__restrict__ x, const double *__restrict__ ab,
                            const double *__restrict__ tab, double *__restrict__ out, int mode,
                            const double *__restrict__ sinv, int64_t n, int64_t npad, int64_t mp0,
-                           int64_t mstride, int64_t ncmax) {
+                           int64_t mstride, int64_t ncmax, int64_t r0) {
   finalize_at<T>(x, ab, tab, out, mode, sinv, n, npad, mp0, mstride, ncmax,
-                 (int64_t)blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+                 (int64_t)blockIdx.x * blockDim.x + threadIdx.x, r0 + blockIdx.y);
 }
 
 // 64 x 64 tile (column tile bx, row tile by) of the residual; 256 threads.
@@ -66,10 +66,12 @@ __device__ __forceinline__ void residual_tile(const double *__restrict__ G,
     if (Y != nullptr) {
       const double *y = Y + i * npad + q;
       const double yc = y[0];
-      const double yu = i > 0 ? y[-npad] : 0.0, yd = i + 1 < npad ? y[npad] : 0.0;
+      // rows across a parity-block boundary (zero coupling) are not read:
+      // the two row-parity blocks may be computed concurrently
+      const double eil = i > 0 ? ev[i - 1] : 0.0, ei = ev[i];
+      const double yu = eil != 0.0 ? y[-npad] : 0.0, yd = ei != 0.0 ? y[npad] : 0.0;
       const double yl = q > 0 ? y[-1] : 0.0, yr = q + 1 < npad ? y[1] : 0.0;
-      const double eil = i > 0 ? ev[i - 1] : 0.0;
-      res -= ax * (dv[i] * yc + eil * yu + ev[i] * yd) + ay * (dq * yc + eql * yl + eq * yr);
+      res -= ax * (dv[i] * yc + eil * yu + ei * yd) + ay * (dq * yc + eql * yl + eq * yr);
     }
     r[i * npad + q] = (float)res;
     tile[rr][tx] = (float)res;
@@ -84,9 +86,9 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ G,
                                                   const double *__restrict__ dv,
                                                   const double *__restrict__ ev,
                                                   float *__restrict__ r, float *__restrict__ rT,
-                                                  int64_t npad, double ax, double ay) {
+                                                  int64_t npad, double ax, double ay, int64_t by0) {
   __shared__ float tile[64][65];
-  residual_tile(G, Y, dv, ev, r, rT, npad, ax, ay, blockIdx.x, blockIdx.y, tile);
+  residual_tile(G, Y, dv, ev, r, rT, npad, ax, ay, blockIdx.x, by0 + blockIdx.y, tile);
 }
 
 __global__ void k_permute_out(const double *__restrict__ src, double *__restrict__ dst, int64_t n,
@@ -477,25 +479,33 @@ hipError_t launch_cube_ifinal(const double *x, const double *ab, const double *t
 template <typename T>
 hipError_t launch_finalize(const T *x, const double *ab, const double *tab, double *out, int mode,
                            const double *sinv, int64_t n, int64_t npad, int64_t mp0,
-                           int64_t mstride, int64_t ncmax, hipStream_t st) {
-  dim3 grid((unsigned)((npad + 255) / 256), (unsigned)npad);
+                           int64_t mstride, int64_t ncmax, hipStream_t st, int64_t r0, int64_t r1) {
+  if (r1 < 0) r1 = npad;
+  if (r0 < 0 || r1 > npad) return hipErrorInvalidValue;
+  if (r0 >= r1) return hipSuccess;
+  dim3 grid((unsigned)((npad + 255) / 256), (unsigned)(r1 - r0));
   hipLaunchKernelGGL(k_finalize<T>, grid, dim3(256), 0, st, x, ab, tab, out, mode, sinv, n, npad,
-                     mp0, mstride, ncmax);
+                     mp0, mstride, ncmax, r0);
   return hipGetLastError();
 }
 template hipError_t launch_finalize<double>(const double *, const double *, const double *, double *,
                                             int, const double *, int64_t, int64_t, int64_t, int64_t,
-                                            int64_t, hipStream_t);
+                                            int64_t, hipStream_t, int64_t, int64_t);
 template hipError_t launch_finalize<float>(const float *, const double *, const double *, double *,
                                            int, const double *, int64_t, int64_t, int64_t, int64_t,
-                                           int64_t, hipStream_t);
+                                           int64_t, hipStream_t, int64_t, int64_t);
 
 hipError_t launch_residual(const double *G, const double *Y, const double *dv, const double *ev,
                            float *r, float *rT, int64_t npad, hipStream_t st, double ax,
-                           double ay) {
-  if (npad % 64 != 0) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(npad / 64), (unsigned)(npad / 64));
-  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, st, G, Y, dv, ev, r, rT, npad, ax, ay);
+                           double ay, int64_t r0, int64_t r1) {
+  if (r1 < 0) r1 = npad;
+  if (npad % 64 != 0 || r0 % 64 != 0 || r1 % 64 != 0 || r0 < 0 || r1 > npad)
+    return hipErrorInvalidValue;
+  if (r0 >= r1) return hipSuccess;
+  if (rT != nullptr && (r0 != 0 || r1 != npad)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(npad / 64), (unsigned)((r1 - r0) / 64));
+  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, st, G, Y, dv, ev, r, rT, npad, ax, ay,
+                     r0 / 64);
   return hipGetLastError();
 }
 

@@ -148,19 +148,23 @@ hipError_t launch_reduce_batch(const BatchReduce *d, const int *wg_prob, int nwg
 // mode 1: write the natural-order n x n array, entry (i,j) times
 //         sinv_i * sinv_j when `sinv` is non-null;
 // mode 2: add Y into the parity-blocked FP64 array `out`.
+// Only the parity-blocked rows r0 .. r1-1 (r1 < 0: all) are finalized.
 template <typename T>
 hipError_t launch_finalize(const T *x, const double *ab, const double *tab, double *out, int mode,
                            const double *sinv, int64_t n, int64_t npad, int64_t mp0,
-                           int64_t mstride, int64_t ncmax, hipStream_t st);
+                           int64_t mstride, int64_t ncmax, hipStream_t st, int64_t r0 = 0,
+                           int64_t r1 = -1);
 
 // Residual of the symmetric Sylvester equation in the parity-blocked layout,
 // r = G - (A~ Y + Y A~) (Y null: r = G), in FP64, stored in float as r and,
 // with rT non-null, r^T.  A~ acts along each parity block as a tridiagonal stencil with
 // diagonal dv[] and coupling ev[] (ev[k] couples positions k and k+1).
 // For a rectangle the operator is ax A~ Y + ay Y A~ (ax = sx2, ay = sy2).
+// Only the rows r0 .. r1-1 (multiples of 64; r1 < 0: all) are formed (rT
+// only with all rows); rows across a zero coupling are not read.
 hipError_t launch_residual(const double *G, const double *Y, const double *dv, const double *ev,
                            float *r, float *rT, int64_t npad, hipStream_t st, double ax = 1.0,
-                           double ay = 1.0);
+                           double ay = 1.0, int64_t r0 = 0, int64_t r1 = -1);
 
 // natural n x n (ld n) -> parity-blocked npad x npad (zero padding); with
 // `sinv` non-null, entry (i, j) is multiplied by sinv[i] * sinv[j].

@@ -111,15 +111,19 @@ def test_bitwise_deterministic_and_reusable_workspace():
     assert torch.equal(U1, U2)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
-def test_row_parity_streams_equal_one_stream(precision):
-    # Chains of more than two chunks (n > 256): the ADI runs its two
-    # row-parity blocks on two streams; with sweep timing on, every launch
-    # goes to the caller's stream instead.  The same kernels see the same
-    # data either way, so the results agree bit for bit.
+@pytest.mark.parametrize("precision,out,box", [("fp64", "cheb", None),
+                                               ("fp32_refined", "cheb", None),
+                                               ("fp64", "native", None),
+                                               ("fp32_refined", "native", None),
+                                               ("fp64", "cheb", (0.0, 2.5, -1.0, 0.25))])
+def test_row_parity_streams_equal_one_stream(precision, out, box):
+    # Chains of more than two chunks (n > 256): a solve runs its two
+    # row-parity blocks (the ADI, or the refinement rounds) on two streams;
+    # with sweep timing on, every launch goes to the caller's stream instead.  The same kernels see the same data either way, so the
+    # results agree bit for bit.
     for n in (300, 1030, 2100):
-        print(f"streams n={n} {precision}", flush=True)
-        p = fps.plan(n, tol=1e-13, precision=precision)
+        print(f"streams n={n} {precision} {out} box={box}", flush=True)
+        p = fps.plan(n, tol=1e-13, precision=precision, out=out, box=box)
         F = _dev(workloads.square_rhs(n, seed=3, decay=0.0))
         U2 = fps.solve(p, F).clone()
         p.set_sweep_timing(2)
@@ -127,7 +131,7 @@ def test_row_parity_streams_equal_one_stream(precision):
         torch.cuda.synchronize()
         p.set_sweep_timing(0)
         assert torch.equal(U1, U2)
-        if precision != "fp64":
+        if precision != "fp64" or out != "cheb" or box is not None:
             continue
         Y2 = fps.adi_native(p, F).clone()
         p.set_sweep_timing(2)
