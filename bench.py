@@ -25,9 +25,9 @@ FP64_MFMA_PEAK_TFLOPS = 78.6  # dense FP64 matrix peak of MI355X
 # (sweep.hip) with this sha256 (the counters were taken on the same device
 # code).
 SWEEP_SOURCES = ("sweep.hip",)
-SWEEP_TRAFFIC = {"sha256": "19b1d2ca50672f539ebec0e6026583baacd03a6896469529490e16a068070fb8",
-                 4096: {"half_step_1": 278.2e6, "half_step_2": 413.0e6},
-                 10000: {"half_step_1": 1748.1e6, "half_step_2": 2529.8e6}}
+SWEEP_TRAFFIC = {"sha256": "cc592ed32081659ae804d8899a39e499d25960ffbd0898cb8118b1649c5567ad",
+                 4096: {"half_step_1": 277.6e6, "half_step_2": 413.0e6},
+                 10000: {"half_step_1": 1764.2e6, "half_step_2": 2529.7e6}}
 
 
 def sweep_sources_sha():
@@ -739,7 +739,9 @@ def main() -> int:
                                  "half_step_2": round(b2 / t2 / 1e9, 1)},
                 "launches_timed": len(sweep_list),
                 "timing": "HIP events recording each sweep dispatch's start and end "
-                          "(hipExtLaunchKernelGGL), separate pass of the same solves "
+                          "(hipExtLaunchKernelGGL), separate pass of the same solves with "
+                          "every launch on one stream (the timed solves run the two "
+                          "row-parity blocks on two streams, half the chains per launch) "
                           f"({instr_ms / args.steps:.2f} ms per solve with the events)",
                 "sweep_share_of_step": round(sum(sweep_list) / instr_ms, 4)}
     # Beside the sweep roofline: the rate a plain copy kernel achieves, and the

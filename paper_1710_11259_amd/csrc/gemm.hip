@@ -16,7 +16,8 @@ namespace {
 // contiguous, lda), B row-major (n contiguous, ldb), C(i, j) at
 // C[i*ldci + j*ldcj].  Tile 128 x 128 x 16, four wavefronts in a 2 x 2
 // grid, each computing a 64 x 64 quarter as 4 x 4 MFMA blocks; the next
-// k-tile is fetched into registers while the current one is multiplied.
+// k-tile is fetched into registers while the current one is multiplied, and
+// stashed into the second of two LDS stages.
 // Operand layout of the 16x16x4 f64 instruction: lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r of lane l
 // holds C[4r + l / 16][l % 16].
@@ -64,8 +65,12 @@ __host__ __device__ inline void tile_krange(const GemmProb &g, int bx, int by, i
 }
 
 // One 128 x 128 output tile (column tile bx, row tile by) of problem g.
+// Two LDS stages (As, Bs and As2, Bs2): the next k-tile is stashed into the
+// stage not being read, so one barrier per k-tile suffices (68 KB of LDS, two
+// workgroups per compute unit).
 __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const int by,
-                                          double (*As)[GBK + 1], double (*Bs)[GBN + GPAD]) {
+                                          double (*As)[GBK + 1], double (*Bs)[GBN + GPAD],
+                                          double (*As2)[GBK + 1], double (*Bs2)[GBN + GPAD]) {
   const int64_t i0 = (int64_t)by * GBM, j0 = (int64_t)bx * GBN;
   if (i0 >= g.M || j0 >= g.N) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -103,14 +108,15 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
   // A is kept row-major in LDS ([row][k], one double of padding): the
   // stash writes each thread's k-run in place and the fragment reads
   // (16 rows at one k per quarter-wave) hit distinct banks.
-  auto stash = [&]() {
+  auto stash_to = [&](double (*Ad)[GBK + 1], double (*Bd)[GBN + GPAD]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      As[ar][ak + 2 * q] = az * ra[q].x;
-      As[ar][ak + 2 * q + 1] = az * ra[q].y;
-      *(dbl2 *)&Bs[bk][bc + 2 * q] = rb[q];
+      Ad[ar][ak + 2 * q] = az * ra[q].x;
+      Ad[ar][ak + 2 * q + 1] = az * ra[q].y;
+      *(dbl2 *)&Bd[bk][bc + 2 * q] = rb[q];
     }
   };
+
 
   dbl4 acc[4][4];
 #pragma unroll
@@ -125,40 +131,46 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
   const int na = mrem >= 64 ? 4 : mrem <= 0 ? 0 : (int)((mrem + 15) / 16);
   const int nb = nrem >= 64 ? 4 : nrem <= 0 ? 0 : (int)((nrem + 15) / 16);
   const bool full = na == 4 && nb == 4;
+  // the products of one k-tile from the stage (Ar, Br)
+  auto mma = [&](double (*Ar)[GBK + 1], double (*Br)[GBN + GPAD]) {
+#pragma unroll
+    for (int ks = 0; ks < GBK; ks += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = Ar[wy * 64 + a * 16 + (lane & 15)][ks + (lane >> 4)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Br[ks + (lane >> 4)][wx * 64 + b * 16 + (lane & 15)];
+      if (full) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (a < na && b < nb)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+  };
   if (klo < khi) {
     fetch(klo);
-    stash();
+    stash_to(As, Bs);
     __syncthreads();
-    for (int64_t k0 = klo; k0 < khi; k0 += GBK) {
+    // stage s is read in k-tile t while stage 1 - s receives tile t + 1; the
+    // barrier after the stash orders both the stash before the next tile's
+    // reads and this tile's reads before the stash that follows
+    int t = 0;
+    for (int64_t k0 = klo; k0 < khi; k0 += GBK, ++t) {
       const bool more = k0 + GBK < khi;
       if (more) fetch(k0 + GBK);
-#pragma unroll
-      for (int ks = 0; ks < GBK; ks += 4) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = As[wy * 64 + a * 16 + (lane & 15)][ks + (lane >> 4)];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = Bs[ks + (lane >> 4)][wx * 64 + b * 16 + (lane & 15)];
-        if (full) {
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-        } else {
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-              if (a < na && b < nb)
-                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-        }
-      }
+      const bool odd = (t & 1) != 0;
+      mma(odd ? As2 : As, odd ? Bs2 : Bs);
+      if (more) stash_to(odd ? As : As2, odd ? Bs : Bs2);
       __syncthreads();
-      if (more) {
-        stash();
-        __syncthreads();
-      }
     }
   }
 #pragma unroll
@@ -174,8 +186,8 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
 }
 
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmBatch batch) {
-  __shared__ double As[GBM][GBK + 1];
-  __shared__ double Bs[GBK][GBN + GPAD];
+  __shared__ double As[GBM][GBK + 1], As2[GBM][GBK + 1];
+  __shared__ double Bs[GBK][GBN + GPAD], Bs2[GBK][GBN + GPAD];
   int bx = blockIdx.x, by = blockIdx.y, z = blockIdx.z;
   if (batch.order != 0) {
     const int nt = gridDim.x, mt = gridDim.y, nz = gridDim.z;
@@ -192,7 +204,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmBatch batch) {
       bx = rem % nt;
     }
   }
-  gemm_tile(batch.p[z], bx, by, As, Bs);
+  gemm_tile(batch.p[z], bx, by, As, Bs, As2, Bs2);
 }
 
 // Table-driven GEMM: workgroup g computes tile (local % ntx, local / ntx),
@@ -206,8 +218,8 @@ __device__ __forceinline__ const double *rebase(const double *p, int id, char *w
 __global__ __launch_bounds__(256, 2) void k_gemm_table(const GemmDesc *__restrict__ d,
                                                        const int *__restrict__ tile_map, char *ws,
                                                        char *out) {
-  __shared__ double As[GBM][GBK + 1];
-  __shared__ double Bs[GBK][GBN + GPAD];
+  __shared__ double As[GBM][GBK + 1], As2[GBM][GBK + 1];
+  __shared__ double Bs[GBK][GBN + GPAD], Bs2[GBK][GBN + GPAD];
   const int k = __builtin_amdgcn_readfirstlane(tile_map[2 * blockIdx.x]);
   const int local = __builtin_amdgcn_readfirstlane(tile_map[2 * blockIdx.x + 1]);
   const GemmDesc &e = d[k];
@@ -215,7 +227,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_table(const GemmDesc *__restric
   g.A = rebase(g.A, e.abase, ws, out);
   g.B = rebase(g.B, e.bbase, ws, out);
   g.C = (double *)rebase(g.C, e.cbase, ws, out);
-  gemm_tile(g, local % e.ntx, local / e.ntx, As, Bs);
+  gemm_tile(g, local % e.ntx, local / e.ntx, As, Bs, As2, Bs2);
 }
 
 // Columns tn.. of every row of a table problem: one wavefront per row,
