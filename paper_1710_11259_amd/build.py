@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfps.so")
-SOURCES = ["planner.cpp", "sweep.hip", "reduce.hip", "gemm.hip", "kernels.hip", "api.cpp", "batch.cpp", "cube.cpp",
+SOURCES = ["planner.cpp", "sweep.hip", "zeig_lds.hip", "reduce.hip", "gemm.hip", "kernels.hip", "api.cpp", "batch.cpp", "cube.cpp",
            "lift.hip", "cylinder.cpp", "cyl.hip", "noalloc.hip",
            "probe.hip"]
 ARCH = os.environ.get("FPS_OFFLOAD_ARCH", "gfx950")

@@ -658,7 +658,7 @@ fps_status zeig_common(fps_plan *pl) {
   pl->off_G = 0;      // G^ (eigen-z slices, [c][y][x])
   pl->off_ZR = vol;   // Y^
   pl->off_RX = 2 * vol;
-  pl->off_RXT = 3 * vol;  // G^ transposed per slice
+  pl->off_RXT = 3 * vol;  // refined plans: transposed float slice arrays
   pl->off_O0 = 4 * vol;
   pl->off_O1 = 5 * vol;
   pl->off_lv = 6 * vol;
@@ -931,8 +931,12 @@ fps_status zeig_upload(fps_plan *pl) {
       const bool last = j == pl->zJ[k] - 1;
       const double pj = pl->zp[(size_t)t1 / 2], qj = pl->zq[(size_t)t1 / 2];
       const double pn = last ? 0.0 : pl->zp[(size_t)t1 / 2 + 1];
+      // Every slice array keeps G^'s layout ([y][x]): the x solve runs along
+      // the storage rows (batched row-chain sweep, out_mode 0: the row-wise
+      // store of v - sigma x), the y solve along the storage columns, stored
+      // in place (out_mode 2; 1 at the last step).
       fps::SweepArgs a1 = A;
-      a1.in = (const void *)(intptr_t)((j == 0 ? pl->off_RXT : pl->off_O1) + so);
+      a1.in = (const void *)(intptr_t)((j == 0 ? pl->off_G : pl->off_O1) + so);
       a1.in_scale = 1.0;
       a1.ab_prev = j == 0 ? nullptr : (const double *)(intptr_t)abo;
       a1.tab_prev = j == 0 ? nullptr : pl->tab_dev(t1 - 1);
@@ -957,7 +961,7 @@ fps_status zeig_upload(fps_plan *pl) {
       a2.l1 = pl->l1_dev(t2);
       a2.sigma = last ? 0.0 : qj - pn;
       a2.out = (void *)(intptr_t)(pl->off_O1 + so);
-      a2.out_mode = last ? 1 : 0;
+      a2.out_mode = last ? 1 : 2;
       if (fused) {  // carries from the producer's boundary values, no carry launch
         a2.lv = (double *)(intptr_t)lvo2;
         if (j > 0) {
@@ -1002,6 +1006,50 @@ fps_status zeig_upload(fps_plan *pl) {
       (s = upload(pl->d_zfin, fin)) != FPS_OK ||
       (fused && (s = upload(pl->d_zrdfin, rdfin)) != FPS_OK))
     return s;
+  // The LDS-resident form: per sorted slice its storage slice, steps, first
+  // table, mu and the sigmas of its steps (those of the descriptors above),
+  // then every storage slice without steps.
+  pl->zlds = fps::zeig_lds_fits(L.m[0], L.m[1]) && L.mp[0] <= 128 && npad - L.mp[0] <= 128 &&
+             L.mstride % fps::kZeigLdsChunk == 0;
+  if (pl->zlds) {
+    std::vector<int> zs, zj, zt, zo;
+    std::vector<double> zm, sg;
+    std::vector<char> seen((size_t)npad, 0);
+    for (int k = 0; k < K; ++k) {
+      zs.push_back(pl->zslice[k]);
+      zj.push_back(pl->zJ[k]);
+      zt.push_back(pl->ztab0[k]);
+      zo.push_back((int)sg.size());
+      zm.push_back(pl->zmu[k]);
+      seen[(size_t)pl->zslice[k]] = 1;
+      for (int j = 0; j < pl->zJ[k]; ++j) {
+        int t1, t2;
+        zeig_tables_of(pl, k, j, &t1, &t2);
+        const bool last = j == pl->zJ[k] - 1;
+        const double pj = pl->zp[(size_t)t1 / 2], qj = pl->zq[(size_t)t1 / 2];
+        const double pn = last ? 0.0 : pl->zp[(size_t)t1 / 2 + 1];
+        sg.push_back(pj - qj);
+        sg.push_back(last ? 0.0 : qj - pn);
+      }
+    }
+    for (int64_t c = 0; c < npad; ++c)
+      if (!seen[(size_t)c]) {
+        zs.push_back((int)c);
+        zj.push_back(0);
+        zt.push_back(0);
+        zo.push_back(0);
+        zm.push_back(0.0);
+      }
+    if (sg.empty()) sg.push_back(0.0);
+    std::vector<double> t32, c32;  // multipliers of the kernel's chunks
+    fps::build_chunk_tables(L, pl->tab, fps::kZeigLdsChunk, t32, c32);
+    if ((s = upload(pl->d_zl_slice, zs)) != FPS_OK || (s = upload(pl->d_zl_J, zj)) != FPS_OK ||
+        (s = upload(pl->d_zl_tab0, zt)) != FPS_OK || (s = upload(pl->d_zl_sig0, zo)) != FPS_OK ||
+        (s = upload(pl->d_zl_mu, zm)) != FPS_OK || (s = upload(pl->d_zl_sig, sg)) != FPS_OK ||
+        (s = upload(pl->d_zl_tab32, t32)) != FPS_OK || (s = upload(pl->d_zl_ctab32, c32)) != FPS_OK)
+      return s;
+    return FPS_OK;  // one launch: no side stream
+  }
   if (pl->zsplit > 0) return create_side_stream(pl);
   return FPS_OK;
 }
@@ -1141,7 +1189,7 @@ fps_status zeigr_adi(fps_plan *pl, char *w, hipStream_t st) {
 fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStream_t st) {
   const fps::Layout &L = pl->L;
   const int64_t npad = L.npad, mp0 = L.mp[0];
-  double *Gh = (double *)(w + pl->off_G), *GhT = (double *)(w + pl->off_RXT);
+  double *Gh = (double *)(w + pl->off_G);
   double *Yh = (double *)(w + pl->off_ZR), *RX = (double *)(w + pl->off_RX);
   double *O0 = (double *)(w + pl->off_O0), *O1 = (double *)(w + pl->off_O1);
   const Dims full = full_dims(L);
@@ -1149,7 +1197,7 @@ fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
   const int64_t ldm[2] = {L.mp[0], L.mp[1]};
   const int64_t Nfull[2] = {L.m[0] > 0 ? L.mp[0] : 0, L.m[1] > 0 ? L.mp[1] : 0};
   fps_status s;
-  // Input map: G^ = F_T x_x Rs x_y Rs x_z (V^T Rs), and its per-slice transpose.
+  // Input map: G^ = F_T x_x Rs x_y Rs x_z (V^T Rs).
   FPS_HIP(fps::launch_permute3_in(F, O0, L.n, npad, mp0, st));
   {
     const double *MB[2] = {(const double *)pl->d_RsB[0].p, (const double *)pl->d_RsB[1].p};
@@ -1164,8 +1212,33 @@ fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
   }
   if (pl->prec == FPS_FP32_REFINED) {
     if ((s = zeigr_adi(pl, w, st)) != FPS_OK) return s;
+  } else if (pl->zlds) {
+    // Every slice's ADI in one launch, each parity block resident in one
+    // workgroup's LDS (timed with the plan's first event pair, if any).
+    fps::ZeigLdsArgs za{};
+    za.G = Gh;
+    za.Y = Yh;
+    za.tab = (const double *)pl->d_tab.p;
+    za.tab32 = (const double *)pl->d_zl_tab32.p;
+    za.ctab32 = (const double *)pl->d_zl_ctab32.p;
+    za.pre = (const double *)pl->d_pre.p;
+    za.mu = (const double *)pl->d_zl_mu.p;
+    za.sig = (const double *)pl->d_zl_sig.p;
+    za.slice = (const int *)pl->d_zl_slice.p;
+    za.J = (const int *)pl->d_zl_J.p;
+    za.tab0 = (const int *)pl->d_zl_tab0.p;
+    za.sig0 = (const int *)pl->d_zl_sig0.p;
+    za.npad = npad;
+    za.mp0 = mp0;
+    za.mstride = L.mstride;
+    za.ncmax = L.ncmax;
+    za.m0 = (int)L.m[0];
+    za.m1 = (int)L.m[1];
+    const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
+    FPS_HIP(fps::launch_zeig_lds(za, (int)npad, st, t ? pl->ev[2 * pl->ev_used] : nullptr,
+                                 t ? pl->ev[2 * pl->ev_used + 1] : nullptr));
+    if (t) ++pl->ev_used;
   } else {
-    FPS_HIP(fps::launch_transpose(Gh, GhT, npad, st, (int)npad));
     // Per-slice ADI, all active slices per launch.
     const int K = (int)pl->zslice.size();
     const int nsw = pl->zsw_start[0], nrd = pl->zrd_start[0];
@@ -1175,12 +1248,15 @@ fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
     fps::SweepArgs plain{}, stencil{};
     stencil.pre = (const double *)pl->d_pre.p;
     // sweep launch, timed with the plan's event pairs while they last
+    // (rows: the x solves, row-chain batches)
     auto sweep = [&](const fps::SweepArgs &types, bool with_g, const fps::BatchSweep *d, int nwg,
-                     int wg_base, hipStream_t s2) -> hipError_t {
+                     int wg_base, hipStream_t s2, bool rows = false) -> hipError_t {
       const bool t = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
-      const hipError_t e = fps::launch_sweep_batch(
-          types, with_g, d, swmap, nwg, w, s2, wg_base, t ? pl->ev[2 * pl->ev_used] : nullptr,
-          t ? pl->ev[2 * pl->ev_used + 1] : nullptr);
+      hipEvent_t e0 = t ? pl->ev[2 * pl->ev_used] : nullptr;
+      hipEvent_t e1 = t ? pl->ev[2 * pl->ev_used + 1] : nullptr;
+      const hipError_t e =
+          rows ? fps::launch_sweep_batch_rows(types, d, swmap, nwg, w, s2, wg_base, e0, e1)
+               : fps::launch_sweep_batch(types, with_g, d, swmap, nwg, w, s2, wg_base, e0, e1);
       if (t && e == hipSuccess) ++pl->ev_used;
       return e;
     };
@@ -1192,7 +1268,7 @@ fps_status zeig_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
         const int k1 = std::min(pl->zactive[j], hi);
         if (k1 <= lo) break;
         const size_t o1 = ((size_t)j * 2 + 0) * K, o2 = ((size_t)j * 2 + 1) * K;
-        e = sweep(plain, false, dsw + o1, (k1 - lo) * nsw, lo * nsw, s2);
+        e = sweep(plain, false, dsw + o1, (k1 - lo) * nsw, lo * nsw, s2, true);
         if (e == hipSuccess && !pl->zfused)
           e = fps::launch_reduce_batch(drd + o1, rdmap, (k1 - lo) * nrd, L.ncmax, w, s2, lo * nrd);
         // y solves: stencil P = A~ + mu before the solve, the identity for

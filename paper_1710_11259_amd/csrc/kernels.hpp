@@ -102,6 +102,38 @@ struct BatchSweep {
 hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSweep *d,
                               const int *wg_prob, int nwg, char *base, hipStream_t st,
                               int wg_base = 0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// LDS-resident slice ADI of the z-eigenbasis cube (zeig_lds.hip): for
+// every sorted slice k (slice[k] its storage slice, J[k] its steps, 0 for the
+// inactive slices, whose Y^ is zeroed), the J[k] steps of the batched slice
+// sweeps' pass form (x solve with tables tab0[k] + 2j, y solve with tables
+// tab0[k] + 2j + 1 and the stencil pre = A~ + mu[k], the identity at the last
+// step; sigmas sig[sig0[k] + 2j], sig[sig0[k] + 2j + 1]) on G^ (npad^3,
+// [z][y][x]), writing Y^ = -(the final y solve) for all four parity blocks of
+// the slice.  Needs parity blocks of at most 128 (zeig_lds_fits).  The chains are solved in chunks of kZeigLdsChunk
+// positions with the chunk multipliers tab32 ([table][2][BF2, Bk2][mstride])
+// and ctab32 ([table][2][F2last, BF2first, Bk2first][mstride /
+// kZeigLdsChunk]) of fps::build_chunk_tables.
+constexpr int kZeigLdsChunk = 16;
+struct ZeigLdsArgs {
+  const double *G;
+  double *Y;
+  const double *tab, *tab32, *ctab32, *pre, *mu, *sig;
+  const int *slice, *J, *tab0, *sig0;
+  int64_t npad, mp0, mstride, ncmax;
+  int m0, m1;
+};
+bool zeig_lds_fits(int64_t m0, int64_t m1);
+hipError_t launch_zeig_lds(const ZeigLdsArgs &a, int nslices, hipStream_t st,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// Batched row-chain sweeps (launch_sweep_rows per problem): every
+// descriptor is a single array whose chains are its storage rows, with
+// out_mode 0 (v - sigma x) or 3 (x), stored in the input's layout; no g term
+// or stencil; in/out storage d/d, f/d or f/f from `types`.  Workgroup g runs
+// chain block local % nbx and chunk row local / nbx of problem wg_prob[g].
+hipError_t launch_sweep_batch_rows(const SweepArgs &types, const BatchSweep *d, const int *wg_prob,
+                                   int nwg, char *base, hipStream_t st, int wg_base = 0,
+                                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Chunk carries: for every chain, the forward and backward carry into each
 // chunk, scaled by `scale`, into ab [2][ncmax][nchains][2] (ctab: the

@@ -277,6 +277,40 @@ void build_sweep_tables(const Layout &L, const std::vector<double> &p, std::vect
   build_sweep_tables_ab(L, std::vector<double>(p.size(), 1.0), p, pos, chunk, &comb, l1);
 }
 
+void build_chunk_tables(const Layout &L, const std::vector<double> &pos, int64_t chunk,
+                        std::vector<double> &out_pos, std::vector<double> &out_chunk) {
+  const int64_t ms = L.mstride, nq = ms / chunk;
+  const size_t J = pos.size() / (size_t)(2 * kNTab * ms);
+  out_pos.assign(J * 2 * 2 * (size_t)ms, 0.0);
+  out_chunk.assign(J * 2 * 3 * (size_t)nq, 0.0);
+  std::vector<long double> F2((size_t)ms);
+  for (size_t j = 0; j < J; ++j)
+    for (int s = 0; s < 2; ++s) {
+      const double *T = pos.data() + (j * 2 + s) * kNTab * (size_t)ms;
+      const double *l = T + T_L * ms, *ib = T + T_IB * ms, *u = T + T_U * ms;
+      double *P = out_pos.data() + (j * 2 + s) * 2 * (size_t)ms;
+      double *C = out_chunk.data() + (j * 2 + s) * 3 * (size_t)nq;
+      for (int64_t c = 0; c < nq; ++c) {
+        const int64_t c0 = c * chunk, c1 = c0 + chunk;
+        long double acc = 1.0L;
+        for (int64_t k = c0; k < c1; ++k) {
+          acc *= -(long double)l[k];
+          F2[(size_t)k] = acc;
+        }
+        long double x = 0.0L, bk = 1.0L;
+        for (int64_t k = c1 - 1; k >= c0; --k) {
+          x = F2[(size_t)k] * (long double)ib[k] - (long double)u[k] * x;
+          bk *= -(long double)u[k];
+          P[k] = (double)x;        // BF2
+          P[ms + k] = (double)bk;  // Bk2
+        }
+        C[c] = (double)F2[(size_t)(c1 - 1)];  // F2last
+        C[nq + c] = P[c0];                    // BF2first
+        C[2 * nq + c] = P[ms + c0];           // Bk2first
+      }
+    }
+}
+
 void build_sweep_tables_ab(const Layout &L, const std::vector<double> &alpha,
                            const std::vector<double> &beta0, std::vector<double> &pos,
                            std::vector<double> &chunk, std::vector<double> *combp,

@@ -113,6 +113,14 @@ void build_sweep_tables_ab(const Layout &L, const std::vector<double> &alpha,
                            std::vector<double> &chunk, std::vector<double> *comb,
                            std::vector<double> &l1);
 
+// Chunk multipliers of the tables `pos` ([J][2][kNTab][mstride], as built
+// above) for chunks of `chunk` positions (a divisor of kChunk): per table
+// and parity, BF2 and Bk2 at every position (out_pos [J][2][2][mstride]) and
+// F2last, BF2first, Bk2first of every chunk (out_chunk [J][2][3][nq], nq =
+// mstride / chunk), formed in extended precision from the stored l, ib, u.
+void build_chunk_tables(const Layout &L, const std::vector<double> &pos, int64_t chunk,
+                        std::vector<double> &out_pos, std::vector<double> &out_chunk);
+
 // Conversion maps split by parity (row-major, float64):
 //   Rs[s]: m[s] x m[s], Rs[s][a][b] = R[2a+s][2b+s] / sqrt((2a+s+1)(2a+s+2)),
 //          R[i][k] = C~_i coefficient of T_k (upper triangular).

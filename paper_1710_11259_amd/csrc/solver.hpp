@@ -148,6 +148,13 @@ struct fps_plan {
   std::vector<double> zp, zq;  // shifts of step j of sorted slice k at index ztab0[k] / 2 + j
   int zJmax = 0;
   fps::detail::DeviceBuf d_zsw, d_zrd, d_zswmap, d_zrdmap, d_zfin;
+  // FP64 plans whose parity blocks fit one workgroup's LDS (n <= 256): the
+  // whole slice ADI as one launch of k_zeig_lds, over the sorted slices and
+  // then the inactive storage slices (zl_slice, zl_J, zl_tab0, zl_sig0 per
+  // entry; zl_mu the shifts mu; zl_sig the two sigmas of every step).
+  bool zlds = false;
+  fps::detail::DeviceBuf d_zl_slice, d_zl_J, d_zl_tab0, d_zl_sig0, d_zl_mu, d_zl_sig;
+  fps::detail::DeviceBuf d_zl_tab32, d_zl_ctab32;  // the kernel's chunk multipliers
   // Sorted slices 0 .. zsplit-1 (the longest) iterate on the plan's own
   // stream zside, the others on the caller's stream, joined by the events
   // zfork / zjoin (zsplit 0: one stream).

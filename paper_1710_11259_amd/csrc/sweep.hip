@@ -456,7 +456,9 @@ __global__ __launch_bounds__(kCols *kWaves, 6) void k_sweep_rows(SweepArgs a) {
 
 // Batched sweep: workgroup g belongs to problem wg_prob[g]; the problem's
 // descriptor holds workspace offsets in place of its workspace pointers.
-template <typename Tin, typename Tg, typename Tout, int kG, bool kPre>
+// kTL: row-chain problems (k_sweep_rows's arithmetic and layout; the
+// descriptors carry out_mode 0 or 3, the row-wise stores).
+template <typename Tin, typename Tg, typename Tout, int kG, bool kPre, bool kTL = false>
 __global__ __launch_bounds__(kCols *kWaves, 6) void k_sweep_batch(const BatchSweep *__restrict__ d,
                                                                   const int *__restrict__ wg_prob,
                                                                   char *base, int wg_base) {
@@ -474,7 +476,7 @@ __global__ __launch_bounds__(kCols *kWaves, 6) void k_sweep_batch(const BatchSwe
   else if (a.tab_prev != nullptr)
     a.ab_prev = (const double *)(base + (intptr_t)a.ab_prev);
   const int local = g - e.wg_start;
-  sweep_block<Tin, Tg, Tout, kG, kPre>(a, local % e.nbx, local / e.nbx, lds);
+  sweep_block<Tin, Tg, Tout, kG, kPre, kTL>(a, local % e.nbx, local / e.nbx, lds);
 }
 
 }  // namespace
@@ -621,6 +623,32 @@ hipError_t launch_sweep_rows(const SweepArgs &a0, hipStream_t st, hipEvent_t ev0
     default: return hipErrorInvalidValue;  // a float output from a double input
   }
 #undef FPS_ROWS
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch_rows(const SweepArgs &types, const BatchSweep *d, const int *wg_prob,
+                                   int nwg, char *base, hipStream_t st, int wg_base, hipEvent_t ev0,
+                                   hipEvent_t ev1) {
+  if (nwg <= 0) return hipSuccess;
+  if (types.blk1 != 0 || types.chk1 != 0 || types.pre != nullptr) return hipErrorInvalidValue;
+  const int code = (types.in_f32 ? 2 : 0) | (types.out_f32 ? 1 : 0);
+  const dim3 grid((unsigned)nwg), block(kCols * kWaves);
+#define FPS_BROWS(TI, TO)                                                                        \
+  do {                                                                                           \
+    if (ev0 != nullptr)                                                                          \
+      hipExtLaunchKernelGGL((k_sweep_batch<TI, double, TO, 0, false, true>), grid, block, 0, st, \
+                            ev0, ev1, 0, d, wg_prob, base, wg_base);                             \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_sweep_batch<TI, double, TO, 0, false, true>), grid, block, 0, st, d, \
+                         wg_prob, base, wg_base);                                                \
+  } while (0)
+  switch (code) {
+    case 0: FPS_BROWS(double, double); break;
+    case 2: FPS_BROWS(float, double); break;
+    case 3: FPS_BROWS(float, float); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef FPS_BROWS
   return hipGetLastError();
 }
 

@@ -1,0 +1,327 @@
+// gfx950 LDS-resident ADI for the z-eigenbasis cube: every z-slice of the
+// eigen-transformed system is a Sylvester equation of its own, and since A~
+// is block diagonal by parity, each slice splits again into four
+// independent problems, one per (y parity, x parity) block of at most
+// 128 x 128 unknowns for n <= 256.  One workgroup keeps such a block in LDS
+// (and the right-hand side in registers) for all the slice's ADI steps of
+// Algorithm 2, so the iteration reads G^ once and writes Y^ once instead of
+// streaming three arrays through HBM per step.
+//
+// Per step j the pass form of the batched slice sweeps (the same tables,
+// shifts and stencil):
+//   x solve along the block's rows:    v <- v - s1 T1^-1 v,
+//   y solve along its columns:         v <- v - s2 T2^-1 P (v - G)
+//                                      (the last step keeps T2^-1 P (v - G)),
+// with T1, T2 the slice's shifted tridiagonals (whole-chain Thomas factors
+// of the plan's tables) and P = A~ + mu the stencil.  Each chain of up to
+// 128 positions is split into eight chunks of 16, one per thread: all solve
+// with zero carries, exchange their boundary values through LDS, and add
+// the carries through the chunk vectors BF2 / Bk2 of 16-position chunks
+// after the chunk-level recurrences (those of the sweeps' carry kernel).
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace fps {
+
+namespace {
+
+constexpr int kLB = 128;             // largest parity block (chain length)
+constexpr int kLQ = 8;               // chunks per chain (threads per chain)
+constexpr int kLH = kLB / kLQ;       // positions per thread (one chunk)
+constexpr int kLP = kLB + 1;         // LDS row pitch in doubles
+constexpr int kLThreads = kLQ * kLB;  // 1024
+static_assert(kLH == kZeigLdsChunk, "chunk tables of the plan");
+
+// Per-solve tables staged in LDS: l, ib, u, BF2, Bk2 at every position,
+// then F2last, BF2first, Bk2first of every chunk.
+constexpr int kNT = 5;
+constexpr int kTabSolve = kNT * kLB + 3 * kLQ;
+constexpr int kTabVals = 2 * kTabSolve;                         // per step
+constexpr int kTabPer = (kTabVals + kLThreads - 1) / kLThreads;  // per thread
+static_assert(T_L == 0 && T_IB == 1 && T_U == 2, "slots kept");
+
+struct Ends {
+  double ylast, xfirst;
+};
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+// One chain chunk in registers: the Thomas recurrences with zero carries
+// over positions k0 .. k1-1 (tables tl, tib, tu in LDS at the chain's
+// positions, 16-byte aligned, readable up to k0 + kLH - 1); r holds the
+// chunk's right-hand side on entry and its chunk-local solution on return.
+// Each pass reads its table values into registers ahead of its recurrence.
+__device__ __forceinline__ Ends chunk_solve(double (&r)[kLH], int k0, int k1, const double *tl,
+                                            const double *tib, const double *tu) {
+  // bursts of kB positions: their table values are read together, and
+  // scheduling barriers keep the compiler from hoisting several bursts at
+  // once (they would not fit the registers of two wavefronts per SIMD)
+  constexpr int kB = 8;
+  double yp = 0.0;
+#pragma unroll
+  for (int b0 = 0; b0 < kLH; b0 += kB) {
+    __builtin_amdgcn_sched_barrier(0);
+    double t[kB];
+#pragma unroll
+    for (int i = 0; i < kB; i += 2) {
+      const dbl2 q = *(const dbl2 *)(tl + k0 + b0 + i);
+      t[i] = q.x;
+      t[i + 1] = q.y;
+    }
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      if (k0 + b0 + i < k1) {
+        r[b0 + i] = r[b0 + i] - t[i] * yp;
+        yp = r[b0 + i];
+      }
+    }
+  }
+  double xn = 0.0, xf = 0.0;
+#pragma unroll
+  for (int b0 = kLH - kB; b0 >= 0; b0 -= kB) {
+    __builtin_amdgcn_sched_barrier(0);
+    double ib[kB], u[kB];
+#pragma unroll
+    for (int i = 0; i < kB; i += 2) {
+      const dbl2 qi = *(const dbl2 *)(tib + k0 + b0 + i);
+      const dbl2 qu = *(const dbl2 *)(tu + k0 + b0 + i);
+      ib[i] = qi.x;
+      ib[i + 1] = qi.y;
+      u[i] = qu.x;
+      u[i + 1] = qu.y;
+    }
+#pragma unroll
+    for (int i = kB - 1; i >= 0; --i) {
+      if (k0 + b0 + i < k1) {
+        r[b0 + i] = r[b0 + i] * ib[i] - u[i] * xn;
+        xn = r[b0 + i];
+        xf = r[b0 + i];
+      }
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  return Ends{yp, xf};
+}
+
+// The carries into chunk q of a chain of nq chunks from every chunk's
+// boundary values (ey, ex: [chunk][chain] in LDS) and the chunk table C
+// (F2last, BF2first, Bk2first by chunk):
+//   cf(0) = 0, cf(c+1) = F2last(c) cf(c) + ylast(c),
+//   cb(nq-1) = 0, cb(c) = Bk2first(c+1) cb(c+1) + xfirst(c+1) + BF2first(c+1) cf(c+1).
+__device__ __forceinline__ void chunk_carries(const double (*ey)[kLB], const double (*ex)[kLB],
+                                              const double *C, int ch, int q, int nq, double *cf,
+                                              double *cb) {
+  double f[kLQ];
+  f[0] = 0.0;
+#pragma unroll
+  for (int c = 0; c + 1 < kLQ; ++c) f[c + 1] = c + 1 < nq ? C[c] * f[c] + ey[c][ch] : 0.0;
+  double b = 0.0, bq = 0.0;
+#pragma unroll
+  for (int c = kLQ - 2; c >= 0; --c) {
+    if (c + 1 < nq) b = C[2 * kLQ + c + 1] * b + (ex[c + 1][ch] + C[kLQ + c + 1] * f[c + 1]);
+    if (c == q) bq = b;
+  }
+  *cf = f[q];
+  *cb = q + 1 < nq ? bq : 0.0;
+}
+
+// Workgroup g: sorted slice g / 4 (J descending, inactive slices last),
+// block (sy, sx) = ((g / 2) % 2, g % 2).  Threads: chain t % 128, chunk
+// t / 128 (two wavefronts per chunk, four per SIMD).  The next step's tables are fetched
+// into registers while a step runs; each solve's LDS tables are replaced
+// right after that solve's last read.
+__global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
+  __shared__ double Yb[kLB * kLP];
+  __shared__ double ey[kLQ][kLB], exf[kLQ][kLB];  // chunk boundary values
+  __shared__ __align__(16) double Tb[2][kTabSolve];  // [x / y solve]
+  __shared__ double Pd[kLB], Pe[kLB];  // A~ along the y parity: diagonal, coupling
+  const int g = blockIdx.x;
+  const int kk = g >> 2, sy = (g >> 1) & 1, sx = g & 1;
+  const int tid = threadIdx.x;
+  const int ch = tid & (kLB - 1);
+  const int q = __builtin_amdgcn_readfirstlane(tid >> 7);
+  const int64_t npad = a.npad, mp0 = a.mp0, ms = a.mstride, nq32 = a.mstride / kLH;
+  const int my = sy ? a.m1 : a.m0, mx = sx ? a.m1 : a.m0;
+  const int64_t mpy = sy ? npad - mp0 : mp0, mpx = sx ? npad - mp0 : mp0;
+  const int64_t r0 = sy ? mp0 : 0, c0 = sx ? mp0 : 0;
+  const int slice = a.slice[kk], J = a.J[kk];
+  const double *__restrict__ Gs = a.G + ((int64_t)slice * npad + r0) * npad + c0;
+  double *__restrict__ Ys = a.Y + ((int64_t)slice * npad + r0) * npad + c0;
+
+  if (J == 0 || my == 0 || mx == 0) {  // uniform: the block of Y^ is zero
+    for (int64_t y = tid / 64; y < mpy; y += kLThreads / 64)
+      for (int64_t x = tid % 64; x < mpx; x += 64) Ys[y * npad + x] = 0.0;
+    return;
+  }
+  const int tab0 = a.tab0[kk];
+  // This thread's share of step j's tables: element e of solve sv (0: x, 1:
+  // y) is slot e / kLB of the position tables (l, ib, u from the plan's
+  // tables, BF2, Bk2 from the kernel's chunk tables) or, past kNT * kLB, entry
+  // (kind, chunk) of the chunk table; zero past the chain's end.
+  double tv[kTabPer];
+  auto fetch = [&](int j) {
+#pragma unroll
+    for (int p = 0; p < kTabPer; ++p) {
+      const int e0 = tid + p * kLThreads;
+      const int sv = e0 >= kTabSolve ? 1 : 0, e = e0 - sv * kTabSolve;
+      const int s = sv ? sy : sx, m = sv ? my : mx;
+      const int64_t t = tab0 + 2 * j + sv;
+      double val = 0.0;
+      if (e0 < kTabVals) {
+        if (e < 3 * kLB) {
+          const int k = e % kLB;
+          if (k < m) val = a.tab[((t * 2 + s) * kNTab + e / kLB) * ms + k];
+        } else if (e < kNT * kLB) {
+          const int k = e % kLB;
+          if (k < m) val = a.tab32[((t * 2 + s) * 2 + (e / kLB - 3)) * ms + k];
+        } else {
+          const int c = (e - kNT * kLB) % kLQ, kind = (e - kNT * kLB) / kLQ;
+          if (c * kLH < m) val = a.ctab32[((t * 2 + s) * 3 + kind) * nq32 + c];
+        }
+      }
+      tv[p] = val;
+    }
+  };
+  // stores the fetched values of solve sv
+  auto stash = [&](int sv) {
+#pragma unroll
+    for (int p = 0; p < kTabPer; ++p) {
+      const int e0 = tid + p * kLThreads;
+      if (e0 < kTabVals && (e0 >= kTabSolve ? 1 : 0) == sv) (&Tb[0][0])[e0] = tv[p];
+    }
+  };
+  fetch(0);
+  // G^ block into LDS (rows y < my, columns x < mx), coalesced by row; the
+  // stencil of the y parity.
+  for (int y = tid / kLB; y < my; y += kLThreads / kLB)
+    if (ch < mx) Yb[y * kLP + ch] = Gs[(int64_t)y * npad + ch];
+  if (tid < kLB) {
+    Pd[tid] = tid < my ? a.pre[r0 + tid] : 0.0;
+    Pe[tid] = tid < my ? a.pre[npad + r0 + tid] : 0.0;
+  }
+  // This thread's column chunk of G^ for every y solve, and the halo values
+  // of the neighbouring chunks (the stencil couples the chunks' ends).
+  const int ky0 = q * kLH, ky1 = ky0 + kLH < my ? ky0 + kLH : my;
+  const int kx0 = q * kLH, kx1 = kx0 + kLH < mx ? kx0 + kLH : mx;
+  const int nqy = (my + kLH - 1) / kLH, nqx = (mx + kLH - 1) / kLH;
+  double gc[kLH];
+#pragma unroll
+  for (int i = 0; i < kLH; ++i)
+    gc[i] = (ch < mx && ky0 + i < ky1) ? Gs[(int64_t)(ky0 + i) * npad + ch] : 0.0;
+  const bool hlo = ky0 > 0 && ky0 <= my, hhi = ky1 < my;
+  const double glo = (ch < mx && hlo) ? Gs[(int64_t)(ky0 - 1) * npad + ch] : 0.0;
+  const double ghi = (ch < mx && hhi) ? Gs[(int64_t)ky1 * npad + ch] : 0.0;
+  stash(0);
+  stash(1);
+  __syncthreads();
+
+  const double mu = a.mu[kk];
+  const double *__restrict__ sig = a.sig + a.sig0[kk];
+  double r[kLH];
+  for (int j = 0; j < J; ++j) {
+    const bool last = j == J - 1;
+    const double s1 = sig[2 * j], s2 = sig[2 * j + 1];
+    if (!last) fetch(j + 1);
+    // ---- x solve: chain = row ch (positions x), chunk q; tables of parity sx
+    {
+      const double *T = Tb[0];
+      const bool on = ch < my && kx0 < mx;
+      double *cell = Yb + ch * kLP + kx0;
+      if (on) {
+#pragma unroll
+        for (int i = 0; i < kLH; ++i) r[i] = kx0 + i < kx1 ? cell[i] : 0.0;
+        const Ends e = chunk_solve(r, kx0, kx1, T, T + kLB, T + 2 * kLB);
+        ey[q][ch] = e.ylast;
+        exf[q][ch] = e.xfirst;
+      }
+      __syncthreads();
+      if (on) {
+        double cf, cb;
+        chunk_carries(ey, exf, T + kNT * kLB, ch, q, nqx, &cf, &cb);
+        const double *bf2 = T + 3 * kLB, *bk2 = T + 4 * kLB;
+        // the cells still hold the input v
+#pragma unroll
+        for (int i = 0; i < kLH; ++i) {
+          const int k = kx0 + i;
+          if (k < kx1) cell[i] = cell[i] - s1 * (r[i] + (cf * bf2[k] + cb * bk2[k]));
+        }
+      }
+      __syncthreads();
+      if (!last) stash(0);  // the x tables were last read above
+    }
+    // ---- y solve: chain = column ch (positions y), chunk q; tables of
+    // parity sy; right-hand side P (v - G) with P = A~ + mu (the identity at
+    // the last step)
+    {
+      const double *T = Tb[1];
+      const bool on = ch < mx && ky0 < my;
+      double *cell = Yb + ky0 * kLP + ch;
+      if (on) {
+        // w = v - G (the cells keep v until after the barrier below)
+#pragma unroll
+        for (int i = 0; i < kLH; ++i) r[i] = ky0 + i < ky1 ? cell[i * kLP] - gc[i] : 0.0;
+        if (!last) {
+          // rhs_k = (d_k + mu) w_k + e_{k-1} w_{k-1} + e_k w_{k+1}
+          double wm = hlo ? Yb[(ky0 - 1) * kLP + ch] - glo : 0.0;
+          const double whi = hhi ? Yb[ky1 * kLP + ch] - ghi : 0.0;
+#pragma unroll
+          for (int i = 0; i < kLH; ++i) {
+            const int k = ky0 + i;
+            if (k < ky1) {
+              const double w = r[i];
+              const double wp = i + 1 < kLH ? r[i + 1] : whi;
+              const double lo = k > 0 ? Pe[k - 1] * wm : 0.0;
+              const double hi = Pe[k] * wp;
+              r[i] = (Pd[k] + mu) * w + lo + hi;
+              wm = w;
+            }
+          }
+        }
+        const Ends e = chunk_solve(r, ky0, ky1, T, T + kLB, T + 2 * kLB);
+        ey[q][ch] = e.ylast;
+        exf[q][ch] = e.xfirst;
+      }
+      __syncthreads();
+      if (on) {
+        double cf, cb;
+        chunk_carries(ey, exf, T + kNT * kLB, ch, q, nqy, &cf, &cb);
+        const double *bf2 = T + 3 * kLB, *bk2 = T + 4 * kLB;
+#pragma unroll
+        for (int i = 0; i < kLH; ++i) {
+          const int k = ky0 + i;
+          if (k < ky1) {
+            const double x = r[i] + (cf * bf2[k] + cb * bk2[k]);
+            cell[i * kLP] = last ? x : cell[i * kLP] - s2 * x;
+          }
+        }
+      }
+      __syncthreads();
+      if (!last) stash(1);  // the y tables were last read above
+    }
+  }
+  // Y^ block = -(the last y solve), zero on the padding.
+  for (int64_t y = tid / 64; y < mpy; y += kLThreads / 64)
+    for (int64_t x = tid % 64; x < mpx; x += 64)
+      Ys[y * npad + x] = (y < my && x < mx) ? -Yb[y * kLP + x] : 0.0;
+}
+
+}  // namespace
+
+bool zeig_lds_fits(int64_t m0, int64_t m1) { return m0 <= kLB && m1 <= kLB; }
+
+hipError_t launch_zeig_lds(const ZeigLdsArgs &a, int nslices, hipStream_t st, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+  if (nslices <= 0) return hipSuccess;
+  if (!zeig_lds_fits(a.m0, a.m1) || a.mp0 > kLB || a.npad - a.mp0 > kLB ||
+      a.mstride % kLH != 0 || a.tab32 == nullptr || a.ctab32 == nullptr)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(4 * nslices)), block(kLThreads);
+  if (ev0 != nullptr)
+    hipExtLaunchKernelGGL(k_zeig_lds, grid, block, 0, st, ev0, ev1, 0, a);
+  else
+    hipLaunchKernelGGL(k_zeig_lds, grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace fps
