@@ -305,8 +305,11 @@ def bench_cube(fps, workloads, torch, tol, n=256, steps=2, check=True, tight=Tru
 
 def bench_cube_zeig(fps, workloads, torch, tol, n=256, steps=3, check=True, tight=True):
     """Cube n^3 solve through the z-eigenbasis (one ADI per z-slice, FP64):
-    time per solve and the batched slice sweeps' achieved bandwidth.
-    Algorithmic bytes per slice: x solve 16 n^2, y solve 24 n^2."""
+    time per solve, and the ADI's own figures: for n <= 256 the one launch
+    that keeps every slice block in LDS (its time, its HBM bytes, and the
+    streamed sweeps' bytes per the same time), else the batched slice
+    sweeps' achieved bandwidth.  Sweep-model bytes per slice and step: x
+    solve 16 n^2, y solve 24 n^2."""
     import numpy as np
     F_host = workloads.cube_rhs(n)
     F = torch.from_numpy(F_host).cuda()
@@ -341,17 +344,32 @@ def bench_cube_zeig(fps, workloads, torch, tol, n=256, steps=3, check=True, tigh
     p.set_sweep_timing(0)
     ms_g, same_g = graph_timing(fps, torch, p, F, U, steps)
     dof = float(n) ** 3
-    tot_b = sum(k * b * n * n for k, b in seq[:len(t)])
-    tot_t = sum(t) * 1e-3
     res = {"n": n, "dof": dof, "ms_per_solve": ms, "dof_per_s": dof / (ms * 1e-3),
            "enclosure": "computed spectrum" if tight else "Lemma B.1",
            "method": "eigenbasis of A~ along z (MFMA transforms), one ADI per z-slice",
-           "slice_steps": sum(counts), "max_slice_J": Jmax, "sweep_launches": len(seq),
-           "sweep_achieved_GBs": round(tot_b / tot_t / 1e9, 1),
-           "sweep_frac_of_8TBs": round(tot_b / tot_t / 8e12, 4),
-           "sweep_share_of_solve": round(sum(t) / ms_instr, 4),
+           "slice_steps": sum(counts), "max_slice_J": Jmax,
            "hip_graph": {"ms_per_solve": ms_g, "dof_per_s": dof / (ms_g * 1e-3),
                          "equals_eager": same_g}}
+    sweep_model = sum(k * b * n * n for k, b in seq)  # 40 B per dof and slice step
+    if len(t) == 1:
+        # every slice's ADI in one launch, each parity block LDS-resident: HBM
+        # sees G^ read and Y^ written once (npad^3 each); the sweep model's
+        # bytes over the kernel's time give the rate the streamed form would
+        # need for the same time
+        npad = ((n + 1) // 2 + 63) // 64 * 64 + (n // 2 + 63) // 64 * 64
+        hbm_b = 2 * 8.0 * npad ** 3
+        res["adi"] = {"form": "one launch, every slice block resident in LDS",
+                      "kernel_ms": round(t[0], 4), "share_of_solve": round(t[0] / ms_instr, 4),
+                      "hbm_bytes": hbm_b, "hbm_GBs": round(hbm_b / (t[0] * 1e-3) / 1e9, 1),
+                      "sweep_model_bytes": sweep_model,
+                      "sweep_model_equiv_GBs": round(sweep_model / (t[0] * 1e-3) / 1e9, 1)}
+    else:
+        tot_b = sum(k * b * n * n for k, b in seq[:len(t)])
+        tot_t = sum(t) * 1e-3
+        res["adi"] = {"form": "batched slice sweeps", "sweep_launches": len(seq),
+                      "sweep_achieved_GBs": round(tot_b / tot_t / 1e9, 1),
+                      "sweep_frac_of_8TBs": round(tot_b / tot_t / 8e12, 4),
+                      "sweep_share_of_solve": round(sum(t) / ms_instr, 4)}
     # FP32 storage + FP64 refinement (rounds of the K-form slice correction)
     pr = fps.plan(n, tol=tol, dim=3, tight=tight, zeig=True, precision="fp32_refined")
     wsr = fps.workspace(pr, "cuda")

@@ -52,6 +52,8 @@ typedef double dbl2 __attribute__((ext_vector_type(2)));
 // positions, 16-byte aligned, readable up to k0 + kLH - 1); r holds the
 // chunk's right-hand side on entry and its chunk-local solution on return.
 // Each pass reads its table values into registers ahead of its recurrence.
+// kFull: the chunk has all kLH positions (no guards).
+template <bool kFull>
 __device__ __forceinline__ Ends chunk_solve(double (&r)[kLH], int k0, int k1, const double *tl,
                                             const double *tib, const double *tu) {
   // bursts of kB positions: their table values are read together, and
@@ -71,7 +73,7 @@ __device__ __forceinline__ Ends chunk_solve(double (&r)[kLH], int k0, int k1, co
     }
 #pragma unroll
     for (int i = 0; i < kB; ++i) {
-      if (k0 + b0 + i < k1) {
+      if (kFull || k0 + b0 + i < k1) {
         r[b0 + i] = r[b0 + i] - t[i] * yp;
         yp = r[b0 + i];
       }
@@ -93,7 +95,7 @@ __device__ __forceinline__ Ends chunk_solve(double (&r)[kLH], int k0, int k1, co
     }
 #pragma unroll
     for (int i = kB - 1; i >= 0; --i) {
-      if (k0 + b0 + i < k1) {
+      if (kFull || k0 + b0 + i < k1) {
         r[b0 + i] = r[b0 + i] * ib[i] - u[i] * xn;
         xn = r[b0 + i];
         xf = r[b0 + i];
@@ -124,6 +126,72 @@ __device__ __forceinline__ void chunk_carries(const double (*ey)[kLB], const dou
   }
   *cf = f[q];
   *cb = q + 1 < nq ? bq : 0.0;
+}
+
+// The two halves of one thread's part of a solve (a barrier and the
+// boundary-value exchange between them).  x solve: chain cells cell[i]
+// (row), right-hand side v; y solve: cells cell[i * kLP] (column),
+// right-hand side P (v - G) (v - G at the last step).  kFull: a full chunk.
+template <bool kFull>
+__device__ __forceinline__ Ends x_local(double (&r)[kLH], const double *cell, int k0, int k1,
+                                        const double *T) {
+#pragma unroll
+  for (int i = 0; i < kLH; ++i) r[i] = (kFull || k0 + i < k1) ? cell[i] : 0.0;
+  return chunk_solve<kFull>(r, k0, k1, T, T + kLB, T + 2 * kLB);
+}
+
+template <bool kFull>
+__device__ __forceinline__ void x_out(const double (&r)[kLH], double *cell, int k0, int k1,
+                                      const double *T, double cf, double cb, double s1) {
+  const double *bf2 = T + 3 * kLB, *bk2 = T + 4 * kLB;
+  // the cells still hold the input v
+#pragma unroll
+  for (int i = 0; i < kLH; ++i) {
+    const int k = k0 + i;
+    if (kFull || k < k1) cell[i] = cell[i] - s1 * (r[i] + (cf * bf2[k] + cb * bk2[k]));
+  }
+}
+
+template <bool kFull>
+__device__ __forceinline__ Ends y_local(double (&r)[kLH], const double *cell, const double *gc,
+                                        int k0, int k1, const double *T, const double *Pd,
+                                        const double *Pe, double mu, double wlo, double whi,
+                                        bool last) {
+  // w = v - G (the cells keep v until after the barrier that follows)
+#pragma unroll
+  for (int i = 0; i < kLH; ++i) r[i] = (kFull || k0 + i < k1) ? cell[i * kLP] - gc[i] : 0.0;
+  if (!last) {
+    // rhs_k = (d_k + mu) w_k + e_{k-1} w_{k-1} + e_k w_{k+1}
+    double wm = wlo;
+#pragma unroll
+    for (int i = 0; i < kLH; ++i) {
+      const int k = k0 + i;
+      if (kFull || k < k1) {
+        const double w = r[i];
+        const double wp = i + 1 < kLH ? r[i + 1] : whi;
+        const double lo = k > 0 ? Pe[k - 1] * wm : 0.0;
+        const double hi = Pe[k] * wp;
+        r[i] = (Pd[k] + mu) * w + lo + hi;
+        wm = w;
+      }
+    }
+  }
+  return chunk_solve<kFull>(r, k0, k1, T, T + kLB, T + 2 * kLB);
+}
+
+template <bool kFull>
+__device__ __forceinline__ void y_out(const double (&r)[kLH], double *cell, int k0, int k1,
+                                      const double *T, double cf, double cb, double s2,
+                                      bool last) {
+  const double *bf2 = T + 3 * kLB, *bk2 = T + 4 * kLB;
+#pragma unroll
+  for (int i = 0; i < kLH; ++i) {
+    const int k = k0 + i;
+    if (kFull || k < k1) {
+      const double x = r[i] + (cf * bf2[k] + cb * bk2[k]);
+      cell[i * kLP] = last ? x : cell[i * kLP] - s2 * x;
+    }
+  }
 }
 
 // Workgroup g: sorted slice g / 4 (J descending, inactive slices last),
@@ -205,6 +273,7 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
   const int ky0 = q * kLH, ky1 = ky0 + kLH < my ? ky0 + kLH : my;
   const int kx0 = q * kLH, kx1 = kx0 + kLH < mx ? kx0 + kLH : mx;
   const int nqy = (my + kLH - 1) / kLH, nqx = (mx + kLH - 1) / kLH;
+  const bool fullx = kx1 - kx0 == kLH, fully = ky1 - ky0 == kLH;  // uniform per wavefront
   double gc[kLH];
 #pragma unroll
   for (int i = 0; i < kLH; ++i)
@@ -229,9 +298,8 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
       const bool on = ch < my && kx0 < mx;
       double *cell = Yb + ch * kLP + kx0;
       if (on) {
-#pragma unroll
-        for (int i = 0; i < kLH; ++i) r[i] = kx0 + i < kx1 ? cell[i] : 0.0;
-        const Ends e = chunk_solve(r, kx0, kx1, T, T + kLB, T + 2 * kLB);
+        const Ends e = fullx ? x_local<true>(r, cell, kx0, kx1, T)
+                             : x_local<false>(r, cell, kx0, kx1, T);
         ey[q][ch] = e.ylast;
         exf[q][ch] = e.xfirst;
       }
@@ -239,13 +307,10 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
       if (on) {
         double cf, cb;
         chunk_carries(ey, exf, T + kNT * kLB, ch, q, nqx, &cf, &cb);
-        const double *bf2 = T + 3 * kLB, *bk2 = T + 4 * kLB;
-        // the cells still hold the input v
-#pragma unroll
-        for (int i = 0; i < kLH; ++i) {
-          const int k = kx0 + i;
-          if (k < kx1) cell[i] = cell[i] - s1 * (r[i] + (cf * bf2[k] + cb * bk2[k]));
-        }
+        if (fullx)
+          x_out<true>(r, cell, kx0, kx1, T, cf, cb, s1);
+        else
+          x_out<false>(r, cell, kx0, kx1, T, cf, cb, s1);
       }
       __syncthreads();
       if (!last) stash(0);  // the x tables were last read above
@@ -258,27 +323,11 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
       const bool on = ch < mx && ky0 < my;
       double *cell = Yb + ky0 * kLP + ch;
       if (on) {
-        // w = v - G (the cells keep v until after the barrier below)
-#pragma unroll
-        for (int i = 0; i < kLH; ++i) r[i] = ky0 + i < ky1 ? cell[i * kLP] - gc[i] : 0.0;
-        if (!last) {
-          // rhs_k = (d_k + mu) w_k + e_{k-1} w_{k-1} + e_k w_{k+1}
-          double wm = hlo ? Yb[(ky0 - 1) * kLP + ch] - glo : 0.0;
-          const double whi = hhi ? Yb[ky1 * kLP + ch] - ghi : 0.0;
-#pragma unroll
-          for (int i = 0; i < kLH; ++i) {
-            const int k = ky0 + i;
-            if (k < ky1) {
-              const double w = r[i];
-              const double wp = i + 1 < kLH ? r[i + 1] : whi;
-              const double lo = k > 0 ? Pe[k - 1] * wm : 0.0;
-              const double hi = Pe[k] * wp;
-              r[i] = (Pd[k] + mu) * w + lo + hi;
-              wm = w;
-            }
-          }
-        }
-        const Ends e = chunk_solve(r, ky0, ky1, T, T + kLB, T + 2 * kLB);
+        const double wlo = hlo ? Yb[(ky0 - 1) * kLP + ch] - glo : 0.0;
+        const double whi = hhi ? Yb[ky1 * kLP + ch] - ghi : 0.0;
+        const Ends e =
+            fully ? y_local<true>(r, cell, gc, ky0, ky1, T, Pd, Pe, mu, wlo, whi, last)
+                  : y_local<false>(r, cell, gc, ky0, ky1, T, Pd, Pe, mu, wlo, whi, last);
         ey[q][ch] = e.ylast;
         exf[q][ch] = e.xfirst;
       }
@@ -286,15 +335,10 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
       if (on) {
         double cf, cb;
         chunk_carries(ey, exf, T + kNT * kLB, ch, q, nqy, &cf, &cb);
-        const double *bf2 = T + 3 * kLB, *bk2 = T + 4 * kLB;
-#pragma unroll
-        for (int i = 0; i < kLH; ++i) {
-          const int k = ky0 + i;
-          if (k < ky1) {
-            const double x = r[i] + (cf * bf2[k] + cb * bk2[k]);
-            cell[i * kLP] = last ? x : cell[i * kLP] - s2 * x;
-          }
-        }
+        if (fully)
+          y_out<true>(r, cell, ky0, ky1, T, cf, cb, s2, last);
+        else
+          y_out<false>(r, cell, ky0, ky1, T, cf, cb, s2, last);
       }
       __syncthreads();
       if (!last) stash(1);  // the y tables were last read above
