@@ -25,9 +25,9 @@ FP64_MFMA_PEAK_TFLOPS = 78.6  # dense FP64 matrix peak of MI355X
 # (sweep.hip) with this sha256 (the counters were taken on the same device
 # code).
 SWEEP_SOURCES = ("sweep.hip",)
-SWEEP_TRAFFIC = {"sha256": "cc592ed32081659ae804d8899a39e499d25960ffbd0898cb8118b1649c5567ad",
+SWEEP_TRAFFIC = {"sha256": "26523be850a96aee6cae29ca6125c86917afec02f83fb7294da6db3a9528f947",
                  4096: {"half_step_1": 277.6e6, "half_step_2": 413.0e6},
-                 10000: {"half_step_1": 1764.2e6, "half_step_2": 2529.7e6}}
+                 10000: {"half_step_1": 1764.2e6, "half_step_2": 2529.8e6}}
 
 
 def sweep_sources_sha():
