@@ -30,7 +30,7 @@ namespace {
 constexpr int kLB = 128;             // largest parity block (chain length)
 constexpr int kLQ = 8;               // chunks per chain (threads per chain)
 constexpr int kLH = kLB / kLQ;       // positions per thread (one chunk)
-constexpr int kLP = kLB + 1;         // LDS row pitch in doubles
+constexpr int kLP = kLB + 2;         // LDS row pitch in doubles (16-byte rows)
 constexpr int kLThreads = kLQ * kLB;  // 1024
 static_assert(kLH == kZeigLdsChunk, "chunk tables of the plan");
 
@@ -106,26 +106,28 @@ __device__ __forceinline__ Ends chunk_solve(double (&r)[kLH], int k0, int k1, co
   return Ends{yp, xf};
 }
 
-// The carries into chunk q of a chain of nq chunks from every chunk's
+// The carries into every chunk of chain ch (nq chunks) from the chunks'
 // boundary values (ey, ex: [chunk][chain] in LDS) and the chunk table C
-// (F2last, BF2first, Bk2first by chunk):
+// (F2last, BF2first, Bk2first by chunk), written back in place: ey[c][ch]
+// <- cf(c), ex[c][ch] <- cb(c), with
 //   cf(0) = 0, cf(c+1) = F2last(c) cf(c) + ylast(c),
 //   cb(nq-1) = 0, cb(c) = Bk2first(c+1) cb(c+1) + xfirst(c+1) + BF2first(c+1) cf(c+1).
-__device__ __forceinline__ void chunk_carries(const double (*ey)[kLB], const double (*ex)[kLB],
-                                              const double *C, int ch, int q, int nq, double *cf,
-                                              double *cb) {
-  double f[kLQ];
+__device__ __forceinline__ void chain_carries(double (*ey)[kLB], double (*ex)[kLB],
+                                              const double *C, int ch, int nq) {
+  double f[kLQ], b[kLQ];
   f[0] = 0.0;
 #pragma unroll
   for (int c = 0; c + 1 < kLQ; ++c) f[c + 1] = c + 1 < nq ? C[c] * f[c] + ey[c][ch] : 0.0;
-  double b = 0.0, bq = 0.0;
+  b[kLQ - 1] = 0.0;
 #pragma unroll
-  for (int c = kLQ - 2; c >= 0; --c) {
-    if (c + 1 < nq) b = C[2 * kLQ + c + 1] * b + (ex[c + 1][ch] + C[kLQ + c + 1] * f[c + 1]);
-    if (c == q) bq = b;
+  for (int c = kLQ - 2; c >= 0; --c)
+    b[c] = c + 1 < nq ? C[2 * kLQ + c + 1] * b[c + 1] + (ex[c + 1][ch] + C[kLQ + c + 1] * f[c + 1])
+                      : 0.0;
+#pragma unroll
+  for (int c = 0; c < kLQ; ++c) {
+    ey[c][ch] = f[c];
+    ex[c][ch] = b[c];
   }
-  *cf = f[q];
-  *cb = q + 1 < nq ? bq : 0.0;
 }
 
 // The two halves of one thread's part of a solve (a barrier and the
@@ -135,8 +137,17 @@ __device__ __forceinline__ void chunk_carries(const double (*ey)[kLB], const dou
 template <bool kFull>
 __device__ __forceinline__ Ends x_local(double (&r)[kLH], const double *cell, int k0, int k1,
                                         const double *T) {
+  if constexpr (kFull) {  // 16-byte reads of the row (cell 16-byte aligned)
 #pragma unroll
-  for (int i = 0; i < kLH; ++i) r[i] = (kFull || k0 + i < k1) ? cell[i] : 0.0;
+    for (int i = 0; i < kLH; i += 2) {
+      const dbl2 p = *(const dbl2 *)(cell + i);
+      r[i] = p.x;
+      r[i + 1] = p.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kLH; ++i) r[i] = k0 + i < k1 ? cell[i] : 0.0;
+  }
   return chunk_solve<kFull>(r, k0, k1, T, T + kLB, T + 2 * kLB);
 }
 
@@ -145,10 +156,20 @@ __device__ __forceinline__ void x_out(const double (&r)[kLH], double *cell, int 
                                       const double *T, double cf, double cb, double s1) {
   const double *bf2 = T + 3 * kLB, *bk2 = T + 4 * kLB;
   // the cells still hold the input v
+  if constexpr (kFull) {
 #pragma unroll
-  for (int i = 0; i < kLH; ++i) {
-    const int k = k0 + i;
-    if (kFull || k < k1) cell[i] = cell[i] - s1 * (r[i] + (cf * bf2[k] + cb * bk2[k]));
+    for (int i = 0; i < kLH; i += 2) {
+      const dbl2 v = *(const dbl2 *)(cell + i);
+      const dbl2 f2 = *(const dbl2 *)(bf2 + k0 + i), b2 = *(const dbl2 *)(bk2 + k0 + i);
+      *(dbl2 *)(cell + i) = dbl2{v.x - s1 * (r[i] + (cf * f2.x + cb * b2.x)),
+                                 v.y - s1 * (r[i + 1] + (cf * f2.y + cb * b2.y))};
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kLH; ++i) {
+      const int k = k0 + i;
+      if (k < k1) cell[i] = cell[i] - s1 * (r[i] + (cf * bf2[k] + cb * bk2[k]));
+    }
   }
 }
 
@@ -200,7 +221,7 @@ __device__ __forceinline__ void y_out(const double (&r)[kLH], double *cell, int 
 // into registers while a step runs; each solve's LDS tables are replaced
 // right after that solve's last read.
 __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
-  __shared__ double Yb[kLB * kLP];
+  __shared__ __align__(16) double Yb[kLB * kLP];
   __shared__ double ey[kLQ][kLB], exf[kLQ][kLB];  // chunk boundary values
   __shared__ __align__(16) double Tb[2][kTabSolve];  // [x / y solve]
   __shared__ double Pd[kLB], Pe[kLB];  // A~ along the y parity: diagonal, coupling
@@ -304,9 +325,11 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
         exf[q][ch] = e.xfirst;
       }
       __syncthreads();
+      // the carries of every chunk of the row, once per chain
+      if (q == 0 && ch < my) chain_carries(ey, exf, T + kNT * kLB, ch, nqx);
+      __syncthreads();
       if (on) {
-        double cf, cb;
-        chunk_carries(ey, exf, T + kNT * kLB, ch, q, nqx, &cf, &cb);
+        const double cf = ey[q][ch], cb = exf[q][ch];
         if (fullx)
           x_out<true>(r, cell, kx0, kx1, T, cf, cb, s1);
         else
@@ -332,9 +355,11 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
         exf[q][ch] = e.xfirst;
       }
       __syncthreads();
+      // the carries of every chunk of the column, once per chain
+      if (q == 0 && ch < mx) chain_carries(ey, exf, T + kNT * kLB, ch, nqy);
+      __syncthreads();
       if (on) {
-        double cf, cb;
-        chunk_carries(ey, exf, T + kNT * kLB, ch, q, nqy, &cf, &cb);
+        const double cf = ey[q][ch], cb = exf[q][ch];
         if (fully)
           y_out<true>(r, cell, ky0, ky1, T, cf, cb, s2, last);
         else
