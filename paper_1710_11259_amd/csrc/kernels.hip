@@ -230,11 +230,13 @@ __global__ void k_permute3_in(const double *__restrict__ src, double *__restrict
 // parity-blocked [.][.][ld] (parity-1 block at mb0 on every axis, row
 // length ld, plane ld * ld) -> natural N^3, times sinv_i sinv_j sinv_k when
 // sinv is non-null.
+// A workgroup covers 256 consecutive elements of one output plane (so a
+// plane of (n + 2)^2 keeps every lane busy but the last workgroup's).
 __global__ void k_permute3_out(const double *__restrict__ src, double *__restrict__ dst, int64_t N,
                                int64_t ld, int64_t mb0, const double *__restrict__ sinv) {
-  const int64_t ix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t iy = blockIdx.y, iz = blockIdx.z;
-  if (ix >= N) return;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x, n32 = (uint32_t)N;
+  if (i >= n32 * n32) return;
+  const int64_t iy = i / n32, ix = i - (uint32_t)iy * n32, iz = blockIdx.y;
   double v = src[(pb_index(iz, mb0) * ld + pb_index(iy, mb0)) * ld + pb_index(ix, mb0)];
   if (sinv) v *= sinv[iz] * sinv[iy] * sinv[ix];
   dst[(iz * N + iy) * N + ix] = v;
@@ -416,7 +418,8 @@ hipError_t launch_permute3_in(const double *src, double *dst, int64_t n, int64_t
 
 hipError_t launch_permute3_out(const double *src, double *dst, int64_t N, int64_t ld, int64_t mb0,
                                const double *sinv, hipStream_t st) {
-  dim3 grid((unsigned)((N + 255) / 256), (unsigned)N, (unsigned)N);
+  if (N > 46340) return hipErrorInvalidValue;  // a plane's index fits 32 bits
+  dim3 grid((unsigned)((N * N + 255) / 256), (unsigned)N);
   hipLaunchKernelGGL(k_permute3_out, grid, dim3(256), 0, st, src, dst, N, ld, mb0, sinv);
   return hipGetLastError();
 }

@@ -38,8 +38,6 @@ static_assert(kLH == kZeigLdsChunk, "chunk tables of the plan");
 // then F2last, BF2first, Bk2first of every chunk.
 constexpr int kNT = 5;
 constexpr int kTabSolve = kNT * kLB + 3 * kLQ;
-constexpr int kTabVals = 2 * kTabSolve;                         // per step
-constexpr int kTabPer = (kTabVals + kLThreads - 1) / kLThreads;  // per thread
 static_assert(T_L == 0 && T_IB == 1 && T_U == 2, "slots kept");
 
 struct Ends {
@@ -244,41 +242,61 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
     return;
   }
   const int tab0 = a.tab0[kk];
-  // This thread's share of step j's tables: element e of solve sv (0: x, 1:
-  // y) is slot e / kLB of the position tables (l, ib, u from the plan's
-  // tables, BF2, Bk2 from the kernel's chunk tables) or, past kNT * kLB, entry
-  // (kind, chunk) of the chunk table; zero past the chain's end.
-  double tv[kTabPer];
-  auto fetch = [&](int j) {
+  // Step j's tables are fetched in 64-value pieces, one per (wavefront,
+  // round p): piece z = p * 16 + wavefront is piece z % 11 of solve z / 11
+  // (0: x, 1: y), either half (z % 11) % 2 of position table (z % 11) / 2 (l,
+  // ib, u from the plan's tables, BF2, Bk2 from the kernel's chunk tables) or,
+  // for z % 11 == 10, the chunk table (kind, chunk) = (lane / 8, lane % 8).
+  // Which table a piece reads, and its stride per step, are uniform over the
+  // wavefront; a lane keeps its offset, the value in flight and whether it
+  // lies before the chain's end (zero past it).
+  constexpr int kWaves = kLThreads / 64;
+  constexpr int kPieces = 2 * kNT + 1;
+  constexpr int kRounds = (2 * kPieces + kWaves - 1) / kWaves;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  double tv[kRounds];
+  const double *src[kRounds];
+  int64_t step[kRounds];
+  int off[kRounds], dst[kRounds], psv[kRounds];
+  bool live[kRounds];
 #pragma unroll
-    for (int p = 0; p < kTabPer; ++p) {
-      const int e0 = tid + p * kLThreads;
-      const int sv = e0 >= kTabSolve ? 1 : 0, e = e0 - sv * kTabSolve;
-      const int s = sv ? sy : sx, m = sv ? my : mx;
-      const int64_t t = tab0 + 2 * j + sv;
-      double val = 0.0;
-      if (e0 < kTabVals) {
-        if (e < 3 * kLB) {
-          const int k = e % kLB;
-          if (k < m) val = a.tab[((t * 2 + s) * kNTab + e / kLB) * ms + k];
-        } else if (e < kNT * kLB) {
-          const int k = e % kLB;
-          if (k < m) val = a.tab32[((t * 2 + s) * 2 + (e / kLB - 3)) * ms + k];
-        } else {
-          const int c = (e - kNT * kLB) % kLQ, kind = (e - kNT * kLB) / kLQ;
-          if (c * kLH < m) val = a.ctab32[((t * 2 + s) * 3 + kind) * nq32 + c];
-        }
-      }
-      tv[p] = val;
+  for (int p = 0; p < kRounds; ++p) {
+    const int z = p * kWaves + wv;
+    const bool act = z < 2 * kPieces;
+    const int sv = z >= kPieces ? 1 : 0, r = z - sv * kPieces;
+    const int s = sv ? sy : sx, m = sv ? my : mx;
+    const int64_t t = tab0 + sv;  // the table of step 0
+    psv[p] = sv;
+    if (r < 2 * kNT) {
+      const int row = r >> 1, k = (r & 1) * 64 + lane;
+      src[p] = row < 3 ? a.tab + ((t * 2 + s) * kNTab + row) * ms
+                       : a.tab32 + ((t * 2 + s) * 2 + (row - 3)) * ms;
+      step[p] = row < 3 ? 4 * kNTab * ms : 8 * ms;
+      off[p] = k;
+      live[p] = act && k < m;
+      dst[p] = act ? sv * kTabSolve + row * kLB + k : -1;
+    } else {
+      const int kind = lane >> 3, c = lane & 7;
+      src[p] = a.ctab32 + (t * 2 + s) * 3 * nq32;
+      step[p] = 12 * nq32;
+      off[p] = kind * (int)nq32 + c;
+      live[p] = act && lane < 3 * kLQ && c * kLH < m;
+      dst[p] = act && lane < 3 * kLQ ? sv * kTabSolve + kNT * kLB + lane : -1;
+    }
+  }
+  // step j's tables (called with j = 0, 1, 2, ... in turn)
+  auto fetch = [&](int) {
+#pragma unroll
+    for (int p = 0; p < kRounds; ++p) {
+      tv[p] = live[p] ? src[p][off[p]] : 0.0;
+      src[p] += step[p];
     }
   };
   // stores the fetched values of solve sv
   auto stash = [&](int sv) {
 #pragma unroll
-    for (int p = 0; p < kTabPer; ++p) {
-      const int e0 = tid + p * kLThreads;
-      if (e0 < kTabVals && (e0 >= kTabSolve ? 1 : 0) == sv) (&Tb[0][0])[e0] = tv[p];
-    }
+    for (int p = 0; p < kRounds; ++p)
+      if (psv[p] == sv && dst[p] >= 0) (&Tb[0][0])[dst[p]] = tv[p];
   };
   fetch(0);
   // G^ block into LDS (rows y < my, columns x < mx), coalesced by row; the
