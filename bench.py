@@ -190,7 +190,8 @@ def calibration_copy(torch, dev, mib):
 def bench_batch(fps, workloads, torch, tol, reps=3, tight=True):
     """256 independent square solves (n_b = 32 U{1..32}, seed 1): one graph
     launch per batch (FP64 and FP32-refined) against a sequential loop of
-    single FP64 solves."""
+    single FP64 solves, run eagerly and replayed from one HIP graph per
+    solve."""
     import numpy as np
     ns, Fs = workloads.batched_problems()
     dof = float(sum(n * n for n in ns))
@@ -221,13 +222,30 @@ def bench_batch(fps, workloads, torch, tol, reps=3, tight=True):
             fps.solve(plans[n], F, out=U, ws=ws)
     t_seq = timed(seq, 1)
     res["sequential_fp64_ms"] = t_seq
+    # the same solves, each captured into its own HIP graph (no host launch
+    # cost inside a solve): the device-side baseline of the batched launches
+    graphs = []
+    for n, F in zip(ns, Fd):
+        g1 = fps.SolveGraph(plans[n])
+        g1.F.copy_(F)
+        graphs.append(g1)
+
+    def seq_graphs():
+        for g1 in graphs:
+            g1.replay()
+    t_seq_graph = timed(seq_graphs, reps)
+    res["sequential_fp64_graph_equals_eager"] = all(
+        bool(torch.equal(g1.U, U)) for g1, U in zip(graphs, Us))
+    res["sequential_fp64_graph_ms"] = t_seq_graph
+    del graphs
     for prec in ("fp64", "fp32_refined"):
         b = fps.batch(ns, tol=tol, precision=prec, tight=tight)
         g = fps.BatchGraph(b)
         g.F.copy_(b.pack(Fs))
         t = timed(g.replay, reps)
         r = {"ms_per_batch": t, "dof_per_s": dof / (t * 1e-3), "speedup_vs_sequential_fp64":
-             t_seq / t, "max_J": b.max_J, "launch": "one HIP graph"}
+             t_seq / t, "speedup_vs_sequential_fp64_graph": t_seq_graph / t, "max_J": b.max_J,
+             "launch": "one HIP graph"}
         got = b.unpack(g.U)
         worst = 0.0
         for U, Ub in zip(Us, got):

@@ -37,7 +37,8 @@ def _plan(kind, n):
 
 # cube_zeig at n = 200 runs its 58 longest slices on the plan's second
 # stream, so the capture also records the fork and join between streams.
-@pytest.mark.parametrize("kind,n", [("square", 300), ("square_refined", 200), ("rect", 130),
+@pytest.mark.parametrize("kind,n", [("square", 64), ("square", 300), ("square", 1024),
+                                    ("square_refined", 200), ("rect", 130),
                                     ("cube_zeig", 33), ("cube_zeig", 200), ("cube", 12),
                                     ("cylinder", 40)])
 def test_solve_graph_replays_match_eager(kind, n):
