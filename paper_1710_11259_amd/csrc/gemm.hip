@@ -79,14 +79,16 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
   tile_krange(g, bx, by, &klo, &khi);
 
   // Loader mapping.  A tile 128 x 16: thread t reads row t/2, k-run (t%2)*8..+8.
-  // B tile 16 x 128: thread t reads k-row t/16, column run (t%16)*8..+8.
+  // B tile 16 x 128: thread t reads k-row t/16, the column pairs bc + 32 q
+  // (bc = 2 (t%16), q = 0..3), so the 16 threads of a row read and stash
+  // 256 contiguous bytes per q (no LDS bank conflicts on the stash).
   const int ar = tid >> 1, ak = (tid & 1) * 8;
-  const int bk = tid >> 4, bc = (tid & 15) * 8;
+  const int bk = tid >> 4, bc = (tid & 15) * 2;
   const int64_t arow = i0 + ar < g.M ? i0 + ar : g.M - 1;
   const double az = i0 + ar < g.M ? 1.0 : 0.0;
   const double *__restrict__ Ap = g.A + arow * g.sai + ak;
   const double *__restrict__ Bp = g.B + (int64_t)bk * g.sbk + j0 + bc;
-  const bool bfull = j0 + bc + 8 <= g.N;
+  const bool bfull = j0 + bc + 3 * 32 + 2 <= g.N;
 
   dbl2 ra[4], rb[4];
   auto fetch = [&](int64_t k0) {
@@ -95,13 +97,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
     const double *bp = Bp + k0 * g.sbk;
     if (bfull) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) rb[q] = *(const dbl2 *)(bp + 2 * q);
+      for (int q = 0; q < 4; ++q) rb[q] = *(const dbl2 *)(bp + 32 * q);
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t jj = j0 + bc + 2 * q;
-        rb[q].x = jj < g.N ? bp[2 * q] : 0.0;
-        rb[q].y = jj + 1 < g.N ? bp[2 * q + 1] : 0.0;
+        const int64_t jj = j0 + bc + 32 * q;
+        rb[q].x = jj < g.N ? bp[32 * q] : 0.0;
+        rb[q].y = jj + 1 < g.N ? bp[32 * q + 1] : 0.0;
       }
     }
   };
@@ -113,7 +115,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &g, const int bx, const
     for (int q = 0; q < 4; ++q) {
       Ad[ar][ak + 2 * q] = az * ra[q].x;
       Ad[ar][ak + 2 * q + 1] = az * ra[q].y;
-      *(dbl2 *)&Bd[bk][bc + 2 * q] = rb[q];
+      *(dbl2 *)&Bd[bk][bc + 32 * q] = rb[q];
     }
   };
 
