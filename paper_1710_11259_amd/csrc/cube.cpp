@@ -264,6 +264,27 @@ fps_status cube_plan_upload(fps_plan *pl) {
     if ((s = upload_table(probs, pl->d_gy_out, pl->d_gy_map_out, pl->gy_tiles[1])) != FPS_OK)
       return s;
   }
+  // The LDS-resident inner ADI: chunk multipliers of every table and, per
+  // outer step, the sigmas of its inner steps (v - 2 p_j x along x, then
+  // v - (p_j + p_{j+1}) x along y; the last y solve keeps x).
+  pl->nlds = pl->prec == FPS_FP64 && fps::zeig_lds_fits(L.m[0], L.m[1]) && L.mp[0] <= 128 &&
+             L.npad - L.mp[0] <= 128 && L.mstride % fps::kZeigLdsChunk == 0;
+  if (pl->nlds) {
+    std::vector<double> t32, c32, sg;
+    fps::build_chunk_tables(L, pl->tab, fps::kZeigLdsChunk, t32, c32);
+    for (int i = 0; i < pl->shifts.J; ++i) {
+      const double *p2 = pl->inner_p.data() + pl->inner_off[i];
+      const int J2 = pl->inner_J[i];
+      for (int j = 0; j < J2; ++j) {
+        sg.push_back(2.0 * p2[j]);
+        sg.push_back(j + 1 < J2 ? p2[j] + p2[j + 1] : 0.0);
+      }
+    }
+    if (sg.empty()) sg.push_back(0.0);
+    if ((s = upload(pl->d_zl_tab32, t32)) != FPS_OK ||
+        (s = upload(pl->d_zl_ctab32, c32)) != FPS_OK || (s = upload(pl->d_zl_sig, sg)) != FPS_OK)
+      return s;
+  }
   return FPS_OK;
 }
 
@@ -338,7 +359,32 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
     const int J2 = pl->inner_J[i];
     const double *p2 = pl->inner_p.data() + pl->inner_off[i];
     const int t0 = J1 + pl->inner_off[i];
-    for (int j = 0; j < J2; ++j) {
+    if (pl->nlds) {
+      // every slice's inner ADI in one launch, each parity block resident
+      // in one workgroup's LDS; the complete final x (no chunk carries
+      // left) goes to O1 in the natural layout
+      fps::ZeigLdsArgs za{};
+      za.G = RX;
+      za.Y = O1;
+      za.tab = (const double *)pl->d_tab.p;
+      za.tab32 = (const double *)pl->d_zl_tab32.p;
+      za.ctab32 = (const double *)pl->d_zl_ctab32.p;
+      za.pre = pre;
+      za.sig = (const double *)pl->d_zl_sig.p + 2 * (int64_t)pl->inner_off[i];
+      za.npad = npad;
+      za.mp0 = mp0;
+      za.mstride = L.mstride;
+      za.ncmax = L.ncmax;
+      za.m0 = (int)L.m[0];
+      za.m1 = (int)L.m[1];
+      za.tab0_all = t0;
+      za.J_all = J2;
+      const bool tm = pl->ev_used * 2 + 1 < (int64_t)pl->ev.size();
+      FPS_HIP(fps::launch_zeig_lds(za, (int)npad, st, tm ? pl->ev[2 * pl->ev_used] : nullptr,
+                                   tm ? pl->ev[2 * pl->ev_used + 1] : nullptr, true));
+      if (tm) ++pl->ev_used;
+    }
+    for (int j = 0; j < (pl->nlds ? 0 : J2); ++j) {
       const int t = t0 + j;
       const bool last = j == J2 - 1;
       fps::SweepArgs a = S;
@@ -370,11 +416,12 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
                                  L.ncmax, st, (int)npad, S.lvb, S.abb));
     }
     const double *tl = pl->tab_dev(t0 + J2 - 1);
+    const double *abf = pl->nlds ? nullptr : ab;
     if (i + 1 < J1) {
-      FPS_HIP(fps::launch_cube_ifinal(O1, ab, tl, RX, B, ZR, p1[i + 1] - q1[i], 1.0, -1.0, npad,
+      FPS_HIP(fps::launch_cube_ifinal(O1, abf, tl, RX, B, ZR, p1[i + 1] - q1[i], 1.0, -1.0, npad,
                                       mp0, L.mstride, L.ncmax, st));
     } else {
-      FPS_HIP(fps::launch_cube_ifinal(O1, ab, tl, nullptr, nullptr, ZR, 1.0, 0.0, 0.0, npad, mp0,
+      FPS_HIP(fps::launch_cube_ifinal(O1, abf, tl, nullptr, nullptr, ZR, 1.0, 0.0, 0.0, npad, mp0,
                                       L.mstride, L.ncmax, st));
     }
   }

@@ -399,9 +399,13 @@ __global__ void k_cube_ifinal(const double *__restrict__ x, const double *__rest
   const int s = y >= mp0 ? 1 : 0;
   const int64_t k = y - (s ? mp0 : 0), c = k / kChunk;
   const double *tp = tab + (int64_t)s * kNTab * mstride;
-  const double *e = ab + z * (2 * ncmax * npad * 2) + (((int64_t)s * ncmax + c) * npad + q) * 2;
   const int64_t i = (z * npad + y) * npad + q;
-  double v = cy * (x[i] + e[0] * tp[T_BF2 * mstride + k] + e[1] * tp[T_BK2 * mstride + k]);
+  double v = x[i];
+  if (ab) {  // null: x is complete (no chunk carries left)
+    const double *e = ab + z * (2 * ncmax * npad * 2) + (((int64_t)s * ncmax + c) * npad + q) * 2;
+    v = x[i] + e[0] * tp[T_BF2 * mstride + k] + e[1] * tp[T_BK2 * mstride + k];
+  }
+  v = cy * v;
   if (R) v += cr * R[i];
   if (B) v += cb * B[i];
   out[i] = v;

@@ -114,6 +114,13 @@ hipError_t launch_sweep_batch(const SweepArgs &types, bool with_g, const BatchSw
 // and ctab32 ([table][2][F2last, BF2first, Bk2first][mstride /
 // kZeigLdsChunk]) of fps::build_chunk_tables.
 constexpr int kZeigLdsChunk = 16;
+//
+// The nested cube's inner ADI (`nested`) runs the same kernel with the
+// stencil pre = A~ in both solves (the last y solve keeps it), mu = 0, both
+// solves of step j on table tab0_all + j, every slice k in storage slice k
+// with J_all steps and the sigmas sig[2j], sig[2j + 1], writing +(the final
+// y solve).  Null per-slice arrays take these uniform values (slice k, mu 0,
+// sig0 0); tab0_all / J_all >= 0 replace tab0[] / J[].
 struct ZeigLdsArgs {
   const double *G;
   double *Y;
@@ -121,10 +128,11 @@ struct ZeigLdsArgs {
   const int *slice, *J, *tab0, *sig0;
   int64_t npad, mp0, mstride, ncmax;
   int m0, m1;
+  int tab0_all = -1, J_all = -1;
 };
 bool zeig_lds_fits(int64_t m0, int64_t m1);
 hipError_t launch_zeig_lds(const ZeigLdsArgs &a, int nslices, hipStream_t st,
-                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool nested = false);
 
 // Batched row-chain sweeps (launch_sweep_rows per problem): every
 // descriptor is a single array whose chains are its storage rows, with
@@ -277,7 +285,7 @@ hipError_t launch_slice_xfinal(const float *x, const double *ab, const double *t
                                float *out, int64_t npad, int64_t mp0, int64_t mstride,
                                int64_t ncmax, int64_t nslices, hipStream_t st);
 // After the last per-slice sweep (chains = x, positions = y, ab per slice):
-// out = cy (x + chunk carries) + cr R + cb B.
+// out = cy (x + chunk carries) + cr R + cb B; ab null: x is complete.
 hipError_t launch_cube_ifinal(const double *x, const double *ab, const double *tab,
                               const double *R, const double *B, double *out, double cy, double cr,
                               double cb, int64_t npad, int64_t mp0, int64_t mstride, int64_t ncmax,

@@ -153,6 +153,11 @@ struct fps_plan {
   // then the inactive storage slices (zl_slice, zl_J, zl_tab0, zl_sig0 per
   // entry; zl_mu the shifts mu; zl_sig the two sigmas of every step).
   bool zlds = false;
+  // Nested cube plans whose parity blocks fit one workgroup's LDS: every
+  // outer step's inner ADI is one k_zeig_lds launch (d_zl_tab32 / ctab32 the
+  // chunk multipliers of every table, d_zl_sig the inner sigmas, outer step i
+  // at 2 inner_off[i]).
+  bool nlds = false;
   fps::detail::DeviceBuf d_zl_slice, d_zl_J, d_zl_tab0, d_zl_sig0, d_zl_mu, d_zl_sig;
   fps::detail::DeviceBuf d_zl_tab32, d_zl_ctab32;  // the kernel's chunk multipliers
   // Sorted slices 0 .. zsplit-1 (the longest) iterate on the plan's own

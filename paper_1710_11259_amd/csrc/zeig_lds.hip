@@ -132,9 +132,13 @@ __device__ __forceinline__ void chain_carries(double (*ey)[kLB], double (*ex)[kL
 // boundary-value exchange between them).  x solve: chain cells cell[i]
 // (row), right-hand side v; y solve: cells cell[i * kLP] (column),
 // right-hand side P (v - G) (v - G at the last step).  kFull: a full chunk.
-template <bool kFull>
+// kSt: the right-hand side is P v with the stencil along the row (diagonal
+// and coupling of position k at Px[k * kLP], Px[k * kLP + 1]; v before and
+// after the chunk wlo, whi, zero past the chain).
+template <bool kFull, bool kSt = false>
 __device__ __forceinline__ Ends x_local(double (&r)[kLH], const double *cell, int k0, int k1,
-                                        const double *T) {
+                                        const double *T, const double *Px = nullptr,
+                                        double wlo = 0.0, double whi = 0.0) {
   if constexpr (kFull) {  // 16-byte reads of the row (cell 16-byte aligned)
 #pragma unroll
     for (int i = 0; i < kLH; i += 2) {
@@ -145,6 +149,22 @@ __device__ __forceinline__ Ends x_local(double (&r)[kLH], const double *cell, in
   } else {
 #pragma unroll
     for (int i = 0; i < kLH; ++i) r[i] = k0 + i < k1 ? cell[i] : 0.0;
+  }
+  if constexpr (kSt) {
+    // rhs_k = d_k v_k + e_{k-1} v_{k-1} + e_k v_{k+1}
+    double wm = wlo;
+#pragma unroll
+    for (int i = 0; i < kLH; ++i) {
+      const int k = k0 + i;
+      if (kFull || k < k1) {
+        const double w = r[i];
+        const double wp = i + 1 < kLH ? r[i + 1] : whi;
+        const double lo = k > 0 ? Px[(k - 1) * kLP + 1] * wm : 0.0;
+        const double hi = Px[k * kLP + 1] * wp;
+        r[i] = (Px[k * kLP] + 0.0) * w + lo + hi;
+        wm = w;
+      }
+    }
   }
   return chunk_solve<kFull>(r, k0, k1, T, T + kLB, T + 2 * kLB);
 }
@@ -175,11 +195,11 @@ template <bool kFull>
 __device__ __forceinline__ Ends y_local(double (&r)[kLH], const double *cell, const double *gc,
                                         int k0, int k1, const double *T, const double *Pd,
                                         const double *Pe, double mu, double wlo, double whi,
-                                        bool last) {
+                                        bool nost) {
   // w = v - G (the cells keep v until after the barrier that follows)
 #pragma unroll
   for (int i = 0; i < kLH; ++i) r[i] = (kFull || k0 + i < k1) ? cell[i * kLP] - gc[i] : 0.0;
-  if (!last) {
+  if (!nost) {
     // rhs_k = (d_k + mu) w_k + e_{k-1} w_{k-1} + e_k w_{k+1}
     double wm = wlo;
 #pragma unroll
@@ -217,7 +237,10 @@ __device__ __forceinline__ void y_out(const double (&r)[kLH], double *cell, int 
 // block (sy, sx) = ((g / 2) % 2, g % 2).  Threads: chain t % 128, chunk
 // t / 128 (two wavefronts per chunk, four per SIMD).  The next step's tables are fetched
 // into registers while a step runs; each solve's LDS tables are replaced
-// right after that solve's last read.
+// right after that solve's last read.  kNested: the nested cube's inner ADI
+// (stencil in both solves, kept at the last step; the row padding of Yb
+// holds the stencil of the x parity; output +(the final y solve)).
+template <bool kNested>
 __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
   __shared__ __align__(16) double Yb[kLB * kLP];
   __shared__ double ey[kLQ][kLB], exf[kLQ][kLB];  // chunk boundary values
@@ -232,7 +255,7 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
   const int my = sy ? a.m1 : a.m0, mx = sx ? a.m1 : a.m0;
   const int64_t mpy = sy ? npad - mp0 : mp0, mpx = sx ? npad - mp0 : mp0;
   const int64_t r0 = sy ? mp0 : 0, c0 = sx ? mp0 : 0;
-  const int slice = a.slice[kk], J = a.J[kk];
+  const int slice = kNested ? kk : a.slice[kk], J = kNested ? a.J_all : a.J[kk];
   const double *__restrict__ Gs = a.G + ((int64_t)slice * npad + r0) * npad + c0;
   double *__restrict__ Ys = a.Y + ((int64_t)slice * npad + r0) * npad + c0;
 
@@ -241,7 +264,9 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
       for (int64_t x = tid % 64; x < mpx; x += 64) Ys[y * npad + x] = 0.0;
     return;
   }
-  const int tab0 = a.tab0[kk];
+  const int tab0 = kNested ? a.tab0_all : a.tab0[kk];
+  // step j: x solve on table tab0 + kTs j, y solve on tab0 + kTs j + kTy
+  constexpr int kTs = kNested ? 1 : 2, kTy = kNested ? 0 : 1;
   // Step j's tables are fetched in 64-value pieces, one per (wavefront,
   // round p): piece z = p * 16 + wavefront is piece z % 11 of solve z / 11
   // (0: x, 1: y), either half (z % 11) % 2 of position table (z % 11) / 2 (l,
@@ -265,20 +290,20 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
     const bool act = z < 2 * kPieces;
     const int sv = z >= kPieces ? 1 : 0, r = z - sv * kPieces;
     const int s = sv ? sy : sx, m = sv ? my : mx;
-    const int64_t t = tab0 + sv;  // the table of step 0
+    const int64_t t = tab0 + kTy * sv;  // the table of step 0
     psv[p] = sv;
     if (r < 2 * kNT) {
       const int row = r >> 1, k = (r & 1) * 64 + lane;
       src[p] = row < 3 ? a.tab + ((t * 2 + s) * kNTab + row) * ms
                        : a.tab32 + ((t * 2 + s) * 2 + (row - 3)) * ms;
-      step[p] = row < 3 ? 4 * kNTab * ms : 8 * ms;
+      step[p] = kTs * (row < 3 ? 2 * kNTab * ms : 4 * ms);
       off[p] = k;
       live[p] = act && k < m;
       dst[p] = act ? sv * kTabSolve + row * kLB + k : -1;
     } else {
       const int kind = lane >> 3, c = lane & 7;
       src[p] = a.ctab32 + (t * 2 + s) * 3 * nq32;
-      step[p] = 12 * nq32;
+      step[p] = kTs * 6 * nq32;
       off[p] = kind * (int)nq32 + c;
       live[p] = act && lane < 3 * kLQ && c * kLH < m;
       dst[p] = act && lane < 3 * kLQ ? sv * kTabSolve + kNT * kLB + lane : -1;
@@ -306,6 +331,10 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
   if (tid < kLB) {
     Pd[tid] = tid < my ? a.pre[r0 + tid] : 0.0;
     Pe[tid] = tid < my ? a.pre[npad + r0 + tid] : 0.0;
+    if constexpr (kNested) {  // the x parity's stencil in the row padding
+      Yb[tid * kLP + kLB] = tid < mx ? a.pre[c0 + tid] : 0.0;
+      Yb[tid * kLP + kLB + 1] = tid < mx ? a.pre[npad + c0 + tid] : 0.0;
+    }
   }
   // This thread's column chunk of G^ for every y solve, and the halo values
   // of the neighbouring chunks (the stencil couples the chunks' ends).
@@ -324,8 +353,8 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
   stash(1);
   __syncthreads();
 
-  const double mu = a.mu[kk];
-  const double *__restrict__ sig = a.sig + a.sig0[kk];
+  const double mu = kNested ? 0.0 : a.mu[kk];
+  const double *__restrict__ sig = kNested ? a.sig : a.sig + a.sig0[kk];
   double r[kLH];
   for (int j = 0; j < J; ++j) {
     const bool last = j == J - 1;
@@ -337,8 +366,14 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
       const bool on = ch < my && kx0 < mx;
       double *cell = Yb + ch * kLP + kx0;
       if (on) {
-        const Ends e = fullx ? x_local<true>(r, cell, kx0, kx1, T)
-                             : x_local<false>(r, cell, kx0, kx1, T);
+        Ends e;
+        if constexpr (kNested) {
+          const double wlo = kx0 > 0 ? cell[-1] : 0.0, whi = kx1 < mx ? cell[kx1 - kx0] : 0.0;
+          e = fullx ? x_local<true, true>(r, cell, kx0, kx1, T, Yb + kLB, wlo, whi)
+                    : x_local<false, true>(r, cell, kx0, kx1, T, Yb + kLB, wlo, whi);
+        } else {
+          e = fullx ? x_local<true>(r, cell, kx0, kx1, T) : x_local<false>(r, cell, kx0, kx1, T);
+        }
         ey[q][ch] = e.ylast;
         exf[q][ch] = e.xfirst;
       }
@@ -367,8 +402,8 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
         const double wlo = hlo ? Yb[(ky0 - 1) * kLP + ch] - glo : 0.0;
         const double whi = hhi ? Yb[ky1 * kLP + ch] - ghi : 0.0;
         const Ends e =
-            fully ? y_local<true>(r, cell, gc, ky0, ky1, T, Pd, Pe, mu, wlo, whi, last)
-                  : y_local<false>(r, cell, gc, ky0, ky1, T, Pd, Pe, mu, wlo, whi, last);
+            fully ? y_local<true>(r, cell, gc, ky0, ky1, T, Pd, Pe, mu, wlo, whi, last && !kNested)
+                  : y_local<false>(r, cell, gc, ky0, ky1, T, Pd, Pe, mu, wlo, whi, last && !kNested);
         ey[q][ch] = e.ylast;
         exf[q][ch] = e.xfirst;
       }
@@ -387,10 +422,10 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
       if (!last) stash(1);  // the y tables were last read above
     }
   }
-  // Y^ block = -(the last y solve), zero on the padding.
+  // Y^ block = -(the last y solve) (kNested: +), zero on the padding.
   for (int64_t y = tid / 64; y < mpy; y += kLThreads / 64)
     for (int64_t x = tid % 64; x < mpx; x += 64)
-      Ys[y * npad + x] = (y < my && x < mx) ? -Yb[y * kLP + x] : 0.0;
+      Ys[y * npad + x] = (y < my && x < mx) ? (kNested ? Yb[y * kLP + x] : -Yb[y * kLP + x]) : 0.0;
 }
 
 }  // namespace
@@ -398,16 +433,21 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
 bool zeig_lds_fits(int64_t m0, int64_t m1) { return m0 <= kLB && m1 <= kLB; }
 
 hipError_t launch_zeig_lds(const ZeigLdsArgs &a, int nslices, hipStream_t st, hipEvent_t ev0,
-                           hipEvent_t ev1) {
+                           hipEvent_t ev1, bool nested) {
   if (nslices <= 0) return hipSuccess;
   if (!zeig_lds_fits(a.m0, a.m1) || a.mp0 > kLB || a.npad - a.mp0 > kLB ||
       a.mstride % kLH != 0 || a.tab32 == nullptr || a.ctab32 == nullptr)
     return hipErrorInvalidValue;
+  if (nested ? (a.tab0_all < 0 || a.J_all < 1 || a.sig == nullptr || nslices > a.npad)
+             : (a.slice == nullptr || a.J == nullptr || a.tab0 == nullptr || a.sig0 == nullptr ||
+                a.mu == nullptr))
+    return hipErrorInvalidValue;
   const dim3 grid((unsigned)(4 * nslices)), block(kLThreads);
+  auto k = nested ? k_zeig_lds<true> : k_zeig_lds<false>;
   if (ev0 != nullptr)
-    hipExtLaunchKernelGGL(k_zeig_lds, grid, block, 0, st, ev0, ev1, 0, a);
+    hipExtLaunchKernelGGL(k, grid, block, 0, st, ev0, ev1, 0, a);
   else
-    hipLaunchKernelGGL(k_zeig_lds, grid, block, 0, st, a);
+    hipLaunchKernelGGL(k, grid, block, 0, st, a);
   return hipGetLastError();
 }
 
