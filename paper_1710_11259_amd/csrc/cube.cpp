@@ -20,6 +20,9 @@
 //   inner:     the square pass form with A~ replaced by -(K + q_i/2) and G by
 //              -R_i, solving (K + q_i/2 - p) = -(I - (q_i/2 - p) A~)^-1 A~...;
 //   finalize:  zR_{i+1} = -B + R_i + (p_{i+1} - q_i) Y_{i+1}.
+// With parity blocks of at most 128 the inner ADI of an outer step runs as
+// one launch of the slice kernel of zeig_lds.hip, every slice block held in
+// LDS for all its inner steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

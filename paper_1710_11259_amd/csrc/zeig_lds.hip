@@ -13,7 +13,9 @@
 //   y solve along its columns:         v <- v - s2 T2^-1 P (v - G)
 //                                      (the last step keeps T2^-1 P (v - G)),
 // with T1, T2 the slice's shifted tridiagonals (whole-chain Thomas factors
-// of the plan's tables) and P = A~ + mu the stencil.  Each chain of up to
+// of the plan's tables) and P = A~ + mu the stencil.  The nested cube's
+// inner ADI on every z-slice is the same loop with the stencil A~ in both
+// solves (x solve: v <- v - s1 T1^-1 A~ v; the last y solve keeps it).  Each chain of up to
 // 128 positions is split into eight chunks of 16, one per thread: all solve
 // with zero carries, exchange their boundary values through LDS, and add
 // the carries through the chunk vectors BF2 / Bk2 of 16-position chunks
