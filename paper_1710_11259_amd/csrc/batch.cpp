@@ -47,9 +47,10 @@ struct fps_batch {
   // g2; (FP64 batches) the adjoint's input map g1, g2 and output map g1, g2
   DeviceBuf d_gd[8], d_gmap[8];
   int gtiles[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  // permute-in (0), transpose (1), finalize (2) and, for refined batches,
-  // residual (3, on the transpose's map) of all problems as one launch each
-  // (elem_ok; else, for very large batches, one launch per problem)
+  // permute-in (0), 64 x 64 tiles (1: the map and descriptors the refined
+  // residual launch runs on), finalize (2) and, for refined batches,
+  // residual (3) of all problems as one launch each (elem_ok; else, for very
+  // large batches, one launch per problem)
   bool elem_ok = false;
   DeviceBuf d_ed[4], d_emap[3];
   int ewg[3] = {0, 0, 0};
@@ -135,7 +136,6 @@ fps_status build_descriptors(fps_batch *bt) {
     const fps::Layout &L = pl->L;
     const int64_t W = bt->ws_off[b];
     const int64_t Gterm = W + (refined ? pl->off_R : pl->off_G);
-    const int64_t GTin = refined ? W + pl->off_R + L.npad * L.npad * 4 : W + pl->off_GT;
     const int64_t O0 = W + pl->off_O0, O1 = W + pl->off_O1, lv = W + pl->off_lv,
                   ab = W + pl->off_ab;
     fps::SweepArgs A{};
@@ -160,9 +160,9 @@ fps_status build_descriptors(fps_batch *bt) {
       const std::vector<double> &p = sh.p;
       for (int j = 0; j < J; ++j) {
         const bool last = j == J - 1;
-        // half-step 1
+        // half-step 1: row chains, output in the input's layout
         fps::SweepArgs a1 = A;
-        a1.in = off_ptr<const void *>(j == 0 ? GTin : O1);
+        a1.in = off_ptr<const void *>(j == 0 ? Gterm : O1);
         a1.in_f32 = j == 0 ? gf : f;
         a1.in_scale = j == 0 ? -1.0 : 1.0;
         a1.ab_prev = j == 0 ? nullptr : off_ptr<const double *>(ab);
@@ -173,7 +173,8 @@ fps_status build_descriptors(fps_batch *bt) {
         a1.sigma = 2.0 * p[j];
         a1.out = off_ptr<void *>(O0);
         a1.out_f32 = f;
-        // half-step 2
+        a1.out_mode = 0;
+        // half-step 2: column chains, stored in place
         fps::SweepArgs a2 = a1;
         a2.in = off_ptr<const void *>(O0);
         a2.in_f32 = f;
@@ -186,7 +187,7 @@ fps_status build_descriptors(fps_batch *bt) {
         a2.sigma = last ? 0.0 : p[j] + p[j + 1];
         a2.out = off_ptr<void *>(O1);
         a2.out_f32 = f;
-        a2.out_mode = last ? 1 : 0;
+        a2.out_mode = last ? 1 : 2;
         const int row = bt->row0[(size_t)r] + j;
         const size_t i1 = ((size_t)row * 2 + 0) * C + k, i2 = ((size_t)row * 2 + 1) * C + k;
         sw[i1] = fps::BatchSweep{a1, bt->sw_start[k], nbx_s};
@@ -299,21 +300,6 @@ fps_status build_elem_tables(fps_batch *bt) {
   return FPS_OK;
 }
 
-// G -> G^T of every problem.
-hipError_t transpose_all(const fps_batch *bt, char *w, hipStream_t st) {
-  if (bt->elem_ok)
-    return fps::launch_transpose_batch((const fps::ElemDesc *)bt->d_ed[1].p,
-                                       (const int *)bt->d_emap[1].p, bt->ewg[1], w, st);
-  for (int b = 0; b < bt->count; ++b) {
-    const fps_plan *pl = bt->plan_of(b);
-    char *wb = w + bt->ws_off[b];
-    const hipError_t e = fps::launch_transpose((const double *)(wb + pl->off_G),
-                                               (double *)(wb + pl->off_GT), pl->L.npad, st);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
 // Final pass of every problem into Y (its G region, or G^T for a refined
 // batch) after refinement round `round`: mode 0 stores, mode 2 adds.
 hipError_t finalize_all(const fps_batch *bt, char *w, int mode, int round, hipStream_t st) {
@@ -366,7 +352,7 @@ fps_status run_adi_batch(fps_batch *bt, int round, char *ws, hipStream_t st) {
     t2.out_f32 = f;
     const int row = bt->row0[(size_t)round] + j;
     const size_t o1 = ((size_t)row * 2 + 0) * C, o2 = ((size_t)row * 2 + 1) * C;
-    FPS_HIP(fps::launch_sweep_batch(t1, false, dsw + o1, swmap, bt->sw_start[k], ws, st));
+    FPS_HIP(fps::launch_sweep_batch_rows(t1, dsw + o1, swmap, bt->sw_start[k], ws, st));
     FPS_HIP(fps::launch_reduce_batch(drd + o1, rdmap, bt->rd_start[k], bt->ncmax_max, ws, st));
     FPS_HIP(fps::launch_sweep_batch(t2, true, dsw + o2, swmap, bt->sw_start[k], ws, st));
     FPS_HIP(fps::launch_reduce_batch(drd + o2, rdmap, bt->rd_start[k], bt->ncmax_max, ws, st));
@@ -507,8 +493,8 @@ fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, 
     return fps::launch_gemm_table((const fps::GemmDesc *)bt->d_gd[t].p,
                                   (const int *)bt->d_gmap[t].p, bt->gtiles[t], w, (char *)U, st);
   };
-  // Input maps: F into each problem's GT region, the two GEMM stages of all
-  // problems, then G^T.
+  // Input maps: F into each problem's GT region, then the two GEMM stages of
+  // all problems (G in its G region).
   if (bt->elem_ok)
     FPS_HIP(fps::launch_permute_in_batch((const fps::ElemDesc *)bt->d_ed[0].p,
                                          (const int *)bt->d_emap[0].p, bt->ewg[0], F, w, st));
@@ -520,7 +506,6 @@ fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, 
     }
   FPS_HIP(gemm(0));
   FPS_HIP(gemm(1));
-  FPS_HIP(transpose_all(bt, w, st));
   // Y of every problem: FP64 lands in its G region, refined in its GT region
   // (as the single-problem solve places it).
   const bool refined = bt->prec == FPS_FP32_REFINED;
@@ -572,15 +557,14 @@ fps_status fps_batch_solve_adjoint(fps_batch *bt, const double *Ubar, double *Fb
     return fps::launch_gemm_table((const fps::GemmDesc *)bt->d_gd[t].p,
                                   (const int *)bt->d_gmap[t].p, bt->gtiles[t], w, out, st);
   };
-  // Ybar of every problem into its G (and G^T) region: the permutations, the
-  // input-map GEMMs of all problems (two table launches), the transposes.
+  // Ybar of every problem into its G region: the permutations and the
+  // input-map GEMMs of all problems (two table launches).
   for (int b = 0; b < C; ++b)
     if ((s = fps::detail::adjoint_in_pre(bt->plan_of(b), Ubar + bt->u_off[b], w + bt->ws_off[b],
                                          st)) != FPS_OK)
       return s;
   FPS_HIP(gemm(4, nullptr));
   FPS_HIP(gemm(5, nullptr));
-  FPS_HIP(transpose_all(bt, w, st));
   // The same ADI map as the forward solve (self-adjoint for symmetric
   // shifts), batched; Gbar lands in each problem's G region (FP64 batch).
   if ((s = run_adi_batch(bt, 0, w, st)) != FPS_OK) return s;
