@@ -242,9 +242,7 @@ fps_status build_elem_tables(fps_batch *bt) {
     pin.sbase = 2;
     pin.dst = W + pl->off_GT;
     pin.nbx = (int)rowb;
-    fps::ElemDesc tr = e;  // G -> G^T
-    tr.src = W + pl->off_G;
-    tr.dst = W + pl->off_GT;
+    fps::ElemDesc tr = e;  // 64 x 64 tiles: the workgroup map of the residual
     tr.nbx = (int)tb;
     fps::ElemDesc fin = e;  // O1 and its carries -> Y (round 0's tables)
     fin.src = W + pl->off_O1;
@@ -521,7 +519,7 @@ fps_status fps_batch_solve(fps_batch *bt, const double *F, double *U, void *ws, 
         FPS_HIP(fps::launch_residual((const double *)(wb + pl->off_G),
                                      k == 0 ? nullptr : (const double *)(wb + pl->off_GT),
                                      (const double *)pl->d_sdiag.p, (const double *)pl->d_soff.p,
-                                     r, r + pl->L.npad * pl->L.npad, pl->L.npad, st));
+                                     r, nullptr, pl->L.npad, st));
       }
     if ((s = run_adi_batch(bt, k, w, st)) != FPS_OK) return s;
     FPS_HIP(finalize_all(bt, w, k == 0 ? 0 : 2, k, st));

@@ -1,5 +1,5 @@
 // gfx950 element-wise and data-movement kernels of the spectral Poisson
-// solver: parity-blocked permutation, transpose, finalization, fill.
+// solver: parity-blocked permutation, residual, finalization, fill.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -125,26 +125,6 @@ __global__ void k_permute_in(const double *__restrict__ src, double *__restrict_
                 blockIdx.y);
 }
 
-// 64 x 64 tile (column tile bx, row tile by) of an npad x npad transpose;
-// 256 threads.
-__device__ __forceinline__ void transpose_tile(const double *__restrict__ src,
-                                               double *__restrict__ dst, int64_t npad, int64_t bx,
-                                               int64_t by, double (*tile)[65]) {
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-  const int64_t r0 = by * 64, c0 = bx * 64;
-  for (int i = ty; i < 64; i += 4) tile[i][tx] = src[(r0 + i) * npad + c0 + tx];
-  __syncthreads();
-  for (int i = ty; i < 64; i += 4) dst[(c0 + i) * npad + r0 + tx] = tile[tx][i];
-}
-
-__global__ __launch_bounds__(256) void k_transpose(const double *__restrict__ src,
-                                                   double *__restrict__ dst, int64_t npad) {
-  __shared__ double tile[64][65];
-  src += (int64_t)blockIdx.z * npad * npad;
-  dst += (int64_t)blockIdx.z * npad * npad;
-  transpose_tile(src, dst, npad, blockIdx.x, blockIdx.y, tile);
-}
-
 // --- batched forms: workgroup g works for problem wg_prob[g] -------------
 
 __device__ __forceinline__ intptr_t elem_base(int id, char *ws, const double *in) {
@@ -163,17 +143,6 @@ __global__ __launch_bounds__(256) void k_permute_in_batch(const ElemDesc *__rest
                 (int64_t)(local % e.nbx) * 256 + threadIdx.x, local / e.nbx);
 }
 
-__global__ __launch_bounds__(256) void k_transpose_batch(const ElemDesc *__restrict__ d,
-                                                         const int *__restrict__ wg_prob,
-                                                         char *ws) {
-  __shared__ double tile[64][65];
-  const int g = blockIdx.x;
-  const ElemDesc &e = d[__builtin_amdgcn_readfirstlane(wg_prob[g])];
-  const int local = g - e.wg_start;
-  const double *src = (const double *)(elem_base(e.sbase, ws, nullptr) + e.src);
-  double *dst = (double *)(elem_base(e.dbase, ws, nullptr) + e.dst);
-  transpose_tile(src, dst, e.npad, local % e.nbx, local / e.nbx, tile);
-}
 
 __global__ __launch_bounds__(256) void k_residual_batch(const ElemDesc *__restrict__ d,
                                                         const int *__restrict__ wg_prob,
@@ -184,7 +153,7 @@ __global__ __launch_bounds__(256) void k_residual_batch(const ElemDesc *__restri
   const int local = g - e.wg_start;
   float *r = (float *)(ws + e.dst);
   residual_tile((const double *)(ws + e.src), with_y ? (const double *)(ws + e.ab) : nullptr, e.tab,
-                e.ev, r, r + e.npad * e.npad, e.npad, 1.0, 1.0, local % e.nbx, local / e.nbx, tile);
+                e.ev, r, nullptr, e.npad, 1.0, 1.0, local % e.nbx, local / e.nbx, tile);
 }
 
 template <typename T>
@@ -530,25 +499,10 @@ hipError_t launch_permute_out(const double *src, double *dst, int64_t n, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st,
-                            int nbatch) {
-  if (npad % 64 != 0 || nbatch < 1) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(npad / 64), (unsigned)(npad / 64), (unsigned)nbatch);
-  hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, src, dst, npad);
-  return hipGetLastError();
-}
-
 hipError_t launch_permute_in_batch(const ElemDesc *d, const int *wg_prob, int nwg, const double *in,
                                    char *ws, hipStream_t st) {
   if (nwg <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_permute_in_batch, dim3((unsigned)nwg), dim3(256), 0, st, d, wg_prob, in, ws);
-  return hipGetLastError();
-}
-
-hipError_t launch_transpose_batch(const ElemDesc *d, const int *wg_prob, int nwg, char *ws,
-                                  hipStream_t st) {
-  if (nwg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_transpose_batch, dim3((unsigned)nwg), dim3(256), 0, st, d, wg_prob, ws);
   return hipGetLastError();
 }
 

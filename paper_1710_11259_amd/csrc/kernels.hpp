@@ -216,19 +216,16 @@ hipError_t launch_permute_in(const double *src, double *dst, int64_t n, int64_t 
 hipError_t launch_permute_out(const double *src, double *dst, int64_t n, int64_t npad, int64_t mp0,
                               const double *sinv, hipStream_t st);
 
-hipError_t launch_transpose(const double *src, double *dst, int64_t npad, hipStream_t st,
-                            int nbatch = 1);
-
 // One problem of a batched element-wise launch (launch_permute_in,
-// launch_transpose or launch_finalize for many problems at once, each
+// launch_residual or launch_finalize for many problems at once, each
 // workgroup doing what the single-problem launch's workgroup does).
 // Workgroups wg_start .. of the launch belong to this problem, nbx per row
 // of its own grid (permute-in, finalize: ceil(npad / 256) per row, npad
-// rows; transpose, residual: npad / 64 tiles per row of tiles).  src / dst
+// rows; residual: npad / 64 tiles per row of tiles).  src / dst
 // are byte offsets from the base named by sbase / dbase (0: absolute, 1:
 // workspace, 2: the input F); ab is a workspace offset, tab and ev device
-// pointers.  The residual takes G at src, Y at ab, r and r^T at dst, the
-// stencil's diagonal at tab and its coupling at ev.
+// pointers.  The residual takes G at src, Y at ab, r at dst, the stencil's
+// diagonal at tab and its coupling at ev.
 struct ElemDesc {
   int64_t src, dst, ab;
   const double *tab, *ev;
@@ -239,9 +236,6 @@ struct ElemDesc {
 // F of every problem into its parity-blocked layout (no sinv).
 hipError_t launch_permute_in_batch(const ElemDesc *d, const int *wg_prob, int nwg, const double *in,
                                    char *ws, hipStream_t st);
-// npad x npad transposes (npad a multiple of 64).
-hipError_t launch_transpose_batch(const ElemDesc *d, const int *wg_prob, int nwg, char *ws,
-                                  hipStream_t st);
 // launch_residual (ax = ay = 1) for every problem; with_y false: r = G.
 hipError_t launch_residual_batch(const ElemDesc *d, const int *wg_prob, int nwg, bool with_y,
                                  char *ws, hipStream_t st);
