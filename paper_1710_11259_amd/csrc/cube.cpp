@@ -356,8 +356,9 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
     Z.out_mode = 2;
     FPS_HIP(timed_sweep(pl, Z, st));
     FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(i), ab, -Z.sigma, ch, Z.nc0, Z.nc1, L.ncmax, st));
-    FPS_HIP(fps::launch_cube_zfinal(O0, ab, pl->tab_dev(i), RX, RXT, npad, mp0, L.mstride, L.ncmax,
-                                    st));
+    // (the LDS-resident inner ADI reads R in place: no per-slice transpose)
+    FPS_HIP(fps::launch_cube_zfinal(O0, ab, pl->tab_dev(i), RX, pl->nlds ? nullptr : RXT, npad, mp0,
+                                    L.mstride, L.ncmax, st));
     // (x, y) half-step: inner ADI on every z-slice
     const int J2 = pl->inner_J[i];
     const double *p2 = pl->inner_p.data() + pl->inner_off[i];
@@ -386,37 +387,38 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
       FPS_HIP(fps::launch_zeig_lds(za, (int)npad, st, tm ? pl->ev[2 * pl->ev_used] : nullptr,
                                    tm ? pl->ev[2 * pl->ev_used + 1] : nullptr, true));
       if (tm) ++pl->ev_used;
-    }
-    for (int j = 0; j < (pl->nlds ? 0 : J2); ++j) {
-      const int t = t0 + j;
-      const bool last = j == J2 - 1;
-      fps::SweepArgs a = S;
-      a.in = j == 0 ? (const void *)RXT : (const void *)O1;
-      a.in_scale = 1.0;
-      a.ab_prev = j == 0 ? nullptr : ab;
-      a.tab_prev = j == 0 ? nullptr : pl->tab_dev(t - 1);
-      a.g = nullptr;
-      a.tab = pl->tab_dev(t);
-      a.l1 = pl->l1_dev(t);
-      a.sigma = 2.0 * p2[j];
-      a.out = O0;
-      a.out_mode = 0;
-      FPS_HIP(timed_sweep(pl, a, st));
-      FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(t), ab, -a.sigma, npad, a.nc0, a.nc1, L.ncmax, st,
-                                 (int)npad, S.lvb, S.abb));
-      fps::SweepArgs b = a;
-      b.in = O0;
-      b.ab_prev = ab;
-      b.tab_prev = pl->tab_dev(t);
-      b.g = RX;
-      b.sg = -1.0;
-      b.og = 0.0;
-      b.sigma = last ? 0.0 : p2[j] + p2[j + 1];
-      b.out = O1;
-      b.out_mode = last ? 1 : 0;
-      FPS_HIP(timed_sweep(pl, b, st));
-      FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(t), ab, last ? 1.0 : -b.sigma, npad, b.nc0, b.nc1,
-                                 L.ncmax, st, (int)npad, S.lvb, S.abb));
+    } else {
+      for (int j = 0; j < J2; ++j) {
+        const int t = t0 + j;
+        const bool last = j == J2 - 1;
+        fps::SweepArgs a = S;
+        a.in = j == 0 ? (const void *)RXT : (const void *)O1;
+        a.in_scale = 1.0;
+        a.ab_prev = j == 0 ? nullptr : ab;
+        a.tab_prev = j == 0 ? nullptr : pl->tab_dev(t - 1);
+        a.g = nullptr;
+        a.tab = pl->tab_dev(t);
+        a.l1 = pl->l1_dev(t);
+        a.sigma = 2.0 * p2[j];
+        a.out = O0;
+        a.out_mode = 0;
+        FPS_HIP(timed_sweep(pl, a, st));
+        FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(t), ab, -a.sigma, npad, a.nc0, a.nc1, L.ncmax,
+                                   st, (int)npad, S.lvb, S.abb));
+        fps::SweepArgs b = a;
+        b.in = O0;
+        b.ab_prev = ab;
+        b.tab_prev = pl->tab_dev(t);
+        b.g = RX;
+        b.sg = -1.0;
+        b.og = 0.0;
+        b.sigma = last ? 0.0 : p2[j] + p2[j + 1];
+        b.out = O1;
+        b.out_mode = last ? 1 : 0;
+        FPS_HIP(timed_sweep(pl, b, st));
+        FPS_HIP(fps::launch_reduce(lv, pl->ctab_dev(t), ab, last ? 1.0 : -b.sigma, npad, b.nc0,
+                                   b.nc1, L.ncmax, st, (int)npad, S.lvb, S.abb));
+      }
     }
     const double *tl = pl->tab_dev(t0 + J2 - 1);
     const double *abf = pl->nlds ? nullptr : ab;

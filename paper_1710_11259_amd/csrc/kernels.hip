@@ -236,6 +236,7 @@ __global__ __launch_bounds__(256) void k_cube_zfinal(const double *__restrict__ 
     R[z * plane + col] = v;
     tile[rr][tx] = v;
   }
+  if (RT == nullptr) return;  // uniform: no transposed copy wanted
   __syncthreads();
   for (int rr = ty; rr < 64; rr += 4) RT[z * plane + (x0 + rr) * npad + y0 + tx] = tile[tx][rr];
 }

@@ -253,7 +253,8 @@ hipError_t launch_permute3_in(const double *src, double *dst, int64_t n, int64_t
 hipError_t launch_permute3_out(const double *src, double *dst, int64_t N, int64_t ld, int64_t mb0,
                                const double *sinv, hipStream_t st);
 // After a z-fiber sweep: R = x + chunk carries (ab over the npad^2 (y, x)
-// chains, tab of the sweep's shift), stored as R[z][y][x] and R^T[z][x][y].
+// chains, tab of the sweep's shift), stored as R[z][y][x] and, unless RT is
+// null, R^T[z][x][y].
 hipError_t launch_cube_zfinal(const double *x, const double *ab, const double *tab, double *R,
                               double *RT, int64_t npad, int64_t mp0, int64_t mstride,
                               int64_t ncmax, hipStream_t st);
