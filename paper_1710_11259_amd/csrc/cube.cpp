@@ -365,11 +365,15 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
     const int t0 = J1 + pl->inner_off[i];
     if (pl->nlds) {
       // every slice's inner ADI in one launch, each parity block resident
-      // in one workgroup's LDS; the complete final x (no chunk carries
-      // left) goes to O1 in the natural layout
+      // in one workgroup's LDS; its epilogue forms the next outer step's
+      // zR (the update of k_cube_ifinal) from the complete final x
       fps::ZeigLdsArgs za{};
       za.G = RX;
-      za.Y = O1;
+      za.Y = ZR;
+      za.B = i + 1 < J1 ? B : nullptr;
+      za.cy = i + 1 < J1 ? p1[i + 1] - q1[i] : 1.0;
+      za.cr = 1.0;
+      za.cb = -1.0;
       za.tab = (const double *)pl->d_tab.p;
       za.tab32 = (const double *)pl->d_zl_tab32.p;
       za.ctab32 = (const double *)pl->d_zl_ctab32.p;
@@ -420,13 +424,13 @@ fps_status cube_solve(fps_plan *pl, const double *F, double *U, char *w, hipStre
                                    b.nc1, L.ncmax, st, (int)npad, S.lvb, S.abb));
       }
     }
+    if (pl->nlds) continue;  // the inner launch wrote zR
     const double *tl = pl->tab_dev(t0 + J2 - 1);
-    const double *abf = pl->nlds ? nullptr : ab;
     if (i + 1 < J1) {
-      FPS_HIP(fps::launch_cube_ifinal(O1, abf, tl, RX, B, ZR, p1[i + 1] - q1[i], 1.0, -1.0, npad,
+      FPS_HIP(fps::launch_cube_ifinal(O1, ab, tl, RX, B, ZR, p1[i + 1] - q1[i], 1.0, -1.0, npad,
                                       mp0, L.mstride, L.ncmax, st));
     } else {
-      FPS_HIP(fps::launch_cube_ifinal(O1, abf, tl, nullptr, nullptr, ZR, 1.0, 0.0, 0.0, npad, mp0,
+      FPS_HIP(fps::launch_cube_ifinal(O1, ab, tl, nullptr, nullptr, ZR, 1.0, 0.0, 0.0, npad, mp0,
                                       L.mstride, L.ncmax, st));
     }
   }

@@ -129,6 +129,9 @@ struct ZeigLdsArgs {
   int64_t npad, mp0, mstride, ncmax;
   int m0, m1;
   int tab0_all = -1, J_all = -1;
+  // nested: Y receives cy x + cr G + cb B instead of x (B null: cy x)
+  const double *B = nullptr;
+  double cy = 1.0, cr = 0.0, cb = 0.0;
 };
 bool zeig_lds_fits(int64_t m0, int64_t m1);
 hipError_t launch_zeig_lds(const ZeigLdsArgs &a, int nslices, hipStream_t st,

@@ -424,10 +424,26 @@ __global__ __launch_bounds__(kLThreads, 1) void k_zeig_lds(ZeigLdsArgs a) {
       if (!last) stash(1);  // the y tables were last read above
     }
   }
-  // Y^ block = -(the last y solve) (kNested: +), zero on the padding.
-  for (int64_t y = tid / 64; y < mpy; y += kLThreads / 64)
-    for (int64_t x = tid % 64; x < mpx; x += 64)
-      Ys[y * npad + x] = (y < my && x < mx) ? (kNested ? Yb[y * kLP + x] : -Yb[y * kLP + x]) : 0.0;
+  // Y^ block = -(the last y solve), zero on the padding; kNested: cy x +
+  // cr G + cb B (the outer step's update of the nested cube), in that order.
+  if constexpr (kNested) {
+    const double *__restrict__ Bs =
+        a.B ? a.B + ((int64_t)slice * npad + r0) * npad + c0 : nullptr;
+    for (int64_t y = tid / 64; y < mpy; y += kLThreads / 64)
+      for (int64_t x = tid % 64; x < mpx; x += 64) {
+        double v = (y < my && x < mx) ? Yb[y * kLP + x] : 0.0;
+        v = a.cy * v;
+        if (Bs) {  // null: the last outer step stores x itself
+          v += a.cr * Gs[y * npad + x];
+          v += a.cb * Bs[y * npad + x];
+        }
+        Ys[y * npad + x] = v;
+      }
+  } else {
+    for (int64_t y = tid / 64; y < mpy; y += kLThreads / 64)
+      for (int64_t x = tid % 64; x < mpx; x += 64)
+        Ys[y * npad + x] = (y < my && x < mx) ? -Yb[y * kLP + x] : 0.0;
+  }
 }
 
 }  // namespace
