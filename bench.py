@@ -264,8 +264,8 @@ def bench_cube(fps, workloads, torch, tol, n=256, steps=2, check=True, tight=Tru
     fiber sweeps' achieved bandwidth.  Algorithmic bytes per dof: z sweep 24
     (read zR and B, write), inner half-step 1 16, half-step 2 24; for parity
     blocks of at most 128 the inner ADI of an outer step is one LDS-resident
-    launch (HBM: R read into LDS and into registers, x written, 24 B per
-    dof)."""
+    launch (HBM: R read into LDS, into registers and for the outer update,
+    B read, the next zR written: 32 B per dof)."""
     import numpy as np
     F_host = workloads.cube_rhs(n)
     F = torch.from_numpy(F_host).cuda()
@@ -319,7 +319,7 @@ def bench_cube(fps, workloads, torch, tol, n=256, steps=2, check=True, tight=Tru
             "form": "one launch per outer step, every slice block resident in LDS",
             "launches": len(ti), "ms_total": round(sum(ti), 3),
             "share_of_solve": round(sum(ti) / ms_instr, 4),
-            "hbm_bytes_per_launch": 3 * 8 * dof,
+            "hbm_bytes_per_launch": 4 * 8 * dof,
             "sweep_model_bytes": 40.0 * dof * sum(counts),
             "sweep_model_equiv_GBs": round(40.0 * dof * sum(counts) / (sum(ti) * 1e-3) / 1e9, 1)}
     for k in ("z", "hs1", "hs2"):
