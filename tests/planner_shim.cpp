@@ -20,6 +20,17 @@ void shim_tables(long long n, int J, const double *p, double *pos, double *chunk
   std::memcpy(pos, a.data(), a.size() * sizeof(double));
   std::memcpy(chunk, b.data(), b.size() * sizeof(double));
 }
+// The chunk multipliers of `chunk`-position chunks (the LDS-resident slice
+// kernel's) for the sweep tables of shifts p.
+void shim_chunk_tables(long long n, int J, const double *p, long long chunk, double *pos,
+                       double *ch) {
+  fps::Layout L = fps::make_layout(n);
+  std::vector<double> pv(p, p + J), a, b, cmb, l1, tp, tc;
+  fps::build_sweep_tables(L, pv, a, b, cmb, l1);
+  fps::build_chunk_tables(L, a, chunk, tp, tc);
+  std::memcpy(pos, tp.data(), tp.size() * sizeof(double));
+  std::memcpy(ch, tc.data(), tc.size() * sizeof(double));
+}
 void shim_comb(long long n, int J, const double *p, double *comb) {
   fps::Layout L = fps::make_layout(n);
   std::vector<double> pv(p, p + J), a, b, cmb, l1;

@@ -350,6 +350,72 @@ def test_conversion_maps_match_oracle(shim, n):
         assert np.abs(P[s].reshape(mo[s], m[s]) - Pref).max() < 1e-13 * max(1, np.abs(Pref).max())
 
 
+@pytest.mark.parametrize("n", [3, 33, 130, 255, 256])
+def test_chunk_tables_reproduce_shifted_solves(shim, n):
+    # The LDS-resident slice kernel's algorithm: every 16-position chunk of a
+    # parity chain solved with zero carries (whole-chain factors l, ib, u),
+    # then the chunk-level recurrences with F2last, BF2first, Bk2first and the
+    # carries added through BF2, Bk2 -- against a dense solve of the shifted
+    # parity block of the oracle's A~.
+    shim.shim_chunk_tables.argtypes = [ctypes.c_longlong, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_longlong,
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+    CH = 16
+    lay = _layout(shim, n)
+    ms, nc = lay["mstride"], lay["ncmax"]
+    J, p, _ = oshifts.square_shifts(n, 1e-13)
+    sel = [0, J // 2, J - 1]
+    pv = np.ascontiguousarray(p[sel])
+    pos = np.zeros(len(sel) * 2 * 7 * ms)
+    ch0 = np.zeros(len(sel) * 2 * 3 * nc)
+    shim.shim_tables(n, len(sel), _ptr(pv), _ptr(pos), _ptr(ch0))
+    pos = pos.reshape(len(sel), 2, 7, ms)
+    nq = ms // CH
+    t32 = np.zeros(len(sel) * 2 * 2 * ms)
+    c32 = np.zeros(len(sel) * 2 * 3 * nq)
+    shim.shim_chunk_tables(n, len(sel), _ptr(pv), CH, _ptr(t32), _ptr(c32))
+    t32 = t32.reshape(len(sel), 2, 2, ms)
+    c32 = c32.reshape(len(sel), 2, 3, nq)
+    A = square.atilde_dense(n)
+    rng = np.random.default_rng(n + 1)
+    for jj, pj in enumerate(pv):
+        for s in (0, 1):
+            idx = np.arange(s, n, 2)
+            m = idx.size
+            if m == 0:
+                continue
+            l, ib, u = pos[jj, s, 0], pos[jj, s, 1], pos[jj, s, 2]
+            BF2, Bk2 = t32[jj, s]
+            F2last, BF2first, Bk2first = c32[jj, s]
+            r = rng.standard_normal(m)
+            nq_s = (m + CH - 1) // CH
+            x = np.zeros(m)
+            ylast, xfirst = np.zeros(nq_s), np.zeros(nq_s)
+            for c in range(nq_s):
+                k0, k1 = c * CH, min(m, (c + 1) * CH)
+                y = np.zeros(k1 - k0)
+                yp = 0.0
+                for k in range(k0, k1):
+                    y[k - k0] = r[k] - l[k] * yp
+                    yp = y[k - k0]
+                xn = 0.0
+                for k in range(k1 - 1, k0 - 1, -1):
+                    x[k] = y[k - k0] * ib[k] - u[k] * xn
+                    xn = x[k]
+                ylast[c], xfirst[c] = yp, x[k0]
+            cf, cb = np.zeros(nq_s), np.zeros(nq_s)
+            for c in range(1, nq_s):
+                cf[c] = F2last[c - 1] * cf[c - 1] + ylast[c - 1]
+            for c in range(nq_s - 2, -1, -1):
+                cb[c] = Bk2first[c + 1] * cb[c + 1] + xfirst[c + 1] + BF2first[c + 1] * cf[c + 1]
+            for c in range(nq_s):
+                k0, k1 = c * CH, min(m, (c + 1) * CH)
+                x[k0:k1] += cf[c] * BF2[k0:k1] + cb[c] * Bk2[k0:k1]
+            xr = np.linalg.solve(A[np.ix_(idx, idx)] + pj * np.eye(m), r)
+            assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.norm(xr), (n, jj, s)
+
+
 @pytest.mark.parametrize("n", [130, 1300, 4096])
 def test_carry_combinations_match_recurrence(shim, n):
     shim.shim_comb.argtypes = [ctypes.c_longlong, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
